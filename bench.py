@@ -1,0 +1,244 @@
+"""Benchmark of the checkerboard SU(3) overrelaxation sweep on one MI355X.
+
+Workload (the bandwidth configuration): a 32^4 periodic lattice, links
+exp(i eps H) with eps = 0.8 and a Haar gauge rotation (seed 0), overrelaxation
+omega = 1.7 (exact SU(2) power), float64 links in the 12-real layout.  One
+step = one sweep = the black half-sweep then the white half-sweep = V site
+updates; the timed region holds `--steps` sweeps with the links resident in
+HBM.  Prints one JSON line.
+
+Extra legs (reported inside the same line): the float32 sweep rate, and a
+cpu_baseline of the FP64 CPU oracle on a bounded number of sweeps of the same
+lattice.  `--copy-probe` adds a plain device copy of known size before the
+timed region, so that a `rocprofv3 --pmc` run of this script can scale the
+HBM counters of the sweep kernel.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, AMD published peak
+BYTES_PER_SITE = {"f64": 1536, "f32": 768}  # 8 links x 12 reals, read + write
+METRIC = "SU(3) OR site-updates/s + HBM GB/s (% peak); converged lattices/s, p99 to θ<1e-12"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "or_sweep_f64_32x4_traffic.md")
+SWEEP_SOURCES = ["gf_sweep.hip", "gf_device.h"]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def sweep_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_1412_3655_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic():
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
+    or None when it is missing or the sweep kernel changed since."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    src = re.search(r"kernel_source_sha256:\s*([0-9a-f]+)", text)
+    val = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not src or not val or src.group(1) != sweep_source_hash():
+        return None
+    return float(val.group(1))
+
+
+def time_sweeps(lat, gf, torch, stream, steps, omega, mode):
+    """Run `steps` sweeps with a HIP event pair around every half-sweep launch.
+    Returns (total seconds, mean half-sweep kernel seconds)."""
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4 * steps)]
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    for k in range(steps):
+        for c in range(2):
+            ev[4 * k + 2 * c].record(stream)
+            gf.gf_half_sweep_or(lat.handle, c, omega, mode)
+            ev[4 * k + 2 * c + 1].record(stream)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total = start.elapsed_time(stop) / 1e3
+    per = [ev[2 * i].elapsed_time(ev[2 * i + 1]) / 1e3 for i in range(2 * steps)]
+    return max(total, 0.0), wall, sum(per) / len(per)
+
+
+def cpu_baseline(links, dims, omega, mode, budget_s):
+    import oracle
+
+    work = links.copy()
+    V = links.shape[0]
+    t0 = time.perf_counter()
+    oracle.sweep(work, dims, 1, omega, mode)
+    first = time.perf_counter() - t0
+    n = max(1, min(200, int(budget_s / max(first, 1e-3)) - 1))
+    t1 = time.perf_counter()
+    oracle.sweep(work, dims, n, omega, mode)
+    dt = time.perf_counter() - t1
+    return {
+        "value": V * n / dt,
+        "unit": "site-updates/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"{n} FP64 oracle sweeps of the same 32^4 lattice (omega={omega}, exact power), "
+                  f"after 1 untimed sweep; {dt:.1f} s",
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--dims", type=str, default="32,32,32,32")
+    ap.add_argument("--eps", type=float, default=0.8)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--omega", type=float, default=1.7)
+    ap.add_argument("--mode", type=int, default=0, help="0 = exact SU(2) power, 1 = binomial form")
+    ap.add_argument("--tps", type=int, default=4)
+    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--tps32", type=int, default=4)
+    ap.add_argument("--block32", type=int, default=256)
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported (the method's "
+              "multi-GPU decomposition is a design note, not part of this build)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import gauge_inputs as gi
+    from paper_1412_3655_amd import gf
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    torch.cuda.set_device(0)
+    dims = tuple(int(x) for x in args.dims.split(","))
+    V = gi.volume(dims)
+    log(f"generating {dims} eps={args.eps} seed={args.seed}")
+    links = gi.gen_links(dims, args.eps, args.seed)
+    stream = torch.cuda.Stream()
+
+    if args.copy_probe:
+        n = 1 << 27  # 1 GiB of float64
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    result = {}
+    with gf.Lattice(dims, gf.GF_FP64, stream=stream) as lat:
+        lat.set_sweep_config(args.tps, args.block)
+        lat.set_links(links)
+        P0 = lat.plaquette()
+        log(f"fp64: warmup {args.warmup} sweeps")
+        with torch.cuda.stream(stream):
+            lat.sweep(args.warmup, args.omega, args.mode)
+            total, wall, per_launch = time_sweeps(lat, gf, torch, stream, args.steps, args.omega, args.mode)
+        th, F = lat.measure()
+        P1 = lat.plaquette()
+        log(f"fp64: {args.steps} sweeps in {total * 1e3:.2f} ms (mean half-sweep {per_launch * 1e6:.1f} us); "
+            f"theta {th:.3e} F {F:.6f} dP {abs(P1 - P0):.1e}")
+        result["f64"] = dict(total=total, wall=wall, per_launch=per_launch, theta=th, F=F, dplaq=abs(P1 - P0))
+
+    if not args.no_fp32:
+        with gf.Lattice(dims, gf.GF_FP32, stream=stream) as lat:
+            lat.set_sweep_config(args.tps32, args.block32)
+            lat.set_links(links)
+            with torch.cuda.stream(stream):
+                lat.sweep(args.warmup, args.omega, args.mode)
+                total, wall, per_launch = time_sweeps(lat, gf, torch, stream, args.steps, args.omega, args.mode)
+            log(f"fp32: {args.steps} sweeps in {total * 1e3:.2f} ms (mean half-sweep {per_launch * 1e6:.1f} us)")
+            result["f32"] = dict(total=total, wall=wall, per_launch=per_launch)
+
+    r64 = result["f64"]
+    rate = V * args.steps / r64["total"]
+    launch_bytes = (V // 2) * BYTES_PER_SITE["f64"]
+    achieved = launch_bytes / r64["per_launch"] / 1e9
+    traffic = committed_traffic()
+    line = {
+        "metric": METRIC,
+        "value": rate,
+        "unit": "site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r64["total"] * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic: exp(i eps H) links + Haar gauge rotation (seeded); no physical ensembles",
+        "config": {
+            "workload": f"SU(3) Landau OR sweep, {'x'.join(map(str, dims))} periodic, eps={args.eps}, "
+                        f"seed {args.seed}, omega={args.omega}, {'exact' if args.mode == 0 else 'binomial'} "
+                        f"power, FP64 12-real links",
+            "lattice": list(dims),
+            "site_updates_per_step": V,
+            "threads_per_site": args.tps,
+            "block": args.block,
+        },
+        "hbm_GBps_algorithmic": rate * BYTES_PER_SITE["f64"] / 1e9,
+        "pct_hbm_peak": 100.0 * rate * BYTES_PER_SITE["f64"] / 1e9 / HBM_PEAK_GBPS,
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS,
+            "traffic": traffic,
+            "kernel": "k_or_half_sweep<double, TPS=%d, exact, %d>" % (args.tps, args.block),
+            "algorithmic_bytes_per_launch": launch_bytes,
+            "mean_launch_us": r64["per_launch"] * 1e6,
+        },
+        "checks": {"theta_after": r64["theta"], "F_after": r64["F"], "plaquette_drift": r64["dplaq"]},
+    }
+    if "f32" in result:
+        r32 = result["f32"]
+        rate32 = V * args.steps / r32["total"]
+        line["fp32"] = {
+            "value": rate32,
+            "unit": "site-updates/s",
+            "hbm_GBps_algorithmic": rate32 * BYTES_PER_SITE["f32"] / 1e9,
+            "mean_launch_us": r32["per_launch"] * 1e6,
+            "note": "201 MB of FP32 links fit in the 256 MB Infinity Cache, so this can exceed HBM peak",
+        }
+    if not args.no_cpu:
+        log("cpu baseline (FP64 oracle)")
+        line["cpu_baseline"] = cpu_baseline(links, dims, args.omega, args.mode, args.cpu_budget)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,172 @@
+/*
+ * gf.h -- C ABI of libgf, SU(3) lattice Landau gauge fixing by checkerboard
+ * overrelaxation on AMD Instinct MI355X (gfx950).
+ *
+ * Method: H. Vogt and M. Schroeck, "cuLGT: Lattice Gauge Fixing on GPUs",
+ * arXiv:1412.3655, Sec. 2 (gauge transformation, Eq. (landaugauge),
+ * Eq. (landaufunctional), Eq. (localfunctional), the SU(2) maximiser, the
+ * SU(2)-subgroup iteration, overrelaxation g -> g^omega and the black/white
+ * checkerboard), Sec. 3.1 (checkerboard-split, site-fastest storage and the
+ * two-row 12-real SU(3) representation).
+ *
+ * Conventions shared by every entry point
+ *   - Host link arrays are "canonical": float64, C order
+ *     [site][mu][row][col][re,im] (18 doubles per link, 72 per site), with the
+ *     lexicographic site index x + Nx*(y + Ny*(z + Nz*t)) and mu = 0..3 for
+ *     x, y, z, t.  Element [site][mu] is U_mu(x), the link from x to x + mu^.
+ *   - Extents dims[4] = {Nx, Ny, Nz, Nt}: each even and >= 2 (the checkerboard
+ *     needs a bipartite periodic lattice); boundaries are periodic.
+ *   - Ownership: the library owns every device buffer it allocates (hipMalloc);
+ *     caller pointers are borrowed for the duration of the call only.
+ *   - Streams: all device work of a lattice is ordered on the hip stream given
+ *     at creation (NULL = the default stream).  Calls marked "async" only
+ *     enqueue work; calls marked "syncs" wait for that stream.
+ *   - Errors: every call returns a gf_status; no C++ exception crosses the ABI.
+ *     Arguments are validated before any device work.  HIP failures return
+ *     GF_E_HIP; gf_last_error() then returns a thread-local message.
+ *   - Threads: one lattice must not be used by two threads at once.
+ */
+#ifndef GF_H
+#define GF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gf_lattice_* gf_lattice; /* opaque, library-owned */
+
+typedef enum {
+    GF_OK = 0,
+    GF_E_ARG = 1,     /* invalid argument (null pointer, odd extent, omega out of range, ...) */
+    GF_E_NOMEM = 2,   /* device allocation failed */
+    GF_E_HIP = 3,     /* a HIP runtime call failed; see gf_last_error() */
+    GF_E_STATE = 4,   /* call not valid in the current state (e.g. no links set) */
+    GF_E_NUMERIC = 5, /* theta or F is NaN or infinite */
+    GF_E_FULL = 6     /* no room (pool admission) */
+} gf_status;
+
+typedef enum {
+    GF_FP64 = 0,  /* links stored and updated in float64 */
+    GF_FP32 = 1,  /* links stored and updated in float32 (sums of theta/F in float64) */
+    GF_MIXED = 2  /* float32 bulk sweeps, then float64 polish (see gf_fix_until) */
+} gf_prec;
+
+typedef enum {
+    /* g^omega taken literally: the principal power of the SU(2) subgroup element,
+     * (cos(w phi), sin(w phi) n) for g = (cos phi, sin phi n) (Sec. 2, overrelaxation). */
+    GF_OR_EXACT = 0,
+    /* normalise(1 + w (g - 1)): first-order form of the same power. */
+    GF_OR_BINOMIAL1 = 1
+} gf_or_mode;
+
+typedef struct {
+    double omega;         /* overrelaxation parameter, 1 <= omega < 2 */
+    int32_t mode;         /* gf_or_mode */
+    double theta_target;  /* stop at the first check with theta < theta_target */
+    int32_t max_sweeps;   /* >= 0 */
+    int32_t check_every;  /* >= 1: sweeps between measurements */
+    int32_t reunit_every; /* reunitarise after every sweep whose count is a multiple of this; 0 = never */
+    double theta_switch;  /* GF_MIXED only: leave float32 once theta < theta_switch */
+} gf_fix_params;
+
+typedef struct {
+    int32_t converged;   /* theta < theta_target at the last check */
+    int32_t sweeps;      /* sweeps done by this call */
+    int32_t sweeps_fp32; /* of which in float32 */
+    int32_t sweeps_fp64; /* of which in float64 */
+    double theta;        /* at the last check */
+    double F;            /* at the last check */
+} gf_fix_result;
+
+/* Create a lattice of extents dims (see conventions) and precision prec.
+ * hip_stream: a hipStream_t (NULL = default stream).  Allocates the link
+ * fields in the checkerboard-split, site-fastest 12-real device layout
+ * (Sec. 3.1): 4*V*12 reals, plus for GF_MIXED the float64 copy of the links
+ * and a float32 gauge-transformation field.  Links start undefined. */
+gf_status gf_create_lattice(const int32_t dims[4], gf_prec prec, void* hip_stream, gf_lattice* out);
+
+/* Free every device buffer of the lattice (waits for its stream).  NULL is accepted. */
+gf_status gf_destroy_lattice(gf_lattice lat);
+
+/* Number of sites V and bytes of device memory held by the lattice. */
+gf_status gf_lattice_info(gf_lattice lat, int64_t* volume, int64_t* device_bytes);
+
+/* Kernel configuration of the overrelaxation sweep of this lattice's working
+ * precision: tps lanes per site (1, 2, 4 or 8; the paper's design uses 4 or
+ * 8 threads per site, Sec. 4.2) and threads per block (64, 128, 256 or 512).
+ * Any valid choice gives bitwise the same links.  Default 4 / 256. */
+gf_status gf_set_sweep_config(gf_lattice lat, int32_t tps, int32_t block);
+
+/* Upload links from a host canonical array of 4*V*18 doubles; only rows 0
+ * and 1 of each link are kept (row 2 is rebuilt as the conjugated cross
+ * product whenever it is needed, Sec. 3.1).  Syncs. */
+gf_status gf_set_links(gf_lattice lat, const double* host);
+
+/* Same, from a device canonical array (hip device pointer).  Async. */
+gf_status gf_set_links_device(gf_lattice lat, const double* dev);
+
+/* Download links into a host canonical array (row 2 rebuilt).  Syncs. */
+gf_status gf_get_links(gf_lattice lat, double* host);
+
+/* Same, into a device canonical array.  Async. */
+gf_status gf_get_links_device(gf_lattice lat, double* dev);
+
+/* n_sweeps overrelaxation sweeps: each sweep updates every black site
+ * ((x+y+z+t) even), then every white site.  A site update forms
+ * K(x) = sum_mu [U_mu(x) + U_mu(x-mu^)^dag] (Eq. localfunctional), iterates
+ * over the SU(2) subgroups (0,1), (0,2), (1,2) with the maximiser of the
+ * SU(2)-span projection of each 2x2 block raised to the power omega, and
+ * applies the accumulated g(x) to the 8 links at x (Sec. 2).
+ * omega in [1, 2).  On a GF_MIXED lattice the sweep runs in the current
+ * phase's precision.  Async. */
+gf_status gf_sweep_or(gf_lattice lat, int32_t n_sweeps, double omega, gf_or_mode mode);
+
+/* One half-sweep over the sites of one colour (0 = black, 1 = white).  Async. */
+gf_status gf_half_sweep_or(gf_lattice lat, int32_t colour, double omega, gf_or_mode mode);
+
+/* n_sweeps heat-bath sweeps (simulated annealing prelude, abstract): every
+ * subgroup element is drawn from exp(Re tr[g k]/T) dHaar(g), T falling
+ * linearly from T_start (first sweep) to T_end (last sweep).  Random numbers:
+ * Philox4x32-10 keyed by seed, counter (site, sweep, subgroup<<16 | call,
+ * 0x48420000); the sweep counter continues across calls (reset by
+ * gf_set_links).  T_start >= T_end > 0.  Async. */
+gf_status gf_anneal(gf_lattice lat, int32_t n_sweeps, double T_start, double T_end, uint64_t seed);
+
+/* theta = (1/(3V)) sum_x tr[Delta(x) Delta(x)^dag] with
+ * Delta(x) = [(K(x) - K(x)^dag)/(2i)]_traceless (equal to Eq. (landaugauge)
+ * with A_mu of Sec. 2, a g = 1) and F = (1/(12V)) sum_x sum_mu Re tr U_mu(x)
+ * (Eq. (landaufunctional) with the transformation already applied).  Sums in
+ * float64 with a fixed reduction order.  Syncs.  GF_E_NUMERIC on NaN/Inf. */
+gf_status gf_measure_theta_F(gf_lattice lat, double* theta, double* F);
+
+/* Measure; then, while theta >= theta_target and sweeps < max_sweeps:
+ * min(check_every, remaining) sweeps (reunitarising after every sweep whose
+ * count is a multiple of reunit_every) and measure again (Sec. 2: iterate
+ * until the gauge condition holds to a given precision).  GF_MIXED: float32
+ * sweeps (with the transformation g(x) tracked) until theta < theta_switch,
+ * then the float64 links are rebuilt as g(x) U0_mu(x) g(x+mu^)^dag from the
+ * original links and the loop continues in float64.  Non-convergence is a
+ * result (converged = 0), not an error.  Syncs. */
+gf_status gf_fix_until(gf_lattice lat, const gf_fix_params* params, gf_fix_result* result);
+
+/* Reunitarise every link: Gram-Schmidt of rows 0 and 1 (row 2 is implicit).  Async. */
+gf_status gf_reunitarize(gf_lattice lat);
+
+/* Average plaquette (1/(18V)) sum_x sum_{mu<nu} Re tr[U_mu(x) U_nu(x+mu^)
+ * U_mu(x+nu^)^dag U_nu(x)^dag], float64 sums; gauge invariant.  Syncs. */
+gf_status gf_plaquette(gf_lattice lat, double* P);
+
+/* Thread-local text of the last error (never NULL). */
+const char* gf_last_error(void);
+
+/* Library version string. */
+const char* gf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GF_H */

@@ -1,0 +1,425 @@
+// gf_capi.hip -- the C ABI of libgf (declared in include/gf.h): lattice
+// objects, argument checking, the fix-until driver (Sec. 2 of
+// arXiv:1412.3655: sweep black then white, iterate until the gauge condition
+// holds to a given precision) and error reporting.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "gf.h"
+#include "gf_kernels.h"
+
+using gf::FastDiv;
+using gf::Geom;
+using gf::LinkField;
+using gf::SweepConfig;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+gf_status fail(gf_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define GF_HIP(expr)                                                                                        \
+    do {                                                                                                    \
+        hipError_t e_ = (expr);                                                                             \
+        if (e_ != hipSuccess)                                                                               \
+            return fail(e_ == hipErrorOutOfMemory ? GF_E_NOMEM : GF_E_HIP, "%s: %s (%s:%d)", #expr,         \
+                        hipGetErrorString(e_), __FILE__, __LINE__);                                         \
+    } while (0)
+
+#define GF_TRY(expr)                     \
+    do {                                 \
+        gf_status s_ = (expr);           \
+        if (s_ != GF_OK) return s_;      \
+    } while (0)
+
+// d >= 1; exact for 0 <= n < limit (checked exhaustively).
+bool make_fastdiv(uint32_t d, uint32_t limit, FastDiv* out)
+{
+    uint32_t l = 0;
+    while ((1ull << l) < d) ++l;
+    FastDiv f;
+    f.m = (uint64_t)(((unsigned __int128)1 << (32 + l)) / d) + 1;
+    f.shift = 32 + l;
+    f.d = d;
+    for (uint32_t n = 0; n < limit; ++n)
+        if ((uint32_t)(((unsigned __int128)n * f.m) >> f.shift) != n / d) return false;
+    *out = f;
+    return true;
+}
+
+}  // namespace
+
+struct gf_lattice_ {
+    int32_t dims[4] = {0, 0, 0, 0};
+    gf_prec prec = GF_FP64;
+    hipStream_t stream = nullptr;
+    Geom geom{};
+    int64_t volume = 0;
+    int64_t bytes = 0;
+    gf::ChunkOf<double>::T* f64 = nullptr;  // float64 links (GF_FP64, GF_MIXED polish and rebuild)
+    gf::ChunkOf<float>::T* f32 = nullptr;   // float32 links (GF_FP32, GF_MIXED bulk)
+    double* partial = nullptr;
+    double* dres = nullptr;
+    double* hres = nullptr;  // pinned
+    bool has_links = false;
+    uint32_t anneal_sweeps = 0;
+    SweepConfig cfg64;
+    SweepConfig cfg32;
+};
+
+namespace {
+
+LinkField<double> field64(const gf_lattice_* L)
+{
+    return LinkField<double>{L->f64, L->geom.ld};
+}
+
+LinkField<float> field32(const gf_lattice_* L)
+{
+    return LinkField<float>{L->f32, L->geom.ld};
+}
+
+bool is_fp32(const gf_lattice_* L)
+{
+    return L->prec == GF_FP32;
+}
+
+gf_status check_ready(gf_lattice L)
+{
+    if (!L) return fail(GF_E_ARG, "null lattice");
+    if (!L->has_links) return fail(GF_E_STATE, "links were never set on this lattice");
+    return GF_OK;
+}
+
+gf_status check_omega(double omega, int mode)
+{
+    if (!(omega >= 1.0 && omega < 2.0)) return fail(GF_E_ARG, "omega = %g is outside [1, 2)", omega);
+    if (mode != GF_OR_EXACT && mode != GF_OR_BINOMIAL1) return fail(GF_E_ARG, "unknown overrelaxation mode %d", mode);
+    return GF_OK;
+}
+
+gf_status do_half_sweep(gf_lattice L, int parity, double omega, int mode)
+{
+    if (is_fp32(L))
+        GF_HIP(gf::launch_or_half_sweep(field32(L), L->geom, parity, (float)omega, mode, L->cfg32, L->stream));
+    else
+        GF_HIP(gf::launch_or_half_sweep(field64(L), L->geom, parity, omega, mode, L->cfg64, L->stream));
+    return GF_OK;
+}
+
+gf_status do_sweeps(gf_lattice L, int32_t n, double omega, int mode)
+{
+    for (int32_t k = 0; k < n; ++k) {
+        GF_TRY(do_half_sweep(L, 0, omega, mode));
+        GF_TRY(do_half_sweep(L, 1, omega, mode));
+    }
+    return GF_OK;
+}
+
+gf_status do_reunitarize(gf_lattice L)
+{
+    if (is_fp32(L))
+        GF_HIP(gf::launch_reunitarize(field32(L), L->geom, L->stream));
+    else
+        GF_HIP(gf::launch_reunitarize(field64(L), L->geom, L->stream));
+    return GF_OK;
+}
+
+gf_status do_measure(gf_lattice L, double* theta, double* F)
+{
+    if (is_fp32(L))
+        GF_HIP(gf::launch_measure(field32(L), L->geom, L->partial, L->dres, L->stream));
+    else
+        GF_HIP(gf::launch_measure(field64(L), L->geom, L->partial, L->dres, L->stream));
+    GF_HIP(hipMemcpyAsync(L->hres, L->dres, 2 * sizeof(double), hipMemcpyDeviceToHost, L->stream));
+    GF_HIP(hipStreamSynchronize(L->stream));
+    *theta = L->hres[0];
+    *F = L->hres[1];
+    if (!std::isfinite(*theta) || !std::isfinite(*F))
+        return fail(GF_E_NUMERIC, "theta = %g, F = %g is not finite", *theta, *F);
+    return GF_OK;
+}
+
+gf_status upload_canonical(gf_lattice L, const double* dev_canon)
+{
+    if (is_fp32(L))
+        GF_HIP(gf::launch_pack(dev_canon, field32(L), L->geom, L->stream));
+    else
+        GF_HIP(gf::launch_pack(dev_canon, field64(L), L->geom, L->stream));
+    L->has_links = true;
+    L->anneal_sweeps = 0;
+    return GF_OK;
+}
+
+gf_status download_canonical(gf_lattice L, double* dev_canon)
+{
+    if (is_fp32(L))
+        GF_HIP(gf::launch_unpack(field32(L), L->geom, dev_canon, L->stream));
+    else
+        GF_HIP(gf::launch_unpack(field64(L), L->geom, dev_canon, L->stream));
+    return GF_OK;
+}
+
+void release(gf_lattice L)
+{
+    if (L->f64) (void)hipFree(L->f64);
+    if (L->f32) (void)hipFree(L->f32);
+    if (L->partial) (void)hipFree(L->partial);
+    if (L->dres) (void)hipFree(L->dres);
+    if (L->hres) (void)hipHostFree(L->hres);
+    L->f64 = nullptr;
+    L->f32 = nullptr;
+    L->partial = nullptr;
+    L->dres = nullptr;
+    L->hres = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gf_last_error(void)
+{
+    return g_last_error.c_str();
+}
+
+const char* gf_version(void)
+{
+    return "libgf 0.1 (gfx950)";
+}
+
+gf_status gf_create_lattice(const int32_t dims[4], gf_prec prec, void* hip_stream, gf_lattice* out)
+{
+    if (!dims || !out) return fail(GF_E_ARG, "null argument");
+    *out = nullptr;
+    int64_t V = 1;
+    for (int m = 0; m < 4; ++m) {
+        if (dims[m] < 2 || dims[m] % 2 != 0)
+            return fail(GF_E_ARG, "extent %d of direction %d must be even and >= 2", dims[m], m);
+        V *= dims[m];
+    }
+    if (V > (int64_t)1 << 31) return fail(GF_E_ARG, "volume %lld exceeds 2^31 sites", (long long)V);
+    if (prec != GF_FP64 && prec != GF_FP32) return fail(GF_E_ARG, "unsupported precision %d", (int)prec);
+
+    gf_lattice_* L = new (std::nothrow) gf_lattice_();
+    if (!L) return fail(GF_E_NOMEM, "host allocation failed");
+    for (int m = 0; m < 4; ++m) L->dims[m] = dims[m];
+    L->prec = prec;
+    L->stream = (hipStream_t)hip_stream;
+    L->volume = V;
+
+    Geom& g = L->geom;
+    for (int m = 0; m < 4; ++m) g.n[m] = dims[m];
+    g.hx = dims[0] / 2;
+    g.vh = (uint32_t)(V / 2);
+    g.ld = (g.vh + 63u) & ~63u;
+    g.hs1 = (uint32_t)g.hx;
+    g.hs2 = (uint32_t)g.hx * (uint32_t)dims[1];
+    g.hs3 = g.hs2 * (uint32_t)dims[2];
+    if (!make_fastdiv((uint32_t)g.hx, g.vh, &g.div_hx) ||
+        !make_fastdiv((uint32_t)dims[1], g.vh / (uint32_t)g.hx, &g.div_ny) ||
+        !make_fastdiv((uint32_t)dims[2], g.vh / g.hs2, &g.div_nz)) {
+        delete L;
+        return fail(GF_E_ARG, "internal: index division check failed");
+    }
+
+    const size_t nchunks = (size_t)2 * 4 * g.ld;  // per chunk slot
+    hipError_t e = hipSuccess;
+    if (prec == GF_FP64) {
+        e = hipMalloc((void**)&L->f64, nchunks * 6 * sizeof(double2));
+        L->bytes += (int64_t)(nchunks * 6 * sizeof(double2));
+    } else {
+        e = hipMalloc((void**)&L->f32, nchunks * 3 * sizeof(float4));
+        L->bytes += (int64_t)(nchunks * 3 * sizeof(float4));
+    }
+    const size_t np = 2 * (size_t)gf::measure_blocks(g);
+    if (e == hipSuccess) e = hipMalloc((void**)&L->partial, np * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&L->dres, 4 * sizeof(double));
+    if (e == hipSuccess) e = hipHostMalloc((void**)&L->hres, 4 * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        release(L);
+        delete L;
+        return fail(e == hipErrorOutOfMemory ? GF_E_NOMEM : GF_E_HIP, "allocation failed: %s", hipGetErrorString(e));
+    }
+    L->bytes += (int64_t)(np * sizeof(double));
+    L->cfg64 = SweepConfig{4, 256};
+    L->cfg32 = SweepConfig{4, 256};
+    *out = L;
+    return GF_OK;
+}
+
+gf_status gf_destroy_lattice(gf_lattice L)
+{
+    if (!L) return GF_OK;
+    hipError_t e = hipStreamSynchronize(L->stream);
+    release(L);
+    delete L;
+    if (e != hipSuccess) return fail(GF_E_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    return GF_OK;
+}
+
+gf_status gf_lattice_info(gf_lattice L, int64_t* volume, int64_t* device_bytes)
+{
+    if (!L) return fail(GF_E_ARG, "null lattice");
+    if (volume) *volume = L->volume;
+    if (device_bytes) *device_bytes = L->bytes;
+    return GF_OK;
+}
+
+gf_status gf_set_sweep_config(gf_lattice L, int32_t tps, int32_t block)
+{
+    if (!L) return fail(GF_E_ARG, "null lattice");
+    SweepConfig c{tps, block};
+    if (!gf::sweep_config_valid(c))
+        return fail(GF_E_ARG, "sweep config tps=%d block=%d: tps must be 1, 2, 4 or 8 and block 64..512", tps, block);
+    if (is_fp32(L))
+        L->cfg32 = c;
+    else
+        L->cfg64 = c;
+    return GF_OK;
+}
+
+gf_status gf_set_links_device(gf_lattice L, const double* dev)
+{
+    if (!L || !dev) return fail(GF_E_ARG, "null argument");
+    return upload_canonical(L, dev);
+}
+
+gf_status gf_set_links(gf_lattice L, const double* host)
+{
+    if (!L || !host) return fail(GF_E_ARG, "null argument");
+    const size_t bytes = (size_t)L->volume * 4 * 18 * sizeof(double);
+    double* stage = nullptr;
+    GF_HIP(hipMalloc((void**)&stage, bytes));
+    hipError_t e = hipMemcpyAsync(stage, host, bytes, hipMemcpyHostToDevice, L->stream);
+    gf_status st = GF_OK;
+    if (e == hipSuccess) st = upload_canonical(L, stage);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    (void)hipFree(stage);
+    if (e != hipSuccess) return fail(GF_E_HIP, "set_links: %s", hipGetErrorString(e));
+    return st;
+}
+
+gf_status gf_get_links_device(gf_lattice L, double* dev)
+{
+    GF_TRY(check_ready(L));
+    if (!dev) return fail(GF_E_ARG, "null argument");
+    return download_canonical(L, dev);
+}
+
+gf_status gf_get_links(gf_lattice L, double* host)
+{
+    GF_TRY(check_ready(L));
+    if (!host) return fail(GF_E_ARG, "null argument");
+    const size_t bytes = (size_t)L->volume * 4 * 18 * sizeof(double);
+    double* stage = nullptr;
+    GF_HIP(hipMalloc((void**)&stage, bytes));
+    gf_status st = download_canonical(L, stage);
+    hipError_t e = hipSuccess;
+    if (st == GF_OK) e = hipMemcpyAsync(host, stage, bytes, hipMemcpyDeviceToHost, L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    (void)hipFree(stage);
+    if (e != hipSuccess) return fail(GF_E_HIP, "get_links: %s", hipGetErrorString(e));
+    return st;
+}
+
+gf_status gf_sweep_or(gf_lattice L, int32_t n_sweeps, double omega, gf_or_mode mode)
+{
+    GF_TRY(check_ready(L));
+    GF_TRY(check_omega(omega, (int)mode));
+    if (n_sweeps < 0) return fail(GF_E_ARG, "n_sweeps = %d < 0", n_sweeps);
+    return do_sweeps(L, n_sweeps, omega, (int)mode);
+}
+
+gf_status gf_half_sweep_or(gf_lattice L, int32_t colour, double omega, gf_or_mode mode)
+{
+    GF_TRY(check_ready(L));
+    GF_TRY(check_omega(omega, (int)mode));
+    if (colour != 0 && colour != 1) return fail(GF_E_ARG, "colour must be 0 (black) or 1 (white)");
+    return do_half_sweep(L, colour, omega, (int)mode);
+}
+
+gf_status gf_anneal(gf_lattice L, int32_t n_sweeps, double T_start, double T_end, uint64_t seed)
+{
+    GF_TRY(check_ready(L));
+    (void)n_sweeps;
+    (void)T_start;
+    (void)T_end;
+    (void)seed;
+    return fail(GF_E_STATE, "gf_anneal is not available in this build");
+}
+
+gf_status gf_measure_theta_F(gf_lattice L, double* theta, double* F)
+{
+    GF_TRY(check_ready(L));
+    if (!theta || !F) return fail(GF_E_ARG, "null argument");
+    return do_measure(L, theta, F);
+}
+
+gf_status gf_reunitarize(gf_lattice L)
+{
+    GF_TRY(check_ready(L));
+    return do_reunitarize(L);
+}
+
+gf_status gf_plaquette(gf_lattice L, double* P)
+{
+    GF_TRY(check_ready(L));
+    if (!P) return fail(GF_E_ARG, "null argument");
+    if (is_fp32(L))
+        GF_HIP(gf::launch_plaquette(field32(L), L->geom, L->partial, L->dres, L->stream));
+    else
+        GF_HIP(gf::launch_plaquette(field64(L), L->geom, L->partial, L->dres, L->stream));
+    GF_HIP(hipMemcpyAsync(L->hres, L->dres, sizeof(double), hipMemcpyDeviceToHost, L->stream));
+    GF_HIP(hipStreamSynchronize(L->stream));
+    *P = L->hres[0];
+    if (!std::isfinite(*P)) return fail(GF_E_NUMERIC, "plaquette is not finite");
+    return GF_OK;
+}
+
+gf_status gf_fix_until(gf_lattice L, const gf_fix_params* p, gf_fix_result* res)
+{
+    GF_TRY(check_ready(L));
+    if (!p || !res) return fail(GF_E_ARG, "null argument");
+    GF_TRY(check_omega(p->omega, p->mode));
+    if (p->max_sweeps < 0 || p->check_every < 1 || p->reunit_every < 0)
+        return fail(GF_E_ARG, "need max_sweeps >= 0, check_every >= 1, reunit_every >= 0");
+    if (!(p->theta_target >= 0.0)) return fail(GF_E_ARG, "theta_target must be >= 0");
+    std::memset(res, 0, sizeof *res);
+    double theta = 0.0, F = 0.0;
+    GF_TRY(do_measure(L, &theta, &F));
+    int32_t sweeps = 0;
+    while (theta >= p->theta_target && sweeps < p->max_sweeps) {
+        const int32_t n = std::min(p->check_every, p->max_sweeps - sweeps);
+        for (int32_t k = 0; k < n; ++k) {
+            GF_TRY(do_sweeps(L, 1, p->omega, p->mode));
+            ++sweeps;
+            if (p->reunit_every > 0 && sweeps % p->reunit_every == 0) GF_TRY(do_reunitarize(L));
+        }
+        GF_TRY(do_measure(L, &theta, &F));
+    }
+    res->converged = theta < p->theta_target;
+    res->sweeps = sweeps;
+    if (is_fp32(L))
+        res->sweeps_fp32 = sweeps;
+    else
+        res->sweeps_fp64 = sweeps;
+    res->theta = theta;
+    res->F = F;
+    return GF_OK;
+}
+
+}  // extern "C"

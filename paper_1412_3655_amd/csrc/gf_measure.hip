@@ -1,0 +1,374 @@
+// gf_measure.hip -- lattice reductions (gauge condition theta, functional F,
+// plaquette), reunitarisation and layout conversion for libgf on gfx950.
+//
+// theta / F (Sec. 2 of arXiv:1412.3655): with K(x) as in Eq. (localfunctional),
+//   Delta(x) = sum_mu (A_mu(x) - A_mu(x-mu^)) = [(K(x) - K(x)^dag)/(2i)]_traceless
+// (A_mu of Sec. 2 with a g = 1; the two forms are equal term by term), and
+//   theta = (1/(3V)) sum_x tr[Delta Delta^dag],
+//   F     = (1/(12V)) sum_x sum_mu Re tr U_mu(x)     (Eq. landaufunctional, g = 1).
+// One thread per site (both colours), float64 arithmetic and sums whatever the
+// link precision; wavefront sums by xor-shuffles, block sums through LDS, one
+// partial per block, then one block adds the partials in index order.  The
+// reduction order depends only on the lattice shape, so results are bitwise
+// reproducible.  Traffic: every link is read twice (once from each end),
+// 768 B per site in FP64.
+#include "gf_kernels.h"
+
+namespace gf {
+
+namespace {
+
+constexpr int RBLOCK = 256;
+
+template <typename R>
+__device__ __forceinline__ void load_full_f64(const LinkField<R>& f, int parity, int mu, uint32_t h, M3<double>& u)
+{
+    M3<R> t;
+    load_rows01(f, parity, mu, h, t);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            u.re[i][j] = (double)t.re[i][j];
+            u.im[i][j] = (double)t.im[i][j];
+        }
+    rebuild_row2(u);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum two values over the block; thread 0 writes them to out[0..1].
+template <int NT>
+__device__ __forceinline__ void block_sum2(double a, double b, double* out)
+{
+    __shared__ double lds[2][NT / 64];
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int w = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0) {
+        lds[0][w] = a;
+        lds[1][w] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sa = 0.0, sb = 0.0;
+        for (int i = 0; i < NT / 64; ++i) {
+            sa += lds[0][i];
+            sb += lds[1][i];
+        }
+        out[0] = sa;
+        out[1] = sb;
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(RBLOCK) k_measure(LinkField<R> f, Geom g, double* partial)
+{
+    const int parity = blockIdx.y;
+    const uint32_t h = blockIdx.x * RBLOCK + threadIdx.x;
+    double th = 0.0, fr = 0.0;
+    if (h < g.vh) {
+        const Site s = decode_site(g, parity, h);
+        M3<double> K;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                K.re[i][j] = 0.0;
+                K.im[i][j] = 0.0;
+            }
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            M3<double> u;
+            load_full_f64(f, parity, mu, h, u);
+            fr += u.re[0][0] + u.re[1][1] + u.re[2][2];
+            m_add(K, u);
+            load_full_f64(f, 1 - parity, mu, back_h(g, h, s, mu), u);
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    K.re[i][j] += u.re[j][i];
+                    K.im[i][j] -= u.im[j][i];
+                }
+        }
+        // M = (K - K^dag)/(2i): diagonal Im K_ii; off-diagonal
+        // ((Im K_ij + Im K_ji) - i (Re K_ij - Re K_ji)) / 2.  Delta = M - tr(M)/3.
+        const double d0 = K.im[0][0], d1 = K.im[1][1], d2 = K.im[2][2];
+        const double tr3 = (d0 + d1 + d2) / 3.0;
+        const double e0 = d0 - tr3, e1 = d1 - tr3, e2 = d2 - tr3;
+        double off = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = i + 1; j < 3; ++j) {
+                const double mr = 0.5 * (K.im[i][j] + K.im[j][i]);
+                const double mi = 0.5 * (K.re[i][j] - K.re[j][i]);
+                off += mr * mr + mi * mi;
+            }
+        th = e0 * e0 + e1 * e1 + e2 * e2 + 2.0 * off;
+    }
+    block_sum2<RBLOCK>(th, fr, partial + 2 * (size_t)(blockIdx.y * gridDim.x + blockIdx.x));
+}
+
+// Re tr[U_mu(x) U_nu(x+mu^) U_mu(x+nu^)^dag U_nu(x)^dag] summed over mu < nu.
+template <typename R>
+__global__ void __launch_bounds__(RBLOCK) k_plaquette(LinkField<R> f, Geom g, double* partial)
+{
+    const int parity = blockIdx.y;
+    const uint32_t h = blockIdx.x * RBLOCK + threadIdx.x;
+    double acc = 0.0;
+    if (h < g.vh) {
+        const Site s = decode_site(g, parity, h);
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+            for (int nu = mu + 1; nu < 4; ++nu) {
+                M3<double> a, b, c, d;
+                load_full_f64(f, parity, mu, h, a);
+                load_full_f64(f, 1 - parity, nu, fwd_h(g, h, s, mu), b);
+                load_full_f64(f, 1 - parity, mu, fwd_h(g, h, s, nu), c);
+                load_full_f64(f, parity, nu, h, d);
+                // P = a b, Q = d c; tr[P Q^dag] = sum_ij P_ij conj(Q_ij)
+                double re = 0.0;
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        double pr = 0.0, pi = 0.0, qr = 0.0, qi = 0.0;
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) {
+                            pr += a.re[i][k] * b.re[k][j] - a.im[i][k] * b.im[k][j];
+                            pi += a.re[i][k] * b.im[k][j] + a.im[i][k] * b.re[k][j];
+                            qr += d.re[i][k] * c.re[k][j] - d.im[i][k] * c.im[k][j];
+                            qi += d.re[i][k] * c.im[k][j] + d.im[i][k] * c.re[k][j];
+                        }
+                        re += pr * qr + pi * qi;
+                    }
+                acc += re;
+            }
+    }
+    block_sum2<RBLOCK>(acc, 0.0, partial + 2 * (size_t)(blockIdx.y * gridDim.x + blockIdx.x));
+}
+
+// out[k] = scale[k] * sum_i partial[2 i + k], summed in a fixed order.
+__global__ void __launch_bounds__(RBLOCK) k_finalize(const double* partial, uint32_t n, double s0, double s1, double* out)
+{
+    double a = 0.0, b = 0.0;
+    for (uint32_t i = threadIdx.x; i < n; i += RBLOCK) {
+        a += partial[2 * (size_t)i];
+        b += partial[2 * (size_t)i + 1];
+    }
+    __shared__ double res[2];
+    block_sum2<RBLOCK>(a, b, res);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[0] = res[0] * s0;
+        out[1] = res[1] * s1;
+    }
+}
+
+// Gram-Schmidt on rows 0, 1 (row 2 stays implicit).
+template <typename R>
+__global__ void __launch_bounds__(RBLOCK) k_reunitarize(LinkField<R> f, uint32_t vh)
+{
+    const uint32_t h = blockIdx.x * RBLOCK + threadIdx.x;
+    if (h >= vh) return;
+    const int parity = blockIdx.y >> 2, mu = blockIdx.y & 3;
+    M3<R> u;
+    load_rows01(f, parity, mu, h, u);
+    R n0 = R(0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) n0 += u.re[0][j] * u.re[0][j] + u.im[0][j] * u.im[0][j];
+    const R i0 = R(1) / sqrt(n0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        u.re[0][j] *= i0;
+        u.im[0][j] *= i0;
+    }
+    // <r0, r1> = sum conj(r0_j) r1_j
+    R pr = R(0), pi = R(0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        pr += u.re[0][j] * u.re[1][j] + u.im[0][j] * u.im[1][j];
+        pi += u.re[0][j] * u.im[1][j] - u.im[0][j] * u.re[1][j];
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        u.re[1][j] -= pr * u.re[0][j] - pi * u.im[0][j];
+        u.im[1][j] -= pr * u.im[0][j] + pi * u.re[0][j];
+    }
+    R n1 = R(0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) n1 += u.re[1][j] * u.re[1][j] + u.im[1][j] * u.im[1][j];
+    const R i1 = R(1) / sqrt(n1);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        u.re[1][j] *= i1;
+        u.im[1][j] *= i1;
+    }
+    store_rows01(f, parity, mu, h, u);
+}
+
+// canonical lex site s, direction mu -> (colour, half index)
+__device__ __forceinline__ void lex_to_half(const Geom& g, uint32_t s, int* parity, uint32_t* h)
+{
+    uint32_t x = s % (uint32_t)g.n[0];
+    uint32_t r = s / (uint32_t)g.n[0];
+    uint32_t y = r % (uint32_t)g.n[1];
+    r /= (uint32_t)g.n[1];
+    uint32_t z = r % (uint32_t)g.n[2];
+    uint32_t t = r / (uint32_t)g.n[2];
+    *parity = (int)((x + y + z + t) & 1u);
+    *h = s >> 1;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(RBLOCK) k_pack(const double* canon, LinkField<R> f, Geom g)
+{
+    const uint64_t gid = (uint64_t)blockIdx.x * RBLOCK + threadIdx.x;
+    const uint64_t nlinks = (uint64_t)g.vh * 8;
+    if (gid >= nlinks) return;
+    const uint32_t s = (uint32_t)(gid >> 2);
+    const int mu = (int)(gid & 3);
+    int parity;
+    uint32_t h;
+    lex_to_half(g, s, &parity, &h);
+    const double* src = canon + gid * 18;
+    M3<R> u;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            u.re[i][j] = (R)src[(i * 3 + j) * 2];
+            u.im[i][j] = (R)src[(i * 3 + j) * 2 + 1];
+        }
+    store_rows01(f, parity, mu, h, u);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(RBLOCK) k_unpack(LinkField<R> f, Geom g, double* canon)
+{
+    const uint64_t gid = (uint64_t)blockIdx.x * RBLOCK + threadIdx.x;
+    const uint64_t nlinks = (uint64_t)g.vh * 8;
+    if (gid >= nlinks) return;
+    const uint32_t s = (uint32_t)(gid >> 2);
+    const int mu = (int)(gid & 3);
+    int parity;
+    uint32_t h;
+    lex_to_half(g, s, &parity, &h);
+    M3<double> u;
+    load_full_f64(f, parity, mu, h, u);
+    double* dst = canon + gid * 18;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            dst[(i * 3 + j) * 2] = u.re[i][j];
+            dst[(i * 3 + j) * 2 + 1] = u.im[i][j];
+        }
+}
+
+uint32_t site_blocks(const Geom& g)
+{
+    return (g.vh + RBLOCK - 1) / RBLOCK;
+}
+
+template <typename R>
+hipError_t measure_impl(const LinkField<R>& f, const Geom& g, double* partial, double* out, hipStream_t st)
+{
+    const uint32_t nb = site_blocks(g);
+    hipLaunchKernelGGL((k_measure<R>), dim3(nb, 2), dim3(RBLOCK), 0, st, f, g, partial);
+    const double V = 2.0 * (double)g.vh;
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RBLOCK), 0, st, partial, 2 * nb, 1.0 / (3.0 * V), 1.0 / (12.0 * V),
+                       out);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t plaquette_impl(const LinkField<R>& f, const Geom& g, double* partial, double* out, hipStream_t st)
+{
+    const uint32_t nb = site_blocks(g);
+    hipLaunchKernelGGL((k_plaquette<R>), dim3(nb, 2), dim3(RBLOCK), 0, st, f, g, partial);
+    const double V = 2.0 * (double)g.vh;
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RBLOCK), 0, st, partial, 2 * nb, 1.0 / (18.0 * V), 0.0, out);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t reunit_impl(const LinkField<R>& f, const Geom& g, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_reunitarize<R>), dim3(site_blocks(g), 8), dim3(RBLOCK), 0, st, f, g.vh);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t pack_impl(const double* canon, const LinkField<R>& f, const Geom& g, hipStream_t st)
+{
+    const uint64_t n = (uint64_t)g.vh * 8;
+    hipLaunchKernelGGL((k_pack<R>), dim3((uint32_t)((n + RBLOCK - 1) / RBLOCK)), dim3(RBLOCK), 0, st, canon, f, g);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t unpack_impl(const LinkField<R>& f, const Geom& g, double* canon, hipStream_t st)
+{
+    const uint64_t n = (uint64_t)g.vh * 8;
+    hipLaunchKernelGGL((k_unpack<R>), dim3((uint32_t)((n + RBLOCK - 1) / RBLOCK)), dim3(RBLOCK), 0, st, f, g, canon);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+uint32_t measure_blocks(const Geom& g)
+{
+    return 2 * site_blocks(g);
+}
+
+hipError_t launch_measure(const LinkField<double>& f, const Geom& g, double* p, double* o, hipStream_t st)
+{
+    return measure_impl(f, g, p, o, st);
+}
+hipError_t launch_measure(const LinkField<float>& f, const Geom& g, double* p, double* o, hipStream_t st)
+{
+    return measure_impl(f, g, p, o, st);
+}
+hipError_t launch_plaquette(const LinkField<double>& f, const Geom& g, double* p, double* o, hipStream_t st)
+{
+    return plaquette_impl(f, g, p, o, st);
+}
+hipError_t launch_plaquette(const LinkField<float>& f, const Geom& g, double* p, double* o, hipStream_t st)
+{
+    return plaquette_impl(f, g, p, o, st);
+}
+hipError_t launch_reunitarize(const LinkField<double>& f, const Geom& g, hipStream_t st)
+{
+    return reunit_impl(f, g, st);
+}
+hipError_t launch_reunitarize(const LinkField<float>& f, const Geom& g, hipStream_t st)
+{
+    return reunit_impl(f, g, st);
+}
+hipError_t launch_pack(const double* c, const LinkField<double>& f, const Geom& g, hipStream_t st)
+{
+    return pack_impl(c, f, g, st);
+}
+hipError_t launch_pack(const double* c, const LinkField<float>& f, const Geom& g, hipStream_t st)
+{
+    return pack_impl(c, f, g, st);
+}
+hipError_t launch_unpack(const LinkField<double>& f, const Geom& g, double* c, hipStream_t st)
+{
+    return unpack_impl(f, g, c, st);
+}
+hipError_t launch_unpack(const LinkField<float>& f, const Geom& g, double* c, hipStream_t st)
+{
+    return unpack_impl(f, g, c, st);
+}
+
+}  // namespace gf

@@ -1,0 +1,342 @@
+"""ctypes binding of libgf (C ABI in include/gf.h).
+
+Argument marshalling only: every step of the gauge-fixing path runs in the
+HIP kernels of libgf.so.  PyTorch is used for device memory (canonical link
+arrays on the GPU) and streams.  If the library is not built, loading fails
+loudly; there is no fallback of any kind.
+
+Function names match the C entry points.  Host link arrays are canonical
+float64 ``(V, 4, 3, 3, 2)`` numpy arrays; device ones are float64 torch
+tensors of the same shape on a HIP device.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgf.so")
+
+GF_OK, GF_E_ARG, GF_E_NOMEM, GF_E_HIP, GF_E_STATE, GF_E_NUMERIC, GF_E_FULL = range(7)
+GF_FP64, GF_FP32, GF_MIXED = 0, 1, 2
+GF_OR_EXACT, GF_OR_BINOMIAL1 = 0, 1
+
+_STATUS_NAMES = {
+    GF_OK: "GF_OK",
+    GF_E_ARG: "GF_E_ARG",
+    GF_E_NOMEM: "GF_E_NOMEM",
+    GF_E_HIP: "GF_E_HIP",
+    GF_E_STATE: "GF_E_STATE",
+    GF_E_NUMERIC: "GF_E_NUMERIC",
+    GF_E_FULL: "GF_E_FULL",
+}
+
+
+class GFError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class gf_fix_params(ctypes.Structure):
+    _fields_ = [
+        ("omega", ctypes.c_double),
+        ("mode", ctypes.c_int32),
+        ("theta_target", ctypes.c_double),
+        ("max_sweeps", ctypes.c_int32),
+        ("check_every", ctypes.c_int32),
+        ("reunit_every", ctypes.c_int32),
+        ("theta_switch", ctypes.c_double),
+    ]
+
+
+class gf_fix_result(ctypes.Structure):
+    _fields_ = [
+        ("converged", ctypes.c_int32),
+        ("sweeps", ctypes.c_int32),
+        ("sweeps_fp32", ctypes.c_int32),
+        ("sweeps_fp64", ctypes.c_int32),
+        ("theta", ctypes.c_double),
+        ("F", ctypes.c_double),
+    ]
+
+
+@dataclass
+class FixResult:
+    converged: bool
+    sweeps: int
+    sweeps_fp32: int
+    sweeps_fp64: int
+    theta: float
+    F: float
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_dp = ctypes.POINTER(ctypes.c_double)
+
+# C entry points: name -> argtypes (all return gf_status unless listed in _RESTYPES)
+_SIGNATURES = {
+    "gf_create_lattice": [ctypes.POINTER(_i32), ctypes.c_int, _vp, ctypes.POINTER(_vp)],
+    "gf_destroy_lattice": [_vp],
+    "gf_lattice_info": [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
+    "gf_set_sweep_config": [_vp, _i32, _i32],
+    "gf_set_links": [_vp, _dp],
+    "gf_set_links_device": [_vp, _vp],
+    "gf_get_links": [_vp, _dp],
+    "gf_get_links_device": [_vp, _vp],
+    "gf_sweep_or": [_vp, _i32, ctypes.c_double, ctypes.c_int],
+    "gf_half_sweep_or": [_vp, _i32, ctypes.c_double, ctypes.c_int],
+    "gf_anneal": [_vp, _i32, ctypes.c_double, ctypes.c_double, ctypes.c_uint64],
+    "gf_measure_theta_F": [_vp, _dp, _dp],
+    "gf_fix_until": [_vp, ctypes.POINTER(gf_fix_params), ctypes.POINTER(gf_fix_result)],
+    "gf_reunitarize": [_vp],
+    "gf_plaquette": [_vp, _dp],
+    "gf_last_error": [],
+    "gf_version": [],
+}
+_RESTYPES = {"gf_last_error": ctypes.c_char_p, "gf_version": ctypes.c_char_p}
+
+
+def _check_single_hip_runtime():
+    """libgf must share the process's HIP runtime with torch (one libamdhip64)."""
+    try:
+        with open("/proc/self/maps") as fh:
+            paths = {line.split()[-1] for line in fh if "libamdhip64" in line}
+    except OSError:
+        return
+    real = {os.path.realpath(p) for p in paths}
+    if len(real) > 1:
+        raise RuntimeError(f"two HIP runtimes are loaded in this process: {sorted(real)}")
+
+
+def lib() -> ctypes.CDLL:
+    """Load libgf.so (after torch, whose HIP runtime it shares)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'`")
+    import torch  # noqa: F401  (loads the HIP runtime first)
+
+    L = ctypes.CDLL(LIB_PATH)
+    for name, args in _SIGNATURES.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = _RESTYPES.get(name, ctypes.c_int)
+    _check_single_hip_runtime()
+    _lib = L
+    return L
+
+
+def exported_symbols():
+    return list(_SIGNATURES)
+
+
+def _call(name, *args):
+    st = getattr(lib(), name)(*args)
+    if st != GF_OK:
+        raise GFError(st, lib().gf_last_error().decode(errors="replace"))
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)  # torch.cuda.Stream
+
+
+def _host_links(u: np.ndarray, volume: int) -> np.ndarray:
+    if not (isinstance(u, np.ndarray) and u.dtype == np.float64 and u.flags.c_contiguous):
+        raise TypeError("host links must be a C-contiguous float64 numpy array")
+    if u.size != volume * 72:
+        raise ValueError(f"host links hold {u.size} doubles, the lattice needs {volume * 72}")
+    return u
+
+
+def _is_device_tensor(x) -> bool:
+    try:
+        import torch
+    except ImportError:
+        return False
+    return isinstance(x, torch.Tensor) and x.is_cuda
+
+
+def _device_links(t, volume: int):
+    import torch
+
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("device links must be a contiguous float64 tensor")
+    if t.numel() != volume * 72:
+        raise ValueError(f"device links hold {t.numel()} doubles, the lattice needs {volume * 72}")
+    return t
+
+
+# ----------------------------------------------------------- entry points --
+
+
+def gf_version() -> str:
+    return lib().gf_version().decode()
+
+
+def gf_last_error() -> str:
+    return lib().gf_last_error().decode(errors="replace")
+
+
+def gf_create_lattice(dims, prec: int = GF_FP64, stream=None) -> ctypes.c_void_p:
+    d = (_i32 * 4)(*[int(x) for x in dims])
+    out = _vp()
+    _call("gf_create_lattice", d, int(prec), _stream_handle(stream), ctypes.byref(out))
+    return out
+
+
+def gf_destroy_lattice(lat) -> None:
+    _call("gf_destroy_lattice", lat)
+
+
+def gf_lattice_info(lat):
+    v = ctypes.c_int64()
+    b = ctypes.c_int64()
+    _call("gf_lattice_info", lat, ctypes.byref(v), ctypes.byref(b))
+    return v.value, b.value
+
+
+def gf_set_sweep_config(lat, tps: int, block: int) -> None:
+    _call("gf_set_sweep_config", lat, int(tps), int(block))
+
+
+def gf_set_links(lat, links) -> None:
+    volume, _ = gf_lattice_info(lat)
+    if _is_device_tensor(links):
+        t = _device_links(links, volume)
+        _call("gf_set_links_device", lat, t.data_ptr())
+    else:
+        u = _host_links(links, volume)
+        _call("gf_set_links", lat, u.ctypes.data_as(_dp))
+
+
+def gf_set_links_device(lat, dev_ptr: int) -> None:
+    _call("gf_set_links_device", lat, int(dev_ptr))
+
+
+def gf_get_links(lat, out=None):
+    """Links as a canonical array: into `out` (numpy or device tensor) or a new numpy array."""
+    volume, _ = gf_lattice_info(lat)
+    if out is None:
+        out = np.empty((volume, 4, 3, 3, 2), dtype=np.float64)
+    if _is_device_tensor(out):
+        t = _device_links(out, volume)
+        _call("gf_get_links_device", lat, t.data_ptr())
+    else:
+        u = _host_links(out, volume)
+        _call("gf_get_links", lat, u.ctypes.data_as(_dp))
+    return out
+
+
+def gf_get_links_device(lat, dev_ptr: int) -> None:
+    _call("gf_get_links_device", lat, int(dev_ptr))
+
+
+def gf_sweep_or(lat, n_sweeps: int, omega: float, mode: int = GF_OR_EXACT) -> None:
+    _call("gf_sweep_or", lat, int(n_sweeps), float(omega), int(mode))
+
+
+def gf_half_sweep_or(lat, colour: int, omega: float, mode: int = GF_OR_EXACT) -> None:
+    _call("gf_half_sweep_or", lat, int(colour), float(omega), int(mode))
+
+
+def gf_anneal(lat, n_sweeps: int, T_start: float, T_end: float, seed: int) -> None:
+    _call("gf_anneal", lat, int(n_sweeps), float(T_start), float(T_end), int(seed) & 0xFFFFFFFFFFFFFFFF)
+
+
+def gf_measure_theta_F(lat):
+    th = ctypes.c_double()
+    f = ctypes.c_double()
+    _call("gf_measure_theta_F", lat, ctypes.byref(th), ctypes.byref(f))
+    return th.value, f.value
+
+
+def gf_fix_until(lat, omega: float = 1.7, mode: int = GF_OR_EXACT, theta_target: float = 1e-12,
+                 max_sweeps: int = 3000, check_every: int = 10, reunit_every: int = 100,
+                 theta_switch: float = 1e-8) -> FixResult:
+    p = gf_fix_params(float(omega), int(mode), float(theta_target), int(max_sweeps), int(check_every),
+                      int(reunit_every), float(theta_switch))
+    r = gf_fix_result()
+    _call("gf_fix_until", lat, ctypes.byref(p), ctypes.byref(r))
+    return FixResult(bool(r.converged), r.sweeps, r.sweeps_fp32, r.sweeps_fp64, r.theta, r.F)
+
+
+def gf_reunitarize(lat) -> None:
+    _call("gf_reunitarize", lat)
+
+
+def gf_plaquette(lat) -> float:
+    p = ctypes.c_double()
+    _call("gf_plaquette", lat, ctypes.byref(p))
+    return p.value
+
+
+class Lattice:
+    """Owning wrapper: ``with Lattice(dims, GF_FP64) as lat: ...``."""
+
+    def __init__(self, dims, prec: int = GF_FP64, stream=None):
+        self.dims = tuple(int(d) for d in dims)
+        self.prec = prec
+        self.handle = gf_create_lattice(self.dims, prec, stream)
+
+    @property
+    def volume(self) -> int:
+        return gf_lattice_info(self.handle)[0]
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            gf_destroy_lattice(self.handle)
+        self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_links(self, links):
+        gf_set_links(self.handle, links)
+
+    def get_links(self, out=None):
+        return gf_get_links(self.handle, out)
+
+    def sweep(self, n: int, omega: float, mode: int = GF_OR_EXACT):
+        gf_sweep_or(self.handle, n, omega, mode)
+
+    def half_sweep(self, colour: int, omega: float, mode: int = GF_OR_EXACT):
+        gf_half_sweep_or(self.handle, colour, omega, mode)
+
+    def anneal(self, n: int, T_start: float, T_end: float, seed: int):
+        gf_anneal(self.handle, n, T_start, T_end, seed)
+
+    def measure(self):
+        return gf_measure_theta_F(self.handle)
+
+    def fix_until(self, **kw) -> FixResult:
+        return gf_fix_until(self.handle, **kw)
+
+    def reunitarize(self):
+        gf_reunitarize(self.handle)
+
+    def plaquette(self) -> float:
+        return gf_plaquette(self.handle)
+
+    def set_sweep_config(self, tps: int, block: int):
+        gf_set_sweep_config(self.handle, tps, block)

@@ -1,0 +1,66 @@
+"""The C-ABI library loads and exports every entry point include/gf.h declares.
+
+CPU only: no device work is started; the calls below fail argument checks
+before any HIP call.
+"""
+
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1412_3655_amd import gf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gf.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:gf_status|const char\*)\s+(gf_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("gf_create_lattice", "gf_sweep_or", "gf_anneal", "gf_measure_theta_F", "gf_fix_until",
+                     "gf_reunitarize"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    assert os.path.exists(gf.LIB_PATH), "libgf.so must be built (__graft_entry__.build())"
+    out = subprocess.run(["nm", "-D", "--defined-only", gf.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\sT\s+(gf_\w+)$", out, flags=re.M))
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    L = gf.lib()
+    for n in declared_functions():
+        assert hasattr(L, n)
+
+
+def test_binding_covers_declared_symbols():
+    assert sorted(gf.exported_symbols()) == declared_functions()
+
+
+def test_version_and_argument_checks_without_device():
+    assert "gfx950" in gf.gf_version()
+    for dims in [(4, 4, 3, 4), (0, 4, 4, 4), (4, 4, 4, 1), (4, -2, 4, 4)]:
+        with pytest.raises(gf.GFError) as e:
+            gf.gf_create_lattice(dims)
+        assert e.value.status == gf.GF_E_ARG
+    with pytest.raises(gf.GFError) as e:
+        gf.gf_create_lattice((4, 4, 4, 4), prec=7)
+    assert e.value.status == gf.GF_E_ARG
+    with pytest.raises(gf.GFError) as e:
+        gf.gf_create_lattice((65536, 65536, 2, 2))
+    assert e.value.status == gf.GF_E_ARG
+    for name in ("gf_sweep_or", "gf_measure_theta_F", "gf_reunitarize", "gf_plaquette", "gf_get_links"):
+        fn = getattr(gf.lib(), name)
+        args = {"gf_sweep_or": (None, 1, 1.5, 0), "gf_measure_theta_F": (None, None, None),
+                "gf_reunitarize": (None,), "gf_plaquette": (None, None), "gf_get_links": (None, None)}[name]
+        assert fn(*args) == gf.GF_E_ARG
+    assert "null" in gf.gf_last_error()
+    assert gf.lib().gf_destroy_lattice(None) == gf.GF_OK
