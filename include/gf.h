@@ -94,11 +94,19 @@ gf_status gf_destroy_lattice(gf_lattice lat);
 /* Number of sites V and bytes of device memory held by the lattice. */
 gf_status gf_lattice_info(gf_lattice lat, int64_t* volume, int64_t* device_bytes);
 
-/* Kernel configuration of the overrelaxation sweep of this lattice's working
- * precision: tps lanes per site (1, 2, 4 or 8; the paper's design uses 4 or
- * 8 threads per site, Sec. 4.2) and threads per block (64, 128, 256 or 512).
- * Any valid choice gives bitwise the same links.  Default 4 / 256. */
-gf_status gf_set_sweep_config(gf_lattice lat, int32_t tps, int32_t block);
+/* Kernel configuration of the overrelaxation sweep in precision `kernel`
+ * (GF_FP64 or GF_FP32; a GF_MIXED lattice uses both): tps lanes per site
+ * (1, 2, 4 or 8; the paper's design uses 4 or 8 threads per site, Sec. 4.2)
+ * and threads per block (64, 128, 256 or 512; not 512 with tps 1).  Every
+ * valid choice gives bitwise the same links.  Default 4 / 256. */
+gf_status gf_set_sweep_config(gf_lattice lat, gf_prec kernel, int32_t tps, int32_t block);
+
+/* GF_MIXED: leave the float32 phase now.  The float64 links become
+ * g(x) U0_mu(x) g(x+mu^)^dag, U0 the links given to gf_set_links and g the
+ * float32 transformation accumulated by the float32 sweeps (re-orthonormalised
+ * in float64), so they stay on the gauge orbit of U0 to float64 precision.
+ * No-op for other precisions or after promotion.  Async. */
+gf_status gf_promote_fp64(gf_lattice lat);
 
 /* Upload links from a host canonical array of 4*V*18 doubles; only rows 0
  * and 1 of each link are kept (row 2 is rebuilt as the conjugated cross
@@ -158,6 +166,79 @@ gf_status gf_reunitarize(gf_lattice lat);
 /* Average plaquette (1/(18V)) sum_x sum_{mu<nu} Re tr[U_mu(x) U_nu(x+mu^)
  * U_mu(x+nu^)^dag U_nu(x)^dag], float64 sums; gauge invariant.  Syncs. */
 gf_status gf_plaquette(gf_lattice lat, double* P);
+
+/* ------------------------------------------------------------------------ */
+/* Batched lattices and serving: a pool of resident lattices ("jobs") of any */
+/* shapes swept together.                                                     */
+/*                                                                            */
+/* Every job runs exactly the fix-until iteration of gf_fix_until (optionally */
+/* after gf_anneal) on its own lattice of the pool's precision, so its result */
+/* equals the one it gets alone.  A pool step advances every active job by   */
+/* up to check_every sweeps: per sweep one persistent launch per kernel kind  */
+/* (heat bath, float32 OR tracking g, float64 OR) covers the sites of that    */
+/* colour of every job in that state, then reunitarisation and measurement    */
+/* launches cover the jobs due for them; the launches of a step are captured  */
+/* once in a hipGraph per work structure and replayed.                        */
+/* ------------------------------------------------------------------------ */
+
+typedef struct gf_pool_* gf_pool; /* opaque, library-owned */
+
+typedef struct {
+    size_t hbm_budget;   /* bytes of device memory the pool may hold for job lattices */
+    int32_t max_slots;   /* maximum number of resident jobs, 1..4096 */
+    int32_t prec;        /* gf_prec of every job: GF_MIXED or GF_FP64 */
+    int32_t check_every; /* sweeps per pool step = every job's measurement cadence, >= 1 */
+    int32_t mode;        /* gf_or_mode of every job */
+    int32_t tps32, block32, tps64, block64; /* sweep kernel configurations; 0 = default (4, 256) */
+} gf_pool_config;
+
+typedef struct {
+    uint64_t job_id;
+    gf_fix_result result;
+    int32_t status; /* GF_OK, or the error that ended the job (e.g. GF_E_NUMERIC); other jobs are unaffected */
+    double t_admit; /* seconds on the library's steady clock */
+    double t_done;  /* end of the pool step in which the job finished */
+} gf_pool_done;
+
+/* Create a pool.  hip_stream: a non-default hipStream_t for all pool work,
+ * or NULL to let the pool create its own (default priority).  Allocates only
+ * bookkeeping; job lattices are allocated on admission. */
+gf_status gf_pool_create(const gf_pool_config* cfg, void* hip_stream, gf_pool* out);
+
+/* Wait for the pool's stream and free everything, including unreleased jobs.  NULL is accepted. */
+gf_status gf_pool_destroy(gf_pool pool);
+
+/* Device bytes one job of extents dims needs in a pool of precision prec. */
+gf_status gf_pool_job_bytes(const int32_t dims[4], int32_t prec, int64_t* bytes);
+
+/* Admit a job: copy its host canonical links (4*V*18 doubles) into a new
+ * resident lattice, then (if anneal_sweeps > 0) run anneal_sweeps heat-bath
+ * sweeps from T_start to T_end with Philox key `seed` (as gf_anneal) before the
+ * fix-until iteration with params (as gf_fix_until; params->mode must equal the
+ * pool's mode).  GF_E_FULL (nothing changed) when no slot is free or the
+ * budget would be exceeded; GF_E_ARG for a duplicate job_id or bad
+ * arguments.  Syncs (the first measurement of a job without annealing). */
+gf_status gf_pool_admit(gf_pool pool, uint64_t job_id, const int32_t dims[4], const double* host_links,
+                        const gf_fix_params* params, int32_t anneal_sweeps, double T_start, double T_end,
+                        uint64_t seed);
+
+/* One pool step (see above).  Syncs. */
+gf_status gf_pool_step(gf_pool pool);
+
+/* Move up to cap jobs that finished since the last poll into out[]; *n = count. */
+gf_status gf_pool_poll(gf_pool pool, gf_pool_done* out, int32_t cap, int32_t* n);
+
+/* Download a finished job's links (host canonical array) and free its lattice.  Syncs. */
+gf_status gf_pool_fetch_links(gf_pool pool, uint64_t job_id, double* host);
+
+/* Free a finished job's lattice without downloading it. */
+gf_status gf_pool_release(gf_pool pool, uint64_t job_id);
+
+/* Resident jobs still iterating, finished jobs not yet released, and device bytes held. */
+gf_status gf_pool_stats(gf_pool pool, int32_t* active, int32_t* finished, int64_t* bytes_in_use);
+
+/* Seconds on the library's steady clock (the clock of t_admit / t_done). */
+double gf_clock(void);
 
 /* Thread-local text of the last error (never NULL). */
 const char* gf_last_error(void);

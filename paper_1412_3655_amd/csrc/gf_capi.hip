@@ -8,15 +8,15 @@
 #include <cstring>
 #include <string>
 
-#include "gf.h"
-#include "gf_kernels.h"
+#include "gf_internal.h"
 
 using gf::FastDiv;
 using gf::Geom;
 using gf::LinkField;
 using gf::SweepConfig;
 
-namespace {
+namespace gf {
+namespace detail {
 
 thread_local std::string g_last_error;
 
@@ -30,20 +30,6 @@ gf_status fail(gf_status st, const char* fmt, ...)
     g_last_error = buf;
     return st;
 }
-
-#define GF_HIP(expr)                                                                                        \
-    do {                                                                                                    \
-        hipError_t e_ = (expr);                                                                             \
-        if (e_ != hipSuccess)                                                                               \
-            return fail(e_ == hipErrorOutOfMemory ? GF_E_NOMEM : GF_E_HIP, "%s: %s (%s:%d)", #expr,         \
-                        hipGetErrorString(e_), __FILE__, __LINE__);                                         \
-    } while (0)
-
-#define GF_TRY(expr)                     \
-    do {                                 \
-        gf_status s_ = (expr);           \
-        if (s_ != GF_OK) return s_;      \
-    } while (0)
 
 // d >= 1; exact for 0 <= n < limit (checked exhaustively).
 bool make_fastdiv(uint32_t d, uint32_t limit, FastDiv* out)
@@ -60,27 +46,6 @@ bool make_fastdiv(uint32_t d, uint32_t limit, FastDiv* out)
     return true;
 }
 
-}  // namespace
-
-struct gf_lattice_ {
-    int32_t dims[4] = {0, 0, 0, 0};
-    gf_prec prec = GF_FP64;
-    hipStream_t stream = nullptr;
-    Geom geom{};
-    int64_t volume = 0;
-    int64_t bytes = 0;
-    gf::ChunkOf<double>::T* f64 = nullptr;  // float64 links (GF_FP64, GF_MIXED polish and rebuild)
-    gf::ChunkOf<float>::T* f32 = nullptr;   // float32 links (GF_FP32, GF_MIXED bulk)
-    double* partial = nullptr;
-    double* dres = nullptr;
-    double* hres = nullptr;  // pinned
-    bool has_links = false;
-    uint32_t anneal_sweeps = 0;
-    SweepConfig cfg64;
-    SweepConfig cfg32;
-};
-
-namespace {
 
 LinkField<double> field64(const gf_lattice_* L)
 {
@@ -92,9 +57,15 @@ LinkField<float> field32(const gf_lattice_* L)
     return LinkField<float>{L->f32, L->geom.ld};
 }
 
+// Whether the working links are the float32 field (GF_FP32, or GF_MIXED before promotion).
 bool is_fp32(const gf_lattice_* L)
 {
-    return L->prec == GF_FP32;
+    return L->prec == GF_FP32 || (L->prec == GF_MIXED && L->phase == 0);
+}
+
+gf::GField g_tracking(const gf_lattice_* L)
+{
+    return L->prec == GF_MIXED && L->phase == 0 ? L->gacc : gf::GField{nullptr, 0};
 }
 
 gf_status check_ready(gf_lattice L)
@@ -114,7 +85,8 @@ gf_status check_omega(double omega, int mode)
 gf_status do_half_sweep(gf_lattice L, int parity, double omega, int mode)
 {
     if (is_fp32(L))
-        GF_HIP(gf::launch_or_half_sweep(field32(L), L->geom, parity, (float)omega, mode, L->cfg32, L->stream));
+        GF_HIP(gf::launch_or_half_sweep(field32(L), L->geom, parity, (float)omega, mode, L->cfg32, g_tracking(L),
+                                        L->stream));
     else
         GF_HIP(gf::launch_or_half_sweep(field64(L), L->geom, parity, omega, mode, L->cfg64, L->stream));
     return GF_OK;
@@ -135,6 +107,18 @@ gf_status do_reunitarize(gf_lattice L)
         GF_HIP(gf::launch_reunitarize(field32(L), L->geom, L->stream));
     else
         GF_HIP(gf::launch_reunitarize(field64(L), L->geom, L->stream));
+    if (g_tracking(L).base) GF_HIP(gf::launch_g_reunitarize(L->gacc, L->geom, L->stream));
+    return GF_OK;
+}
+
+// GF_MIXED: leave the float32 phase.  The float64 field still holds the
+// original links U0; it becomes g(x) U0_mu(x) g(x+mu^)^dag, which is on the
+// gauge orbit of U0 to float64 precision whatever the float32 rounding did.
+gf_status do_promote(gf_lattice L)
+{
+    if (L->prec != GF_MIXED || L->phase != 0) return GF_OK;
+    GF_HIP(gf::launch_rebuild_from_g(field64(L), L->gacc, L->geom, L->stream));
+    L->phase = 1;
     return GF_OK;
 }
 
@@ -155,10 +139,10 @@ gf_status do_measure(gf_lattice L, double* theta, double* F)
 
 gf_status upload_canonical(gf_lattice L, const double* dev_canon)
 {
-    if (is_fp32(L))
-        GF_HIP(gf::launch_pack(dev_canon, field32(L), L->geom, L->stream));
-    else
-        GF_HIP(gf::launch_pack(dev_canon, field64(L), L->geom, L->stream));
+    if (L->f32) GF_HIP(gf::launch_pack(dev_canon, field32(L), L->geom, L->stream));
+    if (L->f64) GF_HIP(gf::launch_pack(dev_canon, field64(L), L->geom, L->stream));
+    if (L->gacc.base) GF_HIP(gf::launch_g_identity(L->gacc, L->geom, L->stream));
+    L->phase = 0;
     L->has_links = true;
     L->anneal_sweeps = 0;
     return GF_OK;
@@ -177,17 +161,22 @@ void release(gf_lattice L)
 {
     if (L->f64) (void)hipFree(L->f64);
     if (L->f32) (void)hipFree(L->f32);
+    if (L->gacc.base) (void)hipFree(L->gacc.base);
     if (L->partial) (void)hipFree(L->partial);
     if (L->dres) (void)hipFree(L->dres);
     if (L->hres) (void)hipHostFree(L->hres);
     L->f64 = nullptr;
     L->f32 = nullptr;
+    L->gacc.base = nullptr;
     L->partial = nullptr;
     L->dres = nullptr;
     L->hres = nullptr;
 }
 
-}  // namespace
+}  // namespace detail
+}  // namespace gf
+
+using namespace gf::detail;
 
 extern "C" {
 
@@ -212,7 +201,8 @@ gf_status gf_create_lattice(const int32_t dims[4], gf_prec prec, void* hip_strea
         V *= dims[m];
     }
     if (V > (int64_t)1 << 31) return fail(GF_E_ARG, "volume %lld exceeds 2^31 sites", (long long)V);
-    if (prec != GF_FP64 && prec != GF_FP32) return fail(GF_E_ARG, "unsupported precision %d", (int)prec);
+    if (prec != GF_FP64 && prec != GF_FP32 && prec != GF_MIXED)
+        return fail(GF_E_ARG, "unsupported precision %d", (int)prec);
 
     gf_lattice_* L = new (std::nothrow) gf_lattice_();
     if (!L) return fail(GF_E_NOMEM, "host allocation failed");
@@ -238,12 +228,19 @@ gf_status gf_create_lattice(const int32_t dims[4], gf_prec prec, void* hip_strea
 
     const size_t nchunks = (size_t)2 * 4 * g.ld;  // per chunk slot
     hipError_t e = hipSuccess;
-    if (prec == GF_FP64) {
+    if (prec == GF_FP64 || prec == GF_MIXED) {
         e = hipMalloc((void**)&L->f64, nchunks * 6 * sizeof(double2));
         L->bytes += (int64_t)(nchunks * 6 * sizeof(double2));
-    } else {
+    }
+    if (e == hipSuccess && (prec == GF_FP32 || prec == GF_MIXED)) {
         e = hipMalloc((void**)&L->f32, nchunks * 3 * sizeof(float4));
         L->bytes += (int64_t)(nchunks * 3 * sizeof(float4));
+    }
+    if (e == hipSuccess && prec == GF_MIXED) {
+        const size_t gbytes = (size_t)2 * 3 * g.ld * sizeof(float4);
+        e = hipMalloc((void**)&L->gacc.base, gbytes);
+        L->gacc.ld = g.ld;
+        L->bytes += (int64_t)gbytes;
     }
     const size_t np = 2 * (size_t)gf::measure_blocks(g);
     if (e == hipSuccess) e = hipMalloc((void**)&L->partial, np * sizeof(double));
@@ -279,17 +276,25 @@ gf_status gf_lattice_info(gf_lattice L, int64_t* volume, int64_t* device_bytes)
     return GF_OK;
 }
 
-gf_status gf_set_sweep_config(gf_lattice L, int32_t tps, int32_t block)
+gf_status gf_set_sweep_config(gf_lattice L, gf_prec kernel, int32_t tps, int32_t block)
 {
     if (!L) return fail(GF_E_ARG, "null lattice");
+    if (kernel != GF_FP64 && kernel != GF_FP32) return fail(GF_E_ARG, "kernel precision must be GF_FP64 or GF_FP32");
     SweepConfig c{tps, block};
     if (!gf::sweep_config_valid(c))
-        return fail(GF_E_ARG, "sweep config tps=%d block=%d: tps must be 1, 2, 4 or 8 and block 64..512", tps, block);
-    if (is_fp32(L))
+        return fail(GF_E_ARG, "sweep config tps=%d block=%d: tps must be 1, 2, 4 or 8, block 64, 128, 256 or 512 "
+                              "(and not 512 with tps 1)", tps, block);
+    if (kernel == GF_FP32)
         L->cfg32 = c;
     else
         L->cfg64 = c;
     return GF_OK;
+}
+
+gf_status gf_promote_fp64(gf_lattice L)
+{
+    GF_TRY(check_ready(L));
+    return do_promote(L);
 }
 
 gf_status gf_set_links_device(gf_lattice L, const double* dev)
@@ -355,11 +360,22 @@ gf_status gf_half_sweep_or(gf_lattice L, int32_t colour, double omega, gf_or_mod
 gf_status gf_anneal(gf_lattice L, int32_t n_sweeps, double T_start, double T_end, uint64_t seed)
 {
     GF_TRY(check_ready(L));
-    (void)n_sweeps;
-    (void)T_start;
-    (void)T_end;
-    (void)seed;
-    return fail(GF_E_STATE, "gf_anneal is not available in this build");
+    if (n_sweeps < 0) return fail(GF_E_ARG, "n_sweeps = %d < 0", n_sweeps);
+    if (!(T_end > 0.0) || !(T_start >= T_end) || !std::isfinite(T_start))
+        return fail(GF_E_ARG, "need T_start >= T_end > 0 (got %g, %g)", T_start, T_end);
+    for (int32_t s = 0; s < n_sweeps; ++s) {
+        const double T = anneal_temperature(s, n_sweeps, T_start, T_end);
+        const uint32_t sweep = L->anneal_sweeps + (uint32_t)s;
+        for (int parity = 0; parity < 2; ++parity) {
+            if (is_fp32(L))
+                GF_HIP(gf::launch_hb_half_sweep(field32(L), L->geom, parity, (float)T, seed, sweep, L->cfg32,
+                                                g_tracking(L), L->stream));
+            else
+                GF_HIP(gf::launch_hb_half_sweep(field64(L), L->geom, parity, T, seed, sweep, L->cfg64, L->stream));
+        }
+    }
+    L->anneal_sweeps += (uint32_t)n_sweeps;
+    return GF_OK;
 }
 
 gf_status gf_measure_theta_F(gf_lattice L, double* theta, double* F)
@@ -398,25 +414,43 @@ gf_status gf_fix_until(gf_lattice L, const gf_fix_params* p, gf_fix_result* res)
     if (p->max_sweeps < 0 || p->check_every < 1 || p->reunit_every < 0)
         return fail(GF_E_ARG, "need max_sweeps >= 0, check_every >= 1, reunit_every >= 0");
     if (!(p->theta_target >= 0.0)) return fail(GF_E_ARG, "theta_target must be >= 0");
+    if (L->prec == GF_MIXED && !(p->theta_switch >= 0.0)) return fail(GF_E_ARG, "theta_switch must be >= 0");
     std::memset(res, 0, sizeof *res);
     double theta = 0.0, F = 0.0;
     GF_TRY(do_measure(L, &theta, &F));
     int32_t sweeps = 0;
+    // float32 phase of GF_MIXED: leave it once theta < theta_switch, or when theta
+    // has not improved by 1% over the last kStall checks (float32 noise floor).
+    constexpr int kStall = 8;
+    double best = theta;
+    int stall = 0;
     while (theta >= p->theta_target && sweeps < p->max_sweeps) {
+        if (L->prec == GF_MIXED && L->phase == 0 && (theta < p->theta_switch || stall >= kStall)) {
+            GF_TRY(do_promote(L));
+            GF_TRY(do_measure(L, &theta, &F));
+            continue;
+        }
+        const bool fp32 = is_fp32(L);
         const int32_t n = std::min(p->check_every, p->max_sweeps - sweeps);
         for (int32_t k = 0; k < n; ++k) {
             GF_TRY(do_sweeps(L, 1, p->omega, p->mode));
             ++sweeps;
             if (p->reunit_every > 0 && sweeps % p->reunit_every == 0) GF_TRY(do_reunitarize(L));
         }
+        if (fp32)
+            res->sweeps_fp32 += n;
+        else
+            res->sweeps_fp64 += n;
         GF_TRY(do_measure(L, &theta, &F));
+        if (theta < 0.99 * best) {
+            best = theta;
+            stall = 0;
+        } else {
+            ++stall;
+        }
     }
     res->converged = theta < p->theta_target;
     res->sweeps = sweeps;
-    if (is_fp32(L))
-        res->sweeps_fp32 = sweeps;
-    else
-        res->sweeps_fp64 = sweeps;
     res->theta = theta;
     res->F = F;
     return GF_OK;

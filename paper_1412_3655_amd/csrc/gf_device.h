@@ -216,6 +216,94 @@ __device__ __forceinline__ void rebuild_row2(M3<R>& u)
     }
 }
 
+// Gram-Schmidt of rows 0 and 1 (row 2 stays implicit):
+// r0 <- r0/|r0|, r1 <- r1 - <r0, r1> r0, r1 <- r1/|r1|, <a, b> = sum conj(a_j) b_j.
+template <typename R>
+__device__ __forceinline__ void gram_schmidt_rows01(M3<R>& u)
+{
+    R n0 = u.re[0][0] * u.re[0][0];
+    n0 = fmad(u.im[0][0], u.im[0][0], n0);
+#pragma unroll
+    for (int j = 1; j < 3; ++j) {
+        n0 = fmad(u.re[0][j], u.re[0][j], n0);
+        n0 = fmad(u.im[0][j], u.im[0][j], n0);
+    }
+    const R i0 = R(1) / sqrt(n0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        u.re[0][j] *= i0;
+        u.im[0][j] *= i0;
+    }
+    R pr = u.re[0][0] * u.re[1][0];
+    R pi = u.re[0][0] * u.im[1][0];
+    pr = fmad(u.im[0][0], u.im[1][0], pr);
+    pi = fmad(-u.im[0][0], u.re[1][0], pi);
+#pragma unroll
+    for (int j = 1; j < 3; ++j) {
+        pr = fmad(u.re[0][j], u.re[1][j], pr);
+        pr = fmad(u.im[0][j], u.im[1][j], pr);
+        pi = fmad(u.re[0][j], u.im[1][j], pi);
+        pi = fmad(-u.im[0][j], u.re[1][j], pi);
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        u.re[1][j] = fmad(-pr, u.re[0][j], fmad(pi, u.im[0][j], u.re[1][j]));
+        u.im[1][j] = fmad(-pr, u.im[0][j], fmad(-pi, u.re[0][j], u.im[1][j]));
+    }
+    R n1 = u.re[1][0] * u.re[1][0];
+    n1 = fmad(u.im[1][0], u.im[1][0], n1);
+#pragma unroll
+    for (int j = 1; j < 3; ++j) {
+        n1 = fmad(u.re[1][j], u.re[1][j], n1);
+        n1 = fmad(u.im[1][j], u.im[1][j], n1);
+    }
+    const R i1 = R(1) / sqrt(n1);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        u.re[1][j] *= i1;
+        u.im[1][j] *= i1;
+    }
+}
+
+// --------------------------------------------------------- gauge-field g(x) --
+//
+// The float32 gauge transformation accumulated by mixed-precision sweeps:
+// rows 0, 1 of g(x) as 3 float4 chunks per site, chunk c of the site (p, h)
+// at base[(p*3 + c)*ld + h] (same chunk contents as a float32 link).
+struct GField {
+    float4* base;
+    uint32_t ld;
+};
+
+__device__ __forceinline__ size_t g_index(const GField& f, int parity, int c, uint32_t h)
+{
+    return ((size_t)(parity * 3 + c)) * f.ld + h;
+}
+
+__device__ __forceinline__ void load_g(const GField& f, int parity, uint32_t h, M3<float>& g)
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        float4 v = f.base[g_index(f, parity, c, h)];
+        const int e0 = 2 * c, e1 = 2 * c + 1;
+        g.re[e0 / 3][e0 % 3] = v.x;
+        g.im[e0 / 3][e0 % 3] = v.y;
+        g.re[e1 / 3][e1 % 3] = v.z;
+        g.im[e1 / 3][e1 % 3] = v.w;
+    }
+}
+
+__device__ __forceinline__ void store_g_chunk(const GField& f, int parity, uint32_t h, int c, const M3<float>& g)
+{
+    const int e0 = 2 * c, e1 = 2 * c + 1;
+    float4 v;
+    v.x = g.re[e0 / 3][e0 % 3];
+    v.y = g.im[e0 / 3][e0 % 3];
+    v.z = g.re[e1 / 3][e1 % 3];
+    v.w = g.im[e1 / 3][e1 % 3];
+    f.base[g_index(f, parity, c, h)] = v;
+}
+
 // ---------------------------------------------------------- cross-lane sums --
 
 // DPP controls: quad_perm [1,0,3,2] (lane ^ 1), quad_perm [2,3,0,1] (lane ^ 2),

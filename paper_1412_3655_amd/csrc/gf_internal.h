@@ -1,0 +1,75 @@
+// gf_internal.h -- the lattice object and the helpers shared by the C ABI
+// (gf_capi.hip) and the pool (gf_pool.hip).  Not part of the public ABI.
+#pragma once
+
+#include <string>
+
+#include "gf.h"
+#include "gf_kernels.h"
+
+// One lattice: geometry, device link fields and measurement scratch.
+struct gf_lattice_ {
+    int32_t dims[4] = {0, 0, 0, 0};
+    gf_prec prec = GF_FP64;
+    hipStream_t stream = nullptr;
+    gf::Geom geom{};
+    int64_t volume = 0;
+    int64_t bytes = 0;
+    gf::ChunkOf<double>::T* f64 = nullptr;  // float64 links (GF_FP64, GF_MIXED polish and rebuild)
+    gf::ChunkOf<float>::T* f32 = nullptr;   // float32 links (GF_FP32, GF_MIXED bulk)
+    gf::GField gacc{nullptr, 0};            // GF_MIXED: float32 g(x) accumulated by the bulk sweeps
+    int phase = 0;                          // GF_MIXED: 0 = float32 bulk, 1 = float64 (after promotion)
+    double* partial = nullptr;              // measurement partial sums (2 per block)
+    double* dres = nullptr;                 // device results (theta, F, ...)
+    double* hres = nullptr;                 // pinned host copy of dres
+    bool has_links = false;
+    uint32_t anneal_sweeps = 0;             // heat-bath sweep counter (Philox counter word)
+    gf::SweepConfig cfg64;
+    gf::SweepConfig cfg32;
+};
+
+namespace gf {
+namespace detail {
+
+extern thread_local std::string g_last_error;
+
+gf_status fail(gf_status st, const char* fmt, ...);
+
+#define GF_HIP(expr)                                                                                        \
+    do {                                                                                                    \
+        hipError_t e_ = (expr);                                                                             \
+        if (e_ != hipSuccess)                                                                               \
+            return fail(e_ == hipErrorOutOfMemory ? GF_E_NOMEM : GF_E_HIP, "%s: %s (%s:%d)", #expr,         \
+                        hipGetErrorString(e_), __FILE__, __LINE__);                                         \
+    } while (0)
+
+#define GF_TRY(expr)                     \
+    do {                                 \
+        gf_status s_ = (expr);           \
+        if (s_ != GF_OK) return s_;      \
+    } while (0)
+
+bool make_fastdiv(uint32_t d, uint32_t limit, FastDiv* out);
+LinkField<double> field64(const gf_lattice_* L);
+LinkField<float> field32(const gf_lattice_* L);
+bool is_fp32(const gf_lattice_* L);
+GField g_tracking(const gf_lattice_* L);
+gf_status check_ready(gf_lattice L);
+gf_status check_omega(double omega, int mode);
+gf_status do_half_sweep(gf_lattice L, int parity, double omega, int mode);
+gf_status do_sweeps(gf_lattice L, int32_t n, double omega, int mode);
+gf_status do_reunitarize(gf_lattice L);
+gf_status do_promote(gf_lattice L);
+gf_status do_measure(gf_lattice L, double* theta, double* F);
+gf_status upload_canonical(gf_lattice L, const double* dev_canon);
+gf_status download_canonical(gf_lattice L, double* dev_canon);
+void release(gf_lattice L);
+
+// Temperature of annealing sweep s of n: linear from T_start (s = 0) to T_end (s = n - 1).
+inline double anneal_temperature(int32_t s, int32_t n, double T_start, double T_end)
+{
+    return n > 1 ? T_start + (T_end - T_start) * (double)s / (double)(n - 1) : T_start;
+}
+
+}  // namespace detail
+}  // namespace gf

@@ -20,8 +20,16 @@ bool sweep_config_valid(const SweepConfig& c);
 // One overrelaxation half-sweep over the sites of colour `parity`.
 hipError_t launch_or_half_sweep(const LinkField<double>& f, const Geom& g, int parity, double omega, int mode,
                                 const SweepConfig& cfg, hipStream_t st);
+// float32; with gacc.base != nullptr the sweep also accumulates g(x) <- G g(x).
 hipError_t launch_or_half_sweep(const LinkField<float>& f, const Geom& g, int parity, float omega, int mode,
-                                const SweepConfig& cfg, hipStream_t st);
+                                const SweepConfig& cfg, const GField& gacc, hipStream_t st);
+
+// One heat-bath half-sweep at temperature T: Philox key = seed, sweep counter
+// `sweep` (float32 with gacc.base != nullptr also accumulates g).
+hipError_t launch_hb_half_sweep(const LinkField<double>& f, const Geom& g, int parity, double T, uint64_t seed,
+                                uint32_t sweep, const SweepConfig& cfg, hipStream_t st);
+hipError_t launch_hb_half_sweep(const LinkField<float>& f, const Geom& g, int parity, float T, uint64_t seed,
+                                uint32_t sweep, const SweepConfig& cfg, const GField& gacc, hipStream_t st);
 
 // theta / F: per-block partial sums (2 doubles per block) then one finalize
 // block; out[0] = theta, out[1] = F.  partial must hold measure_partials(g).
@@ -42,5 +50,12 @@ hipError_t launch_pack(const double* canon, const LinkField<double>& f, const Ge
 hipError_t launch_pack(const double* canon, const LinkField<float>& f, const Geom& g, hipStream_t st);
 hipError_t launch_unpack(const LinkField<double>& f, const Geom& g, double* canon, hipStream_t st);
 hipError_t launch_unpack(const LinkField<float>& f, const Geom& g, double* canon, hipStream_t st);
+
+// Mixed precision: g(x) <- 1; Gram-Schmidt of g; and the float64 rebuild
+// U_mu(x) <- g(x) U0_mu(x) g(x+mu^)^dag in place over the float64 field that
+// holds U0 (g re-orthonormalised in float64 first).
+hipError_t launch_g_identity(const GField& gacc, const Geom& g, hipStream_t st);
+hipError_t launch_g_reunitarize(const GField& gacc, const Geom& g, hipStream_t st);
+hipError_t launch_rebuild_from_g(const LinkField<double>& u0, const GField& gacc, const Geom& g, hipStream_t st);
 
 }  // namespace gf

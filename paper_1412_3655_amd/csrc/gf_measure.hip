@@ -13,6 +13,7 @@
 // reproducible.  Traffic: every link is read twice (once from each end),
 // 768 B per site in FP64.
 #include "gf_kernels.h"
+#include "gf_site.h"
 
 namespace gf {
 
@@ -21,98 +22,12 @@ namespace {
 constexpr int RBLOCK = 256;
 
 template <typename R>
-__device__ __forceinline__ void load_full_f64(const LinkField<R>& f, int parity, int mu, uint32_t h, M3<double>& u)
-{
-    M3<R> t;
-    load_rows01(f, parity, mu, h, t);
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            u.re[i][j] = (double)t.re[i][j];
-            u.im[i][j] = (double)t.im[i][j];
-        }
-    rebuild_row2(u);
-}
-
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// Sum two values over the block; thread 0 writes them to out[0..1].
-template <int NT>
-__device__ __forceinline__ void block_sum2(double a, double b, double* out)
-{
-    __shared__ double lds[2][NT / 64];
-    a = wave_sum(a);
-    b = wave_sum(b);
-    const int w = threadIdx.x / 64;
-    if ((threadIdx.x & 63) == 0) {
-        lds[0][w] = a;
-        lds[1][w] = b;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double sa = 0.0, sb = 0.0;
-        for (int i = 0; i < NT / 64; ++i) {
-            sa += lds[0][i];
-            sb += lds[1][i];
-        }
-        out[0] = sa;
-        out[1] = sb;
-    }
-}
-
-template <typename R>
 __global__ void __launch_bounds__(RBLOCK) k_measure(LinkField<R> f, Geom g, double* partial)
 {
     const int parity = blockIdx.y;
     const uint32_t h = blockIdx.x * RBLOCK + threadIdx.x;
     double th = 0.0, fr = 0.0;
-    if (h < g.vh) {
-        const Site s = decode_site(g, parity, h);
-        M3<double> K;
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                K.re[i][j] = 0.0;
-                K.im[i][j] = 0.0;
-            }
-#pragma unroll
-        for (int mu = 0; mu < 4; ++mu) {
-            M3<double> u;
-            load_full_f64(f, parity, mu, h, u);
-            fr += u.re[0][0] + u.re[1][1] + u.re[2][2];
-            m_add(K, u);
-            load_full_f64(f, 1 - parity, mu, back_h(g, h, s, mu), u);
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    K.re[i][j] += u.re[j][i];
-                    K.im[i][j] -= u.im[j][i];
-                }
-        }
-        // M = (K - K^dag)/(2i): diagonal Im K_ii; off-diagonal
-        // ((Im K_ij + Im K_ji) - i (Re K_ij - Re K_ji)) / 2.  Delta = M - tr(M)/3.
-        const double d0 = K.im[0][0], d1 = K.im[1][1], d2 = K.im[2][2];
-        const double tr3 = (d0 + d1 + d2) / 3.0;
-        const double e0 = d0 - tr3, e1 = d1 - tr3, e2 = d2 - tr3;
-        double off = 0.0;
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = i + 1; j < 3; ++j) {
-                const double mr = 0.5 * (K.im[i][j] + K.im[j][i]);
-                const double mi = 0.5 * (K.re[i][j] - K.re[j][i]);
-                off += mr * mr + mi * mi;
-            }
-        th = e0 * e0 + e1 * e1 + e2 * e2 + 2.0 * off;
-    }
+    if (h < g.vh) measure_site(f, g, parity, h, th, fr);
     block_sum2<RBLOCK>(th, fr, partial + 2 * (size_t)(blockIdx.y * gridDim.x + blockIdx.x));
 }
 
@@ -159,18 +74,7 @@ __global__ void __launch_bounds__(RBLOCK) k_plaquette(LinkField<R> f, Geom g, do
 // out[k] = scale[k] * sum_i partial[2 i + k], summed in a fixed order.
 __global__ void __launch_bounds__(RBLOCK) k_finalize(const double* partial, uint32_t n, double s0, double s1, double* out)
 {
-    double a = 0.0, b = 0.0;
-    for (uint32_t i = threadIdx.x; i < n; i += RBLOCK) {
-        a += partial[2 * (size_t)i];
-        b += partial[2 * (size_t)i + 1];
-    }
-    __shared__ double res[2];
-    block_sum2<RBLOCK>(a, b, res);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        out[0] = res[0] * s0;
-        out[1] = res[1] * s1;
-    }
+    finalize_pairs<RBLOCK>(partial, n, s0, s1, out);
 }
 
 // Gram-Schmidt on rows 0, 1 (row 2 stays implicit).
@@ -182,37 +86,64 @@ __global__ void __launch_bounds__(RBLOCK) k_reunitarize(LinkField<R> f, uint32_t
     const int parity = blockIdx.y >> 2, mu = blockIdx.y & 3;
     M3<R> u;
     load_rows01(f, parity, mu, h, u);
-    R n0 = R(0);
-#pragma unroll
-    for (int j = 0; j < 3; ++j) n0 += u.re[0][j] * u.re[0][j] + u.im[0][j] * u.im[0][j];
-    const R i0 = R(1) / sqrt(n0);
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        u.re[0][j] *= i0;
-        u.im[0][j] *= i0;
-    }
-    // <r0, r1> = sum conj(r0_j) r1_j
-    R pr = R(0), pi = R(0);
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        pr += u.re[0][j] * u.re[1][j] + u.im[0][j] * u.im[1][j];
-        pi += u.re[0][j] * u.im[1][j] - u.im[0][j] * u.re[1][j];
-    }
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        u.re[1][j] -= pr * u.re[0][j] - pi * u.im[0][j];
-        u.im[1][j] -= pr * u.im[0][j] + pi * u.re[0][j];
-    }
-    R n1 = R(0);
-#pragma unroll
-    for (int j = 0; j < 3; ++j) n1 += u.re[1][j] * u.re[1][j] + u.im[1][j] * u.im[1][j];
-    const R i1 = R(1) / sqrt(n1);
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        u.re[1][j] *= i1;
-        u.im[1][j] *= i1;
-    }
+    gram_schmidt_rows01(u);
     store_rows01(f, parity, mu, h, u);
+}
+
+__global__ void __launch_bounds__(RBLOCK) k_g_identity(GField gacc, uint32_t vh)
+{
+    const uint32_t h = blockIdx.x * RBLOCK + threadIdx.x;
+    if (h >= vh) return;
+    const int parity = blockIdx.y;
+    gacc.base[g_index(gacc, parity, 0, h)] = make_float4(1.f, 0.f, 0.f, 0.f);  // g00, g01
+    gacc.base[g_index(gacc, parity, 1, h)] = make_float4(0.f, 0.f, 0.f, 0.f);  // g02, g10
+    gacc.base[g_index(gacc, parity, 2, h)] = make_float4(1.f, 0.f, 0.f, 0.f);  // g11, g12
+}
+
+__global__ void __launch_bounds__(RBLOCK) k_g_reunitarize(GField gacc, uint32_t vh)
+{
+    const uint32_t h = blockIdx.x * RBLOCK + threadIdx.x;
+    if (h >= vh) return;
+    const int parity = blockIdx.y;
+    M3<float> u;
+    load_g(gacc, parity, h, u);
+    gram_schmidt_rows01(u);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) store_g_chunk(gacc, parity, h, c, u);
+}
+
+// g(x) as a float64 SU(3) matrix: rows 0, 1 orthonormalised in float64, row 2 rebuilt.
+__device__ __forceinline__ void load_g_f64(const GField& gacc, int parity, uint32_t h, M3<double>& g)
+{
+    M3<float> t;
+    load_g(gacc, parity, h, t);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            g.re[i][j] = (double)t.re[i][j];
+            g.im[i][j] = (double)t.im[i][j];
+        }
+    gram_schmidt_rows01(g);
+    rebuild_row2(g);
+}
+
+// U_mu(x) <- g(x) U0_mu(x) g(x+mu^)^dag (the gauge transformation of Sec. 2 with
+// the accumulated g), in place over the float64 field that holds U0.
+__global__ void __launch_bounds__(RBLOCK) k_rebuild_from_g(LinkField<double> u0, GField gacc, Geom g)
+{
+    const uint32_t h = blockIdx.x * RBLOCK + threadIdx.x;
+    if (h >= g.vh) return;
+    const int parity = blockIdx.y >> 2, mu = blockIdx.y & 3;
+    const Site s = decode_site(g, parity, h);
+    M3<double> gx, gy, u;
+    load_g_f64(gacc, parity, h, gx);
+    load_g_f64(gacc, 1 - parity, fwd_h(g, h, s, mu), gy);
+    load_rows01(u0, parity, mu, h, u);
+    rebuild_row2(u);
+    left_mul_rows01(gx, u);
+    right_mul_dag_rows01(gy, u);
+    store_rows01(u0, parity, mu, h, u);
 }
 
 // canonical lex site s, direction mu -> (colour, half index)
@@ -324,6 +255,24 @@ hipError_t unpack_impl(const LinkField<R>& f, const Geom& g, double* canon, hipS
 }
 
 }  // namespace
+
+hipError_t launch_g_identity(const GField& gacc, const Geom& g, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_g_identity, dim3(site_blocks(g), 2), dim3(RBLOCK), 0, st, gacc, g.vh);
+    return hipGetLastError();
+}
+
+hipError_t launch_g_reunitarize(const GField& gacc, const Geom& g, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_g_reunitarize, dim3(site_blocks(g), 2), dim3(RBLOCK), 0, st, gacc, g.vh);
+    return hipGetLastError();
+}
+
+hipError_t launch_rebuild_from_g(const LinkField<double>& u0, const GField& gacc, const Geom& g, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_rebuild_from_g, dim3(site_blocks(g), 8), dim3(RBLOCK), 0, st, u0, gacc, g);
+    return hipGetLastError();
+}
 
 uint32_t measure_blocks(const Geom& g)
 {

@@ -1,0 +1,799 @@
+// gf_pool.hip -- batched sweeps of many resident lattices and the job pool
+// behind gf_pool_* (include/gf.h).
+//
+// Each job owns an ordinary lattice object; the pool keeps a device table
+// with one descriptor per slot (field pointers, geometry, rule parameters)
+// and, per pool step of C = check_every sweeps, device work lists:
+// for sweep k of the step and each kernel kind (heat bath / OR in float32
+// with g tracking / OR in float64 / reunitarisation / measurement /
+// finalisation) the list of slots that take part, as (slot, first tile)
+// prefix entries.  The kernels are persistent: a grid sized to the resident
+// capacity strides over the tiles of every listed slot, so one launch per
+// kind covers every lattice of every shape.  Work lists and the slot table
+// live in device memory and are refreshed by one host-to-device copy per
+// step; the launches of a step are captured in a hipGraph once per work
+// structure (which (k, kind) lists are non-empty) and replayed.
+//
+// The per-site bodies are the same functions the single-lattice kernels use
+// (gf_site.h) and the block decomposition of the measurement is the same, so
+// every job's links, theta and F are bitwise those of the same job run alone
+// through gf_anneal / gf_fix_until.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "gf_internal.h"
+#include "gf_site.h"
+
+namespace gf {
+namespace pool {
+
+constexpr int PBLOCK = 256;  // threads per block of every pool kernel
+
+struct SlotDev {
+    LinkField<double> f64;
+    LinkField<float> f32;
+    GField gacc;
+    Geom g;
+    double omega;
+    double T0, T1;
+    int32_t n_anneal;
+    uint32_t key0, key1;
+    uint32_t anneal_base;  // heat-bath sweeps done before this step
+    double scale_theta, scale_F;
+    double* partial;
+    double* result;
+};
+
+// (slot, first tile) prefix entries; entry n (the sentinel) holds the tile total.
+struct Entry {
+    uint32_t slot;
+    uint32_t first;
+};
+
+enum Kind { K_HB32 = 0, K_OR32, K_OR64, K_HB64, K_R32, K_R64, K_M32, K_M64, K_FIN, NKIND };
+
+__device__ __forceinline__ uint32_t find_entry(const Entry* e, uint32_t n, uint32_t t)
+{
+    uint32_t lo = 0, hi = n;  // e[lo].first <= t < e[hi].first
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (e[mid].first <= t)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+template <typename R>
+__device__ __forceinline__ LinkField<R> field_of(const SlotDev& sd);
+template <>
+__device__ __forceinline__ LinkField<double> field_of<double>(const SlotDev& sd)
+{
+    return sd.f64;
+}
+template <>
+__device__ __forceinline__ LinkField<float> field_of<float>(const SlotDev& sd)
+{
+    return sd.f32;
+}
+
+// Linear schedule of gf_anneal: T_start at sweep 0, T_end at sweep n - 1 (float64).
+__device__ __forceinline__ double schedule_T(const SlotDev& sd, uint32_t s)
+{
+    return sd.n_anneal > 1 ? sd.T0 + (sd.T1 - sd.T0) * (double)s / (double)(sd.n_anneal - 1) : sd.T0;
+}
+
+template <typename R, int TPS, int MODE, bool TRACKG>
+__global__ void __launch_bounds__(PBLOCK) k_pool_sweep(const SlotDev* slots, const Entry* list, const uint32_t* count,
+                                                       int parity, uint32_t k)
+{
+    constexpr uint32_t SPB = PBLOCK / TPS;
+    const uint32_t n = *count;
+    const uint32_t total = list[n].first;
+    for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+        const uint32_t i = find_entry(list, n, t);
+        const SlotDev sd = slots[list[i].slot];
+        const uint32_t h = (t - list[i].first) * SPB + threadIdx.x / TPS;
+        const int r = (int)(threadIdx.x % TPS);
+        if (h < sd.g.vh) {  // whole TPS groups take the same branch
+            Rule<R> rule;
+            if constexpr (MODE == HEATBATH) {
+                const uint32_t s = sd.anneal_base + k;
+                rule = Rule<R>{R(1), (R)schedule_T(sd, s), sd.key0, sd.key1, s};
+            } else {
+                rule = Rule<R>{(R)sd.omega, R(1), 0u, 0u, 0u};
+            }
+            site_update<R, TPS, MODE, TRACKG>(field_of<R>(sd), sd.g, parity, h, r, rule, sd.gacc);
+        }
+    }
+}
+
+template <typename R, bool WITH_G>
+__global__ void __launch_bounds__(PBLOCK) k_pool_reunit(const SlotDev* slots, const Entry* list, const uint32_t* count)
+{
+    const uint32_t n = *count;
+    const uint32_t total = list[n].first;
+    for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+        const uint32_t i = find_entry(list, n, t);
+        const SlotDev sd = slots[list[i].slot];
+        const uint32_t h = (t - list[i].first) * PBLOCK + threadIdx.x;
+        if (h >= sd.g.vh) continue;
+        const LinkField<R> f = field_of<R>(sd);
+        for (int pm = 0; pm < 8; ++pm) {
+            M3<R> u;
+            load_rows01(f, pm >> 2, pm & 3, h, u);
+            gram_schmidt_rows01(u);
+            store_rows01(f, pm >> 2, pm & 3, h, u);
+        }
+        if constexpr (WITH_G) {
+            for (int p = 0; p < 2; ++p) {
+                M3<float> u;
+                load_g(sd.gacc, p, h, u);
+                gram_schmidt_rows01(u);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) store_g_chunk(sd.gacc, p, h, c, u);
+            }
+        }
+    }
+}
+
+// Tile b of a slot = measurement block (parity = b / nb, block = b % nb) of the
+// single-lattice measurement, writing the same partial.
+template <typename R>
+__global__ void __launch_bounds__(PBLOCK) k_pool_measure(const SlotDev* slots, const Entry* list, const uint32_t* count)
+{
+    const uint32_t n = *count;
+    const uint32_t total = list[n].first;
+    for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+        const uint32_t i = find_entry(list, n, t);
+        const SlotDev sd = slots[list[i].slot];
+        const uint32_t b = t - list[i].first;
+        const uint32_t nb = (sd.g.vh + PBLOCK - 1) / PBLOCK;
+        const int parity = (int)(b / nb);
+        const uint32_t h = (b % nb) * PBLOCK + threadIdx.x;
+        double th = 0.0, fr = 0.0;
+        if (h < sd.g.vh) measure_site(field_of<R>(sd), sd.g, parity, h, th, fr);
+        block_sum2<PBLOCK>(th, fr, sd.partial + 2 * (size_t)b);
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(PBLOCK) k_pool_finalize(const SlotDev* slots, const Entry* list, const uint32_t* count)
+{
+    const uint32_t n = *count;
+    for (uint32_t t = blockIdx.x; t < n; t += gridDim.x) {
+        const SlotDev sd = slots[list[t].slot];
+        const uint32_t nb = (sd.g.vh + PBLOCK - 1) / PBLOCK;
+        finalize_pairs<PBLOCK>(sd.partial, 2 * nb, sd.scale_theta, sd.scale_F, sd.result);
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ host --
+
+double now_s()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+enum JobState { J_ANNEAL = 0, J_FIX = 1, J_DONE = 2 };
+
+struct Job {
+    uint64_t id = 0;
+    gf_lattice lat = nullptr;
+    int slot = -1;
+    JobState state = J_FIX;
+    gf_fix_params p{};
+    int32_t anneal_total = 0, anneal_done = 0;
+    double T0 = 1.0, T1 = 1.0;
+    uint64_t seed = 0;
+    gf_fix_result res{};
+    double theta = 0.0, F = 0.0, best = 0.0;
+    int stall = 0;
+    gf_status status = GF_OK;
+    double t_admit = 0.0, t_done = 0.0;
+    bool polled = false;
+    int64_t bytes = 0;
+    // plan of the current step
+    int plan_kind = -1, plan_n = 0, plan_measure_k = -1;
+};
+
+}  // namespace pool
+}  // namespace gf
+
+using namespace gf;
+using namespace gf::pool;
+using namespace gf::detail;
+
+struct gf_pool_ {
+    gf_pool_config cfg{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int chunk = 1;
+    std::vector<Job> jobs;           // indexed by slot (slot == index); id 0 with lat == nullptr = free
+    std::vector<SlotDev> slot_host;  // mirror of the device slot table
+    int64_t bytes_in_use = 0;
+    // device buffers
+    SlotDev* slots_dev = nullptr;
+    Entry* lists_dev = nullptr;
+    uint32_t* counts_dev = nullptr;
+    double* results_dev = nullptr;
+    // pinned host staging
+    SlotDev* slots_pin = nullptr;
+    Entry* lists_pin = nullptr;
+    uint32_t* counts_pin = nullptr;
+    double* results_pin = nullptr;
+    size_t list_stride = 0;  // entries per (k, kind) segment = max_slots + 1
+    std::map<std::string, hipGraphExec_t> graphs;
+    std::vector<gf_pool_done> finished;  // not yet polled
+    int grid_sweep[4] = {0, 0, 0, 0};    // persistent grid per kind family
+    int grid_other = 0;
+};
+
+namespace {
+
+gf_status pool_check(gf_pool P)
+{
+    if (!P) return fail(GF_E_ARG, "null pool");
+    return GF_OK;
+}
+
+int64_t lattice_bytes(const int32_t dims[4], int32_t prec)
+{
+    int64_t V = 1;
+    for (int m = 0; m < 4; ++m) V *= dims[m];
+    const int64_t ld = ((V / 2) + 63) & ~(int64_t)63;
+    int64_t b = 0;
+    if (prec == GF_FP64 || prec == GF_MIXED) b += 2 * 4 * ld * 6 * 16;
+    if (prec == GF_FP32 || prec == GF_MIXED) b += 2 * 4 * ld * 3 * 16;
+    if (prec == GF_MIXED) b += 2 * 3 * ld * 16;
+    const int64_t nb = (V / 2 + 255) / 256;
+    b += 2 * 2 * nb * 8;
+    return b;
+}
+
+Entry* seg(gf_pool P, Entry* base, int k, int kind)
+{
+    return base + ((size_t)k * NKIND + kind) * P->list_stride;
+}
+
+uint32_t tiles_of(const Geom& g, int kind, int tps)
+{
+    switch (kind) {
+        case K_HB32:
+        case K_OR32:
+        case K_OR64:
+        case K_HB64: {
+            const uint32_t spb = PBLOCK / (uint32_t)tps;
+            return (g.vh + spb - 1) / spb;
+        }
+        case K_R32:
+        case K_R64: return (g.vh + PBLOCK - 1) / PBLOCK;
+        case K_M32:
+        case K_M64: return 2 * ((g.vh + PBLOCK - 1) / PBLOCK);
+        default: return 1;
+    }
+}
+
+template <typename R, int MODE, bool TRACKG>
+hipError_t launch_sweep_kind(gf_pool P, int tps, const Entry* list, const uint32_t* count, int parity, uint32_t k)
+{
+    const dim3 grid(P->grid_sweep[tps == 1 ? 0 : tps == 2 ? 1 : tps == 8 ? 3 : 2]), block(PBLOCK);
+    switch (tps) {
+        case 1:
+            hipLaunchKernelGGL((k_pool_sweep<R, 1, MODE, TRACKG>), grid, block, 0, P->stream, P->slots_dev, list, count,
+                               parity, k);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_pool_sweep<R, 2, MODE, TRACKG>), grid, block, 0, P->stream, P->slots_dev, list, count,
+                               parity, k);
+            break;
+        case 8:
+            hipLaunchKernelGGL((k_pool_sweep<R, 8, MODE, TRACKG>), grid, block, 0, P->stream, P->slots_dev, list, count,
+                               parity, k);
+            break;
+        default:
+            hipLaunchKernelGGL((k_pool_sweep<R, 4, MODE, TRACKG>), grid, block, 0, P->stream, P->slots_dev, list, count,
+                               parity, k);
+            break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_kind(gf_pool P, int k, int kind, int parity)
+{
+    const Entry* list = seg(P, P->lists_dev, k, kind);
+    const uint32_t* count = P->counts_dev + (size_t)k * NKIND + kind;
+    const int mode = P->cfg.mode;
+    const int t32 = P->cfg.tps32, t64 = P->cfg.tps64;
+    switch (kind) {
+        case K_HB32: return launch_sweep_kind<float, HEATBATH, true>(P, t32, list, count, parity, (uint32_t)k);
+        case K_HB64: return launch_sweep_kind<double, HEATBATH, false>(P, t64, list, count, parity, (uint32_t)k);
+        case K_OR32:
+            return mode == GF_OR_EXACT ? launch_sweep_kind<float, 0, true>(P, t32, list, count, parity, (uint32_t)k)
+                                       : launch_sweep_kind<float, 1, true>(P, t32, list, count, parity, (uint32_t)k);
+        case K_OR64:
+            return mode == GF_OR_EXACT ? launch_sweep_kind<double, 0, false>(P, t64, list, count, parity, (uint32_t)k)
+                                       : launch_sweep_kind<double, 1, false>(P, t64, list, count, parity, (uint32_t)k);
+        case K_R32:
+            hipLaunchKernelGGL((k_pool_reunit<float, true>), dim3(P->grid_other), dim3(PBLOCK), 0, P->stream,
+                               P->slots_dev, list, count);
+            break;
+        case K_R64:
+            hipLaunchKernelGGL((k_pool_reunit<double, false>), dim3(P->grid_other), dim3(PBLOCK), 0, P->stream,
+                               P->slots_dev, list, count);
+            break;
+        case K_M32:
+            hipLaunchKernelGGL((k_pool_measure<float>), dim3(P->grid_other), dim3(PBLOCK), 0, P->stream, P->slots_dev,
+                               list, count);
+            break;
+        case K_M64:
+            hipLaunchKernelGGL((k_pool_measure<double>), dim3(P->grid_other), dim3(PBLOCK), 0, P->stream,
+                               P->slots_dev, list, count);
+            break;
+        default:
+            hipLaunchKernelGGL(k_pool_finalize, dim3(P->grid_other), dim3(PBLOCK), 0, P->stream, P->slots_dev, list,
+                               count);
+            break;
+    }
+    return hipGetLastError();
+}
+
+// Enqueue the whole step for the work structure `sig` (one char per (k, kind)).
+gf_status enqueue_step(gf_pool P, const std::string& sig)
+{
+    static const int sweep_kinds[4] = {K_HB32, K_OR32, K_OR64, K_HB64};
+    for (int k = 0; k < P->chunk; ++k) {
+        const char* row = sig.c_str() + (size_t)k * NKIND;
+        for (int parity = 0; parity < 2; ++parity)
+            for (int kind : sweep_kinds)
+                if (row[kind] == '1') GF_HIP(launch_kind(P, k, kind, parity));
+        for (int kind : {K_R32, K_R64, K_M32, K_M64, K_FIN})
+            if (row[kind] == '1') GF_HIP(launch_kind(P, k, kind, 0));
+    }
+    return GF_OK;
+}
+
+gf_status run_graph(gf_pool P, const std::string& sig)
+{
+    auto it = P->graphs.find(sig);
+    if (it == P->graphs.end()) {
+        if (P->graphs.size() >= 64) {
+            for (auto& kv : P->graphs) (void)hipGraphExecDestroy(kv.second);
+            P->graphs.clear();
+        }
+        hipGraph_t graph = nullptr;
+        GF_HIP(hipStreamBeginCapture(P->stream, hipStreamCaptureModeRelaxed));
+        gf_status st = enqueue_step(P, sig);
+        hipError_t e = hipStreamEndCapture(P->stream, &graph);
+        if (st != GF_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return fail(GF_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return fail(GF_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        it = P->graphs.emplace(sig, exec).first;
+    }
+    GF_HIP(hipGraphLaunch(it->second, P->stream));
+    return GF_OK;
+}
+
+void fill_slot(gf_pool P, int slot)
+{
+    Job& j = P->jobs[slot];
+    gf_lattice L = j.lat;
+    SlotDev& d = P->slot_host[slot];
+    std::memset(&d, 0, sizeof d);
+    d.f64 = LinkField<double>{L->f64, L->geom.ld};
+    d.f32 = LinkField<float>{L->f32, L->geom.ld};
+    d.gacc = L->gacc;
+    d.g = L->geom;
+    d.omega = j.p.omega;
+    d.T0 = j.T0;
+    d.T1 = j.T1;
+    d.n_anneal = j.anneal_total;
+    d.key0 = (uint32_t)j.seed;
+    d.key1 = (uint32_t)(j.seed >> 32);
+    d.anneal_base = L->anneal_sweeps;
+    const double V = 2.0 * (double)L->geom.vh;
+    d.scale_theta = 1.0 / (3.0 * V);
+    d.scale_F = 1.0 / (12.0 * V);
+    d.partial = L->partial;
+    d.result = P->results_dev + 2 * (size_t)slot;
+}
+
+void finish(gf_pool P, Job& j, gf_status status)
+{
+    j.state = J_DONE;
+    j.status = status;
+    j.t_done = now_s();
+    j.res.converged = j.theta < j.p.theta_target && status == GF_OK;
+    j.res.theta = j.theta;
+    j.res.F = j.F;
+    gf_pool_done d{};
+    d.job_id = j.id;
+    d.result = j.res;
+    d.status = status;
+    d.t_admit = j.t_admit;
+    d.t_done = j.t_done;
+    P->finished.push_back(d);
+}
+
+// The loop head of gf_fix_until for a job in the fix phase: finish, or promote
+// and measure again, until the job needs sweeps.
+gf_status fix_head(gf_pool P, Job& j)
+{
+    gf_lattice L = j.lat;
+    for (;;) {
+        if (!(j.theta >= j.p.theta_target && j.res.sweeps < j.p.max_sweeps)) {
+            finish(P, j, GF_OK);
+            return GF_OK;
+        }
+        if (L->prec == GF_MIXED && L->phase == 0 && (j.theta < j.p.theta_switch || j.stall >= 8)) {
+            GF_TRY(do_promote(L));
+            gf_status st = do_measure(L, &j.theta, &j.F);
+            if (st != GF_OK) {
+                finish(P, j, st);
+                return GF_OK;
+            }
+            continue;
+        }
+        return GF_OK;
+    }
+}
+
+void release_job(gf_pool P, Job& j)
+{
+    if (j.lat) {
+        (void)gf_destroy_lattice(j.lat);
+        P->bytes_in_use -= j.bytes;
+    }
+    j = Job();
+}
+
+}  // namespace
+
+extern "C" {
+
+double gf_clock(void)
+{
+    return now_s();
+}
+
+gf_status gf_pool_job_bytes(const int32_t dims[4], int32_t prec, int64_t* bytes)
+{
+    if (!dims || !bytes) return fail(GF_E_ARG, "null argument");
+    for (int m = 0; m < 4; ++m)
+        if (dims[m] < 2 || dims[m] % 2) return fail(GF_E_ARG, "extents must be even and >= 2");
+    if (prec != GF_FP64 && prec != GF_MIXED && prec != GF_FP32) return fail(GF_E_ARG, "bad precision");
+    *bytes = lattice_bytes(dims, prec);
+    return GF_OK;
+}
+
+gf_status gf_pool_create(const gf_pool_config* cfg, void* hip_stream, gf_pool* out)
+{
+    if (!cfg || !out) return fail(GF_E_ARG, "null argument");
+    *out = nullptr;
+    if (cfg->max_slots < 1 || cfg->max_slots > 4096) return fail(GF_E_ARG, "max_slots must be 1..4096");
+    if (cfg->prec != GF_MIXED && cfg->prec != GF_FP64) return fail(GF_E_ARG, "pool precision must be GF_MIXED or GF_FP64");
+    if (cfg->check_every < 1 || cfg->check_every > 1000) return fail(GF_E_ARG, "check_every must be 1..1000");
+    if (cfg->mode != GF_OR_EXACT && cfg->mode != GF_OR_BINOMIAL1) return fail(GF_E_ARG, "unknown mode");
+    gf_pool_config c = *cfg;
+    if (c.tps32 == 0) c.tps32 = 4;
+    if (c.tps64 == 0) c.tps64 = 4;
+    if (c.block32 == 0) c.block32 = 256;
+    if (c.block64 == 0) c.block64 = 256;
+    for (int t : {c.tps32, c.tps64})
+        if (t != 1 && t != 2 && t != 4 && t != 8) return fail(GF_E_ARG, "tps must be 1, 2, 4 or 8");
+    if (!sweep_config_valid(SweepConfig{c.tps32, c.block32}) || !sweep_config_valid(SweepConfig{c.tps64, c.block64}))
+        return fail(GF_E_ARG, "invalid sweep kernel configuration");
+
+    gf_pool_* P = new (std::nothrow) gf_pool_();
+    if (!P) return fail(GF_E_NOMEM, "host allocation failed");
+    P->cfg = c;
+    P->chunk = c.check_every;
+    if (hip_stream) {
+        P->stream = (hipStream_t)hip_stream;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete P;
+            return fail(GF_E_HIP, "hipStreamCreate: %s", hipGetErrorString(e));
+        }
+        P->own_stream = true;
+    }
+    P->jobs.resize(c.max_slots);
+    P->slot_host.resize(c.max_slots);
+    P->list_stride = (size_t)c.max_slots + 1;
+    const size_t nseg = (size_t)P->chunk * NKIND;
+    hipError_t e = hipMalloc((void**)&P->slots_dev, sizeof(SlotDev) * c.max_slots);
+    if (e == hipSuccess) e = hipMalloc((void**)&P->lists_dev, sizeof(Entry) * nseg * P->list_stride);
+    if (e == hipSuccess) e = hipMalloc((void**)&P->counts_dev, sizeof(uint32_t) * nseg);
+    if (e == hipSuccess) e = hipMalloc((void**)&P->results_dev, sizeof(double) * 2 * c.max_slots);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&P->slots_pin, sizeof(SlotDev) * c.max_slots, hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void**)&P->lists_pin, sizeof(Entry) * nseg * P->list_stride, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&P->counts_pin, sizeof(uint32_t) * nseg, hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void**)&P->results_pin, sizeof(double) * 2 * c.max_slots, hipHostMallocDefault);
+    int dev = 0, ncu = 0;
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) {
+        gf_pool_destroy(P);
+        return fail(GF_E_HIP, "pool allocation failed: %s", hipGetErrorString(e));
+    }
+    // persistent grids: a few resident blocks per compute unit
+    for (int i = 0; i < 4; ++i) P->grid_sweep[i] = 2 * ncu;
+    P->grid_other = 4 * ncu;
+    std::memset(P->slots_pin, 0, sizeof(SlotDev) * c.max_slots);
+    *out = P;
+    return GF_OK;
+}
+
+gf_status gf_pool_destroy(gf_pool P)
+{
+    if (!P) return GF_OK;
+    if (P->stream) (void)hipStreamSynchronize(P->stream);
+    for (auto& j : P->jobs) release_job(P, j);
+    for (auto& kv : P->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (P->slots_dev) (void)hipFree(P->slots_dev);
+    if (P->lists_dev) (void)hipFree(P->lists_dev);
+    if (P->counts_dev) (void)hipFree(P->counts_dev);
+    if (P->results_dev) (void)hipFree(P->results_dev);
+    if (P->slots_pin) (void)hipHostFree(P->slots_pin);
+    if (P->lists_pin) (void)hipHostFree(P->lists_pin);
+    if (P->counts_pin) (void)hipHostFree(P->counts_pin);
+    if (P->results_pin) (void)hipHostFree(P->results_pin);
+    if (P->own_stream && P->stream) (void)hipStreamDestroy(P->stream);
+    delete P;
+    return GF_OK;
+}
+
+gf_status gf_pool_admit(gf_pool P, uint64_t job_id, const int32_t dims[4], const double* host_links,
+                        const gf_fix_params* params, int32_t anneal_sweeps, double T_start, double T_end,
+                        uint64_t seed)
+{
+    GF_TRY(pool_check(P));
+    if (!dims || !host_links || !params) return fail(GF_E_ARG, "null argument");
+    GF_TRY(check_omega(params->omega, params->mode));
+    if (params->mode != P->cfg.mode) return fail(GF_E_ARG, "job mode %d differs from the pool's %d", params->mode,
+                                                 P->cfg.mode);
+    if (params->check_every != P->cfg.check_every)
+        return fail(GF_E_ARG, "job check_every %d differs from the pool's %d", params->check_every, P->cfg.check_every);
+    if (params->max_sweeps < 0 || params->reunit_every < 0 || !(params->theta_target >= 0.0) ||
+        !(params->theta_switch >= 0.0))
+        return fail(GF_E_ARG, "bad fix parameters");
+    if (anneal_sweeps < 0) return fail(GF_E_ARG, "anneal_sweeps < 0");
+    if (anneal_sweeps > 0 && (!(T_end > 0.0) || !(T_start >= T_end) || !std::isfinite(T_start)))
+        return fail(GF_E_ARG, "need T_start >= T_end > 0");
+    for (auto& j : P->jobs)
+        if (j.lat && j.id == job_id) return fail(GF_E_ARG, "job id %llu is already in the pool", (unsigned long long)job_id);
+    int64_t bytes = 0;
+    GF_TRY(gf_pool_job_bytes(dims, P->cfg.prec, &bytes));
+    int slot = -1;
+    for (int s = 0; s < (int)P->jobs.size(); ++s)
+        if (!P->jobs[s].lat) {
+            slot = s;
+            break;
+        }
+    if (slot < 0) return fail(GF_E_FULL, "all %d slots are taken", P->cfg.max_slots);
+    if ((size_t)(P->bytes_in_use + bytes) > P->cfg.hbm_budget)
+        return fail(GF_E_FULL, "job needs %lld bytes, %lld of %zu in use", (long long)bytes,
+                    (long long)P->bytes_in_use, P->cfg.hbm_budget);
+
+    gf_lattice L = nullptr;
+    GF_TRY(gf_create_lattice(dims, (gf_prec)P->cfg.prec, P->stream, &L));
+    L->cfg32 = SweepConfig{P->cfg.tps32, P->cfg.block32};
+    L->cfg64 = SweepConfig{P->cfg.tps64, P->cfg.block64};
+    gf_status st = gf_set_links(L, host_links);
+    if (st != GF_OK) {
+        gf_destroy_lattice(L);
+        return st;
+    }
+    Job& j = P->jobs[slot];
+    j = Job();
+    j.id = job_id;
+    j.lat = L;
+    j.slot = slot;
+    j.p = *params;
+    j.anneal_total = anneal_sweeps;
+    j.T0 = T_start;
+    j.T1 = T_end;
+    j.seed = seed;
+    j.t_admit = now_s();
+    j.bytes = L->bytes;
+    P->bytes_in_use += j.bytes;
+    if (anneal_sweeps > 0) {
+        j.state = J_ANNEAL;
+    } else {
+        j.state = J_FIX;
+        st = do_measure(L, &j.theta, &j.F);
+        if (st != GF_OK) {
+            finish(P, j, st);
+        } else {
+            j.best = j.theta;
+            j.stall = 0;
+        }
+    }
+    fill_slot(P, slot);
+    return GF_OK;
+}
+
+gf_status gf_pool_step(gf_pool P)
+{
+    GF_TRY(pool_check(P));
+    const int C = P->chunk;
+    // loop heads (finish / promote) of jobs in the fix phase
+    for (auto& j : P->jobs)
+        if (j.lat && j.state == J_FIX) GF_TRY(fix_head(P, j));
+
+    // plan the step
+    const size_t nseg = (size_t)C * NKIND;
+    std::vector<uint32_t> n_entries(nseg, 0), n_tiles(nseg, 0);
+    auto add = [&](int k, int kind, int slot, const Geom& g) {
+        const size_t sgi = (size_t)k * NKIND + kind;
+        Entry* e = seg(P, P->lists_pin, k, kind);
+        e[n_entries[sgi]] = Entry{(uint32_t)slot, n_tiles[sgi]};
+        n_entries[sgi]++;
+        const int tps = (kind == K_HB32 || kind == K_OR32) ? P->cfg.tps32 : P->cfg.tps64;
+        n_tiles[sgi] += tiles_of(g, kind, tps);
+    };
+    bool any = false;
+    for (auto& j : P->jobs) {
+        j.plan_kind = -1;
+        j.plan_n = 0;
+        j.plan_measure_k = -1;
+        if (!j.lat || j.state == J_DONE) continue;
+        gf_lattice L = j.lat;
+        const bool fp32 = is_fp32(L);
+        if (j.state == J_ANNEAL) {
+            const int a = std::min(j.anneal_total - j.anneal_done, C);
+            const int kind = fp32 ? K_HB32 : K_HB64;
+            for (int k = 0; k < a; ++k) add(k, kind, j.slot, L->geom);
+            j.plan_kind = kind;
+            j.plan_n = a;
+            if (j.anneal_done + a == j.anneal_total) j.plan_measure_k = a - 1;
+        } else {
+            const int n = std::min(j.p.check_every, j.p.max_sweeps - j.res.sweeps);
+            const int kind = fp32 ? K_OR32 : K_OR64;
+            for (int k = 0; k < n; ++k) {
+                add(k, kind, j.slot, L->geom);
+                const int32_t done = j.res.sweeps + k + 1;
+                if (j.p.reunit_every > 0 && done % j.p.reunit_every == 0) add(k, fp32 ? K_R32 : K_R64, j.slot, L->geom);
+            }
+            j.plan_kind = kind;
+            j.plan_n = n;
+            j.plan_measure_k = n - 1;
+        }
+        if (j.plan_measure_k >= 0) {
+            add(j.plan_measure_k, fp32 ? K_M32 : K_M64, j.slot, L->geom);
+            add(j.plan_measure_k, K_FIN, j.slot, L->geom);
+        }
+        any = any || j.plan_n > 0;
+    }
+    if (!any) return GF_OK;
+
+    std::string sig(nseg, '0');
+    for (size_t i = 0; i < nseg; ++i) {
+        const int k = (int)(i / NKIND), kind = (int)(i % NKIND);
+        seg(P, P->lists_pin, k, kind)[n_entries[i]] = Entry{0u, n_tiles[i]};  // sentinel
+        P->counts_pin[i] = n_entries[i];
+        if (n_entries[i]) sig[i] = '1';
+    }
+    for (int s = 0; s < (int)P->jobs.size(); ++s) P->slots_pin[s] = P->slot_host[s];
+
+    GF_HIP(hipMemcpyAsync(P->slots_dev, P->slots_pin, sizeof(SlotDev) * P->jobs.size(), hipMemcpyHostToDevice,
+                          P->stream));
+    GF_HIP(hipMemcpyAsync(P->lists_dev, P->lists_pin, sizeof(Entry) * nseg * P->list_stride, hipMemcpyHostToDevice,
+                          P->stream));
+    GF_HIP(hipMemcpyAsync(P->counts_dev, P->counts_pin, sizeof(uint32_t) * nseg, hipMemcpyHostToDevice, P->stream));
+    GF_TRY(run_graph(P, sig));
+    GF_HIP(hipMemcpyAsync(P->results_pin, P->results_dev, sizeof(double) * 2 * P->jobs.size(), hipMemcpyDeviceToHost,
+                          P->stream));
+    GF_HIP(hipStreamSynchronize(P->stream));
+
+    // apply the step's outcome
+    for (auto& j : P->jobs) {
+        if (!j.lat || j.state == J_DONE || j.plan_n == 0) continue;
+        gf_lattice L = j.lat;
+        if (j.state == J_ANNEAL) {
+            j.anneal_done += j.plan_n;
+            L->anneal_sweeps += (uint32_t)j.plan_n;
+            P->slot_host[j.slot].anneal_base = L->anneal_sweeps;
+            if (j.plan_measure_k >= 0) {
+                j.theta = P->results_pin[2 * j.slot];
+                j.F = P->results_pin[2 * j.slot + 1];
+                j.state = J_FIX;
+                j.best = j.theta;
+                j.stall = 0;
+            }
+        } else {
+            j.res.sweeps += j.plan_n;
+            if (j.plan_kind == K_OR32)
+                j.res.sweeps_fp32 += j.plan_n;
+            else
+                j.res.sweeps_fp64 += j.plan_n;
+            j.theta = P->results_pin[2 * j.slot];
+            j.F = P->results_pin[2 * j.slot + 1];
+            if (j.theta < 0.99 * j.best) {
+                j.best = j.theta;
+                j.stall = 0;
+            } else {
+                ++j.stall;
+            }
+        }
+        if (j.plan_measure_k >= 0 && (!std::isfinite(j.theta) || !std::isfinite(j.F))) {
+            finish(P, j, GF_E_NUMERIC);
+            continue;
+        }
+        if (j.state == J_FIX && !(j.theta >= j.p.theta_target && j.res.sweeps < j.p.max_sweeps)) finish(P, j, GF_OK);
+    }
+    return GF_OK;
+}
+
+gf_status gf_pool_poll(gf_pool P, gf_pool_done* out, int32_t cap, int32_t* n)
+{
+    GF_TRY(pool_check(P));
+    if (!n || (cap > 0 && !out) || cap < 0) return fail(GF_E_ARG, "bad arguments");
+    const int32_t m = std::min<int32_t>(cap, (int32_t)P->finished.size());
+    for (int32_t i = 0; i < m; ++i) out[i] = P->finished[i];
+    P->finished.erase(P->finished.begin(), P->finished.begin() + m);
+    *n = m;
+    return GF_OK;
+}
+
+gf_status gf_pool_fetch_links(gf_pool P, uint64_t job_id, double* host)
+{
+    GF_TRY(pool_check(P));
+    if (!host) return fail(GF_E_ARG, "null argument");
+    for (auto& j : P->jobs)
+        if (j.lat && j.id == job_id) {
+            if (j.state != J_DONE) return fail(GF_E_STATE, "job %llu has not finished", (unsigned long long)job_id);
+            gf_status st = gf_get_links(j.lat, host);
+            if (st != GF_OK) return st;
+            release_job(P, j);
+            return GF_OK;
+        }
+    return fail(GF_E_ARG, "no job %llu in the pool", (unsigned long long)job_id);
+}
+
+gf_status gf_pool_release(gf_pool P, uint64_t job_id)
+{
+    GF_TRY(pool_check(P));
+    for (auto& j : P->jobs)
+        if (j.lat && j.id == job_id) {
+            if (j.state != J_DONE) return fail(GF_E_STATE, "job %llu has not finished", (unsigned long long)job_id);
+            release_job(P, j);
+            return GF_OK;
+        }
+    return fail(GF_E_ARG, "no job %llu in the pool", (unsigned long long)job_id);
+}
+
+gf_status gf_pool_stats(gf_pool P, int32_t* active, int32_t* finished, int64_t* bytes_in_use)
+{
+    GF_TRY(pool_check(P));
+    int32_t a = 0, f = 0;
+    for (auto& j : P->jobs) {
+        if (!j.lat) continue;
+        if (j.state == J_DONE)
+            ++f;
+        else
+            ++a;
+    }
+    if (active) *active = a;
+    if (finished) *finished = f;
+    if (bytes_in_use) *bytes_in_use = P->bytes_in_use;
+    return GF_OK;
+}
+
+}  // extern "C"

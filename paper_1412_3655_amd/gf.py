@@ -65,6 +65,30 @@ class gf_fix_result(ctypes.Structure):
     ]
 
 
+class gf_pool_config(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget", ctypes.c_size_t),
+        ("max_slots", ctypes.c_int32),
+        ("prec", ctypes.c_int32),
+        ("check_every", ctypes.c_int32),
+        ("mode", ctypes.c_int32),
+        ("tps32", ctypes.c_int32),
+        ("block32", ctypes.c_int32),
+        ("tps64", ctypes.c_int32),
+        ("block64", ctypes.c_int32),
+    ]
+
+
+class gf_pool_done(ctypes.Structure):
+    _fields_ = [
+        ("job_id", ctypes.c_uint64),
+        ("result", gf_fix_result),
+        ("status", ctypes.c_int32),
+        ("t_admit", ctypes.c_double),
+        ("t_done", ctypes.c_double),
+    ]
+
+
 @dataclass
 class FixResult:
     converged: bool
@@ -85,7 +109,8 @@ _SIGNATURES = {
     "gf_create_lattice": [ctypes.POINTER(_i32), ctypes.c_int, _vp, ctypes.POINTER(_vp)],
     "gf_destroy_lattice": [_vp],
     "gf_lattice_info": [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
-    "gf_set_sweep_config": [_vp, _i32, _i32],
+    "gf_set_sweep_config": [_vp, ctypes.c_int, _i32, _i32],
+    "gf_promote_fp64": [_vp],
     "gf_set_links": [_vp, _dp],
     "gf_set_links_device": [_vp, _vp],
     "gf_get_links": [_vp, _dp],
@@ -97,10 +122,21 @@ _SIGNATURES = {
     "gf_fix_until": [_vp, ctypes.POINTER(gf_fix_params), ctypes.POINTER(gf_fix_result)],
     "gf_reunitarize": [_vp],
     "gf_plaquette": [_vp, _dp],
+    "gf_pool_create": [ctypes.POINTER(gf_pool_config), _vp, ctypes.POINTER(_vp)],
+    "gf_pool_destroy": [_vp],
+    "gf_pool_job_bytes": [ctypes.POINTER(_i32), _i32, ctypes.POINTER(ctypes.c_int64)],
+    "gf_pool_admit": [_vp, ctypes.c_uint64, ctypes.POINTER(_i32), _dp, ctypes.POINTER(gf_fix_params), _i32,
+                      ctypes.c_double, ctypes.c_double, ctypes.c_uint64],
+    "gf_pool_step": [_vp],
+    "gf_pool_poll": [_vp, ctypes.POINTER(gf_pool_done), _i32, ctypes.POINTER(_i32)],
+    "gf_pool_fetch_links": [_vp, ctypes.c_uint64, _dp],
+    "gf_pool_release": [_vp, ctypes.c_uint64],
+    "gf_pool_stats": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_int64)],
+    "gf_clock": [],
     "gf_last_error": [],
     "gf_version": [],
 }
-_RESTYPES = {"gf_last_error": ctypes.c_char_p, "gf_version": ctypes.c_char_p}
+_RESTYPES = {"gf_last_error": ctypes.c_char_p, "gf_version": ctypes.c_char_p, "gf_clock": ctypes.c_double}
 
 
 def _check_single_hip_runtime():
@@ -207,8 +243,12 @@ def gf_lattice_info(lat):
     return v.value, b.value
 
 
-def gf_set_sweep_config(lat, tps: int, block: int) -> None:
-    _call("gf_set_sweep_config", lat, int(tps), int(block))
+def gf_set_sweep_config(lat, kernel: int, tps: int, block: int) -> None:
+    _call("gf_set_sweep_config", lat, int(kernel), int(tps), int(block))
+
+
+def gf_promote_fp64(lat) -> None:
+    _call("gf_promote_fp64", lat)
 
 
 def gf_set_links(lat, links) -> None:
@@ -338,5 +378,155 @@ class Lattice:
     def plaquette(self) -> float:
         return gf_plaquette(self.handle)
 
-    def set_sweep_config(self, tps: int, block: int):
-        gf_set_sweep_config(self.handle, tps, block)
+    def set_sweep_config(self, tps: int, block: int, kernel=None):
+        """Configure the sweep kernel of `kernel` precision (default: the lattice's own;
+        GF_MIXED configures both)."""
+        kinds = [kernel] if kernel is not None else (
+            [GF_FP32, GF_FP64] if self.prec == GF_MIXED else [self.prec])
+        for k in kinds:
+            gf_set_sweep_config(self.handle, k, tps, block)
+
+    def promote_fp64(self):
+        gf_promote_fp64(self.handle)
+
+
+# ----------------------------------------------------------------- pool --
+
+
+def gf_clock() -> float:
+    return float(lib().gf_clock())
+
+
+def gf_pool_job_bytes(dims, prec: int = GF_MIXED) -> int:
+    d = (_i32 * 4)(*[int(x) for x in dims])
+    b = ctypes.c_int64()
+    _call("gf_pool_job_bytes", d, int(prec), ctypes.byref(b))
+    return b.value
+
+
+def gf_pool_create(hbm_budget: int, max_slots: int, prec: int = GF_MIXED, check_every: int = 10,
+                   mode: int = GF_OR_EXACT, tps32: int = 0, block32: int = 0, tps64: int = 0, block64: int = 0,
+                   stream=None):
+    cfg = gf_pool_config(int(hbm_budget), int(max_slots), int(prec), int(check_every), int(mode), int(tps32),
+                         int(block32), int(tps64), int(block64))
+    out = _vp()
+    _call("gf_pool_create", ctypes.byref(cfg), _stream_handle(stream), ctypes.byref(out))
+    return out
+
+
+def gf_pool_destroy(pool) -> None:
+    _call("gf_pool_destroy", pool)
+
+
+def gf_pool_admit(pool, job_id: int, dims, links: np.ndarray, omega: float = 1.7, mode: int = GF_OR_EXACT,
+                  theta_target: float = 1e-12, max_sweeps: int = 3000, check_every: int = 10,
+                  reunit_every: int = 100, theta_switch: float = 1e-8, anneal_sweeps: int = 0,
+                  T_start: float = 1.25, T_end: float = 0.01, seed: int = 0) -> bool:
+    """Admit a job; returns False (nothing changed) when the pool is full."""
+    d = (_i32 * 4)(*[int(x) for x in dims])
+    v = 1
+    for x in dims:
+        v *= int(x)
+    u = _host_links(links, v)
+    p = gf_fix_params(float(omega), int(mode), float(theta_target), int(max_sweeps), int(check_every),
+                      int(reunit_every), float(theta_switch))
+    st = lib().gf_pool_admit(pool, int(job_id), d, u.ctypes.data_as(_dp), ctypes.byref(p), int(anneal_sweeps),
+                             float(T_start), float(T_end), int(seed) & 0xFFFFFFFFFFFFFFFF)
+    if st == GF_E_FULL:
+        return False
+    if st != GF_OK:
+        raise GFError(st, gf_last_error())
+    return True
+
+
+def gf_pool_step(pool) -> None:
+    _call("gf_pool_step", pool)
+
+
+def gf_pool_poll(pool, cap: int = 256):
+    """Finished jobs since the last poll: list of dicts."""
+    buf = (gf_pool_done * cap)()
+    n = _i32()
+    _call("gf_pool_poll", pool, buf, int(cap), ctypes.byref(n))
+    out = []
+    for i in range(n.value):
+        d = buf[i]
+        r = d.result
+        out.append(dict(job_id=int(d.job_id), status=int(d.status), t_admit=d.t_admit, t_done=d.t_done,
+                        result=FixResult(bool(r.converged), r.sweeps, r.sweeps_fp32, r.sweeps_fp64, r.theta, r.F)))
+    return out
+
+
+def gf_pool_fetch_links(pool, job_id: int, dims) -> np.ndarray:
+    v = 1
+    for x in dims:
+        v *= int(x)
+    out = np.empty((v, 4, 3, 3, 2), dtype=np.float64)
+    _call("gf_pool_fetch_links", pool, int(job_id), out.ctypes.data_as(_dp))
+    return out
+
+
+def gf_pool_release(pool, job_id: int) -> None:
+    _call("gf_pool_release", pool, int(job_id))
+
+
+def gf_pool_stats(pool):
+    a = _i32()
+    f = _i32()
+    b = ctypes.c_int64()
+    _call("gf_pool_stats", pool, ctypes.byref(a), ctypes.byref(f), ctypes.byref(b))
+    return a.value, f.value, b.value
+
+
+class Pool:
+    """Owning wrapper of a gf_pool."""
+
+    def __init__(self, hbm_budget: int, max_slots: int, prec: int = GF_MIXED, check_every: int = 10,
+                 mode: int = GF_OR_EXACT, tps32: int = 0, tps64: int = 0, stream=None):
+        self.check_every = int(check_every)
+        self.mode = int(mode)
+        self.handle = gf_pool_create(hbm_budget, max_slots, prec, check_every, mode, tps32, 0, tps64, 0, stream)
+        self.dims = {}
+
+    def admit(self, job_id, dims, links, **kw) -> bool:
+        kw.setdefault("check_every", self.check_every)
+        kw.setdefault("mode", self.mode)
+        ok = gf_pool_admit(self.handle, job_id, dims, links, **kw)
+        if ok:
+            self.dims[int(job_id)] = tuple(int(x) for x in dims)
+        return ok
+
+    def step(self):
+        gf_pool_step(self.handle)
+
+    def poll(self, cap: int = 256):
+        return gf_pool_poll(self.handle, cap)
+
+    def fetch_links(self, job_id):
+        out = gf_pool_fetch_links(self.handle, job_id, self.dims[int(job_id)])
+        self.dims.pop(int(job_id), None)
+        return out
+
+    def release(self, job_id):
+        gf_pool_release(self.handle, job_id)
+        self.dims.pop(int(job_id), None)
+
+    def stats(self):
+        return gf_pool_stats(self.handle)
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            gf_pool_destroy(self.handle)
+        self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -19,7 +19,7 @@ HEADER = os.path.join(ROOT, "include", "gf.h")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:gf_status|const char\*)\s+(gf_\w+)\s*\(", text, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:gf_status|const char\*|double)\s+(gf_\w+)\s*\(", text, flags=re.M)))
 
 
 def test_header_declares_the_boundary():

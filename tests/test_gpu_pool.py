@@ -1,0 +1,159 @@
+"""The batched pool: every job's result equals the same job run alone.
+
+A job in the pool runs the same fix-until iteration (and annealing prelude)
+as gf_anneal + gf_fix_until on a lone lattice, with the same per-site code and
+the same reduction order, so links, sweep counts, theta and F must agree
+bitwise; tolerance is therefore 0 (the stated bound is 1e-12).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import gauge_inputs as gi
+from paper_1412_3655_amd import gf
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    gf.lib()
+
+
+JOBS = [
+    # (dims, eps, seed, anneal sweeps)
+    ((4, 4, 4, 4), 0.6, 1, 0),
+    ((6, 4, 4, 8), 0.8, 2, 7),
+    ((8, 8, 8, 8), 0.5, 3, 0),
+    ((2, 4, 6, 8), 0.9, 4, 3),
+    ((6, 10, 6, 6), 0.7, 5, 0),
+    ((4, 6, 8, 4), 1.0, 6, 12),
+]
+
+
+def fix_kw(check_every):
+    return dict(omega=1.7, mode=gf.GF_OR_EXACT, theta_target=1e-12, max_sweeps=4000, check_every=check_every,
+                reunit_every=2 * check_every, theta_switch=1e-8)
+
+
+def solo(dims, links, prec, anneal, seed, check_every):
+    with gf.Lattice(dims, prec) as lat:
+        lat.set_links(links)
+        if anneal:
+            lat.anneal(anneal, 1.25, 0.05, seed)
+        r = lat.fix_until(**fix_kw(check_every))
+        return r, lat.get_links()
+
+
+@pytest.mark.parametrize("prec", [gf.GF_MIXED, gf.GF_FP64])
+def test_pool_equals_solo(prec):
+    ce = 5
+    say(f"pool vs solo prec={prec}")
+    inputs = [gi.gen_links(d, e, s) for (d, e, s, _) in JOBS]
+    ref = [solo(d, u, prec, a, 100 + i, ce) for i, ((d, e, s, a), u) in enumerate(zip(JOBS, inputs))]
+    with gf.Pool(1 << 34, 16, prec=prec, check_every=ce) as pool:
+        for i, ((d, e, s, a), u) in enumerate(zip(JOBS, inputs)):
+            assert pool.admit(1000 + i, d, u, anneal_sweeps=a, T_start=1.25, T_end=0.05, seed=100 + i,
+                              **{k: v for k, v in fix_kw(ce).items() if k not in ("check_every", "mode")})
+        done = {}
+        for _ in range(2000):
+            pool.step()
+            for d in pool.poll():
+                done[d["job_id"]] = d
+            if len(done) == len(JOBS):
+                break
+        assert len(done) == len(JOBS)
+        for i, ((dims, e, s, a), (r_solo, l_solo)) in enumerate(zip(JOBS, ref)):
+            d = done[1000 + i]
+            r = d["result"]
+            say(f"  job {i} {dims}: pool sweeps {r.sweeps} ({r.sweeps_fp32}/{r.sweeps_fp64}) theta {r.theta:.3e}; "
+                f"solo {r_solo.sweeps} ({r_solo.sweeps_fp32}/{r_solo.sweeps_fp64}) theta {r_solo.theta:.3e}")
+            assert d["status"] == gf.GF_OK
+            assert r == r_solo
+            links = pool.fetch_links(1000 + i)
+            assert np.array_equal(links, l_solo)
+        assert pool.stats() == (0, 0, 0)
+
+
+def test_pool_admission_backfill_and_failures():
+    say("pool admission, budget, backfill, failures")
+    dims = (4, 4, 4, 4)
+    need = gf.gf_pool_job_bytes(dims, gf.GF_MIXED)
+    u = gi.gen_links(dims, 0.6, 9)
+    bad = u.copy()
+    bad[5, 2, 1, 1, 0] = np.nan
+    with gf.Pool(3 * need, 8, prec=gf.GF_MIXED, check_every=5) as pool:
+        assert pool.admit(1, dims, u)
+        assert pool.admit(2, dims, bad)  # fails numerically at its first measurement
+        assert pool.admit(3, dims, u)
+        assert not pool.admit(4, dims, u)  # budget exhausted: nothing changes
+        with pytest.raises(gf.GFError) as e:
+            pool.admit(1, dims, u)
+        assert e.value.status in (gf.GF_E_ARG, gf.GF_E_FULL)
+        with pytest.raises(gf.GFError) as e:
+            pool.release(3)  # not finished yet
+        assert e.value.status == gf.GF_E_STATE
+        with pytest.raises(gf.GFError):
+            gf.gf_pool_admit(pool.handle, 5, dims, u, check_every=7)  # cadence differs from the pool's
+        done = {}
+        for _ in range(500):
+            pool.step()
+            for d in pool.poll():
+                done[d["job_id"]] = d
+            if len(done) == 3:
+                break
+        assert done[2]["status"] == gf.GF_E_NUMERIC
+        assert done[1]["status"] == gf.GF_OK and done[1]["result"].converged
+        assert done[3]["result"] == done[1]["result"]
+        pool.release(2)
+        assert pool.admit(4, dims, u)  # backfill into the freed budget
+        for _ in range(500):
+            pool.step()
+            got = pool.poll()
+            if got:
+                assert got[0]["job_id"] == 4 and got[0]["result"] == done[1]["result"]
+                break
+        a, f, b = pool.stats()
+        assert a == 0 and f == 3 and b == 3 * need
+
+
+def test_pool_many_shapes_fill():
+    """64 lattices of uneven volume in one pool converge, each equal to its solo run."""
+    say("pool 64 uneven lattices")
+    shapes = [(4, 4, 4, 4), (6, 4, 4, 4), (4, 6, 6, 4), (8, 4, 4, 6)]
+    rng = np.random.default_rng(4)
+    picks = rng.integers(0, len(shapes), 64)
+    with gf.Pool(1 << 34, 64, prec=gf.GF_MIXED, check_every=10) as pool:
+        inputs = {}
+        for i, p in enumerate(picks):
+            d = shapes[p]
+            inputs[i] = (d, gi.gen_links(d, 0.4 + 0.6 * rng.random(), 1000 + i))
+            assert pool.admit(i, d, inputs[i][1], theta_target=1e-12, max_sweeps=3000, reunit_every=100,
+                              theta_switch=1e-8)
+        done = {}
+        for _ in range(1000):
+            pool.step()
+            for d in pool.poll():
+                done[d["job_id"]] = d
+            if len(done) == 64:
+                break
+        assert len(done) == 64
+        for i in (0, 17, 63):
+            d, u = inputs[i]
+            with gf.Lattice(d, gf.GF_MIXED) as lat:
+                lat.set_links(u)
+                r = lat.fix_until(omega=1.7, mode=0, theta_target=1e-12, max_sweeps=3000, check_every=10,
+                                  reunit_every=100, theta_switch=1e-8)
+            assert done[i]["result"] == r
+        assert all(v["result"].converged for v in done.values())
