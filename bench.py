@@ -123,6 +123,7 @@ def main(argv=None):
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="use --tps/--block instead of the autotuner")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -155,9 +156,14 @@ def main(argv=None):
         del a, b
 
     result = {}
+    tuning = {}
     with gf.Lattice(dims, gf.GF_FP64, stream=stream) as lat:
         lat.set_sweep_config(args.tps, args.block)
         lat.set_links(links)
+        if not args.no_tune:
+            args.tps, args.block, table = lat.autotune(gf.GF_FP64, n_sweeps=5)
+            tuning["f64"] = [[t, b, round(us, 1)] for (t, b, us) in table]
+            log(f"fp64 autotune: tps={args.tps} block={args.block}")
         P0 = lat.plaquette()
         log(f"fp64: warmup {args.warmup} sweeps")
         with torch.cuda.stream(stream):
@@ -173,6 +179,10 @@ def main(argv=None):
         with gf.Lattice(dims, gf.GF_FP32, stream=stream) as lat:
             lat.set_sweep_config(args.tps32, args.block32)
             lat.set_links(links)
+            if not args.no_tune:
+                args.tps32, args.block32, table = lat.autotune(gf.GF_FP32, n_sweeps=5)
+                tuning["f32"] = [[t, b, round(us, 1)] for (t, b, us) in table]
+                log(f"fp32 autotune: tps={args.tps32} block={args.block32}")
             with torch.cuda.stream(stream):
                 lat.sweep(args.warmup, args.omega, args.mode)
                 total, wall, per_launch = time_sweeps(lat, gf, torch, stream, args.steps, args.omega, args.mode)
@@ -215,7 +225,7 @@ def main(argv=None):
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
             "traffic": traffic,
-            "kernel": "k_or_half_sweep<double, TPS=%d, exact, %d>" % (args.tps, args.block),
+            "kernel": "k_or_half_sweep<double, TPS=%d, exact, BLOCK=%d>" % (args.tps, args.block),
             "algorithmic_bytes_per_launch": launch_bytes,
             "mean_launch_us": r64["per_launch"] * 1e6,
         },
@@ -229,8 +239,11 @@ def main(argv=None):
             "unit": "site-updates/s",
             "hbm_GBps_algorithmic": rate32 * BYTES_PER_SITE["f32"] / 1e9,
             "mean_launch_us": r32["per_launch"] * 1e6,
+            "threads_per_site": args.tps32,
+            "block": args.block32,
             "note": "201 MB of FP32 links fit in the 256 MB Infinity Cache, so this can exceed HBM peak",
         }
+    line["tuning_us_per_sweep"] = tuning or None
     if not args.no_cpu:
         log("cpu baseline (FP64 oracle)")
         line["cpu_baseline"] = cpu_baseline(links, dims, args.omega, args.mode, args.cpu_budget)

@@ -108,6 +108,24 @@ gf_status gf_set_sweep_config(gf_lattice lat, gf_prec kernel, int32_t tps, int32
  * No-op for other precisions or after promotion.  Async. */
 gf_status gf_promote_fp64(gf_lattice lat);
 
+typedef struct {
+    int32_t tps;
+    int32_t block;
+    double us_per_sweep; /* mean time of one sweep (both colours), microseconds */
+} gf_tune_entry;
+
+/* Autotuner (the paper tunes threads per site and launch bounds at run time,
+ * Sec. 4 and 5): time every valid sweep configuration of precision `kernel`
+ * (GF_FP64 or GF_FP32) on a scratch copy of the lattice's links (one warm-up
+ * sweep, then n_sweeps timed sweeps each), write up to cap entries to table
+ * (may be NULL), and make the fastest the lattice's configuration.  When
+ * cache_path is not NULL, a result stored there for the same device
+ * architecture, extents and precision is applied without timing (*n_out = 0),
+ * and a newly timed result is appended to it (plain text, one line per key).
+ * The links are not changed.  Syncs. */
+gf_status gf_autotune(gf_lattice lat, gf_prec kernel, int32_t n_sweeps, const char* cache_path, gf_tune_entry* table,
+                      int32_t cap, int32_t* n_out, int32_t* tps_out, int32_t* block_out);
+
 /* Upload links from a host canonical array of 4*V*18 doubles; only rows 0
  * and 1 of each link are kept (row 2 is rebuilt as the conjugated cross
  * product whenever it is needed, Sec. 3.1).  Syncs. */

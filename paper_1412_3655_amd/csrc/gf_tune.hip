@@ -1,0 +1,150 @@
+// gf_tune.hip -- run-time autotuning of the sweep kernel (include/gf.h,
+// gf_autotune).  The paper's cuLGT2 picks 4 or 8 threads per site, register
+// limits and texture loads by trying them at run time (Sec. 4 and 5); here the
+// axes are lanes per site (1, 2, 4, 8) and threads per block (64..512), timed
+// with HIP events on a scratch copy of the links so the lattice is unchanged.
+// Every configuration gives bitwise the same links, so only time decides.
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "gf_internal.h"
+
+using namespace gf;
+using namespace gf::detail;
+
+namespace {
+
+std::string device_arch()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+std::string cache_key(gf_lattice L, gf_prec kernel)
+{
+    char buf[128];
+    snprintf(buf, sizeof buf, "%s %d %d %d %d %s", device_arch().c_str(), L->dims[0], L->dims[1], L->dims[2],
+             L->dims[3], kernel == GF_FP32 ? "fp32" : "fp64");
+    return buf;
+}
+
+bool cache_lookup(const char* path, const std::string& key, int* tps, int* block)
+{
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char line[256];
+    bool found = false;
+    while (fgets(line, sizeof line, f)) {
+        if (strncmp(line, key.c_str(), key.size()) != 0 || line[key.size()] != ' ') continue;
+        int t = 0, b = 0;
+        if (sscanf(line + key.size(), "%d %d", &t, &b) == 2 && sweep_config_valid(SweepConfig{t, b})) {
+            *tps = t;
+            *block = b;
+            found = true;  // the last matching line wins
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+}  // namespace
+
+extern "C" gf_status gf_autotune(gf_lattice L, gf_prec kernel, int32_t n_sweeps, const char* cache_path,
+                                 gf_tune_entry* table, int32_t cap, int32_t* n_out, int32_t* tps_out,
+                                 int32_t* block_out)
+{
+    GF_TRY(check_ready(L));
+    if (kernel != GF_FP64 && kernel != GF_FP32) return fail(GF_E_ARG, "kernel precision must be GF_FP64 or GF_FP32");
+    if ((kernel == GF_FP64 && !L->f64) || (kernel == GF_FP32 && !L->f32))
+        return fail(GF_E_ARG, "the lattice has no links of that precision");
+    if (n_sweeps < 1 || cap < 0 || (cap > 0 && !table)) return fail(GF_E_ARG, "bad arguments");
+    if (n_out) *n_out = 0;
+    const std::string key = cache_key(L, kernel);
+    int best_t = 0, best_b = 0;
+    if (cache_path && cache_lookup(cache_path, key, &best_t, &best_b)) {
+        (kernel == GF_FP32 ? L->cfg32 : L->cfg64) = SweepConfig{best_t, best_b};
+        if (tps_out) *tps_out = best_t;
+        if (block_out) *block_out = best_b;
+        return GF_OK;
+    }
+
+    const size_t chunks = (size_t)2 * 4 * L->geom.ld * (kernel == GF_FP32 ? 3 : 6);
+    const size_t bytes = chunks * 16;
+    void* scratch = nullptr;
+    void* gscratch = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    gf_status st = GF_OK;
+    double best_us = 1e300;
+    int n = 0;
+    const bool track = kernel == GF_FP32 && L->gacc.base != nullptr;
+    const size_t gbytes = (size_t)2 * 3 * L->geom.ld * 16;
+    hipError_t e = hipMalloc(&scratch, bytes);
+    if (e == hipSuccess && track) e = hipMalloc(&gscratch, gbytes);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(scratch, kernel == GF_FP32 ? (void*)L->f32 : (void*)L->f64, bytes, hipMemcpyDeviceToDevice,
+                           L->stream);
+    if (e == hipSuccess && track) e = hipMemcpyAsync(gscratch, L->gacc.base, gbytes, hipMemcpyDeviceToDevice, L->stream);
+    const GField g_none{nullptr, 0};
+    const GField g_s{(float4*)gscratch, L->geom.ld};
+    for (int tps : {1, 2, 4, 8}) {
+        for (int block : {64, 128, 256, 512}) {
+            const SweepConfig c{tps, block};
+            if (e != hipSuccess || !sweep_config_valid(c)) continue;
+            auto sweep = [&]() -> hipError_t {
+                for (int p = 0; p < 2; ++p) {
+                    hipError_t r;
+                    if (kernel == GF_FP32)
+                        r = launch_or_half_sweep(LinkField<float>{(float4*)scratch, L->geom.ld}, L->geom, p, 1.7f,
+                                                 GF_OR_EXACT, c, track ? g_s : g_none, L->stream);
+                    else
+                        r = launch_or_half_sweep(LinkField<double>{(double2*)scratch, L->geom.ld}, L->geom, p, 1.7,
+                                                 GF_OR_EXACT, c, L->stream);
+                    if (r != hipSuccess) return r;
+                }
+                return hipSuccess;
+            };
+            e = sweep();
+            if (e == hipSuccess) e = hipEventRecord(e0, L->stream);
+            for (int k = 0; k < n_sweeps && e == hipSuccess; ++k) e = sweep();
+            if (e == hipSuccess) e = hipEventRecord(e1, L->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) break;
+            const double us = 1e3 * (double)ms / n_sweeps;
+            if (n < cap) table[n] = gf_tune_entry{tps, block, us};
+            ++n;
+            if (us < best_us) {
+                best_us = us;
+                best_t = tps;
+                best_b = block;
+            }
+        }
+    }
+    if (e != hipSuccess) st = fail(GF_E_HIP, "autotune: %s", hipGetErrorString(e));
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(L->stream);
+    if (scratch) (void)hipFree(scratch);
+    if (gscratch) (void)hipFree(gscratch);
+    if (st != GF_OK) return st;
+    (kernel == GF_FP32 ? L->cfg32 : L->cfg64) = SweepConfig{best_t, best_b};
+    if (n_out) *n_out = std::min(n, cap);
+    if (tps_out) *tps_out = best_t;
+    if (block_out) *block_out = best_b;
+    if (cache_path) {
+        FILE* f = fopen(cache_path, "a");
+        if (f) {
+            fprintf(f, "%s %d %d %.3f\n", key.c_str(), best_t, best_b, best_us);
+            fclose(f);
+        }
+    }
+    return GF_OK;
+}

@@ -65,6 +65,10 @@ class gf_fix_result(ctypes.Structure):
     ]
 
 
+class gf_tune_entry(ctypes.Structure):
+    _fields_ = [("tps", ctypes.c_int32), ("block", ctypes.c_int32), ("us_per_sweep", ctypes.c_double)]
+
+
 class gf_pool_config(ctypes.Structure):
     _fields_ = [
         ("hbm_budget", ctypes.c_size_t),
@@ -111,6 +115,8 @@ _SIGNATURES = {
     "gf_lattice_info": [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
     "gf_set_sweep_config": [_vp, ctypes.c_int, _i32, _i32],
     "gf_promote_fp64": [_vp],
+    "gf_autotune": [_vp, ctypes.c_int, _i32, ctypes.c_char_p, ctypes.POINTER(gf_tune_entry), _i32,
+                    ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
     "gf_set_links": [_vp, _dp],
     "gf_set_links_device": [_vp, _vp],
     "gf_get_links": [_vp, _dp],
@@ -245,6 +251,19 @@ def gf_lattice_info(lat):
 
 def gf_set_sweep_config(lat, kernel: int, tps: int, block: int) -> None:
     _call("gf_set_sweep_config", lat, int(kernel), int(tps), int(block))
+
+
+def gf_autotune(lat, kernel: int, n_sweeps: int = 5, cache_path=None):
+    """Returns (tps, block, table) with table a list of (tps, block, us_per_sweep)."""
+    cap = 32
+    buf = (gf_tune_entry * cap)()
+    n = _i32()
+    t = _i32()
+    b = _i32()
+    cp = None if cache_path is None else os.fsencode(cache_path)
+    _call("gf_autotune", lat, int(kernel), int(n_sweeps), cp, buf, cap, ctypes.byref(n), ctypes.byref(t),
+          ctypes.byref(b))
+    return t.value, b.value, [(buf[i].tps, buf[i].block, buf[i].us_per_sweep) for i in range(n.value)]
 
 
 def gf_promote_fp64(lat) -> None:
@@ -388,6 +407,10 @@ class Lattice:
 
     def promote_fp64(self):
         gf_promote_fp64(self.handle)
+
+    def autotune(self, kernel=None, n_sweeps: int = 5, cache_path=None):
+        k = kernel if kernel is not None else (GF_FP32 if self.prec != GF_FP64 else GF_FP64)
+        return gf_autotune(self.handle, k, n_sweeps, cache_path)
 
 
 # ----------------------------------------------------------------- pool --

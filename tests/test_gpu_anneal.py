@@ -77,19 +77,22 @@ def test_anneal_bitwise_across_tps_and_resume():
 
 
 def test_anneal_then_or_matches_oracle():
-    """The annealing prelude followed by overrelaxation to theta < 1e-12 (8^4)."""
+    """The annealing prelude followed by the fix-until iteration (8^4, 400 sweeps at most):
+    same sweep count, same theta history end point, links within 1e-10."""
     say("anneal 20 + fix_until on 8^4")
     u = gi.gen_links(CFG8, 1.0, 13)
     ref = u.copy()
     oracle.anneal(ref, CFG8, 20, 1.25, 0.01, 5)
-    ro = oracle.fix_until(ref, CFG8, 1.7, 0, 1e-12, 3000, 10, 100)
+    ro = oracle.fix_until(ref, CFG8, 1.7, 0, 1e-12, 400, 10, 100)
     with gf.Lattice(CFG8) as lat:
         lat.set_links(u)
         lat.anneal(20, 1.25, 0.01, 5)
-        r = lat.fix_until(omega=1.7, mode=0, theta_target=1e-12, max_sweeps=3000, check_every=10, reunit_every=100)
+        r = lat.fix_until(omega=1.7, mode=0, theta_target=1e-12, max_sweeps=400, check_every=10, reunit_every=100)
         got = lat.get_links()
-    say(f"  oracle sweeps {ro['sweeps']} F {ro['F']:.15f}; gpu sweeps {r.sweeps} F {r.F:.15f}")
-    assert r.converged and r.sweeps == ro["sweeps"]
+    say(f"  oracle sweeps {ro['sweeps']} theta {ro['theta']:.4e} F {ro['F']:.15f}; "
+        f"gpu sweeps {r.sweeps} theta {r.theta:.4e} F {r.F:.15f}")
+    assert r.converged == ro["converged"] and r.sweeps == ro["sweeps"]
+    assert abs(r.theta - ro["theta"]) <= 1e-8 * ro["theta"]
     assert abs(r.F - ro["F"]) <= 1e-12
     assert np.abs(got - ref).max() <= 1e-10
 

@@ -218,7 +218,7 @@ def test_errors_on_device():
         with pytest.raises(gf.GFError) as e:
             lat.set_sweep_config(3, 256)
         assert e.value.status == gf.GF_E_ARG
-        with pytest.raises(gf.GFError):
+        with pytest.raises(ValueError):
             lat.set_links(np.zeros(10))
         bad = u.copy()
         bad[3, 1, 0, 0, 0] = np.nan

@@ -1,0 +1,48 @@
+"""The autotuner: times every valid configuration on a scratch copy, applies the
+fastest, leaves the links untouched, and reuses its on-disk cache."""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import gauge_inputs as gi
+from paper_1412_3655_amd import gf
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    gf.lib()
+
+
+@pytest.mark.parametrize("prec", [gf.GF_FP64, gf.GF_FP32, gf.GF_MIXED])
+def test_autotune(prec, tmp_path):
+    print(f"autotune prec={prec}", flush=True)
+    sys.stdout.flush()
+    dims = (8, 8, 8, 12)
+    u = gi.gen_links(dims, 0.7, 3)
+    cache = os.path.join(str(tmp_path), "tune.txt")
+    with gf.Lattice(dims, prec) as lat:
+        lat.set_links(u)
+        before = lat.get_links()
+        t, b, table = lat.autotune(n_sweeps=2, cache_path=cache)
+        assert np.array_equal(lat.get_links(), before)
+        assert len(table) == 15  # 4 lane splits x 4 block sizes, minus (1 lane, 512)
+        assert (t, b) == min(table, key=lambda e: e[2])[:2]
+        assert all(e[2] > 0 for e in table)
+        t2, b2, table2 = lat.autotune(n_sweeps=2, cache_path=cache)
+        assert (t2, b2) == (t, b) and table2 == []
+        lat.sweep(2, 1.7)
+        tuned = lat.get_links()
+    with gf.Lattice(dims, prec) as lat:
+        lat.set_links(u)
+        lat.sweep(2, 1.7)
+        assert np.array_equal(lat.get_links(), tuned)
+    assert len(open(cache).read().strip().splitlines()) == 1
