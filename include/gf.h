@@ -255,6 +255,13 @@ gf_status gf_pool_release(gf_pool pool, uint64_t job_id);
 /* Resident jobs still iterating, finished jobs not yet released, and device bytes held. */
 gf_status gf_pool_stats(gf_pool pool, int32_t* active, int32_t* finished, int64_t* bytes_in_use);
 
+/* Bandwidth probe: a plain float4 copy of `bytes` (>= 4096, multiple of 16)
+ * between two fresh device buffers, `blocks` blocks of 256 threads striding
+ * over it (nontemporal != 0: non-temporal loads and stores), timed over reps
+ * launches on the default stream after one warm-up.  *gbps = 2*bytes*reps /
+ * time (read + write).  Allocates and frees its buffers.  Syncs. */
+gf_status gf_probe_copy(size_t bytes, int32_t reps, int32_t nontemporal, int32_t blocks, double* gbps);
+
 /* Seconds on the library's steady clock (the clock of t_admit / t_done). */
 double gf_clock(void);
 

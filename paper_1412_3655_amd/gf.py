@@ -139,6 +139,7 @@ _SIGNATURES = {
     "gf_pool_release": [_vp, ctypes.c_uint64],
     "gf_pool_stats": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_int64)],
     "gf_clock": [],
+    "gf_probe_copy": [ctypes.c_size_t, _i32, _i32, _i32, _dp],
     "gf_last_error": [],
     "gf_version": [],
 }
@@ -414,6 +415,12 @@ class Lattice:
 
 
 # ----------------------------------------------------------------- pool --
+
+
+def gf_probe_copy(nbytes: int, reps: int = 10, nontemporal: bool = False, blocks: int = 4096) -> float:
+    g = ctypes.c_double()
+    _call("gf_probe_copy", int(nbytes), int(reps), int(bool(nontemporal)), int(blocks), ctypes.byref(g))
+    return g.value
 
 
 def gf_clock() -> float:
