@@ -33,7 +33,7 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, AMD published peak
 BYTES_PER_SITE = {"f64": 1536, "f32": 768}  # 8 links x 12 reals, read + write
 METRIC = "SU(3) OR site-updates/s + HBM GB/s (% peak); converged lattices/s, p99 to θ<1e-12"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "or_sweep_f64_32x4_traffic.md")
-SWEEP_SOURCES = ["gf_sweep.hip", "gf_device.h"]
+SWEEP_SOURCES = ["gf_sweep.hip", "gf_site.h", "gf_device.h"]
 
 
 def log(msg):
