@@ -96,6 +96,32 @@ def copy_bandwidth(gf, nbytes=1 << 30, reps=10):
     return best
 
 
+def fix_until_leg(gf, torch, stream, links, dims, args):
+    """The 32^4 run to theta < 1e-12: plain FP64 and FP32-bulk / FP64-polish (GF_MIXED)."""
+    out = {}
+    kw = dict(omega=args.omega, mode=args.mode, theta_target=1e-12, max_sweeps=args.fix_max_sweeps,
+              check_every=10, reunit_every=100, theta_switch=args.theta_switch)
+    for name, prec in (("fp64", gf.GF_FP64), ("mixed", gf.GF_MIXED)):
+        with gf.Lattice(dims, prec, stream=stream) as lat:
+            lat.set_sweep_config(args.tps, args.block, args.nt, kernel=gf.GF_FP64)
+            if prec == gf.GF_MIXED:
+                lat.set_sweep_config(args.tps32, args.block32, args.nt32, kernel=gf.GF_FP32)
+            lat.set_links(links)
+            P0 = lat.plaquette()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = lat.fix_until(**kw)
+            dt = time.perf_counter() - t0
+            P1 = lat.plaquette()
+        out[name] = {"seconds": dt, "converged": r.converged, "sweeps": r.sweeps, "sweeps_fp32": r.sweeps_fp32,
+                     "sweeps_fp64": r.sweeps_fp64, "theta": r.theta, "F": r.F, "plaquette_drift": abs(P1 - P0)}
+        log(f"fix_until {name}: {dt:.2f} s, sweeps {r.sweeps} ({r.sweeps_fp32}/{r.sweeps_fp64}), "
+            f"theta {r.theta:.3e}, F {r.F:.12f}")
+    out["mixed"]["dF_vs_fp64"] = out["mixed"]["F"] - out["fp64"]["F"]
+    out["speedup_mixed_vs_fp64"] = out["fp64"]["seconds"] / out["mixed"]["seconds"]
+    return out
+
+
 def cpu_baseline(links, dims, omega, mode, budget_s):
     import oracle
 
@@ -130,12 +156,17 @@ def main(argv=None):
     ap.add_argument("--mode", type=int, default=0, help="0 = exact SU(2) power, 1 = binomial form")
     ap.add_argument("--tps", type=int, default=4)
     ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--nt", type=int, default=0, help="non-temporal link accesses (0/1)")
+    ap.add_argument("--nt32", type=int, default=0)
     ap.add_argument("--tps32", type=int, default=4)
     ap.add_argument("--block32", type=int, default=256)
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--no-fix", action="store_true", help="skip the run to theta < 1e-12")
+    ap.add_argument("--fix-max-sweeps", type=int, default=20000)
+    ap.add_argument("--theta-switch", type=float, default=1e-9)
     ap.add_argument("--no-tune", action="store_true", help="use --tps/--block instead of the autotuner")
     args = ap.parse_args(argv)
 
@@ -166,12 +197,12 @@ def main(argv=None):
     result = {}
     tuning = {}
     with gf.Lattice(dims, gf.GF_FP64, stream=stream) as lat:
-        lat.set_sweep_config(args.tps, args.block)
+        lat.set_sweep_config(args.tps, args.block, args.nt)
         lat.set_links(links)
         if not args.no_tune:
-            args.tps, args.block, table = lat.autotune(gf.GF_FP64, n_sweeps=5)
-            tuning["f64"] = [[t, b, round(us, 1)] for (t, b, us) in table]
-            log(f"fp64 autotune: tps={args.tps} block={args.block}")
+            (args.tps, args.block, args.nt), table = lat.autotune(gf.GF_FP64, n_sweeps=5)
+            tuning["f64"] = [[t, b, nt, round(us, 1)] for (t, b, nt, us) in table]
+            log(f"fp64 autotune: tps={args.tps} block={args.block} nontemporal={args.nt}")
         P0 = lat.plaquette()
         log(f"fp64: warmup {args.warmup} sweeps")
         with torch.cuda.stream(stream):
@@ -185,12 +216,12 @@ def main(argv=None):
 
     if not args.no_fp32:
         with gf.Lattice(dims, gf.GF_FP32, stream=stream) as lat:
-            lat.set_sweep_config(args.tps32, args.block32)
+            lat.set_sweep_config(args.tps32, args.block32, args.nt32)
             lat.set_links(links)
             if not args.no_tune:
-                args.tps32, args.block32, table = lat.autotune(gf.GF_FP32, n_sweeps=5)
-                tuning["f32"] = [[t, b, round(us, 1)] for (t, b, us) in table]
-                log(f"fp32 autotune: tps={args.tps32} block={args.block32}")
+                (args.tps32, args.block32, args.nt32), table = lat.autotune(gf.GF_FP32, n_sweeps=5)
+                tuning["f32"] = [[t, b, nt, round(us, 1)] for (t, b, nt, us) in table]
+                log(f"fp32 autotune: tps={args.tps32} block={args.block32} nontemporal={args.nt32}")
             with torch.cuda.stream(stream):
                 lat.sweep(args.warmup, args.omega, args.mode)
                 total, wall, per_launch = time_sweeps(lat, gf, torch, stream, args.steps, args.omega, args.mode)
@@ -223,6 +254,7 @@ def main(argv=None):
             "site_updates_per_step": V,
             "threads_per_site": args.tps,
             "block": args.block,
+            "nontemporal": args.nt,
         },
         "hbm_GBps_algorithmic": rate * BYTES_PER_SITE["f64"] / 1e9,
         "pct_hbm_peak": 100.0 * rate * BYTES_PER_SITE["f64"] / 1e9 / HBM_PEAK_GBPS,
@@ -233,7 +265,7 @@ def main(argv=None):
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
             "traffic": traffic,
-            "kernel": "k_or_half_sweep<double, TPS=%d, exact, BLOCK=%d>" % (args.tps, args.block),
+            "kernel": "k_or_half_sweep<double, TPS=%d, exact, BLOCK=%d, NT=%d>" % (args.tps, args.block, args.nt),
             "algorithmic_bytes_per_launch": launch_bytes,
             "mean_launch_us": r64["per_launch"] * 1e6,
         },
@@ -249,9 +281,12 @@ def main(argv=None):
             "mean_launch_us": r32["per_launch"] * 1e6,
             "threads_per_site": args.tps32,
             "block": args.block32,
+            "nontemporal": args.nt32,
             "note": "201 MB of FP32 links fit in the 256 MB Infinity Cache, so this can exceed HBM peak",
         }
     line["tuning_us_per_sweep"] = tuning or None
+    if not args.no_fix:
+        line["fix_until_theta_1e-12"] = fix_until_leg(gf, torch, stream, links, dims, args)
     line["device_copy_GBps"] = copy_bandwidth(gf)
     if not args.no_cpu:
         log("cpu baseline (FP64 oracle)")

@@ -94,12 +94,14 @@ gf_status gf_destroy_lattice(gf_lattice lat);
 /* Number of sites V and bytes of device memory held by the lattice. */
 gf_status gf_lattice_info(gf_lattice lat, int64_t* volume, int64_t* device_bytes);
 
-/* Kernel configuration of the overrelaxation sweep in precision `kernel`
- * (GF_FP64 or GF_FP32; a GF_MIXED lattice uses both): tps lanes per site
- * (1, 2, 4 or 8; the paper's design uses 4 or 8 threads per site, Sec. 4.2)
- * and threads per block (64, 128, 256 or 512; not 512 with tps 1).  Every
- * valid choice gives bitwise the same links.  Default 4 / 256. */
-gf_status gf_set_sweep_config(gf_lattice lat, gf_prec kernel, int32_t tps, int32_t block);
+/* Kernel configuration of the sweep in precision `kernel` (GF_FP64 or
+ * GF_FP32; a GF_MIXED lattice uses both): tps lanes per site (1, 2, 4 or 8;
+ * the paper's design uses 4 or 8 threads per site, Sec. 4.2), threads per
+ * block (64, 128, 256 or 512; not 512 with tps 1) and the cache policy of the
+ * link accesses (0 = plain, 1 = non-temporal loads and stores, only with
+ * tps <= 4 and block <= 256).  Every valid choice gives bitwise the same
+ * links.  Default 4 / 256 / 0. */
+gf_status gf_set_sweep_config(gf_lattice lat, gf_prec kernel, int32_t tps, int32_t block, int32_t nontemporal);
 
 /* GF_MIXED: leave the float32 phase now.  The float64 links become
  * g(x) U0_mu(x) g(x+mu^)^dag, U0 the links given to gf_set_links and g the
@@ -111,20 +113,23 @@ gf_status gf_promote_fp64(gf_lattice lat);
 typedef struct {
     int32_t tps;
     int32_t block;
+    int32_t nontemporal;
     double us_per_sweep; /* mean time of one sweep (both colours), microseconds */
 } gf_tune_entry;
 
-/* Autotuner (the paper tunes threads per site and launch bounds at run time,
- * Sec. 4 and 5): time every valid sweep configuration of precision `kernel`
+/* Autotuner (the paper tunes threads per site, launch bounds and texture
+ * loads at run time, Sec. 4 and 5): time every valid sweep configuration
+ * (lanes per site, block size, cache policy) of precision `kernel`
  * (GF_FP64 or GF_FP32) on a scratch copy of the lattice's links (one warm-up
  * sweep, then n_sweeps timed sweeps each), write up to cap entries to table
  * (may be NULL), and make the fastest the lattice's configuration.  When
  * cache_path is not NULL, a result stored there for the same device
  * architecture, extents and precision is applied without timing (*n_out = 0),
  * and a newly timed result is appended to it (plain text, one line per key).
- * The links are not changed.  Syncs. */
+ * *chosen (may be NULL) receives the configuration applied.  The links are
+ * not changed.  Syncs. */
 gf_status gf_autotune(gf_lattice lat, gf_prec kernel, int32_t n_sweeps, const char* cache_path, gf_tune_entry* table,
-                      int32_t cap, int32_t* n_out, int32_t* tps_out, int32_t* block_out);
+                      int32_t cap, int32_t* n_out, gf_tune_entry* chosen);
 
 /* Upload links from a host canonical array of 4*V*18 doubles; only rows 0
  * and 1 of each link are kept (row 2 is rebuilt as the conjugated cross

@@ -144,22 +144,79 @@ __device__ __forceinline__ size_t chunk_index(const LinkField<R>& f, int parity,
     return ((size_t)((parity * 4 + mu) * ChunkOf<R>::N + c)) * f.ld + h;
 }
 
+// 16-byte chunk access; NT = non-temporal (streaming) loads and stores, the
+// cache-policy axis of the autotuner.
+typedef double nt_v2d __attribute__((ext_vector_type(2)));
+typedef float nt_v4f __attribute__((ext_vector_type(4)));
+
+template <bool NT>
+__device__ __forceinline__ double2 ld16(const double2* p)
+{
+    if constexpr (NT) {
+        const nt_v2d v = __builtin_nontemporal_load((const nt_v2d*)p);
+        return make_double2(v.x, v.y);
+    } else {
+        return *p;
+    }
+}
+
+template <bool NT>
+__device__ __forceinline__ float4 ld16(const float4* p)
+{
+    if constexpr (NT) {
+        const nt_v4f v = __builtin_nontemporal_load((const nt_v4f*)p);
+        return make_float4(v.x, v.y, v.z, v.w);
+    } else {
+        return *p;
+    }
+}
+
+template <bool NT>
+__device__ __forceinline__ void st16(double2* p, double2 v)
+{
+    if constexpr (NT) {
+        nt_v2d w;
+        w.x = v.x;
+        w.y = v.y;
+        __builtin_nontemporal_store(w, (nt_v2d*)p);
+    } else {
+        *p = v;
+    }
+}
+
+template <bool NT>
+__device__ __forceinline__ void st16(float4* p, float4 v)
+{
+    if constexpr (NT) {
+        nt_v4f w;
+        w.x = v.x;
+        w.y = v.y;
+        w.z = v.z;
+        w.w = v.w;
+        __builtin_nontemporal_store(w, (nt_v4f*)p);
+    } else {
+        *p = v;
+    }
+}
+
 // Rows 0 and 1 of U_mu at (parity, h).
+template <bool NT = false>
 __device__ __forceinline__ void load_rows01(const LinkField<double>& f, int parity, int mu, uint32_t h, M3<double>& u)
 {
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-        double2 v = f.base[chunk_index(f, parity, mu, c, h)];
+        double2 v = ld16<NT>(f.base + chunk_index(f, parity, mu, c, h));
         u.re[c / 3][c % 3] = v.x;
         u.im[c / 3][c % 3] = v.y;
     }
 }
 
+template <bool NT = false>
 __device__ __forceinline__ void load_rows01(const LinkField<float>& f, int parity, int mu, uint32_t h, M3<float>& u)
 {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        float4 v = f.base[chunk_index(f, parity, mu, c, h)];
+        float4 v = ld16<NT>(f.base + chunk_index(f, parity, mu, c, h));
         const int e0 = 2 * c, e1 = 2 * c + 1;
         u.re[e0 / 3][e0 % 3] = v.x;
         u.im[e0 / 3][e0 % 3] = v.y;
@@ -168,6 +225,7 @@ __device__ __forceinline__ void load_rows01(const LinkField<float>& f, int parit
     }
 }
 
+template <bool NT = false>
 __device__ __forceinline__ void store_rows01(const LinkField<double>& f, int parity, int mu, uint32_t h,
                                              const M3<double>& u)
 {
@@ -176,10 +234,11 @@ __device__ __forceinline__ void store_rows01(const LinkField<double>& f, int par
         double2 v;
         v.x = u.re[c / 3][c % 3];
         v.y = u.im[c / 3][c % 3];
-        f.base[chunk_index(f, parity, mu, c, h)] = v;
+        st16<NT>(f.base + chunk_index(f, parity, mu, c, h), v);
     }
 }
 
+template <bool NT = false>
 __device__ __forceinline__ void store_rows01(const LinkField<float>& f, int parity, int mu, uint32_t h,
                                              const M3<float>& u)
 {
@@ -191,7 +250,7 @@ __device__ __forceinline__ void store_rows01(const LinkField<float>& f, int pari
         v.y = u.im[e0 / 3][e0 % 3];
         v.z = u.re[e1 / 3][e1 % 3];
         v.w = u.im[e1 / 3][e1 % 3];
-        f.base[chunk_index(f, parity, mu, c, h)] = v;
+        st16<NT>(f.base + chunk_index(f, parity, mu, c, h), v);
     }
 }
 

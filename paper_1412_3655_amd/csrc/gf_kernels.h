@@ -8,11 +8,13 @@
 
 namespace gf {
 
-// Sweep kernel configuration: lanes per site (1, 2, 4 or 8) and block size
-// (64, 128, 256 or 512 threads).
+// Sweep kernel configuration: lanes per site (1, 2, 4 or 8), block size
+// (64, 128, 256 or 512 threads) and cache policy of the link accesses (0 =
+// plain, 1 = non-temporal; the latter with tps <= 4 and block <= 256).
 struct SweepConfig {
     int tps = 4;
     int block = 256;
+    int nt = 0;
 };
 
 bool sweep_config_valid(const SweepConfig& c);

@@ -10,7 +10,7 @@ namespace gf {
 
 namespace {
 
-template <typename R, int TPS, int MODE, int BLOCK, bool TRACKG>
+template <typename R, int TPS, int MODE, int BLOCK, bool TRACKG, bool NT>
 __global__ void __launch_bounds__(BLOCK) k_or_half_sweep(LinkField<R> f, Geom g, int parity, Rule<R> rule,
                                                          GField gacc)
 {
@@ -19,37 +19,44 @@ __global__ void __launch_bounds__(BLOCK) k_or_half_sweep(LinkField<R> f, Geom g,
     const int r = (int)(gid % TPS);
     // whole groups of TPS lanes leave together, so every DPP partner is live
     if (h >= g.vh) return;
-    site_update<R, TPS, MODE, TRACKG>(f, g, parity, h, r, rule, gacc);
+    site_update<R, TPS, MODE, TRACKG, NT>(f, g, parity, h, r, rule, gacc);
 }
 
 template <typename R, int TPS, int MODE, bool TRACKG>
-hipError_t launch_tps(const LinkField<R>& f, const Geom& g, int parity, const Rule<R>& rule, int block,
+hipError_t launch_tps(const LinkField<R>& f, const Geom& g, int parity, const Rule<R>& rule, const SweepConfig& c,
                       const GField& gacc, hipStream_t st)
 {
+    const int block = c.block;
     const uint64_t threads = (uint64_t)g.vh * TPS;
     const uint32_t grid = (uint32_t)((threads + block - 1) / block);
     if (grid == 0) return hipSuccess;
-    switch (block) {
-        case 64:
-            hipLaunchKernelGGL((k_or_half_sweep<R, TPS, MODE, 64, TRACKG>), dim3(grid), dim3(64), 0, st, f, g, parity,
-                               rule, gacc);
-            break;
-        case 128:
-            hipLaunchKernelGGL((k_or_half_sweep<R, TPS, MODE, 128, TRACKG>), dim3(grid), dim3(128), 0, st, f, g,
-                               parity, rule, gacc);
-            break;
-        case 256:
-            hipLaunchKernelGGL((k_or_half_sweep<R, TPS, MODE, 256, TRACKG>), dim3(grid), dim3(256), 0, st, f, g,
-                               parity, rule, gacc);
-            break;
-        default:
-            if constexpr (TPS > 1)
-                hipLaunchKernelGGL((k_or_half_sweep<R, TPS, MODE, 512, TRACKG>), dim3(grid), dim3(512), 0, st, f, g,
-                                   parity, rule, gacc);
-            else
-                return hipErrorInvalidValue;
-            break;
+#define GF_LAUNCH(B, NTV) \
+    hipLaunchKernelGGL((k_or_half_sweep<R, TPS, MODE, B, TRACKG, NTV>), dim3(grid), dim3(B), 0, st, f, g, parity, rule, gacc)
+    if (c.nt) {
+        if constexpr (TPS <= 4) {
+            switch (block) {
+                case 64: GF_LAUNCH(64, true); break;
+                case 128: GF_LAUNCH(128, true); break;
+                case 256: GF_LAUNCH(256, true); break;
+                default: return hipErrorInvalidValue;
+            }
+        } else {
+            return hipErrorInvalidValue;
+        }
+    } else {
+        switch (block) {
+            case 64: GF_LAUNCH(64, false); break;
+            case 128: GF_LAUNCH(128, false); break;
+            case 256: GF_LAUNCH(256, false); break;
+            default:
+                if constexpr (TPS > 1)
+                    GF_LAUNCH(512, false);
+                else
+                    return hipErrorInvalidValue;
+                break;
+        }
     }
+#undef GF_LAUNCH
     return hipGetLastError();
 }
 
@@ -58,10 +65,10 @@ hipError_t launch_mode(const LinkField<R>& f, const Geom& g, int parity, const R
                        const GField& gacc, hipStream_t st)
 {
     switch (c.tps) {
-        case 1: return launch_tps<R, 1, MODE, TRACKG>(f, g, parity, rule, c.block, gacc, st);
-        case 2: return launch_tps<R, 2, MODE, TRACKG>(f, g, parity, rule, c.block, gacc, st);
-        case 8: return launch_tps<R, 8, MODE, TRACKG>(f, g, parity, rule, c.block, gacc, st);
-        default: return launch_tps<R, 4, MODE, TRACKG>(f, g, parity, rule, c.block, gacc, st);
+        case 1: return launch_tps<R, 1, MODE, TRACKG>(f, g, parity, rule, c, gacc, st);
+        case 2: return launch_tps<R, 2, MODE, TRACKG>(f, g, parity, rule, c, gacc, st);
+        case 8: return launch_tps<R, 8, MODE, TRACKG>(f, g, parity, rule, c, gacc, st);
+        default: return launch_tps<R, 4, MODE, TRACKG>(f, g, parity, rule, c, gacc, st);
     }
 }
 
@@ -71,8 +78,9 @@ bool sweep_config_valid(const SweepConfig& c)
 {
     const bool tps_ok = c.tps == 1 || c.tps == 2 || c.tps == 4 || c.tps == 8;
     const bool blk_ok = c.block == 64 || c.block == 128 || c.block == 256 || c.block == 512;
+    const bool nt_ok = c.nt == 0 || (c.nt == 1 && c.tps <= 4 && c.block <= 256);
     // one lane per site needs more than the 256 registers a 512-thread block allows
-    return tps_ok && blk_ok && !(c.tps == 1 && c.block == 512);
+    return tps_ok && blk_ok && nt_ok && !(c.tps == 1 && c.block == 512);
 }
 
 hipError_t launch_or_half_sweep(const LinkField<double>& f, const Geom& g, int parity, double omega, int mode,

@@ -1,7 +1,8 @@
 // gf_tune.hip -- run-time autotuning of the sweep kernel (include/gf.h,
 // gf_autotune).  The paper's cuLGT2 picks 4 or 8 threads per site, register
 // limits and texture loads by trying them at run time (Sec. 4 and 5); here the
-// axes are lanes per site (1, 2, 4, 8) and threads per block (64..512), timed
+// axes are lanes per site (1, 2, 4, 8), threads per block (64..512) and the
+// cache policy of the link accesses (plain / non-temporal), timed
 // with HIP events on a scratch copy of the links so the lattice is unchanged.
 // Every configuration gives bitwise the same links, so only time decides.
 #include <cstdio>
@@ -33,7 +34,7 @@ std::string cache_key(gf_lattice L, gf_prec kernel)
     return buf;
 }
 
-bool cache_lookup(const char* path, const std::string& key, int* tps, int* block)
+bool cache_lookup(const char* path, const std::string& key, SweepConfig* out)
 {
     FILE* f = fopen(path, "r");
     if (!f) return false;
@@ -41,10 +42,9 @@ bool cache_lookup(const char* path, const std::string& key, int* tps, int* block
     bool found = false;
     while (fgets(line, sizeof line, f)) {
         if (strncmp(line, key.c_str(), key.size()) != 0 || line[key.size()] != ' ') continue;
-        int t = 0, b = 0;
-        if (sscanf(line + key.size(), "%d %d", &t, &b) == 2 && sweep_config_valid(SweepConfig{t, b})) {
-            *tps = t;
-            *block = b;
+        int t = 0, b = 0, nt = 0;
+        if (sscanf(line + key.size(), "%d %d %d", &t, &b, &nt) == 3 && sweep_config_valid(SweepConfig{t, b, nt})) {
+            *out = SweepConfig{t, b, nt};
             found = true;  // the last matching line wins
         }
     }
@@ -55,8 +55,7 @@ bool cache_lookup(const char* path, const std::string& key, int* tps, int* block
 }  // namespace
 
 extern "C" gf_status gf_autotune(gf_lattice L, gf_prec kernel, int32_t n_sweeps, const char* cache_path,
-                                 gf_tune_entry* table, int32_t cap, int32_t* n_out, int32_t* tps_out,
-                                 int32_t* block_out)
+                                 gf_tune_entry* table, int32_t cap, int32_t* n_out, gf_tune_entry* chosen)
 {
     GF_TRY(check_ready(L));
     if (kernel != GF_FP64 && kernel != GF_FP32) return fail(GF_E_ARG, "kernel precision must be GF_FP64 or GF_FP32");
@@ -65,11 +64,10 @@ extern "C" gf_status gf_autotune(gf_lattice L, gf_prec kernel, int32_t n_sweeps,
     if (n_sweeps < 1 || cap < 0 || (cap > 0 && !table)) return fail(GF_E_ARG, "bad arguments");
     if (n_out) *n_out = 0;
     const std::string key = cache_key(L, kernel);
-    int best_t = 0, best_b = 0;
-    if (cache_path && cache_lookup(cache_path, key, &best_t, &best_b)) {
-        (kernel == GF_FP32 ? L->cfg32 : L->cfg64) = SweepConfig{best_t, best_b};
-        if (tps_out) *tps_out = best_t;
-        if (block_out) *block_out = best_b;
+    SweepConfig best{};
+    if (cache_path && cache_lookup(cache_path, key, &best)) {
+        (kernel == GF_FP32 ? L->cfg32 : L->cfg64) = best;
+        if (chosen) *chosen = gf_tune_entry{best.tps, best.block, best.nt, 0.0};
         return GF_OK;
     }
 
@@ -93,9 +91,10 @@ extern "C" gf_status gf_autotune(gf_lattice L, gf_prec kernel, int32_t n_sweeps,
     if (e == hipSuccess && track) e = hipMemcpyAsync(gscratch, L->gacc.base, gbytes, hipMemcpyDeviceToDevice, L->stream);
     const GField g_none{nullptr, 0};
     const GField g_s{(float4*)gscratch, L->geom.ld};
+    for (int nt : {0, 1})
     for (int tps : {1, 2, 4, 8}) {
         for (int block : {64, 128, 256, 512}) {
-            const SweepConfig c{tps, block};
+            const SweepConfig c{tps, block, nt};
             if (e != hipSuccess || !sweep_config_valid(c)) continue;
             auto sweep = [&]() -> hipError_t {
                 for (int p = 0; p < 2; ++p) {
@@ -119,12 +118,11 @@ extern "C" gf_status gf_autotune(gf_lattice L, gf_prec kernel, int32_t n_sweeps,
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
             if (e != hipSuccess) break;
             const double us = 1e3 * (double)ms / n_sweeps;
-            if (n < cap) table[n] = gf_tune_entry{tps, block, us};
+            if (n < cap) table[n] = gf_tune_entry{tps, block, nt, us};
             ++n;
             if (us < best_us) {
                 best_us = us;
-                best_t = tps;
-                best_b = block;
+                best = c;
             }
         }
     }
@@ -135,14 +133,13 @@ extern "C" gf_status gf_autotune(gf_lattice L, gf_prec kernel, int32_t n_sweeps,
     if (scratch) (void)hipFree(scratch);
     if (gscratch) (void)hipFree(gscratch);
     if (st != GF_OK) return st;
-    (kernel == GF_FP32 ? L->cfg32 : L->cfg64) = SweepConfig{best_t, best_b};
+    (kernel == GF_FP32 ? L->cfg32 : L->cfg64) = best;
     if (n_out) *n_out = std::min(n, cap);
-    if (tps_out) *tps_out = best_t;
-    if (block_out) *block_out = best_b;
+    if (chosen) *chosen = gf_tune_entry{best.tps, best.block, best.nt, best_us};
     if (cache_path) {
         FILE* f = fopen(cache_path, "a");
         if (f) {
-            fprintf(f, "%s %d %d %.3f\n", key.c_str(), best_t, best_b, best_us);
+            fprintf(f, "%s %d %d %d %.3f\n", key.c_str(), best.tps, best.block, best.nt, best_us);
             fclose(f);
         }
     }

@@ -66,7 +66,8 @@ class gf_fix_result(ctypes.Structure):
 
 
 class gf_tune_entry(ctypes.Structure):
-    _fields_ = [("tps", ctypes.c_int32), ("block", ctypes.c_int32), ("us_per_sweep", ctypes.c_double)]
+    _fields_ = [("tps", ctypes.c_int32), ("block", ctypes.c_int32), ("nontemporal", ctypes.c_int32),
+                ("us_per_sweep", ctypes.c_double)]
 
 
 class gf_pool_config(ctypes.Structure):
@@ -113,10 +114,10 @@ _SIGNATURES = {
     "gf_create_lattice": [ctypes.POINTER(_i32), ctypes.c_int, _vp, ctypes.POINTER(_vp)],
     "gf_destroy_lattice": [_vp],
     "gf_lattice_info": [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
-    "gf_set_sweep_config": [_vp, ctypes.c_int, _i32, _i32],
+    "gf_set_sweep_config": [_vp, ctypes.c_int, _i32, _i32, _i32],
     "gf_promote_fp64": [_vp],
     "gf_autotune": [_vp, ctypes.c_int, _i32, ctypes.c_char_p, ctypes.POINTER(gf_tune_entry), _i32,
-                    ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
+                    ctypes.POINTER(_i32), ctypes.POINTER(gf_tune_entry)],
     "gf_set_links": [_vp, _dp],
     "gf_set_links_device": [_vp, _vp],
     "gf_get_links": [_vp, _dp],
@@ -250,21 +251,21 @@ def gf_lattice_info(lat):
     return v.value, b.value
 
 
-def gf_set_sweep_config(lat, kernel: int, tps: int, block: int) -> None:
-    _call("gf_set_sweep_config", lat, int(kernel), int(tps), int(block))
+def gf_set_sweep_config(lat, kernel: int, tps: int, block: int, nontemporal: int = 0) -> None:
+    _call("gf_set_sweep_config", lat, int(kernel), int(tps), int(block), int(nontemporal))
 
 
 def gf_autotune(lat, kernel: int, n_sweeps: int = 5, cache_path=None):
-    """Returns (tps, block, table) with table a list of (tps, block, us_per_sweep)."""
-    cap = 32
+    """Returns (chosen, table): chosen = (tps, block, nontemporal), table = list of
+    (tps, block, nontemporal, us_per_sweep) (empty when the cache answered)."""
+    cap = 64
     buf = (gf_tune_entry * cap)()
     n = _i32()
-    t = _i32()
-    b = _i32()
+    ch = gf_tune_entry()
     cp = None if cache_path is None else os.fsencode(cache_path)
-    _call("gf_autotune", lat, int(kernel), int(n_sweeps), cp, buf, cap, ctypes.byref(n), ctypes.byref(t),
-          ctypes.byref(b))
-    return t.value, b.value, [(buf[i].tps, buf[i].block, buf[i].us_per_sweep) for i in range(n.value)]
+    _call("gf_autotune", lat, int(kernel), int(n_sweeps), cp, buf, cap, ctypes.byref(n), ctypes.byref(ch))
+    table = [(buf[i].tps, buf[i].block, buf[i].nontemporal, buf[i].us_per_sweep) for i in range(n.value)]
+    return (ch.tps, ch.block, ch.nontemporal), table
 
 
 def gf_promote_fp64(lat) -> None:
@@ -398,13 +399,13 @@ class Lattice:
     def plaquette(self) -> float:
         return gf_plaquette(self.handle)
 
-    def set_sweep_config(self, tps: int, block: int, kernel=None):
+    def set_sweep_config(self, tps: int, block: int, nontemporal: int = 0, kernel=None):
         """Configure the sweep kernel of `kernel` precision (default: the lattice's own;
         GF_MIXED configures both)."""
         kinds = [kernel] if kernel is not None else (
             [GF_FP32, GF_FP64] if self.prec == GF_MIXED else [self.prec])
         for k in kinds:
-            gf_set_sweep_config(self.handle, k, tps, block)
+            gf_set_sweep_config(self.handle, k, tps, block, nontemporal)
 
     def promote_fp64(self):
         gf_promote_fp64(self.handle)

@@ -40,9 +40,9 @@ def _device():
     gf.lib()
 
 
-def gpu_run(dims, links, prec=gf.GF_FP64, tps=4, block=256, action=None):
+def gpu_run(dims, links, prec=gf.GF_FP64, tps=4, block=256, action=None, nt=0):
     with gf.Lattice(dims, prec) as lat:
-        lat.set_sweep_config(tps, block)
+        lat.set_sweep_config(tps, block, nt)
         lat.set_links(links)
         out = action(lat) if action else None
         return lat.get_links(), out
@@ -121,9 +121,16 @@ def test_bitwise_identical_across_launch_configs():
     say("bitwise across tps/block, RAGGED")
     u = gi.gen_links(RAGGED, 0.8, 5)
     base, _ = gpu_run(RAGGED, u, tps=4, block=256, action=lambda lat: lat.sweep(3, 1.7, 0))
-    for tps, block in [(1, 64), (1, 256), (2, 128), (2, 512), (4, 64), (4, 512), (8, 256), (8, 512)]:
-        got, _ = gpu_run(RAGGED, u, tps=tps, block=block, action=lambda lat: lat.sweep(3, 1.7, 0))
-        assert np.array_equal(got, base), (tps, block)
+    for tps, block, nt in [(1, 64, 0), (1, 256, 0), (2, 128, 0), (2, 512, 0), (4, 64, 0), (4, 512, 0), (8, 256, 0),
+                           (8, 512, 0), (1, 64, 1), (2, 128, 1), (4, 256, 1)]:
+        got, _ = gpu_run(RAGGED, u, tps=tps, block=block, nt=nt, action=lambda lat: lat.sweep(3, 1.7, 0))
+        assert np.array_equal(got, base), (tps, block, nt)
+    for prec in (gf.GF_FP32,):
+        b32, _ = gpu_run(RAGGED, u, prec=prec, tps=4, block=256, action=lambda lat: lat.sweep(3, 1.7, 0))
+        for tps, block, nt in [(1, 128, 0), (2, 64, 1), (8, 512, 0)]:
+            got, _ = gpu_run(RAGGED, u, prec=prec, tps=tps, block=block, nt=nt,
+                             action=lambda lat: lat.sweep(3, 1.7, 0))
+            assert np.array_equal(got, b32), (prec, tps, block, nt)
 
 
 @pytest.mark.parametrize("dims", EDGE)
@@ -215,9 +222,10 @@ def test_errors_on_device():
         with pytest.raises(gf.GFError) as e:
             lat.half_sweep(2, 1.5)
         assert e.value.status == gf.GF_E_ARG
-        with pytest.raises(gf.GFError) as e:
-            lat.set_sweep_config(3, 256)
-        assert e.value.status == gf.GF_E_ARG
+        for bad in [(3, 256, 0), (8, 256, 1), (4, 512, 1), (1, 512, 0), (4, 256, 2)]:
+            with pytest.raises(gf.GFError) as e:
+                lat.set_sweep_config(*bad)
+            assert e.value.status == gf.GF_E_ARG
         with pytest.raises(ValueError):
             lat.set_links(np.zeros(10))
         bad = u.copy()

@@ -32,13 +32,14 @@ def test_autotune(prec, tmp_path):
     with gf.Lattice(dims, prec) as lat:
         lat.set_links(u)
         before = lat.get_links()
-        t, b, table = lat.autotune(n_sweeps=2, cache_path=cache)
+        chosen, table = lat.autotune(n_sweeps=2, cache_path=cache)
         assert np.array_equal(lat.get_links(), before)
-        assert len(table) == 15  # 4 lane splits x 4 block sizes, minus (1 lane, 512)
-        assert (t, b) == min(table, key=lambda e: e[2])[:2]
-        assert all(e[2] > 0 for e in table)
-        t2, b2, table2 = lat.autotune(n_sweeps=2, cache_path=cache)
-        assert (t2, b2) == (t, b) and table2 == []
+        # plain: 4 lane splits x 4 block sizes minus (1 lane, 512); non-temporal: 3 x 3
+        assert len(table) == 15 + 9
+        assert chosen == min(table, key=lambda e: e[3])[:3]
+        assert all(e[3] > 0 for e in table)
+        chosen2, table2 = lat.autotune(n_sweeps=2, cache_path=cache)
+        assert chosen2 == chosen and table2 == []
         lat.sweep(2, 1.7)
         tuned = lat.get_links()
     with gf.Lattice(dims, prec) as lat:
