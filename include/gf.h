@@ -177,8 +177,9 @@ gf_status gf_measure_theta_F(gf_lattice lat, double* theta, double* F);
  * min(check_every, remaining) sweeps (reunitarising after every sweep whose
  * count is a multiple of reunit_every) and measure again (Sec. 2: iterate
  * until the gauge condition holds to a given precision).  GF_MIXED: float32
- * sweeps (with the transformation g(x) tracked) until theta < theta_switch,
- * then the float64 links are rebuilt as g(x) U0_mu(x) g(x+mu^)^dag from the
+ * sweeps (with the transformation g(x) tracked) until theta < theta_switch
+ * or until theta has reached no new minimum for 16 consecutive checks (the
+ * float32 floor), then the float64 links are rebuilt as g(x) U0_mu(x) g(x+mu^)^dag from the
  * original links and the loop continues in float64.  Non-convergence is a
  * result (converged = 0), not an error.  Syncs. */
 gf_status gf_fix_until(gf_lattice lat, const gf_fix_params* params, gf_fix_result* result);

@@ -92,12 +92,50 @@ gf_status do_half_sweep(gf_lattice L, int parity, double omega, int mode)
     return GF_OK;
 }
 
-gf_status do_sweeps(gf_lattice L, int32_t n, double omega, int mode)
+gf_status launch_sweeps(gf_lattice L, int32_t n, double omega, int mode)
 {
     for (int32_t k = 0; k < n; ++k) {
         GF_TRY(do_half_sweep(L, 0, omega, mode));
         GF_TRY(do_half_sweep(L, 1, omega, mode));
     }
+    return GF_OK;
+}
+
+void clear_graphs(gf_lattice L)
+{
+    for (auto& kv : L->sweep_graphs) (void)hipGraphExecDestroy(kv.second);
+    L->sweep_graphs.clear();
+}
+
+// n sweeps.  On a non-default stream runs of two or more sweeps are captured
+// once in a hipGraph (kernel nodes only) and replayed, which removes the
+// launch gaps between the 2n half-sweeps.
+gf_status do_sweeps(gf_lattice L, int32_t n, double omega, int mode)
+{
+    if (n < 2 || L->stream == nullptr) return launch_sweeps(L, n, omega, mode);
+    const bool fp32 = is_fp32(L);
+    const SweepConfig& c = fp32 ? L->cfg32 : L->cfg64;
+    const int kind = fp32 ? (g_tracking(L).base ? 2 : 1) : 0;
+    const auto key = std::make_tuple(n, omega, mode, kind, c.tps, c.block, c.nt);
+    auto it = L->sweep_graphs.find(key);
+    if (it == L->sweep_graphs.end()) {
+        if (L->sweep_graphs.size() >= 16) clear_graphs(L);
+        hipGraph_t graph = nullptr;
+        GF_HIP(hipStreamBeginCapture(L->stream, hipStreamCaptureModeRelaxed));
+        gf_status st = launch_sweeps(L, n, omega, mode);
+        hipError_t e = hipStreamEndCapture(L->stream, &graph);
+        if (st != GF_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return fail(GF_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return fail(GF_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        it = L->sweep_graphs.emplace(key, exec).first;
+    }
+    GF_HIP(hipGraphLaunch(it->second, L->stream));
     return GF_OK;
 }
 
@@ -159,6 +197,7 @@ gf_status download_canonical(gf_lattice L, double* dev_canon)
 
 void release(gf_lattice L)
 {
+    clear_graphs(L);
     if (L->f64) (void)hipFree(L->f64);
     if (L->f32) (void)hipFree(L->f32);
     if (L->gacc.base) (void)hipFree(L->gacc.base);
@@ -420,22 +459,27 @@ gf_status gf_fix_until(gf_lattice L, const gf_fix_params* p, gf_fix_result* res)
     double theta = 0.0, F = 0.0;
     GF_TRY(do_measure(L, &theta, &F));
     int32_t sweeps = 0;
-    // float32 phase of GF_MIXED: leave it once theta < theta_switch, or when theta
-    // has not improved by 1% over the last kStall checks (float32 noise floor).
-    constexpr int kStall = 8;
     double best = theta;
     int stall = 0;
     while (theta >= p->theta_target && sweeps < p->max_sweeps) {
-        if (L->prec == GF_MIXED && L->phase == 0 && (theta < p->theta_switch || stall >= kStall)) {
+        if (L->prec == GF_MIXED && L->phase == 0 && (theta < p->theta_switch || stall >= kStallChecks)) {
             GF_TRY(do_promote(L));
             GF_TRY(do_measure(L, &theta, &F));
             continue;
         }
         const bool fp32 = is_fp32(L);
         const int32_t n = std::min(p->check_every, p->max_sweeps - sweeps);
-        for (int32_t k = 0; k < n; ++k) {
-            GF_TRY(do_sweeps(L, 1, p->omega, p->mode));
-            ++sweeps;
+        // n sweeps, reunitarising after every sweep whose count is a multiple of reunit_every
+        int32_t done = 0;
+        while (done < n) {
+            int32_t run = n - done;
+            if (p->reunit_every > 0) {
+                const int32_t to_reunit = p->reunit_every - (sweeps % p->reunit_every);
+                run = std::min(run, to_reunit);
+            }
+            GF_TRY(do_sweeps(L, run, p->omega, p->mode));
+            sweeps += run;
+            done += run;
             if (p->reunit_every > 0 && sweeps % p->reunit_every == 0) GF_TRY(do_reunitarize(L));
         }
         if (fp32)
@@ -443,12 +487,7 @@ gf_status gf_fix_until(gf_lattice L, const gf_fix_params* p, gf_fix_result* res)
         else
             res->sweeps_fp64 += n;
         GF_TRY(do_measure(L, &theta, &F));
-        if (theta < 0.99 * best) {
-            best = theta;
-            stall = 0;
-        } else {
-            ++stall;
-        }
+        update_stall(theta, &best, &stall);
     }
     res->converged = theta < p->theta_target;
     res->sweeps = sweeps;

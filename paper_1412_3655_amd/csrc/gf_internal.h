@@ -2,7 +2,9 @@
 // (gf_capi.hip) and the pool (gf_pool.hip).  Not part of the public ABI.
 #pragma once
 
+#include <map>
 #include <string>
+#include <tuple>
 
 #include "gf.h"
 #include "gf_kernels.h"
@@ -26,6 +28,9 @@ struct gf_lattice_ {
     uint32_t anneal_sweeps = 0;             // heat-bath sweep counter (Philox counter word)
     gf::SweepConfig cfg64;
     gf::SweepConfig cfg32;
+    // hipGraphs of n back-to-back sweeps, keyed by (n, omega, mode, precision
+    // and g tracking, tps, block, cache policy); only on a non-default stream
+    std::map<std::tuple<int32_t, double, int, int, int, int, int>, hipGraphExec_t> sweep_graphs;
 };
 
 namespace gf {
@@ -64,6 +69,21 @@ gf_status do_measure(gf_lattice L, double* theta, double* F);
 gf_status upload_canonical(gf_lattice L, const double* dev_canon);
 gf_status download_canonical(gf_lattice L, double* dev_canon);
 void release(gf_lattice L);
+
+// Float32 phase of GF_MIXED: it is left once theta < theta_switch or when theta
+// has reached no new minimum for kStallChecks consecutive checks (float32
+// noise floor); update_stall runs after every check that followed sweeps.
+constexpr int kStallChecks = 16;
+
+inline void update_stall(double theta, double* best, int* stall)
+{
+    if (theta < *best) {
+        *best = theta;
+        *stall = 0;
+    } else {
+        ++*stall;
+    }
+}
 
 // Temperature of annealing sweep s of n: linear from T_start (s = 0) to T_end (s = n - 1).
 inline double anneal_temperature(int32_t s, int32_t n, double T_start, double T_end)

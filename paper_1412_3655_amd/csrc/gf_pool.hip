@@ -438,7 +438,7 @@ gf_status fix_head(gf_pool P, Job& j)
             finish(P, j, GF_OK);
             return GF_OK;
         }
-        if (L->prec == GF_MIXED && L->phase == 0 && (j.theta < j.p.theta_switch || j.stall >= 8)) {
+        if (L->prec == GF_MIXED && L->phase == 0 && (j.theta < j.p.theta_switch || j.stall >= kStallChecks)) {
             GF_TRY(do_promote(L));
             gf_status st = do_measure(L, &j.theta, &j.F);
             if (st != GF_OK) {
@@ -725,12 +725,7 @@ gf_status gf_pool_step(gf_pool P)
                 j.res.sweeps_fp64 += j.plan_n;
             j.theta = P->results_pin[2 * j.slot];
             j.F = P->results_pin[2 * j.slot + 1];
-            if (j.theta < 0.99 * j.best) {
-                j.best = j.theta;
-                j.stall = 0;
-            } else {
-                ++j.stall;
-            }
+            update_stall(j.theta, &j.best, &j.stall);
         }
         if (j.plan_measure_k >= 0 && (!std::isfinite(j.theta) || !std::isfinite(j.F))) {
             finish(P, j, GF_E_NUMERIC);

@@ -266,3 +266,38 @@ def test_full_size_32x4_one_sweep():
     th1_o, F1_o = oracle.measure(ref, dims)
     assert abs(th1 - th1_o) <= 1e-10 * th1_o
     assert abs(F1 - F1_o) <= 1e-13
+
+
+def test_graph_replays_match_direct_launches():
+    """On a non-default stream multi-sweep runs are replayed hipGraphs; every replay (with
+    eager work and synchronisation between replays) must equal direct launches bitwise."""
+    import torch
+
+    say("graph replays vs direct launches")
+    u = gi.gen_links(RAGGED, 0.8, 21)
+    direct = []
+    with gf.Lattice(RAGGED) as lat:  # default stream: direct launches
+        lat.set_links(u)
+        for _ in range(3):
+            lat.sweep(4, 1.7)
+            lat.reunitarize()
+            direct.append(lat.get_links())
+        r_direct = None
+    stream = torch.cuda.Stream()
+    with gf.Lattice(RAGGED, stream=stream) as lat:
+        lat.set_links(u)
+        for i in range(3):
+            lat.sweep(4, 1.7)  # first call captures, later calls replay
+            lat.reunitarize()
+            assert np.array_equal(lat.get_links(), direct[i]), i
+            lat.measure()
+    for prec in (gf.GF_FP64, gf.GF_MIXED):
+        res = []
+        for s in (None, stream):
+            with gf.Lattice(CFG8, prec, stream=s) as lat:
+                lat.set_links(gi.gen_links(CFG8, 0.6, 0))
+                res.append((lat.fix_until(omega=1.7, mode=0, theta_target=1e-12, max_sweeps=3000, check_every=10,
+                                          reunit_every=100, theta_switch=1e-8), lat.get_links()))
+        assert res[0][0] == res[1][0]
+        assert np.array_equal(res[0][1], res[1][1])
+    assert r_direct is None
