@@ -108,13 +108,15 @@ def fix_until_leg(gf, torch, stream, links, dims, args):
     out = {}
     kw = dict(omega=args.omega, mode=args.mode, theta_target=1e-12, max_sweeps=args.fix_max_sweeps,
               check_every=10, reunit_every=100, theta_switch=args.theta_switch)
+    P0 = None
     for name, prec in (("fp64", gf.GF_FP64), ("mixed", gf.GF_MIXED)):
         with gf.Lattice(dims, prec, stream=stream) as lat:
             lat.set_sweep_config(args.tps, args.block, args.nt, kernel=gf.GF_FP64)
             if prec == gf.GF_MIXED:
                 lat.set_sweep_config(args.tps32, args.block32, args.nt32, kernel=gf.GF_FP32)
             lat.set_links(links)
-            P0 = lat.plaquette()
+            if P0 is None:
+                P0 = lat.plaquette()  # of the float64 input (a mixed lattice starts on float32 links)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             r = lat.fix_until(**kw)
@@ -171,6 +173,8 @@ def main(argv=None):
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--chunk", type=int, default=10,
+                    help="sweeps per gf_sweep_or call in the timed region (>= 2: replayed hipGraph; 1: direct launches)")
     ap.add_argument("--no-fix", action="store_true", help="skip the run to theta < 1e-12")
     ap.add_argument("--fix-max-sweeps", type=int, default=20000)
     ap.add_argument("--theta-switch", type=float, default=1e-9)
@@ -214,10 +218,10 @@ def main(argv=None):
         log(f"fp64: warmup {args.warmup} sweeps")
         with torch.cuda.stream(stream):
             lat.sweep(args.warmup, args.omega, args.mode)
-            lat.sweep(10, args.omega, args.mode)  # captures the 10-sweep graph
-            total, wall, per_launch = time_run(lat, torch, stream, args.steps, args.omega, args.mode)
-            lat.sweep(10, args.omega, 1 - args.mode)
-            total_other, _, _ = time_run(lat, torch, stream, args.steps, args.omega, 1 - args.mode)
+            lat.sweep(args.chunk, args.omega, args.mode)  # captures the chunk's graph
+            total, wall, per_launch = time_run(lat, torch, stream, args.steps, args.omega, args.mode, args.chunk)
+            lat.sweep(args.chunk, args.omega, 1 - args.mode)
+            total_other, _, _ = time_run(lat, torch, stream, args.steps, args.omega, 1 - args.mode, args.chunk)
         th, F = lat.measure()
         P1 = lat.plaquette()
         log(f"fp64: {args.steps} sweeps in {total * 1e3:.2f} ms (mean half-sweep {per_launch * 1e6:.1f} us); "
@@ -235,8 +239,8 @@ def main(argv=None):
                 log(f"fp32 autotune: tps={args.tps32} block={args.block32} nontemporal={args.nt32}")
             with torch.cuda.stream(stream):
                 lat.sweep(args.warmup, args.omega, args.mode)
-                lat.sweep(10, args.omega, args.mode)
-                total, wall, per_launch = time_run(lat, torch, stream, args.steps, args.omega, args.mode)
+                lat.sweep(args.chunk, args.omega, args.mode)
+                total, wall, per_launch = time_run(lat, torch, stream, args.steps, args.omega, args.mode, args.chunk)
             log(f"fp32: {args.steps} sweeps in {total * 1e3:.2f} ms (mean half-sweep {per_launch * 1e6:.1f} us)")
             result["f32"] = dict(total=total, wall=wall, per_launch=per_launch)
 
@@ -259,6 +263,7 @@ def main(argv=None):
         "dtype": "f64",
         "data": "synthetic: exp(i eps H) links + Haar gauge rotation (seeded); no physical ensembles",
         "config": {
+            "chunk": args.chunk,
             "workload": f"SU(3) Landau OR sweep, {'x'.join(map(str, dims))} periodic, eps={args.eps}, "
                         f"seed {args.seed}, omega={args.omega}, {'exact' if args.mode == 0 else 'binomial'} "
                         f"power, FP64 12-real links",
