@@ -131,6 +131,77 @@ def fix_until_leg(gf, torch, stream, links, dims, args):
     return out
 
 
+def pool_tps(gf, gi, stream):
+    """Lanes per site for the pool's float32 / float64 kernels: the autotuner's pick on a
+    16^4 lattice (the pool kernels use 256-thread blocks)."""
+    best = {}
+    u = gi.gen_links((16, 16, 16, 16), 0.7, 7)
+    for prec in (gf.GF_FP32, gf.GF_FP64):
+        with gf.Lattice((16, 16, 16, 16), prec, stream=stream) as lat:
+            lat.set_links(u)
+            _, table = lat.autotune(prec, n_sweeps=5)
+            t = min((e for e in table if e[1] == 256 and e[2] == 0), key=lambda e: e[3])
+            best[prec] = t[0]
+    return best[gf.GF_FP32], best[gf.GF_FP64]
+
+
+def batched_leg(gf, gi, stream, args):
+    """64 lattices of uneven volume to theta < 1e-12: mixed-precision pool vs FP64 one at a time."""
+    from paper_1412_3655_amd import serving
+
+    jobs = serving.batched_jobs(64, 4)
+    t0 = time.perf_counter()
+    links = {j.job_id: gi.gen_links(j.dims, j.eps, j.seed) for j in jobs}
+    log(f"batched: generated 64 lattices ({sum(serving.volume(j.dims) for j in jobs)} sites) in "
+        f"{time.perf_counter() - t0:.1f} s")
+    fix = dict(omega=args.omega, mode=args.mode, theta_target=1e-12, max_sweeps=args.job_max_sweeps, check_every=10,
+               reunit_every=100, theta_switch=args.theta_switch)
+    t32, t64 = pool_tps(gf, gi, stream)
+    out = {"jobs": 64, "max_sweeps": args.job_max_sweeps, "pool_tps32": t32, "pool_tps64": t64}
+    for name, fn in (
+        ("pool_mixed", lambda: serving.run_pool(jobs, lambda j: links[j.job_id], gf.GF_MIXED, 10, 64, None, fix,
+                                                False, t32, t64)),
+        ("pool_fp64", lambda: serving.run_pool(jobs, lambda j: links[j.job_id], gf.GF_FP64, 10, 64, None, fix,
+                                               False, t32, t64)),
+        ("fifo_fp64", lambda: serving.run_fifo(jobs, lambda j: links[j.job_id], gf.GF_FP64, fix, False, args.tps,
+                                               args.block, args.nt)),
+    ):
+        st = fn()
+        out[name] = st.summary()
+        log(f"batched {name}: {st.converged}/64 converged in {st.seconds:.2f} s")
+    out["speedup_converged_per_s_pool_mixed_vs_fifo_fp64"] = (
+        (out["pool_mixed"]["converged_lattices_per_s"] or 0) / out["fifo_fp64"]["converged_lattices_per_s"]
+        if out["fifo_fp64"]["converged_lattices_per_s"] else None)
+    return out
+
+
+def serving_leg(gf, gi, stream, args):
+    """Poisson arrivals (20/s) of jobs of mixed volume: continuous batching vs FP64 FIFO."""
+    from paper_1412_3655_amd import serving
+
+    jobs = serving.serving_trace(args.serve_jobs, 20.0, 5)
+    t0 = time.perf_counter()
+    bank = {}
+    for j in jobs:
+        key = (j.dims, j.eps)
+        if key not in bank:
+            bank[key] = gi.gen_links(j.dims, j.eps, 3000 + len(bank))
+    log(f"serving: {len(jobs)} jobs, {len(bank)} distinct inputs generated in {time.perf_counter() - t0:.1f} s")
+    fix = dict(omega=args.omega, mode=args.mode, theta_target=1e-12, max_sweeps=args.job_max_sweeps, check_every=10,
+               reunit_every=100, theta_switch=args.theta_switch)
+    t32, t64 = pool_tps(gf, gi, stream)
+    links_of = lambda j: bank[(j.dims, j.eps)]
+    out = {"jobs": len(jobs), "rate_per_s": 20.0, "max_sweeps": args.job_max_sweeps,
+           "distinct_inputs": len(bank), "last_arrival_s": jobs[-1].arrival}
+    st = serving.run_pool(jobs, links_of, gf.GF_MIXED, 10, 256, None, fix, True, t32, t64)
+    out["pool_mixed"] = st.summary()
+    log(f"serving pool: {st.converged}/{len(jobs)} converged, {st.seconds:.1f} s")
+    st = serving.run_fifo(jobs, links_of, gf.GF_FP64, fix, True, args.tps, args.block, args.nt)
+    out["fifo_fp64"] = st.summary()
+    log(f"serving fifo: {st.converged}/{len(jobs)} converged, {st.seconds:.1f} s")
+    return out
+
+
 def cpu_baseline(links, dims, omega, mode, budget_s):
     import oracle
 
@@ -176,6 +247,10 @@ def main(argv=None):
     ap.add_argument("--chunk", type=int, default=10,
                     help="sweeps per gf_sweep_or call in the timed region (>= 2: replayed hipGraph; 1: direct launches)")
     ap.add_argument("--no-fix", action="store_true", help="skip the run to theta < 1e-12")
+    ap.add_argument("--batched", action="store_true", help="also run the 64-lattice batched workload")
+    ap.add_argument("--serve", action="store_true", help="also run the Poisson-arrival serving workload")
+    ap.add_argument("--serve-jobs", type=int, default=200)
+    ap.add_argument("--job-max-sweeps", type=int, default=10000)
     ap.add_argument("--fix-max-sweeps", type=int, default=20000)
     ap.add_argument("--theta-switch", type=float, default=1e-9)
     ap.add_argument("--no-tune", action="store_true", help="use --tps/--block instead of the autotuner")
@@ -310,6 +385,10 @@ def main(argv=None):
     if not args.no_fix:
         line["fix_until_theta_1e-12"] = fix_until_leg(gf, torch, stream, links, dims, args)
     line["device_copy_GBps"] = copy_bandwidth(gf)
+    if args.batched:
+        line["batched_64"] = batched_leg(gf, gi, stream, args)
+    if args.serve:
+        line["serving"] = serving_leg(gf, gi, stream, args)
     if not args.no_cpu:
         log("cpu baseline (FP64 oracle)")
         line["cpu_baseline"] = cpu_baseline(links, dims, args.omega, args.mode, args.cpu_budget)

@@ -1,0 +1,200 @@
+"""Request loop over the native job pool (gf_pool_*): continuous batching of
+gauge-fixing jobs.
+
+The pool (C ABI, include/gf.h) owns the device work: admission by HBM
+footprint, resident lattices, batched persistent sweeps captured in hipGraphs,
+retirement.  This module is the arrival-side driver: it releases jobs into a
+FIFO queue at their arrival times, admits from the head of the queue whenever
+the pool has room (slots and bytes), steps the pool, and retires finished
+jobs (freeing their lattices, which lets queued jobs in).  Latency of a job =
+end of the pool step in which it finished - its arrival, on the library's
+steady clock.
+
+`run_fifo` is the comparison path: one lattice at a time, in arrival order,
+with gf_anneal + gf_fix_until on a lone lattice of the given precision.
+"""
+
+from __future__ import annotations
+
+import collections
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import gf
+
+
+@dataclass
+class Job:
+    job_id: int
+    dims: tuple
+    eps: float
+    seed: int
+    arrival: float = 0.0  # seconds after the start of the run
+    anneal: int = 0       # heat-bath sweeps before the fix-until iteration (T 1.25 -> 0.01)
+
+
+@dataclass
+class RunStats:
+    jobs: int
+    converged: int
+    seconds: float
+    latencies: list = field(default_factory=list)        # every finished job
+    conv_latencies: list = field(default_factory=list)   # converged jobs only
+    sweeps: int = 0
+    site_updates: float = 0.0
+    failed: int = 0
+
+    def summary(self) -> dict:
+        def pct(v, q):
+            return float(np.percentile(v, q)) if v else None
+
+        return {
+            "jobs": self.jobs,
+            "converged": self.converged,
+            "failed": self.failed,
+            "seconds": self.seconds,
+            "converged_lattices_per_s": self.converged / self.seconds if self.seconds > 0 else None,
+            "lattices_per_s": self.jobs / self.seconds if self.seconds > 0 else None,
+            "p50_latency_s_converged": pct(self.conv_latencies, 50),
+            "p99_latency_s_converged": pct(self.conv_latencies, 99),
+            "p50_latency_s_all": pct(self.latencies, 50),
+            "p99_latency_s_all": pct(self.latencies, 99),
+            "site_updates_per_s": self.site_updates / self.seconds if self.seconds > 0 else None,
+        }
+
+
+def volume(dims) -> int:
+    return int(np.prod([int(d) for d in dims]))
+
+
+def batched_jobs(n=64, master_seed=4):
+    """The batched workload: n lattices with shapes uniform over {12^4, 16^4, 16^3x32, 24^3x48},
+    eps uniform in [0.4, 1.0] (drawn from a seeded stream), link seed 1000 + i."""
+    shapes = [(12, 12, 12, 12), (16, 16, 16, 16), (16, 16, 16, 32), (24, 24, 24, 48)]
+    rng = np.random.default_rng(master_seed)
+    out = []
+    for i in range(n):
+        d = shapes[int(rng.integers(0, len(shapes)))]
+        out.append(Job(i, d, float(rng.uniform(0.4, 1.0)), 1000 + i))
+    return out
+
+
+def serving_trace(n=1000, rate=20.0, master_seed=5, anneal_fraction=0.3, anneal_sweeps=500,
+                  eps_buckets=(0.4, 0.7, 1.0)):
+    """The serving workload: Poisson arrivals at `rate` per second; V log-uniform between 8^4 and
+    32^4 with L = even extent nearest V^(1/4); eps uniform in [0.4, 1.0], rounded to the nearest
+    of `eps_buckets` (so inputs can be generated once per (L, eps) and reused); a fraction of the
+    jobs with an annealing prelude; job seed 2000 + k."""
+    rng = np.random.default_rng(master_seed)
+    t = 0.0
+    out = []
+    for k in range(n):
+        t += float(rng.exponential(1.0 / rate))
+        logv = rng.uniform(math.log(8 ** 4), math.log(32 ** 4))
+        L = int(round(math.exp(logv / 4.0) / 2.0)) * 2
+        L = min(32, max(8, L))
+        eps = float(rng.uniform(0.4, 1.0))
+        eps = min(eps_buckets, key=lambda e: abs(e - eps))
+        anneal = anneal_sweeps if rng.random() < anneal_fraction else 0
+        out.append(Job(k, (L, L, L, L), eps, 2000 + k, t, anneal))
+    return out
+
+
+def run_pool(jobs, links_of, prec=gf.GF_MIXED, check_every=10, max_slots=256, hbm_budget=None,
+             fix=None, open_loop=True, tps32=0, tps64=0, log=None):
+    """Run `jobs` through a pool; links_of(job) -> canonical host links."""
+    fix = dict(fix or {})
+    import torch
+
+    free, total = torch.cuda.mem_get_info()
+    if hbm_budget is None:
+        hbm_budget = int(free * 0.8)
+    stats = RunStats(jobs=len(jobs), converged=0, seconds=0.0)
+    arrivals = collections.deque(sorted(jobs, key=lambda j: j.arrival))
+    queue = collections.deque()
+    by_id = {}
+    with gf.Pool(hbm_budget, max_slots, prec=prec, check_every=check_every, mode=fix.get("mode", 0),
+                 tps32=tps32, tps64=tps64) as pool:
+        t0 = gf.gf_clock()
+        done = 0
+        while done < len(jobs):
+            now = gf.gf_clock() - t0
+            while arrivals and (not open_loop or arrivals[0].arrival <= now):
+                queue.append(arrivals.popleft())
+            while queue:
+                j = queue[0]
+                ok = pool.admit(j.job_id, j.dims, links_of(j), anneal_sweeps=j.anneal, T_start=1.25, T_end=0.01,
+                                seed=j.seed, **fix)
+                if not ok:
+                    break
+                by_id[j.job_id] = j
+                queue.popleft()
+            active, finished, _ = pool.stats()
+            if active:
+                pool.step()
+            elif finished == 0 and arrivals and not queue:
+                time.sleep(max(0.0, min(0.05, arrivals[0].arrival - (gf.gf_clock() - t0))))
+            elif queue and active == 0 and finished == 0:
+                raise RuntimeError(f"job {queue[0].job_id} {queue[0].dims} does not fit the pool budget")
+            for d in pool.poll():
+                j = by_id.pop(d["job_id"])
+                pool.release(d["job_id"])
+                lat = d["t_done"] - t0 - j.arrival if open_loop else d["t_done"] - t0
+                r = d["result"]
+                stats.latencies.append(lat)
+                stats.sweeps += r.sweeps + j.anneal
+                stats.site_updates += (r.sweeps + j.anneal) * volume(j.dims)
+                if d["status"] != gf.GF_OK:
+                    stats.failed += 1
+                elif r.converged:
+                    stats.converged += 1
+                    stats.conv_latencies.append(lat)
+                done += 1
+                if log:
+                    log(f"  job {j.job_id} {j.dims} eps={j.eps:.2f} anneal={j.anneal}: sweeps {r.sweeps} "
+                        f"({r.sweeps_fp32}/{r.sweeps_fp64}) theta {r.theta:.2e} latency {lat:.2f} s")
+        stats.seconds = gf.gf_clock() - t0
+    return stats
+
+
+def run_fifo(jobs, links_of, prec=gf.GF_FP64, fix=None, open_loop=True, tps=0, block=0, nt=0, log=None):
+    """One lattice at a time in arrival order (gf_anneal + gf_fix_until on a lone lattice)."""
+    fix = dict(fix or {})
+    stats = RunStats(jobs=len(jobs), converged=0, seconds=0.0)
+    t0 = gf.gf_clock()
+    for j in sorted(jobs, key=lambda j: j.arrival):
+        if open_loop:
+            wait = j.arrival - (gf.gf_clock() - t0)
+            if wait > 0:
+                time.sleep(wait)
+        u = links_of(j)
+        with gf.Lattice(j.dims, prec) as lat:
+            if tps:
+                lat.set_sweep_config(tps, block, nt)
+            lat.set_links(u)
+            if j.anneal:
+                lat.anneal(j.anneal, 1.25, 0.01, j.seed)
+            try:
+                r = lat.fix_until(**fix)
+                ok = True
+            except gf.GFError:
+                ok = False
+        t_done = gf.gf_clock() - t0
+        lat_s = t_done - j.arrival if open_loop else t_done
+        stats.latencies.append(lat_s)
+        if not ok:
+            stats.failed += 1
+            continue
+        stats.sweeps += r.sweeps + j.anneal
+        stats.site_updates += (r.sweeps + j.anneal) * volume(j.dims)
+        if r.converged:
+            stats.converged += 1
+            stats.conv_latencies.append(lat_s)
+        if log:
+            log(f"  fifo job {j.job_id} {j.dims} eps={j.eps:.2f}: sweeps {r.sweeps} theta {r.theta:.2e} "
+                f"latency {lat_s:.2f} s")
+    stats.seconds = gf.gf_clock() - t0
+    return stats
