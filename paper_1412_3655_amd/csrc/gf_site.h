@@ -270,6 +270,15 @@ __device__ __forceinline__ void site_update(const LinkField<R>& f, const Geom& g
     }
 #pragma unroll
     for (int k = 0; k < NL; ++k) load_rows01<NT>(f, bwd[k] ? 1 - parity : parity, mu_of[k], at[k], U[k]);
+    if constexpr (MODE == HEATBATH) {
+        // The heat bath mixes all three rows of every link at every update.  Row 2
+        // is rebuilt from the two stored rows, so a departure d from unitarity of
+        // those rows becomes ~2d after the update and would grow geometrically over
+        // many sweeps; re-orthonormalising the two rows on load keeps every update
+        // inside SU(3) to rounding.
+#pragma unroll
+        for (int k = 0; k < NL; ++k) gram_schmidt_rows01(U[k]);
+    }
 #pragma unroll
     for (int k = 0; k < NL; ++k) rebuild_row2(U[k]);
 

@@ -134,3 +134,30 @@ def test_anneal_argument_checks():
             with pytest.raises(gf.GFError) as e:
                 lat.anneal(*args)
             assert e.value.status == gf.GF_E_ARG
+
+
+@pytest.mark.parametrize("prec", [gf.GF_FP64, gf.GF_FP32, gf.GF_MIXED])
+def test_long_anneal_stays_in_su3(prec):
+    """Regression: 500 heat-bath sweeps (T 1.25 -> 0.01) keep the links in SU(3) and the
+    plaquette unchanged (two-row storage must not amplify non-unitarity)."""
+    say(f"long anneal prec={prec}")
+    u = gi.gen_links(CFG8, 0.7, 2007)
+    P0 = oracle.plaquette(u, CFG8)
+    with gf.Lattice(CFG8, prec) as lat:
+        lat.set_links(u)
+        lat.anneal(500, 1.25, 0.01, 2007)
+        if prec == gf.GF_MIXED:
+            lat.promote_fp64()
+        th, F = lat.measure()
+        P = lat.plaquette()
+        links = lat.get_links()
+    du, dd = oracle.unitarity(links)
+    tol_u = 1e-12 if prec != gf.GF_FP32 else 1e-5
+    say(f"  theta {th:.3e} F {F:.6f} |dP| {abs(P - P0):.2e} unitarity {du:.1e} det {dd:.1e}")
+    assert np.isfinite(th) and 0.0 < F <= 1.0
+    assert du < tol_u and dd < tol_u
+    assert abs(P - P0) < (1e-12 if prec != gf.GF_FP32 else 1e-5)
+    ref = u.copy()
+    oracle.anneal(ref, CFG8, 500, 1.25, 0.01, 2007)
+    _, F_o = oracle.measure(ref, CFG8)
+    assert abs(F - F_o) < 0.02  # same distribution; trajectories decorrelate over 500 sweeps

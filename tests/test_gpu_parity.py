@@ -241,7 +241,8 @@ def test_errors_on_device():
 
 
 def test_full_size_32x4_one_sweep():
-    """32^4, eps = 0.8, seed 0 (the bandwidth workload), FP64, launch config of the benchmark:
+    """32^4, eps = 0.8, seed 0 (the bandwidth workload), FP64, tuned launch config of the benchmark
+    (2 lanes per site, 128-thread blocks, non-temporal):
     theta/F of the input, then every link after one sweep against the oracle."""
     dims = (32, 32, 32, 32)
     say("full size 32^4: generating")
@@ -257,7 +258,7 @@ def test_full_size_32x4_one_sweep():
         lat.sweep(1, 1.7, 0)
         return m0, lat.measure()
 
-    got, ((th, F), (th1, F1)) = gpu_run(dims, u, action=act)
+    got, ((th, F), (th1, F1)) = gpu_run(dims, u, tps=2, block=128, nt=1, action=act)
     assert abs(th - th_o) <= 1e-12 * th_o
     assert abs(F - F_o) <= 1e-14
     d = maxdiff(got, ref)
@@ -301,3 +302,20 @@ def test_graph_replays_match_direct_launches():
         assert res[0][0] == res[1][0]
         assert np.array_equal(res[0][1], res[1][1])
     assert r_direct is None
+
+
+@pytest.mark.parametrize("prec", [gf.GF_FP64, gf.GF_FP32])
+def test_long_or_without_reunitarisation_stays_in_su3(prec):
+    """2000 overrelaxation sweeps with no reunitarisation on a rough input: the two-row storage
+    does not amplify non-unitarity under overrelaxation (the subgroup elements approach 1)."""
+    say(f"long OR without reunitarisation prec={prec}")
+    u = gi.gen_links(CFG8, 1.0, 31)
+    with gf.Lattice(CFG8, prec) as lat:
+        lat.set_links(u)
+        for _ in range(20):
+            lat.sweep(100, 1.7)
+        links = lat.get_links()
+    du, dd = oracle.unitarity(links)
+    say(f"  unitarity {du:.1e} det {dd:.1e}")
+    tol = 1e-12 if prec == gf.GF_FP64 else 1e-4
+    assert du < tol and dd < tol
