@@ -152,7 +152,11 @@ gf_status gf_get_links_device(gf_lattice lat, double* dev);
  * SU(2)-span projection of each 2x2 block raised to the power omega, and
  * applies the accumulated g(x) to the 8 links at x (Sec. 2).
  * omega in [1, 2).  On a GF_MIXED lattice the sweep runs in the current
- * phase's precision.  Async. */
+ * phase's precision.  Only two rows of each link are stored, so rounding
+ * drift from SU(3) is not removed by the sweep itself: call gf_reunitarize
+ * every ~100 sweeps (gf_fix_until does; measured drift without it on rough
+ * inputs: <1e-12 after 2000 float64 sweeps, 2e-4 after 2000 float32 sweeps).
+ * Async. */
 gf_status gf_sweep_or(gf_lattice lat, int32_t n_sweeps, double omega, gf_or_mode mode);
 
 /* One half-sweep over the sites of one colour (0 = black, 1 = white).  Async. */

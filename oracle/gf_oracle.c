@@ -72,6 +72,10 @@ typedef double complex cx;
 
 enum { OR_EXACT = 0, OR_BINOMIAL1 = 1 };
 
+/* Lattices smaller than this are processed by one thread (thread start-up
+ * would dominate); the results do not depend on the thread count. */
+#define OMP_MIN_SITES 32768
+
 /* ------------------------------------------------------------------ */
 /* lattice geometry                                                    */
 /* ------------------------------------------------------------------ */
@@ -326,7 +330,7 @@ double oracle_site_update(double* U, const int32_t* dims, int64_t site, double o
 void oracle_half_sweep(double* U, const int32_t* dims, int colour, double omega, int mode)
 {
     geom g = mkgeom(dims);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (g.V >= OMP_MIN_SITES)
     for (long s = 0; s < g.V; ++s)
         if (colour_of(&g, s) == colour) or_site_update(U, &g, s, omega, mode);
 }
@@ -381,7 +385,7 @@ static double theta_site(const double* U, const geom* g, long s)
 void oracle_theta_density(const double* U, const int32_t* dims, double* out)
 {
     geom g = mkgeom(dims);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (g.V >= OMP_MIN_SITES)
     for (long s = 0; s < g.V; ++s) out[s] = theta_site(U, &g, s);
 }
 
@@ -394,7 +398,7 @@ void oracle_measure(const double* U, const int32_t* dims, double* theta, double*
     geom g = mkgeom(dims);
     double* th = (double*)malloc(sizeof(double) * (size_t)g.V);
     double* fr = (double*)malloc(sizeof(double) * (size_t)g.V);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (g.V >= OMP_MIN_SITES)
     for (long s = 0; s < g.V; ++s) {
         th[s] = theta_site(U, &g, s);
         double f = 0.0;
@@ -417,7 +421,7 @@ double oracle_plaquette(const double* U, const int32_t* dims)
 {
     geom g = mkgeom(dims);
     double* ps = (double*)malloc(sizeof(double) * (size_t)g.V);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (g.V >= OMP_MIN_SITES)
     for (long s = 0; s < g.V; ++s) {
         double acc = 0.0;
         for (int mu = 0; mu < 4; ++mu)
@@ -470,7 +474,7 @@ void oracle_unitarity(const double* U, int64_t nlinks, double* max_unit, double*
 
 void oracle_reunitarize(double* U, int64_t nlinks)
 {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (nlinks >= 4 * OMP_MIN_SITES)
     for (int64_t l = 0; l < nlinks; ++l) {
         cx* u = (cx*)(U + (size_t)l * 18);
         cx* r0 = u;
@@ -497,7 +501,7 @@ void oracle_reunitarize(double* U, int64_t nlinks)
 void oracle_gauge_transform(double* U, const int32_t* dims, const double* G)
 {
     geom g = mkgeom(dims);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (g.V >= OMP_MIN_SITES)
     for (long s = 0; s < g.V; ++s) {
         const cx* gx = (const cx*)(G + (size_t)s * 18);
         for (int mu = 0; mu < 4; ++mu) {
@@ -699,7 +703,7 @@ int64_t oracle_anneal(double* U, const int32_t* dims, int32_t nsweeps, double T0
         double T = anneal_temperature(sw, nsweeps, T0, T1);
         for (int c = 0; c < 2; ++c) {
             int capped = 0;
-#pragma omp parallel for schedule(static) reduction(+ : capped)
+#pragma omp parallel for schedule(static) reduction(+ : capped) if (g.V >= OMP_MIN_SITES)
             for (long s = 0; s < g.V; ++s)
                 if (colour_of(&g, s) == c) hb_site_update(U, &g, s, T, key, (uint32_t)(sweep_offset + sw), &capped);
             capped_total += capped;

@@ -270,12 +270,14 @@ __device__ __forceinline__ void site_update(const LinkField<R>& f, const Geom& g
     }
 #pragma unroll
     for (int k = 0; k < NL; ++k) load_rows01<NT>(f, bwd[k] ? 1 - parity : parity, mu_of[k], at[k], U[k]);
+    // Row 2 is rebuilt from the two stored rows, so a departure d from unitarity
+    // of those rows becomes up to ~2d after an update that mixes the rows.  Every
+    // heat-bath update mixes them strongly (d would grow ~1.35x per sweep), so the
+    // heat bath re-orthonormalises the two rows on load.  Overrelaxation mixes
+    // them little (its subgroup elements approach 1; d grows ~1.004x per sweep on
+    // rough inputs) and relies on the periodic reunitarisation of the fix-until
+    // loop, which keeps its register footprint (and occupancy) unchanged.
     if constexpr (MODE == HEATBATH) {
-        // The heat bath mixes all three rows of every link at every update.  Row 2
-        // is rebuilt from the two stored rows, so a departure d from unitarity of
-        // those rows becomes ~2d after the update and would grow geometrically over
-        // many sweeps; re-orthonormalising the two rows on load keeps every update
-        // inside SU(3) to rounding.
 #pragma unroll
         for (int k = 0; k < NL; ++k) gram_schmidt_rows01(U[k]);
     }
@@ -316,6 +318,7 @@ __device__ __forceinline__ void site_update(const LinkField<R>& f, const Geom& g
     if constexpr (TRACKG) {
         M3<R> gx;
         load_g(gacc, parity, h, gx);
+        gram_schmidt_rows01(gx);  // g is only ever multiplied: keep it in SU(3) (see above)
         rebuild_row2(gx);
         left_mul_rows01(G, gx);
 #pragma unroll
