@@ -133,14 +133,16 @@ def fix_until_leg(gf, torch, stream, links, dims, args):
 
 def pool_tps(gf, gi, stream):
     """Lanes per site for the pool's float32 / float64 kernels: the autotuner's pick on a
-    16^4 lattice (the pool kernels use 256-thread blocks)."""
+    16^4 lattice among the shapes the pool uses (128-thread blocks; non-temporal accesses
+    for float64, plain for float32)."""
     best = {}
     u = gi.gen_links((16, 16, 16, 16), 0.7, 7)
     for prec in (gf.GF_FP32, gf.GF_FP64):
         with gf.Lattice((16, 16, 16, 16), prec, stream=stream) as lat:
             lat.set_links(u)
             _, table = lat.autotune(prec, n_sweeps=5)
-            t = min((e for e in table if e[1] == 256 and e[2] == 0), key=lambda e: e[3])
+            nt = 1 if prec == gf.GF_FP64 else 0
+            t = min((e for e in table if e[1] == 128 and e[2] == nt), key=lambda e: e[3])
             best[prec] = t[0]
     return best[gf.GF_FP32], best[gf.GF_FP64]
 

@@ -31,7 +31,8 @@
 namespace gf {
 namespace pool {
 
-constexpr int PBLOCK = 256;  // threads per block of every pool kernel
+constexpr int PBLOCK = 256;  // threads per block of the reunitarisation / measurement kernels
+constexpr int SBLOCK = 128;  // threads per block of the sweep kernels (the tuned solo shape on MI355X)
 
 struct SlotDev {
     LinkField<double> f64;
@@ -88,11 +89,15 @@ __device__ __forceinline__ double schedule_T(const SlotDev& sd, uint32_t s)
     return sd.n_anneal > 1 ? sd.T0 + (sd.T1 - sd.T0) * (double)s / (double)(sd.n_anneal - 1) : sd.T0;
 }
 
+// float64 links use non-temporal accesses, float32 ones plain accesses (the
+// autotuner's choice for either on MI355X: a float32 lattice can stay in the
+// Infinity Cache, a float64 one streams).
 template <typename R, int TPS, int MODE, bool TRACKG>
-__global__ void __launch_bounds__(PBLOCK) k_pool_sweep(const SlotDev* slots, const Entry* list, const uint32_t* count,
+__global__ void __launch_bounds__(SBLOCK) k_pool_sweep(const SlotDev* slots, const Entry* list, const uint32_t* count,
                                                        int parity, uint32_t k)
 {
-    constexpr uint32_t SPB = PBLOCK / TPS;
+    constexpr uint32_t SPB = SBLOCK / TPS;
+    constexpr bool NT = sizeof(R) == 8;
     const uint32_t n = *count;
     const uint32_t total = list[n].first;
     for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
@@ -108,7 +113,7 @@ __global__ void __launch_bounds__(PBLOCK) k_pool_sweep(const SlotDev* slots, con
             } else {
                 rule = Rule<R>{(R)sd.omega, R(1), 0u, 0u, 0u};
             }
-            site_update<R, TPS, MODE, TRACKG>(field_of<R>(sd), sd.g, parity, h, r, rule, sd.gacc);
+            site_update<R, TPS, MODE, TRACKG, NT>(field_of<R>(sd), sd.g, parity, h, r, rule, sd.gacc);
         }
     }
 }
@@ -270,7 +275,7 @@ uint32_t tiles_of(const Geom& g, int kind, int tps)
         case K_OR32:
         case K_OR64:
         case K_HB64: {
-            const uint32_t spb = PBLOCK / (uint32_t)tps;
+            const uint32_t spb = SBLOCK / (uint32_t)tps;
             return (g.vh + spb - 1) / spb;
         }
         case K_R32:
@@ -284,7 +289,7 @@ uint32_t tiles_of(const Geom& g, int kind, int tps)
 template <typename R, int MODE, bool TRACKG>
 hipError_t launch_sweep_kind(gf_pool P, int tps, const Entry* list, const uint32_t* count, int parity, uint32_t k)
 {
-    const dim3 grid(P->grid_sweep[tps == 1 ? 0 : tps == 2 ? 1 : tps == 8 ? 3 : 2]), block(PBLOCK);
+    const dim3 grid(P->grid_sweep[tps == 1 ? 0 : tps == 2 ? 1 : tps == 8 ? 3 : 2]), block(SBLOCK);
     switch (tps) {
         case 1:
             hipLaunchKernelGGL((k_pool_sweep<R, 1, MODE, TRACKG>), grid, block, 0, P->stream, P->slots_dev, list, count,
@@ -533,7 +538,7 @@ gf_status gf_pool_create(const gf_pool_config* cfg, void* hip_stream, gf_pool* o
         return fail(GF_E_HIP, "pool allocation failed: %s", hipGetErrorString(e));
     }
     // persistent grids: a few resident blocks per compute unit
-    for (int i = 0; i < 4; ++i) P->grid_sweep[i] = 2 * ncu;
+    for (int i = 0; i < 4; ++i) P->grid_sweep[i] = 4 * ncu;
     P->grid_other = 4 * ncu;
     std::memset(P->slots_pin, 0, sizeof(SlotDev) * c.max_slots);
     *out = P;
