@@ -156,7 +156,10 @@ gf_status gf_get_links_device(gf_lattice lat, double* dev);
  * drift from SU(3) is not removed by the sweep itself: call gf_reunitarize
  * every ~100 sweeps (gf_fix_until does; measured drift without it on rough
  * inputs: <1e-12 after 2000 float64 sweeps, 2e-4 after 2000 float32 sweeps).
- * Async. */
+ * On a non-default stream, a call of n_sweeps >= 2 on a lattice of fewer
+ * than 2^16 sites per colour is captured once as a hipGraph and replayed by
+ * later calls with the same arguments and configuration; larger lattices
+ * launch their kernels directly.  Async. */
 gf_status gf_sweep_or(gf_lattice lat, int32_t n_sweeps, double omega, gf_or_mode mode);
 
 /* One half-sweep over the sites of one colour (0 = black, 1 = white).  Async. */
@@ -182,9 +185,11 @@ gf_status gf_measure_theta_F(gf_lattice lat, double* theta, double* F);
  * count is a multiple of reunit_every) and measure again (Sec. 2: iterate
  * until the gauge condition holds to a given precision).  GF_MIXED: float32
  * sweeps (with the transformation g(x) tracked) until theta < theta_switch
- * or until theta has reached no new minimum for 16 consecutive checks (the
- * float32 floor), then the float64 links are rebuilt as g(x) U0_mu(x) g(x+mu^)^dag from the
- * original links and the loop continues in float64.  Non-convergence is a
+ * or until theta has reached no new minimum for 16 consecutive checks with a
+ * best value below 1e-10 (the float32 rounding floor of theta is ~1e-12;
+ * slower progress above it is not a precision limit), then the float64 links
+ * are rebuilt as g(x) U0_mu(x) g(x+mu^)^dag from the original links and the
+ * loop continues in float64.  Non-convergence is a
  * result (converged = 0), not an error.  Syncs. */
 gf_status gf_fix_until(gf_lattice lat, const gf_fix_params* params, gf_fix_result* result);
 

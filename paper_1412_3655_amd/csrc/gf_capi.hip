@@ -112,7 +112,7 @@ void clear_graphs(gf_lattice L)
 // launch gaps between the 2n half-sweeps.
 gf_status do_sweeps(gf_lattice L, int32_t n, double omega, int mode)
 {
-    if (n < 2 || L->stream == nullptr) return launch_sweeps(L, n, omega, mode);
+    if (n < 2 || L->stream == nullptr || L->geom.vh >= kGraphMaxHalfSites) return launch_sweeps(L, n, omega, mode);
     const bool fp32 = is_fp32(L);
     const SweepConfig& c = fp32 ? L->cfg32 : L->cfg64;
     const int kind = fp32 ? (g_tracking(L).base ? 2 : 1) : 0;
@@ -462,7 +462,7 @@ gf_status gf_fix_until(gf_lattice L, const gf_fix_params* p, gf_fix_result* res)
     double best = theta;
     int stall = 0;
     while (theta >= p->theta_target && sweeps < p->max_sweeps) {
-        if (L->prec == GF_MIXED && L->phase == 0 && (theta < p->theta_switch || stall >= kStallChecks)) {
+        if (L->prec == GF_MIXED && L->phase == 0 && leave_fp32(theta, p->theta_switch, best, stall)) {
             GF_TRY(do_promote(L));
             GF_TRY(do_measure(L, &theta, &F));
             continue;

@@ -70,10 +70,27 @@ gf_status upload_canonical(gf_lattice L, const double* dev_canon);
 gf_status download_canonical(gf_lattice L, double* dev_canon);
 void release(gf_lattice L);
 
-// Float32 phase of GF_MIXED: it is left once theta < theta_switch or when theta
-// has reached no new minimum for kStallChecks consecutive checks (float32
-// noise floor); update_stall runs after every check that followed sweeps.
+// Float32 phase of GF_MIXED: it is left once theta < theta_switch, or once
+// theta has reached no new minimum for kStallChecks consecutive checks with
+// its best value below kStallTheta (update_stall runs after every check that
+// followed sweeps).  Float32 rounding puts a floor of about 1e-12 under theta
+// (a few float32 units of |K| in each component of Delta); a stall well above
+// it is the iteration's own slow convergence, which float32 sweeps pursue as
+// well as float64 ones at half the traffic, so it does not end the phase.
 constexpr int kStallChecks = 16;
+constexpr double kStallTheta = 1e-10;
+
+inline bool leave_fp32(double theta, double theta_switch, double best, int stall)
+{
+    return theta < theta_switch || (stall >= kStallChecks && best < kStallTheta);
+}
+
+// Multi-sweep calls on a non-default stream are captured once as a hipGraph
+// and replayed while the lattice has fewer than this many sites per colour;
+// larger lattices launch directly: their kernels hide the launch cost, and on
+// MI355X replayed kernels of a 32^4 lattice took 2-6 % longer than the same
+// kernels launched directly.
+constexpr uint32_t kGraphMaxHalfSites = 1u << 16;
 
 inline void update_stall(double theta, double* best, int* stall)
 {

@@ -7,12 +7,18 @@
 // for sweep k of the step and each kernel kind (heat bath / OR in float32
 // with g tracking / OR in float64 / reunitarisation / measurement /
 // finalisation) the list of slots that take part, as (slot, first tile)
-// prefix entries.  The kernels are persistent: a grid sized to the resident
-// capacity strides over the tiles of every listed slot, so one launch per
-// kind covers every lattice of every shape.  Work lists and the slot table
-// live in device memory and are refreshed by one host-to-device copy per
-// step; the launches of a step are captured in a hipGraph once per work
-// structure (which (k, kind) lists are non-empty) and replayed.
+// prefix entries, so one launch per (sweep, kind) covers every lattice of
+// every shape.  Work lists and the slot table live in device memory and are
+// refreshed by one host-to-device copy per step; the launches of a step are
+// captured in a hipGraph once per work structure (which (k, kind) lists are
+// non-empty) and replayed.  A sweep launch has one block per tile of its
+// list: before each replay the grid of every captured sweep node is set to
+// its list's tile count (hipGraphExecKernelNodeSetParams).  The other kinds
+// (reunitarisation, measurement, finalisation) keep persistent grids that
+// stride over their tiles.  A persistent sweep was measured ~13 % slower on
+// MI355X: across the loop the compiler keeps the math library's polynomial
+// coefficients of the exact power in registers, which pushes the float64
+// sweep over the register file into accumulation-register spills.
 //
 // The per-site bodies are the same functions the single-lattice kernels use
 // (gf_site.h) and the block decomposition of the measurement is the same, so
@@ -92,34 +98,37 @@ __device__ __forceinline__ double schedule_T(const SlotDev& sd, uint32_t s)
 // float64 links use non-temporal accesses, float32 ones plain accesses (the
 // autotuner's choice for either on MI355X: a float32 lattice can stay in the
 // Infinity Cache, a float64 one streams).
+// Block t sweeps tile t of the list (the host launches one block per tile;
+// blocks past the tile total leave).
 template <typename R, int TPS, int MODE, bool TRACKG>
-__global__ void __launch_bounds__(SBLOCK) k_pool_sweep(const SlotDev* slots, const Entry* list, const uint32_t* count,
-                                                       int parity, uint32_t k)
+__global__ void __launch_bounds__(SBLOCK) k_pool_sweep(const SlotDev* __restrict__ slots,
+                                                       const Entry* __restrict__ list,
+                                                       const uint32_t* __restrict__ count, int parity, uint32_t k)
 {
     constexpr uint32_t SPB = SBLOCK / TPS;
     constexpr bool NT = sizeof(R) == 8;
     const uint32_t n = *count;
-    const uint32_t total = list[n].first;
-    for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
-        const uint32_t i = find_entry(list, n, t);
-        const SlotDev sd = slots[list[i].slot];
-        const uint32_t h = (t - list[i].first) * SPB + threadIdx.x / TPS;
-        const int r = (int)(threadIdx.x % TPS);
-        if (h < sd.g.vh) {  // whole TPS groups take the same branch
-            Rule<R> rule;
-            if constexpr (MODE == HEATBATH) {
-                const uint32_t s = sd.anneal_base + k;
-                rule = Rule<R>{R(1), (R)schedule_T(sd, s), sd.key0, sd.key1, s};
-            } else {
-                rule = Rule<R>{(R)sd.omega, R(1), 0u, 0u, 0u};
-            }
-            site_update<R, TPS, MODE, TRACKG, NT>(field_of<R>(sd), sd.g, parity, h, r, rule, sd.gacc);
-        }
+    const uint32_t t = blockIdx.x;
+    if (t >= list[n].first) return;
+    const uint32_t i = find_entry(list, n, t);
+    const SlotDev sd = slots[list[i].slot];
+    const uint32_t h = (t - list[i].first) * SPB + threadIdx.x / TPS;
+    const int r = (int)(threadIdx.x % TPS);
+    if (h >= sd.g.vh) return;  // whole TPS groups leave together
+    Rule<R> rule;
+    if constexpr (MODE == HEATBATH) {
+        const uint32_t s = sd.anneal_base + k;
+        rule = Rule<R>{R(1), (R)schedule_T(sd, s), sd.key0, sd.key1, s};
+    } else {
+        rule = Rule<R>{(R)sd.omega, R(1), 0u, 0u, 0u};
     }
+    site_update<R, TPS, MODE, TRACKG, NT>(field_of<R>(sd), sd.g, parity, h, r, rule, sd.gacc);
 }
 
 template <typename R, bool WITH_G>
-__global__ void __launch_bounds__(PBLOCK) k_pool_reunit(const SlotDev* slots, const Entry* list, const uint32_t* count)
+__global__ void __launch_bounds__(PBLOCK) k_pool_reunit(const SlotDev* __restrict__ slots,
+                                                        const Entry* __restrict__ list,
+                                                        const uint32_t* __restrict__ count)
 {
     const uint32_t n = *count;
     const uint32_t total = list[n].first;
@@ -150,7 +159,9 @@ __global__ void __launch_bounds__(PBLOCK) k_pool_reunit(const SlotDev* slots, co
 // Tile b of a slot = measurement block (parity = b / nb, block = b % nb) of the
 // single-lattice measurement, writing the same partial.
 template <typename R>
-__global__ void __launch_bounds__(PBLOCK) k_pool_measure(const SlotDev* slots, const Entry* list, const uint32_t* count)
+__global__ void __launch_bounds__(PBLOCK) k_pool_measure(const SlotDev* __restrict__ slots,
+                                                         const Entry* __restrict__ list,
+                                                         const uint32_t* __restrict__ count)
 {
     const uint32_t n = *count;
     const uint32_t total = list[n].first;
@@ -168,7 +179,9 @@ __global__ void __launch_bounds__(PBLOCK) k_pool_measure(const SlotDev* slots, c
     }
 }
 
-__global__ void __launch_bounds__(PBLOCK) k_pool_finalize(const SlotDev* slots, const Entry* list, const uint32_t* count)
+__global__ void __launch_bounds__(PBLOCK) k_pool_finalize(const SlotDev* __restrict__ slots,
+                                                          const Entry* __restrict__ list,
+                                                          const uint32_t* __restrict__ count)
 {
     const uint32_t n = *count;
     for (uint32_t t = blockIdx.x; t < n; t += gridDim.x) {
@@ -216,6 +229,28 @@ using namespace gf;
 using namespace gf::pool;
 using namespace gf::detail;
 
+// A captured step: the graph (kept for its node handles) and, for every sweep
+// launch, its node, its captured parameters and its (k, kind) segment.
+struct StepGraph {
+    struct SweepNode {
+        hipGraphNode_t node;
+        hipKernelNodeParams params;
+        size_t seg;
+    };
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<SweepNode> sweeps;
+};
+
+void destroy_step_graph(StepGraph& g)
+{
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g.exec = nullptr;
+    g.graph = nullptr;
+    g.sweeps.clear();
+}
+
 struct gf_pool_ {
     gf_pool_config cfg{};
     hipStream_t stream = nullptr;
@@ -235,10 +270,11 @@ struct gf_pool_ {
     uint32_t* counts_pin = nullptr;
     double* results_pin = nullptr;
     size_t list_stride = 0;  // entries per (k, kind) segment = max_slots + 1
-    std::map<std::string, hipGraphExec_t> graphs;
+    std::map<std::string, StepGraph> graphs;
     std::vector<gf_pool_done> finished;  // not yet polled
-    int grid_sweep[4] = {0, 0, 0, 0};    // persistent grid per kind family
-    int grid_other = 0;
+    std::vector<uint32_t> seg_tiles;     // tiles per (k, kind) list of the step being launched
+    std::vector<size_t> launch_log;      // (k, kind) segment of every launch while capturing
+    int grid_other = 0;                  // persistent grid of the reunitarisation / measurement kernels
 };
 
 namespace {
@@ -287,9 +323,10 @@ uint32_t tiles_of(const Geom& g, int kind, int tps)
 }
 
 template <typename R, int MODE, bool TRACKG>
-hipError_t launch_sweep_kind(gf_pool P, int tps, const Entry* list, const uint32_t* count, int parity, uint32_t k)
+hipError_t launch_sweep_kind(gf_pool P, int tps, uint32_t tiles, const Entry* list, const uint32_t* count, int parity,
+                             uint32_t k)
 {
-    const dim3 grid(P->grid_sweep[tps == 1 ? 0 : tps == 2 ? 1 : tps == 8 ? 3 : 2]), block(SBLOCK);
+    const dim3 grid(tiles), block(SBLOCK);
     switch (tps) {
         case 1:
             hipLaunchKernelGGL((k_pool_sweep<R, 1, MODE, TRACKG>), grid, block, 0, P->stream, P->slots_dev, list, count,
@@ -311,21 +348,30 @@ hipError_t launch_sweep_kind(gf_pool P, int tps, const Entry* list, const uint32
     return hipGetLastError();
 }
 
+bool is_sweep_kind(int kind)
+{
+    return kind == K_HB32 || kind == K_OR32 || kind == K_OR64 || kind == K_HB64;
+}
+
 hipError_t launch_kind(gf_pool P, int k, int kind, int parity)
 {
+    const size_t sgi = (size_t)k * NKIND + kind;
     const Entry* list = seg(P, P->lists_dev, k, kind);
-    const uint32_t* count = P->counts_dev + (size_t)k * NKIND + kind;
+    const uint32_t* count = P->counts_dev + sgi;
+    const uint32_t tiles = P->seg_tiles[sgi];
+    const uint32_t kk = (uint32_t)k;
     const int mode = P->cfg.mode;
     const int t32 = P->cfg.tps32, t64 = P->cfg.tps64;
+    P->launch_log.push_back(sgi);
     switch (kind) {
-        case K_HB32: return launch_sweep_kind<float, HEATBATH, true>(P, t32, list, count, parity, (uint32_t)k);
-        case K_HB64: return launch_sweep_kind<double, HEATBATH, false>(P, t64, list, count, parity, (uint32_t)k);
+        case K_HB32: return launch_sweep_kind<float, HEATBATH, true>(P, t32, tiles, list, count, parity, kk);
+        case K_HB64: return launch_sweep_kind<double, HEATBATH, false>(P, t64, tiles, list, count, parity, kk);
         case K_OR32:
-            return mode == GF_OR_EXACT ? launch_sweep_kind<float, 0, true>(P, t32, list, count, parity, (uint32_t)k)
-                                       : launch_sweep_kind<float, 1, true>(P, t32, list, count, parity, (uint32_t)k);
+            return mode == GF_OR_EXACT ? launch_sweep_kind<float, 0, true>(P, t32, tiles, list, count, parity, kk)
+                                       : launch_sweep_kind<float, 1, true>(P, t32, tiles, list, count, parity, kk);
         case K_OR64:
-            return mode == GF_OR_EXACT ? launch_sweep_kind<double, 0, false>(P, t64, list, count, parity, (uint32_t)k)
-                                       : launch_sweep_kind<double, 1, false>(P, t64, list, count, parity, (uint32_t)k);
+            return mode == GF_OR_EXACT ? launch_sweep_kind<double, 0, false>(P, t64, tiles, list, count, parity, kk)
+                                       : launch_sweep_kind<double, 1, false>(P, t64, tiles, list, count, parity, kk);
         case K_R32:
             hipLaunchKernelGGL((k_pool_reunit<float, true>), dim3(P->grid_other), dim3(PBLOCK), 0, P->stream,
                                P->slots_dev, list, count);
@@ -365,30 +411,79 @@ gf_status enqueue_step(gf_pool P, const std::string& sig)
     return GF_OK;
 }
 
+// Capture the step for `sig` (launches in the order enqueue_step issues them)
+// and record the node of every sweep launch: a stream capture is a chain, so
+// the nodes are walked from the root along their single dependents.
+gf_status capture_step(gf_pool P, const std::string& sig, StepGraph& out)
+{
+    P->launch_log.clear();
+    GF_HIP(hipStreamBeginCapture(P->stream, hipStreamCaptureModeRelaxed));
+    gf_status st = enqueue_step(P, sig);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(P->stream, &graph);
+    if (st != GF_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return fail(GF_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    out.graph = graph;
+    const size_t n = P->launch_log.size();
+    std::vector<hipGraphNode_t> chain;
+    size_t cnt = 0;
+    hipGraphNode_t node = nullptr;
+    e = hipGraphGetRootNodes(graph, nullptr, &cnt);
+    if (e == hipSuccess && cnt == 1) e = hipGraphGetRootNodes(graph, &node, &cnt);
+    while (e == hipSuccess && cnt == 1 && chain.size() <= n) {
+        chain.push_back(node);
+        cnt = 0;
+        e = hipGraphNodeGetDependentNodes(node, nullptr, &cnt);
+        if (e != hipSuccess || cnt != 1) break;
+        e = hipGraphNodeGetDependentNodes(node, &node, &cnt);
+    }
+    if (e != hipSuccess || chain.size() != n) {
+        destroy_step_graph(out);
+        return fail(GF_E_HIP, "captured step is not a chain of %zu launches (%zu nodes)", n, chain.size());
+    }
+    for (size_t i = 0; i < n; ++i) {
+        const size_t sgi = P->launch_log[i];
+        if (!is_sweep_kind((int)(sgi % NKIND))) continue;
+        StepGraph::SweepNode sn{chain[i], {}, sgi};
+        e = hipGraphKernelNodeGetParams(chain[i], &sn.params);
+        if (e != hipSuccess) {
+            destroy_step_graph(out);
+            return fail(GF_E_HIP, "hipGraphKernelNodeGetParams: %s", hipGetErrorString(e));
+        }
+        out.sweeps.push_back(sn);
+    }
+    e = hipGraphInstantiate(&out.exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        destroy_step_graph(out);
+        return fail(GF_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    return GF_OK;
+}
+
 gf_status run_graph(gf_pool P, const std::string& sig)
 {
     auto it = P->graphs.find(sig);
     if (it == P->graphs.end()) {
         if (P->graphs.size() >= 64) {
-            for (auto& kv : P->graphs) (void)hipGraphExecDestroy(kv.second);
+            for (auto& kv : P->graphs) destroy_step_graph(kv.second);
             P->graphs.clear();
         }
-        hipGraph_t graph = nullptr;
-        GF_HIP(hipStreamBeginCapture(P->stream, hipStreamCaptureModeRelaxed));
-        gf_status st = enqueue_step(P, sig);
-        hipError_t e = hipStreamEndCapture(P->stream, &graph);
-        if (st != GF_OK) {
-            if (graph) (void)hipGraphDestroy(graph);
-            return st;
+        StepGraph g;
+        GF_TRY(capture_step(P, sig, g));
+        it = P->graphs.emplace(sig, g).first;
+    } else {
+        // one block per tile of this step's lists
+        for (auto& sn : it->second.sweeps) {
+            const uint32_t tiles = P->seg_tiles[sn.seg];
+            if (sn.params.gridDim.x == tiles) continue;
+            sn.params.gridDim = dim3(tiles);
+            GF_HIP(hipGraphExecKernelNodeSetParams(it->second.exec, sn.node, &sn.params));
         }
-        if (e != hipSuccess) return fail(GF_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
-        hipGraphExec_t exec = nullptr;
-        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (e != hipSuccess) return fail(GF_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
-        it = P->graphs.emplace(sig, exec).first;
     }
-    GF_HIP(hipGraphLaunch(it->second, P->stream));
+    GF_HIP(hipGraphLaunch(it->second.exec, P->stream));
     return GF_OK;
 }
 
@@ -443,7 +538,7 @@ gf_status fix_head(gf_pool P, Job& j)
             finish(P, j, GF_OK);
             return GF_OK;
         }
-        if (L->prec == GF_MIXED && L->phase == 0 && (j.theta < j.p.theta_switch || j.stall >= kStallChecks)) {
+        if (L->prec == GF_MIXED && L->phase == 0 && leave_fp32(j.theta, j.p.theta_switch, j.best, j.stall)) {
             GF_TRY(do_promote(L));
             gf_status st = do_measure(L, &j.theta, &j.F);
             if (st != GF_OK) {
@@ -537,9 +632,9 @@ gf_status gf_pool_create(const gf_pool_config* cfg, void* hip_stream, gf_pool* o
         gf_pool_destroy(P);
         return fail(GF_E_HIP, "pool allocation failed: %s", hipGetErrorString(e));
     }
-    // persistent grids: a few resident blocks per compute unit
-    for (int i = 0; i < 4; ++i) P->grid_sweep[i] = 4 * ncu;
+    // persistent grid of the reunitarisation / measurement kernels: a few resident blocks per compute unit
     P->grid_other = 4 * ncu;
+    P->seg_tiles.assign(nseg, 0);
     std::memset(P->slots_pin, 0, sizeof(SlotDev) * c.max_slots);
     *out = P;
     return GF_OK;
@@ -550,7 +645,7 @@ gf_status gf_pool_destroy(gf_pool P)
     if (!P) return GF_OK;
     if (P->stream) (void)hipStreamSynchronize(P->stream);
     for (auto& j : P->jobs) release_job(P, j);
-    for (auto& kv : P->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto& kv : P->graphs) destroy_step_graph(kv.second);
     if (P->slots_dev) (void)hipFree(P->slots_dev);
     if (P->lists_dev) (void)hipFree(P->lists_dev);
     if (P->counts_dev) (void)hipFree(P->counts_dev);
@@ -693,6 +788,7 @@ gf_status gf_pool_step(gf_pool P)
         const int k = (int)(i / NKIND), kind = (int)(i % NKIND);
         seg(P, P->lists_pin, k, kind)[n_entries[i]] = Entry{0u, n_tiles[i]};  // sentinel
         P->counts_pin[i] = n_entries[i];
+        P->seg_tiles[i] = n_tiles[i];
         if (n_entries[i]) sig[i] = '1';
     }
     for (int s = 0; s < (int)P->jobs.size(); ++s) P->slots_pin[s] = P->slot_host[s];
