@@ -63,10 +63,11 @@ def committed_traffic():
 
 
 def time_run(lat, torch, stream, steps, omega, mode, chunk=10):
-    """Time `steps` sweeps issued as gf_sweep_or calls of `chunk` sweeps (each a replayed
-    hipGraph of 2*chunk half-sweep kernels on this stream), with a HIP event pair around
-    the whole region and around every call.  Returns (region seconds, wall seconds, mean
-    half-sweep kernel seconds = event time of a call / its 2*chunk launches)."""
+    """Time `steps` sweeps issued as gf_sweep_or calls of `chunk` sweeps on this stream (2*chunk
+    half-sweep kernels per call: launched directly on lattices of >= 2^16 sites per colour, a
+    replayed hipGraph below), with a HIP event pair around the whole region and around every
+    call.  Returns (region seconds, wall seconds, mean half-sweep kernel seconds = event time
+    of a call / its 2*chunk launches)."""
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     marks = []
@@ -117,6 +118,10 @@ def fix_until_leg(gf, torch, stream, links, dims, args):
             lat.set_links(links)
             if P0 is None:
                 P0 = lat.plaquette()  # of the float64 input (a mixed lattice starts on float32 links)
+            if prec == gf.GF_MIXED:
+                floor, sw = lat.tune_switch(1e-12)
+                out["fp32_theta_floor"] = floor
+                out["theta_switch"] = sw if args.theta_switch < 0 else args.theta_switch
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             r = lat.fix_until(**kw)
@@ -254,7 +259,8 @@ def main(argv=None):
     ap.add_argument("--serve-jobs", type=int, default=200)
     ap.add_argument("--job-max-sweeps", type=int, default=10000)
     ap.add_argument("--fix-max-sweeps", type=int, default=20000)
-    ap.add_argument("--theta-switch", type=float, default=1e-9)
+    ap.add_argument("--theta-switch", type=float, default=-1.0,
+                    help="float32 -> float64 switch of the mixed runs; < 0: chosen by gf_tune_switch")
     ap.add_argument("--no-tune", action="store_true", help="use --tps/--block instead of the autotuner")
     args = ap.parse_args(argv)
 

@@ -69,7 +69,8 @@ typedef struct {
     int32_t max_sweeps;   /* >= 0 */
     int32_t check_every;  /* >= 1: sweeps between measurements */
     int32_t reunit_every; /* reunitarise after every sweep whose count is a multiple of this; 0 = never */
-    double theta_switch;  /* GF_MIXED only: leave float32 once theta < theta_switch */
+    double theta_switch;  /* GF_MIXED only: leave float32 once theta < theta_switch;
+                             < 0: the switch point gf_tune_switch picks for the lattice */
 } gf_fix_params;
 
 typedef struct {
@@ -184,14 +185,25 @@ gf_status gf_measure_theta_F(gf_lattice lat, double* theta, double* F);
  * min(check_every, remaining) sweeps (reunitarising after every sweep whose
  * count is a multiple of reunit_every) and measure again (Sec. 2: iterate
  * until the gauge condition holds to a given precision).  GF_MIXED: float32
- * sweeps (with the transformation g(x) tracked) until theta < theta_switch
- * or until theta has reached no new minimum for 16 consecutive checks with a
- * best value below 1e-10 (the float32 rounding floor of theta is ~1e-12;
- * slower progress above it is not a precision limit), then the float64 links
- * are rebuilt as g(x) U0_mu(x) g(x+mu^)^dag from the original links and the
- * loop continues in float64.  Non-convergence is a
- * result (converged = 0), not an error.  Syncs. */
+ * sweeps (with the transformation g(x) tracked) until theta < theta_switch,
+ * until theta has reached no new minimum for 16 consecutive checks with a
+ * best value below 1e-10 (a stall well above the float32 rounding floor is
+ * the iteration's own slow convergence, not a precision limit), or until the
+ * loop would end; then the float64 links are rebuilt as
+ * g(x) U0_mu(x) g(x+mu^)^dag from the original links, theta is measured in
+ * float64 and the loop continues in float64, so the result (links, theta, F,
+ * converged) is always the float64 one.  Non-convergence is a result
+ * (converged = 0), not an error.  Syncs. */
 gf_status gf_fix_until(gf_lattice lat, const gf_fix_params* params, gf_fix_result* result);
+
+/* Switch point for the float32 -> float64 handover of GF_MIXED: *floor =
+ * (1/(3V)) sum_x tr[E E^dag] with E = Delta(x) computed in float32 from the
+ * float32-rounded float64 links minus Delta(x) in float64 (the float32
+ * rounding floor of theta for this configuration), *theta_switch =
+ * max(theta_target, 100 * floor).  Reads the float64 links (on GF_MIXED in
+ * the float32 phase: the original links U0).  GF_E_STATE on a GF_FP32
+ * lattice.  gf_fix_until calls it when theta_switch < 0.  Syncs. */
+gf_status gf_tune_switch(gf_lattice lat, double theta_target, double* floor, double* theta_switch);
 
 /* Reunitarise every link: Gram-Schmidt of rows 0 and 1 (row 2 is implicit).  Async. */
 gf_status gf_reunitarize(gf_lattice lat);

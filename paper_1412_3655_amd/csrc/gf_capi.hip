@@ -175,6 +175,29 @@ gf_status do_measure(gf_lattice L, double* theta, double* F)
     return GF_OK;
 }
 
+gf_status do_fp32_floor(gf_lattice L, double* floor)
+{
+    if (!L->f64) return fail(GF_E_STATE, "the float32 floor needs float64 links (GF_FP64 or GF_MIXED lattice)");
+    GF_HIP(gf::launch_fp32_floor(field64(L), L->geom, L->partial, L->dres, L->stream));
+    GF_HIP(hipMemcpyAsync(L->hres, L->dres, sizeof(double), hipMemcpyDeviceToHost, L->stream));
+    GF_HIP(hipStreamSynchronize(L->stream));
+    *floor = L->hres[0];
+    if (!std::isfinite(*floor)) return fail(GF_E_NUMERIC, "float32 floor = %g is not finite", *floor);
+    return GF_OK;
+}
+
+gf_status resolve_switch(gf_lattice L, double theta_target, double theta_switch, double* out)
+{
+    if (theta_switch >= 0.0 || L->prec != GF_MIXED) {
+        *out = theta_switch;
+        return GF_OK;
+    }
+    double floor = 0.0;
+    GF_TRY(do_fp32_floor(L, &floor));
+    *out = std::max(theta_target, kFloorMargin * floor);
+    return GF_OK;
+}
+
 gf_status upload_canonical(gf_lattice L, const double* dev_canon)
 {
     if (L->f32) GF_HIP(gf::launch_pack(dev_canon, field32(L), L->geom, L->stream));
@@ -446,6 +469,16 @@ gf_status gf_plaquette(gf_lattice L, double* P)
     return GF_OK;
 }
 
+gf_status gf_tune_switch(gf_lattice L, double theta_target, double* floor, double* theta_switch)
+{
+    GF_TRY(check_ready(L));
+    if (!floor || !theta_switch) return fail(GF_E_ARG, "null argument");
+    if (!(theta_target >= 0.0)) return fail(GF_E_ARG, "theta_target must be >= 0");
+    GF_TRY(do_fp32_floor(L, floor));
+    *theta_switch = std::max(theta_target, kFloorMargin * *floor);
+    return GF_OK;
+}
+
 gf_status gf_fix_until(gf_lattice L, const gf_fix_params* p, gf_fix_result* res)
 {
     GF_TRY(check_ready(L));
@@ -454,19 +487,25 @@ gf_status gf_fix_until(gf_lattice L, const gf_fix_params* p, gf_fix_result* res)
     if (p->max_sweeps < 0 || p->check_every < 1 || p->reunit_every < 0)
         return fail(GF_E_ARG, "need max_sweeps >= 0, check_every >= 1, reunit_every >= 0");
     if (!(p->theta_target >= 0.0)) return fail(GF_E_ARG, "theta_target must be >= 0");
-    if (L->prec == GF_MIXED && !(p->theta_switch >= 0.0)) return fail(GF_E_ARG, "theta_switch must be >= 0");
+    if (std::isnan(p->theta_switch)) return fail(GF_E_ARG, "theta_switch is NaN");
     std::memset(res, 0, sizeof *res);
+    double theta_switch = 0.0;
+    GF_TRY(resolve_switch(L, p->theta_target, p->theta_switch, &theta_switch));
     double theta = 0.0, F = 0.0;
     GF_TRY(do_measure(L, &theta, &F));
     int32_t sweeps = 0;
     double best = theta;
     int stall = 0;
-    while (theta >= p->theta_target && sweeps < p->max_sweeps) {
-        if (L->prec == GF_MIXED && L->phase == 0 && leave_fp32(theta, p->theta_switch, best, stall)) {
+    for (;;) {
+        const bool finished = !(theta >= p->theta_target && sweeps < p->max_sweeps);
+        // GF_MIXED ends in float64: the float32 phase is left at the switch
+        // point, at a stall below kStallTheta, and when the loop would end.
+        if (L->prec == GF_MIXED && L->phase == 0 && (finished || leave_fp32(theta, theta_switch, best, stall))) {
             GF_TRY(do_promote(L));
             GF_TRY(do_measure(L, &theta, &F));
             continue;
         }
+        if (finished) break;
         const bool fp32 = is_fp32(L);
         const int32_t n = std::min(p->check_every, p->max_sweeps - sweeps);
         // n sweeps, reunitarising after every sweep whose count is a multiple of reunit_every

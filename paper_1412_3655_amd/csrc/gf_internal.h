@@ -66,6 +66,8 @@ gf_status do_sweeps(gf_lattice L, int32_t n, double omega, int mode);
 gf_status do_reunitarize(gf_lattice L);
 gf_status do_promote(gf_lattice L);
 gf_status do_measure(gf_lattice L, double* theta, double* F);
+gf_status do_fp32_floor(gf_lattice L, double* floor);
+gf_status resolve_switch(gf_lattice L, double theta_target, double theta_switch, double* out);
 gf_status upload_canonical(gf_lattice L, const double* dev_canon);
 gf_status download_canonical(gf_lattice L, double* dev_canon);
 void release(gf_lattice L);
@@ -79,6 +81,14 @@ void release(gf_lattice L);
 // well as float64 ones at half the traffic, so it does not end the phase.
 constexpr int kStallChecks = 16;
 constexpr double kStallTheta = 1e-10;
+
+// Chosen switch point (theta_switch < 0 in gf_fix_params):
+// max(theta_target, kFloorMargin * floor), floor = the lattice's float32
+// rounding floor of theta (launch_fp32_floor).  Float32 sweeps converge at the
+// float64 rate while theta is well above that floor (on MI355X: identical
+// sweep counts to theta < 1e-12 for every switch point from 1e-8 down to the
+// target), so the float32 phase is run as far as the floor allows.
+constexpr double kFloorMargin = 100.0;
 
 inline bool leave_fp32(double theta, double theta_switch, double best, int stall)
 {

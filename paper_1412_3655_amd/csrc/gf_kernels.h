@@ -39,6 +39,11 @@ uint32_t measure_blocks(const Geom& g);
 hipError_t launch_measure(const LinkField<double>& f, const Geom& g, double* partial, double* out, hipStream_t st);
 hipError_t launch_measure(const LinkField<float>& f, const Geom& g, double* partial, double* out, hipStream_t st);
 
+// out[0] = (1/(3V)) sum_x tr[E E^dag], E = Delta computed in float32 from the
+// float32-rounded links minus Delta in float64: the float32 rounding floor of
+// theta for this configuration.  partial as for launch_measure.
+hipError_t launch_fp32_floor(const LinkField<double>& f, const Geom& g, double* partial, double* out, hipStream_t st);
+
 // Average plaquette into out[0]; partial as for launch_measure.
 hipError_t launch_plaquette(const LinkField<double>& f, const Geom& g, double* partial, double* out, hipStream_t st);
 hipError_t launch_plaquette(const LinkField<float>& f, const Geom& g, double* partial, double* out, hipStream_t st);

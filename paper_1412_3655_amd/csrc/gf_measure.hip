@@ -71,6 +71,96 @@ __global__ void __launch_bounds__(RBLOCK) k_plaquette(LinkField<R> f, Geom g, do
     block_sum2<RBLOCK>(acc, 0.0, partial + 2 * (size_t)(blockIdx.y * gridDim.x + blockIdx.x));
 }
 
+// The nine independent real components of Delta = [(K - K^dag)/(2i)]_traceless:
+// d[0..2] the traceless diagonal (Im K_ii minus the mean), d[3..8] the real and
+// imaginary parts of the off-diagonal entries (i, j), i < j, which count twice
+// in tr[Delta Delta^dag].
+template <typename T>
+__device__ __forceinline__ void delta_components(const M3<T>& K, T d[9])
+{
+    const T tr3 = (K.im[0][0] + K.im[1][1] + K.im[2][2]) / T(3);
+    d[0] = K.im[0][0] - tr3;
+    d[1] = K.im[1][1] - tr3;
+    d[2] = K.im[2][2] - tr3;
+    int c = 3;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i + 1; j < 3; ++j) {
+            d[c++] = T(0.5) * (K.im[i][j] + K.im[j][i]);
+            d[c++] = T(0.5) * (K.re[i][j] - K.re[j][i]);
+        }
+}
+
+// K(x) of the site from the float64 links, in float64 (K64) and, with every
+// stored real rounded to float32 and row 2 rebuilt in float32, in float32
+// (K32): what a float32 sweep sees of the same configuration.
+__device__ __forceinline__ void site_K_both(const LinkField<double>& f, const Geom& g, int parity, uint32_t h,
+                                            M3<double>& K64, M3<float>& K32)
+{
+    const Site s = decode_site(g, parity, h);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            K64.re[i][j] = 0.0;
+            K64.im[i][j] = 0.0;
+            K32.re[i][j] = 0.f;
+            K32.im[i][j] = 0.f;
+        }
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            M3<double> u;
+            M3<float> v;
+            const int p = b ? 1 - parity : parity;
+            load_rows01(f, p, mu, b ? back_h(g, h, s, mu) : h, u);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    v.re[i][j] = (float)u.re[i][j];
+                    v.im[i][j] = (float)u.im[i][j];
+                }
+            rebuild_row2(u);
+            rebuild_row2(v);
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    K64.re[i][j] += b ? u.re[j][i] : u.re[i][j];
+                    K64.im[i][j] += b ? -u.im[j][i] : u.im[i][j];
+                    K32.re[i][j] += b ? v.re[j][i] : v.re[i][j];
+                    K32.im[i][j] += b ? -v.im[j][i] : v.im[i][j];
+                }
+        }
+}
+
+// Per site: tr[E E^dag] with E = Delta(K32) - Delta(K64), the float32 rounding
+// error of the local gauge condition.
+__global__ void __launch_bounds__(RBLOCK) k_fp32_floor(LinkField<double> f, Geom g, double* partial)
+{
+    const int parity = blockIdx.y;
+    const uint32_t h = blockIdx.x * RBLOCK + threadIdx.x;
+    double acc = 0.0;
+    if (h < g.vh) {
+        M3<double> K64;
+        M3<float> K32;
+        site_K_both(f, g, parity, h, K64, K32);
+        double d64[9];
+        float d32[9];
+        delta_components(K64, d64);
+        delta_components(K32, d32);
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+            const double e = (double)d32[c] - d64[c];
+            acc += (c < 3 ? 1.0 : 2.0) * e * e;
+        }
+    }
+    block_sum2<RBLOCK>(acc, 0.0, partial + 2 * (size_t)(blockIdx.y * gridDim.x + blockIdx.x));
+}
+
 // out[k] = scale[k] * sum_i partial[2 i + k], summed in a fixed order.
 __global__ void __launch_bounds__(RBLOCK) k_finalize(const double* partial, uint32_t n, double s0, double s1, double* out)
 {
@@ -277,6 +367,15 @@ hipError_t launch_rebuild_from_g(const LinkField<double>& u0, const GField& gacc
 uint32_t measure_blocks(const Geom& g)
 {
     return 2 * site_blocks(g);
+}
+
+hipError_t launch_fp32_floor(const LinkField<double>& f, const Geom& g, double* partial, double* out, hipStream_t st)
+{
+    const uint32_t nb = site_blocks(g);
+    hipLaunchKernelGGL(k_fp32_floor, dim3(nb, 2), dim3(RBLOCK), 0, st, f, g, partial);
+    const double V = 2.0 * (double)g.vh;
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RBLOCK), 0, st, partial, 2 * nb, 1.0 / (3.0 * V), 0.0, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_measure(const LinkField<double>& f, const Geom& g, double* p, double* o, hipStream_t st)

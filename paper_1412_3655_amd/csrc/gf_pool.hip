@@ -213,6 +213,7 @@ struct Job {
     uint64_t seed = 0;
     gf_fix_result res{};
     double theta = 0.0, F = 0.0, best = 0.0;
+    double theta_switch = 0.0;  // resolved switch point (p.theta_switch < 0: chosen for the lattice)
     int stall = 0;
     gf_status status = GF_OK;
     double t_admit = 0.0, t_done = 0.0;
@@ -530,15 +531,15 @@ void finish(gf_pool P, Job& j, gf_status status)
 
 // The loop head of gf_fix_until for a job in the fix phase: finish, or promote
 // and measure again, until the job needs sweeps.
+// The loop head of gf_fix_until for a job in the fix phase: promote a GF_MIXED
+// job at its switch point (or when it would end), finish it when done.
 gf_status fix_head(gf_pool P, Job& j)
 {
     gf_lattice L = j.lat;
     for (;;) {
-        if (!(j.theta >= j.p.theta_target && j.res.sweeps < j.p.max_sweeps)) {
-            finish(P, j, GF_OK);
-            return GF_OK;
-        }
-        if (L->prec == GF_MIXED && L->phase == 0 && leave_fp32(j.theta, j.p.theta_switch, j.best, j.stall)) {
+        const bool finished = !(j.theta >= j.p.theta_target && j.res.sweeps < j.p.max_sweeps);
+        const bool in_fp32 = L->prec == GF_MIXED && L->phase == 0;
+        if (in_fp32 && (finished || leave_fp32(j.theta, j.theta_switch, j.best, j.stall))) {
             GF_TRY(do_promote(L));
             gf_status st = do_measure(L, &j.theta, &j.F);
             if (st != GF_OK) {
@@ -547,8 +548,21 @@ gf_status fix_head(gf_pool P, Job& j)
             }
             continue;
         }
+        if (finished) finish(P, j, GF_OK);
         return GF_OK;
     }
+}
+
+// Entering the fix phase (at admission, or after the anneal): the measured
+// theta starts the stall record and the switch point is resolved, as at the
+// start of gf_fix_until.
+void enter_fix(gf_pool P, Job& j)
+{
+    j.state = J_FIX;
+    j.best = j.theta;
+    j.stall = 0;
+    const gf_status st = resolve_switch(j.lat, j.p.theta_target, j.p.theta_switch, &j.theta_switch);
+    if (st != GF_OK) finish(P, j, st);
 }
 
 void release_job(gf_pool P, Job& j)
@@ -671,7 +685,7 @@ gf_status gf_pool_admit(gf_pool P, uint64_t job_id, const int32_t dims[4], const
     if (params->check_every != P->cfg.check_every)
         return fail(GF_E_ARG, "job check_every %d differs from the pool's %d", params->check_every, P->cfg.check_every);
     if (params->max_sweeps < 0 || params->reunit_every < 0 || !(params->theta_target >= 0.0) ||
-        !(params->theta_switch >= 0.0))
+        std::isnan(params->theta_switch))
         return fail(GF_E_ARG, "bad fix parameters");
     if (anneal_sweeps < 0) return fail(GF_E_ARG, "anneal_sweeps < 0");
     if (anneal_sweeps > 0 && (!(T_end > 0.0) || !(T_start >= T_end) || !std::isfinite(T_start)))
@@ -718,12 +732,10 @@ gf_status gf_pool_admit(gf_pool P, uint64_t job_id, const int32_t dims[4], const
     } else {
         j.state = J_FIX;
         st = do_measure(L, &j.theta, &j.F);
-        if (st != GF_OK) {
+        if (st != GF_OK)
             finish(P, j, st);
-        } else {
-            j.best = j.theta;
-            j.stall = 0;
-        }
+        else
+            enter_fix(P, j);
     }
     fill_slot(P, slot);
     return GF_OK;
@@ -814,9 +826,7 @@ gf_status gf_pool_step(gf_pool P)
             if (j.plan_measure_k >= 0) {
                 j.theta = P->results_pin[2 * j.slot];
                 j.F = P->results_pin[2 * j.slot + 1];
-                j.state = J_FIX;
-                j.best = j.theta;
-                j.stall = 0;
+                if (std::isfinite(j.theta) && std::isfinite(j.F)) enter_fix(P, j);
             }
         } else {
             j.res.sweeps += j.plan_n;
@@ -832,7 +842,7 @@ gf_status gf_pool_step(gf_pool P)
             finish(P, j, GF_E_NUMERIC);
             continue;
         }
-        if (j.state == J_FIX && !(j.theta >= j.p.theta_target && j.res.sweeps < j.p.max_sweeps)) finish(P, j, GF_OK);
+        if (j.state == J_FIX) GF_TRY(fix_head(P, j));
     }
     return GF_OK;
 }

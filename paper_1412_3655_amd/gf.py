@@ -127,6 +127,7 @@ _SIGNATURES = {
     "gf_anneal": [_vp, _i32, ctypes.c_double, ctypes.c_double, ctypes.c_uint64],
     "gf_measure_theta_F": [_vp, _dp, _dp],
     "gf_fix_until": [_vp, ctypes.POINTER(gf_fix_params), ctypes.POINTER(gf_fix_result)],
+    "gf_tune_switch": [_vp, ctypes.c_double, _dp, _dp],
     "gf_reunitarize": [_vp],
     "gf_plaquette": [_vp, _dp],
     "gf_pool_create": [ctypes.POINTER(gf_pool_config), _vp, ctypes.POINTER(_vp)],
@@ -325,12 +326,21 @@ def gf_measure_theta_F(lat):
 
 def gf_fix_until(lat, omega: float = 1.7, mode: int = GF_OR_EXACT, theta_target: float = 1e-12,
                  max_sweeps: int = 3000, check_every: int = 10, reunit_every: int = 100,
-                 theta_switch: float = 1e-8) -> FixResult:
+                 theta_switch: float = -1.0) -> FixResult:
+    """theta_switch < 0: the library picks the float32 -> float64 switch point (gf_tune_switch)."""
     p = gf_fix_params(float(omega), int(mode), float(theta_target), int(max_sweeps), int(check_every),
                       int(reunit_every), float(theta_switch))
     r = gf_fix_result()
     _call("gf_fix_until", lat, ctypes.byref(p), ctypes.byref(r))
     return FixResult(bool(r.converged), r.sweeps, r.sweeps_fp32, r.sweeps_fp64, r.theta, r.F)
+
+
+def gf_tune_switch(lat, theta_target: float = 1e-12):
+    """(float32 rounding floor of theta, chosen switch point) for the lattice's float64 links."""
+    fl = ctypes.c_double()
+    sw = ctypes.c_double()
+    _call("gf_tune_switch", lat, float(theta_target), ctypes.byref(fl), ctypes.byref(sw))
+    return fl.value, sw.value
 
 
 def gf_reunitarize(lat) -> None:
@@ -393,6 +403,9 @@ class Lattice:
     def fix_until(self, **kw) -> FixResult:
         return gf_fix_until(self.handle, **kw)
 
+    def tune_switch(self, theta_target: float = 1e-12):
+        return gf_tune_switch(self.handle, theta_target)
+
     def reunitarize(self):
         gf_reunitarize(self.handle)
 
@@ -451,7 +464,7 @@ def gf_pool_destroy(pool) -> None:
 
 def gf_pool_admit(pool, job_id: int, dims, links: np.ndarray, omega: float = 1.7, mode: int = GF_OR_EXACT,
                   theta_target: float = 1e-12, max_sweeps: int = 3000, check_every: int = 10,
-                  reunit_every: int = 100, theta_switch: float = 1e-8, anneal_sweeps: int = 0,
+                  reunit_every: int = 100, theta_switch: float = -1.0, anneal_sweeps: int = 0,
                   T_start: float = 1.25, T_end: float = 0.01, seed: int = 0) -> bool:
     """Admit a job; returns False (nothing changed) when the pool is full."""
     d = (_i32 * 4)(*[int(x) for x in dims])

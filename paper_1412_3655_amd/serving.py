@@ -44,6 +44,8 @@ class RunStats:
     latencies: list = field(default_factory=list)        # every finished job
     conv_latencies: list = field(default_factory=list)   # converged jobs only
     sweeps: int = 0
+    sweeps_fp32: int = 0     # fix-phase sweeps in float32 (mixed precision)
+    sweeps_fp64: int = 0     # fix-phase sweeps in float64
     site_updates: float = 0.0
     failed: int = 0
 
@@ -63,6 +65,9 @@ class RunStats:
             "p50_latency_s_all": pct(self.latencies, 50),
             "p99_latency_s_all": pct(self.latencies, 99),
             "site_updates_per_s": self.site_updates / self.seconds if self.seconds > 0 else None,
+            "sweeps": self.sweeps,
+            "fix_sweeps_fp32": self.sweeps_fp32,
+            "fix_sweeps_fp64": self.sweeps_fp64,
         }
 
 
@@ -146,6 +151,8 @@ def run_pool(jobs, links_of, prec=gf.GF_MIXED, check_every=10, max_slots=256, hb
                 r = d["result"]
                 stats.latencies.append(lat)
                 stats.sweeps += r.sweeps + j.anneal
+                stats.sweeps_fp32 += r.sweeps_fp32
+                stats.sweeps_fp64 += r.sweeps_fp64
                 stats.site_updates += (r.sweeps + j.anneal) * volume(j.dims)
                 if d["status"] != gf.GF_OK:
                     stats.failed += 1
@@ -189,6 +196,8 @@ def run_fifo(jobs, links_of, prec=gf.GF_FP64, fix=None, open_loop=True, tps=0, b
             stats.failed += 1
             continue
         stats.sweeps += r.sweeps + j.anneal
+        stats.sweeps_fp32 += r.sweeps_fp32
+        stats.sweeps_fp64 += r.sweeps_fp64
         stats.site_updates += (r.sweeps + j.anneal) * volume(j.dims)
         if r.converged:
             stats.converged += 1

@@ -117,3 +117,63 @@ def test_mixed_stall_switch():
                           reunit_every=100, theta_switch=0.0)
     say(f"  sweeps {r.sweeps} fp32 {r.sweeps_fp32} fp64 {r.sweeps_fp64} theta {r.theta:.2e}")
     assert r.converged and r.sweeps_fp64 > 0
+
+
+def test_fp32_floor_matches_oracle_and_sets_the_switch():
+    """gf_tune_switch: the float32 rounding floor of theta against the oracle's.  Both form the
+    float32 two-row store and K in float32 in the same order; the GPU rebuilds row 2 with fused
+    multiply-adds and the oracle without, so the per-site errors differ and the two mean-square
+    floors agree statistically (measured within a few per cent on 8^4), not bitwise: 25 %.
+    Float-exact links give exactly 0 on both sides."""
+    for dims, eps, seed in ((CFG8, 0.6, 0), (RAGGED, 1.0, 4)):
+        u = gi.gen_links(dims, eps, seed)
+        f_o = oracle.fp32_floor(u, dims)
+        with gf.Lattice(dims, gf.GF_MIXED) as lat:
+            lat.set_links(u)
+            f_g, sw = lat.tune_switch(1e-12)
+            f_g2, sw2 = lat.tune_switch(1e-20)
+        say(f"  floor {dims} eps {eps}: gpu {f_g:.4e} oracle {f_o:.4e} ratio {f_g / f_o:.3f}; switch {sw:.3e}")
+        assert abs(f_g / f_o - 1.0) < 0.25
+        assert sw == max(1e-12, 100.0 * f_g) and sw2 == 100.0 * f_g2 and f_g2 == f_g
+    from tests.test_oracle_pins import _float_exact_links
+
+    ex = _float_exact_links(CFG8, 3)
+    assert oracle.fp32_floor(ex, CFG8) == 0.0
+    with gf.Lattice(CFG8, gf.GF_FP64) as lat:
+        lat.set_links(ex)
+        f_g, sw = lat.tune_switch(1e-12)
+    assert f_g == 0.0 and sw == 1e-12
+    with gf.Lattice(CFG8, gf.GF_FP32) as lat:
+        lat.set_links(ex)
+        with pytest.raises(gf.GFError):
+            lat.tune_switch(1e-12)
+
+
+@pytest.mark.parametrize("dims,eps,seed", [(CFG8, 0.6, 0), ((16, 16, 16, 16), 0.4, 11)])
+def test_mixed_auto_switch_ends_in_float64(dims, eps, seed):
+    """theta_switch < 0: the library's switch point.  Float32 sweeps run down to it and the result
+    is the float64 one (links rebuilt from g and U0, theta and F measured in float64): the oracle's
+    theta of the downloaded links is below the target, the plaquette is the input's, and the
+    sweep count is the float64 run's (float32 converges at the float64 rate above its floor)."""
+    u = gi.gen_links(dims, eps, seed)
+    P0 = oracle.plaquette(u, dims)
+    with gf.Lattice(dims, gf.GF_FP64) as lat:
+        lat.set_links(u)
+        r64 = lat.fix_until(omega=1.7, mode=0, theta_target=1e-12, max_sweeps=6000, check_every=10,
+                            reunit_every=100, theta_switch=0.0)
+    with gf.Lattice(dims, gf.GF_MIXED) as lat:
+        lat.set_links(u)
+        _, sw = lat.tune_switch(1e-12)
+        r = lat.fix_until(omega=1.7, mode=0, theta_target=1e-12, max_sweeps=6000, check_every=10,
+                          reunit_every=100, theta_switch=-1.0)
+        P = lat.plaquette()
+        links = lat.get_links()
+    th_o, F_o = oracle.measure(links, dims)
+    say(f"  auto switch {dims} eps {eps}: switch {sw:.2e}, sweeps {r.sweeps} ({r.sweeps_fp32}/{r.sweeps_fp64}) "
+        f"vs float64 {r64.sweeps}; theta {r.theta:.3e} (oracle {th_o:.3e})")
+    assert r.converged and r64.converged
+    assert r.sweeps_fp32 > 0 and r.sweeps_fp32 + r.sweeps_fp64 == r.sweeps
+    assert th_o < 1e-12 and abs(th_o - r.theta) <= 1e-8 * r.theta
+    assert abs(F_o - r.F) < 1e-13
+    assert abs(P - P0) < 1e-12
+    assert abs(r.sweeps - r64.sweeps) <= 0.1 * r64.sweeps
