@@ -219,11 +219,12 @@ gf_status gf_plaquette(gf_lattice lat, double* P);
 /* Every job runs exactly the fix-until iteration of gf_fix_until (optionally */
 /* after gf_anneal) on its own lattice of the pool's precision, so its result */
 /* equals the one it gets alone.  A pool step advances every active job by   */
-/* up to check_every sweeps: per sweep one persistent launch per kernel kind  */
-/* (heat bath, float32 OR tracking g, float64 OR) covers the sites of that    */
-/* colour of every job in that state, then reunitarisation and measurement    */
-/* launches cover the jobs due for them; the launches of a step are captured  */
-/* once in a hipGraph per work structure and replayed.                        */
+/* up to check_every sweeps: per sweep one launch per kernel kind (heat      */
+/* bath, float32 OR tracking g, float64 OR), one block per tile, covers the  */
+/* sites of that colour of every job in that state, then reunitarisation and */
+/* measurement launches cover the jobs due for them; the launches of a step  */
+/* are captured once in a hipGraph per work structure and replayed with each */
+/* sweep node's grid set to the step's tile count.                            */
 /* ------------------------------------------------------------------------ */
 
 typedef struct gf_pool_* gf_pool; /* opaque, library-owned */

@@ -2,8 +2,8 @@
 gauge-fixing jobs.
 
 The pool (C ABI, include/gf.h) owns the device work: admission by HBM
-footprint, resident lattices, batched persistent sweeps captured in hipGraphs,
-retirement.  This module is the arrival-side driver: it releases jobs into a
+footprint, resident lattices, batched sweeps (one launch per kernel kind over
+every lattice) captured in hipGraphs, retirement.  This module is the arrival-side driver: it releases jobs into a
 FIFO queue at their arrival times, admits from the head of the queue whenever
 the pool has room (slots and bytes), steps the pool, and retires finished
 jobs (freeing their lattices, which lets queued jobs in).  Latency of a job =
