@@ -200,12 +200,59 @@ def serving_leg(gf, gi, stream, args):
     links_of = lambda j: bank[(j.dims, j.eps)]
     out = {"jobs": len(jobs), "rate_per_s": 20.0, "max_sweeps": args.job_max_sweeps,
            "distinct_inputs": len(bank), "last_arrival_s": jobs[-1].arrival}
-    st = serving.run_pool(jobs, links_of, gf.GF_MIXED, 10, 256, None, fix, True, t32, t64)
+    budget = int(args.serve_budget_gb * 1e9) if args.serve_budget_gb > 0 else None
+    out["hbm_budget_bytes"] = budget
+    st = serving.run_pool(jobs, links_of, gf.GF_MIXED, 10, 256, budget, fix, True, t32, t64)
     out["pool_mixed"] = st.summary()
     log(f"serving pool: {st.converged}/{len(jobs)} converged, {st.seconds:.1f} s")
     st = serving.run_fifo(jobs, links_of, gf.GF_FP64, fix, True, args.tps, args.block, args.nt)
     out["fifo_fp64"] = st.summary()
     log(f"serving fifo: {st.converged}/{len(jobs)} converged, {st.seconds:.1f} s")
+    return out
+
+
+def fullsize_leg(gf, gi, torch, stream, args):
+    """The 48^3 x 96 workload (eps = 1.0, seed 0) in mixed precision: 2000 float32 heat-bath sweeps
+    on g(x) with T falling linearly from 1.25 to 0.01 (Philox per site), then overrelaxation to
+    theta < 1e-13 with float32 bulk, float64 polish and reunitarisation every 100 sweeps."""
+    dims = (48, 48, 48, 96)
+    V = gi.volume(dims)
+    t0 = time.perf_counter()
+    u = gi.gen_links(dims, 1.0, 0)
+    log(f"fullsize: generated {dims} in {time.perf_counter() - t0:.1f} s")
+    out = {"workload": "48x48x48x96, eps=1.0, seed 0; anneal 2000 (T 1.25 -> 0.01), then OR to theta < 1e-13",
+           "max_sweeps": args.full_max_sweeps}
+    with gf.Lattice(dims, gf.GF_FP64, stream=stream) as lat:
+        lat.set_links(u)
+        P0 = lat.plaquette()
+    with gf.Lattice(dims, gf.GF_MIXED, stream=stream) as lat:
+        lat.set_links(u)
+        del u
+        cfg = {}
+        for kernel, name in ((gf.GF_FP32, "f32"), (gf.GF_FP64, "f64")):
+            chosen, _ = lat.autotune(kernel, n_sweeps=3)
+            cfg[name] = list(chosen)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.anneal(2000, 1.25, 0.01, 0)
+        th_a, F_a = lat.measure()
+        t_anneal = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        r = lat.fix_until(omega=args.omega, mode=args.mode, theta_target=1e-13, max_sweeps=args.full_max_sweeps,
+                          check_every=10, reunit_every=100, theta_switch=args.theta_switch)
+        t_fix = time.perf_counter() - t0
+        P1 = lat.plaquette()
+    out.update({
+        "tuned_f32": cfg["f32"], "tuned_f64": cfg["f64"],
+        "anneal_seconds": t_anneal, "anneal_site_updates_per_s": 2000 * V / t_anneal,
+        "after_anneal": {"theta": th_a, "F": F_a},
+        "fix_seconds": t_fix, "converged": r.converged, "sweeps": r.sweeps, "sweeps_fp32": r.sweeps_fp32,
+        "sweeps_fp64": r.sweeps_fp64, "theta": r.theta, "F": r.F,
+        "fix_site_updates_per_s": r.sweeps * V / t_fix if t_fix > 0 else None,
+        "plaquette_drift": abs(P1 - P0),
+    })
+    log(f"fullsize: anneal {t_anneal:.1f} s, theta {th_a:.3e}; OR {t_fix:.1f} s, sweeps {r.sweeps} "
+        f"({r.sweeps_fp32}/{r.sweeps_fp64}), theta {r.theta:.3e}, converged {r.converged}, |dP| {abs(P1 - P0):.1e}")
     return out
 
 
@@ -257,6 +304,10 @@ def main(argv=None):
     ap.add_argument("--batched", action="store_true", help="also run the 64-lattice batched workload")
     ap.add_argument("--serve", action="store_true", help="also run the Poisson-arrival serving workload")
     ap.add_argument("--serve-jobs", type=int, default=200)
+    ap.add_argument("--serve-budget-gb", type=float, default=0.0,
+                    help="HBM budget of the serving pool (0: 80 %% of free device memory)")
+    ap.add_argument("--fullsize", action="store_true", help="also run the 48^3x96 anneal + mixed-precision workload")
+    ap.add_argument("--full-max-sweeps", type=int, default=10000)
     ap.add_argument("--job-max-sweeps", type=int, default=10000)
     ap.add_argument("--fix-max-sweeps", type=int, default=20000)
     ap.add_argument("--theta-switch", type=float, default=-1.0,
@@ -397,6 +448,8 @@ def main(argv=None):
         line["batched_64"] = batched_leg(gf, gi, stream, args)
     if args.serve:
         line["serving"] = serving_leg(gf, gi, stream, args)
+    if args.fullsize:
+        line["fullsize_48x96"] = fullsize_leg(gf, gi, torch, stream, args)
     if not args.no_cpu:
         log("cpu baseline (FP64 oracle)")
         line["cpu_baseline"] = cpu_baseline(links, dims, args.omega, args.mode, args.cpu_budget)

@@ -45,7 +45,8 @@ typedef enum {
     GF_E_HIP = 3,     /* a HIP runtime call failed; see gf_last_error() */
     GF_E_STATE = 4,   /* call not valid in the current state (e.g. no links set) */
     GF_E_NUMERIC = 5, /* theta or F is NaN or infinite */
-    GF_E_FULL = 6     /* no room (pool admission) */
+    GF_E_FULL = 6,    /* no room (pool admission) */
+    GF_E_CANCELLED = 7 /* the job was cancelled (gf_pool_cancel) */
 } gf_status;
 
 typedef enum {
@@ -281,6 +282,14 @@ gf_status gf_pool_fetch_links(gf_pool pool, uint64_t job_id, double* host);
 
 /* Free a finished job's lattice without downloading it. */
 gf_status gf_pool_release(gf_pool pool, uint64_t job_id);
+
+/* Cancel a resident job that has not finished: it takes no further part in
+ * pool steps and is reported by the next gf_pool_poll with status
+ * GF_E_CANCELLED and its last measured theta and F (converged = 0); its links
+ * stay resident until gf_pool_release / gf_pool_fetch_links.  Other jobs are
+ * unaffected.  GF_E_STATE if the job has already finished, GF_E_ARG if no
+ * such job is resident. */
+gf_status gf_pool_cancel(gf_pool pool, uint64_t job_id);
 
 /* Resident jobs still iterating, finished jobs not yet released, and device bytes held. */
 gf_status gf_pool_stats(gf_pool pool, int32_t* active, int32_t* finished, int64_t* bytes_in_use);

@@ -885,6 +885,18 @@ gf_status gf_pool_release(gf_pool P, uint64_t job_id)
     return fail(GF_E_ARG, "no job %llu in the pool", (unsigned long long)job_id);
 }
 
+gf_status gf_pool_cancel(gf_pool P, uint64_t job_id)
+{
+    GF_TRY(pool_check(P));
+    for (auto& j : P->jobs)
+        if (j.lat && j.id == job_id) {
+            if (j.state == J_DONE) return fail(GF_E_STATE, "job %llu has already finished", (unsigned long long)job_id);
+            finish(P, j, GF_E_CANCELLED);
+            return GF_OK;
+        }
+    return fail(GF_E_ARG, "no job %llu in the pool", (unsigned long long)job_id);
+}
+
 gf_status gf_pool_stats(gf_pool P, int32_t* active, int32_t* finished, int64_t* bytes_in_use)
 {
     GF_TRY(pool_check(P));

@@ -21,7 +21,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgf.so")
 
-GF_OK, GF_E_ARG, GF_E_NOMEM, GF_E_HIP, GF_E_STATE, GF_E_NUMERIC, GF_E_FULL = range(7)
+GF_OK, GF_E_ARG, GF_E_NOMEM, GF_E_HIP, GF_E_STATE, GF_E_NUMERIC, GF_E_FULL, GF_E_CANCELLED = range(8)
 GF_FP64, GF_FP32, GF_MIXED = 0, 1, 2
 GF_OR_EXACT, GF_OR_BINOMIAL1 = 0, 1
 
@@ -33,6 +33,7 @@ _STATUS_NAMES = {
     GF_E_STATE: "GF_E_STATE",
     GF_E_NUMERIC: "GF_E_NUMERIC",
     GF_E_FULL: "GF_E_FULL",
+    GF_E_CANCELLED: "GF_E_CANCELLED",
 }
 
 
@@ -139,6 +140,7 @@ _SIGNATURES = {
     "gf_pool_poll": [_vp, ctypes.POINTER(gf_pool_done), _i32, ctypes.POINTER(_i32)],
     "gf_pool_fetch_links": [_vp, ctypes.c_uint64, _dp],
     "gf_pool_release": [_vp, ctypes.c_uint64],
+    "gf_pool_cancel": [_vp, ctypes.c_uint64],
     "gf_pool_stats": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_int64)],
     "gf_clock": [],
     "gf_probe_copy": [ctypes.c_size_t, _i32, _i32, _i32, _dp],
@@ -514,6 +516,10 @@ def gf_pool_release(pool, job_id: int) -> None:
     _call("gf_pool_release", pool, int(job_id))
 
 
+def gf_pool_cancel(pool, job_id: int) -> None:
+    _call("gf_pool_cancel", pool, int(job_id))
+
+
 def gf_pool_stats(pool):
     a = _i32()
     f = _i32()
@@ -554,6 +560,9 @@ class Pool:
     def release(self, job_id):
         gf_pool_release(self.handle, job_id)
         self.dims.pop(int(job_id), None)
+
+    def cancel(self, job_id):
+        gf_pool_cancel(self.handle, job_id)
 
     def stats(self):
         return gf_pool_stats(self.handle)

@@ -48,6 +48,9 @@ class RunStats:
     sweeps_fp64: int = 0     # fix-phase sweeps in float64
     site_updates: float = 0.0
     failed: int = 0
+    max_queue: int = 0       # most jobs waiting for admission at once
+    max_resident: int = 0    # most jobs resident in the pool at once
+    peak_bytes: int = 0      # most device bytes the pool held for job lattices
 
     def summary(self) -> dict:
         def pct(v, q):
@@ -68,6 +71,9 @@ class RunStats:
             "sweeps": self.sweeps,
             "fix_sweeps_fp32": self.sweeps_fp32,
             "fix_sweeps_fp64": self.sweeps_fp64,
+            "max_queue_depth": self.max_queue,
+            "max_resident_jobs": self.max_resident,
+            "peak_hbm_bytes": self.peak_bytes,
         }
 
 
@@ -137,7 +143,10 @@ def run_pool(jobs, links_of, prec=gf.GF_MIXED, check_every=10, max_slots=256, hb
                     break
                 by_id[j.job_id] = j
                 queue.popleft()
-            active, finished, _ = pool.stats()
+            active, finished, held = pool.stats()
+            stats.max_queue = max(stats.max_queue, len(queue))
+            stats.max_resident = max(stats.max_resident, active + finished)
+            stats.peak_bytes = max(stats.peak_bytes, held)
             if active:
                 pool.step()
             elif finished == 0 and arrivals and not queue:

@@ -157,3 +157,44 @@ def test_pool_many_shapes_fill():
                                   reunit_every=100, theta_switch=1e-8)
             assert done[i]["result"] == r
         assert all(v["result"].converged for v in done.values())
+
+
+def test_pool_cancel_mid_run():
+    """Cancelling a job mid-run: it is polled with GF_E_CANCELLED and its last theta, takes no
+    further steps, and every other job still equals its solo run bitwise."""
+    say("pool cancel mid-run")
+    ce = 5
+    jobs = [((8, 8, 8, 8), 0.6, 31), ((6, 10, 6, 6), 0.7, 32), ((4, 4, 4, 8), 0.5, 33)]
+    inputs = [gi.gen_links(d, e, s) for (d, e, s) in jobs]
+    ref = {i: solo(d, u, gf.GF_MIXED, 0, 0, ce) for i, ((d, e, s), u) in enumerate(zip(jobs, inputs))}
+    kw = {k: v for k, v in fix_kw(ce).items() if k not in ("check_every", "mode")}
+    with gf.Pool(1 << 34, 8, prec=gf.GF_MIXED, check_every=ce) as pool:
+        for i, ((d, e, s), u) in enumerate(zip(jobs, inputs)):
+            assert pool.admit(i, d, u, **kw)
+        for _ in range(3):
+            pool.step()
+        assert pool.poll() == []
+        pool.cancel(1)
+        with pytest.raises(gf.GFError) as e:
+            pool.cancel(1)  # already finished (cancelled)
+        assert e.value.status == gf.GF_E_STATE
+        with pytest.raises(gf.GFError) as e:
+            pool.cancel(99)
+        assert e.value.status == gf.GF_E_ARG
+        done = {}
+        for _ in range(2000):
+            for d in pool.poll():
+                done[d["job_id"]] = d
+            if len(done) == len(jobs):
+                break
+            pool.step()
+        assert len(done) == len(jobs)
+        c = done[1]
+        assert c["status"] == gf.GF_E_CANCELLED and not c["result"].converged
+        assert c["result"].sweeps == 3 * ce and np.isfinite(c["result"].theta)
+        for i in (0, 2):
+            assert done[i]["status"] == gf.GF_OK
+            assert done[i]["result"] == ref[i][0]
+            assert np.array_equal(pool.fetch_links(i), ref[i][1])
+        pool.release(1)
+        assert pool.stats() == (0, 0, 0)
