@@ -47,6 +47,9 @@ class RunStats:
     sweeps_fp32: int = 0     # fix-phase sweeps in float32 (mixed precision)
     sweeps_fp64: int = 0     # fix-phase sweeps in float64
     site_updates: float = 0.0
+    site_updates_fp32: float = 0.0  # fix-phase site updates in float32
+    site_updates_fp64: float = 0.0  # fix-phase site updates in float64
+    site_updates_anneal: float = 0.0
     failed: int = 0
     max_queue: int = 0       # most jobs waiting for admission at once
     max_resident: int = 0    # most jobs resident in the pool at once
@@ -71,6 +74,10 @@ class RunStats:
             "sweeps": self.sweeps,
             "fix_sweeps_fp32": self.sweeps_fp32,
             "fix_sweeps_fp64": self.sweeps_fp64,
+            "site_updates": self.site_updates,
+            "fix_site_updates_fp32": self.site_updates_fp32,
+            "fix_site_updates_fp64": self.site_updates_fp64,
+            "anneal_site_updates": self.site_updates_anneal,
             "max_queue_depth": self.max_queue,
             "max_resident_jobs": self.max_resident,
             "peak_hbm_bytes": self.peak_bytes,
@@ -163,6 +170,9 @@ def run_pool(jobs, links_of, prec=gf.GF_MIXED, check_every=10, max_slots=256, hb
                 stats.sweeps_fp32 += r.sweeps_fp32
                 stats.sweeps_fp64 += r.sweeps_fp64
                 stats.site_updates += (r.sweeps + j.anneal) * volume(j.dims)
+                stats.site_updates_fp32 += r.sweeps_fp32 * volume(j.dims)
+                stats.site_updates_fp64 += r.sweeps_fp64 * volume(j.dims)
+                stats.site_updates_anneal += j.anneal * volume(j.dims)
                 if d["status"] != gf.GF_OK:
                     stats.failed += 1
                 elif r.converged:
@@ -208,6 +218,9 @@ def run_fifo(jobs, links_of, prec=gf.GF_FP64, fix=None, open_loop=True, tps=0, b
         stats.sweeps_fp32 += r.sweeps_fp32
         stats.sweeps_fp64 += r.sweeps_fp64
         stats.site_updates += (r.sweeps + j.anneal) * volume(j.dims)
+        stats.site_updates_fp32 += r.sweeps_fp32 * volume(j.dims)
+        stats.site_updates_fp64 += r.sweeps_fp64 * volume(j.dims)
+        stats.site_updates_anneal += j.anneal * volume(j.dims)
         if r.converged:
             stats.converged += 1
             stats.conv_latencies.append(lat_s)

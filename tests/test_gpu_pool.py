@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import gauge_inputs as gi
+import oracle
 from paper_1412_3655_amd import gf
 
 pytestmark = pytest.mark.gpu
@@ -198,3 +199,58 @@ def test_pool_cancel_mid_run():
             assert np.array_equal(pool.fetch_links(i), ref[i][1])
         pool.release(1)
         assert pool.stats() == (0, 0, 0)
+
+
+BATCH_SHAPES = [(12, 12, 12, 12), (16, 16, 16, 16), (16, 16, 16, 32), (24, 24, 24, 48)]
+
+
+@pytest.mark.timeout(900)
+def test_pool_full_size_batched_shapes():
+    """The batched workload's four lattice shapes at full size, in the pool's launch shapes
+    (128-thread blocks; 1 or 2 lanes per site for float64 and 2 for float32, the autotuner's
+    picks on MI355X): a float64 pool doing one sweep per job against the oracle's sweep of each
+    lattice (1e-12), then a mixed pool (one job with a heat-bath prelude) against each job's solo
+    gf_anneal + gf_fix_until run (bitwise)."""
+    eps = (0.5, 0.7, 0.9, 1.0)
+    inputs = [gi.gen_links(d, e, 1000 + i) for i, (d, e) in enumerate(zip(BATCH_SHAPES, eps))]
+    refs = [oracle.sweep(u.copy(), d, 1, 1.7, oracle.OR_EXACT) for d, u in zip(BATCH_SHAPES, inputs)]
+    for tps64 in (1, 2):
+        say(f"pool full-size shapes, float64, one sweep, tps64={tps64}")
+        with gf.Pool(1 << 36, 8, prec=gf.GF_FP64, check_every=1, tps64=tps64) as pool:
+            for i, (d, u) in enumerate(zip(BATCH_SHAPES, inputs)):
+                assert pool.admit(i, d, u, theta_target=0.0, max_sweeps=1, reunit_every=0)
+            pool.step()
+            done = {d["job_id"]: d for d in pool.poll()}
+            assert sorted(done) == [0, 1, 2, 3]
+            for i, d in enumerate(BATCH_SHAPES):
+                assert done[i]["status"] == gf.GF_OK and done[i]["result"].sweeps == 1
+                diff = float(np.abs(pool.fetch_links(i) - refs[i]).max())
+                say(f"  {d}: max|pool - oracle| = {diff:.2e}")
+                assert diff <= 1e-12
+    say("pool full-size shapes, mixed, against solo runs")
+    kw = dict(omega=1.7, mode=gf.GF_OR_EXACT, theta_target=1e-12, max_sweeps=100, check_every=10,
+              reunit_every=50, theta_switch=-1.0)
+    anneal = (0, 0, 0, 20)
+    solo_res = []
+    for i, (d, u) in enumerate(zip(BATCH_SHAPES, inputs)):
+        with gf.Lattice(d, gf.GF_MIXED) as lat:
+            lat.set_links(u)
+            if anneal[i]:
+                lat.anneal(anneal[i], 1.25, 0.01, 77)
+            solo_res.append((lat.fix_until(**kw), lat.get_links()))
+    with gf.Pool(1 << 36, 8, prec=gf.GF_MIXED, check_every=10, tps32=2, tps64=2) as pool:
+        for i, (d, u) in enumerate(zip(BATCH_SHAPES, inputs)):
+            assert pool.admit(i, d, u, anneal_sweeps=anneal[i], T_start=1.25, T_end=0.01, seed=77,
+                              **{k: v for k, v in kw.items() if k not in ("check_every", "mode")})
+        done = {}
+        for _ in range(40):
+            pool.step()
+            for d in pool.poll():
+                done[d["job_id"]] = d
+            if len(done) == 4:
+                break
+        assert sorted(done) == [0, 1, 2, 3]
+        for i in range(4):
+            r, links = solo_res[i]
+            assert done[i]["result"] == r
+            assert np.array_equal(pool.fetch_links(i), links)
