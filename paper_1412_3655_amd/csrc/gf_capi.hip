@@ -422,6 +422,7 @@ gf_status gf_half_sweep_or(gf_lattice L, int32_t colour, double omega, gf_or_mod
 
 gf_status gf_anneal(gf_lattice L, int32_t n_sweeps, double T_start, double T_end, uint64_t seed)
 {
+    TraceRange range("gf_anneal");
     GF_TRY(check_ready(L));
     if (n_sweeps < 0) return fail(GF_E_ARG, "n_sweeps = %d < 0", n_sweeps);
     if (!(T_end > 0.0) || !(T_start >= T_end) || !std::isfinite(T_start))
@@ -481,6 +482,7 @@ gf_status gf_tune_switch(gf_lattice L, double theta_target, double* floor, doubl
 
 gf_status gf_fix_until(gf_lattice L, const gf_fix_params* p, gf_fix_result* res)
 {
+    TraceRange range("gf_fix_until");
     GF_TRY(check_ready(L));
     if (!p || !res) return fail(GF_E_ARG, "null argument");
     GF_TRY(check_omega(p->omega, p->mode));
@@ -501,11 +503,13 @@ gf_status gf_fix_until(gf_lattice L, const gf_fix_params* p, gf_fix_result* res)
         // GF_MIXED ends in float64: the float32 phase is left at the switch
         // point, at a stall below kStallTheta, and when the loop would end.
         if (L->prec == GF_MIXED && L->phase == 0 && (finished || leave_fp32(theta, theta_switch, best, stall))) {
+            TraceRange promote("promote_fp64");
             GF_TRY(do_promote(L));
             GF_TRY(do_measure(L, &theta, &F));
             continue;
         }
         if (finished) break;
+        TraceRange check(is_fp32(L) ? "fix_check_fp32" : "fix_check_fp64");
         const bool fp32 = is_fp32(L);
         const int32_t n = std::min(p->check_every, p->max_sweeps - sweeps);
         // n sweeps, reunitarising after every sweep whose count is a multiple of reunit_every

@@ -6,6 +6,8 @@
 #include <string>
 #include <tuple>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "gf.h"
 #include "gf_kernels.h"
 
@@ -101,6 +103,16 @@ inline bool leave_fp32(double theta, double theta_switch, double best, int stall
 // MI355X replayed kernels of a 32^4 lattice took 2-6 % longer than the same
 // kernels launched directly.
 constexpr uint32_t kGraphMaxHalfSites = 1u << 16;
+
+// A named range on the roctx marker stream for the lifetime of the object
+// (rocprofv3 --marker-trace shows it around the kernels it encloses; without
+// a profiler attached the calls do nothing).
+struct TraceRange {
+    explicit TraceRange(const char* name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
 
 inline void update_stall(double theta, double* best, int* stall)
 {

@@ -743,6 +743,7 @@ gf_status gf_pool_admit(gf_pool P, uint64_t job_id, const int32_t dims[4], const
 
 gf_status gf_pool_step(gf_pool P)
 {
+    TraceRange range("gf_pool_step");
     GF_TRY(pool_check(P));
     const int C = P->chunk;
     // loop heads (finish / promote) of jobs in the fix phase

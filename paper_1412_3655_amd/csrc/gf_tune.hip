@@ -57,6 +57,7 @@ bool cache_lookup(const char* path, const std::string& key, SweepConfig* out)
 extern "C" gf_status gf_autotune(gf_lattice L, gf_prec kernel, int32_t n_sweeps, const char* cache_path,
                                  gf_tune_entry* table, int32_t cap, int32_t* n_out, gf_tune_entry* chosen)
 {
+    TraceRange range("gf_autotune");
     GF_TRY(check_ready(L));
     if (kernel != GF_FP64 && kernel != GF_FP32) return fail(GF_E_ARG, "kernel precision must be GF_FP64 or GF_FP32");
     if ((kernel == GF_FP64 && !L->f64) || (kernel == GF_FP32 && !L->f32))
