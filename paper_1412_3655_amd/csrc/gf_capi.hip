@@ -107,9 +107,10 @@ void clear_graphs(gf_lattice L)
     L->sweep_graphs.clear();
 }
 
-// n sweeps.  On a non-default stream runs of two or more sweeps are captured
-// once in a hipGraph (kernel nodes only) and replayed, which removes the
-// launch gaps between the 2n half-sweeps.
+// n sweeps.  On a non-default stream runs of two or more sweeps on a lattice
+// of fewer than kGraphMaxHalfSites sites per colour are captured once in a
+// hipGraph (kernel nodes only) and replayed, which removes the launch gaps
+// between the 2n short half-sweeps; larger lattices launch directly.
 gf_status do_sweeps(gf_lattice L, int32_t n, double omega, int mode)
 {
     if (n < 2 || L->stream == nullptr || L->geom.vh >= kGraphMaxHalfSites) return launch_sweeps(L, n, omega, mode);
@@ -188,7 +189,7 @@ gf_status do_fp32_floor(gf_lattice L, double* floor)
 
 gf_status resolve_switch(gf_lattice L, double theta_target, double theta_switch, double* out)
 {
-    if (theta_switch >= 0.0 || L->prec != GF_MIXED) {
+    if (theta_switch >= 0.0 || L->prec != GF_MIXED || L->phase != 0) {
         *out = theta_switch;
         return GF_OK;
     }
