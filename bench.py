@@ -290,7 +290,8 @@ def main(argv=None):
     ap.add_argument("--mode", type=int, default=0, help="0 = exact SU(2) power, 1 = binomial form")
     ap.add_argument("--tps", type=int, default=4)
     ap.add_argument("--block", type=int, default=256)
-    ap.add_argument("--nt", type=int, default=0, help="non-temporal link accesses (0/1)")
+    ap.add_argument("--nt", type=int, default=0,
+                    help="cache policy: 0 plain, 1 non-temporal loads and stores, 2 non-temporal stores")
     ap.add_argument("--nt32", type=int, default=0)
     ap.add_argument("--tps32", type=int, default=4)
     ap.add_argument("--block32", type=int, default=256)
@@ -347,7 +348,7 @@ def main(argv=None):
         if not args.no_tune:
             (args.tps, args.block, args.nt), table = lat.autotune(gf.GF_FP64, n_sweeps=5)
             tuning["f64"] = [[t, b, nt, round(us, 1)] for (t, b, nt, us) in table]
-            log(f"fp64 autotune: tps={args.tps} block={args.block} nontemporal={args.nt}")
+            log(f"fp64 autotune: tps={args.tps} block={args.block} cache policy={args.nt}")
         P0 = lat.plaquette()
         log(f"fp64: warmup {args.warmup} sweeps")
         with torch.cuda.stream(stream):
@@ -370,7 +371,7 @@ def main(argv=None):
             if not args.no_tune:
                 (args.tps32, args.block32, args.nt32), table = lat.autotune(gf.GF_FP32, n_sweeps=5)
                 tuning["f32"] = [[t, b, nt, round(us, 1)] for (t, b, nt, us) in table]
-                log(f"fp32 autotune: tps={args.tps32} block={args.block32} nontemporal={args.nt32}")
+                log(f"fp32 autotune: tps={args.tps32} block={args.block32} cache policy={args.nt32}")
             with torch.cuda.stream(stream):
                 lat.sweep(args.warmup, args.omega, args.mode)
                 lat.sweep(args.chunk, args.omega, args.mode)
@@ -416,7 +417,8 @@ def main(argv=None):
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
             "traffic": traffic,
-            "kernel": "k_or_half_sweep<double, TPS=%d, exact, BLOCK=%d, NT=%d>" % (args.tps, args.block, args.nt),
+            "kernel": "k_or_half_sweep<double, TPS=%d, exact, BLOCK=%d, cache policy %d>" % (args.tps, args.block,
+                                                                                            args.nt),
             "algorithmic_bytes_per_launch": launch_bytes,
             "mean_launch_us": r64["per_launch"] * 1e6,
         },

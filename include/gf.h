@@ -100,9 +100,9 @@ gf_status gf_lattice_info(gf_lattice lat, int64_t* volume, int64_t* device_bytes
  * GF_FP32; a GF_MIXED lattice uses both): tps lanes per site (1, 2, 4 or 8;
  * the paper's design uses 4 or 8 threads per site, Sec. 4.2), threads per
  * block (64, 128, 256 or 512; not 512 with tps 1) and the cache policy of the
- * link accesses (0 = plain, 1 = non-temporal loads and stores, only with
- * tps <= 4 and block <= 256).  Every valid choice gives bitwise the same
- * links.  Default 4 / 256 / 0. */
+ * link accesses (0 = plain, 1 = non-temporal loads and stores, 2 = plain
+ * loads and non-temporal stores; 1 and 2 only with tps <= 4 and block <= 256).
+ * Every valid choice gives bitwise the same links.  Default 4 / 256 / 0. */
 gf_status gf_set_sweep_config(gf_lattice lat, gf_prec kernel, int32_t tps, int32_t block, int32_t nontemporal);
 
 /* GF_MIXED: leave the float32 phase now.  The float64 links become

@@ -144,8 +144,19 @@ __device__ __forceinline__ size_t chunk_index(const LinkField<R>& f, int parity,
     return ((size_t)((parity * 4 + mu) * ChunkOf<R>::N + c)) * f.ld + h;
 }
 
-// 16-byte chunk access; NT = non-temporal (streaming) loads and stores, the
-// cache-policy axis of the autotuner.
+// 16-byte chunk access; NT = non-temporal (streaming) access.
+//
+// Cache policy of a sweep's link accesses, the autotuner's cache axis:
+// 0 = plain loads and stores, 1 = non-temporal loads and stores,
+// 2 = plain loads and non-temporal stores.
+constexpr bool nt_loads(int cp)
+{
+    return cp == 1;
+}
+constexpr bool nt_stores(int cp)
+{
+    return cp == 1 || cp == 2;
+}
 typedef double nt_v2d __attribute__((ext_vector_type(2)));
 typedef float nt_v4f __attribute__((ext_vector_type(4)));
 

@@ -10,7 +10,8 @@ namespace gf {
 
 // Sweep kernel configuration: lanes per site (1, 2, 4 or 8), block size
 // (64, 128, 256 or 512 threads) and cache policy of the link accesses (0 =
-// plain, 1 = non-temporal; the latter with tps <= 4 and block <= 256).
+// plain, 1 = non-temporal loads and stores, 2 = plain loads and non-temporal
+// stores; 1 and 2 with tps <= 4 and block <= 256).
 struct SweepConfig {
     int tps = 4;
     int block = 256;

@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(SBLOCK) k_pool_sweep(const SlotDev* __restrict
                                                        const uint32_t* __restrict__ count, int parity, uint32_t k)
 {
     constexpr uint32_t SPB = SBLOCK / TPS;
-    constexpr bool NT = sizeof(R) == 8;
+    constexpr int CP = sizeof(R) == 8 ? 1 : 0;  // cache policy (gf_device.h)
     const uint32_t n = *count;
     const uint32_t t = blockIdx.x;
     if (t >= list[n].first) return;
@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(SBLOCK) k_pool_sweep(const SlotDev* __restrict
     } else {
         rule = Rule<R>{(R)sd.omega, R(1), 0u, 0u, 0u};
     }
-    site_update<R, TPS, MODE, TRACKG, NT>(field_of<R>(sd), sd.g, parity, h, r, rule, sd.gacc);
+    site_update<R, TPS, MODE, TRACKG, CP>(field_of<R>(sd), sd.g, parity, h, r, rule, sd.gacc);
 }
 
 template <typename R, bool WITH_G>

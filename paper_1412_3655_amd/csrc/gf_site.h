@@ -249,7 +249,7 @@ __device__ __forceinline__ void leaf_tree(const M3<R>* U, const bool* bwd, M3<R>
 // TRACKG (float32 mixed-precision bulk): also g(x) <- G g(x) for the float32
 // gauge transformation accumulated since the original links; lane r of the
 // group stores the chunks c with c % TPS == r.
-template <typename R, int TPS, int MODE, bool TRACKG, bool NT = false>
+template <typename R, int TPS, int MODE, bool TRACKG, int CP = 0>
 __device__ __forceinline__ void site_update(const LinkField<R>& f, const Geom& g, int parity, uint32_t h, int r,
                                             const Rule<R>& rule, const GField& gacc)
 {
@@ -269,7 +269,7 @@ __device__ __forceinline__ void site_update(const LinkField<R>& f, const Geom& g
         at[k] = bwd[k] ? back_h(g, h, s, mu_of[k]) : h;
     }
 #pragma unroll
-    for (int k = 0; k < NL; ++k) load_rows01<NT>(f, bwd[k] ? 1 - parity : parity, mu_of[k], at[k], U[k]);
+    for (int k = 0; k < NL; ++k) load_rows01<nt_loads(CP)>(f, bwd[k] ? 1 - parity : parity, mu_of[k], at[k], U[k]);
     // Row 2 is rebuilt from the two stored rows, so a departure d from unitarity
     // of those rows becomes up to ~2d after an update that mixes the rows.  Every
     // heat-bath update mixes them strongly (d would grow ~1.35x per sweep), so the
@@ -312,7 +312,7 @@ __device__ __forceinline__ void site_update(const LinkField<R>& f, const Geom& g
             right_mul_dag_rows01(G, U[k]);
         else
             left_mul_rows01(G, U[k]);
-        store_rows01<NT>(f, bwd[k] ? 1 - parity : parity, mu_of[k], at[k], U[k]);
+        store_rows01<nt_stores(CP)>(f, bwd[k] ? 1 - parity : parity, mu_of[k], at[k], U[k]);
     }
 
     if constexpr (TRACKG) {

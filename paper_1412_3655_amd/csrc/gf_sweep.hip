@@ -10,7 +10,7 @@ namespace gf {
 
 namespace {
 
-template <typename R, int TPS, int MODE, int BLOCK, bool TRACKG, bool NT>
+template <typename R, int TPS, int MODE, int BLOCK, bool TRACKG, int CP>
 __global__ void __launch_bounds__(BLOCK) k_or_half_sweep(LinkField<R> f, Geom g, int parity, Rule<R> rule,
                                                          GField gacc)
 {
@@ -19,7 +19,7 @@ __global__ void __launch_bounds__(BLOCK) k_or_half_sweep(LinkField<R> f, Geom g,
     const int r = (int)(gid % TPS);
     // whole groups of TPS lanes leave together, so every DPP partner is live
     if (h >= g.vh) return;
-    site_update<R, TPS, MODE, TRACKG, NT>(f, g, parity, h, r, rule, gacc);
+    site_update<R, TPS, MODE, TRACKG, CP>(f, g, parity, h, r, rule, gacc);
 }
 
 template <typename R, int TPS, int MODE, bool TRACKG>
@@ -30,32 +30,41 @@ hipError_t launch_tps(const LinkField<R>& f, const Geom& g, int parity, const Ru
     const uint64_t threads = (uint64_t)g.vh * TPS;
     const uint32_t grid = (uint32_t)((threads + block - 1) / block);
     if (grid == 0) return hipSuccess;
-#define GF_LAUNCH(B, NTV) \
-    hipLaunchKernelGGL((k_or_half_sweep<R, TPS, MODE, B, TRACKG, NTV>), dim3(grid), dim3(B), 0, st, f, g, parity, rule, gacc)
-    if (c.nt) {
+#define GF_LAUNCH(B, CPV) \
+    hipLaunchKernelGGL((k_or_half_sweep<R, TPS, MODE, B, TRACKG, CPV>), dim3(grid), dim3(B), 0, st, f, g, parity, rule, gacc)
+#define GF_LAUNCH_SMALL_BLOCKS(CPV)                  \
+    switch (block) {                                 \
+        case 64: GF_LAUNCH(64, CPV); break;          \
+        case 128: GF_LAUNCH(128, CPV); break;        \
+        case 256: GF_LAUNCH(256, CPV); break;        \
+        default: return hipErrorInvalidValue;        \
+    }
+    if (c.nt == 1 || c.nt == 2) {
         if constexpr (TPS <= 4) {
-            switch (block) {
-                case 64: GF_LAUNCH(64, true); break;
-                case 128: GF_LAUNCH(128, true); break;
-                case 256: GF_LAUNCH(256, true); break;
-                default: return hipErrorInvalidValue;
+            if (c.nt == 1) {
+                GF_LAUNCH_SMALL_BLOCKS(1)
+            } else {
+                GF_LAUNCH_SMALL_BLOCKS(2)
             }
         } else {
             return hipErrorInvalidValue;
         }
-    } else {
+    } else if (c.nt == 0) {
         switch (block) {
-            case 64: GF_LAUNCH(64, false); break;
-            case 128: GF_LAUNCH(128, false); break;
-            case 256: GF_LAUNCH(256, false); break;
+            case 64: GF_LAUNCH(64, 0); break;
+            case 128: GF_LAUNCH(128, 0); break;
+            case 256: GF_LAUNCH(256, 0); break;
             default:
                 if constexpr (TPS > 1)
-                    GF_LAUNCH(512, false);
+                    GF_LAUNCH(512, 0);
                 else
                     return hipErrorInvalidValue;
                 break;
         }
+    } else {
+        return hipErrorInvalidValue;
     }
+#undef GF_LAUNCH_SMALL_BLOCKS
 #undef GF_LAUNCH
     return hipGetLastError();
 }
@@ -78,7 +87,7 @@ bool sweep_config_valid(const SweepConfig& c)
 {
     const bool tps_ok = c.tps == 1 || c.tps == 2 || c.tps == 4 || c.tps == 8;
     const bool blk_ok = c.block == 64 || c.block == 128 || c.block == 256 || c.block == 512;
-    const bool nt_ok = c.nt == 0 || (c.nt == 1 && c.tps <= 4 && c.block <= 256);
+    const bool nt_ok = c.nt == 0 || ((c.nt == 1 || c.nt == 2) && c.tps <= 4 && c.block <= 256);
     // one lane per site needs more than the 256 registers a 512-thread block allows
     return tps_ok && blk_ok && nt_ok && !(c.tps == 1 && c.block == 512);
 }

@@ -92,7 +92,7 @@ extern "C" gf_status gf_autotune(gf_lattice L, gf_prec kernel, int32_t n_sweeps,
     if (e == hipSuccess && track) e = hipMemcpyAsync(gscratch, L->gacc.base, gbytes, hipMemcpyDeviceToDevice, L->stream);
     const GField g_none{nullptr, 0};
     const GField g_s{(float4*)gscratch, L->geom.ld};
-    for (int nt : {0, 1})
+    for (int nt : {0, 1, 2})
     for (int tps : {1, 2, 4, 8}) {
         for (int block : {64, 128, 256, 512}) {
             const SweepConfig c{tps, block, nt};

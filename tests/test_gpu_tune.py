@@ -34,8 +34,10 @@ def test_autotune(prec, tmp_path):
         before = lat.get_links()
         chosen, table = lat.autotune(n_sweeps=2, cache_path=cache)
         assert np.array_equal(lat.get_links(), before)
-        # plain: 4 lane splits x 4 block sizes minus (1 lane, 512); non-temporal: 3 x 3
-        assert len(table) == 15 + 9
+        # plain: 4 lane splits x 4 block sizes minus (1 lane, 512); each of the two
+        # non-temporal policies: 3 lane splits (1, 2, 4) x 3 block sizes (64, 128, 256)
+        assert len(table) == 15 + 9 + 9
+        assert {e[2] for e in table} == {0, 1, 2}
         assert chosen == min(table, key=lambda e: e[3])[:3]
         assert all(e[3] > 0 for e in table)
         chosen2, table2 = lat.autotune(n_sweeps=2, cache_path=cache)
