@@ -137,19 +137,31 @@ def fix_until_leg(gf, torch, stream, links, dims, args):
 
 
 def pool_tps(gf, gi, stream):
-    """Lanes per site for the pool's float32 / float64 kernels: the autotuner's pick on a
-    16^4 lattice among the shapes the pool uses (128-thread blocks; non-temporal accesses
-    for float64, plain for float32)."""
+    """Lanes per site of the pool's float32 / float64 sweeps (128-thread blocks): each candidate
+    timed on the pool's own kernels, 20 sweeps of eight lattices of the batched shapes (uploads and
+    first measurements outside the timed steps)."""
+    import torch
+
+    shapes = [(12, 12, 12, 12), (16, 16, 16, 16), (16, 16, 16, 32), (24, 24, 24, 48)] * 2
+    links = [gi.gen_links(d, 0.7, 700 + i) for i, d in enumerate(shapes)]
+    fix = dict(omega=1.7, mode=0, theta_target=0.0, max_sweeps=20, reunit_every=0, theta_switch=0.0)
     best = {}
-    u = gi.gen_links((16, 16, 16, 16), 0.7, 7)
-    for prec in (gf.GF_FP32, gf.GF_FP64):
-        with gf.Lattice((16, 16, 16, 16), prec, stream=stream) as lat:
-            lat.set_links(u)
-            _, table = lat.autotune(prec, n_sweeps=5)
-            nt = 1 if prec == gf.GF_FP64 else 0
-            t = min((e for e in table if e[1] == 128 and e[2] == nt), key=lambda e: e[3])
-            best[prec] = t[0]
-    return best[gf.GF_FP32], best[gf.GF_FP64]
+    for prec, key in ((gf.GF_MIXED, "tps32"), (gf.GF_FP64, "tps64")):
+        times = {}
+        for tps in (1, 2, 4):
+            with gf.Pool(1 << 36, len(shapes), prec=prec, check_every=10, **{key: tps}) as pool:
+                for i, (d, u) in enumerate(zip(shapes, links)):
+                    assert pool.admit(i, d, u, **fix)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                done = 0
+                while done < len(shapes):
+                    pool.step()
+                    done += len(pool.poll())
+                times[tps] = time.perf_counter() - t0
+        best[key] = min(times, key=times.get)
+        log(f"pool {key}: " + ", ".join(f"{t}: {1e3 * v:.1f} ms" for t, v in times.items()))
+    return best["tps32"], best["tps64"]
 
 
 def batched_leg(gf, gi, stream, args):
