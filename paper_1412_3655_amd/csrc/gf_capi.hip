@@ -345,8 +345,9 @@ gf_status gf_set_sweep_config(gf_lattice L, gf_prec kernel, int32_t tps, int32_t
     if (kernel != GF_FP64 && kernel != GF_FP32) return fail(GF_E_ARG, "kernel precision must be GF_FP64 or GF_FP32");
     SweepConfig c{tps, block, nontemporal};
     if (!gf::sweep_config_valid(c))
-        return fail(GF_E_ARG, "sweep config tps=%d block=%d nt=%d: tps must be 1, 2, 4 or 8, block 64, 128, 256 or "
-                              "512 (not 512 with tps 1), non-temporal only with tps <= 4 and block <= 256",
+        return fail(GF_E_ARG,
+                    "sweep config tps=%d block=%d policy=%d: tps must be 1, 2, 4 or 8, block 64, 128, 256 or 512 "
+                    "(not 512 with tps 1), cache policy 0, 1 or 2 (1 and 2 only with tps <= 4 and block <= 256)",
                     tps, block, nontemporal);
     if (kernel == GF_FP32)
         L->cfg32 = c;

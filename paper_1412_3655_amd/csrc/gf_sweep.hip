@@ -2,7 +2,8 @@
 // (overrelaxation and heat bath, Sec. 2 and the abstract of arXiv:1412.3655)
 // for gfx950.  The per-site body lives in gf_site.h.  The loop over sites is
 // over the half index of one colour: every link is read once and written once
-// per half-sweep (768 B per site update in FP64 with 12-real links).
+// per half-sweep (per site update in FP64 with 12-real links: 768 B read and
+// 768 B written).
 #include "gf_kernels.h"
 #include "gf_site.h"
 

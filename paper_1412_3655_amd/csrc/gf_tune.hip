@@ -2,8 +2,9 @@
 // gf_autotune).  The paper's cuLGT2 picks 4 or 8 threads per site, register
 // limits and texture loads by trying them at run time (Sec. 4 and 5); here the
 // axes are lanes per site (1, 2, 4, 8), threads per block (64..512) and the
-// cache policy of the link accesses (plain / non-temporal), timed
-// with HIP events on a scratch copy of the links so the lattice is unchanged.
+// cache policy of the link accesses (plain / non-temporal / non-temporal
+// stores only), timed with HIP events on a scratch copy of the links so the
+// lattice is unchanged.
 // Every configuration gives bitwise the same links, so only time decides.
 #include <cstdio>
 #include <cstring>
