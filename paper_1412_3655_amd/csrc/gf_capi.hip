@@ -278,7 +278,7 @@ gf_status gf_create_lattice(const int32_t dims[4], gf_prec prec, void* hip_strea
     for (int m = 0; m < 4; ++m) g.n[m] = dims[m];
     g.hx = dims[0] / 2;
     g.vh = (uint32_t)(V / 2);
-    g.ld = (g.vh + 63u) & ~63u;
+    g.ld = (g.vh + gf::kLinkTile - 1) / gf::kLinkTile * gf::kLinkTile;  // whole tiles of the link layout
     g.hs1 = (uint32_t)g.hx;
     g.hs2 = (uint32_t)g.hx * (uint32_t)dims[1];
     g.hs3 = g.hs2 * (uint32_t)dims[2];

@@ -7,12 +7,18 @@
 //   site of colour p has the half index h = lex >> 1, lex = x + Nx*(y + ...),
 //   so both colours number their sites 0..V/2-1 and the half index of
 //   (x, y, z, t) is (x>>1) + Nx/2*(y + Ny*(z + Nz*t)).
-//   Links are stored as 16-byte chunks, chunk c of the link U_mu of the site
-//   (p, h) at  base[((p*4 + mu)*NC + c)*ld + h],  ld = V/2 rounded up to 64.
+//   Links are stored as 16-byte chunks in tiles of T = 64 sites: chunk c of
+//   the link U_mu of the site (p, h) at
+//     base[(((p*4 + mu)*(ld/T) + h/T)*NC + c)*T + h%T],
+//   ld = V/2 rounded up to 64.  A tile holds the NC chunk runs of 64
+//   consecutive sites of one colour and direction back to back (6 KiB in
+//   FP64), so a wavefront's loads of one link fall in one contiguous region
+//   instead of NC regions ld apart.
 //   FP64: NC = 6 chunks of double2 = (re, im) of u00 u01 u02 u10 u11 u12.
 //   FP32: NC = 3 chunks of float4  = (u00 u01), (u02 u10), (u11 u12).
-//   Consecutive sites of one colour are consecutive 16-byte words, so a
-//   wavefront reads each chunk of its forward links as one contiguous run.
+//   Consecutive sites of one colour are consecutive 16-byte words within a
+//   chunk run, so a wavefront reads each chunk of its forward links as one
+//   contiguous run.
 //   Row 2 is never stored; it is rebuilt as conj(row0 x row1).
 //   A backward link U_mu(x - mu^) lives in the other colour at half index
 //   h - stride_mu/2 for mu = y, z, t (wrapping), and at h or h-1 for mu = x:
@@ -138,10 +144,13 @@ struct M3 {
     R im[3][3];
 };
 
+constexpr uint32_t kLinkTile = 64;  // sites per tile of the link layout; ld is a multiple of it
+
 template <typename R>
 __device__ __forceinline__ size_t chunk_index(const LinkField<R>& f, int parity, int mu, int c, uint32_t h)
 {
-    return ((size_t)((parity * 4 + mu) * ChunkOf<R>::N + c)) * f.ld + h;
+    const size_t tile = (size_t)(parity * 4 + mu) * (f.ld / kLinkTile) + h / kLinkTile;
+    return (tile * ChunkOf<R>::N + c) * kLinkTile + h % kLinkTile;
 }
 
 // 16-byte chunk access; NT = non-temporal (streaming) access.
