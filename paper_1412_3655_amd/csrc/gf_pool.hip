@@ -76,6 +76,51 @@ __device__ __forceinline__ uint32_t find_entry(const Entry* e, uint32_t n, uint3
     return lo;
 }
 
+// The entry of tile t found by one wave in one round of independent loads:
+// every lane reads a strided share of the segment's `stride` entries while
+// the count is read, and the wave counts the entries j < n with
+// first <= t (first is a prefix sum from 0, so that count minus one is the
+// entry).  A binary search would chain log2(n) dependent loads before the
+// block could issue its first link load.  Lists of up to 64 * kWaveEntries
+// entries; *slot and *first receive the entry's fields (false: empty list).
+constexpr uint32_t kWaveEntries = 8;
+
+__device__ __forceinline__ bool find_entry_wave(const Entry* e, const uint32_t* count, uint32_t stride, uint32_t t,
+                                                uint32_t* slot, uint32_t* first)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t fs[kWaveEntries], ss[kWaveEntries];
+#pragma unroll
+    for (uint32_t q = 0; q < kWaveEntries; ++q) {
+        const uint32_t j = lane + 64u * q;
+        fs[q] = 0xFFFFFFFFu;
+        ss[q] = 0u;
+        if (j < stride) {
+            fs[q] = e[j].first;
+            ss[q] = e[j].slot;
+        }
+    }
+    const uint32_t n = *count;
+    uint32_t cnt = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < kWaveEntries; ++q) {
+        const uint32_t j = lane + 64u * q;
+        cnt += (uint32_t)__popcll(__ballot(j < n && fs[q] <= t));
+    }
+    if (cnt == 0u) return false;  // empty list (never launched)
+    const uint32_t i = cnt - 1u;
+    uint32_t my_slot = 0u, my_first = 0u;
+#pragma unroll
+    for (uint32_t q = 0; q < kWaveEntries; ++q)
+        if (q == i / 64u) {
+            my_slot = ss[q];
+            my_first = fs[q];
+        }
+    *slot = (uint32_t)__shfl((int)my_slot, (int)(i % 64u), 64);
+    *first = (uint32_t)__shfl((int)my_first, (int)(i % 64u), 64);
+    return true;
+}
+
 template <typename R>
 __device__ __forceinline__ LinkField<R> field_of(const SlotDev& sd);
 template <>
@@ -98,21 +143,30 @@ __device__ __forceinline__ double schedule_T(const SlotDev& sd, uint32_t s)
 // float64 links use non-temporal accesses, float32 ones plain accesses (the
 // autotuner's choice for either on MI355X: a float32 lattice can stay in the
 // Infinity Cache, a float64 one streams).
-// Block t sweeps tile t of the list (the host launches one block per tile;
-// blocks past the tile total leave).
+// Block t sweeps tile t of the list (the host launches one block per tile of
+// the list; a block past the tile total lands past the last lattice's sites
+// and leaves).  stride = entries per list segment.
 template <typename R, int TPS, int MODE, bool TRACKG>
 __global__ void __launch_bounds__(SBLOCK) k_pool_sweep(const SlotDev* __restrict__ slots,
                                                        const Entry* __restrict__ list,
-                                                       const uint32_t* __restrict__ count, int parity, uint32_t k)
+                                                       const uint32_t* __restrict__ count, uint32_t stride,
+                                                       int parity, uint32_t k)
 {
     constexpr uint32_t SPB = SBLOCK / TPS;
     constexpr int CP = sizeof(R) == 8 ? 1 : 0;  // cache policy (gf_device.h)
-    const uint32_t n = *count;
     const uint32_t t = blockIdx.x;
-    if (t >= list[n].first) return;
-    const uint32_t i = find_entry(list, n, t);
-    const SlotDev sd = slots[list[i].slot];
-    const uint32_t h = (t - list[i].first) * SPB + threadIdx.x / TPS;
+    uint32_t slot, first;
+    if (stride <= 64u * kWaveEntries) {
+        if (!find_entry_wave(list, count, stride, t, &slot, &first)) return;
+    } else {
+        const uint32_t n = *count;
+        if (t >= list[n].first) return;
+        const uint32_t i = find_entry(list, n, t);
+        slot = list[i].slot;
+        first = list[i].first;
+    }
+    const SlotDev sd = slots[slot];
+    const uint32_t h = (t - first) * SPB + threadIdx.x / TPS;
     const int r = (int)(threadIdx.x % TPS);
     if (h >= sd.g.vh) return;  // whole TPS groups leave together
     Rule<R> rule;
@@ -328,22 +382,23 @@ hipError_t launch_sweep_kind(gf_pool P, int tps, uint32_t tiles, const Entry* li
                              uint32_t k)
 {
     const dim3 grid(tiles), block(SBLOCK);
+    const uint32_t stride = (uint32_t)P->list_stride;
     switch (tps) {
         case 1:
             hipLaunchKernelGGL((k_pool_sweep<R, 1, MODE, TRACKG>), grid, block, 0, P->stream, P->slots_dev, list, count,
-                               parity, k);
+                               stride, parity, k);
             break;
         case 2:
             hipLaunchKernelGGL((k_pool_sweep<R, 2, MODE, TRACKG>), grid, block, 0, P->stream, P->slots_dev, list, count,
-                               parity, k);
+                               stride, parity, k);
             break;
         case 8:
             hipLaunchKernelGGL((k_pool_sweep<R, 8, MODE, TRACKG>), grid, block, 0, P->stream, P->slots_dev, list, count,
-                               parity, k);
+                               stride, parity, k);
             break;
         default:
             hipLaunchKernelGGL((k_pool_sweep<R, 4, MODE, TRACKG>), grid, block, 0, P->stream, P->slots_dev, list, count,
-                               parity, k);
+                               stride, parity, k);
             break;
     }
     return hipGetLastError();
