@@ -343,8 +343,8 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported (the method's "
-              "multi-GPU decomposition is a design note, not part of this build)", file=sys.stderr)
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported (the decomposition of "
+              "a lattice over several GPUs is described in the design notes, not implemented)", file=sys.stderr)
         return 2
 
     import torch

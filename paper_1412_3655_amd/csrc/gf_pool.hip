@@ -76,7 +76,7 @@ __device__ __forceinline__ uint32_t find_entry(const Entry* e, uint32_t n, uint3
     return lo;
 }
 
-// The entry of tile t found by one wave in one round of independent loads:
+// The entry of tile t found by one wave in one pass of independent loads:
 // every lane reads a strided share of the segment's `stride` entries while
 // the count is read, and the wave counts the entries j < n with
 // first <= t (first is a prefix sum from 0, so that count minus one is the

@@ -64,3 +64,16 @@ def test_version_and_argument_checks_without_device():
         assert fn(*args) == gf.GF_E_ARG
     assert "null" in gf.gf_last_error()
     assert gf.lib().gf_destroy_lattice(None) == gf.GF_OK
+
+
+def test_bench_rejects_several_gpus():
+    """bench.py measures one GPU: --gpus above 1 exits with status 2 and a message, before any
+    device work."""
+    import subprocess
+    import sys
+
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout == ""
