@@ -254,3 +254,27 @@ def test_pool_full_size_batched_shapes():
             r, links = solo_res[i]
             assert done[i]["result"] == r
             assert np.array_equal(pool.fetch_links(i), links)
+
+
+def test_pool_large_slot_table_uses_the_search_fallback():
+    """A pool of more than 511 slots (work-list segments longer than one wave's strided read)
+    finds tiles by binary search; its jobs still equal their solo runs."""
+    say("pool with 600 slots")
+    ce = 5
+    jobs = [((6, 4, 4, 8), 0.6, 41), ((4, 4, 4, 4), 0.5, 42), ((8, 8, 8, 8), 0.7, 43)]
+    inputs = [gi.gen_links(d, e, s) for (d, e, s) in jobs]
+    ref = [solo(d, u, gf.GF_MIXED, 0, 0, ce) for (d, e, s), u in zip(jobs, inputs)]
+    kw = {k: v for k, v in fix_kw(ce).items() if k not in ("check_every", "mode")}
+    with gf.Pool(1 << 34, 600, prec=gf.GF_MIXED, check_every=ce) as pool:
+        for i, ((d, e, s), u) in enumerate(zip(jobs, inputs)):
+            assert pool.admit(i, d, u, **kw)
+        done = {}
+        for _ in range(2000):
+            pool.step()
+            for d in pool.poll():
+                done[d["job_id"]] = d
+            if len(done) == len(jobs):
+                break
+        for i in range(len(jobs)):
+            assert done[i]["result"] == ref[i][0]
+            assert np.array_equal(pool.fetch_links(i), ref[i][1])
