@@ -257,6 +257,8 @@ def fullsize_leg(gf, gi, torch, stream, args):
         for kernel, name in ((gf.GF_FP32, "f32"), (gf.GF_FP64, "f64")):
             chosen, _ = lat.autotune(kernel, n_sweeps=3)
             cfg[name] = list(chosen)
+        chosen, _ = lat.autotune_anneal(gf.GF_FP32, n_sweeps=2)
+        cfg["hb_f32"] = list(chosen)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         lat.anneal(2000, 1.25, 0.01, 0)
@@ -268,7 +270,7 @@ def fullsize_leg(gf, gi, torch, stream, args):
         t_fix = time.perf_counter() - t0
         P1 = lat.plaquette()
     out.update({
-        "tuned_f32": cfg["f32"], "tuned_f64": cfg["f64"],
+        "tuned_f32": cfg["f32"], "tuned_f64": cfg["f64"], "tuned_heat_bath_f32": cfg["hb_f32"],
         "anneal_seconds": t_anneal, "anneal_site_updates_per_s": 2000 * V / t_anneal,
         "after_anneal": {"theta": th_a, "F": F_a},
         "fix_seconds": t_fix, "converged": r.converged, "sweeps": r.sweeps, "sweeps_fp32": r.sweeps_fp32,

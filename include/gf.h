@@ -105,6 +105,11 @@ gf_status gf_lattice_info(gf_lattice lat, int64_t* volume, int64_t* device_bytes
  * Every valid choice gives bitwise the same links.  Default 4 / 256 / 0. */
 gf_status gf_set_sweep_config(gf_lattice lat, gf_prec kernel, int32_t tps, int32_t block, int32_t nontemporal);
 
+/* The same for the heat-bath sweeps of gf_anneal, which sample every
+ * subgroup element in each lane of a site's group (so fewer lanes do less
+ * arithmetic).  Default 1 / 256 / 0 for float32, 1 / 128 / 2 for float64. */
+gf_status gf_set_anneal_config(gf_lattice lat, gf_prec kernel, int32_t tps, int32_t block, int32_t nontemporal);
+
 /* GF_MIXED: leave the float32 phase now.  The float64 links become
  * g(x) U0_mu(x) g(x+mu^)^dag, U0 the links given to gf_set_links and g the
  * float32 transformation accumulated by the float32 sweeps (re-orthonormalised
@@ -132,6 +137,12 @@ typedef struct {
  * not changed.  Syncs. */
 gf_status gf_autotune(gf_lattice lat, gf_prec kernel, int32_t n_sweeps, const char* cache_path, gf_tune_entry* table,
                       int32_t cap, int32_t* n_out, gf_tune_entry* chosen);
+
+/* As gf_autotune for the heat-bath sweep of gf_anneal (timed at T = 1 on the
+ * scratch copy; cache lines keyed with an "-hb" suffix); sets the
+ * configuration gf_set_anneal_config sets.  Syncs. */
+gf_status gf_autotune_anneal(gf_lattice lat, gf_prec kernel, int32_t n_sweeps, const char* cache_path,
+                             gf_tune_entry* table, int32_t cap, int32_t* n_out, gf_tune_entry* chosen);
 
 /* Upload links from a host canonical array of 4*V*18 doubles; only rows 0
  * and 1 of each link are kept (row 2 is rebuilt as the conjugated cross

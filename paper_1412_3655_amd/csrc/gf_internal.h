@@ -28,8 +28,10 @@ struct gf_lattice_ {
     double* hres = nullptr;                 // pinned host copy of dres
     bool has_links = false;
     uint32_t anneal_sweeps = 0;             // heat-bath sweep counter (Philox counter word)
-    gf::SweepConfig cfg64;
+    gf::SweepConfig cfg64;     // overrelaxation sweeps
     gf::SweepConfig cfg32;
+    gf::SweepConfig cfg_hb64;  // heat-bath sweeps (gf_anneal)
+    gf::SweepConfig cfg_hb32;
     // hipGraphs of n back-to-back sweeps, keyed by (n, omega, mode, precision
     // and g tracking, tps, block, cache policy); only on a non-default stream
     std::map<std::tuple<int32_t, double, int, int, int, int, int>, hipGraphExec_t> sweep_graphs;

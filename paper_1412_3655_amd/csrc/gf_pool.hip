@@ -39,6 +39,7 @@ namespace pool {
 
 constexpr int PBLOCK = 256;  // threads per block of the reunitarisation / measurement kernels
 constexpr int SBLOCK = 128;  // threads per block of the sweep kernels (the tuned solo shape on MI355X)
+constexpr int kHeatBathTps = 1;  // lanes per site of the heat-bath sweeps (its sampling is per lane)
 
 struct SlotDev {
     LinkField<double> f64;
@@ -420,8 +421,9 @@ hipError_t launch_kind(gf_pool P, int k, int kind, int parity)
     const int t32 = P->cfg.tps32, t64 = P->cfg.tps64;
     P->launch_log.push_back(sgi);
     switch (kind) {
-        case K_HB32: return launch_sweep_kind<float, HEATBATH, true>(P, t32, tiles, list, count, parity, kk);
-        case K_HB64: return launch_sweep_kind<double, HEATBATH, false>(P, t64, tiles, list, count, parity, kk);
+        case K_HB32: return launch_sweep_kind<float, HEATBATH, true>(P, kHeatBathTps, tiles, list, count, parity, kk);
+        case K_HB64:
+            return launch_sweep_kind<double, HEATBATH, false>(P, kHeatBathTps, tiles, list, count, parity, kk);
         case K_OR32:
             return mode == GF_OR_EXACT ? launch_sweep_kind<float, 0, true>(P, t32, tiles, list, count, parity, kk)
                                        : launch_sweep_kind<float, 1, true>(P, t32, tiles, list, count, parity, kk);
@@ -813,7 +815,7 @@ gf_status gf_pool_step(gf_pool P)
         Entry* e = seg(P, P->lists_pin, k, kind);
         e[n_entries[sgi]] = Entry{(uint32_t)slot, n_tiles[sgi]};
         n_entries[sgi]++;
-        const int tps = (kind == K_HB32 || kind == K_OR32) ? P->cfg.tps32 : P->cfg.tps64;
+        const int tps = kind == K_OR32 ? P->cfg.tps32 : kind == K_OR64 ? P->cfg.tps64 : kHeatBathTps;
         n_tiles[sgi] += tiles_of(g, kind, tps);
     };
     bool any = false;

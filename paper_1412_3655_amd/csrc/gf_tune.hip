@@ -53,22 +53,25 @@ bool cache_lookup(const char* path, const std::string& key, SweepConfig* out)
     return found;
 }
 
-}  // namespace
-
-extern "C" gf_status gf_autotune(gf_lattice L, gf_prec kernel, int32_t n_sweeps, const char* cache_path,
-                                 gf_tune_entry* table, int32_t cap, int32_t* n_out, gf_tune_entry* chosen)
+// Time every valid configuration of the overrelaxation sweep (heat_bath =
+// false) or of the heat-bath sweep (true, at T = 1) of precision `kernel` on a
+// scratch copy of the links, apply the fastest to the lattice and append it to
+// the cache; shared by gf_autotune and gf_autotune_anneal.
+gf_status tune(gf_lattice L, gf_prec kernel, bool heat_bath, int32_t n_sweeps, const char* cache_path,
+               gf_tune_entry* table, int32_t cap, int32_t* n_out, gf_tune_entry* chosen)
 {
-    TraceRange range("gf_autotune");
     GF_TRY(check_ready(L));
     if (kernel != GF_FP64 && kernel != GF_FP32) return fail(GF_E_ARG, "kernel precision must be GF_FP64 or GF_FP32");
     if ((kernel == GF_FP64 && !L->f64) || (kernel == GF_FP32 && !L->f32))
         return fail(GF_E_ARG, "the lattice has no links of that precision");
     if (n_sweeps < 1 || cap < 0 || (cap > 0 && !table)) return fail(GF_E_ARG, "bad arguments");
     if (n_out) *n_out = 0;
-    const std::string key = cache_key(L, kernel);
+    SweepConfig& target = heat_bath ? (kernel == GF_FP32 ? L->cfg_hb32 : L->cfg_hb64)
+                                    : (kernel == GF_FP32 ? L->cfg32 : L->cfg64);
+    const std::string key = cache_key(L, kernel) + (heat_bath ? "-hb" : "");
     SweepConfig best{};
     if (cache_path && cache_lookup(cache_path, key, &best)) {
-        (kernel == GF_FP32 ? L->cfg32 : L->cfg64) = best;
+        target = best;
         if (chosen) *chosen = gf_tune_entry{best.tps, best.block, best.nt, 0.0};
         return GF_OK;
     }
@@ -93,6 +96,9 @@ extern "C" gf_status gf_autotune(gf_lattice L, gf_prec kernel, int32_t n_sweeps,
     if (e == hipSuccess && track) e = hipMemcpyAsync(gscratch, L->gacc.base, gbytes, hipMemcpyDeviceToDevice, L->stream);
     const GField g_none{nullptr, 0};
     const GField g_s{(float4*)gscratch, L->geom.ld};
+    const LinkField<float> f32{(float4*)scratch, L->geom.ld};
+    const LinkField<double> f64{(double2*)scratch, L->geom.ld};
+    uint32_t hb_sweep = 0;
     for (int nt : {0, 1, 2})
     for (int tps : {1, 2, 4, 8}) {
         for (int block : {64, 128, 256, 512}) {
@@ -101,14 +107,19 @@ extern "C" gf_status gf_autotune(gf_lattice L, gf_prec kernel, int32_t n_sweeps,
             auto sweep = [&]() -> hipError_t {
                 for (int p = 0; p < 2; ++p) {
                     hipError_t r;
-                    if (kernel == GF_FP32)
-                        r = launch_or_half_sweep(LinkField<float>{(float4*)scratch, L->geom.ld}, L->geom, p, 1.7f,
-                                                 GF_OR_EXACT, c, track ? g_s : g_none, L->stream);
+                    if (heat_bath && kernel == GF_FP32)
+                        r = launch_hb_half_sweep(f32, L->geom, p, 1.0f, 1u, hb_sweep, c, track ? g_s : g_none,
+                                                 L->stream);
+                    else if (heat_bath)
+                        r = launch_hb_half_sweep(f64, L->geom, p, 1.0, 1u, hb_sweep, c, L->stream);
+                    else if (kernel == GF_FP32)
+                        r = launch_or_half_sweep(f32, L->geom, p, 1.7f, GF_OR_EXACT, c, track ? g_s : g_none,
+                                                 L->stream);
                     else
-                        r = launch_or_half_sweep(LinkField<double>{(double2*)scratch, L->geom.ld}, L->geom, p, 1.7,
-                                                 GF_OR_EXACT, c, L->stream);
+                        r = launch_or_half_sweep(f64, L->geom, p, 1.7, GF_OR_EXACT, c, L->stream);
                     if (r != hipSuccess) return r;
                 }
+                ++hb_sweep;
                 return hipSuccess;
             };
             e = sweep();
@@ -135,7 +146,7 @@ extern "C" gf_status gf_autotune(gf_lattice L, gf_prec kernel, int32_t n_sweeps,
     if (scratch) (void)hipFree(scratch);
     if (gscratch) (void)hipFree(gscratch);
     if (st != GF_OK) return st;
-    (kernel == GF_FP32 ? L->cfg32 : L->cfg64) = best;
+    target = best;
     if (n_out) *n_out = std::min(n, cap);
     if (chosen) *chosen = gf_tune_entry{best.tps, best.block, best.nt, best_us};
     if (cache_path) {
@@ -146,4 +157,20 @@ extern "C" gf_status gf_autotune(gf_lattice L, gf_prec kernel, int32_t n_sweeps,
         }
     }
     return GF_OK;
+}
+
+}  // namespace
+
+extern "C" gf_status gf_autotune(gf_lattice L, gf_prec kernel, int32_t n_sweeps, const char* cache_path,
+                                 gf_tune_entry* table, int32_t cap, int32_t* n_out, gf_tune_entry* chosen)
+{
+    TraceRange range("gf_autotune");
+    return tune(L, kernel, false, n_sweeps, cache_path, table, cap, n_out, chosen);
+}
+
+extern "C" gf_status gf_autotune_anneal(gf_lattice L, gf_prec kernel, int32_t n_sweeps, const char* cache_path,
+                                        gf_tune_entry* table, int32_t cap, int32_t* n_out, gf_tune_entry* chosen)
+{
+    TraceRange range("gf_autotune_anneal");
+    return tune(L, kernel, true, n_sweeps, cache_path, table, cap, n_out, chosen);
 }

@@ -116,7 +116,10 @@ _SIGNATURES = {
     "gf_destroy_lattice": [_vp],
     "gf_lattice_info": [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
     "gf_set_sweep_config": [_vp, ctypes.c_int, _i32, _i32, _i32],
+    "gf_set_anneal_config": [_vp, ctypes.c_int, _i32, _i32, _i32],
     "gf_promote_fp64": [_vp],
+    "gf_autotune_anneal": [_vp, ctypes.c_int, _i32, ctypes.c_char_p, ctypes.POINTER(gf_tune_entry), _i32,
+                           ctypes.POINTER(_i32), ctypes.POINTER(gf_tune_entry)],
     "gf_autotune": [_vp, ctypes.c_int, _i32, ctypes.c_char_p, ctypes.POINTER(gf_tune_entry), _i32,
                     ctypes.POINTER(_i32), ctypes.POINTER(gf_tune_entry)],
     "gf_set_links": [_vp, _dp],
@@ -258,17 +261,30 @@ def gf_set_sweep_config(lat, kernel: int, tps: int, block: int, nontemporal: int
     _call("gf_set_sweep_config", lat, int(kernel), int(tps), int(block), int(nontemporal))
 
 
-def gf_autotune(lat, kernel: int, n_sweeps: int = 5, cache_path=None):
-    """Returns (chosen, table): chosen = (tps, block, nontemporal), table = list of
-    (tps, block, nontemporal, us_per_sweep) (empty when the cache answered)."""
+def gf_set_anneal_config(lat, kernel: int, tps: int, block: int, nontemporal: int = 0) -> None:
+    _call("gf_set_anneal_config", lat, int(kernel), int(tps), int(block), int(nontemporal))
+
+
+def _tune(name, lat, kernel, n_sweeps, cache_path):
     cap = 64
     buf = (gf_tune_entry * cap)()
     n = _i32()
     ch = gf_tune_entry()
     cp = None if cache_path is None else os.fsencode(cache_path)
-    _call("gf_autotune", lat, int(kernel), int(n_sweeps), cp, buf, cap, ctypes.byref(n), ctypes.byref(ch))
+    _call(name, lat, int(kernel), int(n_sweeps), cp, buf, cap, ctypes.byref(n), ctypes.byref(ch))
     table = [(buf[i].tps, buf[i].block, buf[i].nontemporal, buf[i].us_per_sweep) for i in range(n.value)]
     return (ch.tps, ch.block, ch.nontemporal), table
+
+
+def gf_autotune(lat, kernel: int, n_sweeps: int = 5, cache_path=None):
+    """Returns (chosen, table): chosen = (tps, block, nontemporal), table = list of
+    (tps, block, nontemporal, us_per_sweep) (empty when the cache answered)."""
+    return _tune("gf_autotune", lat, kernel, n_sweeps, cache_path)
+
+
+def gf_autotune_anneal(lat, kernel: int, n_sweeps: int = 5, cache_path=None):
+    """As gf_autotune, for the heat-bath sweep of gf_anneal."""
+    return _tune("gf_autotune_anneal", lat, kernel, n_sweeps, cache_path)
 
 
 def gf_promote_fp64(lat) -> None:
@@ -428,6 +444,16 @@ class Lattice:
     def autotune(self, kernel=None, n_sweeps: int = 5, cache_path=None):
         k = kernel if kernel is not None else (GF_FP32 if self.prec != GF_FP64 else GF_FP64)
         return gf_autotune(self.handle, k, n_sweeps, cache_path)
+
+    def set_anneal_config(self, tps: int, block: int, nontemporal: int = 0, kernel=None):
+        kinds = [kernel] if kernel is not None else (
+            [GF_FP32, GF_FP64] if self.prec == GF_MIXED else [self.prec])
+        for k in kinds:
+            gf_set_anneal_config(self.handle, k, tps, block, nontemporal)
+
+    def autotune_anneal(self, kernel=None, n_sweeps: int = 5, cache_path=None):
+        k = kernel if kernel is not None else (GF_FP32 if self.prec != GF_FP64 else GF_FP64)
+        return gf_autotune_anneal(self.handle, k, n_sweeps, cache_path)
 
 
 # ----------------------------------------------------------------- pool --

@@ -36,9 +36,9 @@ def _device():
     gf.lib()
 
 
-def gpu_anneal(dims, u, calls, prec=gf.GF_FP64, tps=4):
+def gpu_anneal(dims, u, calls, prec=gf.GF_FP64, tps=4, block=256, cp=0):
     with gf.Lattice(dims, prec) as lat:
-        lat.set_sweep_config(tps, 256)
+        lat.set_anneal_config(tps, block, cp)
         lat.set_links(u)
         for (n, T0, T1, seed) in calls:
             lat.anneal(n, T0, T1, seed)
@@ -64,9 +64,9 @@ def test_anneal_bitwise_across_tps_and_resume():
     say("anneal bitwise across tps, resume")
     u = gi.gen_links(RAGGED, 1.0, 12)
     base, _ = gpu_anneal(RAGGED, u, [(4, 0.8, 0.8, 7)], tps=4)
-    for tps in (1, 2, 8):
-        got, _ = gpu_anneal(RAGGED, u, [(4, 0.8, 0.8, 7)], tps=tps)
-        assert np.array_equal(got, base), tps
+    for tps, block, cp in ((1, 256, 0), (2, 256, 0), (8, 256, 0), (1, 128, 2), (2, 64, 1), (1, 64, 2)):
+        got, _ = gpu_anneal(RAGGED, u, [(4, 0.8, 0.8, 7)], tps=tps, block=block, cp=cp)
+        assert np.array_equal(got, base), (tps, block, cp)
     # the sweep counter continues across calls: 2 + 2 sweeps == 4 sweeps at constant T
     split, _ = gpu_anneal(RAGGED, u, [(2, 0.8, 0.8, 7), (2, 0.8, 0.8, 7)])
     assert np.array_equal(split, base)

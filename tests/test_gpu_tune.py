@@ -49,3 +49,29 @@ def test_autotune(prec, tmp_path):
         lat.sweep(2, 1.7)
         assert np.array_equal(lat.get_links(), tuned)
     assert len(open(cache).read().strip().splitlines()) == 1
+
+
+@pytest.mark.parametrize("prec", [gf.GF_FP64, gf.GF_MIXED])
+def test_autotune_anneal(prec, tmp_path):
+    """The heat-bath tuner times every shape on a scratch copy (links unchanged), applies the
+    fastest to gf_anneal only, answers from its cache the second time, and the anneal it
+    configures gives bitwise the links of the default configuration."""
+    print(f"autotune anneal prec={prec}", flush=True)
+    dims = (8, 8, 8, 12)
+    u = gi.gen_links(dims, 0.7, 4)
+    cache = os.path.join(str(tmp_path), "tune.txt")
+    with gf.Lattice(dims, prec) as lat:
+        lat.set_links(u)
+        lat.anneal(3, 1.25, 0.5, 9)
+        default = lat.get_links()
+    with gf.Lattice(dims, prec) as lat:
+        lat.set_links(u)
+        before = lat.get_links()
+        chosen, table = lat.autotune_anneal(n_sweeps=2, cache_path=cache)
+        assert np.array_equal(lat.get_links(), before)
+        assert len(table) == 15 + 9 + 9
+        assert chosen == min(table, key=lambda e: e[3])[:3]
+        chosen2, table2 = lat.autotune_anneal(n_sweeps=2, cache_path=cache)
+        assert chosen2 == chosen and table2 == []
+        lat.anneal(3, 1.25, 0.5, 9)
+        assert np.array_equal(lat.get_links(), default)
