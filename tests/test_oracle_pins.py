@@ -512,3 +512,27 @@ def test_fp32_floor_pins():
         h = gi.haar_su3(np.random.default_rng(9), gi.volume(dims))
         fr = oracle.fp32_floor(oracle.gauge_transform(u.copy(), dims, gi.to_canonical(h)), dims)
         assert abs(fr / f - 1.0) < 0.2, (eps, fr / f)
+
+
+def test_unitarity_measure_closed_forms():
+    """(max ||U^dag U - 1||_F, max |det U - 1|) on matrices with known answers: diag(1+d, 1, 1)
+    gives (2d + d^2, d); a unitary phase matrix gives (0, 0) to rounding; s*W with W in SU(3)
+    gives (sqrt(3)|s^2 - 1|, |s^3 - 1|); the maximum is taken over all links."""
+    d = 1e-3
+    m = np.zeros((4, 3, 3), dtype=np.complex128)
+    m[0] = np.diag([1 + d, 1, 1])
+    phi = 0.37
+    m[1] = np.diag([np.exp(1j * phi), np.exp(-1j * phi), 1])
+    w = gi.haar_su3(np.random.default_rng(3), 1)[0]
+    s = 1.0 + 2e-4
+    m[2] = s * w
+    m[3] = np.eye(3)
+    u = gi.to_canonical(m).reshape(-1)
+    for k, (eu, ed) in enumerate([(2 * d + d * d, d), (0.0, 0.0), (np.sqrt(3) * (s * s - 1), s ** 3 - 1),
+                                  (0.0, 0.0)]):
+        one = gi.to_canonical(m[k:k + 1]).reshape(-1)
+        du, dd = oracle.unitarity(one)
+        assert abs(du - eu) <= 1e-12 + 1e-9 * eu, (k, du, eu)
+        assert abs(dd - ed) <= 1e-12 + 1e-9 * ed, (k, dd, ed)
+    du, dd = oracle.unitarity(u)
+    assert abs(du - (2 * d + d * d)) <= 1e-12 and abs(dd - d) <= 1e-12
