@@ -186,6 +186,16 @@ gf_status gf_half_sweep_or(gf_lattice lat, int32_t colour, double omega, gf_or_m
  * gf_set_links).  T_start >= T_end > 0.  Async. */
 gf_status gf_anneal(gf_lattice lat, int32_t n_sweeps, double T_start, double T_end, uint64_t seed);
 
+/* Checkpoint / resume of annealing: the heat-bath sweep counter (sweeps run
+ * by gf_anneal since gf_set_links).  Links saved with gf_get_links and the
+ * counter, restored with gf_set_links and gf_set_anneal_counter, continue
+ * bitwise as if never interrupted (counter-based random numbers).  GF_FP64
+ * and GF_FP32 lattices; a GF_MIXED lattice also holds U0 and the float32
+ * transformation, which gf_get_links does not return, so it cannot be
+ * checkpointed this way (GF_E_STATE).  Neither call touches the device. */
+gf_status gf_get_anneal_counter(gf_lattice lat, uint32_t* sweeps_done);
+gf_status gf_set_anneal_counter(gf_lattice lat, uint32_t sweeps_done);
+
 /* theta = (1/(3V)) sum_x tr[Delta(x) Delta(x)^dag] with
  * Delta(x) = [(K(x) - K(x)^dag)/(2i)]_traceless (equal to Eq. (landaugauge)
  * with A_mu of Sec. 2, a g = 1) and F = (1/(12V)) sum_x sum_mu Re tr U_mu(x)

@@ -442,6 +442,22 @@ gf_status gf_half_sweep_or(gf_lattice L, int32_t colour, double omega, gf_or_mod
     return do_half_sweep(L, colour, omega, (int)mode);
 }
 
+gf_status gf_get_anneal_counter(gf_lattice L, uint32_t* sweeps_done)
+{
+    if (!L || !sweeps_done) return fail(GF_E_ARG, "null argument");
+    if (L->prec == GF_MIXED) return fail(GF_E_STATE, "a GF_MIXED lattice cannot be checkpointed by its links");
+    *sweeps_done = L->anneal_sweeps;
+    return GF_OK;
+}
+
+gf_status gf_set_anneal_counter(gf_lattice L, uint32_t sweeps_done)
+{
+    GF_TRY(check_ready(L));
+    if (L->prec == GF_MIXED) return fail(GF_E_STATE, "a GF_MIXED lattice cannot be checkpointed by its links");
+    L->anneal_sweeps = sweeps_done;
+    return GF_OK;
+}
+
 gf_status gf_anneal(gf_lattice L, int32_t n_sweeps, double T_start, double T_end, uint64_t seed)
 {
     TraceRange range("gf_anneal");

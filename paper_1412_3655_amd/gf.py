@@ -117,6 +117,8 @@ _SIGNATURES = {
     "gf_lattice_info": [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
     "gf_set_sweep_config": [_vp, ctypes.c_int, _i32, _i32, _i32],
     "gf_set_anneal_config": [_vp, ctypes.c_int, _i32, _i32, _i32],
+    "gf_get_anneal_counter": [_vp, ctypes.POINTER(ctypes.c_uint32)],
+    "gf_set_anneal_counter": [_vp, ctypes.c_uint32],
     "gf_promote_fp64": [_vp],
     "gf_autotune_anneal": [_vp, ctypes.c_int, _i32, ctypes.c_char_p, ctypes.POINTER(gf_tune_entry), _i32,
                            ctypes.POINTER(_i32), ctypes.POINTER(gf_tune_entry)],
@@ -259,6 +261,16 @@ def gf_lattice_info(lat):
 
 def gf_set_sweep_config(lat, kernel: int, tps: int, block: int, nontemporal: int = 0) -> None:
     _call("gf_set_sweep_config", lat, int(kernel), int(tps), int(block), int(nontemporal))
+
+
+def gf_get_anneal_counter(lat) -> int:
+    c = ctypes.c_uint32()
+    _call("gf_get_anneal_counter", lat, ctypes.byref(c))
+    return c.value
+
+
+def gf_set_anneal_counter(lat, sweeps_done: int) -> None:
+    _call("gf_set_anneal_counter", lat, int(sweeps_done))
 
 
 def gf_set_anneal_config(lat, kernel: int, tps: int, block: int, nontemporal: int = 0) -> None:
@@ -444,6 +456,14 @@ class Lattice:
     def autotune(self, kernel=None, n_sweeps: int = 5, cache_path=None):
         k = kernel if kernel is not None else (GF_FP32 if self.prec != GF_FP64 else GF_FP64)
         return gf_autotune(self.handle, k, n_sweeps, cache_path)
+
+    @property
+    def anneal_counter(self) -> int:
+        return gf_get_anneal_counter(self.handle)
+
+    @anneal_counter.setter
+    def anneal_counter(self, sweeps_done: int):
+        gf_set_anneal_counter(self.handle, sweeps_done)
 
     def set_anneal_config(self, tps: int, block: int, nontemporal: int = 0, kernel=None):
         kinds = [kernel] if kernel is not None else (
