@@ -8,9 +8,10 @@ updates; the timed region holds `--steps` sweeps with the links resident in
 HBM.  Prints one JSON line.
 
 Extra legs (reported inside the same line): the float32 sweep rate, the 32^4
-run to theta < 1e-12 in float64 and in mixed precision (capped), a
+run to theta < 1e-12 in float64 and in mixed precision (capped; it is also
+run on a smoother input of the same generator, eps = 0.6, which converges), a
 cpu_baseline of the FP64 CPU oracle on a bounded number of sweeps of the same
-lattice, and the serving workload (Poisson arrivals of jobs of mixed volume,
+lattice (all host cores, and one core), and the serving workload (Poisson arrivals of jobs of mixed volume,
 continuous-batching pool in mixed precision vs float64 one lattice at a time:
 converged lattices/s and p50/p99 time to theta < 1e-12; `--no-serve` skips
 it).  `--batched` and `--fullsize` add the 64-lattice and the 48^3 x 96
@@ -109,9 +110,9 @@ def copy_bandwidth(gf, nbytes=1 << 30, reps=10):
     return best
 
 
-def fix_until_leg(gf, torch, stream, links, dims, args):
-    """The 32^4 run to theta < 1e-12: plain FP64 and FP32-bulk / FP64-polish (GF_MIXED)."""
-    out = {}
+def fix_until_leg(gf, torch, stream, links, dims, args, eps):
+    """The run of one input to theta < 1e-12: plain FP64 and FP32-bulk / FP64-polish (GF_MIXED)."""
+    out = {"eps": eps}
     kw = dict(omega=args.omega, mode=args.mode, theta_target=1e-12, max_sweeps=args.fix_max_sweeps,
               check_every=10, reunit_every=100, theta_switch=args.theta_switch)
     P0 = None
@@ -134,7 +135,7 @@ def fix_until_leg(gf, torch, stream, links, dims, args):
             P1 = lat.plaquette()
         out[name] = {"seconds": dt, "converged": r.converged, "sweeps": r.sweeps, "sweeps_fp32": r.sweeps_fp32,
                      "sweeps_fp64": r.sweeps_fp64, "theta": r.theta, "F": r.F, "plaquette_drift": abs(P1 - P0)}
-        log(f"fix_until {name}: {dt:.2f} s, sweeps {r.sweeps} ({r.sweeps_fp32}/{r.sweeps_fp64}), "
+        log(f"fix_until eps={eps} {name}: {dt:.2f} s, sweeps {r.sweeps} ({r.sweeps_fp32}/{r.sweeps_fp64}), "
             f"theta {r.theta:.3e}, F {r.F:.12f}")
     out["mixed"]["dF_vs_fp64"] = out["mixed"]["F"] - out["fp64"]["F"]
     out["speedup_mixed_vs_fp64"] = out["fp64"]["seconds"] / out["mixed"]["seconds"]
@@ -283,26 +284,42 @@ def fullsize_leg(gf, gi, torch, stream, args):
     return out
 
 
-def cpu_baseline(links, dims, omega, mode, budget_s):
-    import oracle
-
+def _time_oracle(oracle, links, dims, omega, mode, budget_s):
+    """(sweeps, seconds) of oracle sweeps filling about budget_s, after one untimed sweep."""
     work = links.copy()
-    V = links.shape[0]
     t0 = time.perf_counter()
     oracle.sweep(work, dims, 1, omega, mode)
     first = time.perf_counter() - t0
     n = max(1, min(200, int(budget_s / max(first, 1e-3)) - 1))
     t1 = time.perf_counter()
     oracle.sweep(work, dims, n, omega, mode)
-    dt = time.perf_counter() - t1
-    return {
+    return n, time.perf_counter() - t1
+
+
+def cpu_baseline(links, dims, omega, mode, budget_s, budget_1core_s):
+    import oracle
+
+    V = links.shape[0]
+    cores = oracle.num_threads()
+    n, dt = _time_oracle(oracle, links, dims, omega, mode, budget_s)
+    out = {
         "value": V * n / dt,
         "unit": "site-updates/s",
-        "cores": oracle.num_threads(),
+        "cores": cores,
         "kind": "oracle",
-        "sample": f"{n} FP64 oracle sweeps of the same 32^4 lattice (omega={omega}, exact power), "
-                  f"after 1 untimed sweep; {dt:.1f} s",
+        "sample": f"{n} FP64 oracle sweeps of the same {'x'.join(map(str, dims))} lattice (omega={omega}, "
+                  f"{'exact' if mode == 0 else 'binomial'} power), after 1 untimed sweep; {dt:.1f} s",
     }
+    if budget_1core_s > 0:
+        # the same oracle on one core (its results do not depend on the thread count)
+        oracle.set_num_threads(1)
+        try:
+            n1, dt1 = _time_oracle(oracle, links, dims, omega, mode, budget_1core_s)
+        finally:
+            oracle.set_num_threads(cores)
+        out["one_core"] = {"value": V * n1 / dt1, "unit": "site-updates/s", "cores": 1,
+                           "sample": f"{n1} sweeps after 1 untimed sweep; {dt1:.1f} s"}
+    return out
 
 
 def main(argv=None):
@@ -324,6 +341,8 @@ def main(argv=None):
     ap.add_argument("--block32", type=int, default=256)
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
+    ap.add_argument("--cpu-1core-budget", type=float, default=6.0,
+                    help="seconds of single-core oracle work (0: skip the one-core figure)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--chunk", type=int, default=10,
@@ -339,6 +358,8 @@ def main(argv=None):
     ap.add_argument("--full-max-sweeps", type=int, default=10000)
     ap.add_argument("--job-max-sweeps", type=int, default=10000)
     ap.add_argument("--fix-max-sweeps", type=int, default=20000)
+    ap.add_argument("--fix-eps-smooth", type=float, default=0.6,
+                    help="second run to theta < 1e-12 on a smoother input of the same lattice (0: skip)")
     ap.add_argument("--theta-switch", type=float, default=-1.0,
                     help="float32 -> float64 switch of the mixed runs; < 0: chosen by gf_tune_switch")
     ap.add_argument("--no-tune", action="store_true", help="use --tps/--block instead of the autotuner")
@@ -472,7 +493,13 @@ def main(argv=None):
         }
     line["tuning_us_per_sweep"] = tuning or None
     if not args.no_fix:
-        line["fix_until_theta_1e-12"] = fix_until_leg(gf, torch, stream, links, dims, args)
+        line["fix_until_theta_1e-12"] = fix_until_leg(gf, torch, stream, links, dims, args, args.eps)
+        if args.fix_eps_smooth > 0:
+            log(f"generating {dims} eps={args.fix_eps_smooth} seed={args.seed}")
+            smooth = gi.gen_links(dims, args.fix_eps_smooth, args.seed)
+            line["fix_until_theta_1e-12_smooth"] = fix_until_leg(gf, torch, stream, smooth, dims, args,
+                                                                 args.fix_eps_smooth)
+            del smooth
     line["device_copy_GBps"] = copy_bandwidth(gf)
     if args.batched:
         line["batched_64"] = batched_leg(gf, gi, stream, args)
@@ -482,7 +509,8 @@ def main(argv=None):
         line["fullsize_48x96"] = fullsize_leg(gf, gi, torch, stream, args)
     if not args.no_cpu:
         log("cpu baseline (FP64 oracle)")
-        line["cpu_baseline"] = cpu_baseline(links, dims, args.omega, args.mode, args.cpu_budget)
+        line["cpu_baseline"] = cpu_baseline(links, dims, args.omega, args.mode, args.cpu_budget,
+                                            args.cpu_1core_budget)
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)

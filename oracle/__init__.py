@@ -26,6 +26,7 @@ __all__ = [
     "build",
     "lib",
     "num_threads",
+    "set_num_threads",
     "su2_project",
     "su2_maximiser",
     "su2_overrelax",
@@ -114,6 +115,7 @@ def _declare(L):
     L.oracle_hb_sample_su2.argtypes = [ctypes.c_double, ctypes.c_uint64, ctypes.c_int64, _dp]
     L.oracle_hb_sample_su2.restype = ctypes.c_int64
     L.oracle_num_threads.restype = ctypes.c_int
+    L.oracle_set_num_threads.argtypes = [ctypes.c_int]
 
 
 def _links(u: np.ndarray) -> np.ndarray:
@@ -139,6 +141,11 @@ def _p(a, t=_dp):
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on (timing control; results do not depend on it)."""
+    lib().oracle_set_num_threads(int(n))
 
 
 def _c2(m) -> np.ndarray:

@@ -847,3 +847,13 @@ int oracle_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the OpenMP loops from now on (n >= 1); timing control only. */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

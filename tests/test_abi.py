@@ -77,3 +77,28 @@ def test_bench_rejects_several_gpus():
     assert r.returncode == 2
     assert "one GPU only" in r.stderr
     assert r.stdout == ""
+
+
+def test_bench_cpu_baseline_fields():
+    """bench.py's cpu_baseline: the oracle on all host threads and on one core, with the thread count
+    restored afterwards (a 4^4 lattice, a fraction of a second each)."""
+    import sys
+
+    import numpy as np
+
+    import gauge_inputs as gi
+    import oracle
+
+    sys.path.insert(0, ROOT)
+    import bench
+
+    dims = (4, 4, 4, 4)
+    u = gi.gen_links(dims, 0.6, 3)
+    before = oracle.num_threads()
+    cb = bench.cpu_baseline(u, dims, 1.7, 0, 0.05, 0.05)
+    assert oracle.num_threads() == before
+    assert cb["kind"] == "oracle" and cb["unit"] == "site-updates/s" and cb["cores"] == before
+    assert cb["value"] > 0 and cb["one_core"]["cores"] == 1 and cb["one_core"]["value"] > 0
+    assert "4x4x4x4" in cb["sample"]
+    # the timing copies the input: the caller's links are untouched
+    assert np.array_equal(u, gi.gen_links(dims, 0.6, 3))
