@@ -15,12 +15,13 @@ template <typename R, int TPS, int MODE, int BLOCK, bool TRACKG, int CP>
 __global__ void __launch_bounds__(BLOCK) k_or_half_sweep(LinkField<R> f, Geom g, int parity, Rule<R> rule,
                                                          GField gacc)
 {
-    // The white half-sweep takes the blocks in reverse order, so it starts on
-    // the links the black half-sweep touched last, which are still in the
-    // Infinity Cache (a 32^4 float64 field is 402 MB against 256 MB of cache),
-    // and ends where the next black half-sweep starts.  Sites of one colour
-    // are independent, so the result does not depend on the order.
-    const uint32_t b = parity ? gridDim.x - 1u - blockIdx.x : blockIdx.x;
+    // With cached loads the white half-sweep takes the blocks in reverse
+    // order, so it starts on the links the black half-sweep touched last,
+    // which are still in the Infinity Cache (a 32^4 float64 field is 402 MB
+    // against 256 MB of cache), and ends where the next black half-sweep
+    // starts; non-temporal loads leave nothing there to reuse.  Sites of one
+    // colour are independent, so the result does not depend on the order.
+    const uint32_t b = (parity && !nt_loads(CP)) ? gridDim.x - 1u - blockIdx.x : blockIdx.x;
     const uint32_t gid = b * (uint32_t)BLOCK + threadIdx.x;
     const uint32_t h = gid / TPS;
     const int r = (int)(gid % TPS);
