@@ -142,42 +142,6 @@ def fix_until_leg(gf, torch, stream, links, dims, args, eps):
     return out
 
 
-_POOL_TPS = {}
-
-
-def pool_tps(gf, gi, stream):
-    """Lanes per site of the pool's float32 / float64 sweeps (128-thread blocks): each candidate
-    timed on the pool's own kernels, 100 sweeps of eight lattices of the batched shapes, best of two
-    runs (uploads and first measurements outside the timed steps)."""
-    import torch
-
-    if _POOL_TPS:
-        return _POOL_TPS["tps32"], _POOL_TPS["tps64"]
-    shapes = [(12, 12, 12, 12), (16, 16, 16, 16), (16, 16, 16, 32), (24, 24, 24, 48)] * 2
-    links = [gi.gen_links(d, 0.7, 700 + i) for i, d in enumerate(shapes)]
-    fix = dict(omega=1.7, mode=0, theta_target=0.0, max_sweeps=100, reunit_every=0, theta_switch=0.0)
-    best = {}
-    for prec, key in ((gf.GF_MIXED, "tps32"), (gf.GF_FP64, "tps64")):
-        times = {}
-        for rep in range(2):
-            for tps in (1, 2, 4):
-                with gf.Pool(1 << 36, len(shapes), prec=prec, check_every=10, **{key: tps}) as pool:
-                    for i, (d, u) in enumerate(zip(shapes, links)):
-                        assert pool.admit(i, d, u, **fix)
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    done = 0
-                    while done < len(shapes):
-                        pool.step()
-                        done += len(pool.poll())
-                    dt = time.perf_counter() - t0
-                times[tps] = min(dt, times.get(tps, dt))
-        best[key] = min(times, key=times.get)
-        log(f"pool {key}: " + ", ".join(f"{t}: {1e3 * v:.1f} ms" for t, v in times.items()))
-    _POOL_TPS.update(best)
-    return best["tps32"], best["tps64"]
-
-
 def batched_leg(gf, gi, stream, args):
     """64 lattices of uneven volume to theta < 1e-12: mixed-precision pool vs FP64 one at a time."""
     from paper_1412_3655_amd import serving
@@ -189,7 +153,7 @@ def batched_leg(gf, gi, stream, args):
         f"{time.perf_counter() - t0:.1f} s")
     fix = dict(omega=args.omega, mode=args.mode, theta_target=1e-12, max_sweeps=args.job_max_sweeps, check_every=10,
                reunit_every=100, theta_switch=args.theta_switch)
-    t32, t64 = pool_tps(gf, gi, stream)
+    t32, t64 = args.pool_tps32, args.pool_tps64
     out = {"jobs": 64, "max_sweeps": args.job_max_sweeps, "pool_tps32": t32, "pool_tps64": t64}
     for name, fn in (
         ("pool_mixed", lambda: serving.run_pool(jobs, lambda j: links[j.job_id], gf.GF_MIXED, 10, 64, None, fix,
@@ -222,10 +186,10 @@ def serving_leg(gf, gi, stream, args):
     log(f"serving: {len(jobs)} jobs, {len(bank)} distinct inputs generated in {time.perf_counter() - t0:.1f} s")
     fix = dict(omega=args.omega, mode=args.mode, theta_target=1e-12, max_sweeps=args.job_max_sweeps, check_every=10,
                reunit_every=100, theta_switch=args.theta_switch)
-    t32, t64 = pool_tps(gf, gi, stream)
+    t32, t64 = args.pool_tps32, args.pool_tps64
     links_of = lambda j: bank[(j.dims, j.eps)]
     out = {"jobs": len(jobs), "rate_per_s": 20.0, "max_sweeps": args.job_max_sweeps,
-           "distinct_inputs": len(bank), "last_arrival_s": jobs[-1].arrival}
+           "distinct_inputs": len(bank), "last_arrival_s": jobs[-1].arrival, "pool_tps32": t32, "pool_tps64": t64}
     budget = int(args.serve_budget_gb * 1e9) if args.serve_budget_gb > 0 else None
     out["hbm_budget_bytes"] = budget
     st = serving.run_pool(jobs, links_of, gf.GF_MIXED, 10, 256, budget, fix, True, t32, t64)
@@ -356,6 +320,10 @@ def main(argv=None):
     ap.add_argument("--serve-jobs", type=int, default=100)
     ap.add_argument("--serve-budget-gb", type=float, default=0.0,
                     help="HBM budget of the serving pool (0: 80 %% of free device memory)")
+    ap.add_argument("--pool-tps32", type=int, default=2,
+                    help="lanes per site of the pool's float32 sweeps (2: fastest over the batched set on MI355X)")
+    ap.add_argument("--pool-tps64", type=int, default=1,
+                    help="lanes per site of the pool's float64 sweeps (1: fastest over the batched set on MI355X)")
     ap.add_argument("--fullsize", action="store_true", help="also run the 48^3x96 anneal + mixed-precision workload")
     ap.add_argument("--full-max-sweeps", type=int, default=10000)
     ap.add_argument("--job-max-sweeps", type=int, default=10000)

@@ -258,8 +258,9 @@ typedef struct {
     int32_t check_every; /* sweeps per pool step = every job's measurement cadence, >= 1 */
     int32_t mode;        /* gf_or_mode of every job */
     int32_t tps32, block32, tps64, block64; /* lanes per site of the pool's float32 / float64
-                                               overrelaxation sweeps (0 = default 4; the pool's sweeps use
-                                               128-thread blocks, its heat-bath sweeps one lane per site);
+                                               overrelaxation sweeps (0 = default: 2 for float32, 1 for
+                                               float64; the pool's sweeps use 128-thread blocks, its
+                                               heat-bath sweeps one lane per site);
                                                block32 / block64 configure the jobs' own lattices (0 = 256) */
 } gf_pool_config;
 
