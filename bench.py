@@ -119,9 +119,15 @@ def fix_until_leg(gf, torch, stream, links, dims, args, eps):
     for name, prec in (("fp64", gf.GF_FP64), ("mixed", gf.GF_MIXED)):
         with gf.Lattice(dims, prec, stream=stream) as lat:
             lat.set_sweep_config(args.tps, args.block, args.nt, kernel=gf.GF_FP64)
-            if prec == gf.GF_MIXED:
-                lat.set_sweep_config(args.tps32, args.block32, args.nt32, kernel=gf.GF_FP32)
             lat.set_links(links)
+            if prec == gf.GF_MIXED:
+                # the float32 sweeps of a mixed lattice also update g(x): tuned as their own kernel
+                if args.no_tune:
+                    lat.set_sweep_config(args.tps32, args.block32, args.nt32, kernel=gf.GF_FP32)
+                    out["mixed_fp32_config"] = [args.tps32, args.block32, args.nt32]
+                else:
+                    out["mixed_fp32_config"] = list(lat.autotune(gf.GF_FP32, n_sweeps=5)[0])
+                log(f"fix_until eps={eps}: mixed float32 sweeps with g tracking at {out['mixed_fp32_config']}")
             if P0 is None:
                 P0 = lat.plaquette()  # of the float64 input (a mixed lattice starts on float32 links)
             if prec == gf.GF_MIXED:

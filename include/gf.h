@@ -131,7 +131,9 @@ typedef struct {
  * sweep, then n_sweeps timed sweeps each), write up to cap entries to table
  * (may be NULL), and make the fastest the lattice's configuration.  When
  * cache_path is not NULL, a result stored there for the same device
- * architecture, extents and precision is applied without timing (*n_out = 0),
+ * architecture, extents and kernel (float64; float32; float32 with the g(x)
+ * update that a GF_MIXED lattice's float32 sweeps make) is applied without
+ * timing (*n_out = 0),
  * and a newly timed result is appended to it (plain text, one line per key).
  * *chosen (may be NULL) receives the configuration applied.  The links are
  * not changed.  Syncs. */

@@ -27,11 +27,14 @@ std::string device_arch()
     return colon == std::string::npos ? a : a.substr(0, colon);
 }
 
+// A GF_MIXED lattice's float32 sweeps also update g(x) (another 96 B per site
+// update and more registers), so they are a kernel of their own: "fp32g".
 std::string cache_key(gf_lattice L, gf_prec kernel)
 {
     char buf[128];
+    const char* k = kernel == GF_FP64 ? "fp64" : (L->gacc.base ? "fp32g" : "fp32");
     snprintf(buf, sizeof buf, "%s %d %d %d %d %s", device_arch().c_str(), L->dims[0], L->dims[1], L->dims[2],
-             L->dims[3], kernel == GF_FP32 ? "fp32" : "fp64");
+             L->dims[3], k);
     return buf;
 }
 

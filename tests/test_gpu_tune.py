@@ -51,6 +51,23 @@ def test_autotune(prec, tmp_path):
     assert len(open(cache).read().strip().splitlines()) == 1
 
 
+def test_autotune_cache_tells_g_tracking_apart(tmp_path):
+    """A GF_MIXED lattice's float32 sweeps also update g(x): their tuning is cached apart from
+    that of a GF_FP32 lattice of the same extents, so neither answers for the other."""
+    dims = (8, 8, 8, 12)
+    u = gi.gen_links(dims, 0.7, 5)
+    cache = os.path.join(str(tmp_path), "tune.txt")
+    for prec in (gf.GF_FP32, gf.GF_MIXED):
+        with gf.Lattice(dims, prec) as lat:
+            lat.set_links(u)
+            _, table = lat.autotune(gf.GF_FP32, n_sweeps=2, cache_path=cache)
+            assert len(table) == 15 + 9 + 9  # timed, not read from the other kernel's entry
+            _, table2 = lat.autotune(gf.GF_FP32, n_sweeps=2, cache_path=cache)
+            assert table2 == []
+    keys = [line.split()[-5] for line in open(cache).read().strip().splitlines()]
+    assert sorted(keys) == ["fp32", "fp32g"]
+
+
 @pytest.mark.parametrize("prec", [gf.GF_FP64, gf.GF_MIXED])
 def test_autotune_anneal(prec, tmp_path):
     """The heat-bath tuner times every shape on a scratch copy (links unchanged), applies the
