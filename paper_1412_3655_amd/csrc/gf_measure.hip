@@ -21,14 +21,20 @@ namespace {
 
 constexpr int RBLOCK = 256;
 
+// Blocks alternate colours tile by tile (block 2b + p: colour p, tile b), so
+// the second read of a link (from its other end, a few planes away) follows
+// the first while the Infinity Cache still holds it, instead of half a lattice
+// later.  Partial (p, b) holds the same sites whatever the dispatch order.
 template <typename R>
 __global__ void __launch_bounds__(RBLOCK) k_measure(LinkField<R> f, Geom g, double* partial)
 {
-    const int parity = blockIdx.y;
-    const uint32_t h = blockIdx.x * RBLOCK + threadIdx.x;
+    const int parity = (int)(blockIdx.x & 1u);
+    const uint32_t tile = blockIdx.x >> 1;
+    const uint32_t tiles = gridDim.x >> 1;
+    const uint32_t h = tile * RBLOCK + threadIdx.x;
     double th = 0.0, fr = 0.0;
     if (h < g.vh) measure_site(f, g, parity, h, th, fr);
-    block_sum2<RBLOCK>(th, fr, partial + 2 * (size_t)(blockIdx.y * gridDim.x + blockIdx.x));
+    block_sum2<RBLOCK>(th, fr, partial + 2 * (size_t)(parity * tiles + tile));
 }
 
 // Re tr[U_mu(x) U_nu(x+mu^) U_mu(x+nu^)^dag U_nu(x)^dag] summed over mu < nu.
@@ -304,7 +310,7 @@ template <typename R>
 hipError_t measure_impl(const LinkField<R>& f, const Geom& g, double* partial, double* out, hipStream_t st)
 {
     const uint32_t nb = site_blocks(g);
-    hipLaunchKernelGGL((k_measure<R>), dim3(nb, 2), dim3(RBLOCK), 0, st, f, g, partial);
+    hipLaunchKernelGGL((k_measure<R>), dim3(2 * nb), dim3(RBLOCK), 0, st, f, g, partial);
     const double V = 2.0 * (double)g.vh;
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RBLOCK), 0, st, partial, 2 * nb, 1.0 / (3.0 * V), 1.0 / (12.0 * V),
                        out);
