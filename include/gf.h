@@ -194,7 +194,9 @@ gf_status gf_anneal(gf_lattice lat, int32_t n_sweeps, double T_start, double T_e
  * bitwise as if never interrupted (counter-based random numbers).  GF_FP64
  * and GF_FP32 lattices; a GF_MIXED lattice also holds U0 and the float32
  * transformation, which gf_get_links does not return, so it cannot be
- * checkpointed this way (GF_E_STATE).  Neither call touches the device. */
+ * checkpointed this way (GF_E_STATE).  gf_set_anneal_counter comes after
+ * gf_set_links (which resets the counter to 0; before any links: GF_E_STATE).
+ * Neither call touches the device. */
 gf_status gf_get_anneal_counter(gf_lattice lat, uint32_t* sweeps_done);
 gf_status gf_set_anneal_counter(gf_lattice lat, uint32_t sweeps_done);
 
