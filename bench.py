@@ -206,6 +206,18 @@ def serving_leg(gf, gi, stream, args):
     log(f"serving fifo: {st.converged}/{len(jobs)} converged, {st.seconds:.1f} s")
     a, b = out["pool_mixed"]["converged_lattices_per_s"], out["fifo_fp64"]["converged_lattices_per_s"]
     out["speedup_converged_per_s_pool_mixed_vs_fifo_fp64"] = a / b if a and b else None
+    if args.serve_closed:
+        # the same jobs all queued at t = 0: peak throughput, latency counted from t = 0
+        closed = {}
+        st = serving.run_pool(jobs, links_of, gf.GF_MIXED, 10, 256, budget, fix, False, t32, t64)
+        closed["pool_mixed"] = st.summary()
+        log(f"serving closed loop pool: {st.converged}/{len(jobs)} converged, {st.seconds:.1f} s")
+        st = serving.run_fifo(jobs, links_of, gf.GF_FP64, fix, False, args.tps, args.block, args.nt)
+        closed["fifo_fp64"] = st.summary()
+        log(f"serving closed loop fifo: {st.converged}/{len(jobs)} converged, {st.seconds:.1f} s")
+        a, b = closed["pool_mixed"]["converged_lattices_per_s"], closed["fifo_fp64"]["converged_lattices_per_s"]
+        closed["speedup_converged_per_s_pool_mixed_vs_fifo_fp64"] = a / b if a and b else None
+        out["closed_loop"] = closed
     return out
 
 
@@ -324,6 +336,8 @@ def main(argv=None):
     ap.add_argument("--serve", action="store_true", help="(the serving leg runs by default; kept for scripts)")
     ap.add_argument("--no-serve", action="store_true", help="skip the Poisson-arrival serving workload")
     ap.add_argument("--serve-jobs", type=int, default=100)
+    ap.add_argument("--serve-closed", action="store_true",
+                    help="also run the serving jobs closed loop (all queued at t = 0: peak lattices/s)")
     ap.add_argument("--serve-budget-gb", type=float, default=0.0,
                     help="HBM budget of the serving pool (0: 80 %% of free device memory)")
     ap.add_argument("--pool-tps32", type=int, default=2,
