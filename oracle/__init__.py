@@ -45,6 +45,7 @@ __all__ = [
     "anneal",
     "hb_sample_r0",
     "hb_sample_su2",
+    "hb_subgroup_draws",
 ]
 
 OR_EXACT = 0
@@ -114,6 +115,8 @@ def _declare(L):
     L.oracle_hb_sample_r0.restype = ctypes.c_int64
     L.oracle_hb_sample_su2.argtypes = [ctypes.c_double, ctypes.c_uint64, ctypes.c_int64, _dp]
     L.oracle_hb_sample_su2.restype = ctypes.c_int64
+    L.oracle_hb_subgroup_draws.argtypes = [_dp, ctypes.c_double, ctypes.c_uint64, ctypes.c_int64, _dp]
+    L.oracle_hb_subgroup_draws.restype = ctypes.c_int64
     L.oracle_num_threads.restype = ctypes.c_int
     L.oracle_set_num_threads.argtypes = [ctypes.c_int]
 
@@ -313,4 +316,14 @@ def hb_sample_su2(kappa: float, seed: int, n: int):
     """n heat-bath SU(2) draws as quaternions (r0, r1, r2, r3)."""
     out = np.empty((int(n), 4))
     capped = lib().oracle_hb_sample_su2(float(kappa), int(seed), int(n), _p(out))
+    return out, int(capped)
+
+
+def hb_subgroup_draws(k, T: float, seed: int, n: int):
+    """n heat-bath subgroup elements (2x2 complex) drawn for the fixed 2x2 block k at
+    temperature T, by the same code path as the annealing sweep."""
+    kk = np.ascontiguousarray(np.asarray(k, dtype=np.complex128).reshape(2, 2))
+    out = np.empty((int(n), 2, 2), dtype=np.complex128)
+    capped = lib().oracle_hb_subgroup_draws(_p(kk.view(np.float64)), float(T), int(seed), int(n),
+                                            _p(out.view(np.float64)))
     return out, int(capped)

@@ -751,41 +751,54 @@ static void hb_sample_su2(hb_stream* st, double kappa, int* capped, cx* w)
     w[3] = r0 - I * r3;
 }
 
+/* One subgroup element drawn from exp(Re tr[g k] / T) dHaar(g) for the 2x2
+ * block k of K.  With q = n * qhat the SU(2)-span projection of k (qhat in
+ * SU(2)), Re tr[g k] = Re tr[g q] = 2 n w0 for g = w qhat^dag, so w has
+ * density exp(2 n w0 / T) dHaar(w): kappa = 2n/T; qhat^dag is the SU(2)
+ * maximiser.  n = 0 draws g Haar-uniformly (kappa = 0). */
+static void hb_subgroup_element(const cx* k, double T, hb_stream* st, int* capped, cx* g2)
+{
+    cx q[4], gm[4], w[4];
+    oracle_su2_project((const double*)k, (double*)q);
+    double det = creal(q[0] * q[3] - q[1] * q[2]);
+    double n = det > 0.0 ? sqrt(det) : 0.0;
+    if (n == 0.0) {
+        hb_sample_su2(st, 0.0, capped, g2);
+        return;
+    }
+    hb_sample_su2(st, 2.0 * n / T, capped, w);
+    oracle_su2_maximiser((const double*)k, (double*)gm);
+    g2[0] = w[0] * gm[0] + w[1] * gm[2];
+    g2[1] = w[0] * gm[1] + w[1] * gm[3];
+    g2[2] = w[2] * gm[0] + w[3] * gm[2];
+    g2[3] = w[2] * gm[1] + w[3] * gm[3];
+}
+
 /* Heat-bath update of site s at temperature T: for every subgroup the new
- * element is drawn from exp(Re tr[g k] / T) dHaar(g).  With q = n * qhat the
- * projected block (qhat in SU(2)), g = w qhat^dag where w has density
- * exp(2 n w0 / T) dHaar(w); qhat^dag is the SU(2) maximiser. */
+ * element is drawn by hb_subgroup_element from the current block of K. */
 static void hb_site_update(double* U, const geom* g, long s, double T, const uint32_t* key, uint32_t sweep,
                            int* capped)
 {
     for (int sg = 0; sg < 3; ++sg) {
         int i = SUBGROUP[sg][0], j = SUBGROUP[sg][1];
-        cx K[9], k[4], q[4], gm[4], w[4], g2[4], S[9];
+        cx K[9], k[4], g2[4], S[9];
         local_K(U, g, s, K);
         block_of(K, i, j, k);
-        oracle_su2_project((const double*)k, (double*)q);
-        double det = creal(q[0] * q[3] - q[1] * q[2]);
-        double n = det > 0.0 ? sqrt(det) : 0.0;
         hb_stream st = {{key[0], key[1]}, (uint32_t)s, sweep, (uint32_t)sg, 0u};
-        if (n == 0.0) {
-            hb_sample_su2(&st, 0.0, capped, g2);
-        } else {
-            hb_sample_su2(&st, 2.0 * n / T, capped, w);
-            oracle_su2_maximiser((const double*)k, (double*)gm);
-            g2[0] = w[0] * gm[0] + w[1] * gm[2];
-            g2[1] = w[0] * gm[1] + w[1] * gm[3];
-            g2[2] = w[2] * gm[0] + w[3] * gm[2];
-            g2[3] = w[2] * gm[1] + w[3] * gm[3];
-        }
+        hb_subgroup_element(k, T, &st, capped, g2);
         embed(g2, i, j, S);
         transform_site(U, g, s, S);
     }
 }
 
-/* Temperature of annealing sweep s of n: linear from T0 (s = 0) to T1 (s = n-1). */
+/* Temperature of annealing sweep s of n: linear from T0 (s = 0) to T1
+ * (s = n-1), both endpoints taken exactly (the interpolation formula alone can
+ * miss T1 by an ulp). */
 static double anneal_temperature(int32_t s, int32_t n, double T0, double T1)
 {
-    return n > 1 ? T0 + (T1 - T0) * (double)s / (double)(n - 1) : T0;
+    if (n <= 1 || s == 0) return T0;
+    if (s == n - 1) return T1;
+    return T0 + (T1 - T0) * (double)s / (double)(n - 1);
 }
 
 /* n heat-bath sweeps (black then white) with the linear schedule; the Philox
@@ -835,6 +848,21 @@ int64_t oracle_hb_sample_su2(double kappa, uint64_t seed, int64_t n, double* out
         out[4 * i + 1] = cimag(w[1]);
         out[4 * i + 2] = creal(w[1]);
         out[4 * i + 3] = cimag(w[0]);
+    }
+    return capped;
+}
+
+/* Site-level heat-bath draws: n subgroup elements for one fixed 2x2 block k
+ * (4 complex numbers, row-major, as 8 doubles) at temperature T, draw i on
+ * counter site = i, sweep = 0, subgroup = 0; out holds n 2x2 complex
+ * matrices (8 doubles each).  The same code path as the annealing sweep. */
+int64_t oracle_hb_subgroup_draws(const double* k, double T, uint64_t seed, int64_t n, double* out)
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    int capped = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        hb_stream st = {{key[0], key[1]}, (uint32_t)i, 0u, 0u, 0u};
+        hb_subgroup_element((const cx*)k, T, &st, &capped, (cx*)(out + 8 * i));
     }
     return capped;
 }

@@ -126,10 +126,13 @@ inline void update_stall(double theta, double* best, int* stall)
     }
 }
 
-// Temperature of annealing sweep s of n: linear from T_start (s = 0) to T_end (s = n - 1).
+// Temperature of annealing sweep s of n: linear from T_start (s = 0) to T_end
+// (s = n - 1), both endpoints exact.
 inline double anneal_temperature(int32_t s, int32_t n, double T_start, double T_end)
 {
-    return n > 1 ? T_start + (T_end - T_start) * (double)s / (double)(n - 1) : T_start;
+    if (n <= 1 || s == 0) return T_start;
+    if (s == n - 1) return T_end;
+    return T_start + (T_end - T_start) * (double)s / (double)(n - 1);
 }
 
 }  // namespace detail

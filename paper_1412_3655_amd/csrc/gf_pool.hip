@@ -135,10 +135,13 @@ __device__ __forceinline__ LinkField<float> field_of<float>(const SlotDev& sd)
     return sd.f32;
 }
 
-// Linear schedule of gf_anneal: T_start at sweep 0, T_end at sweep n - 1 (float64).
+// Linear schedule of gf_anneal: T_start at sweep 0, T_end at sweep n - 1,
+// both endpoints exact (float64).
 __device__ __forceinline__ double schedule_T(const SlotDev& sd, uint32_t s)
 {
-    return sd.n_anneal > 1 ? sd.T0 + (sd.T1 - sd.T0) * (double)s / (double)(sd.n_anneal - 1) : sd.T0;
+    if (sd.n_anneal <= 1 || s == 0) return sd.T0;
+    if (s == (uint32_t)(sd.n_anneal - 1)) return sd.T1;
+    return sd.T0 + (sd.T1 - sd.T0) * (double)s / (double)(sd.n_anneal - 1);
 }
 
 // float64 links use non-temporal accesses, float32 ones plain accesses (the

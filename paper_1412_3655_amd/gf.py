@@ -241,15 +241,56 @@ def gf_last_error() -> str:
     return lib().gf_last_error().decode(errors="replace")
 
 
+# hip stream handle of each live lattice (None = the default stream), so that the
+# device-array calls can order the lattice's stream against torch's
+_LATTICE_STREAM = {}
+
+
 def gf_create_lattice(dims, prec: int = GF_FP64, stream=None) -> ctypes.c_void_p:
     d = (_i32 * 4)(*[int(x) for x in dims])
     out = _vp()
-    _call("gf_create_lattice", d, int(prec), _stream_handle(stream), ctypes.byref(out))
+    h = _stream_handle(stream)
+    _call("gf_create_lattice", d, int(prec), h, ctypes.byref(out))
+    _LATTICE_STREAM[out.value] = h
     return out
 
 
 def gf_destroy_lattice(lat) -> None:
     _call("gf_destroy_lattice", lat)
+    _LATTICE_STREAM.pop(getattr(lat, "value", lat), None)
+
+
+def _lattice_stream(lat, tensor):
+    """(torch's current stream on the tensor's device, the lattice's stream as a torch
+    stream), or None when the two are the same stream."""
+    import torch
+
+    cur = torch.cuda.current_stream(tensor.device)
+    h = _LATTICE_STREAM.get(getattr(lat, "value", lat))
+    if (h or 0) == int(cur.cuda_stream):
+        return None
+    ls = torch.cuda.ExternalStream(h, device=tensor.device) if h else torch.cuda.default_stream(tensor.device)
+    return cur, ls
+
+
+def _before_lattice_reads(lat, tensor) -> None:
+    """The lattice's stream waits for torch's current stream (which produced the
+    tensor), and the caching allocator keeps the tensor's memory until the lattice's
+    stream has used it."""
+    pair = _lattice_stream(lat, tensor)
+    if pair is not None:
+        cur, ls = pair
+        ls.wait_stream(cur)
+        tensor.record_stream(ls)
+
+
+def _after_lattice_writes(lat, tensor) -> None:
+    """Torch's current stream waits for the lattice's stream (which wrote the tensor)."""
+    pair = _lattice_stream(lat, tensor)
+    if pair is not None:
+        cur, ls = pair
+        tensor.record_stream(ls)
+        cur.wait_stream(ls)
 
 
 def gf_lattice_info(lat):
@@ -307,6 +348,7 @@ def gf_set_links(lat, links) -> None:
     volume, _ = gf_lattice_info(lat)
     if _is_device_tensor(links):
         t = _device_links(links, volume)
+        _before_lattice_reads(lat, t)
         _call("gf_set_links_device", lat, t.data_ptr())
     else:
         u = _host_links(links, volume)
@@ -324,7 +366,9 @@ def gf_get_links(lat, out=None):
         out = np.empty((volume, 4, 3, 3, 2), dtype=np.float64)
     if _is_device_tensor(out):
         t = _device_links(out, volume)
+        _before_lattice_reads(lat, t)  # earlier torch work on `out` completes first
         _call("gf_get_links_device", lat, t.data_ptr())
+        _after_lattice_writes(lat, t)
     else:
         u = _host_links(out, volume)
         _call("gf_get_links", lat, u.ctypes.data_as(_dp))

@@ -74,13 +74,19 @@ def test_anneal_bitwise_across_tps_and_resume():
     oracle.anneal(ref, RAGGED, 2, 0.8, 0.8, 7, 0)
     oracle.anneal(ref, RAGGED, 2, 0.8, 0.8, 7, 2)
     assert np.abs(split - ref).max() <= 1e-12
+    # schedule endpoints are exact: 2 sweeps 1.25 -> 0.01 == one at 1.25, then one at 0.01
+    two, _ = gpu_anneal(RAGGED, u, [(2, 1.25, 0.01, 7)])
+    steps, _ = gpu_anneal(RAGGED, u, [(1, 1.25, 1.25, 7), (1, 0.01, 0.01, 7)])
+    assert np.array_equal(two, steps)
 
 
 def test_anneal_then_or_matches_oracle():
     """5 heat-bath sweeps (T 1.25 -> 0.01) within 1e-12 of the oracle, then 30 sweeps of the
     fix-until iteration within 1e-10, with the same sweep count, theta and F.  (Rounding
-    differences grow by ~1.7x per low-temperature heat-bath sweep, so longer anneals are
-    compared through theta, F and the plaquette.)"""
+    differences grow about 2.7x per hot (T = 1.25) heat-bath sweep and hardly at all below
+    T = 0.3: two oracle runs one ulp apart stay below 1e-13 over these 5 schedule sweeps but
+    pass 1e-12 over 20, see test_heat_bath_rounding_growth_sets_parity_length, so longer
+    anneals are compared through theta, F and the plaquette.)"""
     say("anneal 5 + fix_until 30 on 8^4")
     u = gi.gen_links(CFG8, 1.0, 13)
     ref = u.copy()

@@ -69,6 +69,31 @@ def test_roundtrip_host_and_device():
         assert np.array_equal(out.cpu().numpy(), got)
 
 
+def test_device_links_on_a_side_stream_lattice():
+    """A lattice on its own stream reads a temporary tensor that torch's current stream
+    produced and then frees, and writes into a tensor torch then reads: the binding
+    orders the two streams and keeps the temporary's memory until the lattice has read it."""
+    import torch
+
+    say("device links with the lattice on a side stream, RAGGED")
+    u = gi.gen_links(RAGGED, 0.7, 4)
+    ref = u.copy()
+    oracle.sweep(ref, RAGGED, 1, 1.7, oracle.OR_EXACT)
+    side = torch.cuda.Stream()
+    src = torch.from_numpy(u).cuda()
+    with gf.Lattice(RAGGED, gf.GF_FP64, stream=side) as lat:
+        tmp = src * 1.0  # produced on torch's current stream
+        lat.set_links(tmp)
+        del tmp
+        junk = torch.full_like(src, float("nan"))  # may take the freed block
+        lat.sweep(1, 1.7, gf.GF_OR_EXACT)
+        out = torch.zeros_like(src)
+        lat.get_links(out)
+        got = (out * 1.0).cpu().numpy()  # consumed on torch's current stream
+        del junk
+    assert maxdiff(got, ref) <= 1e-12
+
+
 @pytest.mark.parametrize("dims", [CFG8, RAGGED] + EDGE)
 def test_measure_and_plaquette(dims):
     say(f"measure/plaquette dims={dims}")

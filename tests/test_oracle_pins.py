@@ -445,6 +445,113 @@ def test_anneal_cold_limit_increases_functional():
     assert abs(F1 - Fw) < 0.02
 
 
+def _su2_span_projection(k):
+    """Projection of a 2x2 complex block onto the real span of SU(2): (k + s2 k* s2)/2."""
+    s2 = np.array([[0, -1j], [1j, 0]])
+    return 0.5 * (k + s2 @ k.conj() @ s2)
+
+
+@pytest.mark.parametrize("kappa", [0.5, 2.0, 8.0])
+def test_heat_bath_site_draw_weight(kappa):
+    """The annealing prelude (abstract) samples each subgroup element g from
+    exp(Re tr[g k] / T) dHaar(g).  For g = w qhat^dag (q = n qhat the SU(2)-span
+    projection of k), Re tr[g k] = 2 n w0, so r0 = Re tr[g k] / (2n) must have density
+    sqrt(1 - r0^2) exp(kappa r0) with kappa = 2n/T, mean I2(kappa)/I1(kappa), and the
+    direction of w must be isotropic.  n comes from numpy here, not from the oracle; a
+    weight with kappa = n/T (a dropped factor 2) fails the KS and mean checks."""
+    import scipy.special
+
+    rng = np.random.default_rng(int(kappa * 10))
+    k = rng.normal(size=(2, 2)) + 1j * rng.normal(size=(2, 2))
+    q = _su2_span_projection(k)
+    n = math.sqrt(np.linalg.det(q).real)
+    T = 2.0 * n / kappa
+    g, capped = oracle.hb_subgroup_draws(k, T, 77, 40000)
+    assert capped == 0
+    eye = np.eye(2)
+    assert np.abs(np.einsum("nij,nkj->nik", g, g.conj()) - eye).max() < 1e-14
+    assert np.abs(np.linalg.det(g) - 1).max() < 1e-14
+    r0 = np.einsum("nij,ji->n", g, k).real / (2.0 * n)
+    assert r0.min() >= -1 - 1e-12 and r0.max() <= 1 + 1e-12
+    assert scipy.stats.kstest(r0, _r0_cdf(kappa)).pvalue > 1e-3
+    mean = scipy.special.iv(2, kappa) / scipy.special.iv(1, kappa)
+    assert abs(r0.mean() - mean) < 5 * r0.std() / math.sqrt(len(r0))
+    # w = g qhat: its vector part points uniformly over the sphere
+    w = g @ (q / n)
+    vec = np.stack([w[:, 0, 1].imag, w[:, 0, 1].real, w[:, 0, 0].imag], axis=1)
+    assert np.abs(w[:, 0, 0].real - r0).max() < 1e-12
+    nv = vec / np.linalg.norm(vec, axis=1, keepdims=True)
+    for i in range(3):
+        assert scipy.stats.kstest(nv[:, i], scipy.stats.uniform(-1, 2).cdf).pvalue > 1e-3
+
+
+def test_heat_bath_zero_block_draws_haar():
+    """A block with n = 0 carries no weight: g is Haar-distributed (E[Re tr g] = 0,
+    Re tr g / 2 has the kappa = 0 density sqrt(1 - r^2))."""
+    g, capped = oracle.hb_subgroup_draws(np.zeros((2, 2)), 0.7, 3, 40000)
+    assert capped == 0
+    r0 = np.trace(g, axis1=1, axis2=2).real / 2
+    assert scipy.stats.kstest(r0, _r0_cdf(0.0)).pvalue > 1e-3
+
+
+def test_anneal_schedule_endpoints():
+    """T falls linearly from T0 at the first annealing sweep to T1 at the last: a
+    2-sweep anneal equals one sweep at T0 then one at T1 (sweep counter 1), and a
+    3-sweep anneal takes (T0 + T1)/2 in the middle, bitwise."""
+    dims = SMALL
+    u = gi.gen_links(dims, 1.0, 10)
+    T0, T1 = 1.25, 0.01
+    a = u.copy()
+    oracle.anneal(a, dims, 2, T0, T1, 42)
+    b = u.copy()
+    oracle.anneal(b, dims, 1, T0, T0, 42, 0)
+    oracle.anneal(b, dims, 1, T1, T1, 42, 1)
+    assert np.array_equal(a, b)
+    a = u.copy()
+    oracle.anneal(a, dims, 3, T0, T1, 42)
+    b = u.copy()
+    oracle.anneal(b, dims, 1, T0, T0, 42, 0)
+    Tm = T0 + (T1 - T0) * 1.0 / 2.0
+    oracle.anneal(b, dims, 1, Tm, Tm, 42, 1)
+    oracle.anneal(b, dims, 1, T1, T1, 42, 2)
+    assert np.array_equal(a, b)
+    c = u.copy()
+    oracle.anneal(c, dims, 1, T0, T0, 42, 1)  # the same temperature on another sweep counter
+    assert not np.array_equal(c, b)
+
+
+def _ulp_growth(dims, seed, temps):
+    u = gi.gen_links(dims, 1.0, seed)
+    v = np.nextafter(u, np.inf)
+    d = []
+    for s, T in enumerate(temps):
+        oracle.anneal(u, dims, 1, T, T, 5, s)
+        oracle.anneal(v, dims, 1, T, T, 5, s)
+        d.append(float(np.abs(u - v).max()))
+    return np.array(d)
+
+
+def test_heat_bath_rounding_growth_sets_parity_length():
+    """Why the heat-bath parity run is 5 sweeps of the schedule 1.25 -> 0.01: the
+    oracle against itself from inputs one ulp apart.  Hot sweeps (T = 1.25) amplify a
+    rounding difference about 2.7x per sweep (the drawn elements depend smoothly on K
+    until an accept test flips); cold ones (T <= 0.3) hardly at all.  Over 5 schedule
+    sweeps the difference stays below 1e-13, a tenth of the 1e-12 bound; over 20 it
+    passes 1e-12, so longer anneals are compared through theta, F and the plaquette."""
+    dims = (8, 8, 8, 8)
+    hot = _ulp_growth(dims, 13, [1.25] * 12)
+    rate_hot = (hot[-1] / hot[0]) ** (1.0 / 11)
+    cold = _ulp_growth(dims, 13, [0.05] * 12)
+    rate_cold = (cold[-1] / cold[0]) ** (1.0 / 11)
+    assert 1.8 < rate_hot < 4.0, rate_hot
+    assert rate_cold < 1.3, rate_cold
+    for seed in (11, 13):
+        five = _ulp_growth(dims, seed, [1.25 + (0.01 - 1.25) * s / 4 for s in range(5)])
+        assert five[-1] < 1e-13, five
+        twenty = _ulp_growth(dims, seed, [1.25 + (0.01 - 1.25) * s / 19 for s in range(20)])
+        assert twenty[-1] > 1e-12, twenty
+
+
 # --------------------------------------------------------------- generator ---
 
 
