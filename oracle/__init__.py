@@ -46,6 +46,11 @@ __all__ = [
     "hb_sample_r0",
     "hb_sample_su2",
     "hb_subgroup_draws",
+    "coulomb_half_sweep",
+    "coulomb_sweep",
+    "coulomb_update_sites_in_order",
+    "coulomb_measure",
+    "coulomb_fix_until",
 ]
 
 OR_EXACT = 0
@@ -115,6 +120,14 @@ def _declare(L):
     L.oracle_hb_sample_r0.restype = ctypes.c_int64
     L.oracle_hb_sample_su2.argtypes = [ctypes.c_double, ctypes.c_uint64, ctypes.c_int64, _dp]
     L.oracle_hb_sample_su2.restype = ctypes.c_int64
+    L.oracle_coulomb_half_sweep.argtypes = [_dp, _ip, ctypes.c_int, ctypes.c_double, ctypes.c_int]
+    L.oracle_coulomb_sweep.argtypes = [_dp, _ip, ctypes.c_int32, ctypes.c_double, ctypes.c_int]
+    L.oracle_coulomb_update_sites_in_order.argtypes = [_dp, _ip, _i64p, ctypes.c_int64, ctypes.c_double,
+                                                       ctypes.c_int]
+    L.oracle_coulomb_measure.argtypes = [_dp, _ip, _dp, _dp]
+    L.oracle_coulomb_fix_until.argtypes = [_dp, _ip, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                           ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _ip, _dp, _dp]
+    L.oracle_coulomb_fix_until.restype = ctypes.c_int
     L.oracle_hb_subgroup_draws.argtypes = [_dp, ctypes.c_double, ctypes.c_uint64, ctypes.c_int64, _dp]
     L.oracle_hb_subgroup_draws.restype = ctypes.c_int64
     L.oracle_num_threads.restype = ctypes.c_int
@@ -327,3 +340,54 @@ def hb_subgroup_draws(k, T: float, seed: int, n: int):
     capped = lib().oracle_hb_subgroup_draws(_p(kk.view(np.float64)), float(T), int(seed), int(n),
                                             _p(out.view(np.float64)))
     return out, int(capped)
+
+
+# ------------------------------------------------------------- Coulomb gauge --
+
+
+def coulomb_half_sweep(u, dims, colour: int, omega: float, mode: int = OR_EXACT):
+    """Coulomb-gauge overrelaxation over the sites of one colour (in place)."""
+    u = _links(u)
+    d = _dims(dims, u)
+    lib().oracle_coulomb_half_sweep(_p(u), _p(d, _ip), int(colour), float(omega), int(mode))
+    return u
+
+
+def coulomb_sweep(u, dims, nsweeps: int, omega: float, mode: int = OR_EXACT):
+    u = _links(u)
+    d = _dims(dims, u)
+    lib().oracle_coulomb_sweep(_p(u), _p(d, _ip), int(nsweeps), float(omega), int(mode))
+    return u
+
+
+def coulomb_update_sites_in_order(u, dims, sites, omega: float, mode: int = OR_EXACT):
+    u = _links(u)
+    d = _dims(dims, u)
+    s = np.ascontiguousarray(np.asarray(sites, dtype=np.int64))
+    lib().oracle_coulomb_update_sites_in_order(_p(u), _p(d, _ip), _p(s, _i64p), len(s), float(omega), int(mode))
+    return u
+
+
+def coulomb_measure(u, dims):
+    """(theta_C(t), F_C(t)) per timeslice t, as two arrays of Nt."""
+    u = _links(u)
+    d = _dims(dims, u)
+    th = np.empty(int(d[3]))
+    fr = np.empty(int(d[3]))
+    lib().oracle_coulomb_measure(_p(u), _p(d, _ip), _p(th), _p(fr))
+    return th, fr
+
+
+def coulomb_fix_until(u, dims, omega: float = 1.7, mode: int = OR_EXACT, theta_target: float = 1e-12,
+                      max_sweeps: int = 3000, check_every: int = 10, reunit_every: int = 100) -> dict:
+    """Coulomb fix-until in place: theta = max over timeslices, F = mean over timeslices."""
+    u = _links(u)
+    d = _dims(dims, u)
+    sw = ctypes.c_int32()
+    th = ctypes.c_double()
+    f = ctypes.c_double()
+    conv = lib().oracle_coulomb_fix_until(_p(u), _p(d, _ip), float(omega), int(mode), float(theta_target),
+                                          int(max_sweeps), int(check_every), int(reunit_every),
+                                          ctypes.byref(sw), ctypes.byref(th), ctypes.byref(f))
+    return dict(converged=bool(conv), sweeps=sw.value, theta=th.value, F=f.value)
+

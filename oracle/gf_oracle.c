@@ -39,6 +39,9 @@
  *                            the standard SU(2)-subgroup heat bath (Creutz
  *                            sampler for small kappa, Kennedy-Pendleton above)
  *                            driven by Philox4x32-10 (Salmon et al., SC'11).
+ *   oracle_coulomb_* ....... Coulomb gauge (abstract, Sec. 1): the same
+ *                            iteration with K, Delta and F over the spatial
+ *                            directions only, per timeslice.
  *   oracle_reunitarize ..... Gram-Schmidt of rows 0 and 1, row 2 rebuilt as
  *                            the conjugated cross product (the two-row
  *                            representation of Sec. 3.1 keeps row 2 implicit).
@@ -185,11 +188,13 @@ static double m_retr(const cx* a)
 /* the local problem at one site                                       */
 /* ------------------------------------------------------------------ */
 
-/* K(x) = sum_mu [ U_mu(x) + U_mu(x - mu^)^dagger ]   (Eq. localfunctional) */
-static void local_K(const double* U, const geom* g, long s, cx* K)
+/* K(x) = sum_mu [ U_mu(x) + U_mu(x - mu^)^dagger ]   (Eq. localfunctional),
+ * mu over the first ndir directions: 4 for Landau gauge, 3 (x, y, z) for
+ * Coulomb gauge. */
+static void local_K(const double* U, const geom* g, long s, int ndir, cx* K)
 {
     m_zero(K);
-    for (int mu = 0; mu < 4; ++mu) {
+    for (int mu = 0; mu < ndir; ++mu) {
         const cx* f = clink_at(U, s, mu);
         const cx* b = clink_at(U, hop(g, s, mu, -1), mu);
         for (int i = 0; i < 3; ++i)
@@ -304,14 +309,16 @@ static void embed(const cx* g2, int i, int j, cx* S)
     S[3 * j + j] = g2[3];
 }
 
-/* One overrelaxation update of site s; returns the change of Re tr K(x). */
-static double or_site_update(double* U, const geom* g, long s, double omega, int mode)
+/* One overrelaxation update of site s; returns the change of Re tr K(x).  K
+ * sums the first ndir directions; the transformation acts on all 8 links at
+ * s (a gauge transformation, Sec. 2). */
+static double or_site_update(double* U, const geom* g, long s, double omega, int mode, int ndir)
 {
     double gain = 0.0;
     for (int sg = 0; sg < 3; ++sg) {
         int i = SUBGROUP[sg][0], j = SUBGROUP[sg][1];
         cx K[9], k[4], g2[4], S[9], SK[9];
-        local_K(U, g, s, K);
+        local_K(U, g, s, ndir, K);
         block_of(K, i, j, k);
         if (!oracle_su2_maximiser((const double*)k, (double*)g2)) continue;
         oracle_su2_overrelax((const double*)g2, omega, mode, (double*)g2);
@@ -326,7 +333,7 @@ static double or_site_update(double* U, const geom* g, long s, double omega, int
 double oracle_site_update(double* U, const int32_t* dims, int64_t site, double omega, int mode)
 {
     geom g = mkgeom(dims);
-    return or_site_update(U, &g, (long)site, omega, mode);
+    return or_site_update(U, &g, (long)site, omega, mode, 4);
 }
 
 /* Update every site of one colour (0 = black = even x+y+z+t).  Sites of one
@@ -336,7 +343,7 @@ void oracle_half_sweep(double* U, const int32_t* dims, int colour, double omega,
     geom g = mkgeom(dims);
 #pragma omp parallel for schedule(static) if (g.V >= OMP_MIN_SITES)
     for (long s = 0; s < g.V; ++s)
-        if (colour_of(&g, s) == colour) or_site_update(U, &g, s, omega, mode);
+        if (colour_of(&g, s) == colour) or_site_update(U, &g, s, omega, mode, 4);
 }
 
 /* Sequential updates in a caller-given order (for the order-independence check). */
@@ -344,7 +351,7 @@ void oracle_update_sites_in_order(double* U, const int32_t* dims, const int64_t*
                                   double omega, int mode)
 {
     geom g = mkgeom(dims);
-    for (int64_t i = 0; i < n; ++i) or_site_update(U, &g, (long)sites[i], omega, mode);
+    for (int64_t i = 0; i < n; ++i) or_site_update(U, &g, (long)sites[i], omega, mode, 4);
 }
 
 void oracle_sweep(double* U, const int32_t* dims, int32_t nsweeps, double omega, int mode)
@@ -370,12 +377,13 @@ static void gauge_potential(const cx* u, cx* A)
     A[8] -= tr;
 }
 
-/* tr[Delta(x) Delta(x)^dag] with Delta(x) = sum_mu (A_mu(x) - A_mu(x - mu^)) */
-static double theta_site(const double* U, const geom* g, long s)
+/* tr[Delta(x) Delta(x)^dag] with Delta(x) = sum_mu (A_mu(x) - A_mu(x - mu^)),
+ * mu over the first ndir directions (4: Landau, 3: Coulomb). */
+static double theta_site(const double* U, const geom* g, long s, int ndir)
 {
     cx D[9], A[9], Dd[9], P[9];
     m_zero(D);
-    for (int mu = 0; mu < 4; ++mu) {
+    for (int mu = 0; mu < ndir; ++mu) {
         gauge_potential(clink_at(U, s, mu), A);
         for (int i = 0; i < 9; ++i) D[i] += A[i];
         gauge_potential(clink_at(U, hop(g, s, mu, -1), mu), A);
@@ -390,7 +398,7 @@ void oracle_theta_density(const double* U, const int32_t* dims, double* out)
 {
     geom g = mkgeom(dims);
 #pragma omp parallel for schedule(static) if (g.V >= OMP_MIN_SITES)
-    for (long s = 0; s < g.V; ++s) out[s] = theta_site(U, &g, s);
+    for (long s = 0; s < g.V; ++s) out[s] = theta_site(U, &g, s, 4);
 }
 
 /* theta = (1/(N_c V)) sum_x tr[Delta Delta^dag],
@@ -404,7 +412,7 @@ void oracle_measure(const double* U, const int32_t* dims, double* theta, double*
     double* fr = (double*)malloc(sizeof(double) * (size_t)g.V);
 #pragma omp parallel for schedule(static) if (g.V >= OMP_MIN_SITES)
     for (long s = 0; s < g.V; ++s) {
-        th[s] = theta_site(U, &g, s);
+        th[s] = theta_site(U, &g, s, 4);
         double f = 0.0;
         for (int mu = 0; mu < 4; ++mu) f += m_retr(clink_at(U, s, mu));
         fr[s] = f;
@@ -484,7 +492,7 @@ static double fp32_floor_site(const double* U, const geom* g, long s)
     float dr[9], di[9];
     delta_f32(kr, ki, dr, di);
     cx K[9], D[9];
-    local_K(U, g, s, K);
+    local_K(U, g, s, 4, K);
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) D[3 * i + j] = (K[3 * i + j] - conj(K[3 * j + i])) / (2.0 * I);
     const cx t = (D[0] + D[4] + D[8]) / 3.0;
@@ -652,6 +660,112 @@ int oracle_fix_until(double* U, const int32_t* dims, double omega, int mode, dou
 }
 
 /* ------------------------------------------------------------------ */
+/* Coulomb gauge                                                       */
+/* ------------------------------------------------------------------ */
+
+/* Coulomb gauge (abstract and Sec. 1 list it beside Landau gauge): the
+ * condition and functional of Sec. 2 with mu restricted to the spatial
+ * directions x, y, z.  The functional sum_x sum_i Re tr[g(x) U_i(x)
+ * g(x+i^)^dag] decouples into one independent problem per timeslice, so the
+ * site update maximises Re tr[g(x) K_C(x)] with K_C(x) = sum_i [U_i(x) +
+ * U_i(x-i^)^dag]; g(x) is a gauge transformation and acts on all 8 links at x,
+ * the temporal ones included, which keeps the configuration on its gauge
+ * orbit.  Per timeslice t (V_3 = Nx Ny Nz sites):
+ *   theta_C(t) = (1/(N_c V_3)) sum_{x in t} tr[Delta_C Delta_C^dag],
+ *   Delta_C(x) = sum_i (A_i(x) - A_i(x - i^)),
+ *   F_C(t)     = (1/((N_d - 1) N_c V_3)) sum_{x in t} sum_i Re tr U_i(x). */
+
+void oracle_coulomb_half_sweep(double* U, const int32_t* dims, int colour, double omega, int mode)
+{
+    geom g = mkgeom(dims);
+#pragma omp parallel for schedule(static) if (g.V >= OMP_MIN_SITES)
+    for (long s = 0; s < g.V; ++s)
+        if (colour_of(&g, s) == colour) or_site_update(U, &g, s, omega, mode, 3);
+}
+
+void oracle_coulomb_sweep(double* U, const int32_t* dims, int32_t nsweeps, double omega, int mode)
+{
+    for (int32_t k = 0; k < nsweeps; ++k) {
+        oracle_coulomb_half_sweep(U, dims, 0, omega, mode);
+        oracle_coulomb_half_sweep(U, dims, 1, omega, mode);
+    }
+}
+
+/* Sequential Coulomb updates in a caller-given order. */
+void oracle_coulomb_update_sites_in_order(double* U, const int32_t* dims, const int64_t* sites, int64_t n,
+                                          double omega, int mode)
+{
+    geom g = mkgeom(dims);
+    for (int64_t i = 0; i < n; ++i) or_site_update(U, &g, (long)sites[i], omega, mode, 3);
+}
+
+/* theta_C(t) and F_C(t) for every timeslice t = 0 .. Nt-1 (arrays of Nt);
+ * per-site terms summed in site order. */
+void oracle_coulomb_measure(const double* U, const int32_t* dims, double* theta_t, double* F_t)
+{
+    geom g = mkgeom(dims);
+    const long V3 = g.V / g.n[3];
+    double* th = (double*)malloc(sizeof(double) * (size_t)g.V);
+    double* fr = (double*)malloc(sizeof(double) * (size_t)g.V);
+#pragma omp parallel for schedule(static) if (g.V >= OMP_MIN_SITES)
+    for (long s = 0; s < g.V; ++s) {
+        th[s] = theta_site(U, &g, s, 3);
+        double f = 0.0;
+        for (int i = 0; i < 3; ++i) f += m_retr(clink_at(U, s, i));
+        fr[s] = f;
+    }
+    for (int t = 0; t < g.n[3]; ++t) {
+        double st = 0.0, sf = 0.0;
+        for (long s = (long)t * V3; s < (long)(t + 1) * V3; ++s) {
+            st += th[s];
+            sf += fr[s];
+        }
+        theta_t[t] = st / (3.0 * (double)V3);
+        F_t[t] = sf / (9.0 * (double)V3);
+    }
+    free(th);
+    free(fr);
+}
+
+/* As oracle_fix_until for Coulomb gauge: the stop test is max_t theta_C(t) <
+ * target (every timeslice satisfies the condition).  *theta_out = that
+ * maximum, *F_out = the mean of F_C(t) over timeslices. */
+int oracle_coulomb_fix_until(double* U, const int32_t* dims, double omega, int mode, double theta_target,
+                             int32_t max_sweeps, int32_t check_every, int32_t reunit_every, int32_t* sweeps_out,
+                             double* theta_out, double* F_out)
+{
+    geom g = mkgeom(dims);
+    const int nt = g.n[3];
+    double* th = (double*)malloc(sizeof(double) * (size_t)nt);
+    double* fr = (double*)malloc(sizeof(double) * (size_t)nt);
+    double theta = 0.0, F = 0.0;
+    int32_t sweeps = 0;
+    for (;;) {
+        oracle_coulomb_measure(U, dims, th, fr);
+        theta = 0.0;
+        F = 0.0;
+        for (int t = 0; t < nt; ++t) {
+            if (th[t] > theta) theta = th[t];
+            F += fr[t];
+        }
+        F /= (double)nt;
+        if (!(theta >= theta_target) || sweeps >= max_sweeps) break;
+        int32_t n = max_sweeps - sweeps < check_every ? max_sweeps - sweeps : check_every;
+        for (int32_t k = 0; k < n; ++k) {
+            oracle_coulomb_sweep(U, dims, 1, omega, mode);
+            ++sweeps;
+            if (reunit_every > 0 && sweeps % reunit_every == 0) oracle_reunitarize(U, 4 * (int64_t)g.V);
+        }
+    }
+    free(th);
+    free(fr);
+    *sweeps_out = sweeps;
+    *theta_out = theta;
+    *F_out = F;
+    return theta < theta_target;
+}
+
+/* ------------------------------------------------------------------ */
 /* Philox4x32-10 and the heat-bath prelude                             */
 /* ------------------------------------------------------------------ */
 
@@ -782,7 +896,7 @@ static void hb_site_update(double* U, const geom* g, long s, double T, const uin
     for (int sg = 0; sg < 3; ++sg) {
         int i = SUBGROUP[sg][0], j = SUBGROUP[sg][1];
         cx K[9], k[4], g2[4], S[9];
-        local_K(U, g, s, K);
+        local_K(U, g, s, 4, K);
         block_of(K, i, j, k);
         hb_stream st = {{key[0], key[1]}, (uint32_t)s, sweep, (uint32_t)sg, 0u};
         hb_subgroup_element(k, T, &st, capped, g2);
