@@ -231,6 +231,27 @@ gf_status gf_fix_until(gf_lattice lat, const gf_fix_params* params, gf_fix_resul
  * lattice.  gf_fix_until calls it when theta_switch < 0.  Syncs. */
 gf_status gf_tune_switch(gf_lattice lat, double theta_target, double* floor, double* theta_switch);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): theta and F
+ * exactly as gf_measure_theta_F computes them (same kernels, same reduction
+ * order: bitwise equal to gf_measure_theta_F of a GF_FP64 lattice holding the
+ * same links), over links the caller holds on the current device.
+ *   dims       extents (even, >= 2), at most 2^24 sites (GF_E_ARG beyond:
+ *              the reduction scratch is a fixed 1 MiB device array)
+ *   dev_links  device canonical float64 array of 4*V*18 doubles (layout of
+ *              the conventions above), read only; rows 0 and 1 of each link
+ *              are read and row 2 is rebuilt from them
+ *   dev_out    device array of 2 doubles: theta, then F
+ *   hip_stream a hipStream_t of the current device (NULL = default stream)
+ * Async: only enqueues kernels (no allocation, no memset, no copy, no
+ * synchronisation), so it may be captured into a hipGraph; the caller checks
+ * dev_out for NaN/Inf.  The scratch is one array per device, shared by every
+ * call on that device: calls that overlap on one device race (serialise them
+ * on one stream).  The first call on a device looks up that device's copy of
+ * the array (hipGetSymbolAddress) and must not itself be under capture. */
+gf_status gf_measure_theta_F_noalloc(const int32_t dims[4], const double* dev_links, double* dev_out,
+                                     void* hip_stream);
+
 /* Reunitarise every link: Gram-Schmidt of rows 0 and 1 (row 2 is implicit).  Async. */
 gf_status gf_reunitarize(gf_lattice lat);
 

@@ -46,6 +46,44 @@ bool make_fastdiv(uint32_t d, uint32_t limit, FastDiv* out)
     return true;
 }
 
+// Geometry of a lattice of extents dims (each even and >= 2, V <= 2^31;
+// checked by the caller).  False if a magic-number division fails its check.
+bool make_geom(const int32_t dims[4], Geom* out)
+{
+    Geom g{};
+    int64_t V = 1;
+    for (int m = 0; m < 4; ++m) {
+        g.n[m] = dims[m];
+        V *= dims[m];
+    }
+    g.hx = dims[0] / 2;
+    g.vh = (uint32_t)(V / 2);
+    g.ld = (g.vh + gf::kLinkTile - 1) / gf::kLinkTile * gf::kLinkTile;  // whole tiles of the link layout
+    g.hs1 = (uint32_t)g.hx;
+    g.hs2 = (uint32_t)g.hx * (uint32_t)dims[1];
+    g.hs3 = g.hs2 * (uint32_t)dims[2];
+    if (!make_fastdiv((uint32_t)g.hx, g.vh, &g.div_hx) ||
+        !make_fastdiv((uint32_t)dims[1], g.vh / (uint32_t)g.hx, &g.div_ny) ||
+        !make_fastdiv((uint32_t)dims[2], g.vh / g.hs2, &g.div_nz))
+        return false;
+    *out = g;
+    return true;
+}
+
+// Extents each even and >= 2 with at most 2^31 sites; *V receives the volume.
+gf_status check_dims(const int32_t dims[4], int64_t* V)
+{
+    if (!dims) return fail(GF_E_ARG, "null extents");
+    int64_t v = 1;
+    for (int m = 0; m < 4; ++m) {
+        if (dims[m] < 2 || dims[m] % 2 != 0)
+            return fail(GF_E_ARG, "extent %d of direction %d must be even and >= 2", dims[m], m);
+        v *= dims[m];
+    }
+    if (v > (int64_t)1 << 31) return fail(GF_E_ARG, "volume %lld exceeds 2^31 sites", (long long)v);
+    *V = v;
+    return GF_OK;
+}
 
 LinkField<double> field64(const gf_lattice_* L)
 {
@@ -258,12 +296,7 @@ gf_status gf_create_lattice(const int32_t dims[4], gf_prec prec, void* hip_strea
     if (!dims || !out) return fail(GF_E_ARG, "null argument");
     *out = nullptr;
     int64_t V = 1;
-    for (int m = 0; m < 4; ++m) {
-        if (dims[m] < 2 || dims[m] % 2 != 0)
-            return fail(GF_E_ARG, "extent %d of direction %d must be even and >= 2", dims[m], m);
-        V *= dims[m];
-    }
-    if (V > (int64_t)1 << 31) return fail(GF_E_ARG, "volume %lld exceeds 2^31 sites", (long long)V);
+    GF_TRY(check_dims(dims, &V));
     if (prec != GF_FP64 && prec != GF_FP32 && prec != GF_MIXED)
         return fail(GF_E_ARG, "unsupported precision %d", (int)prec);
 
@@ -275,16 +308,7 @@ gf_status gf_create_lattice(const int32_t dims[4], gf_prec prec, void* hip_strea
     L->volume = V;
 
     Geom& g = L->geom;
-    for (int m = 0; m < 4; ++m) g.n[m] = dims[m];
-    g.hx = dims[0] / 2;
-    g.vh = (uint32_t)(V / 2);
-    g.ld = (g.vh + gf::kLinkTile - 1) / gf::kLinkTile * gf::kLinkTile;  // whole tiles of the link layout
-    g.hs1 = (uint32_t)g.hx;
-    g.hs2 = (uint32_t)g.hx * (uint32_t)dims[1];
-    g.hs3 = g.hs2 * (uint32_t)dims[2];
-    if (!make_fastdiv((uint32_t)g.hx, g.vh, &g.div_hx) ||
-        !make_fastdiv((uint32_t)dims[1], g.vh / (uint32_t)g.hx, &g.div_ny) ||
-        !make_fastdiv((uint32_t)dims[2], g.vh / g.hs2, &g.div_nz)) {
+    if (!make_geom(dims, &g)) {
         delete L;
         return fail(GF_E_ARG, "internal: index division check failed");
     }

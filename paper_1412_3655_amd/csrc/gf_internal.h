@@ -59,6 +59,8 @@ gf_status fail(gf_status st, const char* fmt, ...);
     } while (0)
 
 bool make_fastdiv(uint32_t d, uint32_t limit, FastDiv* out);
+bool make_geom(const int32_t dims[4], Geom* out);
+gf_status check_dims(const int32_t dims[4], int64_t* V);
 LinkField<double> field64(const gf_lattice_* L);
 LinkField<float> field32(const gf_lattice_* L);
 bool is_fp32(const gf_lattice_* L);

@@ -39,6 +39,9 @@ hipError_t launch_hb_half_sweep(const LinkField<float>& f, const Geom& g, int pa
 uint32_t measure_blocks(const Geom& g);
 hipError_t launch_measure(const LinkField<double>& f, const Geom& g, double* partial, double* out, hipStream_t st);
 hipError_t launch_measure(const LinkField<float>& f, const Geom& g, double* partial, double* out, hipStream_t st);
+// The same over links in the ABI's canonical float64 array (device), read in
+// place; bitwise equal to launch_measure over the packed float64 field.
+hipError_t launch_measure_canonical(const double* canon, const Geom& g, double* partial, double* out, hipStream_t st);
 
 // out[0] = (1/(3V)) sum_x tr[E E^dag], E = Delta computed in float32 from the
 // float32-rounded links minus Delta in float64: the float32 rounding floor of

@@ -25,8 +25,8 @@ constexpr int RBLOCK = 256;
 // the second read of a link (from its other end, a few planes away) follows
 // the first while the Infinity Cache still holds it, instead of half a lattice
 // later.  Partial (p, b) holds the same sites whatever the dispatch order.
-template <typename R>
-__global__ void __launch_bounds__(RBLOCK) k_measure(LinkField<R> f, Geom g, double* partial)
+template <typename Field>
+__global__ void __launch_bounds__(RBLOCK) k_measure(Field f, Geom g, double* partial)
 {
     const int parity = (int)(blockIdx.x & 1u);
     const uint32_t tile = blockIdx.x >> 1;
@@ -306,11 +306,11 @@ uint32_t site_blocks(const Geom& g)
     return (g.vh + RBLOCK - 1) / RBLOCK;
 }
 
-template <typename R>
-hipError_t measure_impl(const LinkField<R>& f, const Geom& g, double* partial, double* out, hipStream_t st)
+template <typename Field>
+hipError_t measure_impl(const Field& f, const Geom& g, double* partial, double* out, hipStream_t st)
 {
     const uint32_t nb = site_blocks(g);
-    hipLaunchKernelGGL((k_measure<R>), dim3(2 * nb), dim3(RBLOCK), 0, st, f, g, partial);
+    hipLaunchKernelGGL((k_measure<Field>), dim3(2 * nb), dim3(RBLOCK), 0, st, f, g, partial);
     const double V = 2.0 * (double)g.vh;
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RBLOCK), 0, st, partial, 2 * nb, 1.0 / (3.0 * V), 1.0 / (12.0 * V),
                        out);
@@ -391,6 +391,10 @@ hipError_t launch_measure(const LinkField<double>& f, const Geom& g, double* p, 
 hipError_t launch_measure(const LinkField<float>& f, const Geom& g, double* p, double* o, hipStream_t st)
 {
     return measure_impl(f, g, p, o, st);
+}
+hipError_t launch_measure_canonical(const double* canon, const Geom& g, double* p, double* o, hipStream_t st)
+{
+    return measure_impl(CanonField{canon, g}, g, p, o, st);
 }
 hipError_t launch_plaquette(const LinkField<double>& f, const Geom& g, double* p, double* o, hipStream_t st)
 {

@@ -344,6 +344,31 @@ __device__ __forceinline__ void load_full_f64(const LinkField<R>& f, int parity,
     rebuild_row2(u);
 }
 
+// Links read in place from the ABI's canonical float64 array
+// [site][mu][row][col][re,im], lexicographic site x + Nx(y + Ny(z + Nz t)).
+// The half index h of (parity, h) is lex >> 1 (Nx is even), so
+// lex = 2h + (x & 1).  Rows 0 and 1 are read and row 2 is rebuilt from them,
+// exactly as from the 12-real device layout, so every measurement over a
+// CanonField equals the one over the packed float64 field of the same links.
+struct CanonField {
+    const double* base;
+    Geom g;
+};
+
+__device__ __forceinline__ void load_full_f64(const CanonField& f, int parity, int mu, uint32_t h, M3<double>& u)
+{
+    const Site s = decode_site(f.g, parity, h);
+    const size_t lex = 2 * (size_t)h + (size_t)(s.x & 1);
+    const double2* p = (const double2*)(f.base + (lex * 4 + (size_t)mu) * 18);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const double2 v = p[c];
+        u.re[c / 3][c % 3] = v.x;
+        u.im[c / 3][c % 3] = v.y;
+    }
+    rebuild_row2(u);
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -397,8 +422,8 @@ __device__ __forceinline__ void finalize_pairs(const double* partial, uint32_t n
 // Gauge-condition and functional terms of the site (parity, h), float64:
 // th = tr[Delta Delta^dag] with Delta = [(K - K^dag)/(2i)]_traceless (equal to
 // Eq. (landaugauge) with A_mu of Sec. 2, a g = 1), fr = sum_mu Re tr U_mu(x).
-template <typename R>
-__device__ __forceinline__ void measure_site(const LinkField<R>& f, const Geom& g, int parity, uint32_t h, double& th,
+template <typename Field>
+__device__ __forceinline__ void measure_site(const Field& f, const Geom& g, int parity, uint32_t h, double& th,
                                              double& fr)
 {
     const Site s = decode_site(g, parity, h);

@@ -132,6 +132,7 @@ _SIGNATURES = {
     "gf_half_sweep_or": [_vp, _i32, ctypes.c_double, ctypes.c_int],
     "gf_anneal": [_vp, _i32, ctypes.c_double, ctypes.c_double, ctypes.c_uint64],
     "gf_measure_theta_F": [_vp, _dp, _dp],
+    "gf_measure_theta_F_noalloc": [ctypes.POINTER(_i32), _vp, _vp, _vp],
     "gf_fix_until": [_vp, ctypes.POINTER(gf_fix_params), ctypes.POINTER(gf_fix_result)],
     "gf_tune_switch": [_vp, ctypes.c_double, _dp, _dp],
     "gf_reunitarize": [_vp],
@@ -396,6 +397,20 @@ def gf_measure_theta_F(lat):
     f = ctypes.c_double()
     _call("gf_measure_theta_F", lat, ctypes.byref(th), ctypes.byref(f))
     return th.value, f.value
+
+
+def gf_measure_theta_F_noalloc(dims, dev_links, dev_out, stream=None) -> None:
+    """theta, F of canonical device links into dev_out[0:2] (device float64), enqueued on
+    `stream` (default: torch's current stream) without allocating; async."""
+    import torch
+
+    d = [int(x) for x in dims]
+    volume = int(np.prod(d))
+    t = _device_links(dev_links, volume)
+    if dev_out.dtype != torch.float64 or not dev_out.is_cuda or not dev_out.is_contiguous() or dev_out.numel() < 2:
+        raise TypeError("dev_out must be a contiguous float64 device tensor of at least 2 elements")
+    h = _stream_handle(stream) if stream is not None else int(torch.cuda.current_stream().cuda_stream)
+    _call("gf_measure_theta_F_noalloc", (_i32 * 4)(*d), t.data_ptr(), dev_out.data_ptr(), h)
 
 
 def gf_fix_until(lat, omega: float = 1.7, mode: int = GF_OR_EXACT, theta_target: float = 1e-12,
