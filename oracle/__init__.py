@@ -51,6 +51,7 @@ __all__ = [
     "coulomb_update_sites_in_order",
     "coulomb_measure",
     "coulomb_fix_until",
+    "coulomb_anneal",
 ]
 
 OR_EXACT = 0
@@ -128,6 +129,9 @@ def _declare(L):
     L.oracle_coulomb_fix_until.argtypes = [_dp, _ip, ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                            ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _ip, _dp, _dp]
     L.oracle_coulomb_fix_until.restype = ctypes.c_int
+    L.oracle_coulomb_anneal.argtypes = [_dp, _ip, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_uint64, ctypes.c_int32]
+    L.oracle_coulomb_anneal.restype = ctypes.c_int64
     L.oracle_hb_subgroup_draws.argtypes = [_dp, ctypes.c_double, ctypes.c_uint64, ctypes.c_int64, _dp]
     L.oracle_hb_subgroup_draws.restype = ctypes.c_int64
     L.oracle_num_threads.restype = ctypes.c_int
@@ -391,3 +395,12 @@ def coulomb_fix_until(u, dims, omega: float = 1.7, mode: int = OR_EXACT, theta_t
                                           ctypes.byref(sw), ctypes.byref(th), ctypes.byref(f))
     return dict(converged=bool(conv), sweeps=sw.value, theta=th.value, F=f.value)
 
+
+
+def coulomb_anneal(u, dims, nsweeps: int, T0: float, T1: float, seed: int, sweep_offset: int = 0) -> int:
+    """Heat-bath sweeps of the Coulomb functional in place (K over x, y, z); returns the
+    count of rejection-capped subgroup updates."""
+    u = _links(u)
+    d = _dims(dims, u)
+    return int(lib().oracle_coulomb_anneal(_p(u), _p(d, _ip), int(nsweeps), float(T0), float(T1),
+                                           int(seed) & 0xFFFFFFFFFFFFFFFF, int(sweep_offset)))

@@ -41,7 +41,8 @@
  *                            driven by Philox4x32-10 (Salmon et al., SC'11).
  *   oracle_coulomb_* ....... Coulomb gauge (abstract, Sec. 1): the same
  *                            iteration with K, Delta and F over the spatial
- *                            directions only, per timeslice.
+ *                            directions only, per timeslice; the heat-bath
+ *                            prelude of the Coulomb functional likewise.
  *   oracle_reunitarize ..... Gram-Schmidt of rows 0 and 1, row 2 rebuilt as
  *                            the conjugated cross product (the two-row
  *                            representation of Sec. 3.1 keeps row 2 implicit).
@@ -889,14 +890,15 @@ static void hb_subgroup_element(const cx* k, double T, hb_stream* st, int* cappe
 }
 
 /* Heat-bath update of site s at temperature T: for every subgroup the new
- * element is drawn by hb_subgroup_element from the current block of K. */
+ * element is drawn by hb_subgroup_element from the current block of K, K
+ * summed over the first ndir directions (4: Landau, 3: Coulomb). */
 static void hb_site_update(double* U, const geom* g, long s, double T, const uint32_t* key, uint32_t sweep,
-                           int* capped)
+                           int* capped, int ndir)
 {
     for (int sg = 0; sg < 3; ++sg) {
         int i = SUBGROUP[sg][0], j = SUBGROUP[sg][1];
         cx K[9], k[4], g2[4], S[9];
-        local_K(U, g, s, 4, K);
+        local_K(U, g, s, ndir, K);
         block_of(K, i, j, k);
         hb_stream st = {{key[0], key[1]}, (uint32_t)s, sweep, (uint32_t)sg, 0u};
         hb_subgroup_element(k, T, &st, capped, g2);
@@ -918,8 +920,8 @@ static double anneal_temperature(int32_t s, int32_t n, double T0, double T1)
 /* n heat-bath sweeps (black then white) with the linear schedule; the Philox
  * key is the 64-bit seed and the sweep counter starts at sweep_offset.
  * Returns the number of subgroup updates that hit the rejection cap. */
-int64_t oracle_anneal(double* U, const int32_t* dims, int32_t nsweeps, double T0, double T1, uint64_t seed,
-                      int32_t sweep_offset)
+static int64_t anneal_ndir(double* U, const int32_t* dims, int32_t nsweeps, double T0, double T1, uint64_t seed,
+                           int32_t sweep_offset, int ndir)
 {
     geom g = mkgeom(dims);
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
@@ -930,11 +932,27 @@ int64_t oracle_anneal(double* U, const int32_t* dims, int32_t nsweeps, double T0
             int capped = 0;
 #pragma omp parallel for schedule(static) reduction(+ : capped) if (g.V >= OMP_MIN_SITES)
             for (long s = 0; s < g.V; ++s)
-                if (colour_of(&g, s) == c) hb_site_update(U, &g, s, T, key, (uint32_t)(sweep_offset + sw), &capped);
+                if (colour_of(&g, s) == c)
+                    hb_site_update(U, &g, s, T, key, (uint32_t)(sweep_offset + sw), &capped, ndir);
             capped_total += capped;
         }
     }
     return capped_total;
+}
+
+int64_t oracle_anneal(double* U, const int32_t* dims, int32_t nsweeps, double T0, double T1, uint64_t seed,
+                      int32_t sweep_offset)
+{
+    return anneal_ndir(U, dims, nsweeps, T0, T1, seed, sweep_offset, 4);
+}
+
+/* Simulated annealing of the Coulomb functional: the heat bath above with the
+ * weight exp(Re tr[g k_C]/T), k_C a block of the spatial K_C(x); g(x) still
+ * transforms all 8 links at x. */
+int64_t oracle_coulomb_anneal(double* U, const int32_t* dims, int32_t nsweeps, double T0, double T1, uint64_t seed,
+                              int32_t sweep_offset)
+{
+    return anneal_ndir(U, dims, nsweeps, T0, T1, seed, sweep_offset, 3);
 }
 
 /* Sampler checks: n draws of r0 (or of the SU(2) element as 4 reals) at a

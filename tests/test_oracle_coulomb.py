@@ -170,3 +170,57 @@ def test_coulomb_fix_until_converges_8x4():
     assert r["converged"] and r["sweeps"] < 3000
     th, F = oracle.coulomb_measure(u, dims)
     assert r["theta"] == th.max() and abs(r["F"] - F.mean()) < 1e-15
+
+
+def test_coulomb_anneal_timeslices_are_independent():
+    """The Coulomb heat bath draws each subgroup element from the block of K_C, which holds
+    spatial links of the site's timeslice only, and its Philox stream is keyed by the site:
+    spatial links of every other timeslice end bitwise identical when timeslice 0's spatial
+    links and all temporal links start elsewhere.  (A heat bath weighted by the Landau K,
+    temporal links included, fails this.)"""
+    dims = SMALL
+    a = gi.gen_links(dims, 0.8, 15)
+    b = a.copy()
+    other = gi.gen_links(dims, 0.5, 16)
+    t = gi.lex_coords(dims)[:, 3]
+    b[t == 0, :3] = other[t == 0, :3]
+    b[:, 3] = other[:, 3]
+    for u in (a, b):
+        assert oracle.coulomb_anneal(u, dims, 3, 1.25, 0.5, 77) == 0
+    keep = t != 0
+    assert np.array_equal(a[keep, :3], b[keep, :3])
+    assert not np.array_equal(a[~keep, :3], b[~keep, :3])
+
+
+def test_coulomb_anneal_is_a_gauge_transformation():
+    """Annealing moves along the gauge orbit: every plaquette unchanged, temporal links
+    transformed, links in SU(3), and the draws differ from the Landau heat bath's."""
+    dims = RAGGED
+    u = gi.gen_links(dims, 0.9, 17)
+    P0 = oracle.plaquette(u, dims)
+    land = u.copy()
+    u0 = u.copy()
+    assert oracle.coulomb_anneal(u, dims, 10, 1.25, 0.01, 5) == 0
+    oracle.anneal(land, dims, 10, 1.25, 0.01, 5)
+    assert abs(oracle.plaquette(u, dims) - P0) < 1e-12
+    assert not np.array_equal(u[:, 3], u0[:, 3])
+    assert np.abs(u - land).max() > 1e-3
+    du, dd = oracle.unitarity(u)
+    assert du < 1e-13 and dd < 1e-13
+
+
+def test_coulomb_anneal_cold_limit_is_the_maximiser():
+    """At T -> 0 the subgroup weight exp(2 n r0 / T) pins r0 to 1 (1 - r0 = O(T), the
+    direction off the maximiser O(sqrt(T))), so one heat-bath sweep is one omega = 1
+    overrelaxation sweep of the Coulomb functional up to O(sqrt(T)) in the links and in F_C
+    (later sites maximise against links already moved by O(sqrt(T)))."""
+    dims = SMALL
+    u = gi.gen_links(dims, 0.6, 18)
+    hb = u.copy()
+    orr = u.copy()
+    oracle.coulomb_anneal(hb, dims, 1, 1e-10, 1e-10, 3)
+    oracle.coulomb_sweep(orr, dims, 1, 1.0)
+    assert np.abs(hb - orr).max() < 1e-3
+    _, F_hb = oracle.coulomb_measure(hb, dims)
+    _, F_or = oracle.coulomb_measure(orr, dims)
+    assert np.abs(F_hb - F_or).max() < 1e-5
