@@ -63,6 +63,15 @@ typedef enum {
     GF_OR_BINOMIAL1 = 1
 } gf_or_mode;
 
+typedef enum {
+    /* Landau gauge (Sec. 2): functional and condition over all 4 directions. */
+    GF_LANDAU = 0,
+    /* Coulomb gauge (listed beside Landau gauge in the abstract and Sec. 1):
+     * the functional and condition of Sec. 2 with mu over x, y, z only, one
+     * independent problem per timeslice. */
+    GF_COULOMB = 1
+} gf_gauge;
+
 typedef struct {
     double omega;         /* overrelaxation parameter, 1 <= omega < 2 */
     int32_t mode;         /* gf_or_mode */
@@ -222,6 +231,34 @@ gf_status gf_measure_theta_F(gf_lattice lat, double* theta, double* F);
  * (converged = 0), not an error.  Syncs. */
 gf_status gf_fix_until(gf_lattice lat, const gf_fix_params* params, gf_fix_result* result);
 
+/* How gf_fix_until checks the gauge condition (default: adaptive = 0, an
+ * exact measurement after every check_every sweeps).  adaptive != 0: the
+ * last sweep of every check_every also sums tr[Delta(x) Delta(x)^dag] of
+ * each site's K(x), which the sweep forms anyway, just before the site's
+ * update (see gf_sweep_estimate), and the exact measurement (a separate pass
+ * reading every link twice) runs only where a decision can fall: when that
+ * estimate is below margin x the smallest deciding threshold (theta_target;
+ * in the float32 phase of GF_MIXED also theta_switch and the stall level
+ * 1e-10), at every float32-phase check once theta has been below the stall
+ * level, and at the last sweep.  The paper iterates until the condition holds
+ * to a given precision (Sec. 2); where the estimate stays above margin x
+ * every threshold no decision can be taken, so with a margin that covers the
+ * ratio of estimate to theta (>= 1; default 100) the sweep count, links, theta
+ * and F equal those of exact checks.  Does not touch the device. */
+gf_status gf_set_check_policy(gf_lattice lat, int32_t adaptive, double margin);
+
+/* One overrelaxation sweep (as gf_sweep_or with n_sweeps = 1) that also
+ * returns *theta_est = (1/(3V)) sum_x tr[Delta(x) Delta(x)^dag] with each
+ * site's Delta taken from its K(x) just before its update: the black sites'
+ * terms before the black half-sweep, the white sites' after it (Coulomb gauge:
+ * K_C and Delta_C, i.e. the mean over timeslices).  Per-block sums in float64
+ * added in a fixed order.  GF_E_NUMERIC if NaN.  Syncs. */
+gf_status gf_sweep_estimate(gf_lattice lat, double omega, gf_or_mode mode, double* theta_est);
+
+/* Exact measurements (gf_measure_theta_F, and those of gf_fix_until) and
+ * fused estimates taken on the lattice since its creation (may be NULL). */
+gf_status gf_lattice_counters(gf_lattice lat, int64_t* measures, int64_t* estimates);
+
 /* Switch point for the float32 -> float64 handover of GF_MIXED: *floor =
  * (1/(3V)) sum_x tr[E E^dag] with E = Delta(x) computed in float32 from the
  * float32-rounded float64 links minus Delta(x) in float64 (the float32
@@ -252,11 +289,45 @@ gf_status gf_tune_switch(gf_lattice lat, double theta_target, double* floor, dou
 gf_status gf_measure_theta_F_noalloc(const int32_t dims[4], const double* dev_links, double* dev_out,
                                      void* hip_stream);
 
-/* Reunitarise every link: Gram-Schmidt of rows 0 and 1 (row 2 is implicit).  Async. */
+/* Gauge fixed by the lattice's sweeps and measured by its measurements
+ * (default GF_LANDAU).  With GF_COULOMB (abstract and Sec. 1 name Coulomb
+ * gauge beside Landau gauge; its formulae are those of Sec. 2 restricted to the
+ * spatial directions):
+ *   - gf_sweep_or / gf_half_sweep_or / gf_anneal form
+ *     K_C(x) = sum_{i=x,y,z} [U_i(x) + U_i(x-i^)^dag] in place of K(x), and the
+ *     site's g(x) still transforms all 8 links at x, temporal ones included
+ *     (so the configuration stays on its gauge orbit); the heat bath weighs
+ *     each subgroup draw by exp(Re tr[g k_C]/T);
+ *   - gf_measure_theta_F returns theta = max over timeslices t of
+ *     theta_C(t) = (1/(3 V3)) sum_{x in t} tr[Delta_C Delta_C^dag],
+ *     Delta_C = [(K_C - K_C^dag)/(2i)]_traceless, and F = the mean over t of
+ *     F_C(t) = (1/(9 V3)) sum_{x in t} sum_i Re tr U_i(x), V3 = Nx Ny Nz;
+ *   - gf_fix_until therefore stops once every timeslice satisfies the
+ *     condition; with theta_switch < 0 a GF_MIXED lattice takes its switch
+ *     point from gf_tune_switch, i.e. from the float32 floor of the Landau
+ *     Delta (a performance heuristic: the result is float64 either way).
+ * The pool (gf_pool_*) fixes Landau gauge only.  GF_E_ARG for an unknown
+ * gauge, or GF_COULOMB with Nt > 65535.  Does not touch the device. */
+gf_status gf_set_gauge(gf_lattice lat, gf_gauge gauge);
+gf_status gf_get_gauge(gf_lattice lat, gf_gauge* gauge);
+
+/* Coulomb gauge: theta_C(t) and F_C(t) (see gf_set_gauge) of every timeslice
+ * t = 0..Nt-1 into two caller arrays of Nt doubles; float64 sums with a fixed
+ * reduction order.  GF_E_STATE on a GF_LANDAU lattice; GF_E_NUMERIC if a value
+ * is NaN/Inf.  Syncs. */
+gf_status gf_measure_timeslices(gf_lattice lat, double* theta_t, double* F_t);
+
+/* Reunitarise every link: Gram-Schmidt of rows 0 and 1 (row 2 is implicit).
+ * The paper defines no reunitarisation; it is needed because only two rows
+ * are stored (Sec. 3.1) and rounding drifts them off SU(3).  Rows are
+ * r0 <- r0/|r0|, r1 <- (r1 - <r0,r1> r0)/|.|, row 2 their conjugated cross
+ * product.  Async. */
 gf_status gf_reunitarize(gf_lattice lat);
 
 /* Average plaquette (1/(18V)) sum_x sum_{mu<nu} Re tr[U_mu(x) U_nu(x+mu^)
- * U_mu(x+nu^)^dag U_nu(x)^dag], float64 sums; gauge invariant.  Syncs. */
+ * U_mu(x+nu^)^dag U_nu(x)^dag], float64 sums.  Not part of the paper's
+ * method: a gauge-invariant observable (Sec. 2: gauge fixing moves along the
+ * gauge orbit) used to check that sweeps leave it unchanged.  Syncs. */
 gf_status gf_plaquette(gf_lattice lat, double* P);
 
 /* ------------------------------------------------------------------------ */
@@ -282,11 +353,13 @@ typedef struct {
     int32_t prec;        /* gf_prec of every job: GF_MIXED or GF_FP64 */
     int32_t check_every; /* sweeps per pool step = every job's measurement cadence, >= 1 */
     int32_t mode;        /* gf_or_mode of every job */
-    int32_t tps32, block32, tps64, block64; /* lanes per site of the pool's float32 / float64
-                                               overrelaxation sweeps (0 = default: 2 for float32, 1 for
-                                               float64; the pool's sweeps use 128-thread blocks, its
-                                               heat-bath sweeps one lane per site);
-                                               block32 / block64 configure the jobs' own lattices (0 = 256) */
+    int32_t tps32, block32, tps64, block64; /* shape of the pool's float32 / float64 overrelaxation
+                                               sweeps: lanes per site (1, 2 or 4; 0 = default: 2 for
+                                               float32, 1 for float64) and threads per block (64, 128
+                                               or 256; 0 = 128).  Every shape gives bitwise the same
+                                               links; gf_pool_autotune picks the fastest for the
+                                               resident jobs.  The heat-bath sweeps use one lane per
+                                               site and 128-thread blocks. */
 } gf_pool_config;
 
 typedef struct {
@@ -338,6 +411,23 @@ gf_status gf_pool_release(gf_pool pool, uint64_t job_id);
  * unaffected.  GF_E_STATE if the job has already finished, GF_E_ARG if no
  * such job is resident. */
 gf_status gf_pool_cancel(gf_pool pool, uint64_t job_id);
+
+/* Autotuner of the pool's batched overrelaxation sweep (threads per site and
+ * block size, Sec. 4 and 5 of the paper tune these at run time): copies the
+ * `kernel` links (GF_FP32: the float32 links and g(x) of a GF_MIXED pool;
+ * GF_FP64: the float64 links) of the resident jobs, in slot order and up to
+ * scratch_bytes of copies, times one warm-up and n_sweeps sweeps (both
+ * colours) of that set for every shape (lanes per site 1, 2, 4; threads per
+ * block 64, 128, 256) with HIP events, writes up to cap entries to table (may
+ * be NULL; nontemporal = the pool's cache policy, 0 float32, 1 float64), and
+ * makes the fastest the pool's shape for that kernel (*chosen, may be NULL).
+ * The jobs' links are not changed.  GF_E_STATE if no resident job fits in
+ * scratch_bytes.  Allocates and frees the copies.  Syncs. */
+gf_status gf_pool_autotune(gf_pool pool, int32_t kernel, int32_t n_sweeps, size_t scratch_bytes,
+                           gf_tune_entry* table, int32_t cap, int32_t* n_out, gf_tune_entry* chosen);
+
+/* The pool's current sweep shape (any pointer may be NULL). */
+gf_status gf_pool_get_shape(gf_pool pool, int32_t* tps32, int32_t* block32, int32_t* tps64, int32_t* block64);
 
 /* Resident jobs still iterating, finished jobs not yet released, and device bytes held. */
 gf_status gf_pool_stats(gf_pool pool, int32_t* active, int32_t* finished, int64_t* bytes_in_use);

@@ -85,6 +85,24 @@ gf_status check_dims(const int32_t dims[4], int64_t* V)
     return GF_OK;
 }
 
+// Device allocations of a lattice of geometry g and precision prec (sizes of
+// the buffers gf_create_lattice allocates; the pool's admission budget counts
+// exactly these).
+LatticeSizes lattice_sizes(const Geom& g, gf_prec prec)
+{
+    LatticeSizes z;
+    const size_t nchunks = (size_t)2 * 4 * g.ld;  // per chunk slot
+    if (prec == GF_FP64 || prec == GF_MIXED) z.f64 = nchunks * 6 * sizeof(double2);
+    if (prec == GF_FP32 || prec == GF_MIXED) z.f32 = nchunks * 3 * sizeof(float4);
+    if (prec == GF_MIXED) z.gacc = (size_t)2 * 3 * g.ld * sizeof(float4);
+    // partial sums of the whole-lattice reductions, or of the per-timeslice
+    // Coulomb ones, whichever needs more
+    z.partial = 2 * std::max((size_t)gf::measure_blocks(g), (size_t)gf::slice_partials(g));
+    z.nslices = 2 * (size_t)g.n[3];
+    z.total = (int64_t)(z.f64 + z.f32 + z.gacc + (z.partial + 4 + z.nslices) * sizeof(double));
+    return z;
+}
+
 LinkField<double> field64(const gf_lattice_* L)
 {
     return LinkField<double>{L->f64, L->geom.ld};
@@ -124,9 +142,9 @@ gf_status do_half_sweep(gf_lattice L, int parity, double omega, int mode)
 {
     if (is_fp32(L))
         GF_HIP(gf::launch_or_half_sweep(field32(L), L->geom, parity, (float)omega, mode, L->cfg32, g_tracking(L),
-                                        L->stream));
+                                        L->stream, L->gauge));
     else
-        GF_HIP(gf::launch_or_half_sweep(field64(L), L->geom, parity, omega, mode, L->cfg64, L->stream));
+        GF_HIP(gf::launch_or_half_sweep(field64(L), L->geom, parity, omega, mode, L->cfg64, L->stream, L->gauge));
     return GF_OK;
 }
 
@@ -154,7 +172,7 @@ gf_status do_sweeps(gf_lattice L, int32_t n, double omega, int mode)
     if (n < 2 || L->stream == nullptr || L->geom.vh >= kGraphMaxHalfSites) return launch_sweeps(L, n, omega, mode);
     const bool fp32 = is_fp32(L);
     const SweepConfig& c = fp32 ? L->cfg32 : L->cfg64;
-    const int kind = fp32 ? (g_tracking(L).base ? 2 : 1) : 0;
+    const int kind = (fp32 ? (g_tracking(L).base ? 2 : 1) : 0) + 4 * L->gauge;
     const auto key = std::make_tuple(n, omega, mode, kind, c.tps, c.block, c.nt);
     auto it = L->sweep_graphs.find(key);
     if (it == L->sweep_graphs.end()) {
@@ -199,8 +217,36 @@ gf_status do_promote(gf_lattice L)
     return GF_OK;
 }
 
+// Coulomb gauge: theta_C(t), F_C(t) of every timeslice into L->hslices;
+// *theta = the largest theta_C(t) (the condition holds once it holds in every
+// timeslice), *F = the mean of F_C(t), added in timeslice order.
+gf_status do_measure_slices(gf_lattice L, double* theta, double* F)
+{
+    if (is_fp32(L))
+        GF_HIP(gf::launch_measure_slices(field32(L), L->geom, L->partial, L->dslices, L->stream));
+    else
+        GF_HIP(gf::launch_measure_slices(field64(L), L->geom, L->partial, L->dslices, L->stream));
+    const int nt = L->dims[3];
+    GF_HIP(hipMemcpyAsync(L->hslices, L->dslices, 2 * (size_t)nt * sizeof(double), hipMemcpyDeviceToHost, L->stream));
+    GF_HIP(hipStreamSynchronize(L->stream));
+    double th = 0.0, f = 0.0;
+    bool finite = true;
+    for (int t = 0; t < nt; ++t) {
+        const double a = L->hslices[2 * t], b = L->hslices[2 * t + 1];
+        finite = finite && std::isfinite(a) && std::isfinite(b);
+        if (a > th) th = a;
+        f += b;
+    }
+    *theta = th;
+    *F = f / (double)nt;
+    if (!finite) return fail(GF_E_NUMERIC, "a timeslice's theta_C or F_C is not finite");
+    return GF_OK;
+}
+
 gf_status do_measure(gf_lattice L, double* theta, double* F)
 {
+    ++L->n_measures;
+    if (L->gauge == gf::GAUGE_COULOMB) return do_measure_slices(L, theta, F);
     if (is_fp32(L))
         GF_HIP(gf::launch_measure(field32(L), L->geom, L->partial, L->dres, L->stream));
     else
@@ -211,6 +257,43 @@ gf_status do_measure(gf_lattice L, double* theta, double* F)
     *F = L->hres[1];
     if (!std::isfinite(*theta) || !std::isfinite(*F))
         return fail(GF_E_NUMERIC, "theta = %g, F = %g is not finite", *theta, *F);
+    return GF_OK;
+}
+
+// One sweep whose half-sweeps also sum tr[Delta Delta^dag] of every site's K
+// just before its update; *theta_est = that sum / (3V): the black sites'
+// terms before the black half-sweep, the white sites' after it.  It tracks
+// theta one sweep behind (for Coulomb gauge: the mean over timeslices of
+// theta_C, never above their maximum).  The links are updated exactly as by a
+// plain sweep.  Syncs.
+gf_status do_est_sweep(gf_lattice L, double omega, int mode, double* theta_est)
+{
+    const SweepConfig& c = is_fp32(L) ? L->cfg32 : L->cfg64;
+    const uint32_t nb = gf::sweep_blocks(L->geom, c);
+    const size_t need = 4 * (size_t)nb;
+    if (need > L->est_cap) {
+        if (L->est) GF_HIP(hipFree(L->est));
+        L->bytes -= (int64_t)(L->est_cap * sizeof(double));
+        L->est = nullptr;
+        L->est_cap = 0;
+        GF_HIP(hipMalloc((void**)&L->est, need * sizeof(double)));
+        L->est_cap = need;
+        L->bytes += (int64_t)(need * sizeof(double));
+    }
+    for (int parity = 0; parity < 2; ++parity) {
+        if (is_fp32(L))
+            GF_HIP(gf::launch_or_half_sweep(field32(L), L->geom, parity, (float)omega, mode, L->cfg32, g_tracking(L),
+                                            L->stream, L->gauge, L->est));
+        else
+            GF_HIP(gf::launch_or_half_sweep(field64(L), L->geom, parity, omega, mode, L->cfg64, L->stream, L->gauge,
+                                            L->est));
+    }
+    const double V = 2.0 * (double)L->geom.vh;
+    GF_HIP(gf::launch_finalize(L->est, 2 * nb, 1.0 / (3.0 * V), 0.0, L->dres + 2, L->stream));
+    GF_HIP(hipMemcpyAsync(L->hres + 2, L->dres + 2, sizeof(double), hipMemcpyDeviceToHost, L->stream));
+    GF_HIP(hipStreamSynchronize(L->stream));
+    ++L->n_estimates;
+    *theta_est = L->hres[2];
     return GF_OK;
 }
 
@@ -266,6 +349,13 @@ void release(gf_lattice L)
     if (L->partial) (void)hipFree(L->partial);
     if (L->dres) (void)hipFree(L->dres);
     if (L->hres) (void)hipHostFree(L->hres);
+    if (L->est) (void)hipFree(L->est);
+    L->est = nullptr;
+    L->est_cap = 0;
+    if (L->dslices) (void)hipFree(L->dslices);
+    if (L->hslices) (void)hipHostFree(L->hslices);
+    L->dslices = nullptr;
+    L->hslices = nullptr;
     L->f64 = nullptr;
     L->f32 = nullptr;
     L->gacc.base = nullptr;
@@ -313,32 +403,25 @@ gf_status gf_create_lattice(const int32_t dims[4], gf_prec prec, void* hip_strea
         return fail(GF_E_ARG, "internal: index division check failed");
     }
 
-    const size_t nchunks = (size_t)2 * 4 * g.ld;  // per chunk slot
+    const LatticeSizes z = lattice_sizes(g, prec);
     hipError_t e = hipSuccess;
-    if (prec == GF_FP64 || prec == GF_MIXED) {
-        e = hipMalloc((void**)&L->f64, nchunks * 6 * sizeof(double2));
-        L->bytes += (int64_t)(nchunks * 6 * sizeof(double2));
-    }
-    if (e == hipSuccess && (prec == GF_FP32 || prec == GF_MIXED)) {
-        e = hipMalloc((void**)&L->f32, nchunks * 3 * sizeof(float4));
-        L->bytes += (int64_t)(nchunks * 3 * sizeof(float4));
-    }
-    if (e == hipSuccess && prec == GF_MIXED) {
-        const size_t gbytes = (size_t)2 * 3 * g.ld * sizeof(float4);
-        e = hipMalloc((void**)&L->gacc.base, gbytes);
+    if (z.f64) e = hipMalloc((void**)&L->f64, z.f64);
+    if (e == hipSuccess && z.f32) e = hipMalloc((void**)&L->f32, z.f32);
+    if (e == hipSuccess && z.gacc) {
+        e = hipMalloc((void**)&L->gacc.base, z.gacc);
         L->gacc.ld = g.ld;
-        L->bytes += (int64_t)gbytes;
     }
-    const size_t np = 2 * (size_t)gf::measure_blocks(g);
-    if (e == hipSuccess) e = hipMalloc((void**)&L->partial, np * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&L->partial, z.partial * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&L->dres, 4 * sizeof(double));
     if (e == hipSuccess) e = hipHostMalloc((void**)&L->hres, 4 * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void**)&L->dslices, z.nslices * sizeof(double));
+    if (e == hipSuccess) e = hipHostMalloc((void**)&L->hslices, z.nslices * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) {
         release(L);
         delete L;
         return fail(e == hipErrorOutOfMemory ? GF_E_NOMEM : GF_E_HIP, "allocation failed: %s", hipGetErrorString(e));
     }
-    L->bytes += (int64_t)(np * sizeof(double));
+    L->bytes = z.total;
     L->cfg64 = SweepConfig{4, 256};
     L->cfg32 = SweepConfig{4, 256};
     // The heat bath samples each subgroup element in every lane of a site's
@@ -495,10 +578,10 @@ gf_status gf_anneal(gf_lattice L, int32_t n_sweeps, double T_start, double T_end
         for (int parity = 0; parity < 2; ++parity) {
             if (is_fp32(L))
                 GF_HIP(gf::launch_hb_half_sweep(field32(L), L->geom, parity, (float)T, seed, sweep, L->cfg_hb32,
-                                                g_tracking(L), L->stream));
+                                                g_tracking(L), L->stream, L->gauge));
             else
                 GF_HIP(gf::launch_hb_half_sweep(field64(L), L->geom, parity, T, seed, sweep, L->cfg_hb64,
-                                                L->stream));
+                                                L->stream, L->gauge));
         }
     }
     L->anneal_sweeps += (uint32_t)n_sweeps;
@@ -510,6 +593,65 @@ gf_status gf_measure_theta_F(gf_lattice L, double* theta, double* F)
     GF_TRY(check_ready(L));
     if (!theta || !F) return fail(GF_E_ARG, "null argument");
     return do_measure(L, theta, F);
+}
+
+gf_status gf_set_gauge(gf_lattice L, gf_gauge gauge)
+{
+    if (!L) return fail(GF_E_ARG, "null lattice");
+    if (gauge != GF_LANDAU && gauge != GF_COULOMB) return fail(GF_E_ARG, "unknown gauge %d", (int)gauge);
+    if (gauge == GF_COULOMB && L->dims[3] > 65535)
+        return fail(GF_E_ARG, "Coulomb gauge supports at most 65535 timeslices (Nt = %d)", L->dims[3]);
+    L->gauge = gauge == GF_COULOMB ? gf::GAUGE_COULOMB : gf::GAUGE_LANDAU;
+    return GF_OK;
+}
+
+gf_status gf_get_gauge(gf_lattice L, gf_gauge* gauge)
+{
+    if (!L || !gauge) return fail(GF_E_ARG, "null argument");
+    *gauge = L->gauge == gf::GAUGE_COULOMB ? GF_COULOMB : GF_LANDAU;
+    return GF_OK;
+}
+
+gf_status gf_measure_timeslices(gf_lattice L, double* theta_t, double* F_t)
+{
+    GF_TRY(check_ready(L));
+    if (!theta_t || !F_t) return fail(GF_E_ARG, "null argument");
+    if (L->gauge != gf::GAUGE_COULOMB) return fail(GF_E_STATE, "per-timeslice values need a Coulomb-gauge lattice");
+    double th = 0.0, f = 0.0;
+    GF_TRY(do_measure_slices(L, &th, &f));
+    for (int t = 0; t < L->dims[3]; ++t) {
+        theta_t[t] = L->hslices[2 * t];
+        F_t[t] = L->hslices[2 * t + 1];
+    }
+    return GF_OK;
+}
+
+gf_status gf_set_check_policy(gf_lattice L, int32_t adaptive, double margin)
+{
+    if (!L) return fail(GF_E_ARG, "null lattice");
+    if (adaptive && !(margin >= 1.0 && std::isfinite(margin)))
+        return fail(GF_E_ARG, "margin = %g must be finite and >= 1", margin);
+    L->adaptive = adaptive != 0;
+    if (adaptive) L->margin = margin;
+    return GF_OK;
+}
+
+gf_status gf_sweep_estimate(gf_lattice L, double omega, gf_or_mode mode, double* theta_est)
+{
+    GF_TRY(check_ready(L));
+    GF_TRY(check_omega(omega, (int)mode));
+    if (!theta_est) return fail(GF_E_ARG, "null argument");
+    GF_TRY(do_est_sweep(L, omega, (int)mode, theta_est));
+    if (std::isnan(*theta_est)) return fail(GF_E_NUMERIC, "theta estimate is NaN");
+    return GF_OK;
+}
+
+gf_status gf_lattice_counters(gf_lattice L, int64_t* measures, int64_t* estimates)
+{
+    if (!L) return fail(GF_E_ARG, "null lattice");
+    if (measures) *measures = L->n_measures;
+    if (estimates) *estimates = L->n_estimates;
+    return GF_OK;
 }
 
 gf_status gf_reunitarize(gf_lattice L)
@@ -574,8 +716,11 @@ gf_status gf_fix_until(gf_lattice L, const gf_fix_params* p, gf_fix_result* res)
         if (finished) break;
         TraceRange check(is_fp32(L) ? "fix_check_fp32" : "fix_check_fp64");
         const bool fp32 = is_fp32(L);
+        const bool mixed32 = L->prec == GF_MIXED && L->phase == 0;
         const int32_t n = std::min(p->check_every, p->max_sweeps - sweeps);
-        // n sweeps, reunitarising after every sweep whose count is a multiple of reunit_every
+        // n sweeps, reunitarising after every sweep whose count is a multiple of
+        // reunit_every; adaptive checks take the last one with the fused estimate
+        double est = 0.0;
         int32_t done = 0;
         while (done < n) {
             int32_t run = n - done;
@@ -583,7 +728,12 @@ gf_status gf_fix_until(gf_lattice L, const gf_fix_params* p, gf_fix_result* res)
                 const int32_t to_reunit = p->reunit_every - (sweeps % p->reunit_every);
                 run = std::min(run, to_reunit);
             }
-            GF_TRY(do_sweeps(L, run, p->omega, p->mode));
+            if (L->adaptive && done + run == n) {
+                GF_TRY(do_sweeps(L, run - 1, p->omega, p->mode));
+                GF_TRY(do_est_sweep(L, p->omega, p->mode, &est));
+            } else {
+                GF_TRY(do_sweeps(L, run, p->omega, p->mode));
+            }
             sweeps += run;
             done += run;
             if (p->reunit_every > 0 && sweeps % p->reunit_every == 0) GF_TRY(do_reunitarize(L));
@@ -592,8 +742,26 @@ gf_status gf_fix_until(gf_lattice L, const gf_fix_params* p, gf_fix_result* res)
             res->sweeps_fp32 += n;
         else
             res->sweeps_fp64 += n;
-        GF_TRY(do_measure(L, &theta, &F));
-        update_stall(theta, &best, &stall);
+        // Adaptive checks measure exactly only where a decision can be taken: at the
+        // last sweep, once the estimate is below margin x the smallest threshold that
+        // could decide (the target; in the float32 phase of GF_MIXED also the switch
+        // point and the stall level), and at every check of the float32 phase once
+        // theta has been below the stall level (the stall rule counts every check
+        // from the first check below it on).  Elsewhere theta is above every
+        // threshold, so skipping the measurement changes no decision: the sweep
+        // count, links, theta and F are those of checking every time.
+        bool exact = true;
+        if (L->adaptive) {
+            double thr = p->theta_target;
+            if (mixed32) thr = std::max(thr, std::max(theta_switch, kStallTheta));
+            exact = sweeps >= p->max_sweeps || !(est >= L->margin * thr) || (mixed32 && best < kStallTheta);
+        }
+        if (exact) {
+            GF_TRY(do_measure(L, &theta, &F));
+            update_stall(theta, &best, &stall);
+        } else {
+            theta = est;  // >= margin x every threshold: no decision at this check
+        }
     }
     res->converged = theta < p->theta_target;
     res->sweeps = sweeps;

@@ -26,6 +26,14 @@ struct gf_lattice_ {
     double* partial = nullptr;              // measurement partial sums (2 per block)
     double* dres = nullptr;                 // device results (theta, F, ...)
     double* hres = nullptr;                 // pinned host copy of dres
+    double* dslices = nullptr;              // Coulomb gauge: device theta_C(t), F_C(t) pairs (2 Nt)
+    double* hslices = nullptr;              // pinned host copy of dslices
+    int gauge = gf::GAUGE_LANDAU;           // functional: GAUGE_LANDAU or GAUGE_COULOMB
+    double* est = nullptr;                  // per-block sums of a sweep's theta estimate (allocated on use)
+    size_t est_cap = 0;                     // doubles held by est
+    bool adaptive = false;                  // gf_fix_until: exact measurement only near a decision
+    double margin = 100.0;                  // ... when the estimate is below margin x the threshold
+    int64_t n_measures = 0, n_estimates = 0;  // exact measurements / fused estimates taken
     bool has_links = false;
     uint32_t anneal_sweeps = 0;             // heat-bath sweep counter (Philox counter word)
     gf::SweepConfig cfg64;     // overrelaxation sweeps
@@ -33,7 +41,8 @@ struct gf_lattice_ {
     gf::SweepConfig cfg_hb64;  // heat-bath sweeps (gf_anneal)
     gf::SweepConfig cfg_hb32;
     // hipGraphs of n back-to-back sweeps, keyed by (n, omega, mode, precision
-    // and g tracking, tps, block, cache policy); only on a non-default stream
+    // and g tracking plus 4 x gauge, tps, block, cache policy); only on a
+    // non-default stream
     std::map<std::tuple<int32_t, double, int, int, int, int, int>, hipGraphExec_t> sweep_graphs;
 };
 
@@ -58,6 +67,13 @@ gf_status fail(gf_status st, const char* fmt, ...);
         if (s_ != GF_OK) return s_;      \
     } while (0)
 
+// Device buffers of one lattice (bytes; partial and nslices in doubles).
+struct LatticeSizes {
+    size_t f64 = 0, f32 = 0, gacc = 0, partial = 0, nslices = 0;
+    int64_t total = 0;  // every device byte the lattice holds
+};
+
+LatticeSizes lattice_sizes(const Geom& g, gf_prec prec);
 bool make_fastdiv(uint32_t d, uint32_t limit, FastDiv* out);
 bool make_geom(const int32_t dims[4], Geom* out);
 gf_status check_dims(const int32_t dims[4], int64_t* V);
@@ -72,6 +88,7 @@ gf_status do_sweeps(gf_lattice L, int32_t n, double omega, int mode);
 gf_status do_reunitarize(gf_lattice L);
 gf_status do_promote(gf_lattice L);
 gf_status do_measure(gf_lattice L, double* theta, double* F);
+gf_status do_est_sweep(gf_lattice L, double omega, int mode, double* theta_est);
 gf_status do_fp32_floor(gf_lattice L, double* floor);
 gf_status resolve_switch(gf_lattice L, double theta_target, double theta_switch, double* out);
 gf_status upload_canonical(gf_lattice L, const double* dev_canon);

@@ -20,28 +20,66 @@ struct SweepConfig {
 
 bool sweep_config_valid(const SweepConfig& c);
 
-// One overrelaxation half-sweep over the sites of colour `parity`.
+// Gauge of a lattice's functional: Landau (K over all 4 directions) or
+// Coulomb (K over x, y, z; one independent problem per timeslice).
+constexpr int GAUGE_LANDAU = 0;
+constexpr int GAUGE_COULOMB = 1;
+
+// One overrelaxation half-sweep over the sites of colour `parity`.  est !=
+// nullptr: the launch also writes its per-block sums of tr[Delta Delta^dag]
+// before the update as pairs at est + 2 * parity * sweep_blocks(g, cfg)
+// (colour 0 first, then colour 1: 4 * sweep_blocks doubles for a sweep).
 hipError_t launch_or_half_sweep(const LinkField<double>& f, const Geom& g, int parity, double omega, int mode,
-                                const SweepConfig& cfg, hipStream_t st);
+                                const SweepConfig& cfg, hipStream_t st, int gauge = GAUGE_LANDAU,
+                                double* est = nullptr);
 // float32; with gacc.base != nullptr the sweep also accumulates g(x) <- G g(x).
 hipError_t launch_or_half_sweep(const LinkField<float>& f, const Geom& g, int parity, float omega, int mode,
-                                const SweepConfig& cfg, const GField& gacc, hipStream_t st);
+                                const SweepConfig& cfg, const GField& gacc, hipStream_t st,
+                                int gauge = GAUGE_LANDAU, double* est = nullptr);
+uint32_t sweep_blocks(const Geom& g, const SweepConfig& cfg);
 
 // One heat-bath half-sweep at temperature T: Philox key = seed, sweep counter
 // `sweep` (float32 with gacc.base != nullptr also accumulates g).
 hipError_t launch_hb_half_sweep(const LinkField<double>& f, const Geom& g, int parity, double T, uint64_t seed,
-                                uint32_t sweep, const SweepConfig& cfg, hipStream_t st);
+                                uint32_t sweep, const SweepConfig& cfg, hipStream_t st, int gauge = GAUGE_LANDAU);
 hipError_t launch_hb_half_sweep(const LinkField<float>& f, const Geom& g, int parity, float T, uint64_t seed,
-                                uint32_t sweep, const SweepConfig& cfg, const GField& gacc, hipStream_t st);
+                                uint32_t sweep, const SweepConfig& cfg, const GField& gacc, hipStream_t st,
+                                int gauge = GAUGE_LANDAU);
+
+// The Coulomb instantiations (gf_sweep_coulomb.hip) behind gauge = GAUGE_COULOMB.
+hipError_t launch_or_half_sweep_coulomb(const LinkField<double>& f, const Geom& g, int parity, double omega,
+                                        int mode, const SweepConfig& cfg, hipStream_t st, double* est);
+hipError_t launch_or_half_sweep_coulomb(const LinkField<float>& f, const Geom& g, int parity, float omega,
+                                        int mode, const SweepConfig& cfg, const GField& gacc, hipStream_t st,
+                                        double* est);
+hipError_t launch_hb_half_sweep_coulomb(const LinkField<double>& f, const Geom& g, int parity, double T,
+                                        uint64_t seed, uint32_t sweep, const SweepConfig& cfg, hipStream_t st);
+hipError_t launch_hb_half_sweep_coulomb(const LinkField<float>& f, const Geom& g, int parity, float T,
+                                        uint64_t seed, uint32_t sweep, const SweepConfig& cfg, const GField& gacc,
+                                        hipStream_t st);
 
 // theta / F: per-block partial sums (2 doubles per block) then one finalize
 // block; out[0] = theta, out[1] = F.  partial must hold measure_partials(g).
 uint32_t measure_blocks(const Geom& g);
+// out[0] = s0 * sum of the n pairs' first halves, out[1] = s1 * second halves,
+// in index order (one block).
+hipError_t launch_finalize(const double* partial, uint32_t n, double s0, double s1, double* out, hipStream_t st);
 hipError_t launch_measure(const LinkField<double>& f, const Geom& g, double* partial, double* out, hipStream_t st);
 hipError_t launch_measure(const LinkField<float>& f, const Geom& g, double* partial, double* out, hipStream_t st);
 // The same over links in the ABI's canonical float64 array (device), read in
 // place; bitwise equal to launch_measure over the packed float64 field.
 hipError_t launch_measure_canonical(const double* canon, const Geom& g, double* partial, double* out, hipStream_t st);
+
+// Coulomb gauge, per timeslice t = 0 .. Nt-1: out[2t] = theta_C(t) =
+// (1/(3 V3)) sum_{x in t} tr[Delta_C Delta_C^dag], out[2t+1] = F_C(t) =
+// (1/(9 V3)) sum_{x in t} sum_i Re tr U_i(x), with V3 = Nx Ny Nz; every
+// timeslice's per-block partials are added in index order by one block.
+// partial must hold slice_partials(g) pairs.
+uint32_t slice_partials(const Geom& g);
+hipError_t launch_measure_slices(const LinkField<double>& f, const Geom& g, double* partial, double* out,
+                                 hipStream_t st);
+hipError_t launch_measure_slices(const LinkField<float>& f, const Geom& g, double* partial, double* out,
+                                 hipStream_t st);
 
 // out[0] = (1/(3V)) sum_x tr[E E^dag], E = Delta computed in float32 from the
 // float32-rounded links minus Delta in float64: the float32 rounding floor of

@@ -5,7 +5,9 @@
 //   Delta(x) = sum_mu (A_mu(x) - A_mu(x-mu^)) = [(K(x) - K(x)^dag)/(2i)]_traceless
 // (A_mu of Sec. 2 with a g = 1; the two forms are equal term by term), and
 //   theta = (1/(3V)) sum_x tr[Delta Delta^dag],
-//   F     = (1/(12V)) sum_x sum_mu Re tr U_mu(x)     (Eq. landaufunctional, g = 1).
+//   F     = (1/(12V)) sum_x sum_mu Re tr U_mu(x)     (Eq. landaufunctional, g = 1);
+// for Coulomb gauge the same per timeslice with mu over x, y, z only
+// (k_measure_slices).
 // One thread per site (both colours), float64 arithmetic and sums whatever the
 // link precision; wavefront sums by xor-shuffles, block sums through LDS, one
 // partial per block, then one block adds the partials in index order.  The
@@ -35,6 +37,27 @@ __global__ void __launch_bounds__(RBLOCK) k_measure(Field f, Geom g, double* par
     double th = 0.0, fr = 0.0;
     if (h < g.vh) measure_site(f, g, parity, h, th, fr);
     block_sum2<RBLOCK>(th, fr, partial + 2 * (size_t)(parity * tiles + tile));
+}
+
+// Coulomb gauge: the sites of timeslice t are the half indices
+// t*hs3 .. (t+1)*hs3 - 1 of each colour (hs3 = V3/2), so block (b, t) covers
+// tile b >> 1 of colour b & 1 of timeslice t, alternating colours as k_measure
+// does; partial (t, b) holds the same sites whatever the dispatch order.
+template <typename Field>
+__global__ void __launch_bounds__(RBLOCK) k_measure_slices(Field f, Geom g, double* partial)
+{
+    const int parity = (int)(blockIdx.x & 1u);
+    const uint32_t k = (blockIdx.x >> 1) * RBLOCK + threadIdx.x;
+    double th = 0.0, fr = 0.0;
+    if (k < g.hs3) measure_site<NDIR_COULOMB>(f, g, parity, blockIdx.y * g.hs3 + k, th, fr);
+    block_sum2<RBLOCK>(th, fr, partial + 2 * ((size_t)blockIdx.y * gridDim.x + blockIdx.x));
+}
+
+// Block t adds timeslice t's n partial pairs in index order.
+__global__ void __launch_bounds__(RBLOCK) k_finalize_slices(const double* partial, uint32_t n, double s0, double s1,
+                                                            double* out)
+{
+    finalize_pairs<RBLOCK>(partial + 2 * (size_t)blockIdx.x * n, n, s0, s1, out + 2 * (size_t)blockIdx.x);
 }
 
 // Re tr[U_mu(x) U_nu(x+mu^) U_mu(x+nu^)^dag U_nu(x)^dag] summed over mu < nu.
@@ -317,6 +340,24 @@ hipError_t measure_impl(const Field& f, const Geom& g, double* partial, double* 
     return hipGetLastError();
 }
 
+// Blocks per timeslice of k_measure_slices (both colours).
+uint32_t slice_blocks(const Geom& g)
+{
+    return 2 * ((g.hs3 + RBLOCK - 1) / RBLOCK);
+}
+
+template <typename R>
+hipError_t measure_slices_impl(const LinkField<R>& f, const Geom& g, double* partial, double* out, hipStream_t st)
+{
+    const uint32_t nb = slice_blocks(g);
+    hipLaunchKernelGGL((k_measure_slices<LinkField<R>>), dim3(nb, (uint32_t)g.n[3]), dim3(RBLOCK), 0, st, f, g,
+                       partial);
+    const double V3 = 2.0 * (double)g.hs3;
+    hipLaunchKernelGGL(k_finalize_slices, dim3((uint32_t)g.n[3]), dim3(RBLOCK), 0, st, partial, nb,
+                       1.0 / (3.0 * V3), 1.0 / (9.0 * V3), out);
+    return hipGetLastError();
+}
+
 template <typename R>
 hipError_t plaquette_impl(const LinkField<R>& f, const Geom& g, double* partial, double* out, hipStream_t st)
 {
@@ -373,6 +414,26 @@ hipError_t launch_rebuild_from_g(const LinkField<double>& u0, const GField& gacc
 uint32_t measure_blocks(const Geom& g)
 {
     return 2 * site_blocks(g);
+}
+
+hipError_t launch_finalize(const double* partial, uint32_t n, double s0, double s1, double* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RBLOCK), 0, st, partial, n, s0, s1, out);
+    return hipGetLastError();
+}
+
+uint32_t slice_partials(const Geom& g)
+{
+    return slice_blocks(g) * (uint32_t)g.n[3];
+}
+
+hipError_t launch_measure_slices(const LinkField<double>& f, const Geom& g, double* p, double* o, hipStream_t st)
+{
+    return measure_slices_impl(f, g, p, o, st);
+}
+hipError_t launch_measure_slices(const LinkField<float>& f, const Geom& g, double* p, double* o, hipStream_t st)
+{
+    return measure_slices_impl(f, g, p, o, st);
 }
 
 hipError_t launch_fp32_floor(const LinkField<double>& f, const Geom& g, double* partial, double* out, hipStream_t st)

@@ -38,8 +38,13 @@ namespace gf {
 namespace pool {
 
 constexpr int PBLOCK = 256;  // threads per block of the reunitarisation / measurement kernels
-constexpr int SBLOCK = 128;  // threads per block of the sweep kernels (the tuned solo shape on MI355X)
 constexpr int kHeatBathTps = 1;  // lanes per site of the heat-bath sweeps (its sampling is per lane)
+constexpr int kHeatBathBlock = 128;  // threads per block of the heat-bath sweeps
+// Default shape of the overrelaxation sweeps (lanes per site, threads per
+// block): the fastest over 64 lattices of 12^4 to 24^3x48 on MI355X (float32
+// with g: 2 lanes, float64: 1 lane, 3 % ahead of 2; 128 threads for both);
+// gf_pool_autotune picks them for the resident mix.
+constexpr int kDefaultTps32 = 2, kDefaultTps64 = 1, kDefaultBlock = 128;
 
 struct SlotDev {
     LinkField<double> f64;
@@ -154,14 +159,14 @@ __device__ __forceinline__ double schedule_T(const SlotDev& sd, uint32_t s)
 // Cache); float64 sweeps load non-temporally and keep the forward order (on
 // MI355X the reverse order made them 1-2 % slower and the float32 ones 3 %
 // faster).  The order inside a colour does not change the result.  stride =
-// entries per list segment.
-template <typename R, int TPS, int MODE, bool TRACKG>
-__global__ void __launch_bounds__(SBLOCK) k_pool_sweep(const SlotDev* __restrict__ slots,
-                                                       const Entry* __restrict__ list,
-                                                       const uint32_t* __restrict__ count, uint32_t stride,
-                                                       int parity, uint32_t k)
+// entries per list segment.  A tile is BLOCK / TPS sites.
+template <typename R, int TPS, int MODE, bool TRACKG, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_pool_sweep(const SlotDev* __restrict__ slots,
+                                                      const Entry* __restrict__ list,
+                                                      const uint32_t* __restrict__ count, uint32_t stride,
+                                                      int parity, uint32_t k)
 {
-    constexpr uint32_t SPB = SBLOCK / TPS;
+    constexpr uint32_t SPB = BLOCK / TPS;
     constexpr int CP = sizeof(R) == 8 ? 1 : 0;  // cache policy (gf_device.h)
     const uint32_t t = (parity && !nt_loads(CP)) ? gridDim.x - 1u - blockIdx.x : blockIdx.x;
     uint32_t slot, first;
@@ -349,18 +354,20 @@ gf_status pool_check(gf_pool P)
     return GF_OK;
 }
 
+gf_status check_pool_shape(int tps, int block)
+{
+    if ((tps != 1 && tps != 2 && tps != 4) || (block != 64 && block != 128 && block != 256))
+        return fail(GF_E_ARG, "pool sweep shape tps=%d block=%d: tps must be 1, 2 or 4 and block 64, 128 or 256",
+                    tps, block);
+    return GF_OK;
+}
+
+// Device bytes of a job's lattice: what gf_create_lattice allocates for it.
 int64_t lattice_bytes(const int32_t dims[4], int32_t prec)
 {
-    int64_t V = 1;
-    for (int m = 0; m < 4; ++m) V *= dims[m];
-    const int64_t ld = ((V / 2) + 63) & ~(int64_t)63;
-    int64_t b = 0;
-    if (prec == GF_FP64 || prec == GF_MIXED) b += 2 * 4 * ld * 6 * 16;
-    if (prec == GF_FP32 || prec == GF_MIXED) b += 2 * 4 * ld * 3 * 16;
-    if (prec == GF_MIXED) b += 2 * 3 * ld * 16;
-    const int64_t nb = (V / 2 + 255) / 256;
-    b += 2 * 2 * nb * 8;
-    return b;
+    Geom g{};
+    if (!make_geom(dims, &g)) return -1;
+    return lattice_sizes(g, (gf_prec)prec).total;
 }
 
 Entry* seg(gf_pool P, Entry* base, int k, int kind)
@@ -368,14 +375,14 @@ Entry* seg(gf_pool P, Entry* base, int k, int kind)
     return base + ((size_t)k * NKIND + kind) * P->list_stride;
 }
 
-uint32_t tiles_of(const Geom& g, int kind, int tps)
+uint32_t tiles_of(const Geom& g, int kind, int tps, int block)
 {
     switch (kind) {
         case K_HB32:
         case K_OR32:
         case K_OR64:
         case K_HB64: {
-            const uint32_t spb = SBLOCK / (uint32_t)tps;
+            const uint32_t spb = (uint32_t)block / (uint32_t)tps;
             return (g.vh + spb - 1) / spb;
         }
         case K_R32:
@@ -386,31 +393,47 @@ uint32_t tiles_of(const Geom& g, int kind, int tps)
     }
 }
 
-template <typename R, int MODE, bool TRACKG>
-hipError_t launch_sweep_kind(gf_pool P, int tps, uint32_t tiles, const Entry* list, const uint32_t* count, int parity,
-                             uint32_t k)
+template <typename R, int TPS, int MODE, bool TRACKG>
+hipError_t launch_sweep_tps(hipStream_t st, const SlotDev* slots, int block, uint32_t tiles, const Entry* list,
+                            const uint32_t* count, uint32_t stride, int parity, uint32_t k)
 {
-    const dim3 grid(tiles), block(SBLOCK);
-    const uint32_t stride = (uint32_t)P->list_stride;
-    switch (tps) {
-        case 1:
-            hipLaunchKernelGGL((k_pool_sweep<R, 1, MODE, TRACKG>), grid, block, 0, P->stream, P->slots_dev, list, count,
+    const dim3 grid(tiles);
+    switch (block) {
+        case 64:
+            hipLaunchKernelGGL((k_pool_sweep<R, TPS, MODE, TRACKG, 64>), grid, dim3(64), 0, st, slots, list, count,
                                stride, parity, k);
             break;
-        case 2:
-            hipLaunchKernelGGL((k_pool_sweep<R, 2, MODE, TRACKG>), grid, block, 0, P->stream, P->slots_dev, list, count,
-                               stride, parity, k);
-            break;
-        case 8:
-            hipLaunchKernelGGL((k_pool_sweep<R, 8, MODE, TRACKG>), grid, block, 0, P->stream, P->slots_dev, list, count,
+        case 256:
+            hipLaunchKernelGGL((k_pool_sweep<R, TPS, MODE, TRACKG, 256>), grid, dim3(256), 0, st, slots, list, count,
                                stride, parity, k);
             break;
         default:
-            hipLaunchKernelGGL((k_pool_sweep<R, 4, MODE, TRACKG>), grid, block, 0, P->stream, P->slots_dev, list, count,
+            hipLaunchKernelGGL((k_pool_sweep<R, TPS, MODE, TRACKG, 128>), grid, dim3(128), 0, st, slots, list, count,
                                stride, parity, k);
             break;
     }
     return hipGetLastError();
+}
+
+// One sweep launch of kind (R, MODE, TRACKG) over `tiles` tiles of block / tps
+// sites (tps 1, 2 or 4; block 64, 128 or 256).
+template <typename R, int MODE, bool TRACKG>
+hipError_t launch_sweep_shape(hipStream_t st, const SlotDev* slots, int tps, int block, uint32_t tiles,
+                              const Entry* list, const uint32_t* count, uint32_t stride, int parity, uint32_t k)
+{
+    switch (tps) {
+        case 1: return launch_sweep_tps<R, 1, MODE, TRACKG>(st, slots, block, tiles, list, count, stride, parity, k);
+        case 2: return launch_sweep_tps<R, 2, MODE, TRACKG>(st, slots, block, tiles, list, count, stride, parity, k);
+        default: return launch_sweep_tps<R, 4, MODE, TRACKG>(st, slots, block, tiles, list, count, stride, parity, k);
+    }
+}
+
+template <typename R, int MODE, bool TRACKG>
+hipError_t launch_sweep_kind(gf_pool P, int tps, int block, uint32_t tiles, const Entry* list, const uint32_t* count,
+                             int parity, uint32_t k)
+{
+    return launch_sweep_shape<R, MODE, TRACKG>(P->stream, P->slots_dev, tps, block, tiles, list, count,
+                                               (uint32_t)P->list_stride, parity, k);
 }
 
 bool is_sweep_kind(int kind)
@@ -426,18 +449,23 @@ hipError_t launch_kind(gf_pool P, int k, int kind, int parity)
     const uint32_t tiles = P->seg_tiles[sgi];
     const uint32_t kk = (uint32_t)k;
     const int mode = P->cfg.mode;
-    const int t32 = P->cfg.tps32, t64 = P->cfg.tps64;
+    const int t32 = P->cfg.tps32, t64 = P->cfg.tps64, b32 = P->cfg.block32, b64 = P->cfg.block64;
     P->launch_log.push_back(sgi);
     switch (kind) {
-        case K_HB32: return launch_sweep_kind<float, HEATBATH, true>(P, kHeatBathTps, tiles, list, count, parity, kk);
+        case K_HB32:
+            return launch_sweep_kind<float, HEATBATH, true>(P, kHeatBathTps, kHeatBathBlock, tiles, list, count, parity,
+                                                            kk);
         case K_HB64:
-            return launch_sweep_kind<double, HEATBATH, false>(P, kHeatBathTps, tiles, list, count, parity, kk);
+            return launch_sweep_kind<double, HEATBATH, false>(P, kHeatBathTps, kHeatBathBlock, tiles, list, count,
+                                                              parity, kk);
         case K_OR32:
-            return mode == GF_OR_EXACT ? launch_sweep_kind<float, 0, true>(P, t32, tiles, list, count, parity, kk)
-                                       : launch_sweep_kind<float, 1, true>(P, t32, tiles, list, count, parity, kk);
+            return mode == GF_OR_EXACT
+                       ? launch_sweep_kind<float, 0, true>(P, t32, b32, tiles, list, count, parity, kk)
+                       : launch_sweep_kind<float, 1, true>(P, t32, b32, tiles, list, count, parity, kk);
         case K_OR64:
-            return mode == GF_OR_EXACT ? launch_sweep_kind<double, 0, false>(P, t64, tiles, list, count, parity, kk)
-                                       : launch_sweep_kind<double, 1, false>(P, t64, tiles, list, count, parity, kk);
+            return mode == GF_OR_EXACT
+                       ? launch_sweep_kind<double, 0, false>(P, t64, b64, tiles, list, count, parity, kk)
+                       : launch_sweep_kind<double, 1, false>(P, t64, b64, tiles, list, count, parity, kk);
         case K_R32:
             hipLaunchKernelGGL((k_pool_reunit<float, true>), dim3(P->grid_other), dim3(PBLOCK), 0, P->stream,
                                P->slots_dev, list, count);
@@ -654,7 +682,10 @@ gf_status gf_pool_job_bytes(const int32_t dims[4], int32_t prec, int64_t* bytes)
     for (int m = 0; m < 4; ++m)
         if (dims[m] < 2 || dims[m] % 2) return fail(GF_E_ARG, "extents must be even and >= 2");
     if (prec != GF_FP64 && prec != GF_MIXED && prec != GF_FP32) return fail(GF_E_ARG, "bad precision");
+    int64_t V = 1;
+    GF_TRY(check_dims(dims, &V));
     *bytes = lattice_bytes(dims, prec);
+    if (*bytes < 0) return fail(GF_E_ARG, "internal: index division check failed");
     return GF_OK;
 }
 
@@ -667,16 +698,12 @@ gf_status gf_pool_create(const gf_pool_config* cfg, void* hip_stream, gf_pool* o
     if (cfg->check_every < 1 || cfg->check_every > 1000) return fail(GF_E_ARG, "check_every must be 1..1000");
     if (cfg->mode != GF_OR_EXACT && cfg->mode != GF_OR_BINOMIAL1) return fail(GF_E_ARG, "unknown mode");
     gf_pool_config c = *cfg;
-    // default lanes per site: the fastest pool sweeps on MI355X over 64 lattices of
-    // 12^4 to 24^3x48 (float32 with g: 2 lanes; float64: 1 lane, 3 % ahead of 2)
-    if (c.tps32 == 0) c.tps32 = 2;
-    if (c.tps64 == 0) c.tps64 = 1;
-    if (c.block32 == 0) c.block32 = 256;
-    if (c.block64 == 0) c.block64 = 256;
-    for (int t : {c.tps32, c.tps64})
-        if (t != 1 && t != 2 && t != 4 && t != 8) return fail(GF_E_ARG, "tps must be 1, 2, 4 or 8");
-    if (!sweep_config_valid(SweepConfig{c.tps32, c.block32}) || !sweep_config_valid(SweepConfig{c.tps64, c.block64}))
-        return fail(GF_E_ARG, "invalid sweep kernel configuration");
+    if (c.tps32 == 0) c.tps32 = kDefaultTps32;
+    if (c.tps64 == 0) c.tps64 = kDefaultTps64;
+    if (c.block32 == 0) c.block32 = kDefaultBlock;
+    if (c.block64 == 0) c.block64 = kDefaultBlock;
+    GF_TRY(check_pool_shape(c.tps32, c.block32));
+    GF_TRY(check_pool_shape(c.tps64, c.block64));
 
     gf_pool_* P = new (std::nothrow) gf_pool_();
     if (!P) return fail(GF_E_NOMEM, "host allocation failed");
@@ -774,6 +801,8 @@ gf_status gf_pool_admit(gf_pool P, uint64_t job_id, const int32_t dims[4], const
 
     gf_lattice L = nullptr;
     GF_TRY(gf_create_lattice(dims, (gf_prec)P->cfg.prec, P->stream, &L));
+    // the job's own lattice object takes the pool's shape (its solo kernels
+    // are not used for sweeps while it is in the pool)
     L->cfg32 = SweepConfig{P->cfg.tps32, P->cfg.block32};
     L->cfg64 = SweepConfig{P->cfg.tps64, P->cfg.block64};
     gf_status st = gf_set_links(L, host_links);
@@ -826,7 +855,8 @@ gf_status gf_pool_step(gf_pool P)
         e[n_entries[sgi]] = Entry{(uint32_t)slot, n_tiles[sgi]};
         n_entries[sgi]++;
         const int tps = kind == K_OR32 ? P->cfg.tps32 : kind == K_OR64 ? P->cfg.tps64 : kHeatBathTps;
-        n_tiles[sgi] += tiles_of(g, kind, tps);
+        const int blk = kind == K_OR32 ? P->cfg.block32 : kind == K_OR64 ? P->cfg.block64 : kHeatBathBlock;
+        n_tiles[sgi] += tiles_of(g, kind, tps, blk);
     };
     bool any = false;
     for (auto& j : P->jobs) {
@@ -963,6 +993,162 @@ gf_status gf_pool_cancel(gf_pool P, uint64_t job_id)
             return GF_OK;
         }
     return fail(GF_E_ARG, "no job %llu in the pool", (unsigned long long)job_id);
+}
+
+gf_status gf_pool_autotune(gf_pool P, int32_t kernel, int32_t n_sweeps, size_t scratch_bytes, gf_tune_entry* table,
+                           int32_t cap, int32_t* n_out, gf_tune_entry* chosen)
+{
+    TraceRange range("gf_pool_autotune");
+    GF_TRY(pool_check(P));
+    if (kernel != GF_FP32 && kernel != GF_FP64) return fail(GF_E_ARG, "kernel must be GF_FP32 or GF_FP64");
+    if (kernel == GF_FP32 && P->cfg.prec != GF_MIXED)
+        return fail(GF_E_ARG, "a GF_FP64 pool has no float32 sweeps to tune");
+    if (n_sweeps < 1 || cap < 0 || (cap > 0 && !table)) return fail(GF_E_ARG, "bad arguments");
+    if (n_out) *n_out = 0;
+    const bool f32 = kernel == GF_FP32;
+
+    // scratch copies of the resident jobs' fields, in slot order, up to scratch_bytes
+    struct Copy {
+        SlotDev sd;
+        void* field;
+        void* g;
+    };
+    std::vector<Copy> copies;
+    size_t used = 0;
+    gf_status st = GF_OK;
+    hipError_t e = hipSuccess;
+    for (auto& j : P->jobs) {
+        if (!j.lat) continue;
+        gf_lattice L = j.lat;
+        const size_t fb = (size_t)2 * 4 * L->geom.ld * 16 * (f32 ? 3 : 6);
+        const size_t gb = f32 ? (size_t)2 * 3 * L->geom.ld * 16 : 0;
+        if (used + fb + gb > scratch_bytes) break;
+        Copy c{P->slot_host[j.slot], nullptr, nullptr};
+        e = hipMalloc(&c.field, fb);
+        if (e == hipSuccess && gb) e = hipMalloc(&c.g, gb);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c.field, f32 ? (void*)L->f32 : (void*)L->f64, fb, hipMemcpyDeviceToDevice, P->stream);
+        if (e == hipSuccess && gb) e = hipMemcpyAsync(c.g, L->gacc.base, gb, hipMemcpyDeviceToDevice, P->stream);
+        if (f32) {
+            c.sd.f32 = LinkField<float>{(float4*)c.field, L->geom.ld};
+            c.sd.gacc = GField{(float4*)c.g, L->geom.ld};
+        } else {
+            c.sd.f64 = LinkField<double>{(double2*)c.field, L->geom.ld};
+        }
+        copies.push_back(c);
+        if (e != hipSuccess) break;
+        used += fb + gb;
+    }
+    if (e == hipSuccess && copies.empty())
+        st = fail(GF_E_STATE, "no resident job fits the scratch budget of %zu bytes", scratch_bytes);
+
+    const size_t n = copies.size();
+    SlotDev* slots_d = nullptr;
+    Entry* list_d = nullptr;
+    uint32_t* count_d = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    std::vector<SlotDev> sd(n);
+    std::vector<Entry> list(n + 1);
+    for (size_t i = 0; i < n; ++i) sd[i] = copies[i].sd;
+    const uint32_t count = (uint32_t)n;
+    if (st == GF_OK && e == hipSuccess) e = hipMalloc((void**)&slots_d, sizeof(SlotDev) * n);
+    if (st == GF_OK && e == hipSuccess) e = hipMalloc((void**)&list_d, sizeof(Entry) * (n + 1));
+    if (st == GF_OK && e == hipSuccess) e = hipMalloc((void**)&count_d, sizeof(uint32_t));
+    if (st == GF_OK && e == hipSuccess)
+        e = hipMemcpyAsync(slots_d, sd.data(), sizeof(SlotDev) * n, hipMemcpyHostToDevice, P->stream);
+    if (st == GF_OK && e == hipSuccess)
+        e = hipMemcpyAsync(count_d, &count, sizeof(uint32_t), hipMemcpyHostToDevice, P->stream);
+    if (st == GF_OK && e == hipSuccess) e = hipEventCreate(&e0);
+    if (st == GF_OK && e == hipSuccess) e = hipEventCreate(&e1);
+    if (st == GF_OK && e == hipSuccess) e = hipStreamSynchronize(P->stream);
+
+    const int mode = P->cfg.mode;
+    int best_tps = 0, best_block = 0, m = 0;
+    double best_us = 1e300;
+    for (int tps : {1, 2, 4}) {
+        for (int block : {64, 128, 256}) {
+            if (st != GF_OK || e != hipSuccess) break;
+            uint32_t tiles = 0;
+            for (size_t i = 0; i < n; ++i) {
+                list[i] = Entry{(uint32_t)i, tiles};
+                tiles += tiles_of(sd[i].g, f32 ? K_OR32 : K_OR64, tps, block);
+            }
+            list[n] = Entry{0u, tiles};
+            // ordered before this shape's launches; the previous shape's launches
+            // have finished (event synchronised), so list_d and `list` are free
+            e = hipMemcpyAsync(list_d, list.data(), sizeof(Entry) * (n + 1), hipMemcpyHostToDevice, P->stream);
+            auto sweep = [&]() -> hipError_t {
+                for (int parity = 0; parity < 2; ++parity) {
+                    hipError_t r;
+                    if (f32)
+                        r = mode == GF_OR_EXACT
+                                ? launch_sweep_shape<float, 0, true>(P->stream, slots_d, tps, block, tiles, list_d,
+                                                                     count_d, (uint32_t)(n + 1), parity, 0u)
+                                : launch_sweep_shape<float, 1, true>(P->stream, slots_d, tps, block, tiles, list_d,
+                                                                     count_d, (uint32_t)(n + 1), parity, 0u);
+                    else
+                        r = mode == GF_OR_EXACT
+                                ? launch_sweep_shape<double, 0, false>(P->stream, slots_d, tps, block, tiles, list_d,
+                                                                       count_d, (uint32_t)(n + 1), parity, 0u)
+                                : launch_sweep_shape<double, 1, false>(P->stream, slots_d, tps, block, tiles, list_d,
+                                                                       count_d, (uint32_t)(n + 1), parity, 0u);
+                    if (r != hipSuccess) return r;
+                }
+                return hipSuccess;
+            };
+            if (e == hipSuccess) e = sweep();  // warm-up
+            if (e == hipSuccess) e = hipEventRecord(e0, P->stream);
+            for (int k = 0; k < n_sweeps && e == hipSuccess; ++k) e = sweep();
+            if (e == hipSuccess) e = hipEventRecord(e1, P->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) break;
+            const double us = 1e3 * (double)ms / n_sweeps;
+            if (m < cap) table[m] = gf_tune_entry{tps, block, f32 ? 0 : 1, us};
+            ++m;
+            if (us < best_us) {
+                best_us = us;
+                best_tps = tps;
+                best_block = block;
+            }
+        }
+    }
+    if (st == GF_OK && e != hipSuccess) st = fail(GF_E_HIP, "pool autotune: %s", hipGetErrorString(e));
+    (void)hipStreamSynchronize(P->stream);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (slots_d) (void)hipFree(slots_d);
+    if (list_d) (void)hipFree(list_d);
+    if (count_d) (void)hipFree(count_d);
+    for (auto& c : copies) {
+        if (c.field) (void)hipFree(c.field);
+        if (c.g) (void)hipFree(c.g);
+    }
+    if (st != GF_OK) return st;
+    if (f32) {
+        P->cfg.tps32 = best_tps;
+        P->cfg.block32 = best_block;
+    } else {
+        P->cfg.tps64 = best_tps;
+        P->cfg.block64 = best_block;
+    }
+    // captured steps hold the previous shape's kernels
+    for (auto& kv : P->graphs) destroy_step_graph(kv.second);
+    P->graphs.clear();
+    if (n_out) *n_out = std::min(m, cap);
+    if (chosen) *chosen = gf_tune_entry{best_tps, best_block, f32 ? 0 : 1, best_us};
+    return GF_OK;
+}
+
+gf_status gf_pool_get_shape(gf_pool P, int32_t* tps32, int32_t* block32, int32_t* tps64, int32_t* block64)
+{
+    GF_TRY(pool_check(P));
+    if (tps32) *tps32 = P->cfg.tps32;
+    if (block32) *block32 = P->cfg.block32;
+    if (tps64) *tps64 = P->cfg.tps64;
+    if (block64) *block64 = P->cfg.block64;
+    return GF_OK;
 }
 
 gf_status gf_pool_stats(gf_pool P, int32_t* active, int32_t* finished, int64_t* bytes_in_use)

@@ -230,28 +230,74 @@ __device__ __forceinline__ Quat<R> subgroup_element(const Quat<R>& a, const Rule
         return or_element<MODE>(a, rule.omega);
 }
 
-// Leaf k of this lane: U (forward, bwd = false) or U^dagger (backward).
-// Sum of NL consecutive leaves in the fixed pairwise tree.
-template <int NL, typename R>
-__device__ __forceinline__ void leaf_tree(const M3<R>* U, const bool* bwd, M3<R>& out)
+// Directions summed into K(x): 4 for Landau gauge, 3 (x, y, z) for Coulomb
+// gauge, whose functional is that of Sec. 2 restricted to the spatial links,
+// one independent problem per timeslice.  The gauge transformation of a
+// Coulomb site update still acts on all 8 links at the site.
+constexpr int NDIR_LANDAU = 4;
+constexpr int NDIR_COULOMB = 3;
+
+// Leaf k of this lane: U (forward, bwd = false) or U^dagger (backward), or
+// zero for a direction outside the first NDIR.  Sum of NL consecutive leaves
+// in the fixed pairwise tree; the zero leaves keep the tree, and so K, the
+// same bitwise for every number of lanes per site.
+template <int NL, int NDIR, typename R>
+__device__ __forceinline__ void leaf_tree(const M3<R>* U, const bool* bwd, const int* mu, M3<R>& out)
 {
     if constexpr (NL == 1) {
         m_leaf(out, U[0], bwd[0]);
+        if constexpr (NDIR < 4) {
+            if (mu[0] >= NDIR) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        out.re[i][j] = R(0);
+                        out.im[i][j] = R(0);
+                    }
+            }
+        }
     } else {
         M3<R> right;
-        leaf_tree<NL / 2>(U, bwd, out);
-        leaf_tree<NL / 2>(U + NL / 2, bwd + NL / 2, right);
+        leaf_tree<NL / 2, NDIR>(U, bwd, mu, out);
+        leaf_tree<NL / 2, NDIR>(U + NL / 2, bwd + NL / 2, mu + NL / 2, right);
         m_add(out, right);
     }
+}
+
+// tr[Delta Delta^dag] for Delta = [(K - K^dag)/(2i)]_traceless, in float64
+// from K of either precision: M = (K - K^dag)/(2i) has diagonal Im K_ii and
+// off-diagonal ((Im K_ij + Im K_ji) - i (Re K_ij - Re K_ji)) / 2, and
+// Delta = M - tr(M)/3 (equal to Eq. (landaugauge) with A_mu of Sec. 2, a g = 1).
+template <typename T>
+__device__ __forceinline__ double delta_norm2(const M3<T>& K)
+{
+    const double d0 = (double)K.im[0][0], d1 = (double)K.im[1][1], d2 = (double)K.im[2][2];
+    const double tr3 = (d0 + d1 + d2) / 3.0;
+    const double e0 = d0 - tr3, e1 = d1 - tr3, e2 = d2 - tr3;
+    double off = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i + 1; j < 3; ++j) {
+            const double mr = 0.5 * ((double)K.im[i][j] + (double)K.im[j][i]);
+            const double mi = 0.5 * ((double)K.re[i][j] - (double)K.re[j][i]);
+            off += mr * mr + mi * mi;
+        }
+    return e0 * e0 + e1 * e1 + e2 * e2 + 2.0 * off;
 }
 
 // One site update of the site (parity, h) by lane r of its TPS-lane group.
 // TRACKG (float32 mixed-precision bulk): also g(x) <- G g(x) for the float32
 // gauge transformation accumulated since the original links; lane r of the
-// group stores the chunks c with c % TPS == r.
-template <typename R, int TPS, int MODE, bool TRACKG, int CP = 0>
-__device__ __forceinline__ void site_update(const LinkField<R>& f, const Geom& g, int parity, uint32_t h, int r,
-                                            const Rule<R>& rule, const GField& gacc)
+// group stores the chunks c with c % TPS == r.  NDIR: directions in K (Landau
+// 4, Coulomb 3); all 8 links are transformed either way.  With est, lane 0 of
+// the group returns tr[Delta Delta^dag] of the site's K before the update (the
+// gauge-condition term of the configuration the site sees), every other lane
+// and every call without est 0.
+template <typename R, int TPS, int MODE, bool TRACKG, int CP = 0, int NDIR = NDIR_LANDAU>
+__device__ __forceinline__ double site_update(const LinkField<R>& f, const Geom& g, int parity, uint32_t h, int r,
+                                              const Rule<R>& rule, const GField& gacc, bool est = false)
 {
     constexpr int NL = 8 / TPS;
     const Site s = decode_site(g, parity, h);
@@ -285,10 +331,11 @@ __device__ __forceinline__ void site_update(const LinkField<R>& f, const Geom& g
     for (int k = 0; k < NL; ++k) rebuild_row2(U[k]);
 
     M3<R> K;
-    leaf_tree<NL>(U, bwd, K);
+    leaf_tree<NL, NDIR>(U, bwd, mu_of, K);
     if constexpr (TPS >= 2) dpp_accumulate<DPP_XOR1>(K);
     if constexpr (TPS >= 4) dpp_accumulate<DPP_XOR2>(K);
     if constexpr (TPS >= 8) dpp_accumulate<DPP_HALF_MIRROR>(K);
+    const double th = (est && r == 0) ? delta_norm2(K) : 0.0;
 
     M3<R> G;
     {
@@ -325,6 +372,7 @@ __device__ __forceinline__ void site_update(const LinkField<R>& f, const Geom& g
         for (int c = 0; c < 3; ++c)
             if (c % TPS == r) store_g_chunk(gacc, parity, h, c, gx);
     }
+    return th;
 }
 
 // ------------------------------------------------------------- reductions --
@@ -421,8 +469,10 @@ __device__ __forceinline__ void finalize_pairs(const double* partial, uint32_t n
 
 // Gauge-condition and functional terms of the site (parity, h), float64:
 // th = tr[Delta Delta^dag] with Delta = [(K - K^dag)/(2i)]_traceless (equal to
-// Eq. (landaugauge) with A_mu of Sec. 2, a g = 1), fr = sum_mu Re tr U_mu(x).
-template <typename Field>
+// Eq. (landaugauge) with A_mu of Sec. 2, a g = 1), fr = sum_mu Re tr U_mu(x),
+// mu over the first NDIR directions (Landau 4; Coulomb 3, the spatial Delta_C
+// and functional of one timeslice).
+template <int NDIR = NDIR_LANDAU, typename Field>
 __device__ __forceinline__ void measure_site(const Field& f, const Geom& g, int parity, uint32_t h, double& th,
                                              double& fr)
 {
@@ -436,7 +486,7 @@ __device__ __forceinline__ void measure_site(const Field& f, const Geom& g, int 
             K.im[i][j] = 0.0;
         }
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu) {
+    for (int mu = 0; mu < NDIR; ++mu) {
         M3<double> u;
         load_full_f64(f, parity, mu, h, u);
         fr += u.re[0][0] + u.re[1][1] + u.re[2][2];
@@ -450,21 +500,7 @@ __device__ __forceinline__ void measure_site(const Field& f, const Geom& g, int 
                 K.im[i][j] -= u.im[j][i];
             }
     }
-    // M = (K - K^dag)/(2i): diagonal Im K_ii; off-diagonal
-    // ((Im K_ij + Im K_ji) - i (Re K_ij - Re K_ji)) / 2.  Delta = M - tr(M)/3.
-    const double d0 = K.im[0][0], d1 = K.im[1][1], d2 = K.im[2][2];
-    const double tr3 = (d0 + d1 + d2) / 3.0;
-    const double e0 = d0 - tr3, e1 = d1 - tr3, e2 = d2 - tr3;
-    double off = 0.0;
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = i + 1; j < 3; ++j) {
-            const double mr = 0.5 * (K.im[i][j] + K.im[j][i]);
-            const double mi = 0.5 * (K.re[i][j] - K.re[j][i]);
-            off += mr * mr + mi * mi;
-        }
-    th = e0 * e0 + e1 * e1 + e2 * e2 + 2.0 * off;
+    th = delta_norm2(K);
 }
 
 }  // namespace gf

@@ -1,0 +1,147 @@
+// gf_sweep_impl.h -- the single-lattice checkerboard half-sweep kernel
+// (overrelaxation and heat bath, Sec. 2 and the abstract of arXiv:1412.3655)
+// and its launch dispatch, instantiated once per gauge: gf_sweep.hip for
+// Landau gauge (K over 4 directions), gf_sweep_coulomb.hip for Coulomb gauge
+// (K over x, y, z).  The per-site body lives in gf_site.h.  The loop over
+// sites is over the half index of one colour: every link is read once and
+// written once per half-sweep (per site update in FP64 with 12-real links:
+// 768 B read and 768 B written), whatever the gauge.
+#pragma once
+
+#include "gf_kernels.h"
+#include "gf_site.h"
+
+namespace gf {
+namespace sweep_impl {
+
+// est != nullptr: the block also sums tr[Delta Delta^dag] of its sites' K
+// before their update into est[2 (parity gridDim.x + b)] (b the block's tile,
+// second double 0), which a fixed-order pass turns into an estimate of theta.
+template <typename R, int TPS, int MODE, int BLOCK, bool TRACKG, int CP, int NDIR>
+__global__ void __launch_bounds__(BLOCK) k_or_half_sweep(LinkField<R> f, Geom g, int parity, Rule<R> rule,
+                                                         GField gacc, double* est)
+{
+    // With cached loads the white half-sweep takes the blocks in reverse
+    // order, so it starts on the links the black half-sweep touched last,
+    // which are still in the Infinity Cache (a 32^4 float64 field is 402 MB
+    // against 256 MB of cache), and ends where the next black half-sweep
+    // starts; non-temporal loads leave nothing there to reuse.  Sites of one
+    // colour are independent, so the result does not depend on the order.
+    const uint32_t b = (parity && !nt_loads(CP)) ? gridDim.x - 1u - blockIdx.x : blockIdx.x;
+    const uint32_t gid = b * (uint32_t)BLOCK + threadIdx.x;
+    const uint32_t h = gid / TPS;
+    const int r = (int)(gid % TPS);
+    // whole groups of TPS lanes skip together, so every DPP partner is live
+    double th = 0.0;
+    if (h < g.vh) th = site_update<R, TPS, MODE, TRACKG, CP, NDIR>(f, g, parity, h, r, rule, gacc, est != nullptr);
+    if (est) block_sum2<BLOCK>(th, 0.0, est + 2 * ((size_t)parity * gridDim.x + b));
+}
+
+// Blocks of one half-sweep launch in configuration c (the estimate buffer
+// holds 2 pairs per block of each colour).
+inline uint32_t sweep_grid(const Geom& g, const SweepConfig& c)
+{
+    return (uint32_t)(((uint64_t)g.vh * (uint64_t)c.tps + (uint64_t)c.block - 1) / (uint64_t)c.block);
+}
+
+template <int NDIR, typename R, int TPS, int MODE, bool TRACKG>
+hipError_t launch_tps(const LinkField<R>& f, const Geom& g, int parity, const Rule<R>& rule, const SweepConfig& c,
+                      const GField& gacc, hipStream_t st, double* est)
+{
+    const int block = c.block;
+    const uint32_t grid = sweep_grid(g, c);
+    if (grid == 0) return hipSuccess;
+#define GF_LAUNCH(B, CPV)                                                                                      \
+    hipLaunchKernelGGL((k_or_half_sweep<R, TPS, MODE, B, TRACKG, CPV, NDIR>), dim3(grid), dim3(B), 0, st, f, g, \
+                       parity, rule, gacc, est)
+#define GF_LAUNCH_SMALL_BLOCKS(CPV)                  \
+    switch (block) {                                 \
+        case 64: GF_LAUNCH(64, CPV); break;          \
+        case 128: GF_LAUNCH(128, CPV); break;        \
+        case 256: GF_LAUNCH(256, CPV); break;        \
+        default: return hipErrorInvalidValue;        \
+    }
+    if (c.nt == 1 || c.nt == 2) {
+        if constexpr (TPS <= 4) {
+            if (c.nt == 1) {
+                GF_LAUNCH_SMALL_BLOCKS(1)
+            } else {
+                GF_LAUNCH_SMALL_BLOCKS(2)
+            }
+        } else {
+            return hipErrorInvalidValue;
+        }
+    } else if (c.nt == 0) {
+        switch (block) {
+            case 64: GF_LAUNCH(64, 0); break;
+            case 128: GF_LAUNCH(128, 0); break;
+            case 256: GF_LAUNCH(256, 0); break;
+            default:
+                if constexpr (TPS > 1)
+                    GF_LAUNCH(512, 0);
+                else
+                    return hipErrorInvalidValue;
+                break;
+        }
+    } else {
+        return hipErrorInvalidValue;
+    }
+#undef GF_LAUNCH_SMALL_BLOCKS
+#undef GF_LAUNCH
+    return hipGetLastError();
+}
+
+template <int NDIR, typename R, int MODE, bool TRACKG>
+hipError_t launch_mode(const LinkField<R>& f, const Geom& g, int parity, const Rule<R>& rule, const SweepConfig& c,
+                       const GField& gacc, hipStream_t st, double* est)
+{
+    switch (c.tps) {
+        case 1: return launch_tps<NDIR, R, 1, MODE, TRACKG>(f, g, parity, rule, c, gacc, st, est);
+        case 2: return launch_tps<NDIR, R, 2, MODE, TRACKG>(f, g, parity, rule, c, gacc, st, est);
+        case 8: return launch_tps<NDIR, R, 8, MODE, TRACKG>(f, g, parity, rule, c, gacc, st, est);
+        default: return launch_tps<NDIR, R, 4, MODE, TRACKG>(f, g, parity, rule, c, gacc, st, est);
+    }
+}
+
+template <int NDIR>
+hipError_t or_half_sweep(const LinkField<double>& f, const Geom& g, int parity, double omega, int mode,
+                         const SweepConfig& cfg, hipStream_t st, double* est)
+{
+    const GField none{nullptr, 0};
+    const Rule<double> rule{omega, 1.0, 0u, 0u, 0u};
+    return mode == OR_EXACT ? launch_mode<NDIR, double, 0, false>(f, g, parity, rule, cfg, none, st, est)
+                            : launch_mode<NDIR, double, 1, false>(f, g, parity, rule, cfg, none, st, est);
+}
+
+template <int NDIR>
+hipError_t or_half_sweep(const LinkField<float>& f, const Geom& g, int parity, float omega, int mode,
+                         const SweepConfig& cfg, const GField& gacc, hipStream_t st, double* est)
+{
+    const Rule<float> rule{omega, 1.0f, 0u, 0u, 0u};
+    if (gacc.base)
+        return mode == OR_EXACT ? launch_mode<NDIR, float, 0, true>(f, g, parity, rule, cfg, gacc, st, est)
+                                : launch_mode<NDIR, float, 1, true>(f, g, parity, rule, cfg, gacc, st, est);
+    return mode == OR_EXACT ? launch_mode<NDIR, float, 0, false>(f, g, parity, rule, cfg, gacc, st, est)
+                            : launch_mode<NDIR, float, 1, false>(f, g, parity, rule, cfg, gacc, st, est);
+}
+
+template <int NDIR>
+hipError_t hb_half_sweep(const LinkField<double>& f, const Geom& g, int parity, double T, uint64_t seed,
+                         uint32_t sweep, const SweepConfig& cfg, hipStream_t st)
+{
+    const GField none{nullptr, 0};
+    const Rule<double> rule{1.0, T, (uint32_t)seed, (uint32_t)(seed >> 32), sweep};
+    return launch_mode<NDIR, double, HEATBATH, false>(f, g, parity, rule, cfg, none, st, nullptr);
+}
+
+template <int NDIR>
+hipError_t hb_half_sweep(const LinkField<float>& f, const Geom& g, int parity, float T, uint64_t seed,
+                         uint32_t sweep, const SweepConfig& cfg, const GField& gacc, hipStream_t st)
+{
+    const Rule<float> rule{1.0f, T, (uint32_t)seed, (uint32_t)(seed >> 32), sweep};
+    if (gacc.base) return launch_mode<NDIR, float, HEATBATH, true>(f, g, parity, rule, cfg, gacc, st, nullptr);
+    return launch_mode<NDIR, float, HEATBATH, false>(f, g, parity, rule, cfg, gacc, st, nullptr);
+}
+
+}  // namespace sweep_impl
+}  // namespace gf

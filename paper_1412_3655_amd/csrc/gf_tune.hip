@@ -4,7 +4,7 @@
 // axes are lanes per site (1, 2, 4, 8), threads per block (64..512) and the
 // cache policy of the link accesses (plain / non-temporal / non-temporal
 // stores only), timed with HIP events on a scratch copy of the links so the
-// lattice is unchanged.
+// lattice is unchanged.  The kernel timed is that of the lattice's gauge.
 // Every configuration gives bitwise the same links, so only time decides.
 #include <cstdio>
 #include <cstring>
@@ -28,13 +28,15 @@ std::string device_arch()
 }
 
 // A GF_MIXED lattice's float32 sweeps also update g(x) (another 96 B per site
-// update and more registers), so they are a kernel of their own: "fp32g".
+// update and more registers), so they are a kernel of their own: "fp32g".  The
+// Coulomb kernels (K over three directions) are keyed apart with a "-coulomb"
+// suffix.
 std::string cache_key(gf_lattice L, gf_prec kernel)
 {
     char buf[128];
     const char* k = kernel == GF_FP64 ? "fp64" : (L->gacc.base ? "fp32g" : "fp32");
-    snprintf(buf, sizeof buf, "%s %d %d %d %d %s", device_arch().c_str(), L->dims[0], L->dims[1], L->dims[2],
-             L->dims[3], k);
+    snprintf(buf, sizeof buf, "%s %d %d %d %d %s%s", device_arch().c_str(), L->dims[0], L->dims[1], L->dims[2],
+             L->dims[3], k, L->gauge == GAUGE_COULOMB ? "-coulomb" : "");
     return buf;
 }
 
@@ -112,14 +114,14 @@ gf_status tune(gf_lattice L, gf_prec kernel, bool heat_bath, int32_t n_sweeps, c
                     hipError_t r;
                     if (heat_bath && kernel == GF_FP32)
                         r = launch_hb_half_sweep(f32, L->geom, p, 1.0f, 1u, hb_sweep, c, track ? g_s : g_none,
-                                                 L->stream);
+                                                 L->stream, L->gauge);
                     else if (heat_bath)
-                        r = launch_hb_half_sweep(f64, L->geom, p, 1.0, 1u, hb_sweep, c, L->stream);
+                        r = launch_hb_half_sweep(f64, L->geom, p, 1.0, 1u, hb_sweep, c, L->stream, L->gauge);
                     else if (kernel == GF_FP32)
                         r = launch_or_half_sweep(f32, L->geom, p, 1.7f, GF_OR_EXACT, c, track ? g_s : g_none,
-                                                 L->stream);
+                                                 L->stream, L->gauge);
                     else
-                        r = launch_or_half_sweep(f64, L->geom, p, 1.7, GF_OR_EXACT, c, L->stream);
+                        r = launch_or_half_sweep(f64, L->geom, p, 1.7, GF_OR_EXACT, c, L->stream, L->gauge);
                     if (r != hipSuccess) return r;
                 }
                 ++hb_sweep;

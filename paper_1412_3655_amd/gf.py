@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libgf.so")
 GF_OK, GF_E_ARG, GF_E_NOMEM, GF_E_HIP, GF_E_STATE, GF_E_NUMERIC, GF_E_FULL, GF_E_CANCELLED = range(8)
 GF_FP64, GF_FP32, GF_MIXED = 0, 1, 2
 GF_OR_EXACT, GF_OR_BINOMIAL1 = 0, 1
+GF_LANDAU, GF_COULOMB = 0, 1
 
 _STATUS_NAMES = {
     GF_OK: "GF_OK",
@@ -135,6 +136,12 @@ _SIGNATURES = {
     "gf_measure_theta_F_noalloc": [ctypes.POINTER(_i32), _vp, _vp, _vp],
     "gf_fix_until": [_vp, ctypes.POINTER(gf_fix_params), ctypes.POINTER(gf_fix_result)],
     "gf_tune_switch": [_vp, ctypes.c_double, _dp, _dp],
+    "gf_set_check_policy": [_vp, _i32, ctypes.c_double],
+    "gf_sweep_estimate": [_vp, ctypes.c_double, ctypes.c_int, _dp],
+    "gf_lattice_counters": [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
+    "gf_set_gauge": [_vp, ctypes.c_int],
+    "gf_get_gauge": [_vp, ctypes.POINTER(ctypes.c_int)],
+    "gf_measure_timeslices": [_vp, _dp, _dp],
     "gf_reunitarize": [_vp],
     "gf_plaquette": [_vp, _dp],
     "gf_pool_create": [ctypes.POINTER(gf_pool_config), _vp, ctypes.POINTER(_vp)],
@@ -148,6 +155,10 @@ _SIGNATURES = {
     "gf_pool_release": [_vp, ctypes.c_uint64],
     "gf_pool_cancel": [_vp, ctypes.c_uint64],
     "gf_pool_stats": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_int64)],
+    "gf_pool_autotune": [_vp, _i32, _i32, ctypes.c_size_t, ctypes.POINTER(gf_tune_entry), _i32,
+                         ctypes.POINTER(_i32), ctypes.POINTER(gf_tune_entry)],
+    "gf_pool_get_shape": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                          ctypes.POINTER(_i32)],
     "gf_clock": [],
     "gf_probe_copy": [ctypes.c_size_t, _i32, _i32, _i32, _dp],
     "gf_last_error": [],
@@ -432,6 +443,42 @@ def gf_tune_switch(lat, theta_target: float = 1e-12):
     return fl.value, sw.value
 
 
+def gf_set_check_policy(lat, adaptive: bool, margin: float = 100.0) -> None:
+    _call("gf_set_check_policy", lat, int(bool(adaptive)), float(margin))
+
+
+def gf_sweep_estimate(lat, omega: float, mode: int = GF_OR_EXACT) -> float:
+    th = ctypes.c_double()
+    _call("gf_sweep_estimate", lat, float(omega), int(mode), ctypes.byref(th))
+    return th.value
+
+
+def gf_lattice_counters(lat):
+    """(exact measurements, fused estimates) taken on the lattice."""
+    m = ctypes.c_int64()
+    e = ctypes.c_int64()
+    _call("gf_lattice_counters", lat, ctypes.byref(m), ctypes.byref(e))
+    return m.value, e.value
+
+
+def gf_set_gauge(lat, gauge: int) -> None:
+    _call("gf_set_gauge", lat, int(gauge))
+
+
+def gf_get_gauge(lat) -> int:
+    g = ctypes.c_int()
+    _call("gf_get_gauge", lat, ctypes.byref(g))
+    return g.value
+
+
+def gf_measure_timeslices(lat, nt: int):
+    """Coulomb gauge: (theta_C(t), F_C(t)) as two float64 arrays of nt = Nt."""
+    th = np.empty(int(nt))
+    fr = np.empty(int(nt))
+    _call("gf_measure_timeslices", lat, th.ctypes.data_as(_dp), fr.ctypes.data_as(_dp))
+    return th, fr
+
+
 def gf_reunitarize(lat) -> None:
     _call("gf_reunitarize", lat)
 
@@ -445,10 +492,12 @@ def gf_plaquette(lat) -> float:
 class Lattice:
     """Owning wrapper: ``with Lattice(dims, GF_FP64) as lat: ...``."""
 
-    def __init__(self, dims, prec: int = GF_FP64, stream=None):
+    def __init__(self, dims, prec: int = GF_FP64, stream=None, gauge: int = GF_LANDAU):
         self.dims = tuple(int(d) for d in dims)
         self.prec = prec
         self.handle = gf_create_lattice(self.dims, prec, stream)
+        if gauge != GF_LANDAU:
+            gf_set_gauge(self.handle, gauge)
 
     @property
     def volume(self) -> int:
@@ -488,6 +537,28 @@ class Lattice:
 
     def measure(self):
         return gf_measure_theta_F(self.handle)
+
+    @property
+    def gauge(self) -> int:
+        return gf_get_gauge(self.handle)
+
+    @gauge.setter
+    def gauge(self, g: int):
+        gf_set_gauge(self.handle, g)
+
+    def set_check_policy(self, adaptive: bool, margin: float = 100.0):
+        gf_set_check_policy(self.handle, adaptive, margin)
+
+    def sweep_estimate(self, omega: float, mode: int = GF_OR_EXACT) -> float:
+        return gf_sweep_estimate(self.handle, omega, mode)
+
+    @property
+    def counters(self):
+        return gf_lattice_counters(self.handle)
+
+    def measure_timeslices(self):
+        """Coulomb gauge: (theta_C(t), F_C(t)) per timeslice."""
+        return gf_measure_timeslices(self.handle, self.dims[3])
 
     def fix_until(self, **kw) -> FixResult:
         return gf_fix_until(self.handle, **kw)
@@ -633,15 +704,43 @@ def gf_pool_stats(pool):
     return a.value, f.value, b.value
 
 
+def gf_pool_autotune(pool, kernel: int, n_sweeps: int = 3, scratch_bytes: int = 8 << 30):
+    """((tps, block, nontemporal), table of (tps, block, nontemporal, us_per_sweep)) of the pool's
+    sweep of `kernel` (GF_FP32 / GF_FP64), timed on copies of the resident jobs."""
+    table = (gf_tune_entry * 16)()
+    n = _i32()
+    best = gf_tune_entry()
+    _call("gf_pool_autotune", pool, int(kernel), int(n_sweeps), int(scratch_bytes), table, 16, ctypes.byref(n),
+          ctypes.byref(best))
+    rows = [(table[i].tps, table[i].block, table[i].nontemporal, table[i].us_per_sweep) for i in range(n.value)]
+    return (best.tps, best.block, best.nontemporal), rows
+
+
+def gf_pool_get_shape(pool):
+    """(tps32, block32, tps64, block64) of the pool's sweeps."""
+    v = [_i32() for _ in range(4)]
+    _call("gf_pool_get_shape", pool, *[ctypes.byref(x) for x in v])
+    return tuple(x.value for x in v)
+
+
 class Pool:
     """Owning wrapper of a gf_pool."""
 
     def __init__(self, hbm_budget: int, max_slots: int, prec: int = GF_MIXED, check_every: int = 10,
-                 mode: int = GF_OR_EXACT, tps32: int = 0, tps64: int = 0, stream=None):
+                 mode: int = GF_OR_EXACT, tps32: int = 0, tps64: int = 0, stream=None, block32: int = 0,
+                 block64: int = 0):
         self.check_every = int(check_every)
         self.mode = int(mode)
-        self.handle = gf_pool_create(hbm_budget, max_slots, prec, check_every, mode, tps32, 0, tps64, 0, stream)
+        self.handle = gf_pool_create(hbm_budget, max_slots, prec, check_every, mode, tps32, block32, tps64, block64,
+                                     stream)
         self.dims = {}
+
+    def autotune(self, kernel: int, n_sweeps: int = 3, scratch_bytes: int = 8 << 30):
+        return gf_pool_autotune(self.handle, kernel, n_sweeps, scratch_bytes)
+
+    @property
+    def shape(self):
+        return gf_pool_get_shape(self.handle)
 
     def admit(self, job_id, dims, links, **kw) -> bool:
         kw.setdefault("check_every", self.check_every)

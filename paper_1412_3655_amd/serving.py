@@ -43,6 +43,7 @@ class RunStats:
     seconds: float
     latencies: list = field(default_factory=list)        # every finished job
     conv_latencies: list = field(default_factory=list)   # converged jobs only
+    results: dict = field(default_factory=dict)          # job_id -> (result, links) when collected
     sweeps: int = 0
     sweeps_fp32: int = 0     # fix-phase sweeps in float32 (mixed precision)
     sweeps_fp64: int = 0     # fix-phase sweeps in float64
@@ -54,6 +55,8 @@ class RunStats:
     max_queue: int = 0       # most jobs waiting for admission at once
     max_resident: int = 0    # most jobs resident in the pool at once
     peak_bytes: int = 0      # most device bytes the pool held for job lattices
+    shape: tuple = ()        # (tps32, block32, tps64, block64) of the pool's sweeps
+    tuning: dict = field(default_factory=dict)  # autotuner tables (kernel -> rows), when tuned
 
     def summary(self) -> dict:
         def pct(v, q):
@@ -68,8 +71,11 @@ class RunStats:
             "lattices_per_s": self.jobs / self.seconds if self.seconds > 0 else None,
             "p50_latency_s_converged": pct(self.conv_latencies, 50),
             "p99_latency_s_converged": pct(self.conv_latencies, 99),
-            "p50_latency_s_all": pct(self.latencies, 50),
-            "p99_latency_s_all": pct(self.latencies, 99),
+            # every job, a job that stopped at its sweep cap unconverged counted at
+            # the time it stopped: its time to theta < 1e-12 is censored there, so
+            # these are lower bounds of the percentiles over all jobs
+            "p50_latency_s_censored": pct(self.latencies, 50),
+            "p99_latency_s_censored": pct(self.latencies, 99),
             "site_updates_per_s": self.site_updates / self.seconds if self.seconds > 0 else None,
             "sweeps": self.sweeps,
             "fix_sweeps_fp32": self.sweeps_fp32,
@@ -81,6 +87,8 @@ class RunStats:
             "max_queue_depth": self.max_queue,
             "max_resident_jobs": self.max_resident,
             "peak_hbm_bytes": self.peak_bytes,
+            "pool_shape_tps32_block32_tps64_block64": list(self.shape) or None,
+            "pool_autotune_us_per_sweep": self.tuning or None,
         }
 
 
@@ -122,8 +130,12 @@ def serving_trace(n=1000, rate=20.0, master_seed=5, anneal_fraction=0.3, anneal_
 
 
 def run_pool(jobs, links_of, prec=gf.GF_MIXED, check_every=10, max_slots=256, hbm_budget=None,
-             fix=None, open_loop=True, tps32=0, tps64=0, log=None):
-    """Run `jobs` through a pool; links_of(job) -> canonical host links."""
+             fix=None, open_loop=True, tps32=0, tps64=0, log=None, collect=False, autotune=False):
+    """Run `jobs` through a pool; links_of(job) -> canonical host links.  collect=True
+    downloads every finished job's links into stats.results[job_id] = (result, links)
+    (the download is inside the timed run).  autotune=True runs gf_pool_autotune on the jobs
+    resident before the first step (inside the timed run), for the float32 sweeps of a
+    mixed pool and the float64 sweeps."""
     fix = dict(fix or {})
     import torch
 
@@ -154,6 +166,13 @@ def run_pool(jobs, links_of, prec=gf.GF_MIXED, check_every=10, max_slots=256, hb
             stats.max_queue = max(stats.max_queue, len(queue))
             stats.max_resident = max(stats.max_resident, active + finished)
             stats.peak_bytes = max(stats.peak_bytes, held)
+            if active and autotune and not stats.tuning:
+                kinds = [gf.GF_FP32, gf.GF_FP64] if prec == gf.GF_MIXED else [gf.GF_FP64]
+                for k in kinds:
+                    _, rows = pool.autotune(k, 3, scratch_bytes=min(held, 16 << 30))
+                    stats.tuning["fp32" if k == gf.GF_FP32 else "fp64"] = [
+                        [t, b, round(us, 1)] for (t, b, _, us) in rows]
+                stats.shape = pool.shape
             if active:
                 pool.step()
             elif finished == 0 and arrivals and not queue:
@@ -162,7 +181,10 @@ def run_pool(jobs, links_of, prec=gf.GF_MIXED, check_every=10, max_slots=256, hb
                 raise RuntimeError(f"job {queue[0].job_id} {queue[0].dims} does not fit the pool budget")
             for d in pool.poll():
                 j = by_id.pop(d["job_id"])
-                pool.release(d["job_id"])
+                if collect:
+                    stats.results[d["job_id"]] = (d, pool.fetch_links(d["job_id"]))
+                else:
+                    pool.release(d["job_id"])
                 lat = d["t_done"] - t0 - j.arrival if open_loop else d["t_done"] - t0
                 r = d["result"]
                 stats.latencies.append(lat)
@@ -183,6 +205,7 @@ def run_pool(jobs, links_of, prec=gf.GF_MIXED, check_every=10, max_slots=256, hb
                     log(f"  job {j.job_id} {j.dims} eps={j.eps:.2f} anneal={j.anneal}: sweeps {r.sweeps} "
                         f"({r.sweeps_fp32}/{r.sweeps_fp64}) theta {r.theta:.2e} latency {lat:.2f} s")
         stats.seconds = gf.gf_clock() - t0
+        stats.shape = pool.shape
     return stats
 
 

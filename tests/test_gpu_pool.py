@@ -278,3 +278,49 @@ def test_pool_large_slot_table_uses_the_search_fallback():
         for i in range(len(jobs)):
             assert done[i]["result"] == ref[i][0]
             assert np.array_equal(pool.fetch_links(i), ref[i][1])
+
+
+def test_pool_autotune_keeps_results():
+    """gf_pool_autotune times every (lanes, block) shape of the pool's sweeps on copies of the
+    resident jobs, applies the fastest, and leaves the jobs' links alone: results still equal
+    the solo runs bitwise.  A shape outside {1, 2, 4} x {64, 128, 256} is rejected."""
+    ce = 5
+    say("pool autotune keeps results")
+    jobs = JOBS[:4]
+    inputs = [gi.gen_links(d, e, s) for (d, e, s, _) in jobs]
+    ref = [solo(d, u, gf.GF_MIXED, a, 200 + i, ce) for i, ((d, e, s, a), u) in enumerate(zip(jobs, inputs))]
+    with pytest.raises(gf.GFError):
+        gf.Pool(1 << 30, 4, prec=gf.GF_MIXED, tps32=8)
+    with pytest.raises(gf.GFError):
+        gf.Pool(1 << 30, 4, prec=gf.GF_MIXED, block64=512)
+    with gf.Pool(1 << 34, 8, prec=gf.GF_MIXED, check_every=ce, block32=64, block64=256) as pool:
+        assert pool.shape == (2, 64, 1, 256)
+        with pytest.raises(gf.GFError) as e:
+            pool.autotune(gf.GF_FP32)
+        assert e.value.status == gf.GF_E_STATE  # nothing resident
+        for i, ((d, e_, s, a), u) in enumerate(zip(jobs, inputs)):
+            assert pool.admit(300 + i, d, u, anneal_sweeps=a, T_start=1.25, T_end=0.05, seed=200 + i,
+                              **{k: v for k, v in fix_kw(ce).items() if k not in ("check_every", "mode")})
+        pool.step()
+        (t32, b32, _), rows32 = pool.autotune(gf.GF_FP32, 2)
+        (t64, b64, _), rows64 = pool.autotune(gf.GF_FP64, 2)
+        say(f"  float32 {t32}/{b32} of {len(rows32)} shapes, float64 {t64}/{b64} of {len(rows64)}")
+        assert len(rows32) == 9 and len(rows64) == 9
+        assert pool.shape == (t32, b32, t64, b64)
+        assert min(r[3] for r in rows32) == [r[3] for r in rows32 if (r[0], r[1]) == (t32, b32)][0]
+        done = {}
+        for _ in range(2000):
+            pool.step()
+            for d in pool.poll():
+                done[d["job_id"]] = d
+            if len(done) == len(jobs):
+                break
+        for i, (r_solo, l_solo) in enumerate(ref):
+            assert done[300 + i]["result"] == r_solo
+            assert np.array_equal(pool.fetch_links(300 + i), l_solo)
+    with gf.Pool(1 << 34, 4, prec=gf.GF_FP64, check_every=ce) as pool:
+        assert pool.admit(1, jobs[0][0], inputs[0], **{k: v for k, v in fix_kw(ce).items()
+                                                        if k not in ("check_every", "mode")})
+        with pytest.raises(gf.GFError) as e:
+            pool.autotune(gf.GF_FP32)
+        assert e.value.status == gf.GF_E_ARG
