@@ -47,6 +47,11 @@ __all__ = [
     "gen_links",
     "pure_gauge_links",
     "su2_embedded_links",
+    "random_traceless_hermitian2",
+    "haar_su2",
+    "gen_links_su2",
+    "identity_links_su2",
+    "pure_gauge_links_su2",
 ]
 
 
@@ -189,3 +194,62 @@ def su2_embedded_links(dims, seed: int, eps: float = 0.8) -> np.ndarray:
     u[:, 1, 1] = a[:, 0] - 1j * a[:, 3]
     u[:, 2, 2] = 1.0
     return to_canonical(u.reshape(v, 4, 3, 3))
+
+
+# ------------------------------------------------------------- SU(2) links --
+# Canonical SU(2) layout: (V, 4, 2, 2, 2) float64 = [site][mu][row][col][re, im].
+
+
+def random_traceless_hermitian2(rng: np.random.Generator, n: int) -> np.ndarray:
+    """n random traceless Hermitian 2x2 matrices: diagonal N(0,1) minus the mean,
+    off-diagonal (a + i b)/sqrt(2)."""
+    d = rng.standard_normal((n, 2))
+    d -= d.mean(axis=1, keepdims=True)
+    off = rng.standard_normal((n, 2)) / math.sqrt(2.0)
+    h = np.zeros((n, 2, 2), dtype=np.complex128)
+    h[:, 0, 0] = d[:, 0]
+    h[:, 1, 1] = d[:, 1]
+    h[:, 0, 1] = off[:, 0] + 1j * off[:, 1]
+    h[:, 1, 0] = off[:, 0] - 1j * off[:, 1]
+    return h
+
+
+def haar_su2(rng: np.random.Generator, n: int) -> np.ndarray:
+    """n Haar-distributed SU(2) matrices: a normalised Gaussian 4-vector (r0, r1, r2, r3) as
+    [[r0 + i r3, r2 + i r1], [-r2 + i r1, r0 - i r3]]."""
+    r = rng.standard_normal((n, 4))
+    r /= np.linalg.norm(r, axis=1, keepdims=True)
+    g = np.empty((n, 2, 2), dtype=np.complex128)
+    g[:, 0, 0] = r[:, 0] + 1j * r[:, 3]
+    g[:, 0, 1] = r[:, 2] + 1j * r[:, 1]
+    g[:, 1, 0] = -r[:, 2] + 1j * r[:, 1]
+    g[:, 1, 1] = r[:, 0] - 1j * r[:, 3]
+    return g
+
+
+def identity_links_su2(dims) -> np.ndarray:
+    v = volume(dims)
+    u = np.zeros((v, 4, 2, 2), dtype=np.complex128)
+    u[:, :, 0, 0] = u[:, :, 1, 1] = 1.0
+    return to_canonical(u)
+
+
+def gen_links_su2(dims, eps: float, seed: int, gauge_rotate: bool = True) -> np.ndarray:
+    """SU(2) configuration of the same recipe: exp(i eps H), H random traceless Hermitian 2x2,
+    then a Haar SU(2) gauge rotation h(x) U_mu(x) h(x+mu^)^dag.  (V, 4, 2, 2, 2) float64."""
+    dims = tuple(int(d) for d in dims)
+    v = volume(dims)
+    rng = np.random.default_rng(int(seed))
+    h = random_traceless_hermitian2(rng, 4 * v)
+    u = expi_hermitian(h, float(eps)).reshape(v, 4, 2, 2)
+    if gauge_rotate:
+        u = _gauge_rotate(u, haar_su2(rng, v), dims)
+    return to_canonical(u)
+
+
+def pure_gauge_links_su2(dims, seed: int) -> np.ndarray:
+    """U_mu(x) = h(x) h(x+mu^)^dagger with Haar SU(2) h."""
+    dims = tuple(int(d) for d in dims)
+    rng = np.random.default_rng(int(seed))
+    u = complex_view(identity_links_su2(dims)).copy()
+    return to_canonical(_gauge_rotate(u, haar_su2(rng, volume(dims)), dims))

@@ -52,6 +52,18 @@ __all__ = [
     "coulomb_measure",
     "coulomb_fix_until",
     "coulomb_anneal",
+    "su2lat_site_update",
+    "su2lat_half_sweep",
+    "su2lat_sweep",
+    "su2lat_update_sites_in_order",
+    "su2lat_theta_density",
+    "su2lat_measure",
+    "su2lat_coulomb_measure",
+    "su2lat_plaquette",
+    "su2lat_unitarity",
+    "su2lat_reunitarize",
+    "su2lat_fix_until",
+    "su2lat_anneal",
 ]
 
 OR_EXACT = 0
@@ -132,6 +144,25 @@ def _declare(L):
     L.oracle_coulomb_anneal.argtypes = [_dp, _ip, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                         ctypes.c_uint64, ctypes.c_int32]
     L.oracle_coulomb_anneal.restype = ctypes.c_int64
+    L.oracle_su2lat_site_update.argtypes = [_dp, _ip, ctypes.c_int64, ctypes.c_double, ctypes.c_int, ctypes.c_int]
+    L.oracle_su2lat_site_update.restype = ctypes.c_double
+    L.oracle_su2lat_half_sweep.argtypes = [_dp, _ip, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int]
+    L.oracle_su2lat_sweep.argtypes = [_dp, _ip, ctypes.c_int32, ctypes.c_double, ctypes.c_int, ctypes.c_int]
+    L.oracle_su2lat_update_sites_in_order.argtypes = [_dp, _ip, _i64p, ctypes.c_int64, ctypes.c_double,
+                                                      ctypes.c_int, ctypes.c_int]
+    L.oracle_su2lat_theta_density.argtypes = [_dp, _ip, ctypes.c_int, _dp]
+    L.oracle_su2lat_measure.argtypes = [_dp, _ip, _dp, _dp]
+    L.oracle_su2lat_coulomb_measure.argtypes = [_dp, _ip, _dp, _dp]
+    L.oracle_su2lat_plaquette.argtypes = [_dp, _ip]
+    L.oracle_su2lat_plaquette.restype = ctypes.c_double
+    L.oracle_su2lat_unitarity.argtypes = [_dp, ctypes.c_int64, _dp, _dp]
+    L.oracle_su2lat_reunitarize.argtypes = [_dp, ctypes.c_int64]
+    L.oracle_su2lat_fix_until.argtypes = [_dp, _ip, ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_int, _ip, _dp, _dp]
+    L.oracle_su2lat_fix_until.restype = ctypes.c_int
+    L.oracle_su2lat_anneal.argtypes = [_dp, _ip, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
+                                       ctypes.c_int32, ctypes.c_int]
+    L.oracle_su2lat_anneal.restype = ctypes.c_int64
     L.oracle_hb_subgroup_draws.argtypes = [_dp, ctypes.c_double, ctypes.c_uint64, ctypes.c_int64, _dp]
     L.oracle_hb_subgroup_draws.restype = ctypes.c_int64
     L.oracle_num_threads.restype = ctypes.c_int
@@ -404,3 +435,115 @@ def coulomb_anneal(u, dims, nsweeps: int, T0: float, T1: float, seed: int, sweep
     d = _dims(dims, u)
     return int(lib().oracle_coulomb_anneal(_p(u), _p(d, _ip), int(nsweeps), float(T0), float(T1),
                                            int(seed) & 0xFFFFFFFFFFFFFFFF, int(sweep_offset)))
+
+
+# --------------------------------------------------------- SU(2) gauge group --
+# Links are canonical float64 arrays (V, 4, 2, 2, 2); ndir = 4 (Landau) or 3 (Coulomb).
+
+
+def _links2(u: np.ndarray) -> np.ndarray:
+    if not (isinstance(u, np.ndarray) and u.dtype == np.float64 and u.flags.c_contiguous):
+        raise TypeError("links must be a C-contiguous float64 numpy array")
+    if u.shape[-4:] != (4, 2, 2, 2):
+        raise ValueError("SU(2) links must have shape (V, 4, 2, 2, 2)")
+    return u
+
+
+def su2lat_site_update(u, dims, site: int, omega: float, mode: int = OR_EXACT, ndir: int = 4) -> float:
+    """Overrelax one site in place; returns the change of Re tr K at that site."""
+    u = _links2(u)
+    d = _dims(dims, u)
+    return float(lib().oracle_su2lat_site_update(_p(u), _p(d, _ip), int(site), float(omega), int(mode), int(ndir)))
+
+
+def su2lat_half_sweep(u, dims, colour: int, omega: float, mode: int = OR_EXACT, ndir: int = 4):
+    u = _links2(u)
+    d = _dims(dims, u)
+    lib().oracle_su2lat_half_sweep(_p(u), _p(d, _ip), int(colour), float(omega), int(mode), int(ndir))
+    return u
+
+
+def su2lat_sweep(u, dims, nsweeps: int, omega: float, mode: int = OR_EXACT, ndir: int = 4):
+    u = _links2(u)
+    d = _dims(dims, u)
+    lib().oracle_su2lat_sweep(_p(u), _p(d, _ip), int(nsweeps), float(omega), int(mode), int(ndir))
+    return u
+
+
+def su2lat_update_sites_in_order(u, dims, sites, omega: float, mode: int = OR_EXACT, ndir: int = 4):
+    u = _links2(u)
+    d = _dims(dims, u)
+    s = np.ascontiguousarray(np.asarray(sites, dtype=np.int64))
+    lib().oracle_su2lat_update_sites_in_order(_p(u), _p(d, _ip), _p(s, _i64p), s.size, float(omega), int(mode),
+                                              int(ndir))
+    return u
+
+
+def su2lat_theta_density(u, dims, ndir: int = 4) -> np.ndarray:
+    u = _links2(u)
+    d = _dims(dims, u)
+    out = np.empty(u.shape[0])
+    lib().oracle_su2lat_theta_density(_p(u), _p(d, _ip), int(ndir), _p(out))
+    return out
+
+
+def su2lat_measure(u, dims):
+    """(theta, F) of Landau gauge, N_c = 2."""
+    u = _links2(u)
+    d = _dims(dims, u)
+    th = ctypes.c_double()
+    f = ctypes.c_double()
+    lib().oracle_su2lat_measure(_p(u), _p(d, _ip), ctypes.byref(th), ctypes.byref(f))
+    return th.value, f.value
+
+
+def su2lat_coulomb_measure(u, dims):
+    """(theta_C(t), F_C(t)) per timeslice, N_c = 2."""
+    u = _links2(u)
+    d = _dims(dims, u)
+    th = np.empty(int(d[3]))
+    fr = np.empty(int(d[3]))
+    lib().oracle_su2lat_coulomb_measure(_p(u), _p(d, _ip), _p(th), _p(fr))
+    return th, fr
+
+
+def su2lat_plaquette(u, dims) -> float:
+    u = _links2(u)
+    d = _dims(dims, u)
+    return float(lib().oracle_su2lat_plaquette(_p(u), _p(d, _ip)))
+
+
+def su2lat_unitarity(u):
+    a = np.ascontiguousarray(u, dtype=np.float64)
+    mu = ctypes.c_double()
+    md = ctypes.c_double()
+    lib().oracle_su2lat_unitarity(_p(a), a.size // 8, ctypes.byref(mu), ctypes.byref(md))
+    return mu.value, md.value
+
+
+def su2lat_reunitarize(u):
+    if not (u.dtype == np.float64 and u.flags.c_contiguous) or u.size % 8:
+        raise TypeError("need a C-contiguous float64 array of 2x2 complex matrices")
+    lib().oracle_su2lat_reunitarize(_p(u), u.size // 8)
+    return u
+
+
+def su2lat_fix_until(u, dims, omega: float = 1.7, mode: int = OR_EXACT, theta_target: float = 1e-12,
+                     max_sweeps: int = 3000, check_every: int = 10, reunit_every: int = 100, ndir: int = 4) -> dict:
+    u = _links2(u)
+    d = _dims(dims, u)
+    sw = ctypes.c_int32()
+    th = ctypes.c_double()
+    f = ctypes.c_double()
+    conv = lib().oracle_su2lat_fix_until(_p(u), _p(d, _ip), float(omega), int(mode), float(theta_target),
+                                         int(max_sweeps), int(check_every), int(reunit_every), int(ndir),
+                                         ctypes.byref(sw), ctypes.byref(th), ctypes.byref(f))
+    return dict(converged=bool(conv), sweeps=sw.value, theta=th.value, F=f.value)
+
+
+def su2lat_anneal(u, dims, nsweeps: int, T0: float, T1: float, seed: int, sweep_offset: int = 0,
+                  ndir: int = 4) -> int:
+    u = _links2(u)
+    d = _dims(dims, u)
+    return int(lib().oracle_su2lat_anneal(_p(u), _p(d, _ip), int(nsweeps), float(T0), float(T1),
+                                          int(seed) & 0xFFFFFFFFFFFFFFFF, int(sweep_offset), int(ndir)))

@@ -43,6 +43,9 @@
  *                            iteration with K, Delta and F over the spatial
  *                            directions only, per timeslice; the heat-bath
  *                            prelude of the Coulomb functional likewise.
+ *   oracle_su2lat_* ........ the same method for gauge group SU(2) (abstract;
+ *                            Sec. 2's maximiser applies to K directly, Sec.
+ *                            4.1 swaps the group by the parameterisation).
  *   oracle_reunitarize ..... Gram-Schmidt of rows 0 and 1, row 2 rebuilt as
  *                            the conjugated cross product (the two-row
  *                            representation of Sec. 3.1 keeps row 2 implicit).
@@ -997,6 +1000,309 @@ int64_t oracle_hb_subgroup_draws(const double* k, double T, uint64_t seed, int64
         hb_subgroup_element((const cx*)k, T, &st, &capped, (cx*)(out + 8 * i));
     }
     return capped;
+}
+
+/* ------------------------------------------------------------------ */
+/* SU(2) gauge group                                                   */
+/* ------------------------------------------------------------------ */
+
+/* The paper's method for gauge group SU(2) (abstract; Sec. 2 states the SU(2)
+ * maximiser, and Sec. 4.1 changes the group by the link parameterisation
+ * alone): links are 2x2 complex matrices, canonical layout
+ * U[site][mu][row][col][re,im] (8 doubles per link).  K(x) sums U_mu(x) +
+ * U_mu(x-mu^)^dag over the first ndir directions (4: Landau, 3: Coulomb); the
+ * site's element is the maximiser K^dag / sqrt(det K^dag) itself (no subgroup
+ * iteration; a sum of SU(2) matrices lies in the real span of SU(2), so the
+ * projection leaves it unchanged) raised to omega, and it transforms the 8
+ * links at x.  Measurements with N_c = 2:
+ *   theta = (1/(2V)) sum_x tr[Delta Delta^dag],  F = (1/(8V)) sum_x sum_mu Re tr U,
+ *   plaquette = (1/(12V)) sum_x sum_{mu<nu} Re tr[U U U^dag U^dag]. */
+
+static cx* link2_at(double* U, long s, int mu)
+{
+    return (cx*)(U + ((size_t)s * 4 + (size_t)mu) * 8);
+}
+
+static const cx* clink2_at(const double* U, long s, int mu)
+{
+    return (const cx*)(U + ((size_t)s * 4 + (size_t)mu) * 8);
+}
+
+static void m2_mul(cx* c, const cx* a, const cx* b)
+{
+    cx t[4];
+    t[0] = a[0] * b[0] + a[1] * b[2];
+    t[1] = a[0] * b[1] + a[1] * b[3];
+    t[2] = a[2] * b[0] + a[3] * b[2];
+    t[3] = a[2] * b[1] + a[3] * b[3];
+    memcpy(c, t, sizeof t);
+}
+
+static void m2_dag(cx* d, const cx* a)
+{
+    cx t[4] = {conj(a[0]), conj(a[2]), conj(a[1]), conj(a[3])};
+    memcpy(d, t, sizeof t);
+}
+
+static void local_K2(const double* U, const geom* g, long s, int ndir, cx* K)
+{
+    K[0] = K[1] = K[2] = K[3] = 0.0;
+    for (int mu = 0; mu < ndir; ++mu) {
+        const cx* f = clink2_at(U, s, mu);
+        cx b[4];
+        m2_dag(b, clink2_at(U, hop(g, s, mu, -1), mu));
+        for (int i = 0; i < 4; ++i) K[i] += f[i] + b[i];
+    }
+}
+
+/* U_mu(x) <- S U_mu(x), U_mu(x-mu^) <- U_mu(x-mu^) S^dag for all 4 mu. */
+static void transform_site2(double* U, const geom* g, long s, const cx* S)
+{
+    cx Sd[4];
+    m2_dag(Sd, S);
+    for (int mu = 0; mu < 4; ++mu) {
+        cx* f = link2_at(U, s, mu);
+        m2_mul(f, S, f);
+        cx* b = link2_at(U, hop(g, s, mu, -1), mu);
+        m2_mul(b, b, Sd);
+    }
+}
+
+/* Overrelaxation update of site s; returns the change of Re tr K(x). */
+static double su2lat_site_update(double* U, const geom* g, long s, double omega, int mode, int ndir)
+{
+    cx K[4], g2[4], SK[4];
+    local_K2(U, g, s, ndir, K);
+    if (!oracle_su2_maximiser((const double*)K, (double*)g2)) return 0.0;
+    oracle_su2_overrelax((const double*)g2, omega, mode, (double*)g2);
+    m2_mul(SK, g2, K);
+    transform_site2(U, g, s, g2);
+    return creal(SK[0] + SK[3]) - creal(K[0] + K[3]);
+}
+
+double oracle_su2lat_site_update(double* U, const int32_t* dims, int64_t site, double omega, int mode, int ndir)
+{
+    geom g = mkgeom(dims);
+    return su2lat_site_update(U, &g, (long)site, omega, mode, ndir);
+}
+
+void oracle_su2lat_half_sweep(double* U, const int32_t* dims, int colour, double omega, int mode, int ndir)
+{
+    geom g = mkgeom(dims);
+#pragma omp parallel for schedule(static) if (g.V >= OMP_MIN_SITES)
+    for (long s = 0; s < g.V; ++s)
+        if (colour_of(&g, s) == colour) su2lat_site_update(U, &g, s, omega, mode, ndir);
+}
+
+void oracle_su2lat_sweep(double* U, const int32_t* dims, int32_t nsweeps, double omega, int mode, int ndir)
+{
+    for (int32_t k = 0; k < nsweeps; ++k) {
+        oracle_su2lat_half_sweep(U, dims, 0, omega, mode, ndir);
+        oracle_su2lat_half_sweep(U, dims, 1, omega, mode, ndir);
+    }
+}
+
+void oracle_su2lat_update_sites_in_order(double* U, const int32_t* dims, const int64_t* sites, int64_t n,
+                                         double omega, int mode, int ndir)
+{
+    geom g = mkgeom(dims);
+    for (int64_t i = 0; i < n; ++i) su2lat_site_update(U, &g, (long)sites[i], omega, mode, ndir);
+}
+
+/* A = [(U - U^dag)/(2i)]_traceless for a 2x2 link. */
+static void gauge_potential2(const cx* u, cx* A)
+{
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) A[2 * i + j] = (u[2 * i + j] - conj(u[2 * j + i])) / (2.0 * I);
+    cx tr = (A[0] + A[3]) / 2.0;
+    A[0] -= tr;
+    A[3] -= tr;
+}
+
+static double theta_site2(const double* U, const geom* g, long s, int ndir)
+{
+    cx D[4] = {0.0, 0.0, 0.0, 0.0}, A[4], Dd[4], P[4];
+    for (int mu = 0; mu < ndir; ++mu) {
+        gauge_potential2(clink2_at(U, s, mu), A);
+        for (int i = 0; i < 4; ++i) D[i] += A[i];
+        gauge_potential2(clink2_at(U, hop(g, s, mu, -1), mu), A);
+        for (int i = 0; i < 4; ++i) D[i] -= A[i];
+    }
+    m2_dag(Dd, D);
+    m2_mul(P, D, Dd);
+    return creal(P[0] + P[3]);
+}
+
+void oracle_su2lat_theta_density(const double* U, const int32_t* dims, int ndir, double* out)
+{
+    geom g = mkgeom(dims);
+#pragma omp parallel for schedule(static) if (g.V >= OMP_MIN_SITES)
+    for (long s = 0; s < g.V; ++s) out[s] = theta_site2(U, &g, s, ndir);
+}
+
+/* Landau gauge (ndir 4): theta = (1/(2V)) sum tr[Delta Delta^dag], F = (1/(8V)) sum sum Re tr U. */
+void oracle_su2lat_measure(const double* U, const int32_t* dims, double* theta, double* F)
+{
+    geom g = mkgeom(dims);
+    double* th = (double*)malloc(sizeof(double) * (size_t)g.V);
+    double* fr = (double*)malloc(sizeof(double) * (size_t)g.V);
+#pragma omp parallel for schedule(static) if (g.V >= OMP_MIN_SITES)
+    for (long s = 0; s < g.V; ++s) {
+        th[s] = theta_site2(U, &g, s, 4);
+        double f = 0.0;
+        for (int mu = 0; mu < 4; ++mu) f += creal(clink2_at(U, s, mu)[0] + clink2_at(U, s, mu)[3]);
+        fr[s] = f;
+    }
+    double st = 0.0, sf = 0.0;
+    for (long s = 0; s < g.V; ++s) {
+        st += th[s];
+        sf += fr[s];
+    }
+    free(th);
+    free(fr);
+    *theta = st / (2.0 * (double)g.V);
+    *F = sf / (8.0 * (double)g.V);
+}
+
+/* Coulomb gauge: theta_C(t) = (1/(2 V3)) sum_{x in t} tr[Delta_C Delta_C^dag],
+ * F_C(t) = (1/(6 V3)) sum_{x in t} sum_i Re tr U_i(x). */
+void oracle_su2lat_coulomb_measure(const double* U, const int32_t* dims, double* theta_t, double* F_t)
+{
+    geom g = mkgeom(dims);
+    const long V3 = g.V / g.n[3];
+    for (int t = 0; t < g.n[3]; ++t) {
+        double st = 0.0, sf = 0.0;
+        for (long s = (long)t * V3; s < (long)(t + 1) * V3; ++s) {
+            st += theta_site2(U, &g, s, 3);
+            for (int i = 0; i < 3; ++i) sf += creal(clink2_at(U, s, i)[0] + clink2_at(U, s, i)[3]);
+        }
+        theta_t[t] = st / (2.0 * (double)V3);
+        F_t[t] = sf / (6.0 * (double)V3);
+    }
+}
+
+double oracle_su2lat_plaquette(const double* U, const int32_t* dims)
+{
+    geom g = mkgeom(dims);
+    double sum = 0.0;
+    for (long s = 0; s < g.V; ++s)
+        for (int mu = 0; mu < 4; ++mu)
+            for (int nu = mu + 1; nu < 4; ++nu) {
+                cx t1[4], a[4], b[4];
+                m2_mul(t1, clink2_at(U, s, mu), clink2_at(U, hop(&g, s, mu, +1), nu));
+                m2_dag(a, clink2_at(U, hop(&g, s, nu, +1), mu));
+                m2_mul(t1, t1, a);
+                m2_dag(b, clink2_at(U, s, nu));
+                m2_mul(t1, t1, b);
+                sum += creal(t1[0] + t1[3]);
+            }
+    return sum / (12.0 * (double)g.V);
+}
+
+/* max over links of ||U^dag U - 1||_F and |det U - 1| (2x2 links) */
+void oracle_su2lat_unitarity(const double* U, int64_t nlinks, double* max_unit, double* max_det)
+{
+    double mu = 0.0, md = 0.0;
+    for (int64_t l = 0; l < nlinks; ++l) {
+        const cx* u = (const cx*)(U + (size_t)l * 8);
+        cx ud[4], p[4];
+        m2_dag(ud, u);
+        m2_mul(p, ud, u);
+        double fro = 0.0;
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) {
+                cx e = p[2 * i + j] - (i == j ? 1.0 : 0.0);
+                fro += creal(e * conj(e));
+            }
+        fro = sqrt(fro);
+        double dd = cabs(u[0] * u[3] - u[1] * u[2] - 1.0);
+        if (fro > mu) mu = fro;
+        if (dd > md) md = dd;
+    }
+    *max_unit = mu;
+    *max_det = md;
+}
+
+/* Back onto SU(2): the projection onto the real span of SU(2) (as for a
+ * subgroup block), divided by the square root of its determinant. */
+void oracle_su2lat_reunitarize(double* U, int64_t nlinks)
+{
+    for (int64_t l = 0; l < nlinks; ++l) {
+        cx* u = (cx*)(U + (size_t)l * 8);
+        cx q[4];
+        oracle_su2_project((const double*)u, (double*)q);
+        cx root = csqrt(q[0] * q[3] - q[1] * q[2]);
+        for (int i = 0; i < 4; ++i) u[i] = q[i] / root;
+    }
+}
+
+/* Fix-until for SU(2) (the loop of oracle_fix_until; Coulomb gauge: theta =
+ * the largest theta_C(t), F = the mean F_C(t)). */
+int oracle_su2lat_fix_until(double* U, const int32_t* dims, double omega, int mode, double theta_target,
+                            int32_t max_sweeps, int32_t check_every, int32_t reunit_every, int ndir,
+                            int32_t* sweeps_out, double* theta_out, double* F_out)
+{
+    geom g = mkgeom(dims);
+    const int nt = g.n[3];
+    double* th = (double*)malloc(sizeof(double) * (size_t)nt);
+    double* fr = (double*)malloc(sizeof(double) * (size_t)nt);
+    double theta = 0.0, F = 0.0;
+    int32_t sweeps = 0;
+    for (;;) {
+        if (ndir == 4) {
+            oracle_su2lat_measure(U, dims, &theta, &F);
+        } else {
+            oracle_su2lat_coulomb_measure(U, dims, th, fr);
+            theta = 0.0;
+            F = 0.0;
+            for (int t = 0; t < nt; ++t) {
+                if (th[t] > theta) theta = th[t];
+                F += fr[t];
+            }
+            F /= (double)nt;
+        }
+        if (!(theta >= theta_target) || sweeps >= max_sweeps) break;
+        int32_t n = max_sweeps - sweeps < check_every ? max_sweeps - sweeps : check_every;
+        for (int32_t k = 0; k < n; ++k) {
+            oracle_su2lat_sweep(U, dims, 1, omega, mode, ndir);
+            ++sweeps;
+            if (reunit_every > 0 && sweeps % reunit_every == 0) oracle_su2lat_reunitarize(U, 4 * (int64_t)g.V);
+        }
+    }
+    free(th);
+    free(fr);
+    *sweeps_out = sweeps;
+    *theta_out = theta;
+    *F_out = F;
+    return theta < theta_target;
+}
+
+/* Heat bath for SU(2): each site's element is drawn from exp(Re tr[g K]/T)
+ * dHaar(g) with the sampler of the SU(3) subgroups (subgroup index 0 of the
+ * Philox counter), K over the first ndir directions. */
+int64_t oracle_su2lat_anneal(double* U, const int32_t* dims, int32_t nsweeps, double T0, double T1, uint64_t seed,
+                             int32_t sweep_offset, int ndir)
+{
+    geom g = mkgeom(dims);
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    int64_t capped_total = 0;
+    for (int32_t sw = 0; sw < nsweeps; ++sw) {
+        double T = anneal_temperature(sw, nsweeps, T0, T1);
+        for (int c = 0; c < 2; ++c) {
+            int capped = 0;
+#pragma omp parallel for schedule(static) reduction(+ : capped) if (g.V >= OMP_MIN_SITES)
+            for (long s = 0; s < g.V; ++s) {
+                if (colour_of(&g, s) != c) continue;
+                cx K[4], g2[4];
+                local_K2(U, &g, s, ndir, K);
+                hb_stream st = {{key[0], key[1]}, (uint32_t)s, (uint32_t)(sweep_offset + sw), 0u, 0u};
+                hb_subgroup_element(K, T, &st, &capped, g2);
+                transform_site2(U, &g, s, g2);
+            }
+            capped_total += capped;
+        }
+    }
+    return capped_total;
 }
 
 int oracle_num_threads(void)
