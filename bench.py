@@ -7,18 +7,25 @@ step = one sweep = the black half-sweep then the white half-sweep = V site
 updates; the timed region holds `--steps` sweeps with the links resident in
 HBM.  Prints one JSON line.
 
-Extra legs (reported inside the same line): the float32 sweep rate, the 32^4
-run to theta < 1e-12 in float64 and in mixed precision (capped; it is also
-run on a smoother input of the same generator, eps = 0.6, which converges), a
-cpu_baseline of the FP64 CPU oracle on a bounded number of sweeps of the same
-lattice (all host cores, and one core), and the serving workload (Poisson arrivals of jobs of mixed volume,
-continuous-batching pool in mixed precision vs float64 one lattice at a time:
-converged lattices/s and p50/p99 time to theta < 1e-12; `--no-serve` skips
-it).  `--batched` and `--fullsize` add the 64-lattice and the 48^3 x 96
-workloads.  `--copy-probe` adds a plain device copy of known size (the library's
-streaming probe, 1 GiB read + 1 GiB written per dispatch, one warm-up and one
-timed dispatch) before the timed region, so that a `rocprofv3 --pmc` run of
-this script can scale the HBM counters of the sweep kernel.
+Extra legs (reported inside the same line; each has a --no-... switch): the
+float32 sweep rate; the float64 sweep on the 48^3 x 96 lattice (4.08 GB of
+links, far above the 256 MB Infinity Cache: the HBM-only bandwidth point);
+the 32^4 run to theta < 1e-12 in float64 and in mixed precision (capped; also
+on a smoother input of the same generator, eps = 0.6, which converges); the
+8^4 convergence workload in float64 and mixed precision; the 64-lattice
+batched workload (mixed-precision pool vs float64 one lattice at a time); the
+serving workload (Poisson arrivals of jobs of mixed volume, continuous-batching
+pool in mixed precision under an HBM budget vs float64 one lattice at a time:
+converged lattices/s and p50/p99 time to theta < 1e-12); the 48^3 x 96
+anneal + mixed-precision workload; and a cpu_baseline of the FP64 CPU oracle
+(a bounded number of 32^4 sweeps on all host cores and on one core, and the
+8^4 run to theta < 1e-12, against which the GPU's 8^4 results are compared).
+Inputs are generated on host threads from the start; only the 32^4 sweep
+legs, timed with HIP events, overlap that generation.  `--copy-probe` adds a
+plain device copy of known size (the library's streaming probe, 1 GiB read +
+1 GiB written per dispatch, one warm-up and one timed dispatch) before the
+timed region, so that a `rocprofv3 --pmc` run of this script can scale the HBM
+counters of the sweep kernel.
 """
 
 from __future__ import annotations
@@ -30,6 +37,7 @@ import os
 import re
 import sys
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -37,9 +45,21 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, AMD published peak
 BYTES_PER_SITE = {"f64": 1536, "f32": 768}  # 8 links x 12 reals, read + write
+# Floating-point operations of one overrelaxation site update as the kernel computes it
+# (K tracked through the subgroups; exact power; add, sub, mul = 1, FMA = 2, sqrt, div,
+# atan2, sin, cos = 1 each): row 2 of 8 links 8 x 42 = 336, K from 8 leaves 7 x 18 = 126,
+# 3 subgroups 3 x (8 projection + 14 power) = 66, 2 rotations of K and 2 of G by a
+# subgroup element 4 x 84 = 336, rows 0-1 of G U or U G^dag for 8 links 8 x 132 = 1056.
+FLOPS_PER_SITE_UPDATE = 336 + 126 + 66 + 336 + 1056
+# The paper's 470 GFlops at ~80 % of a GTX 580's 192.4 GB/s with 768-B single-precision site
+# updates implies ~2.35e3 flop per site update: its convention, used for a like-for-like figure.
+PAPER_FLOPS_PER_SITE_UPDATE = 2350
+PAPER_GFLOPS = 470.0
 METRIC = "SU(3) OR site-updates/s + HBM GB/s (% peak); converged lattices/s, p99 to θ<1e-12"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "or_sweep_f64_32x4_traffic.md")
-SWEEP_SOURCES = ["gf_sweep.hip", "gf_site.h", "gf_device.h"]
+TRAFFIC_FILE_48 = os.path.join(ROOT, "profiles", "or_sweep_f64_48x96_traffic.md")
+FULL_DIMS = (48, 48, 48, 96)
+SWEEP_SOURCES = ["gf_sweep.hip", "gf_sweep_impl.h", "gf_site.h", "gf_device.h"]
 
 
 def log(msg):
@@ -54,11 +74,11 @@ def sweep_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def committed_traffic():
+def committed_traffic(path=TRAFFIC_FILE):
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
     or None when it is missing or the sweep kernel changed since."""
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(path).read()
     except OSError:
         return None
     src = re.search(r"kernel_source_sha256:\s*([0-9a-f]+)", text)
@@ -66,6 +86,50 @@ def committed_traffic():
     if not src or not val or src.group(1) != sweep_source_hash():
         return None
     return float(val.group(1))
+
+
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+class Inputs:
+    """The legs' inputs, generated up front several lattices at a time on host threads
+    (the generator is deterministic per (dims, eps, seed) whatever thread runs it), so that
+    no timed leg waits for the CPU or shares it with generation."""
+
+    def __init__(self, gi, workers):
+        self.gi = gi
+        self.ex = ThreadPoolExecutor(max(1, workers))
+        self.fut = {}
+
+    def want(self, dims, eps, seed):
+        key = (tuple(int(d) for d in dims), float(eps), int(seed))
+        if key not in self.fut:
+            self.fut[key] = self.ex.submit(self.gi.gen_links, *key)
+        return key
+
+    def get(self, dims, eps, seed):
+        return self.fut[self.want(dims, eps, seed)].result()
+
+    def wait_all(self):
+        t0 = time.perf_counter()
+        for f in list(self.fut.values()):
+            f.result()
+        return time.perf_counter() - t0
+
+    def drop(self, dims, eps, seed):
+        self.fut.pop((tuple(int(d) for d in dims), float(eps), int(seed)), None)
+
+    def close(self):
+        self.ex.shutdown(wait=True)
+        self.fut.clear()
 
 
 def time_run(lat, torch, stream, steps, omega, mode, chunk=10):
@@ -110,14 +174,20 @@ def copy_bandwidth(gf, nbytes=1 << 30, reps=10):
     return best
 
 
-def fix_until_leg(gf, torch, stream, links, dims, args, eps):
-    """The run of one input to theta < 1e-12: plain FP64 and FP32-bulk / FP64-polish (GF_MIXED)."""
+def fix_until_leg(gf, torch, stream, links, dims, args, eps, adaptive_too=False):
+    """The run of one input to theta < 1e-12: plain FP64 and FP32-bulk / FP64-polish (GF_MIXED),
+    with exact checks every 10 sweeps, and (adaptive_too) again with adaptive checks (the
+    fused estimate decides where the exact measurement runs; same result bitwise)."""
     out = {"eps": eps}
     kw = dict(omega=args.omega, mode=args.mode, theta_target=1e-12, max_sweeps=args.fix_max_sweeps,
               check_every=10, reunit_every=100, theta_switch=args.theta_switch)
     P0 = None
-    for name, prec in (("fp64", gf.GF_FP64), ("mixed", gf.GF_MIXED)):
+    runs = [("fp64", gf.GF_FP64, False), ("mixed", gf.GF_MIXED, False)]
+    if adaptive_too:
+        runs += [("fp64_adaptive", gf.GF_FP64, True), ("mixed_adaptive", gf.GF_MIXED, True)]
+    for name, prec, adaptive in runs:
         with gf.Lattice(dims, prec, stream=stream) as lat:
+            lat.set_check_policy(adaptive)
             lat.set_sweep_config(args.tps, args.block, args.nt, kernel=gf.GF_FP64)
             lat.set_links(links)
             if prec == gf.GF_MIXED:
@@ -138,37 +208,50 @@ def fix_until_leg(gf, torch, stream, links, dims, args, eps):
             t0 = time.perf_counter()
             r = lat.fix_until(**kw)
             dt = time.perf_counter() - t0
+            measures, estimates = lat.counters
             P1 = lat.plaquette()
         out[name] = {"seconds": dt, "converged": r.converged, "sweeps": r.sweeps, "sweeps_fp32": r.sweeps_fp32,
-                     "sweeps_fp64": r.sweeps_fp64, "theta": r.theta, "F": r.F, "plaquette_drift": abs(P1 - P0)}
+                     "sweeps_fp64": r.sweeps_fp64, "theta": r.theta, "F": r.F, "plaquette_drift": abs(P1 - P0),
+                     "exact_measurements": measures, "estimates": estimates}
         log(f"fix_until eps={eps} {name}: {dt:.2f} s, sweeps {r.sweeps} ({r.sweeps_fp32}/{r.sweeps_fp64}), "
             f"theta {r.theta:.3e}, F {r.F:.12f}")
+    # the float64 GPU run is the reference here (it is parity-tested against the oracle)
     out["mixed"]["dF_vs_fp64"] = out["mixed"]["F"] - out["fp64"]["F"]
+    out["mixed"]["dtheta_vs_fp64"] = out["mixed"]["theta"] - out["fp64"]["theta"]
     out["speedup_mixed_vs_fp64"] = out["fp64"]["seconds"] / out["mixed"]["seconds"]
+    for name in ("fp64", "mixed"):
+        a = out.get(name + "_adaptive")
+        if a:
+            same = all(a[k] == out[name][k] for k in ("sweeps", "sweeps_fp32", "sweeps_fp64", "theta", "F"))
+            a["same_result_as_exact_checks"] = same
+            a["speedup_vs_exact_checks"] = out[name]["seconds"] / a["seconds"]
     return out
 
 
-def batched_leg(gf, gi, stream, args):
-    """64 lattices of uneven volume to theta < 1e-12: mixed-precision pool vs FP64 one at a time."""
+def batched_leg(gf, inputs, stream, args):
+    """64 lattices of uneven volume to theta < 1e-12: mixed-precision pool vs FP64 one at a time
+    (and, with --batched-fp64-pool, the float64 pool)."""
     from paper_1412_3655_amd import serving
 
     jobs = serving.batched_jobs(64, 4)
-    t0 = time.perf_counter()
-    links = {j.job_id: gi.gen_links(j.dims, j.eps, j.seed) for j in jobs}
-    log(f"batched: generated 64 lattices ({sum(serving.volume(j.dims) for j in jobs)} sites) in "
-        f"{time.perf_counter() - t0:.1f} s")
+    links = {j.job_id: inputs.get(j.dims, j.eps, j.seed) for j in jobs}
     fix = dict(omega=args.omega, mode=args.mode, theta_target=1e-12, max_sweeps=args.job_max_sweeps, check_every=10,
                reunit_every=100, theta_switch=args.theta_switch)
     t32, t64 = args.pool_tps32, args.pool_tps64
-    out = {"jobs": 64, "max_sweeps": args.job_max_sweeps, "pool_tps32": t32, "pool_tps64": t64}
-    for name, fn in (
-        ("pool_mixed", lambda: serving.run_pool(jobs, lambda j: links[j.job_id], gf.GF_MIXED, 10, 64, None, fix,
-                                                False, t32, t64)),
-        ("pool_fp64", lambda: serving.run_pool(jobs, lambda j: links[j.job_id], gf.GF_FP64, 10, 64, None, fix,
-                                               False, t32, t64)),
-        ("fifo_fp64", lambda: serving.run_fifo(jobs, lambda j: links[j.job_id], gf.GF_FP64, fix, False, args.tps,
-                                               args.block, args.nt)),
-    ):
+    out = {"workload": "64 lattices, shapes uniform over {12^4, 16^4, 16^3x32, 24^3x48}, eps uniform in "
+                       "[0.4, 1.0] (master seed 4), link seeds 1000+i, to theta < 1e-12",
+           "jobs": 64, "sites": sum(serving.volume(j.dims) for j in jobs), "max_sweeps": args.job_max_sweeps,
+           "pool_tps32": t32, "pool_tps64": t64}
+    tune = not args.no_pool_autotune
+    out["pool_autotune"] = tune
+    legs = [("pool_mixed", lambda: serving.run_pool(jobs, lambda j: links[j.job_id], gf.GF_MIXED, 10, 64, None,
+                                                    fix, False, t32, t64, autotune=tune))]
+    if args.batched_fp64_pool:
+        legs.append(("pool_fp64", lambda: serving.run_pool(jobs, lambda j: links[j.job_id], gf.GF_FP64, 10, 64,
+                                                           None, fix, False, t32, t64, autotune=tune)))
+    legs.append(("fifo_fp64", lambda: serving.run_fifo(jobs, lambda j: links[j.job_id], gf.GF_FP64, fix, False,
+                                                       args.tps, args.block, args.nt)))
+    for name, fn in legs:
         st = fn()
         out[name] = st.summary()
         log(f"batched {name}: {st.converged}/64 converged in {st.seconds:.2f} s")
@@ -178,29 +261,38 @@ def batched_leg(gf, gi, stream, args):
     return out
 
 
-def serving_leg(gf, gi, stream, args):
-    """Poisson arrivals (20/s) of jobs of mixed volume: continuous batching vs FP64 FIFO."""
+def serving_jobs(args):
     from paper_1412_3655_amd import serving
 
     jobs = serving.serving_trace(args.serve_jobs, 20.0, 5)
-    t0 = time.perf_counter()
     bank = {}
     for j in jobs:
-        key = (j.dims, j.eps)
-        if key not in bank:
-            bank[key] = gi.gen_links(j.dims, j.eps, 3000 + len(bank))
-    log(f"serving: {len(jobs)} jobs, {len(bank)} distinct inputs generated in {time.perf_counter() - t0:.1f} s")
+        bank.setdefault((j.dims, j.eps), 3000 + len(bank))
+    return jobs, bank
+
+
+def serving_leg(gf, inputs, stream, args):
+    """Poisson arrivals (20/s) of jobs of mixed volume: continuous batching vs FP64 FIFO."""
+    from paper_1412_3655_amd import serving
+
+    jobs, seeds = serving_jobs(args)
+    links_of = lambda j: inputs.get(j.dims, j.eps, seeds[(j.dims, j.eps)])
     fix = dict(omega=args.omega, mode=args.mode, theta_target=1e-12, max_sweeps=args.job_max_sweeps, check_every=10,
                reunit_every=100, theta_switch=args.theta_switch)
     t32, t64 = args.pool_tps32, args.pool_tps64
-    links_of = lambda j: bank[(j.dims, j.eps)]
-    out = {"jobs": len(jobs), "rate_per_s": 20.0, "max_sweeps": args.job_max_sweeps,
-           "distinct_inputs": len(bank), "last_arrival_s": jobs[-1].arrival, "pool_tps32": t32, "pool_tps64": t64}
     budget = int(args.serve_budget_gb * 1e9) if args.serve_budget_gb > 0 else None
-    out["hbm_budget_bytes"] = budget
+    out = {"workload": f"{len(jobs)} Poisson arrivals at 20/s (master seed 5), L^4 with V log-uniform in "
+                       "[8^4, 32^4], 30 % with a 500-sweep anneal (T 1.25 -> 0.01), to theta < 1e-12; eps drawn "
+                       "uniform in [0.4, 1.0] and rounded to the nearest of {0.4, 0.7, 1.0}, and jobs with equal "
+                       "(L, eps) share one input (each input takes seconds of CPU to generate)",
+           "jobs": len(jobs), "rate_per_s": 20.0, "max_sweeps": args.job_max_sweeps,
+           "distinct_inputs": len(seeds), "last_arrival_s": jobs[-1].arrival, "pool_tps32": t32, "pool_tps64": t64,
+           "hbm_budget_bytes": budget,
+           "largest_job_bytes": max(gf.gf_pool_job_bytes(j.dims, gf.GF_MIXED) for j in jobs)}
     st = serving.run_pool(jobs, links_of, gf.GF_MIXED, 10, 256, budget, fix, True, t32, t64)
     out["pool_mixed"] = st.summary()
-    log(f"serving pool: {st.converged}/{len(jobs)} converged, {st.seconds:.1f} s")
+    log(f"serving pool: {st.converged}/{len(jobs)} converged, {st.seconds:.1f} s, max queue {st.max_queue}, "
+        f"peak {st.peak_bytes / 1e9:.2f} GB")
     st = serving.run_fifo(jobs, links_of, gf.GF_FP64, fix, True, args.tps, args.block, args.nt)
     out["fifo_fp64"] = st.summary()
     log(f"serving fifo: {st.converged}/{len(jobs)} converged, {st.seconds:.1f} s")
@@ -221,15 +313,56 @@ def serving_leg(gf, gi, stream, args):
     return out
 
 
-def fullsize_leg(gf, gi, torch, stream, args):
+def fullsize_f64_leg(gf, torch, stream, u, args):
+    """Float64 overrelaxation sweep on 48^3 x 96 (eps = 1.0, seed 0): 4.08 GB of links against a
+    256 MB Infinity Cache, so the half-sweep streams from HBM: the clean bandwidth point."""
+    dims = FULL_DIMS
+    V = u.shape[0]
+    with gf.Lattice(dims, gf.GF_FP64, stream=stream) as lat:
+        lat.set_links(u)
+        (tps, block, nt), table = lat.autotune(gf.GF_FP64, n_sweeps=3)
+        log(f"fullsize fp64 autotune: tps={tps} block={block} cache policy={nt}")
+        with torch.cuda.stream(stream):
+            lat.sweep(args.warmup, args.omega, args.mode)
+            total, wall, per_launch = time_run(lat, torch, stream, args.full_steps, args.omega, args.mode,
+                                               args.chunk)
+        th, F = lat.measure()
+    rate = V * args.full_steps / total
+    launch_bytes = (V // 2) * BYTES_PER_SITE["f64"]
+    achieved = launch_bytes / per_launch / 1e9
+    log(f"fullsize fp64: {args.full_steps} sweeps in {total * 1e3:.1f} ms (mean half-sweep {per_launch * 1e6:.1f} us, "
+        f"{achieved:.0f} GB/s)")
+    return {
+        "workload": "SU(3) Landau OR sweep, 48x48x48x96 periodic, eps=1.0, seed 0, omega=%g, %s power, FP64 "
+                    "12-real links" % (args.omega, "exact" if args.mode == 0 else "binomial"),
+        "steps": args.full_steps,
+        "value": rate,
+        "unit": "site-updates/s",
+        "ms_per_step": total * 1e3 / args.full_steps,
+        "gflops": rate * FLOPS_PER_SITE_UPDATE / 1e9,
+        "threads_per_site": tps, "block": block, "nontemporal": nt,
+        "tuning_us_per_sweep": [[t, b, c, round(us, 1)] for (t, b, c, us) in table],
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS,
+            "traffic": committed_traffic(TRAFFIC_FILE_48),
+            "kernel": "k_or_half_sweep<double, TPS=%d, exact, BLOCK=%d, cache policy %d>" % (tps, block, nt),
+            "algorithmic_bytes_per_launch": launch_bytes,
+            "mean_launch_us": per_launch * 1e6,
+        },
+        "checks": {"theta_after": th, "F_after": F},
+    }
+
+
+def fullsize_leg(gf, torch, stream, u, args):
     """The 48^3 x 96 workload (eps = 1.0, seed 0) in mixed precision: 2000 float32 heat-bath sweeps
     on g(x) with T falling linearly from 1.25 to 0.01 (Philox per site), then overrelaxation to
     theta < 1e-13 with float32 bulk, float64 polish and reunitarisation every 100 sweeps."""
-    dims = (48, 48, 48, 96)
-    V = gi.volume(dims)
-    t0 = time.perf_counter()
-    u = gi.gen_links(dims, 1.0, 0)
-    log(f"fullsize: generated {dims} in {time.perf_counter() - t0:.1f} s")
+    dims = FULL_DIMS
+    V = u.shape[0]
     out = {"workload": "48x48x48x96, eps=1.0, seed 0; anneal 2000 (T 1.25 -> 0.01), then OR to theta < 1e-13",
            "max_sweeps": args.full_max_sweeps}
     with gf.Lattice(dims, gf.GF_FP64, stream=stream) as lat:
@@ -237,7 +370,6 @@ def fullsize_leg(gf, gi, torch, stream, args):
         P0 = lat.plaquette()
     with gf.Lattice(dims, gf.GF_MIXED, stream=stream) as lat:
         lat.set_links(u)
-        del u
         cfg = {}
         for kernel, name in ((gf.GF_FP32, "f32"), (gf.GF_FP64, "f64")):
             chosen, _ = lat.autotune(kernel, n_sweeps=3)
@@ -268,6 +400,26 @@ def fullsize_leg(gf, gi, torch, stream, args):
     return out
 
 
+def fix_8x4_leg(gf, torch, u, args):
+    """The 8^4 convergence workload (eps = 0.6, seed 0, omega 1.7, checked every sweep,
+    reunitarised every 100) in float64 and in mixed precision on the GPU; the oracle's run of the
+    same input is timed and compared in the cpu_baseline leg."""
+    dims = (8, 8, 8, 8)
+    out = {}
+    for name, prec in (("fp64", gf.GF_FP64), ("mixed", gf.GF_MIXED)):
+        with gf.Lattice(dims, prec) as lat:
+            lat.set_links(u)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = lat.fix_until(omega=1.7, mode=0, theta_target=1e-12, max_sweeps=3000, check_every=1,
+                              reunit_every=100, theta_switch=args.theta_switch)
+            dt = time.perf_counter() - t0
+            links = lat.get_links()
+        out[name] = {"seconds": dt, "converged": r.converged, "sweeps": r.sweeps, "sweeps_fp32": r.sweeps_fp32,
+                     "sweeps_fp64": r.sweeps_fp64, "theta": r.theta, "F": r.F, "links": links}
+    return out
+
+
 def _time_oracle(oracle, links, dims, omega, mode, budget_s):
     """(sweeps, seconds) of oracle sweeps filling about budget_s, after one untimed sweep."""
     work = links.copy()
@@ -280,7 +432,9 @@ def _time_oracle(oracle, links, dims, omega, mode, budget_s):
     return n, time.perf_counter() - t1
 
 
-def cpu_baseline(links, dims, omega, mode, budget_s, budget_1core_s):
+def cpu_baseline(links, dims, omega, mode, budget_s, budget_1core_s, fix8=None, u8=None):
+    import numpy as np
+
     import oracle
 
     V = links.shape[0]
@@ -290,10 +444,12 @@ def cpu_baseline(links, dims, omega, mode, budget_s, budget_1core_s):
         "value": V * n / dt,
         "unit": "site-updates/s",
         "cores": cores,
+        "cpu_model": host_cpu_model(),
         "kind": "oracle",
         "sample": f"{n} FP64 oracle sweeps of the same {'x'.join(map(str, dims))} lattice (omega={omega}, "
                   f"{'exact' if mode == 0 else 'binomial'} power), after 1 untimed sweep; {dt:.1f} s",
     }
+    out["hbm_equivalent_GBps"] = out["value"] * BYTES_PER_SITE["f64"] / 1e9
     if budget_1core_s > 0:
         # the same oracle on one core (its results do not depend on the thread count)
         oracle.set_num_threads(1)
@@ -303,6 +459,26 @@ def cpu_baseline(links, dims, omega, mode, budget_s, budget_1core_s):
             oracle.set_num_threads(cores)
         out["one_core"] = {"value": V * n1 / dt1, "unit": "site-updates/s", "cores": 1,
                            "sample": f"{n1} sweeps after 1 untimed sweep; {dt1:.1f} s"}
+    if fix8 is not None:
+        # the 8^4 convergence workload through the oracle: its time to theta < 1e-12, and the GPU
+        # float64 and mixed-precision results' errors against it
+        d8 = (8, 8, 8, 8)
+        ref = u8.copy()
+        t0 = time.perf_counter()
+        r = oracle.fix_until(ref, d8, 1.7, 0, 1e-12, 3000, 1, 100)
+        t_or = time.perf_counter() - t0
+        cmp = {"workload": "8^4, eps=0.6, seed 0, omega 1.7, exact power, checked every sweep, reunitarised "
+                           "every 100, to theta < 1e-12 (3000 sweeps at most)",
+               "oracle": {"seconds": t_or, "converged": r["converged"], "sweeps": r["sweeps"], "theta": r["theta"],
+                          "F": r["F"], "threads": 1}}  # 4096 sites: below the oracle's OpenMP threshold
+        for name, g in fix8.items():
+            cmp["gpu_" + name] = {
+                "seconds": g["seconds"], "converged": g["converged"], "sweeps": g["sweeps"],
+                "sweeps_fp32": g["sweeps_fp32"], "sweeps_fp64": g["sweeps_fp64"], "theta": g["theta"], "F": g["F"],
+                "theta_minus_oracle": g["theta"] - r["theta"], "F_minus_oracle": g["F"] - r["F"],
+                "max_abs_links_minus_oracle": float(np.abs(g["links"] - ref).max()),
+            }
+        out["fix_8x4"] = cmp
     return out
 
 
@@ -331,20 +507,29 @@ def main(argv=None):
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--chunk", type=int, default=10,
                     help="sweeps per gf_sweep_or call in the timed region (>= 2: replayed hipGraph; 1: direct launches)")
-    ap.add_argument("--no-fix", action="store_true", help="skip the run to theta < 1e-12")
-    ap.add_argument("--batched", action="store_true", help="also run the 64-lattice batched workload")
+    ap.add_argument("--no-fix", action="store_true", help="skip the runs to theta < 1e-12 (32^4 and 8^4)")
+    ap.add_argument("--batched", action="store_true", help="(the batched leg runs by default; kept for scripts)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-lattice batched workload")
+    ap.add_argument("--batched-fp64-pool", action="store_true", help="also run the batched jobs in a float64 pool")
     ap.add_argument("--serve", action="store_true", help="(the serving leg runs by default; kept for scripts)")
     ap.add_argument("--no-serve", action="store_true", help="skip the Poisson-arrival serving workload")
     ap.add_argument("--serve-jobs", type=int, default=100)
     ap.add_argument("--serve-closed", action="store_true",
                     help="also run the serving jobs closed loop (all queued at t = 0: peak lattices/s)")
-    ap.add_argument("--serve-budget-gb", type=float, default=0.0,
-                    help="HBM budget of the serving pool (0: 80 %% of free device memory)")
+    ap.add_argument("--serve-budget-gb", type=float, default=4.0,
+                    help="HBM budget of the serving pool in GB (0: 80 %% of free device memory)")
     ap.add_argument("--pool-tps32", type=int, default=2,
                     help="lanes per site of the pool's float32 sweeps (2: fastest over the batched set on MI355X)")
+    ap.add_argument("--no-pool-autotune", action="store_true",
+                    help="batched leg: keep the pool's default sweep shape instead of gf_pool_autotune")
     ap.add_argument("--pool-tps64", type=int, default=1,
                     help="lanes per site of the pool's float64 sweeps (1: fastest over the batched set on MI355X)")
-    ap.add_argument("--fullsize", action="store_true", help="also run the 48^3x96 anneal + mixed-precision workload")
+    ap.add_argument("--fullsize", action="store_true", help="(the 48^3x96 legs run by default; kept for scripts)")
+    ap.add_argument("--no-fullsize", action="store_true",
+                    help="skip the 48^3x96 float64 sweep and the 48^3x96 anneal + mixed-precision workload")
+    ap.add_argument("--no-fullsize-pipeline", action="store_true",
+                    help="run the 48^3x96 float64 sweep but not the anneal + mixed-precision workload")
+    ap.add_argument("--full-steps", type=int, default=40, help="timed float64 sweeps of the 48^3x96 lattice")
     ap.add_argument("--full-max-sweeps", type=int, default=10000)
     ap.add_argument("--job-max-sweeps", type=int, default=10000)
     ap.add_argument("--fix-max-sweeps", type=int, default=20000)
@@ -353,6 +538,7 @@ def main(argv=None):
     ap.add_argument("--theta-switch", type=float, default=-1.0,
                     help="float32 -> float64 switch of the mixed runs; < 0: chosen by gf_tune_switch")
     ap.add_argument("--no-tune", action="store_true", help="use --tps/--block instead of the autotuner")
+    ap.add_argument("--gen-threads", type=int, default=8, help="host threads generating the inputs up front")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -371,8 +557,28 @@ def main(argv=None):
     torch.cuda.set_device(0)
     dims = tuple(int(x) for x in args.dims.split(","))
     V = gi.volume(dims)
-    log(f"generating {dims} eps={args.eps} seed={args.seed}")
-    links = gi.gen_links(dims, args.eps, args.seed)
+
+    # every input of every leg, generated on host threads from the start; the 32^4 sweep is
+    # timed with HIP events meanwhile, and every other leg waits until generation is done
+    inputs = Inputs(gi, args.gen_threads)
+    t_gen0 = time.perf_counter()
+    inputs.want(dims, args.eps, args.seed)
+    if not args.no_fix:
+        inputs.want((8, 8, 8, 8), 0.6, 0)
+        if args.fix_eps_smooth > 0:
+            inputs.want(dims, args.fix_eps_smooth, args.seed)
+    if not args.no_fullsize:
+        inputs.want(FULL_DIMS, 1.0, 0)
+    if not args.no_batched:
+        from paper_1412_3655_amd import serving
+
+        for j in serving.batched_jobs(64, 4):
+            inputs.want(j.dims, j.eps, j.seed)
+    if not args.no_serve:
+        for (d, e), seed in serving_jobs(args)[1].items():
+            inputs.want(d, e, seed)
+    log(f"generating {len(inputs.fut)} inputs on {args.gen_threads} threads")
+    links = inputs.get(dims, args.eps, args.seed)
     stream = torch.cuda.Stream()
 
     if args.copy_probe:
@@ -418,6 +624,10 @@ def main(argv=None):
             log(f"fp32: {args.steps} sweeps in {total * 1e3:.2f} ms (mean half-sweep {per_launch * 1e6:.1f} us)")
             result["f32"] = dict(total=total, wall=wall, per_launch=per_launch)
 
+    waited = inputs.wait_all()
+    t_gen = time.perf_counter() - t_gen0
+    log(f"inputs ready after {t_gen:.1f} s (waited {waited:.1f} s after the 32^4 sweep legs)")
+
     r64 = result["f64"]
     rate = V * args.steps / r64["total"]
     launch_bytes = (V // 2) * BYTES_PER_SITE["f64"]
@@ -460,6 +670,17 @@ def main(argv=None):
                                                                                             args.nt),
             "algorithmic_bytes_per_launch": launch_bytes,
             "mean_launch_us": r64["per_launch"] * 1e6,
+            "note": "the 403 MB float64 field partly fits the 256 MB Infinity Cache, which the reversed white "
+                    "half-sweep reuses; fullsize_48x96_f64 is the HBM-only point",
+        },
+        "gflops": {
+            "value": rate * FLOPS_PER_SITE_UPDATE / 1e9,
+            "flops_per_site_update": FLOPS_PER_SITE_UPDATE,
+            "value_paper_convention": rate * PAPER_FLOPS_PER_SITE_UPDATE / 1e9,
+            "paper_flops_per_site_update": PAPER_FLOPS_PER_SITE_UPDATE,
+            "paper_gflops_gtx580": PAPER_GFLOPS,
+            "note": "the paper's figure: up to 470 GFlops at ~80 % of a GeForce GTX 580's bandwidth (context, "
+                    "another machine and precision)",
         },
         "checks": {"theta_after": r64["theta"], "F_after": r64["F"], "plaquette_drift": r64["dplaq"]},
         "other_or_mode": {
@@ -467,6 +688,7 @@ def main(argv=None):
             "value": V * args.steps / r64["total_other"],
             "unit": "site-updates/s",
         },
+        "input_generation_s": t_gen,
     }
     if "f32" in result:
         r32 = result["f32"]
@@ -482,27 +704,37 @@ def main(argv=None):
             "note": "201 MB of FP32 links fit in the 256 MB Infinity Cache, so this can exceed HBM peak",
         }
     line["tuning_us_per_sweep"] = tuning or None
+    if not args.no_fullsize:
+        full = inputs.get(FULL_DIMS, 1.0, 0)
+        line["fullsize_48x96_f64"] = fullsize_f64_leg(gf, torch, stream, full, args)
+    fix8 = None
     if not args.no_fix:
         line["fix_until_theta_1e-12"] = fix_until_leg(gf, torch, stream, links, dims, args, args.eps)
         if args.fix_eps_smooth > 0:
-            log(f"generating {dims} eps={args.fix_eps_smooth} seed={args.seed}")
-            smooth = gi.gen_links(dims, args.fix_eps_smooth, args.seed)
+            smooth = inputs.get(dims, args.fix_eps_smooth, args.seed)
             line["fix_until_theta_1e-12_smooth"] = fix_until_leg(gf, torch, stream, smooth, dims, args,
-                                                                 args.fix_eps_smooth)
+                                                                 args.fix_eps_smooth, adaptive_too=True)
+            inputs.drop(dims, args.fix_eps_smooth, args.seed)
             del smooth
+        fix8 = fix_8x4_leg(gf, torch, inputs.get((8, 8, 8, 8), 0.6, 0), args)
+        line["fix_8x4"] = {k: {kk: vv for kk, vv in v.items() if kk != "links"} for k, v in fix8.items()}
     line["device_copy_GBps"] = copy_bandwidth(gf)
-    if args.batched:
-        line["batched_64"] = batched_leg(gf, gi, stream, args)
+    if not args.no_batched:
+        line["batched_64"] = batched_leg(gf, inputs, stream, args)
     if not args.no_serve:
-        line["serving"] = serving_leg(gf, gi, stream, args)
-    if args.fullsize:
-        line["fullsize_48x96"] = fullsize_leg(gf, gi, torch, stream, args)
+        line["serving"] = serving_leg(gf, inputs, stream, args)
+    if not args.no_fullsize and not args.no_fullsize_pipeline:
+        line["fullsize_48x96"] = fullsize_leg(gf, torch, stream, inputs.get(FULL_DIMS, 1.0, 0), args)
+    if not args.no_fullsize:
+        inputs.drop(FULL_DIMS, 1.0, 0)
     if not args.no_cpu:
         log("cpu baseline (FP64 oracle)")
         line["cpu_baseline"] = cpu_baseline(links, dims, args.omega, args.mode, args.cpu_budget,
-                                            args.cpu_1core_budget)
+                                            args.cpu_1core_budget, fix8,
+                                            inputs.get((8, 8, 8, 8), 0.6, 0) if fix8 else None)
     else:
         line["cpu_baseline"] = None
+    inputs.close()
     print(json.dumps(line), flush=True)
     return 0
 

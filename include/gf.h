@@ -99,6 +99,32 @@ typedef struct {
  * and a float32 gauge-transformation field.  Links start undefined. */
 gf_status gf_create_lattice(const int32_t dims[4], gf_prec prec, void* hip_stream, gf_lattice* out);
 
+/* The same method for gauge group SU(2) (the abstract lists SU(2) beside
+ * SU(3); Sec. 2's maximiser K^dag / sqrt(det K^dag) is exact for SU(2), so a
+ * site update has no subgroup iteration; Sec. 4.1 changes the group by the
+ * link parameterisation).  prec GF_FP64 or GF_FP32 (GF_MIXED: GF_E_ARG).
+ * Links are stored as quaternions (q0, q1, q2, q3) of
+ * U = [[q0 + i q3, q2 + i q1], [-q2 + i q1, q0 - i q3]] in the same
+ * checkerboard, site-fastest tiled layout (32 B per float64 link; a site
+ * update moves 512 B).  Every entry point taking a lattice accepts an SU(2)
+ * lattice, with these differences:
+ *   - canonical arrays hold 2x2 links: [site][mu][row][col][re,im], 8 doubles
+ *     per link, 32 per site (gf_set_links keeps the element's projection onto
+ *     the real span of SU(2), i.e. the link itself for an SU(2) matrix);
+ *   - theta = (1/(2V)) sum_x tr[Delta Delta^dag], F = (1/(8V)) sum_x sum_mu
+ *     Re tr U, plaquette normalised by 12V (N_c = 2); Coulomb gauge:
+ *     theta_C(t) and F_C(t) with 1/(2 V3) and 1/(6 V3);
+ *   - the heat bath draws g from exp(Re tr[g K]/T) dHaar with the SU(3)
+ *     subgroup sampler, Philox subgroup index 0;
+ *   - sweep configurations: one lane per site (tps 1), block 64..512, cache
+ *     policy 0..2; gf_autotune times those;
+ *   - reunitarisation divides each quaternion by its norm;
+ *   - gf_tune_switch and the pool are SU(3) only (GF_E_STATE / not offered). */
+gf_status gf_create_lattice_su2(const int32_t dims[4], gf_prec prec, void* hip_stream, gf_lattice* out);
+
+/* N_c of the lattice's gauge group: 3 (gf_create_lattice) or 2 (gf_create_lattice_su2). */
+gf_status gf_lattice_group(gf_lattice lat, int32_t* nc);
+
 /* Free every device buffer of the lattice (waits for its stream).  NULL is accepted. */
 gf_status gf_destroy_lattice(gf_lattice lat);
 

@@ -88,16 +88,18 @@ gf_status check_dims(const int32_t dims[4], int64_t* V)
 // Device allocations of a lattice of geometry g and precision prec (sizes of
 // the buffers gf_create_lattice allocates; the pool's admission budget counts
 // exactly these).
-LatticeSizes lattice_sizes(const Geom& g, gf_prec prec)
+LatticeSizes lattice_sizes(const Geom& g, gf_prec prec, int group)
 {
     LatticeSizes z;
     const size_t nchunks = (size_t)2 * 4 * g.ld;  // per chunk slot
-    if (prec == GF_FP64 || prec == GF_MIXED) z.f64 = nchunks * 6 * sizeof(double2);
-    if (prec == GF_FP32 || prec == GF_MIXED) z.f32 = nchunks * 3 * sizeof(float4);
+    const bool su2 = group == 2;
+    if (prec == GF_FP64 || prec == GF_MIXED) z.f64 = nchunks * (su2 ? 2 : 6) * sizeof(double2);
+    if (prec == GF_FP32 || prec == GF_MIXED) z.f32 = nchunks * (su2 ? 1 : 3) * sizeof(float4);
     if (prec == GF_MIXED) z.gacc = (size_t)2 * 3 * g.ld * sizeof(float4);
     // partial sums of the whole-lattice reductions, or of the per-timeslice
     // Coulomb ones, whichever needs more
-    z.partial = 2 * std::max((size_t)gf::measure_blocks(g), (size_t)gf::slice_partials(g));
+    z.partial = su2 ? 2 * (size_t)gf::su2_partials(g)
+                    : 2 * std::max((size_t)gf::measure_blocks(g), (size_t)gf::slice_partials(g));
     z.nslices = 2 * (size_t)g.n[3];
     z.total = (int64_t)(z.f64 + z.f32 + z.gacc + (z.partial + 4 + z.nslices) * sizeof(double));
     return z;
@@ -111,6 +113,16 @@ LinkField<double> field64(const gf_lattice_* L)
 LinkField<float> field32(const gf_lattice_* L)
 {
     return LinkField<float>{L->f32, L->geom.ld};
+}
+
+Su2Field<double> su2_64(const gf_lattice_* L)
+{
+    return Su2Field<double>{L->f64, L->geom.ld};
+}
+
+Su2Field<float> su2_32(const gf_lattice_* L)
+{
+    return Su2Field<float>{L->f32, L->geom.ld};
 }
 
 // Whether the working links are the float32 field (GF_FP32, or GF_MIXED before promotion).
@@ -140,6 +152,14 @@ gf_status check_omega(double omega, int mode)
 
 gf_status do_half_sweep(gf_lattice L, int parity, double omega, int mode)
 {
+    if (L->group == 2) {
+        if (is_fp32(L))
+            GF_HIP(gf::launch_su2_or(su2_32(L), L->geom, parity, (float)omega, mode, L->cfg32, L->stream, L->gauge,
+                                     nullptr));
+        else
+            GF_HIP(gf::launch_su2_or(su2_64(L), L->geom, parity, omega, mode, L->cfg64, L->stream, L->gauge, nullptr));
+        return GF_OK;
+    }
     if (is_fp32(L))
         GF_HIP(gf::launch_or_half_sweep(field32(L), L->geom, parity, (float)omega, mode, L->cfg32, g_tracking(L),
                                         L->stream, L->gauge));
@@ -172,7 +192,7 @@ gf_status do_sweeps(gf_lattice L, int32_t n, double omega, int mode)
     if (n < 2 || L->stream == nullptr || L->geom.vh >= kGraphMaxHalfSites) return launch_sweeps(L, n, omega, mode);
     const bool fp32 = is_fp32(L);
     const SweepConfig& c = fp32 ? L->cfg32 : L->cfg64;
-    const int kind = (fp32 ? (g_tracking(L).base ? 2 : 1) : 0) + 4 * L->gauge;
+    const int kind = (fp32 ? (g_tracking(L).base ? 2 : 1) : 0) + 4 * L->gauge + 8 * (L->group == 2);
     const auto key = std::make_tuple(n, omega, mode, kind, c.tps, c.block, c.nt);
     auto it = L->sweep_graphs.find(key);
     if (it == L->sweep_graphs.end()) {
@@ -198,6 +218,13 @@ gf_status do_sweeps(gf_lattice L, int32_t n, double omega, int mode)
 
 gf_status do_reunitarize(gf_lattice L)
 {
+    if (L->group == 2) {
+        if (is_fp32(L))
+            GF_HIP(gf::launch_su2_reunitarize(su2_32(L), L->geom, L->stream));
+        else
+            GF_HIP(gf::launch_su2_reunitarize(su2_64(L), L->geom, L->stream));
+        return GF_OK;
+    }
     if (is_fp32(L))
         GF_HIP(gf::launch_reunitarize(field32(L), L->geom, L->stream));
     else
@@ -222,7 +249,11 @@ gf_status do_promote(gf_lattice L)
 // timeslice), *F = the mean of F_C(t), added in timeslice order.
 gf_status do_measure_slices(gf_lattice L, double* theta, double* F)
 {
-    if (is_fp32(L))
+    if (L->group == 2 && is_fp32(L))
+        GF_HIP(gf::launch_su2_measure(su2_32(L), L->geom, gf::GAUGE_COULOMB, L->partial, L->dslices, L->stream));
+    else if (L->group == 2)
+        GF_HIP(gf::launch_su2_measure(su2_64(L), L->geom, gf::GAUGE_COULOMB, L->partial, L->dslices, L->stream));
+    else if (is_fp32(L))
         GF_HIP(gf::launch_measure_slices(field32(L), L->geom, L->partial, L->dslices, L->stream));
     else
         GF_HIP(gf::launch_measure_slices(field64(L), L->geom, L->partial, L->dslices, L->stream));
@@ -247,7 +278,11 @@ gf_status do_measure(gf_lattice L, double* theta, double* F)
 {
     ++L->n_measures;
     if (L->gauge == gf::GAUGE_COULOMB) return do_measure_slices(L, theta, F);
-    if (is_fp32(L))
+    if (L->group == 2 && is_fp32(L))
+        GF_HIP(gf::launch_su2_measure(su2_32(L), L->geom, gf::GAUGE_LANDAU, L->partial, L->dres, L->stream));
+    else if (L->group == 2)
+        GF_HIP(gf::launch_su2_measure(su2_64(L), L->geom, gf::GAUGE_LANDAU, L->partial, L->dres, L->stream));
+    else if (is_fp32(L))
         GF_HIP(gf::launch_measure(field32(L), L->geom, L->partial, L->dres, L->stream));
     else
         GF_HIP(gf::launch_measure(field64(L), L->geom, L->partial, L->dres, L->stream));
@@ -269,7 +304,8 @@ gf_status do_measure(gf_lattice L, double* theta, double* F)
 gf_status do_est_sweep(gf_lattice L, double omega, int mode, double* theta_est)
 {
     const SweepConfig& c = is_fp32(L) ? L->cfg32 : L->cfg64;
-    const uint32_t nb = gf::sweep_blocks(L->geom, c);
+    const bool su2 = L->group == 2;
+    const uint32_t nb = su2 ? gf::su2_sweep_blocks(L->geom, c) : gf::sweep_blocks(L->geom, c);
     const size_t need = 4 * (size_t)nb;
     if (need > L->est_cap) {
         if (L->est) GF_HIP(hipFree(L->est));
@@ -281,7 +317,12 @@ gf_status do_est_sweep(gf_lattice L, double omega, int mode, double* theta_est)
         L->bytes += (int64_t)(need * sizeof(double));
     }
     for (int parity = 0; parity < 2; ++parity) {
-        if (is_fp32(L))
+        if (su2 && is_fp32(L))
+            GF_HIP(gf::launch_su2_or(su2_32(L), L->geom, parity, (float)omega, mode, L->cfg32, L->stream, L->gauge,
+                                     L->est));
+        else if (su2)
+            GF_HIP(gf::launch_su2_or(su2_64(L), L->geom, parity, omega, mode, L->cfg64, L->stream, L->gauge, L->est));
+        else if (is_fp32(L))
             GF_HIP(gf::launch_or_half_sweep(field32(L), L->geom, parity, (float)omega, mode, L->cfg32, g_tracking(L),
                                             L->stream, L->gauge, L->est));
         else
@@ -289,7 +330,8 @@ gf_status do_est_sweep(gf_lattice L, double omega, int mode, double* theta_est)
                                             L->est));
     }
     const double V = 2.0 * (double)L->geom.vh;
-    GF_HIP(gf::launch_finalize(L->est, 2 * nb, 1.0 / (3.0 * V), 0.0, L->dres + 2, L->stream));
+    const double nc = su2 ? 2.0 : 3.0;
+    GF_HIP(gf::launch_finalize(L->est, 2 * nb, 1.0 / (nc * V), 0.0, L->dres + 2, L->stream));
     GF_HIP(hipMemcpyAsync(L->hres + 2, L->dres + 2, sizeof(double), hipMemcpyDeviceToHost, L->stream));
     GF_HIP(hipStreamSynchronize(L->stream));
     ++L->n_estimates;
@@ -299,6 +341,7 @@ gf_status do_est_sweep(gf_lattice L, double omega, int mode, double* theta_est)
 
 gf_status do_fp32_floor(gf_lattice L, double* floor)
 {
+    if (L->group == 2) return fail(GF_E_STATE, "the float32 floor is defined for SU(3) lattices");
     if (!L->f64) return fail(GF_E_STATE, "the float32 floor needs float64 links (GF_FP64 or GF_MIXED lattice)");
     GF_HIP(gf::launch_fp32_floor(field64(L), L->geom, L->partial, L->dres, L->stream));
     GF_HIP(hipMemcpyAsync(L->hres, L->dres, sizeof(double), hipMemcpyDeviceToHost, L->stream));
@@ -322,6 +365,14 @@ gf_status resolve_switch(gf_lattice L, double theta_target, double theta_switch,
 
 gf_status upload_canonical(gf_lattice L, const double* dev_canon)
 {
+    if (L->group == 2) {
+        if (L->f32) GF_HIP(gf::launch_su2_pack(dev_canon, su2_32(L), L->geom, L->stream));
+        if (L->f64) GF_HIP(gf::launch_su2_pack(dev_canon, su2_64(L), L->geom, L->stream));
+        L->phase = 0;
+        L->has_links = true;
+        L->anneal_sweeps = 0;
+        return GF_OK;
+    }
     if (L->f32) GF_HIP(gf::launch_pack(dev_canon, field32(L), L->geom, L->stream));
     if (L->f64) GF_HIP(gf::launch_pack(dev_canon, field64(L), L->geom, L->stream));
     if (L->gacc.base) GF_HIP(gf::launch_g_identity(L->gacc, L->geom, L->stream));
@@ -333,6 +384,13 @@ gf_status upload_canonical(gf_lattice L, const double* dev_canon)
 
 gf_status download_canonical(gf_lattice L, double* dev_canon)
 {
+    if (L->group == 2) {
+        if (is_fp32(L))
+            GF_HIP(gf::launch_su2_unpack(su2_32(L), L->geom, dev_canon, L->stream));
+        else
+            GF_HIP(gf::launch_su2_unpack(su2_64(L), L->geom, dev_canon, L->stream));
+        return GF_OK;
+    }
     if (is_fp32(L))
         GF_HIP(gf::launch_unpack(field32(L), L->geom, dev_canon, L->stream));
     else
@@ -381,7 +439,9 @@ const char* gf_version(void)
     return "libgf 0.1 (gfx950)";
 }
 
-gf_status gf_create_lattice(const int32_t dims[4], gf_prec prec, void* hip_stream, gf_lattice* out)
+namespace {
+
+gf_status create_lattice(const int32_t dims[4], gf_prec prec, int group, void* hip_stream, gf_lattice* out)
 {
     if (!dims || !out) return fail(GF_E_ARG, "null argument");
     *out = nullptr;
@@ -389,11 +449,14 @@ gf_status gf_create_lattice(const int32_t dims[4], gf_prec prec, void* hip_strea
     GF_TRY(check_dims(dims, &V));
     if (prec != GF_FP64 && prec != GF_FP32 && prec != GF_MIXED)
         return fail(GF_E_ARG, "unsupported precision %d", (int)prec);
+    if (group == 2 && prec == GF_MIXED)
+        return fail(GF_E_ARG, "SU(2) lattices are GF_FP64 or GF_FP32 (no mixed precision)");
 
     gf_lattice_* L = new (std::nothrow) gf_lattice_();
     if (!L) return fail(GF_E_NOMEM, "host allocation failed");
     for (int m = 0; m < 4; ++m) L->dims[m] = dims[m];
     L->prec = prec;
+    L->group = group;
     L->stream = (hipStream_t)hip_stream;
     L->volume = V;
 
@@ -403,7 +466,7 @@ gf_status gf_create_lattice(const int32_t dims[4], gf_prec prec, void* hip_strea
         return fail(GF_E_ARG, "internal: index division check failed");
     }
 
-    const LatticeSizes z = lattice_sizes(g, prec);
+    const LatticeSizes z = lattice_sizes(g, prec, group);
     hipError_t e = hipSuccess;
     if (z.f64) e = hipMalloc((void**)&L->f64, z.f64);
     if (e == hipSuccess && z.f32) e = hipMalloc((void**)&L->f32, z.f32);
@@ -430,7 +493,32 @@ gf_status gf_create_lattice(const int32_t dims[4], gf_prec prec, void* hip_strea
     // vs 282 us at 4; float64 414 us vs 544 us at 2).
     L->cfg_hb64 = SweepConfig{1, 128, 2};
     L->cfg_hb32 = SweepConfig{1, 256, 0};
+    if (group == 2) {
+        // one lane per site: the SU(2) site update is a few quaternion products
+        L->cfg64 = SweepConfig{1, 256, 0};
+        L->cfg32 = SweepConfig{1, 256, 0};
+        L->cfg_hb64 = SweepConfig{1, 256, 0};
+    }
     *out = L;
+    return GF_OK;
+}
+
+}  // namespace
+
+gf_status gf_create_lattice(const int32_t dims[4], gf_prec prec, void* hip_stream, gf_lattice* out)
+{
+    return create_lattice(dims, prec, 3, hip_stream, out);
+}
+
+gf_status gf_create_lattice_su2(const int32_t dims[4], gf_prec prec, void* hip_stream, gf_lattice* out)
+{
+    return create_lattice(dims, prec, 2, hip_stream, out);
+}
+
+gf_status gf_lattice_group(gf_lattice L, int32_t* nc)
+{
+    if (!L || !nc) return fail(GF_E_ARG, "null argument");
+    *nc = L->group;
     return GF_OK;
 }
 
@@ -459,7 +547,13 @@ gf_status set_config(gf_lattice L, gf_prec kernel, int32_t tps, int32_t block, i
     if (!L) return fail(GF_E_ARG, "null lattice");
     if (kernel != GF_FP64 && kernel != GF_FP32) return fail(GF_E_ARG, "kernel precision must be GF_FP64 or GF_FP32");
     SweepConfig c{tps, block, nontemporal};
-    if (!gf::sweep_config_valid(c))
+    if (L->group == 2) {
+        if (!gf::su2_config_valid(c))
+            return fail(GF_E_ARG,
+                        "SU(2) sweep config tps=%d block=%d policy=%d: one lane per site, block 64, 128, 256 or 512, "
+                        "cache policy 0, 1 or 2",
+                        tps, block, nontemporal);
+    } else if (!gf::sweep_config_valid(c))
         return fail(GF_E_ARG,
                     "sweep config tps=%d block=%d policy=%d: tps must be 1, 2, 4 or 8, block 64, 128, 256 or 512 "
                     "(not 512 with tps 1), cache policy 0, 1 or 2 (1 and 2 only with tps <= 4 and block <= 256)",
@@ -498,7 +592,7 @@ gf_status gf_set_links_device(gf_lattice L, const double* dev)
 gf_status gf_set_links(gf_lattice L, const double* host)
 {
     if (!L || !host) return fail(GF_E_ARG, "null argument");
-    const size_t bytes = (size_t)L->volume * 4 * 18 * sizeof(double);
+    const size_t bytes = (size_t)L->volume * 4 * canon_per_link(L) * sizeof(double);
     double* stage = nullptr;
     GF_HIP(hipMalloc((void**)&stage, bytes));
     hipError_t e = hipMemcpyAsync(stage, host, bytes, hipMemcpyHostToDevice, L->stream);
@@ -521,7 +615,7 @@ gf_status gf_get_links(gf_lattice L, double* host)
 {
     GF_TRY(check_ready(L));
     if (!host) return fail(GF_E_ARG, "null argument");
-    const size_t bytes = (size_t)L->volume * 4 * 18 * sizeof(double);
+    const size_t bytes = (size_t)L->volume * 4 * canon_per_link(L) * sizeof(double);
     double* stage = nullptr;
     GF_HIP(hipMalloc((void**)&stage, bytes));
     gf_status st = download_canonical(L, stage);
@@ -576,7 +670,13 @@ gf_status gf_anneal(gf_lattice L, int32_t n_sweeps, double T_start, double T_end
         const double T = anneal_temperature(s, n_sweeps, T_start, T_end);
         const uint32_t sweep = L->anneal_sweeps + (uint32_t)s;
         for (int parity = 0; parity < 2; ++parity) {
-            if (is_fp32(L))
+            if (L->group == 2 && is_fp32(L))
+                GF_HIP(gf::launch_su2_hb(su2_32(L), L->geom, parity, (float)T, seed, sweep, L->cfg_hb32, L->stream,
+                                         L->gauge));
+            else if (L->group == 2)
+                GF_HIP(gf::launch_su2_hb(su2_64(L), L->geom, parity, T, seed, sweep, L->cfg_hb64, L->stream,
+                                         L->gauge));
+            else if (is_fp32(L))
                 GF_HIP(gf::launch_hb_half_sweep(field32(L), L->geom, parity, (float)T, seed, sweep, L->cfg_hb32,
                                                 g_tracking(L), L->stream, L->gauge));
             else
@@ -664,7 +764,11 @@ gf_status gf_plaquette(gf_lattice L, double* P)
 {
     GF_TRY(check_ready(L));
     if (!P) return fail(GF_E_ARG, "null argument");
-    if (is_fp32(L))
+    if (L->group == 2 && is_fp32(L))
+        GF_HIP(gf::launch_su2_plaquette(su2_32(L), L->geom, L->partial, L->dres, L->stream));
+    else if (L->group == 2)
+        GF_HIP(gf::launch_su2_plaquette(su2_64(L), L->geom, L->partial, L->dres, L->stream));
+    else if (is_fp32(L))
         GF_HIP(gf::launch_plaquette(field32(L), L->geom, L->partial, L->dres, L->stream));
     else
         GF_HIP(gf::launch_plaquette(field64(L), L->geom, L->partial, L->dres, L->stream));

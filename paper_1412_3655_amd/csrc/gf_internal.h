@@ -10,6 +10,7 @@
 
 #include "gf.h"
 #include "gf_kernels.h"
+#include "gf_su2.h"
 
 // One lattice: geometry, device link fields and measurement scratch.
 struct gf_lattice_ {
@@ -29,6 +30,7 @@ struct gf_lattice_ {
     double* dslices = nullptr;              // Coulomb gauge: device theta_C(t), F_C(t) pairs (2 Nt)
     double* hslices = nullptr;              // pinned host copy of dslices
     int gauge = gf::GAUGE_LANDAU;           // functional: GAUGE_LANDAU or GAUGE_COULOMB
+    int group = 3;                          // gauge group SU(3) or SU(2); f64 / f32 hold quaternions for SU(2)
     double* est = nullptr;                  // per-block sums of a sweep's theta estimate (allocated on use)
     size_t est_cap = 0;                     // doubles held by est
     bool adaptive = false;                  // gf_fix_until: exact measurement only near a decision
@@ -73,7 +75,14 @@ struct LatticeSizes {
     int64_t total = 0;  // every device byte the lattice holds
 };
 
-LatticeSizes lattice_sizes(const Geom& g, gf_prec prec);
+LatticeSizes lattice_sizes(const Geom& g, gf_prec prec, int group = 3);
+Su2Field<double> su2_64(const gf_lattice_* L);
+Su2Field<float> su2_32(const gf_lattice_* L);
+// Doubles per link of the canonical host / device arrays (18 for SU(3), 8 for SU(2)).
+inline size_t canon_per_link(const gf_lattice_* L)
+{
+    return L->group == 2 ? 8 : 18;
+}
 bool make_fastdiv(uint32_t d, uint32_t limit, FastDiv* out);
 bool make_geom(const int32_t dims[4], Geom* out);
 gf_status check_dims(const int32_t dims[4], int64_t* V);

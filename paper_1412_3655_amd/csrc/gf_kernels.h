@@ -52,6 +52,16 @@ hipError_t launch_or_half_sweep_coulomb(const LinkField<double>& f, const Geom& 
 hipError_t launch_or_half_sweep_coulomb(const LinkField<float>& f, const Geom& g, int parity, float omega,
                                         int mode, const SweepConfig& cfg, const GField& gacc, hipStream_t st,
                                         double* est);
+// The estimating overrelaxation sweeps (gf_sweep_est.hip, gf_sweep_coulomb_est.hip); est != nullptr.
+hipError_t launch_or_half_sweep_est(const LinkField<double>& f, const Geom& g, int parity, double omega, int mode,
+                                    const SweepConfig& cfg, hipStream_t st, double* est);
+hipError_t launch_or_half_sweep_est(const LinkField<float>& f, const Geom& g, int parity, float omega, int mode,
+                                    const SweepConfig& cfg, const GField& gacc, hipStream_t st, double* est);
+hipError_t launch_or_half_sweep_coulomb_est(const LinkField<double>& f, const Geom& g, int parity, double omega,
+                                            int mode, const SweepConfig& cfg, hipStream_t st, double* est);
+hipError_t launch_or_half_sweep_coulomb_est(const LinkField<float>& f, const Geom& g, int parity, float omega,
+                                            int mode, const SweepConfig& cfg, const GField& gacc, hipStream_t st,
+                                            double* est);
 hipError_t launch_hb_half_sweep_coulomb(const LinkField<double>& f, const Geom& g, int parity, double T,
                                         uint64_t seed, uint32_t sweep, const SweepConfig& cfg, hipStream_t st);
 hipError_t launch_hb_half_sweep_coulomb(const LinkField<float>& f, const Geom& g, int parity, float T,

@@ -1,7 +1,8 @@
 // gf_sweep.hip -- the single-lattice half-sweep launchers of libgf on gfx950:
 // Landau gauge here (K over all 4 directions, Eq. localfunctional of
 // arXiv:1412.3655); the Coulomb instantiation of the same kernel is compiled
-// in gf_sweep_coulomb.hip and reached through the gauge argument.
+// in gf_sweep_coulomb.hip and reached through the gauge argument, the
+// estimating sweeps in gf_sweep_est.hip / gf_sweep_coulomb_est.hip.
 #include "gf_sweep_impl.h"
 
 namespace gf {
@@ -19,7 +20,8 @@ hipError_t launch_or_half_sweep(const LinkField<double>& f, const Geom& g, int p
                                 const SweepConfig& cfg, hipStream_t st, int gauge, double* est)
 {
     if (gauge == GAUGE_COULOMB) return launch_or_half_sweep_coulomb(f, g, parity, omega, mode, cfg, st, est);
-    return sweep_impl::or_half_sweep<NDIR_LANDAU>(f, g, parity, omega, mode, cfg, st, est);
+    if (est) return launch_or_half_sweep_est(f, g, parity, omega, mode, cfg, st, est);
+    return sweep_impl::or_half_sweep<NDIR_LANDAU, false>(f, g, parity, omega, mode, cfg, st, nullptr);
 }
 
 hipError_t launch_or_half_sweep(const LinkField<float>& f, const Geom& g, int parity, float omega, int mode,
@@ -27,7 +29,8 @@ hipError_t launch_or_half_sweep(const LinkField<float>& f, const Geom& g, int pa
 {
     if (gauge == GAUGE_COULOMB)
         return launch_or_half_sweep_coulomb(f, g, parity, omega, mode, cfg, gacc, st, est);
-    return sweep_impl::or_half_sweep<NDIR_LANDAU>(f, g, parity, omega, mode, cfg, gacc, st, est);
+    if (est) return launch_or_half_sweep_est(f, g, parity, omega, mode, cfg, gacc, st, est);
+    return sweep_impl::or_half_sweep<NDIR_LANDAU, false>(f, g, parity, omega, mode, cfg, gacc, st, nullptr);
 }
 
 uint32_t sweep_blocks(const Geom& g, const SweepConfig& cfg)

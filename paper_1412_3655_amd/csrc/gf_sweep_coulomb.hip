@@ -13,14 +13,16 @@ namespace gf {
 hipError_t launch_or_half_sweep_coulomb(const LinkField<double>& f, const Geom& g, int parity, double omega,
                                         int mode, const SweepConfig& cfg, hipStream_t st, double* est)
 {
-    return sweep_impl::or_half_sweep<NDIR_COULOMB>(f, g, parity, omega, mode, cfg, st, est);
+    if (est) return launch_or_half_sweep_coulomb_est(f, g, parity, omega, mode, cfg, st, est);
+    return sweep_impl::or_half_sweep<NDIR_COULOMB, false>(f, g, parity, omega, mode, cfg, st, nullptr);
 }
 
 hipError_t launch_or_half_sweep_coulomb(const LinkField<float>& f, const Geom& g, int parity, float omega,
                                         int mode, const SweepConfig& cfg, const GField& gacc, hipStream_t st,
                                         double* est)
 {
-    return sweep_impl::or_half_sweep<NDIR_COULOMB>(f, g, parity, omega, mode, cfg, gacc, st, est);
+    if (est) return launch_or_half_sweep_coulomb_est(f, g, parity, omega, mode, cfg, gacc, st, est);
+    return sweep_impl::or_half_sweep<NDIR_COULOMB, false>(f, g, parity, omega, mode, cfg, gacc, st, nullptr);
 }
 
 hipError_t launch_hb_half_sweep_coulomb(const LinkField<double>& f, const Geom& g, int parity, double T,

@@ -1,8 +1,10 @@
 // gf_sweep_impl.h -- the single-lattice checkerboard half-sweep kernel
 // (overrelaxation and heat bath, Sec. 2 and the abstract of arXiv:1412.3655)
-// and its launch dispatch, instantiated once per gauge: gf_sweep.hip for
-// Landau gauge (K over 4 directions), gf_sweep_coulomb.hip for Coulomb gauge
-// (K over x, y, z).  The per-site body lives in gf_site.h.  The loop over
+// and its launch dispatch, instantiated per gauge and per estimate flag in
+// translation units of their own (compiled in parallel): gf_sweep.hip
+// (Landau gauge, K over 4 directions), gf_sweep_coulomb.hip (Coulomb gauge, K
+// over x, y, z), gf_sweep_est.hip and gf_sweep_coulomb_est.hip (the sweeps
+// that also sum the estimate of theta).  The per-site body lives in gf_site.h.  The loop over
 // sites is over the half index of one colour: every link is read once and
 // written once per half-sweep (per site update in FP64 with 12-real links:
 // 768 B read and 768 B written), whatever the gauge.
@@ -14,10 +16,11 @@
 namespace gf {
 namespace sweep_impl {
 
-// est != nullptr: the block also sums tr[Delta Delta^dag] of its sites' K
-// before their update into est[2 (parity gridDim.x + b)] (b the block's tile,
-// second double 0), which a fixed-order pass turns into an estimate of theta.
-template <typename R, int TPS, int MODE, int BLOCK, bool TRACKG, int CP, int NDIR>
+// EST: the block also sums tr[Delta Delta^dag] of its sites' K before their
+// update into est[2 (parity gridDim.x + b)] (b the block's tile, second double
+// 0), which a fixed-order pass turns into an estimate of theta.  A template
+// parameter, so the plain sweep carries none of it.
+template <typename R, int TPS, int MODE, int BLOCK, bool TRACKG, int CP, int NDIR, bool EST>
 __global__ void __launch_bounds__(BLOCK) k_or_half_sweep(LinkField<R> f, Geom g, int parity, Rule<R> rule,
                                                          GField gacc, double* est)
 {
@@ -31,10 +34,15 @@ __global__ void __launch_bounds__(BLOCK) k_or_half_sweep(LinkField<R> f, Geom g,
     const uint32_t gid = b * (uint32_t)BLOCK + threadIdx.x;
     const uint32_t h = gid / TPS;
     const int r = (int)(gid % TPS);
-    // whole groups of TPS lanes skip together, so every DPP partner is live
-    double th = 0.0;
-    if (h < g.vh) th = site_update<R, TPS, MODE, TRACKG, CP, NDIR>(f, g, parity, h, r, rule, gacc, est != nullptr);
-    if (est) block_sum2<BLOCK>(th, 0.0, est + 2 * ((size_t)parity * gridDim.x + b));
+    // whole groups of TPS lanes leave or skip together, so every DPP partner is live
+    if constexpr (!EST) {
+        if (h >= g.vh) return;
+        site_update<R, TPS, MODE, TRACKG, CP, NDIR>(f, g, parity, h, r, rule, gacc);
+    } else {
+        double th = 0.0;
+        if (h < g.vh) th = site_update<R, TPS, MODE, TRACKG, CP, NDIR>(f, g, parity, h, r, rule, gacc, true);
+        block_sum2<BLOCK>(th, 0.0, est + 2 * ((size_t)parity * gridDim.x + b));
+    }
 }
 
 // Blocks of one half-sweep launch in configuration c (the estimate buffer
@@ -44,7 +52,7 @@ inline uint32_t sweep_grid(const Geom& g, const SweepConfig& c)
     return (uint32_t)(((uint64_t)g.vh * (uint64_t)c.tps + (uint64_t)c.block - 1) / (uint64_t)c.block);
 }
 
-template <int NDIR, typename R, int TPS, int MODE, bool TRACKG>
+template <int NDIR, bool EST, typename R, int TPS, int MODE, bool TRACKG>
 hipError_t launch_tps(const LinkField<R>& f, const Geom& g, int parity, const Rule<R>& rule, const SweepConfig& c,
                       const GField& gacc, hipStream_t st, double* est)
 {
@@ -52,8 +60,8 @@ hipError_t launch_tps(const LinkField<R>& f, const Geom& g, int parity, const Ru
     const uint32_t grid = sweep_grid(g, c);
     if (grid == 0) return hipSuccess;
 #define GF_LAUNCH(B, CPV)                                                                                      \
-    hipLaunchKernelGGL((k_or_half_sweep<R, TPS, MODE, B, TRACKG, CPV, NDIR>), dim3(grid), dim3(B), 0, st, f, g, \
-                       parity, rule, gacc, est)
+    hipLaunchKernelGGL((k_or_half_sweep<R, TPS, MODE, B, TRACKG, CPV, NDIR, EST>), dim3(grid), dim3(B), 0, st, f, \
+                       g, parity, rule, gacc, est)
 #define GF_LAUNCH_SMALL_BLOCKS(CPV)                  \
     switch (block) {                                 \
         case 64: GF_LAUNCH(64, CPV); break;          \
@@ -91,38 +99,39 @@ hipError_t launch_tps(const LinkField<R>& f, const Geom& g, int parity, const Ru
     return hipGetLastError();
 }
 
-template <int NDIR, typename R, int MODE, bool TRACKG>
+template <int NDIR, bool EST, typename R, int MODE, bool TRACKG>
 hipError_t launch_mode(const LinkField<R>& f, const Geom& g, int parity, const Rule<R>& rule, const SweepConfig& c,
                        const GField& gacc, hipStream_t st, double* est)
 {
     switch (c.tps) {
-        case 1: return launch_tps<NDIR, R, 1, MODE, TRACKG>(f, g, parity, rule, c, gacc, st, est);
-        case 2: return launch_tps<NDIR, R, 2, MODE, TRACKG>(f, g, parity, rule, c, gacc, st, est);
-        case 8: return launch_tps<NDIR, R, 8, MODE, TRACKG>(f, g, parity, rule, c, gacc, st, est);
-        default: return launch_tps<NDIR, R, 4, MODE, TRACKG>(f, g, parity, rule, c, gacc, st, est);
+        case 1: return launch_tps<NDIR, EST, R, 1, MODE, TRACKG>(f, g, parity, rule, c, gacc, st, est);
+        case 2: return launch_tps<NDIR, EST, R, 2, MODE, TRACKG>(f, g, parity, rule, c, gacc, st, est);
+        case 8: return launch_tps<NDIR, EST, R, 8, MODE, TRACKG>(f, g, parity, rule, c, gacc, st, est);
+        default: return launch_tps<NDIR, EST, R, 4, MODE, TRACKG>(f, g, parity, rule, c, gacc, st, est);
     }
 }
 
-template <int NDIR>
+// EST = true needs est != nullptr; EST = false ignores est.
+template <int NDIR, bool EST>
 hipError_t or_half_sweep(const LinkField<double>& f, const Geom& g, int parity, double omega, int mode,
                          const SweepConfig& cfg, hipStream_t st, double* est)
 {
     const GField none{nullptr, 0};
     const Rule<double> rule{omega, 1.0, 0u, 0u, 0u};
-    return mode == OR_EXACT ? launch_mode<NDIR, double, 0, false>(f, g, parity, rule, cfg, none, st, est)
-                            : launch_mode<NDIR, double, 1, false>(f, g, parity, rule, cfg, none, st, est);
+    return mode == OR_EXACT ? launch_mode<NDIR, EST, double, 0, false>(f, g, parity, rule, cfg, none, st, est)
+                            : launch_mode<NDIR, EST, double, 1, false>(f, g, parity, rule, cfg, none, st, est);
 }
 
-template <int NDIR>
+template <int NDIR, bool EST>
 hipError_t or_half_sweep(const LinkField<float>& f, const Geom& g, int parity, float omega, int mode,
                          const SweepConfig& cfg, const GField& gacc, hipStream_t st, double* est)
 {
     const Rule<float> rule{omega, 1.0f, 0u, 0u, 0u};
     if (gacc.base)
-        return mode == OR_EXACT ? launch_mode<NDIR, float, 0, true>(f, g, parity, rule, cfg, gacc, st, est)
-                                : launch_mode<NDIR, float, 1, true>(f, g, parity, rule, cfg, gacc, st, est);
-    return mode == OR_EXACT ? launch_mode<NDIR, float, 0, false>(f, g, parity, rule, cfg, gacc, st, est)
-                            : launch_mode<NDIR, float, 1, false>(f, g, parity, rule, cfg, gacc, st, est);
+        return mode == OR_EXACT ? launch_mode<NDIR, EST, float, 0, true>(f, g, parity, rule, cfg, gacc, st, est)
+                                : launch_mode<NDIR, EST, float, 1, true>(f, g, parity, rule, cfg, gacc, st, est);
+    return mode == OR_EXACT ? launch_mode<NDIR, EST, float, 0, false>(f, g, parity, rule, cfg, gacc, st, est)
+                            : launch_mode<NDIR, EST, float, 1, false>(f, g, parity, rule, cfg, gacc, st, est);
 }
 
 template <int NDIR>
@@ -131,7 +140,7 @@ hipError_t hb_half_sweep(const LinkField<double>& f, const Geom& g, int parity, 
 {
     const GField none{nullptr, 0};
     const Rule<double> rule{1.0, T, (uint32_t)seed, (uint32_t)(seed >> 32), sweep};
-    return launch_mode<NDIR, double, HEATBATH, false>(f, g, parity, rule, cfg, none, st, nullptr);
+    return launch_mode<NDIR, false, double, HEATBATH, false>(f, g, parity, rule, cfg, none, st, nullptr);
 }
 
 template <int NDIR>
@@ -139,8 +148,8 @@ hipError_t hb_half_sweep(const LinkField<float>& f, const Geom& g, int parity, f
                          uint32_t sweep, const SweepConfig& cfg, const GField& gacc, hipStream_t st)
 {
     const Rule<float> rule{1.0f, T, (uint32_t)seed, (uint32_t)(seed >> 32), sweep};
-    if (gacc.base) return launch_mode<NDIR, float, HEATBATH, true>(f, g, parity, rule, cfg, gacc, st, nullptr);
-    return launch_mode<NDIR, float, HEATBATH, false>(f, g, parity, rule, cfg, gacc, st, nullptr);
+    if (gacc.base) return launch_mode<NDIR, false, float, HEATBATH, true>(f, g, parity, rule, cfg, gacc, st, nullptr);
+    return launch_mode<NDIR, false, float, HEATBATH, false>(f, g, parity, rule, cfg, gacc, st, nullptr);
 }
 
 }  // namespace sweep_impl

@@ -35,8 +35,8 @@ std::string cache_key(gf_lattice L, gf_prec kernel)
 {
     char buf[128];
     const char* k = kernel == GF_FP64 ? "fp64" : (L->gacc.base ? "fp32g" : "fp32");
-    snprintf(buf, sizeof buf, "%s %d %d %d %d %s%s", device_arch().c_str(), L->dims[0], L->dims[1], L->dims[2],
-             L->dims[3], k, L->gauge == GAUGE_COULOMB ? "-coulomb" : "");
+    snprintf(buf, sizeof buf, "%s %d %d %d %d %s%s%s", device_arch().c_str(), L->dims[0], L->dims[1], L->dims[2],
+             L->dims[3], k, L->gauge == GAUGE_COULOMB ? "-coulomb" : "", L->group == 2 ? "-su2" : "");
     return buf;
 }
 
@@ -49,7 +49,8 @@ bool cache_lookup(const char* path, const std::string& key, SweepConfig* out)
     while (fgets(line, sizeof line, f)) {
         if (strncmp(line, key.c_str(), key.size()) != 0 || line[key.size()] != ' ') continue;
         int t = 0, b = 0, nt = 0;
-        if (sscanf(line + key.size(), "%d %d %d", &t, &b, &nt) == 3 && sweep_config_valid(SweepConfig{t, b, nt})) {
+        if (sscanf(line + key.size(), "%d %d %d", &t, &b, &nt) == 3 &&
+            (sweep_config_valid(SweepConfig{t, b, nt}) || su2_config_valid(SweepConfig{t, b, nt}))) {
             *out = SweepConfig{t, b, nt};
             found = true;  // the last matching line wins
         }
@@ -81,7 +82,8 @@ gf_status tune(gf_lattice L, gf_prec kernel, bool heat_bath, int32_t n_sweeps, c
         return GF_OK;
     }
 
-    const size_t chunks = (size_t)2 * 4 * L->geom.ld * (kernel == GF_FP32 ? 3 : 6);
+    const bool su2 = L->group == 2;
+    const size_t chunks = (size_t)2 * 4 * L->geom.ld * (kernel == GF_FP32 ? (su2 ? 1 : 3) : (su2 ? 2 : 6));
     const size_t bytes = chunks * 16;
     void* scratch = nullptr;
     void* gscratch = nullptr;
@@ -103,16 +105,26 @@ gf_status tune(gf_lattice L, gf_prec kernel, bool heat_bath, int32_t n_sweeps, c
     const GField g_s{(float4*)gscratch, L->geom.ld};
     const LinkField<float> f32{(float4*)scratch, L->geom.ld};
     const LinkField<double> f64{(double2*)scratch, L->geom.ld};
+    const Su2Field<float> q32{(float4*)scratch, L->geom.ld};
+    const Su2Field<double> q64{(double2*)scratch, L->geom.ld};
     uint32_t hb_sweep = 0;
     for (int nt : {0, 1, 2})
     for (int tps : {1, 2, 4, 8}) {
         for (int block : {64, 128, 256, 512}) {
             const SweepConfig c{tps, block, nt};
-            if (e != hipSuccess || !sweep_config_valid(c)) continue;
+            if (e != hipSuccess || !(su2 ? su2_config_valid(c) : sweep_config_valid(c))) continue;
             auto sweep = [&]() -> hipError_t {
                 for (int p = 0; p < 2; ++p) {
                     hipError_t r;
-                    if (heat_bath && kernel == GF_FP32)
+                    if (su2 && heat_bath && kernel == GF_FP32)
+                        r = launch_su2_hb(q32, L->geom, p, 1.0f, 1u, hb_sweep, c, L->stream, L->gauge);
+                    else if (su2 && heat_bath)
+                        r = launch_su2_hb(q64, L->geom, p, 1.0, 1u, hb_sweep, c, L->stream, L->gauge);
+                    else if (su2 && kernel == GF_FP32)
+                        r = launch_su2_or(q32, L->geom, p, 1.7f, GF_OR_EXACT, c, L->stream, L->gauge, nullptr);
+                    else if (su2)
+                        r = launch_su2_or(q64, L->geom, p, 1.7, GF_OR_EXACT, c, L->stream, L->gauge, nullptr);
+                    else if (heat_bath && kernel == GF_FP32)
                         r = launch_hb_half_sweep(f32, L->geom, p, 1.0f, 1u, hb_sweep, c, track ? g_s : g_none,
                                                  L->stream, L->gauge);
                     else if (heat_bath)

@@ -115,6 +115,8 @@ _dp = ctypes.POINTER(ctypes.c_double)
 _SIGNATURES = {
     "gf_create_lattice": [ctypes.POINTER(_i32), ctypes.c_int, _vp, ctypes.POINTER(_vp)],
     "gf_destroy_lattice": [_vp],
+    "gf_create_lattice_su2": [ctypes.POINTER(_i32), ctypes.c_int, _vp, ctypes.POINTER(_vp)],
+    "gf_lattice_group": [_vp, ctypes.POINTER(_i32)],
     "gf_lattice_info": [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
     "gf_set_sweep_config": [_vp, ctypes.c_int, _i32, _i32, _i32],
     "gf_set_anneal_config": [_vp, ctypes.c_int, _i32, _i32, _i32],
@@ -216,11 +218,11 @@ def _stream_handle(stream):
     return int(stream.cuda_stream)  # torch.cuda.Stream
 
 
-def _host_links(u: np.ndarray, volume: int) -> np.ndarray:
+def _host_links(u: np.ndarray, volume: int, per_site: int = 72) -> np.ndarray:
     if not (isinstance(u, np.ndarray) and u.dtype == np.float64 and u.flags.c_contiguous):
         raise TypeError("host links must be a C-contiguous float64 numpy array")
-    if u.size != volume * 72:
-        raise ValueError(f"host links hold {u.size} doubles, the lattice needs {volume * 72}")
+    if u.size != volume * per_site:
+        raise ValueError(f"host links hold {u.size} doubles, the lattice needs {volume * per_site}")
     return u
 
 
@@ -232,13 +234,13 @@ def _is_device_tensor(x) -> bool:
     return isinstance(x, torch.Tensor) and x.is_cuda
 
 
-def _device_links(t, volume: int):
+def _device_links(t, volume: int, per_site: int = 72):
     import torch
 
     if t.dtype != torch.float64 or not t.is_contiguous():
         raise TypeError("device links must be a contiguous float64 tensor")
-    if t.numel() != volume * 72:
-        raise ValueError(f"device links hold {t.numel()} doubles, the lattice needs {volume * 72}")
+    if t.numel() != volume * per_site:
+        raise ValueError(f"device links hold {t.numel()} doubles, the lattice needs {volume * per_site}")
     return t
 
 
@@ -258,13 +260,23 @@ def gf_last_error() -> str:
 _LATTICE_STREAM = {}
 
 
-def gf_create_lattice(dims, prec: int = GF_FP64, stream=None) -> ctypes.c_void_p:
+def gf_create_lattice(dims, prec: int = GF_FP64, stream=None, group: int = 3) -> ctypes.c_void_p:
+    """group 3: SU(3) (gf_create_lattice); group 2: SU(2) (gf_create_lattice_su2)."""
     d = (_i32 * 4)(*[int(x) for x in dims])
     out = _vp()
     h = _stream_handle(stream)
-    _call("gf_create_lattice", d, int(prec), h, ctypes.byref(out))
+    if group not in (2, 3):
+        raise ValueError("group must be 2 (SU(2)) or 3 (SU(3))")
+    _call("gf_create_lattice_su2" if group == 2 else "gf_create_lattice", d, int(prec), h, ctypes.byref(out))
     _LATTICE_STREAM[out.value] = h
     return out
+
+
+def gf_lattice_group(lat) -> int:
+    """N_c of the lattice's gauge group (2 or 3)."""
+    n = _i32()
+    _call("gf_lattice_group", lat, ctypes.byref(n))
+    return n.value
 
 
 def gf_destroy_lattice(lat) -> None:
@@ -358,12 +370,14 @@ def gf_promote_fp64(lat) -> None:
 
 def gf_set_links(lat, links) -> None:
     volume, _ = gf_lattice_info(lat)
+    nc = gf_lattice_group(lat)
+    per_site = 4 * 2 * nc * nc
     if _is_device_tensor(links):
-        t = _device_links(links, volume)
+        t = _device_links(links, volume, per_site)
         _before_lattice_reads(lat, t)
         _call("gf_set_links_device", lat, t.data_ptr())
     else:
-        u = _host_links(links, volume)
+        u = _host_links(links, volume, per_site)
         _call("gf_set_links", lat, u.ctypes.data_as(_dp))
 
 
@@ -374,15 +388,17 @@ def gf_set_links_device(lat, dev_ptr: int) -> None:
 def gf_get_links(lat, out=None):
     """Links as a canonical array: into `out` (numpy or device tensor) or a new numpy array."""
     volume, _ = gf_lattice_info(lat)
+    nc = gf_lattice_group(lat)
+    per_site = 4 * 2 * nc * nc
     if out is None:
-        out = np.empty((volume, 4, 3, 3, 2), dtype=np.float64)
+        out = np.empty((volume, 4, nc, nc, 2), dtype=np.float64)
     if _is_device_tensor(out):
-        t = _device_links(out, volume)
+        t = _device_links(out, volume, per_site)
         _before_lattice_reads(lat, t)  # earlier torch work on `out` completes first
         _call("gf_get_links_device", lat, t.data_ptr())
         _after_lattice_writes(lat, t)
     else:
-        u = _host_links(out, volume)
+        u = _host_links(out, volume, per_site)
         _call("gf_get_links", lat, u.ctypes.data_as(_dp))
     return out
 
@@ -492,10 +508,11 @@ def gf_plaquette(lat) -> float:
 class Lattice:
     """Owning wrapper: ``with Lattice(dims, GF_FP64) as lat: ...``."""
 
-    def __init__(self, dims, prec: int = GF_FP64, stream=None, gauge: int = GF_LANDAU):
+    def __init__(self, dims, prec: int = GF_FP64, stream=None, gauge: int = GF_LANDAU, group: int = 3):
         self.dims = tuple(int(d) for d in dims)
         self.prec = prec
-        self.handle = gf_create_lattice(self.dims, prec, stream)
+        self.group = group
+        self.handle = gf_create_lattice(self.dims, prec, stream, group)
         if gauge != GF_LANDAU:
             gf_set_gauge(self.handle, gauge)
 
