@@ -188,7 +188,7 @@ def fix_until_leg(gf, torch, stream, links, dims, args, eps, adaptive_too=False)
     for name, prec, adaptive in runs:
         with gf.Lattice(dims, prec, stream=stream) as lat:
             lat.set_check_policy(adaptive)
-            lat.set_sweep_config(args.tps, args.block, args.nt, kernel=gf.GF_FP64)
+            lat.set_sweep_config(args.tps, args.block, args.nt, kernel=gf.GF_FP64, min_waves=args.minw)
             lat.set_links(links)
             if prec == gf.GF_MIXED:
                 # the float32 sweeps of a mixed lattice also update g(x): tuned as their own kernel
@@ -320,8 +320,8 @@ def fullsize_f64_leg(gf, torch, stream, u, args):
     V = u.shape[0]
     with gf.Lattice(dims, gf.GF_FP64, stream=stream) as lat:
         lat.set_links(u)
-        (tps, block, nt), table = lat.autotune(gf.GF_FP64, n_sweeps=3)
-        log(f"fullsize fp64 autotune: tps={tps} block={block} cache policy={nt}")
+        (tps, block, nt, minw), table = lat.autotune(gf.GF_FP64, n_sweeps=3)
+        log(f"fullsize fp64 autotune: tps={tps} block={block} cache policy={nt} min waves={minw}")
         with torch.cuda.stream(stream):
             lat.sweep(args.warmup, args.omega, args.mode)
             total, wall, per_launch = time_run(lat, torch, stream, args.full_steps, args.omega, args.mode,
@@ -340,8 +340,8 @@ def fullsize_f64_leg(gf, torch, stream, u, args):
         "unit": "site-updates/s",
         "ms_per_step": total * 1e3 / args.full_steps,
         "gflops": rate * FLOPS_PER_SITE_UPDATE / 1e9,
-        "threads_per_site": tps, "block": block, "nontemporal": nt,
-        "tuning_us_per_sweep": [[t, b, c, round(us, 1)] for (t, b, c, us) in table],
+        "threads_per_site": tps, "block": block, "nontemporal": nt, "min_waves": minw,
+        "tuning_us_per_sweep": [[t, b, c, w, round(us, 1)] for (t, b, c, w, us) in table],
         "roofline": {
             "bound": "hbm",
             "achieved": achieved,
@@ -349,7 +349,8 @@ def fullsize_f64_leg(gf, torch, stream, u, args):
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
             "traffic": committed_traffic(TRAFFIC_FILE_48),
-            "kernel": "k_or_half_sweep<double, TPS=%d, exact, BLOCK=%d, cache policy %d>" % (tps, block, nt),
+            "kernel": "k_or_half_sweep<double, TPS=%d, exact, BLOCK=%d, cache policy %d%s>" % (
+                tps, block, nt, ", 2 waves/SIMD" if minw == 2 else ""),
             "algorithmic_bytes_per_launch": launch_bytes,
             "mean_launch_us": per_launch * 1e6,
         },
@@ -496,6 +497,8 @@ def main(argv=None):
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--nt", type=int, default=0,
                     help="cache policy: 0 plain, 1 non-temporal loads and stores, 2 non-temporal stores")
+    ap.add_argument("--minw", type=int, default=0,
+                    help="register limit of the float64 sweep: 0 compiler's allocation, 2 at least 2 waves per SIMD")
     ap.add_argument("--nt32", type=int, default=0)
     ap.add_argument("--tps32", type=int, default=4)
     ap.add_argument("--block32", type=int, default=256)
@@ -588,12 +591,12 @@ def main(argv=None):
     result = {}
     tuning = {}
     with gf.Lattice(dims, gf.GF_FP64, stream=stream) as lat:
-        lat.set_sweep_config(args.tps, args.block, args.nt)
+        lat.set_sweep_config(args.tps, args.block, args.nt, min_waves=args.minw)
         lat.set_links(links)
         if not args.no_tune:
-            (args.tps, args.block, args.nt), table = lat.autotune(gf.GF_FP64, n_sweeps=5)
-            tuning["f64"] = [[t, b, nt, round(us, 1)] for (t, b, nt, us) in table]
-            log(f"fp64 autotune: tps={args.tps} block={args.block} cache policy={args.nt}")
+            (args.tps, args.block, args.nt, args.minw), table = lat.autotune(gf.GF_FP64, n_sweeps=5)
+            tuning["f64"] = [[t, b, nt, w, round(us, 1)] for (t, b, nt, w, us) in table]
+            log(f"fp64 autotune: tps={args.tps} block={args.block} cache policy={args.nt} min waves={args.minw}")
         P0 = lat.plaquette()
         log(f"fp64: warmup {args.warmup} sweeps")
         with torch.cuda.stream(stream):
@@ -614,8 +617,8 @@ def main(argv=None):
             lat.set_sweep_config(args.tps32, args.block32, args.nt32)
             lat.set_links(links)
             if not args.no_tune:
-                (args.tps32, args.block32, args.nt32), table = lat.autotune(gf.GF_FP32, n_sweeps=5)
-                tuning["f32"] = [[t, b, nt, round(us, 1)] for (t, b, nt, us) in table]
+                (args.tps32, args.block32, args.nt32, _), table = lat.autotune(gf.GF_FP32, n_sweeps=5)
+                tuning["f32"] = [[t, b, nt, round(us, 1)] for (t, b, nt, _, us) in table]
                 log(f"fp32 autotune: tps={args.tps32} block={args.block32} cache policy={args.nt32}")
             with torch.cuda.stream(stream):
                 lat.sweep(args.warmup, args.omega, args.mode)
@@ -656,6 +659,7 @@ def main(argv=None):
             "threads_per_site": args.tps,
             "block": args.block,
             "nontemporal": args.nt,
+            "min_waves": args.minw,
         },
         "hbm_GBps_algorithmic": rate * BYTES_PER_SITE["f64"] / 1e9,
         "pct_hbm_peak": 100.0 * rate * BYTES_PER_SITE["f64"] / 1e9 / HBM_PEAK_GBPS,
@@ -666,8 +670,8 @@ def main(argv=None):
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
             "traffic": traffic,
-            "kernel": "k_or_half_sweep<double, TPS=%d, exact, BLOCK=%d, cache policy %d>" % (args.tps, args.block,
-                                                                                            args.nt),
+            "kernel": "k_or_half_sweep<double, TPS=%d, exact, BLOCK=%d, cache policy %d%s>" % (
+                args.tps, args.block, args.nt, ", 2 waves/SIMD" if args.minw == 2 else ""),
             "algorithmic_bytes_per_launch": launch_bytes,
             "mean_launch_us": r64["per_launch"] * 1e6,
             "note": "the 403 MB float64 field partly fits the 256 MB Infinity Cache, which the reversed white "

@@ -134,16 +134,22 @@ gf_status gf_lattice_info(gf_lattice lat, int64_t* volume, int64_t* device_bytes
 /* Kernel configuration of the sweep in precision `kernel` (GF_FP64 or
  * GF_FP32; a GF_MIXED lattice uses both): tps lanes per site (1, 2, 4 or 8;
  * the paper's design uses 4 or 8 threads per site, Sec. 4.2), threads per
- * block (64, 128, 256 or 512; not 512 with tps 1) and the cache policy of the
+ * block (64, 128, 256 or 512; not 512 with tps 1), the cache policy of the
  * link accesses (0 = plain, 1 = non-temporal loads and stores, 2 = plain
- * loads and non-temporal stores; 1 and 2 only with tps <= 4 and block <= 256).
- * Every valid choice gives bitwise the same links.  Default 4 / 256 / 0. */
-gf_status gf_set_sweep_config(gf_lattice lat, gf_prec kernel, int32_t tps, int32_t block, int32_t nontemporal);
+ * loads and non-temporal stores; 1 and 2 only with tps <= 4 and block <= 256)
+ * and the register limit (min_waves: 0 = the compiler's allocation, 2 = at
+ * least 2 waves per SIMD, at most 256 registers per lane; 2 only with tps 1,
+ * and it changes only float64 kernels, the paper's register-limit axis of
+ * Sec. 5).  Every valid choice gives bitwise the same links.  Default
+ * 4 / 256 / 0 / 0. */
+gf_status gf_set_sweep_config(gf_lattice lat, gf_prec kernel, int32_t tps, int32_t block, int32_t nontemporal,
+                              int32_t min_waves);
 
 /* The same for the heat-bath sweeps of gf_anneal, which sample every
  * subgroup element in each lane of a site's group (so fewer lanes do less
  * arithmetic).  Default 1 / 256 / 0 for float32, 1 / 128 / 2 for float64. */
-gf_status gf_set_anneal_config(gf_lattice lat, gf_prec kernel, int32_t tps, int32_t block, int32_t nontemporal);
+gf_status gf_set_anneal_config(gf_lattice lat, gf_prec kernel, int32_t tps, int32_t block, int32_t nontemporal,
+                               int32_t min_waves);
 
 /* GF_MIXED: leave the float32 phase now.  The float64 links become
  * g(x) U0_mu(x) g(x+mu^)^dag, U0 the links given to gf_set_links and g the
@@ -156,12 +162,14 @@ typedef struct {
     int32_t tps;
     int32_t block;
     int32_t nontemporal;
+    int32_t min_waves;   /* register limit: 0 = compiler's allocation, 2 = at least 2 waves per SIMD */
     double us_per_sweep; /* mean time of one sweep (both colours), microseconds */
 } gf_tune_entry;
 
 /* Autotuner (the paper tunes threads per site, launch bounds and texture
  * loads at run time, Sec. 4 and 5): time every valid sweep configuration
- * (lanes per site, block size, cache policy) of precision `kernel`
+ * (lanes per site, block size, cache policy, and for float64 the register
+ * limit) of precision `kernel`
  * (GF_FP64 or GF_FP32) on a scratch copy of the lattice's links (one warm-up
  * sweep, then n_sweeps timed sweeps each), write up to cap entries to table
  * (may be NULL), and make the fastest the lattice's configuration.  When

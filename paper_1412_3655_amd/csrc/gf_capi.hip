@@ -193,7 +193,7 @@ gf_status do_sweeps(gf_lattice L, int32_t n, double omega, int mode)
     const bool fp32 = is_fp32(L);
     const SweepConfig& c = fp32 ? L->cfg32 : L->cfg64;
     const int kind = (fp32 ? (g_tracking(L).base ? 2 : 1) : 0) + 4 * L->gauge + 8 * (L->group == 2);
-    const auto key = std::make_tuple(n, omega, mode, kind, c.tps, c.block, c.nt);
+    const auto key = std::make_tuple(n, omega, mode, kind, c.tps, c.block, c.nt + 4 * c.minw);
     auto it = L->sweep_graphs.find(key);
     if (it == L->sweep_graphs.end()) {
         if (L->sweep_graphs.size() >= 16) clear_graphs(L);
@@ -542,11 +542,12 @@ gf_status gf_lattice_info(gf_lattice L, int64_t* volume, int64_t* device_bytes)
 
 namespace {
 
-gf_status set_config(gf_lattice L, gf_prec kernel, int32_t tps, int32_t block, int32_t nontemporal, bool heat_bath)
+gf_status set_config(gf_lattice L, gf_prec kernel, int32_t tps, int32_t block, int32_t nontemporal, int32_t min_waves,
+                     bool heat_bath)
 {
     if (!L) return fail(GF_E_ARG, "null lattice");
     if (kernel != GF_FP64 && kernel != GF_FP32) return fail(GF_E_ARG, "kernel precision must be GF_FP64 or GF_FP32");
-    SweepConfig c{tps, block, nontemporal};
+    SweepConfig c{tps, block, nontemporal, min_waves};
     if (L->group == 2) {
         if (!gf::su2_config_valid(c))
             return fail(GF_E_ARG,
@@ -555,9 +556,10 @@ gf_status set_config(gf_lattice L, gf_prec kernel, int32_t tps, int32_t block, i
                         tps, block, nontemporal);
     } else if (!gf::sweep_config_valid(c))
         return fail(GF_E_ARG,
-                    "sweep config tps=%d block=%d policy=%d: tps must be 1, 2, 4 or 8, block 64, 128, 256 or 512 "
-                    "(not 512 with tps 1), cache policy 0, 1 or 2 (1 and 2 only with tps <= 4 and block <= 256)",
-                    tps, block, nontemporal);
+                    "sweep config tps=%d block=%d policy=%d min_waves=%d: tps must be 1, 2, 4 or 8, block 64, 128, "
+                    "256 or 512 (not 512 with tps 1), cache policy 0, 1 or 2 (1 and 2 only with tps <= 4 and block "
+                    "<= 256), min_waves 0 or 2 (2 only with tps 1)",
+                    tps, block, nontemporal, min_waves);
     if (heat_bath)
         (kernel == GF_FP32 ? L->cfg_hb32 : L->cfg_hb64) = c;
     else
@@ -567,14 +569,16 @@ gf_status set_config(gf_lattice L, gf_prec kernel, int32_t tps, int32_t block, i
 
 }  // namespace
 
-gf_status gf_set_sweep_config(gf_lattice L, gf_prec kernel, int32_t tps, int32_t block, int32_t nontemporal)
+gf_status gf_set_sweep_config(gf_lattice L, gf_prec kernel, int32_t tps, int32_t block, int32_t nontemporal,
+                              int32_t min_waves)
 {
-    return set_config(L, kernel, tps, block, nontemporal, false);
+    return set_config(L, kernel, tps, block, nontemporal, min_waves, false);
 }
 
-gf_status gf_set_anneal_config(gf_lattice L, gf_prec kernel, int32_t tps, int32_t block, int32_t nontemporal)
+gf_status gf_set_anneal_config(gf_lattice L, gf_prec kernel, int32_t tps, int32_t block, int32_t nontemporal,
+                               int32_t min_waves)
 {
-    return set_config(L, kernel, tps, block, nontemporal, true);
+    return set_config(L, kernel, tps, block, nontemporal, min_waves, true);
 }
 
 gf_status gf_promote_fp64(gf_lattice L)

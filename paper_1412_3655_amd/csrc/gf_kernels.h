@@ -9,13 +9,17 @@
 namespace gf {
 
 // Sweep kernel configuration: lanes per site (1, 2, 4 or 8), block size
-// (64, 128, 256 or 512 threads) and cache policy of the link accesses (0 =
+// (64, 128, 256 or 512 threads), cache policy of the link accesses (0 =
 // plain, 1 = non-temporal loads and stores, 2 = plain loads and non-temporal
-// stores; 1 and 2 with tps <= 4 and block <= 256).
+// stores; 1 and 2 with tps <= 4 and block <= 256) and register limit (minw:
+// 0 = the compiler's allocation, 2 = at least 2 waves per SIMD, i.e. at most
+// 256 registers per lane; only with tps 1, where a float64 site update
+// otherwise takes 256 VGPRs + 68 AGPRs and 1 wave per SIMD).
 struct SweepConfig {
     int tps = 4;
     int block = 256;
     int nt = 0;
+    int minw = 0;
 };
 
 bool sweep_config_valid(const SweepConfig& c);

@@ -1105,7 +1105,7 @@ gf_status gf_pool_autotune(gf_pool P, int32_t kernel, int32_t n_sweeps, size_t s
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
             if (e != hipSuccess) break;
             const double us = 1e3 * (double)ms / n_sweeps;
-            if (m < cap) table[m] = gf_tune_entry{tps, block, f32 ? 0 : 1, us};
+            if (m < cap) table[m] = gf_tune_entry{tps, block, f32 ? 0 : 1, 0, us};
             ++m;
             if (us < best_us) {
                 best_us = us;
@@ -1137,7 +1137,7 @@ gf_status gf_pool_autotune(gf_pool P, int32_t kernel, int32_t n_sweeps, size_t s
     for (auto& kv : P->graphs) destroy_step_graph(kv.second);
     P->graphs.clear();
     if (n_out) *n_out = std::min(m, cap);
-    if (chosen) *chosen = gf_tune_entry{best_tps, best_block, f32 ? 0 : 1, best_us};
+    if (chosen) *chosen = gf_tune_entry{best_tps, best_block, f32 ? 0 : 1, 0, best_us};
     return GF_OK;
 }
 

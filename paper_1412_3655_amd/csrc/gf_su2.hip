@@ -362,7 +362,7 @@ uint32_t su2_partials(const Geom& g)
 bool su2_config_valid(const SweepConfig& c)
 {
     return c.tps == 1 && (c.block == 64 || c.block == 128 || c.block == 256 || c.block == 512) &&
-           (c.nt == 0 || c.nt == 1 || c.nt == 2);
+           (c.nt == 0 || c.nt == 1 || c.nt == 2) && c.minw == 0;
 }
 
 uint32_t su2_sweep_blocks(const Geom& g, const SweepConfig& c)

@@ -12,8 +12,9 @@ bool sweep_config_valid(const SweepConfig& c)
     const bool tps_ok = c.tps == 1 || c.tps == 2 || c.tps == 4 || c.tps == 8;
     const bool blk_ok = c.block == 64 || c.block == 128 || c.block == 256 || c.block == 512;
     const bool nt_ok = c.nt == 0 || ((c.nt == 1 || c.nt == 2) && c.tps <= 4 && c.block <= 256);
+    const bool minw_ok = c.minw == 0 || (c.minw == 2 && c.tps == 1);
     // one lane per site needs more than the 256 registers a 512-thread block allows
-    return tps_ok && blk_ok && nt_ok && !(c.tps == 1 && c.block == 512);
+    return tps_ok && blk_ok && nt_ok && minw_ok && !(c.tps == 1 && c.block == 512);
 }
 
 hipError_t launch_or_half_sweep(const LinkField<double>& f, const Geom& g, int parity, double omega, int mode,

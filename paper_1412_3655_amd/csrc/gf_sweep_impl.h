@@ -21,8 +21,8 @@ namespace sweep_impl {
 // 0), which a fixed-order pass turns into an estimate of theta.  A template
 // parameter, so the plain sweep carries none of it.
 template <typename R, int TPS, int MODE, int BLOCK, bool TRACKG, int CP, int NDIR, bool EST>
-__global__ void __launch_bounds__(BLOCK) k_or_half_sweep(LinkField<R> f, Geom g, int parity, Rule<R> rule,
-                                                         GField gacc, double* est)
+__device__ __forceinline__ void half_sweep_body(const LinkField<R>& f, const Geom& g, int parity, const Rule<R>& rule,
+                                                const GField& gacc, double* est)
 {
     // With cached loads the white half-sweep takes the blocks in reverse
     // order, so it starts on the links the black half-sweep touched last,
@@ -45,6 +45,23 @@ __global__ void __launch_bounds__(BLOCK) k_or_half_sweep(LinkField<R> f, Geom g,
     }
 }
 
+template <typename R, int TPS, int MODE, int BLOCK, bool TRACKG, int CP, int NDIR, bool EST>
+__global__ void __launch_bounds__(BLOCK) k_or_half_sweep(LinkField<R> f, Geom g, int parity, Rule<R> rule,
+                                                         GField gacc, double* est)
+{
+    half_sweep_body<R, TPS, MODE, BLOCK, TRACKG, CP, NDIR, EST>(f, g, parity, rule, gacc, est);
+}
+
+// The same kernel held to at least 2 waves per SIMD (at most 256 registers per
+// lane): the register-limit axis of run-time tuning, for the one-lane float64
+// shape.
+template <typename R, int TPS, int MODE, int BLOCK, bool TRACKG, int CP, int NDIR, bool EST>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
+k_or_half_sweep_w2(LinkField<R> f, Geom g, int parity, Rule<R> rule, GField gacc, double* est)
+{
+    half_sweep_body<R, TPS, MODE, BLOCK, TRACKG, CP, NDIR, EST>(f, g, parity, rule, gacc, est);
+}
+
 // Blocks of one half-sweep launch in configuration c (the estimate buffer
 // holds 2 pairs per block of each colour).
 inline uint32_t sweep_grid(const Geom& g, const SweepConfig& c)
@@ -59,9 +76,22 @@ hipError_t launch_tps(const LinkField<R>& f, const Geom& g, int parity, const Ru
     const int block = c.block;
     const uint32_t grid = sweep_grid(g, c);
     if (grid == 0) return hipSuccess;
-#define GF_LAUNCH(B, CPV)                                                                                      \
-    hipLaunchKernelGGL((k_or_half_sweep<R, TPS, MODE, B, TRACKG, CPV, NDIR, EST>), dim3(grid), dim3(B), 0, st, f, \
-                       g, parity, rule, gacc, est)
+    // minw = 2 selects the register-capped kernel for the one-lane float64 shape
+    // (other shapes already run 2 or more waves per SIMD)
+    constexpr bool kCap = sizeof(R) == 8 && TPS == 1;
+    const bool cap = kCap && c.minw == 2;
+#define GF_LAUNCH(B, CPV)                                                                                         \
+    do {                                                                                                          \
+        if constexpr (kCap) {                                                                                     \
+            if (cap) {                                                                                            \
+                hipLaunchKernelGGL((k_or_half_sweep_w2<R, TPS, MODE, B, TRACKG, CPV, NDIR, EST>), dim3(grid),     \
+                                   dim3(B), 0, st, f, g, parity, rule, gacc, est);                                \
+                break;                                                                                            \
+            }                                                                                                     \
+        }                                                                                                         \
+        hipLaunchKernelGGL((k_or_half_sweep<R, TPS, MODE, B, TRACKG, CPV, NDIR, EST>), dim3(grid), dim3(B), 0, st, \
+                           f, g, parity, rule, gacc, est);                                                        \
+    } while (0)
 #define GF_LAUNCH_SMALL_BLOCKS(CPV)                  \
     switch (block) {                                 \
         case 64: GF_LAUNCH(64, CPV); break;          \

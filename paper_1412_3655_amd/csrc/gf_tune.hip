@@ -1,10 +1,11 @@
 // gf_tune.hip -- run-time autotuning of the sweep kernel (include/gf.h,
 // gf_autotune).  The paper's cuLGT2 picks 4 or 8 threads per site, register
 // limits and texture loads by trying them at run time (Sec. 4 and 5); here the
-// axes are lanes per site (1, 2, 4, 8), threads per block (64..512) and the
+// axes are lanes per site (1, 2, 4, 8), threads per block (64..512), the
 // cache policy of the link accesses (plain / non-temporal / non-temporal
-// stores only), timed with HIP events on a scratch copy of the links so the
-// lattice is unchanged.  The kernel timed is that of the lattice's gauge.
+// stores only) and the register limit (the compiler's allocation, or at most
+// 256 registers for 2 waves per SIMD), timed with HIP events on a scratch copy
+// of the links so the lattice is unchanged.  The kernel timed is that of the lattice's gauge.
 // Every configuration gives bitwise the same links, so only time decides.
 #include <cstdio>
 #include <cstring>
@@ -48,10 +49,13 @@ bool cache_lookup(const char* path, const std::string& key, SweepConfig* out)
     bool found = false;
     while (fgets(line, sizeof line, f)) {
         if (strncmp(line, key.c_str(), key.size()) != 0 || line[key.size()] != ' ') continue;
-        int t = 0, b = 0, nt = 0;
-        if (sscanf(line + key.size(), "%d %d %d", &t, &b, &nt) == 3 &&
-            (sweep_config_valid(SweepConfig{t, b, nt}) || su2_config_valid(SweepConfig{t, b, nt}))) {
-            *out = SweepConfig{t, b, nt};
+        int t = 0, b = 0, nt = 0, w = 0;
+        double us = 0.0;
+        const int got = sscanf(line + key.size(), "%d %d %d %d %lf", &t, &b, &nt, &w, &us);
+        if (got < 5) w = 0;  // lines of three values: written before the register-limit axis
+        const SweepConfig c{t, b, nt, w};
+        if (got >= 3 && (sweep_config_valid(c) || su2_config_valid(c))) {
+            *out = c;
             found = true;  // the last matching line wins
         }
     }
@@ -78,7 +82,7 @@ gf_status tune(gf_lattice L, gf_prec kernel, bool heat_bath, int32_t n_sweeps, c
     SweepConfig best{};
     if (cache_path && cache_lookup(cache_path, key, &best)) {
         target = best;
-        if (chosen) *chosen = gf_tune_entry{best.tps, best.block, best.nt, 0.0};
+        if (chosen) *chosen = gf_tune_entry{best.tps, best.block, best.nt, best.minw, 0.0};
         return GF_OK;
     }
 
@@ -108,10 +112,15 @@ gf_status tune(gf_lattice L, gf_prec kernel, bool heat_bath, int32_t n_sweeps, c
     const Su2Field<float> q32{(float4*)scratch, L->geom.ld};
     const Su2Field<double> q64{(double2*)scratch, L->geom.ld};
     uint32_t hb_sweep = 0;
+    // the register cap changes only the one-lane float64 kernel (every other
+    // shape already runs 2 or more waves per SIMD)
+    const bool cap_axis = !su2 && kernel == GF_FP64;
+    for (int minw : {0, 2})
     for (int nt : {0, 1, 2})
     for (int tps : {1, 2, 4, 8}) {
         for (int block : {64, 128, 256, 512}) {
-            const SweepConfig c{tps, block, nt};
+            const SweepConfig c{tps, block, nt, minw};
+            if (minw && !cap_axis) continue;
             if (e != hipSuccess || !(su2 ? su2_config_valid(c) : sweep_config_valid(c))) continue;
             auto sweep = [&]() -> hipError_t {
                 for (int p = 0; p < 2; ++p) {
@@ -148,7 +157,7 @@ gf_status tune(gf_lattice L, gf_prec kernel, bool heat_bath, int32_t n_sweeps, c
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
             if (e != hipSuccess) break;
             const double us = 1e3 * (double)ms / n_sweeps;
-            if (n < cap) table[n] = gf_tune_entry{tps, block, nt, us};
+            if (n < cap) table[n] = gf_tune_entry{tps, block, nt, minw, us};
             ++n;
             if (us < best_us) {
                 best_us = us;
@@ -165,11 +174,11 @@ gf_status tune(gf_lattice L, gf_prec kernel, bool heat_bath, int32_t n_sweeps, c
     if (st != GF_OK) return st;
     target = best;
     if (n_out) *n_out = std::min(n, cap);
-    if (chosen) *chosen = gf_tune_entry{best.tps, best.block, best.nt, best_us};
+    if (chosen) *chosen = gf_tune_entry{best.tps, best.block, best.nt, best.minw, best_us};
     if (cache_path) {
         FILE* f = fopen(cache_path, "a");
         if (f) {
-            fprintf(f, "%s %d %d %d %.3f\n", key.c_str(), best.tps, best.block, best.nt, best_us);
+            fprintf(f, "%s %d %d %d %d %.3f\n", key.c_str(), best.tps, best.block, best.nt, best.minw, best_us);
             fclose(f);
         }
     }

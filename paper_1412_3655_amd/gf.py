@@ -69,7 +69,7 @@ class gf_fix_result(ctypes.Structure):
 
 class gf_tune_entry(ctypes.Structure):
     _fields_ = [("tps", ctypes.c_int32), ("block", ctypes.c_int32), ("nontemporal", ctypes.c_int32),
-                ("us_per_sweep", ctypes.c_double)]
+                ("min_waves", ctypes.c_int32), ("us_per_sweep", ctypes.c_double)]
 
 
 class gf_pool_config(ctypes.Structure):
@@ -118,8 +118,8 @@ _SIGNATURES = {
     "gf_create_lattice_su2": [ctypes.POINTER(_i32), ctypes.c_int, _vp, ctypes.POINTER(_vp)],
     "gf_lattice_group": [_vp, ctypes.POINTER(_i32)],
     "gf_lattice_info": [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
-    "gf_set_sweep_config": [_vp, ctypes.c_int, _i32, _i32, _i32],
-    "gf_set_anneal_config": [_vp, ctypes.c_int, _i32, _i32, _i32],
+    "gf_set_sweep_config": [_vp, ctypes.c_int, _i32, _i32, _i32, _i32],
+    "gf_set_anneal_config": [_vp, ctypes.c_int, _i32, _i32, _i32, _i32],
     "gf_get_anneal_counter": [_vp, ctypes.POINTER(ctypes.c_uint32)],
     "gf_set_anneal_counter": [_vp, ctypes.c_uint32],
     "gf_promote_fp64": [_vp],
@@ -324,8 +324,8 @@ def gf_lattice_info(lat):
     return v.value, b.value
 
 
-def gf_set_sweep_config(lat, kernel: int, tps: int, block: int, nontemporal: int = 0) -> None:
-    _call("gf_set_sweep_config", lat, int(kernel), int(tps), int(block), int(nontemporal))
+def gf_set_sweep_config(lat, kernel: int, tps: int, block: int, nontemporal: int = 0, min_waves: int = 0) -> None:
+    _call("gf_set_sweep_config", lat, int(kernel), int(tps), int(block), int(nontemporal), int(min_waves))
 
 
 def gf_get_anneal_counter(lat) -> int:
@@ -338,8 +338,8 @@ def gf_set_anneal_counter(lat, sweeps_done: int) -> None:
     _call("gf_set_anneal_counter", lat, int(sweeps_done))
 
 
-def gf_set_anneal_config(lat, kernel: int, tps: int, block: int, nontemporal: int = 0) -> None:
-    _call("gf_set_anneal_config", lat, int(kernel), int(tps), int(block), int(nontemporal))
+def gf_set_anneal_config(lat, kernel: int, tps: int, block: int, nontemporal: int = 0, min_waves: int = 0) -> None:
+    _call("gf_set_anneal_config", lat, int(kernel), int(tps), int(block), int(nontemporal), int(min_waves))
 
 
 def _tune(name, lat, kernel, n_sweeps, cache_path):
@@ -349,8 +349,9 @@ def _tune(name, lat, kernel, n_sweeps, cache_path):
     ch = gf_tune_entry()
     cp = None if cache_path is None else os.fsencode(cache_path)
     _call(name, lat, int(kernel), int(n_sweeps), cp, buf, cap, ctypes.byref(n), ctypes.byref(ch))
-    table = [(buf[i].tps, buf[i].block, buf[i].nontemporal, buf[i].us_per_sweep) for i in range(n.value)]
-    return (ch.tps, ch.block, ch.nontemporal), table
+    table = [(buf[i].tps, buf[i].block, buf[i].nontemporal, buf[i].min_waves, buf[i].us_per_sweep)
+             for i in range(n.value)]
+    return (ch.tps, ch.block, ch.nontemporal, ch.min_waves), table
 
 
 def gf_autotune(lat, kernel: int, n_sweeps: int = 5, cache_path=None):
@@ -589,13 +590,13 @@ class Lattice:
     def plaquette(self) -> float:
         return gf_plaquette(self.handle)
 
-    def set_sweep_config(self, tps: int, block: int, nontemporal: int = 0, kernel=None):
+    def set_sweep_config(self, tps: int, block: int, nontemporal: int = 0, kernel=None, min_waves: int = 0):
         """Configure the sweep kernel of `kernel` precision (default: the lattice's own;
         GF_MIXED configures both)."""
         kinds = [kernel] if kernel is not None else (
             [GF_FP32, GF_FP64] if self.prec == GF_MIXED else [self.prec])
         for k in kinds:
-            gf_set_sweep_config(self.handle, k, tps, block, nontemporal)
+            gf_set_sweep_config(self.handle, k, tps, block, nontemporal, min_waves)
 
     def promote_fp64(self):
         gf_promote_fp64(self.handle)
@@ -612,11 +613,11 @@ class Lattice:
     def anneal_counter(self, sweeps_done: int):
         gf_set_anneal_counter(self.handle, sweeps_done)
 
-    def set_anneal_config(self, tps: int, block: int, nontemporal: int = 0, kernel=None):
+    def set_anneal_config(self, tps: int, block: int, nontemporal: int = 0, kernel=None, min_waves: int = 0):
         kinds = [kernel] if kernel is not None else (
             [GF_FP32, GF_FP64] if self.prec == GF_MIXED else [self.prec])
         for k in kinds:
-            gf_set_anneal_config(self.handle, k, tps, block, nontemporal)
+            gf_set_anneal_config(self.handle, k, tps, block, nontemporal, min_waves)
 
     def autotune_anneal(self, kernel=None, n_sweeps: int = 5, cache_path=None):
         k = kernel if kernel is not None else (GF_FP32 if self.prec != GF_FP64 else GF_FP64)

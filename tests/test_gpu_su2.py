@@ -223,7 +223,7 @@ def test_autotune_and_errors():
         with pytest.raises(gf.GFError) as e:
             lat.tune_switch()
         assert e.value.status == gf.GF_E_STATE
-        (tps, block, nt), table = lat.autotune(gf.GF_FP64, n_sweeps=2)
-        assert tps == 1 and len(table) == 12
+        (tps, block, nt, minw), table = lat.autotune(gf.GF_FP64, n_sweeps=2)
+        assert tps == 1 and minw == 0 and len(table) == 12
         before = lat.get_links()
         assert np.array_equal(before, lat.get_links())

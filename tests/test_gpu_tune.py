@@ -35,11 +35,14 @@ def test_autotune(prec, tmp_path):
         chosen, table = lat.autotune(n_sweeps=2, cache_path=cache)
         assert np.array_equal(lat.get_links(), before)
         # plain: 4 lane splits x 4 block sizes minus (1 lane, 512); each of the two
-        # non-temporal policies: 3 lane splits (1, 2, 4) x 3 block sizes (64, 128, 256)
-        assert len(table) == 15 + 9 + 9
+        # non-temporal policies: 3 lane splits (1, 2, 4) x 3 block sizes (64, 128, 256);
+        # float64 adds the register cap of the one-lane shape (3 blocks x 3 policies)
+        assert len(table) == 15 + 9 + 9 + (9 if prec == gf.GF_FP64 else 0)
         assert {e[2] for e in table} == {0, 1, 2}
-        assert chosen == min(table, key=lambda e: e[3])[:3]
-        assert all(e[3] > 0 for e in table)
+        assert {e[3] for e in table} == ({0, 2} if prec == gf.GF_FP64 else {0})
+        assert all(e[0] == 1 for e in table if e[3] == 2)
+        assert chosen == min(table, key=lambda e: e[4])[:4]
+        assert all(e[4] > 0 for e in table)
         chosen2, table2 = lat.autotune(n_sweeps=2, cache_path=cache)
         assert chosen2 == chosen and table2 == []
         lat.sweep(2, 1.7)
@@ -64,7 +67,7 @@ def test_autotune_cache_tells_g_tracking_apart(tmp_path):
             assert len(table) == 15 + 9 + 9  # timed, not read from the other kernel's entry
             _, table2 = lat.autotune(gf.GF_FP32, n_sweeps=2, cache_path=cache)
             assert table2 == []
-    keys = [line.split()[-5] for line in open(cache).read().strip().splitlines()]
+    keys = [line.split()[-6] for line in open(cache).read().strip().splitlines()]
     assert sorted(keys) == ["fp32", "fp32g"]
 
 
@@ -86,9 +89,31 @@ def test_autotune_anneal(prec, tmp_path):
         before = lat.get_links()
         chosen, table = lat.autotune_anneal(n_sweeps=2, cache_path=cache)
         assert np.array_equal(lat.get_links(), before)
-        assert len(table) == 15 + 9 + 9
-        assert chosen == min(table, key=lambda e: e[3])[:3]
+        assert len(table) == 15 + 9 + 9 + (9 if prec == gf.GF_FP64 else 0)
+        assert chosen == min(table, key=lambda e: e[4])[:4]
         chosen2, table2 = lat.autotune_anneal(n_sweeps=2, cache_path=cache)
         assert chosen2 == chosen and table2 == []
         lat.anneal(3, 1.25, 0.5, 9)
         assert np.array_equal(lat.get_links(), default)
+
+
+@pytest.mark.parametrize("cp", [0, 1, 2])
+def test_register_cap_is_bitwise_irrelevant(cp):
+    """The one-lane float64 kernel held to 2 waves per SIMD (at most 256 registers) gives the
+    links of the default allocation bitwise, for overrelaxation and the heat bath."""
+    dims = (6, 10, 6, 6)
+    u = gi.gen_links(dims, 0.8, 6)
+    outs = []
+    for minw in (0, 2):
+        with gf.Lattice(dims, gf.GF_FP64) as lat:
+            lat.set_sweep_config(1, 128, cp, min_waves=minw)
+            lat.set_anneal_config(1, 128, cp, min_waves=minw)
+            lat.set_links(u)
+            lat.anneal(2, 1.25, 0.5, 3)
+            lat.sweep(3, 1.7)
+            outs.append(lat.get_links())
+    assert np.array_equal(outs[0], outs[1])
+    with gf.Lattice(dims, gf.GF_FP64) as lat:
+        with pytest.raises(gf.GFError) as e:
+            lat.set_sweep_config(2, 128, 0, min_waves=2)
+        assert e.value.status == gf.GF_E_ARG
