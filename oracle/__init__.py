@@ -64,6 +64,9 @@ __all__ = [
     "su2lat_reunitarize",
     "su2lat_fix_until",
     "su2lat_anneal",
+    "min8_encode",
+    "min8_decode",
+    "min8_store",
 ]
 
 OR_EXACT = 0
@@ -165,6 +168,9 @@ def _declare(L):
     L.oracle_su2lat_anneal.restype = ctypes.c_int64
     L.oracle_hb_subgroup_draws.argtypes = [_dp, ctypes.c_double, ctypes.c_uint64, ctypes.c_int64, _dp]
     L.oracle_hb_subgroup_draws.restype = ctypes.c_int64
+    L.oracle_min8_encode.argtypes = [_dp, ctypes.c_int64, _dp]
+    L.oracle_min8_decode.argtypes = [_dp, ctypes.c_int64, _dp]
+    L.oracle_min8_store.argtypes = [_dp, ctypes.c_int64]
     L.oracle_num_threads.restype = ctypes.c_int
     L.oracle_set_num_threads.argtypes = [ctypes.c_int]
 
@@ -547,3 +553,36 @@ def su2lat_anneal(u, dims, nsweeps: int, T0: float, T1: float, seed: int, sweep_
     d = _dims(dims, u)
     return int(lib().oracle_su2lat_anneal(_p(u), _p(d, _ip), int(nsweeps), float(T0), float(T1),
                                           int(seed) & 0xFFFFFFFFFFFFFFFF, int(sweep_offset), int(ndir)))
+
+
+def _mats(u: np.ndarray) -> np.ndarray:
+    if not (isinstance(u, np.ndarray) and u.dtype == np.float64 and u.flags.c_contiguous):
+        raise TypeError("links must be a C-contiguous float64 numpy array")
+    if u.shape[-3:] != (3, 3, 2):
+        raise ValueError(f"links must end in (3, 3, 2), got {u.shape}")
+    return u
+
+
+def min8_encode(u) -> np.ndarray:
+    """8 reals per SU(3) link (the row-pivoted minimal representation; see
+    gf_oracle.c): shape (..., 3, 3, 2) -> (..., 8)."""
+    u = _mats(u)
+    out = np.empty(u.shape[:-3] + (8,), dtype=np.float64)
+    lib().oracle_min8_encode(_p(u), u.size // 18, _p(out))
+    return out
+
+
+def min8_decode(p) -> np.ndarray:
+    """The SU(3) links of 8-real parameters: shape (..., 8) -> (..., 3, 3, 2)."""
+    if not (isinstance(p, np.ndarray) and p.dtype == np.float64 and p.flags.c_contiguous and p.shape[-1] == 8):
+        raise TypeError("parameters must be a C-contiguous float64 array ending in 8")
+    out = np.empty(p.shape[:-1] + (3, 3, 2), dtype=np.float64)
+    lib().oracle_min8_decode(_p(p), p.size // 8, _p(out))
+    return out
+
+
+def min8_store(u):
+    """In place: the links a lattice stored in 8 reals per link holds after u was written to it."""
+    u = _mats(u)
+    lib().oracle_min8_store(_p(u), u.size // 18)
+    return u

@@ -51,6 +51,9 @@
  *                            representation of Sec. 3.1 keeps row 2 implicit).
  *   oracle_plaquette ....... the gauge-invariant average plaquette, used to
  *                            check that sweeps stay on the gauge orbit.
+ *   oracle_min8_* .......... the minimal 8-parameter SU(3) representation
+ *                            that Sec. 4.1 names (the paper gives no
+ *                            formulae; see the definition at the functions).
  *   oracle_fp32_floor ...... the float32 rounding floor of theta: Delta(x)
  *                            of the float32 two-row store (Sec. 3.1) with K
  *                            summed in float32, against Delta(x) in float64;
@@ -1303,6 +1306,156 @@ int64_t oracle_su2lat_anneal(double* U, const int32_t* dims, int32_t nsweeps, do
         }
     }
     return capped_total;
+}
+
+/* ------------------------------------------------------------------ */
+/* 8-real storage of an SU(3) link                                     */
+/* ------------------------------------------------------------------ */
+
+/* Sec. 4.1 names the minimal 8-parameter representation of an SU(3) link
+ * among the ones cuLGT2 does not provide; the paper gives no formulae.  The
+ * parameterisation here is the row-pivoted variant of the 8-real
+ * reconstruction of Clark et al. (Comput. Phys. Commun. 181 (2010) 1517),
+ * chosen so that every square root is taken of a quantity >= 1/3 and every
+ * phase is a half-angle tangent (no trigonometric function in the decode):
+ *
+ *   U in SU(3) with rows r0, r1 (r2 = conj(r0 x r1)).
+ *   k = the column of the largest |U_0c| (first maximum), i = k+1, j = k+2
+ *   (mod 3).  Columns are taken in the cyclic order (k, i, j) below.
+ *   p0 + i p1 = U_0i,  p2 + i p3 = U_0j,  p4 = tan(arg(U_0k) / 2),
+ *   so |U_0k| = sqrt(1 - |U_0i|^2 - |U_0j|^2) >= 1/sqrt(3).
+ *   n = sqrt(1 - |U_0j|^2); over (k, i, j)
+ *     e1 = (-conj(U_0i), conj(U_0k), 0) / n,
+ *     e2 = (-U_0k conj(U_0j) / n, -U_0i conj(U_0j) / n, n)
+ *   form an orthonormal basis of the complement of r0 (e2 = conj(r0 x e1)),
+ *   and r1 = alpha e1 + beta e2 with |alpha|^2 + |beta|^2 = 1.
+ *   q = 1 if |beta| > |alpha| (else 0); s = the smaller, b = the larger of the
+ *   two: p5 + i p6 = s, p7 = tan(arg(b) / 2), |b| = sqrt(1 - |s|^2) >= 1/sqrt(2).
+ *   The three bits k (2 bits) and q are the lowest mantissa bits of p0, p1
+ *   (bit 0 and bit 1 of k) and p5 (q); writing them moves those values by at
+ *   most one unit in the last place.
+ *   A half-angle tangent t of the phase c + i s: c = (1 - t^2)/(1 + t^2),
+ *   s = 2t/(1 + t^2); t is formed as Im/(|z| + Re) for Re >= 0 and as
+ *   (|z| - Re)/Im otherwise (no cancellation either way), and held to
+ *   |t| <= 1e150 (the phase pi).
+ * A float64 site update then moves 8 links x 8 reals x 8 B x 2 = 1024 B. */
+
+static double tan_half_arg(cx z)
+{
+    const double a = cabs(z), re = creal(z), im = cimag(z);
+    double t = re >= 0.0 ? im / (a + re) : (a - re) / im;
+    if (!(fabs(t) <= 1e150)) t = im < 0.0 || (im == 0.0 && signbit(im)) ? -1e150 : 1e150;
+    return t;
+}
+
+static cx phase_of_tan_half(double t)
+{
+    const double d = 1.0 + t * t;
+    return (1.0 - t * t) / d + I * (2.0 * t / d);
+}
+
+static double with_low_bit(double v, int bit)
+{
+    uint64_t w;
+    memcpy(&w, &v, sizeof w);
+    w = (w & ~(uint64_t)1) | (uint64_t)(bit & 1);
+    memcpy(&v, &w, sizeof v);
+    return v;
+}
+
+static int low_bit(double v)
+{
+    uint64_t w;
+    memcpy(&w, &v, sizeof w);
+    return (int)(w & 1u);
+}
+
+/* rows r0, r1 of an SU(3) matrix (columns in natural order) -> 8 reals */
+static void min8_encode_link(const cx* u, double* p)
+{
+    const cx* r0 = u;
+    const cx* r1 = u + 3;
+    int k = 0;
+    for (int c = 1; c < 3; ++c)
+        if (cabs(r0[c]) > cabs(r0[k])) k = c;
+    const int i = (k + 1) % 3, j = (k + 2) % 3;
+    const cx ak = r0[k], ai = r0[i], aj = r0[j];
+    const double n = sqrt(1.0 - creal(aj * conj(aj)));
+    /* e1, e2 as above, indexed by the natural column */
+    cx e1[3], e2[3];
+    e1[k] = -conj(ai) / n;
+    e1[i] = conj(ak) / n;
+    e1[j] = 0.0;
+    e2[k] = -ak * conj(aj) / n;
+    e2[i] = -ai * conj(aj) / n;
+    e2[j] = n;
+    cx alpha = 0.0, beta = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        alpha += conj(e1[c]) * r1[c];
+        beta += conj(e2[c]) * r1[c];
+    }
+    const int q = cabs(beta) > cabs(alpha);
+    const cx sm = q ? alpha : beta, big = q ? beta : alpha;
+    p[0] = with_low_bit(creal(ai), k & 1);
+    p[1] = with_low_bit(cimag(ai), k >> 1);
+    p[2] = creal(aj);
+    p[3] = cimag(aj);
+    p[4] = tan_half_arg(ak);
+    p[5] = with_low_bit(creal(sm), q);
+    p[6] = cimag(sm);
+    p[7] = tan_half_arg(big);
+}
+
+/* 8 reals -> the full SU(3) matrix (3 rows) */
+static void min8_decode_link(const double* p, cx* u)
+{
+    const int k = low_bit(p[0]) | (low_bit(p[1]) << 1);
+    const int q = low_bit(p[5]);
+    const int i = (k + 1) % 3, j = (k + 2) % 3;
+    const cx ai = p[0] + I * p[1];
+    const cx aj = p[2] + I * p[3];
+    const double rho = sqrt(fmax(0.0, 1.0 - creal(ai * conj(ai)) - creal(aj * conj(aj))));
+    const cx ak = rho * phase_of_tan_half(p[4]);
+    const double n = sqrt(1.0 - creal(aj * conj(aj)));
+    const cx sm = p[5] + I * p[6];
+    const cx big = sqrt(fmax(0.0, 1.0 - creal(sm * conj(sm)))) * phase_of_tan_half(p[7]);
+    const cx alpha = q ? sm : big, beta = q ? big : sm;
+    cx* r0 = u;
+    cx* r1 = u + 3;
+    cx* r2 = u + 6;
+    r0[k] = ak;
+    r0[i] = ai;
+    r0[j] = aj;
+    r1[k] = alpha * (-conj(ai) / n) + beta * (-ak * conj(aj) / n);
+    r1[i] = alpha * (conj(ak) / n) + beta * (-ai * conj(aj) / n);
+    r1[j] = beta * n;
+    r2[0] = conj(r0[1] * r1[2] - r0[2] * r1[1]);
+    r2[1] = conj(r0[2] * r1[0] - r0[0] * r1[2]);
+    r2[2] = conj(r0[0] * r1[1] - r0[1] * r1[0]);
+}
+
+/* nlinks canonical links (18 reals each) -> 8 reals each */
+void oracle_min8_encode(const double* U, int64_t nlinks, double* P)
+{
+    for (int64_t l = 0; l < nlinks; ++l) min8_encode_link((const cx*)(U + (size_t)l * 18), P + (size_t)l * 8);
+}
+
+/* nlinks x 8 reals -> canonical links */
+void oracle_min8_decode(const double* P, int64_t nlinks, double* U)
+{
+    for (int64_t l = 0; l < nlinks; ++l) min8_decode_link(P + (size_t)l * 8, (cx*)(U + (size_t)l * 18));
+}
+
+/* The configuration a lattice stored in 8 reals per link holds after the
+ * links U were written to it: decode(encode(U)) per link, in place. */
+void oracle_min8_store(double* U, int64_t nlinks)
+{
+    for (int64_t l = 0; l < nlinks; ++l) {
+        double p[8];
+        cx* u = (cx*)(U + (size_t)l * 18);
+        min8_encode_link(u, p);
+        min8_decode_link(p, u);
+    }
 }
 
 int oracle_num_threads(void)
