@@ -10,7 +10,8 @@ HBM.  Prints one JSON line.
 Extra legs (reported inside the same line; each has a --no-... switch): the
 float32 sweep rate; the float64 sweep on the 48^3 x 96 lattice (4.08 GB of
 links, far above the 256 MB Infinity Cache: the HBM-only bandwidth point);
-the 32^4 run to theta < 1e-12 in float64 and in mixed precision (capped; also
+the float64 sweeps of both lattices with links stored in 8 reals (the minimal
+representation, 1024 B per site update); the 32^4 run to theta < 1e-12 in float64 and in mixed precision (capped; also
 on a smoother input of the same generator, eps = 0.6, which converges); the
 8^4 convergence workload in float64 and mixed precision; the 64-lattice
 batched workload (mixed-precision pool vs float64 one lattice at a time); the
@@ -44,7 +45,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, AMD published peak
-BYTES_PER_SITE = {"f64": 1536, "f32": 768}  # 8 links x 12 reals, read + write
+BYTES_PER_SITE = {"f64": 1536, "f32": 768,  # 8 links x 12 reals, read + write
+                  "f64_min8": 1024}  # 8 links x 8 reals (minimal representation), read + write
 # Floating-point operations of one overrelaxation site update as the kernel computes it
 # (K tracked through the subgroups; exact power; add, sub, mul = 1, FMA = 2, sqrt, div,
 # atan2, sin, cos = 1 each): row 2 of 8 links 8 x 42 = 336, K from 8 leaves 7 x 18 = 126,
@@ -316,29 +318,36 @@ def serving_leg(gf, inputs, stream, args):
 def fullsize_f64_leg(gf, torch, stream, u, args):
     """Float64 overrelaxation sweep on 48^3 x 96 (eps = 1.0, seed 0): 4.08 GB of links against a
     256 MB Infinity Cache, so the half-sweep streams from HBM: the clean bandwidth point."""
-    dims = FULL_DIMS
+    return sweep_leg(gf, torch, stream, u, FULL_DIMS, args, args.full_steps, 12, "eps=1.0, seed 0",
+                     TRAFFIC_FILE_48)
+
+
+def sweep_leg(gf, torch, stream, u, dims, args, steps, storage, input_name, traffic_file=None):
+    """Tune, warm up and time `steps` float64 overrelaxation sweeps of one lattice whose links are
+    stored in `storage` reals (12: two rows; 8: the minimal representation)."""
     V = u.shape[0]
-    with gf.Lattice(dims, gf.GF_FP64, stream=stream) as lat:
+    name = "x".join(map(str, dims))
+    with gf.Lattice(dims, gf.GF_FP64, stream=stream, storage=storage) as lat:
         lat.set_links(u)
         (tps, block, nt, minw), table = lat.autotune(gf.GF_FP64, n_sweeps=3)
-        log(f"fullsize fp64 autotune: tps={tps} block={block} cache policy={nt} min waves={minw}")
+        log(f"{name} fp64/{storage} autotune: tps={tps} block={block} cache policy={nt} min waves={minw}")
         with torch.cuda.stream(stream):
             lat.sweep(args.warmup, args.omega, args.mode)
-            total, wall, per_launch = time_run(lat, torch, stream, args.full_steps, args.omega, args.mode,
-                                               args.chunk)
+            total, wall, per_launch = time_run(lat, torch, stream, steps, args.omega, args.mode, args.chunk)
         th, F = lat.measure()
-    rate = V * args.full_steps / total
-    launch_bytes = (V // 2) * BYTES_PER_SITE["f64"]
+    rate = V * steps / total
+    bps = BYTES_PER_SITE["f64"] if storage == 12 else BYTES_PER_SITE["f64_min8"]
+    launch_bytes = (V // 2) * bps
     achieved = launch_bytes / per_launch / 1e9
-    log(f"fullsize fp64: {args.full_steps} sweeps in {total * 1e3:.1f} ms (mean half-sweep {per_launch * 1e6:.1f} us, "
+    log(f"{name} fp64/{storage}: {steps} sweeps in {total * 1e3:.1f} ms (mean half-sweep {per_launch * 1e6:.1f} us, "
         f"{achieved:.0f} GB/s)")
     return {
-        "workload": "SU(3) Landau OR sweep, 48x48x48x96 periodic, eps=1.0, seed 0, omega=%g, %s power, FP64 "
-                    "12-real links" % (args.omega, "exact" if args.mode == 0 else "binomial"),
-        "steps": args.full_steps,
+        "workload": "SU(3) Landau OR sweep, %s periodic, %s, omega=%g, %s power, FP64 %d-real links" % (
+            name, input_name, args.omega, "exact" if args.mode == 0 else "binomial", storage),
+        "steps": steps,
         "value": rate,
         "unit": "site-updates/s",
-        "ms_per_step": total * 1e3 / args.full_steps,
+        "ms_per_step": total * 1e3 / steps,
         "gflops": rate * FLOPS_PER_SITE_UPDATE / 1e9,
         "threads_per_site": tps, "block": block, "nontemporal": nt, "min_waves": minw,
         "tuning_us_per_sweep": [[t, b, c, w, round(us, 1)] for (t, b, c, w, us) in table],
@@ -348,14 +357,27 @@ def fullsize_f64_leg(gf, torch, stream, u, args):
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": committed_traffic(TRAFFIC_FILE_48),
-            "kernel": "k_or_half_sweep<double, TPS=%d, exact, BLOCK=%d, cache policy %d%s>" % (
-                tps, block, nt, ", 2 waves/SIMD" if minw == 2 else ""),
+            "traffic": committed_traffic(traffic_file) if traffic_file else None,
+            "kernel": "k_or_half_sweep<double, TPS=%d, exact, BLOCK=%d, cache policy %d%s%s>" % (
+                tps, block, nt, ", 2 waves/SIMD" if minw == 2 else "", ", 8-real links" if storage == 8 else ""),
             "algorithmic_bytes_per_launch": launch_bytes,
+            "bytes_per_site_update": bps,
             "mean_launch_us": per_launch * 1e6,
         },
         "checks": {"theta_after": th, "F_after": F},
     }
+
+
+def min8_legs(gf, torch, stream, links, dims, full, args):
+    """Beside the 12-real figures: the same float64 sweeps with links stored in 8 reals (1024 B per
+    site update instead of 1536 B), on the bandwidth lattice and on 48^3 x 96."""
+    out = {"bytes_per_site_update": BYTES_PER_SITE["f64_min8"]}
+    out["bandwidth_lattice"] = sweep_leg(gf, torch, stream, links, dims, args, args.steps, 8,
+                                         f"eps={args.eps}, seed {args.seed}")
+    if full is not None:
+        out["fullsize_48x96"] = sweep_leg(gf, torch, stream, full, FULL_DIMS, args, args.full_steps, 8,
+                                          "eps=1.0, seed 0")
+    return out
 
 
 def fullsize_leg(gf, torch, stream, u, args):
@@ -511,6 +533,8 @@ def main(argv=None):
     ap.add_argument("--chunk", type=int, default=10,
                     help="sweeps per gf_sweep_or call in the timed region (>= 2: replayed hipGraph; 1: direct launches)")
     ap.add_argument("--no-fix", action="store_true", help="skip the runs to theta < 1e-12 (32^4 and 8^4)")
+    ap.add_argument("--no-min8", action="store_true",
+                    help="skip the float64 sweeps with links stored in 8 reals (bandwidth lattice and 48^3x96)")
     ap.add_argument("--batched", action="store_true", help="(the batched leg runs by default; kept for scripts)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-lattice batched workload")
     ap.add_argument("--batched-fp64-pool", action="store_true", help="also run the batched jobs in a float64 pool")
@@ -708,9 +732,13 @@ def main(argv=None):
             "note": "201 MB of FP32 links fit in the 256 MB Infinity Cache, so this can exceed HBM peak",
         }
     line["tuning_us_per_sweep"] = tuning or None
+    full = None
     if not args.no_fullsize:
         full = inputs.get(FULL_DIMS, 1.0, 0)
         line["fullsize_48x96_f64"] = fullsize_f64_leg(gf, torch, stream, full, args)
+    if not args.no_min8:
+        line["f64_min8"] = min8_legs(gf, torch, stream, links, dims, full, args)
+    del full
     fix8 = None
     if not args.no_fix:
         line["fix_until_theta_1e-12"] = fix_until_leg(gf, torch, stream, links, dims, args, args.eps)

@@ -125,6 +125,35 @@ gf_status gf_create_lattice_su2(const int32_t dims[4], gf_prec prec, void* hip_s
 /* N_c of the lattice's gauge group: 3 (gf_create_lattice) or 2 (gf_create_lattice_su2). */
 gf_status gf_lattice_group(gf_lattice lat, int32_t* nc);
 
+/* An SU(3) float64 lattice whose links are stored in 8 reals: the minimal
+ * 8-parameter representation that Sec. 4.1 names among those cuLGT2 does
+ * not provide (the paper gives no formulae).  The parameterisation is a
+ * row-pivoted form of the 8-real reconstruction of Clark et al. (Comput.
+ * Phys. Commun. 181 (2010) 1517): with k the column of the largest |U_0c|
+ * and i, j the next two columns cyclically, the stored reals are U_0i, U_0j,
+ * tan(arg U_0k / 2), and row 1's coordinates (alpha, beta) in an orthonormal
+ * basis of row 0's complement as the smaller of the two plus the half-angle
+ * tangent of the larger's phase; k and which of alpha, beta is larger ride in
+ * the lowest mantissa bits of three stored reals (each moved by at most one
+ * unit in the last place).  Every square root in the decode is taken of a
+ * quantity >= 1/3, so a stored link is SU(3) to float64 rounding.  Same
+ * checkerboard, site-fastest tiled layout as the 12-real field with 4
+ * chunks of 16 B per link: 64 B per link, a site update moves 1024 B instead
+ * of 1536 B, at the cost of a decode per link load and an encode per store.
+ * Every entry point taking a lattice accepts it, with these differences:
+ *   - gf_set_links stores the projection of rows 0, 1 of each link onto
+ *     SU(3) (the link itself for an SU(3) matrix, to rounding);
+ *   - gf_reunitarize does nothing: every store re-projects onto SU(3);
+ *   - sweep configurations as for GF_FP64 with min_waves 0 (gf_autotune
+ *     times those; kernel GF_FP64);
+ *   - gf_tune_switch: GF_E_STATE (no float32 phase).
+ * Otherwise as gf_create_lattice(dims, GF_FP64, ...). */
+gf_status gf_create_lattice_min8(const int32_t dims[4], void* hip_stream, gf_lattice* out);
+
+/* Reals stored per link: 12 (SU(3), two rows), 8 (gf_create_lattice_min8) or
+ * 4 (SU(2) quaternion). */
+gf_status gf_lattice_storage(gf_lattice lat, int32_t* reals_per_link);
+
 /* Free every device buffer of the lattice (waits for its stream).  NULL is accepted. */
 gf_status gf_destroy_lattice(gf_lattice lat);
 

@@ -88,12 +88,13 @@ gf_status check_dims(const int32_t dims[4], int64_t* V)
 // Device allocations of a lattice of geometry g and precision prec (sizes of
 // the buffers gf_create_lattice allocates; the pool's admission budget counts
 // exactly these).
-LatticeSizes lattice_sizes(const Geom& g, gf_prec prec, int group)
+LatticeSizes lattice_sizes(const Geom& g, gf_prec prec, int group, bool min8)
 {
     LatticeSizes z;
     const size_t nchunks = (size_t)2 * 4 * g.ld;  // per chunk slot
     const bool su2 = group == 2;
-    if (prec == GF_FP64 || prec == GF_MIXED) z.f64 = nchunks * (su2 ? 2 : 6) * sizeof(double2);
+    const size_t c64 = su2 ? 2 : (min8 ? (size_t)gf::kMin8Chunks : 6);
+    if (prec == GF_FP64 || prec == GF_MIXED) z.f64 = nchunks * c64 * sizeof(double2);
     if (prec == GF_FP32 || prec == GF_MIXED) z.f32 = nchunks * (su2 ? 1 : 3) * sizeof(float4);
     if (prec == GF_MIXED) z.gacc = (size_t)2 * 3 * g.ld * sizeof(float4);
     // partial sums of the whole-lattice reductions, or of the per-timeslice
@@ -108,6 +109,11 @@ LatticeSizes lattice_sizes(const Geom& g, gf_prec prec, int group)
 LinkField<double> field64(const gf_lattice_* L)
 {
     return LinkField<double>{L->f64, L->geom.ld};
+}
+
+Link8Field field8(const gf_lattice_* L)
+{
+    return Link8Field{L->f64, L->geom.ld};
 }
 
 LinkField<float> field32(const gf_lattice_* L)
@@ -160,7 +166,9 @@ gf_status do_half_sweep(gf_lattice L, int parity, double omega, int mode)
             GF_HIP(gf::launch_su2_or(su2_64(L), L->geom, parity, omega, mode, L->cfg64, L->stream, L->gauge, nullptr));
         return GF_OK;
     }
-    if (is_fp32(L))
+    if (L->min8)
+        GF_HIP(gf::launch_or_half_sweep(field8(L), L->geom, parity, omega, mode, L->cfg64, L->stream, L->gauge));
+    else if (is_fp32(L))
         GF_HIP(gf::launch_or_half_sweep(field32(L), L->geom, parity, (float)omega, mode, L->cfg32, g_tracking(L),
                                         L->stream, L->gauge));
     else
@@ -192,7 +200,7 @@ gf_status do_sweeps(gf_lattice L, int32_t n, double omega, int mode)
     if (n < 2 || L->stream == nullptr || L->geom.vh >= kGraphMaxHalfSites) return launch_sweeps(L, n, omega, mode);
     const bool fp32 = is_fp32(L);
     const SweepConfig& c = fp32 ? L->cfg32 : L->cfg64;
-    const int kind = (fp32 ? (g_tracking(L).base ? 2 : 1) : 0) + 4 * L->gauge + 8 * (L->group == 2);
+    const int kind = (fp32 ? (g_tracking(L).base ? 2 : 1) : 0) + 4 * L->gauge + 8 * (L->group == 2) + 16 * L->min8;
     const auto key = std::make_tuple(n, omega, mode, kind, c.tps, c.block, c.nt + 4 * c.minw);
     auto it = L->sweep_graphs.find(key);
     if (it == L->sweep_graphs.end()) {
@@ -218,6 +226,9 @@ gf_status do_sweeps(gf_lattice L, int32_t n, double omega, int mode)
 
 gf_status do_reunitarize(gf_lattice L)
 {
+    // 8-real links decode to SU(3) to rounding and are re-encoded from rows 0
+    // and 1 at every store: they are reunitarised at every sweep already
+    if (L->min8) return GF_OK;
     if (L->group == 2) {
         if (is_fp32(L))
             GF_HIP(gf::launch_su2_reunitarize(su2_32(L), L->geom, L->stream));
@@ -253,6 +264,8 @@ gf_status do_measure_slices(gf_lattice L, double* theta, double* F)
         GF_HIP(gf::launch_su2_measure(su2_32(L), L->geom, gf::GAUGE_COULOMB, L->partial, L->dslices, L->stream));
     else if (L->group == 2)
         GF_HIP(gf::launch_su2_measure(su2_64(L), L->geom, gf::GAUGE_COULOMB, L->partial, L->dslices, L->stream));
+    else if (L->min8)
+        GF_HIP(gf::launch_measure_slices(field8(L), L->geom, L->partial, L->dslices, L->stream));
     else if (is_fp32(L))
         GF_HIP(gf::launch_measure_slices(field32(L), L->geom, L->partial, L->dslices, L->stream));
     else
@@ -282,6 +295,8 @@ gf_status do_measure(gf_lattice L, double* theta, double* F)
         GF_HIP(gf::launch_su2_measure(su2_32(L), L->geom, gf::GAUGE_LANDAU, L->partial, L->dres, L->stream));
     else if (L->group == 2)
         GF_HIP(gf::launch_su2_measure(su2_64(L), L->geom, gf::GAUGE_LANDAU, L->partial, L->dres, L->stream));
+    else if (L->min8)
+        GF_HIP(gf::launch_measure(field8(L), L->geom, L->partial, L->dres, L->stream));
     else if (is_fp32(L))
         GF_HIP(gf::launch_measure(field32(L), L->geom, L->partial, L->dres, L->stream));
     else
@@ -322,6 +337,9 @@ gf_status do_est_sweep(gf_lattice L, double omega, int mode, double* theta_est)
                                      L->est));
         else if (su2)
             GF_HIP(gf::launch_su2_or(su2_64(L), L->geom, parity, omega, mode, L->cfg64, L->stream, L->gauge, L->est));
+        else if (L->min8)
+            GF_HIP(gf::launch_or_half_sweep(field8(L), L->geom, parity, omega, mode, L->cfg64, L->stream, L->gauge,
+                                            L->est));
         else if (is_fp32(L))
             GF_HIP(gf::launch_or_half_sweep(field32(L), L->geom, parity, (float)omega, mode, L->cfg32, g_tracking(L),
                                             L->stream, L->gauge, L->est));
@@ -342,6 +360,7 @@ gf_status do_est_sweep(gf_lattice L, double omega, int mode, double* theta_est)
 gf_status do_fp32_floor(gf_lattice L, double* floor)
 {
     if (L->group == 2) return fail(GF_E_STATE, "the float32 floor is defined for SU(3) lattices");
+    if (L->min8) return fail(GF_E_STATE, "the float32 floor is defined for 12-real (two-row) links");
     if (!L->f64) return fail(GF_E_STATE, "the float32 floor needs float64 links (GF_FP64 or GF_MIXED lattice)");
     GF_HIP(gf::launch_fp32_floor(field64(L), L->geom, L->partial, L->dres, L->stream));
     GF_HIP(hipMemcpyAsync(L->hres, L->dres, sizeof(double), hipMemcpyDeviceToHost, L->stream));
@@ -374,7 +393,10 @@ gf_status upload_canonical(gf_lattice L, const double* dev_canon)
         return GF_OK;
     }
     if (L->f32) GF_HIP(gf::launch_pack(dev_canon, field32(L), L->geom, L->stream));
-    if (L->f64) GF_HIP(gf::launch_pack(dev_canon, field64(L), L->geom, L->stream));
+    if (L->f64 && L->min8)
+        GF_HIP(gf::launch_pack(dev_canon, field8(L), L->geom, L->stream));
+    else if (L->f64)
+        GF_HIP(gf::launch_pack(dev_canon, field64(L), L->geom, L->stream));
     if (L->gacc.base) GF_HIP(gf::launch_g_identity(L->gacc, L->geom, L->stream));
     L->phase = 0;
     L->has_links = true;
@@ -391,7 +413,9 @@ gf_status download_canonical(gf_lattice L, double* dev_canon)
             GF_HIP(gf::launch_su2_unpack(su2_64(L), L->geom, dev_canon, L->stream));
         return GF_OK;
     }
-    if (is_fp32(L))
+    if (L->min8)
+        GF_HIP(gf::launch_unpack(field8(L), L->geom, dev_canon, L->stream));
+    else if (is_fp32(L))
         GF_HIP(gf::launch_unpack(field32(L), L->geom, dev_canon, L->stream));
     else
         GF_HIP(gf::launch_unpack(field64(L), L->geom, dev_canon, L->stream));
@@ -441,7 +465,8 @@ const char* gf_version(void)
 
 namespace {
 
-gf_status create_lattice(const int32_t dims[4], gf_prec prec, int group, void* hip_stream, gf_lattice* out)
+gf_status create_lattice(const int32_t dims[4], gf_prec prec, int group, bool min8, void* hip_stream,
+                         gf_lattice* out)
 {
     if (!dims || !out) return fail(GF_E_ARG, "null argument");
     *out = nullptr;
@@ -457,6 +482,7 @@ gf_status create_lattice(const int32_t dims[4], gf_prec prec, int group, void* h
     for (int m = 0; m < 4; ++m) L->dims[m] = dims[m];
     L->prec = prec;
     L->group = group;
+    L->min8 = min8;
     L->stream = (hipStream_t)hip_stream;
     L->volume = V;
 
@@ -466,7 +492,7 @@ gf_status create_lattice(const int32_t dims[4], gf_prec prec, int group, void* h
         return fail(GF_E_ARG, "internal: index division check failed");
     }
 
-    const LatticeSizes z = lattice_sizes(g, prec, group);
+    const LatticeSizes z = lattice_sizes(g, prec, group, min8);
     hipError_t e = hipSuccess;
     if (z.f64) e = hipMalloc((void**)&L->f64, z.f64);
     if (e == hipSuccess && z.f32) e = hipMalloc((void**)&L->f32, z.f32);
@@ -507,12 +533,24 @@ gf_status create_lattice(const int32_t dims[4], gf_prec prec, int group, void* h
 
 gf_status gf_create_lattice(const int32_t dims[4], gf_prec prec, void* hip_stream, gf_lattice* out)
 {
-    return create_lattice(dims, prec, 3, hip_stream, out);
+    return create_lattice(dims, prec, 3, false, hip_stream, out);
 }
 
 gf_status gf_create_lattice_su2(const int32_t dims[4], gf_prec prec, void* hip_stream, gf_lattice* out)
 {
-    return create_lattice(dims, prec, 2, hip_stream, out);
+    return create_lattice(dims, prec, 2, false, hip_stream, out);
+}
+
+gf_status gf_create_lattice_min8(const int32_t dims[4], void* hip_stream, gf_lattice* out)
+{
+    return create_lattice(dims, GF_FP64, 3, true, hip_stream, out);
+}
+
+gf_status gf_lattice_storage(gf_lattice L, int32_t* reals_per_link)
+{
+    if (!L || !reals_per_link) return fail(GF_E_ARG, "null argument");
+    *reals_per_link = L->group == 2 ? 4 : (L->min8 ? 8 : 12);
+    return GF_OK;
 }
 
 gf_status gf_lattice_group(gf_lattice L, int32_t* nc)
@@ -560,6 +598,8 @@ gf_status set_config(gf_lattice L, gf_prec kernel, int32_t tps, int32_t block, i
                     "256 or 512 (not 512 with tps 1), cache policy 0, 1 or 2 (1 and 2 only with tps <= 4 and block "
                     "<= 256), min_waves 0 or 2 (2 only with tps 1)",
                     tps, block, nontemporal, min_waves);
+    if (L->min8 && min_waves != 0)
+        return fail(GF_E_ARG, "8-real links: min_waves must be 0 (the register cap is an axis of the 12-real kernel)");
     if (heat_bath)
         (kernel == GF_FP32 ? L->cfg_hb32 : L->cfg_hb64) = c;
     else
@@ -680,6 +720,9 @@ gf_status gf_anneal(gf_lattice L, int32_t n_sweeps, double T_start, double T_end
             else if (L->group == 2)
                 GF_HIP(gf::launch_su2_hb(su2_64(L), L->geom, parity, T, seed, sweep, L->cfg_hb64, L->stream,
                                          L->gauge));
+            else if (L->min8)
+                GF_HIP(gf::launch_hb_half_sweep(field8(L), L->geom, parity, T, seed, sweep, L->cfg_hb64, L->stream,
+                                                L->gauge));
             else if (is_fp32(L))
                 GF_HIP(gf::launch_hb_half_sweep(field32(L), L->geom, parity, (float)T, seed, sweep, L->cfg_hb32,
                                                 g_tracking(L), L->stream, L->gauge));
@@ -772,6 +815,8 @@ gf_status gf_plaquette(gf_lattice L, double* P)
         GF_HIP(gf::launch_su2_plaquette(su2_32(L), L->geom, L->partial, L->dres, L->stream));
     else if (L->group == 2)
         GF_HIP(gf::launch_su2_plaquette(su2_64(L), L->geom, L->partial, L->dres, L->stream));
+    else if (L->min8)
+        GF_HIP(gf::launch_plaquette(field8(L), L->geom, L->partial, L->dres, L->stream));
     else if (is_fp32(L))
         GF_HIP(gf::launch_plaquette(field32(L), L->geom, L->partial, L->dres, L->stream));
     else

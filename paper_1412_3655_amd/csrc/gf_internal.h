@@ -31,6 +31,7 @@ struct gf_lattice_ {
     double* hslices = nullptr;              // pinned host copy of dslices
     int gauge = gf::GAUGE_LANDAU;           // functional: GAUGE_LANDAU or GAUGE_COULOMB
     int group = 3;                          // gauge group SU(3) or SU(2); f64 / f32 hold quaternions for SU(2)
+    bool min8 = false;                      // SU(3) float64 links stored in 8 reals (f64 holds a Link8Field)
     double* est = nullptr;                  // per-block sums of a sweep's theta estimate (allocated on use)
     size_t est_cap = 0;                     // doubles held by est
     bool adaptive = false;                  // gf_fix_until: exact measurement only near a decision
@@ -75,7 +76,7 @@ struct LatticeSizes {
     int64_t total = 0;  // every device byte the lattice holds
 };
 
-LatticeSizes lattice_sizes(const Geom& g, gf_prec prec, int group = 3);
+LatticeSizes lattice_sizes(const Geom& g, gf_prec prec, int group = 3, bool min8 = false);
 Su2Field<double> su2_64(const gf_lattice_* L);
 Su2Field<float> su2_32(const gf_lattice_* L);
 // Doubles per link of the canonical host / device arrays (18 for SU(3), 8 for SU(2)).
@@ -87,6 +88,7 @@ bool make_fastdiv(uint32_t d, uint32_t limit, FastDiv* out);
 bool make_geom(const int32_t dims[4], Geom* out);
 gf_status check_dims(const int32_t dims[4], int64_t* V);
 LinkField<double> field64(const gf_lattice_* L);
+Link8Field field8(const gf_lattice_* L);
 LinkField<float> field32(const gf_lattice_* L);
 bool is_fp32(const gf_lattice_* L);
 GField g_tracking(const gf_lattice_* L);

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "gf_device.h"
+#include "gf_min8.h"
 
 namespace gf {
 
@@ -72,6 +73,18 @@ hipError_t launch_hb_half_sweep_coulomb(const LinkField<float>& f, const Geom& g
                                         uint64_t seed, uint32_t sweep, const SweepConfig& cfg, const GField& gacc,
                                         hipStream_t st);
 
+// Float64 links stored in 8 reals (gf_min8.h): the same sweeps, decoding on
+// load and encoding on store; est as above.
+hipError_t launch_or_half_sweep(const Link8Field& f, const Geom& g, int parity, double omega, int mode,
+                                const SweepConfig& cfg, hipStream_t st, int gauge = GAUGE_LANDAU,
+                                double* est = nullptr);
+hipError_t launch_hb_half_sweep(const Link8Field& f, const Geom& g, int parity, double T, uint64_t seed,
+                                uint32_t sweep, const SweepConfig& cfg, hipStream_t st, int gauge = GAUGE_LANDAU);
+hipError_t launch_or_half_sweep_min8_coulomb(const Link8Field& f, const Geom& g, int parity, double omega, int mode,
+                                             const SweepConfig& cfg, hipStream_t st, double* est);
+hipError_t launch_or_half_sweep_min8_est(const Link8Field& f, const Geom& g, int parity, double omega, int mode,
+                                         const SweepConfig& cfg, hipStream_t st, double* est, int gauge);
+
 // theta / F: per-block partial sums (2 doubles per block) then one finalize
 // block; out[0] = theta, out[1] = F.  partial must hold measure_partials(g).
 uint32_t measure_blocks(const Geom& g);
@@ -107,6 +120,14 @@ hipError_t launch_plaquette(const LinkField<float>& f, const Geom& g, double* pa
 // Gram-Schmidt of rows 0, 1 of every link.
 hipError_t launch_reunitarize(const LinkField<double>& f, const Geom& g, hipStream_t st);
 hipError_t launch_reunitarize(const LinkField<float>& f, const Geom& g, hipStream_t st);
+
+// The reductions and layout conversion of float64 links stored in 8 reals
+// (pack encodes, unpack decodes).
+hipError_t launch_measure(const Link8Field& f, const Geom& g, double* partial, double* out, hipStream_t st);
+hipError_t launch_measure_slices(const Link8Field& f, const Geom& g, double* partial, double* out, hipStream_t st);
+hipError_t launch_plaquette(const Link8Field& f, const Geom& g, double* partial, double* out, hipStream_t st);
+hipError_t launch_pack(const double* canon, const Link8Field& f, const Geom& g, hipStream_t st);
+hipError_t launch_unpack(const Link8Field& f, const Geom& g, double* canon, hipStream_t st);
 
 // Canonical float64 [site][mu][3][3][2] (device) <-> device layout.
 hipError_t launch_pack(const double* canon, const LinkField<double>& f, const Geom& g, hipStream_t st);

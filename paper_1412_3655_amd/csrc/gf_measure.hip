@@ -61,8 +61,8 @@ __global__ void __launch_bounds__(RBLOCK) k_finalize_slices(const double* partia
 }
 
 // Re tr[U_mu(x) U_nu(x+mu^) U_mu(x+nu^)^dag U_nu(x)^dag] summed over mu < nu.
-template <typename R>
-__global__ void __launch_bounds__(RBLOCK) k_plaquette(LinkField<R> f, Geom g, double* partial)
+template <typename Field>
+__global__ void __launch_bounds__(RBLOCK) k_plaquette(Field f, Geom g, double* partial)
 {
     const int parity = blockIdx.y;
     const uint32_t h = blockIdx.x * RBLOCK + threadIdx.x;
@@ -278,8 +278,10 @@ __device__ __forceinline__ void lex_to_half(const Geom& g, uint32_t s, int* pari
     *h = s >> 1;
 }
 
-template <typename R>
-__global__ void __launch_bounds__(RBLOCK) k_pack(const double* canon, LinkField<R> f, Geom g)
+// R: the field's real type; Field: 12-real LinkField<R> or 8-real Link8Field
+// (rows 0 and 1 of the canonical link are encoded).
+template <typename R, typename Field>
+__global__ void __launch_bounds__(RBLOCK) k_pack(const double* canon, Field f, Geom g)
 {
     const uint64_t gid = (uint64_t)blockIdx.x * RBLOCK + threadIdx.x;
     const uint64_t nlinks = (uint64_t)g.vh * 8;
@@ -298,11 +300,11 @@ __global__ void __launch_bounds__(RBLOCK) k_pack(const double* canon, LinkField<
             u.re[i][j] = (R)src[(i * 3 + j) * 2];
             u.im[i][j] = (R)src[(i * 3 + j) * 2 + 1];
         }
-    store_rows01(f, parity, mu, h, u);
+    store_link(f, parity, mu, h, u);
 }
 
-template <typename R>
-__global__ void __launch_bounds__(RBLOCK) k_unpack(LinkField<R> f, Geom g, double* canon)
+template <typename Field>
+__global__ void __launch_bounds__(RBLOCK) k_unpack(Field f, Geom g, double* canon)
 {
     const uint64_t gid = (uint64_t)blockIdx.x * RBLOCK + threadIdx.x;
     const uint64_t nlinks = (uint64_t)g.vh * 8;
@@ -346,23 +348,22 @@ uint32_t slice_blocks(const Geom& g)
     return 2 * ((g.hs3 + RBLOCK - 1) / RBLOCK);
 }
 
-template <typename R>
-hipError_t measure_slices_impl(const LinkField<R>& f, const Geom& g, double* partial, double* out, hipStream_t st)
+template <typename Field>
+hipError_t measure_slices_impl(const Field& f, const Geom& g, double* partial, double* out, hipStream_t st)
 {
     const uint32_t nb = slice_blocks(g);
-    hipLaunchKernelGGL((k_measure_slices<LinkField<R>>), dim3(nb, (uint32_t)g.n[3]), dim3(RBLOCK), 0, st, f, g,
-                       partial);
+    hipLaunchKernelGGL((k_measure_slices<Field>), dim3(nb, (uint32_t)g.n[3]), dim3(RBLOCK), 0, st, f, g, partial);
     const double V3 = 2.0 * (double)g.hs3;
     hipLaunchKernelGGL(k_finalize_slices, dim3((uint32_t)g.n[3]), dim3(RBLOCK), 0, st, partial, nb,
                        1.0 / (3.0 * V3), 1.0 / (9.0 * V3), out);
     return hipGetLastError();
 }
 
-template <typename R>
-hipError_t plaquette_impl(const LinkField<R>& f, const Geom& g, double* partial, double* out, hipStream_t st)
+template <typename Field>
+hipError_t plaquette_impl(const Field& f, const Geom& g, double* partial, double* out, hipStream_t st)
 {
     const uint32_t nb = site_blocks(g);
-    hipLaunchKernelGGL((k_plaquette<R>), dim3(nb, 2), dim3(RBLOCK), 0, st, f, g, partial);
+    hipLaunchKernelGGL((k_plaquette<Field>), dim3(nb, 2), dim3(RBLOCK), 0, st, f, g, partial);
     const double V = 2.0 * (double)g.vh;
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RBLOCK), 0, st, partial, 2 * nb, 1.0 / (18.0 * V), 0.0, out);
     return hipGetLastError();
@@ -375,19 +376,21 @@ hipError_t reunit_impl(const LinkField<R>& f, const Geom& g, hipStream_t st)
     return hipGetLastError();
 }
 
-template <typename R>
-hipError_t pack_impl(const double* canon, const LinkField<R>& f, const Geom& g, hipStream_t st)
+template <typename R, typename Field>
+hipError_t pack_impl(const double* canon, const Field& f, const Geom& g, hipStream_t st)
 {
     const uint64_t n = (uint64_t)g.vh * 8;
-    hipLaunchKernelGGL((k_pack<R>), dim3((uint32_t)((n + RBLOCK - 1) / RBLOCK)), dim3(RBLOCK), 0, st, canon, f, g);
+    hipLaunchKernelGGL((k_pack<R, Field>), dim3((uint32_t)((n + RBLOCK - 1) / RBLOCK)), dim3(RBLOCK), 0, st, canon, f,
+                       g);
     return hipGetLastError();
 }
 
-template <typename R>
-hipError_t unpack_impl(const LinkField<R>& f, const Geom& g, double* canon, hipStream_t st)
+template <typename Field>
+hipError_t unpack_impl(const Field& f, const Geom& g, double* canon, hipStream_t st)
 {
     const uint64_t n = (uint64_t)g.vh * 8;
-    hipLaunchKernelGGL((k_unpack<R>), dim3((uint32_t)((n + RBLOCK - 1) / RBLOCK)), dim3(RBLOCK), 0, st, f, g, canon);
+    hipLaunchKernelGGL((k_unpack<Field>), dim3((uint32_t)((n + RBLOCK - 1) / RBLOCK)), dim3(RBLOCK), 0, st, f, g,
+                       canon);
     return hipGetLastError();
 }
 
@@ -475,17 +478,38 @@ hipError_t launch_reunitarize(const LinkField<float>& f, const Geom& g, hipStrea
 }
 hipError_t launch_pack(const double* c, const LinkField<double>& f, const Geom& g, hipStream_t st)
 {
-    return pack_impl(c, f, g, st);
+    return pack_impl<double>(c, f, g, st);
 }
 hipError_t launch_pack(const double* c, const LinkField<float>& f, const Geom& g, hipStream_t st)
 {
-    return pack_impl(c, f, g, st);
+    return pack_impl<float>(c, f, g, st);
 }
 hipError_t launch_unpack(const LinkField<double>& f, const Geom& g, double* c, hipStream_t st)
 {
     return unpack_impl(f, g, c, st);
 }
 hipError_t launch_unpack(const LinkField<float>& f, const Geom& g, double* c, hipStream_t st)
+{
+    return unpack_impl(f, g, c, st);
+}
+
+hipError_t launch_measure(const Link8Field& f, const Geom& g, double* p, double* o, hipStream_t st)
+{
+    return measure_impl(f, g, p, o, st);
+}
+hipError_t launch_measure_slices(const Link8Field& f, const Geom& g, double* p, double* o, hipStream_t st)
+{
+    return measure_slices_impl(f, g, p, o, st);
+}
+hipError_t launch_plaquette(const Link8Field& f, const Geom& g, double* p, double* o, hipStream_t st)
+{
+    return plaquette_impl(f, g, p, o, st);
+}
+hipError_t launch_pack(const double* c, const Link8Field& f, const Geom& g, hipStream_t st)
+{
+    return pack_impl<double>(c, f, g, st);
+}
+hipError_t launch_unpack(const Link8Field& f, const Geom& g, double* c, hipStream_t st)
 {
     return unpack_impl(f, g, c, st);
 }

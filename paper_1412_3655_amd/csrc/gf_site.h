@@ -22,7 +22,10 @@
 // group, and each lane applies G to the links it loaded and stores them.
 #pragma once
 
+#include <type_traits>
+
 #include "gf_device.h"
+#include "gf_min8.h"
 
 namespace gf {
 
@@ -294,11 +297,15 @@ __device__ __forceinline__ double delta_norm2(const M3<T>& K)
 // 4, Coulomb 3); all 8 links are transformed either way.  With est, lane 0 of
 // the group returns tr[Delta Delta^dag] of the site's K before the update (the
 // gauge-condition term of the configuration the site sees), every other lane
-// and every call without est 0.
-template <typename R, int TPS, int MODE, bool TRACKG, int CP = 0, int NDIR = NDIR_LANDAU>
-__device__ __forceinline__ double site_update(const LinkField<R>& f, const Geom& g, int parity, uint32_t h, int r,
+// and every call without est 0.  F: the link field, 12 reals per link
+// (LinkField<R>) or float64 in 8 reals (Link8Field, decoded on load and
+// encoded on store).
+template <typename R, int TPS, int MODE, bool TRACKG, int CP = 0, int NDIR = NDIR_LANDAU, typename F = LinkField<R>>
+__device__ __forceinline__ double site_update(const F& f, const Geom& g, int parity, uint32_t h, int r,
                                               const Rule<R>& rule, const GField& gacc, bool est = false)
 {
+    constexpr bool kMin8 = std::is_same<F, Link8Field>::value;
+    static_assert(!kMin8 || (std::is_same<R, double>::value && !TRACKG), "8-real links are float64");
     constexpr int NL = 8 / TPS;
     const Site s = decode_site(g, parity, h);
     const uint32_t lex = 2 * h + (uint32_t)(s.x & 1);
@@ -314,21 +321,32 @@ __device__ __forceinline__ double site_update(const LinkField<R>& f, const Geom&
         bwd[k] = (li & 1) != 0;
         at[k] = bwd[k] ? back_h(g, h, s, mu_of[k]) : h;
     }
+    if constexpr (kMin8) {
+        // every load first, then the decodes (each yields SU(3) to rounding)
+        double2 raw[NL][kMin8Chunks];
 #pragma unroll
-    for (int k = 0; k < NL; ++k) load_rows01<nt_loads(CP)>(f, bwd[k] ? 1 - parity : parity, mu_of[k], at[k], U[k]);
-    // Row 2 is rebuilt from the two stored rows, so a departure d from unitarity
-    // of those rows becomes up to ~2d after an update that mixes the rows.  Every
-    // heat-bath update mixes them strongly (d would grow ~1.35x per sweep), so the
-    // heat bath re-orthonormalises the two rows on load.  Overrelaxation mixes
-    // them little (its subgroup elements approach 1; d grows ~1.004x per sweep on
-    // rough inputs) and relies on the periodic reunitarisation of the fix-until
-    // loop, which keeps its register footprint (and occupancy) unchanged.
-    if constexpr (MODE == HEATBATH) {
+        for (int k = 0; k < NL; ++k)
+            load_min8_raw<nt_loads(CP)>(f, bwd[k] ? 1 - parity : parity, mu_of[k], at[k], raw[k]);
 #pragma unroll
-        for (int k = 0; k < NL; ++k) gram_schmidt_rows01(U[k]);
+        for (int k = 0; k < NL; ++k) decode_min8(raw[k], U[k]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < NL; ++k)
+            load_rows01<nt_loads(CP)>(f, bwd[k] ? 1 - parity : parity, mu_of[k], at[k], U[k]);
+        // Row 2 is rebuilt from the two stored rows, so a departure d from unitarity
+        // of those rows becomes up to ~2d after an update that mixes the rows.  Every
+        // heat-bath update mixes them strongly (d would grow ~1.35x per sweep), so the
+        // heat bath re-orthonormalises the two rows on load.  Overrelaxation mixes
+        // them little (its subgroup elements approach 1; d grows ~1.004x per sweep on
+        // rough inputs) and relies on the periodic reunitarisation of the fix-until
+        // loop, which keeps its register footprint (and occupancy) unchanged.
+        if constexpr (MODE == HEATBATH) {
+#pragma unroll
+            for (int k = 0; k < NL; ++k) gram_schmidt_rows01(U[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < NL; ++k) rebuild_row2(U[k]);
     }
-#pragma unroll
-    for (int k = 0; k < NL; ++k) rebuild_row2(U[k]);
 
     M3<R> K;
     leaf_tree<NL, NDIR>(U, bwd, mu_of, K);
@@ -359,7 +377,7 @@ __device__ __forceinline__ double site_update(const LinkField<R>& f, const Geom&
             right_mul_dag_rows01(G, U[k]);
         else
             left_mul_rows01(G, U[k]);
-        store_rows01<nt_stores(CP)>(f, bwd[k] ? 1 - parity : parity, mu_of[k], at[k], U[k]);
+        store_link<nt_stores(CP)>(f, bwd[k] ? 1 - parity : parity, mu_of[k], at[k], U[k]);
     }
 
     if constexpr (TRACKG) {

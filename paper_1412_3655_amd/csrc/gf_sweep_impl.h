@@ -7,7 +7,8 @@
 // that also sum the estimate of theta).  The per-site body lives in gf_site.h.  The loop over
 // sites is over the half index of one colour: every link is read once and
 // written once per half-sweep (per site update in FP64 with 12-real links:
-// 768 B read and 768 B written), whatever the gauge.
+// 768 B read and 768 B written; with 8-real links 512 B and 512 B), whatever
+// the gauge.  The 8-real instantiations are compiled in gf_sweep_min8*.hip.
 #pragma once
 
 #include "gf_kernels.h"
@@ -20,8 +21,8 @@ namespace sweep_impl {
 // update into est[2 (parity gridDim.x + b)] (b the block's tile, second double
 // 0), which a fixed-order pass turns into an estimate of theta.  A template
 // parameter, so the plain sweep carries none of it.
-template <typename R, int TPS, int MODE, int BLOCK, bool TRACKG, int CP, int NDIR, bool EST>
-__device__ __forceinline__ void half_sweep_body(const LinkField<R>& f, const Geom& g, int parity, const Rule<R>& rule,
+template <typename R, int TPS, int MODE, int BLOCK, bool TRACKG, int CP, int NDIR, bool EST, typename F>
+__device__ __forceinline__ void half_sweep_body(const F& f, const Geom& g, int parity, const Rule<R>& rule,
                                                 const GField& gacc, double* est)
 {
     // With cached loads the white half-sweep takes the blocks in reverse
@@ -37,29 +38,29 @@ __device__ __forceinline__ void half_sweep_body(const LinkField<R>& f, const Geo
     // whole groups of TPS lanes leave or skip together, so every DPP partner is live
     if constexpr (!EST) {
         if (h >= g.vh) return;
-        site_update<R, TPS, MODE, TRACKG, CP, NDIR>(f, g, parity, h, r, rule, gacc);
+        site_update<R, TPS, MODE, TRACKG, CP, NDIR, F>(f, g, parity, h, r, rule, gacc);
     } else {
         double th = 0.0;
-        if (h < g.vh) th = site_update<R, TPS, MODE, TRACKG, CP, NDIR>(f, g, parity, h, r, rule, gacc, true);
+        if (h < g.vh) th = site_update<R, TPS, MODE, TRACKG, CP, NDIR, F>(f, g, parity, h, r, rule, gacc, true);
         block_sum2<BLOCK>(th, 0.0, est + 2 * ((size_t)parity * gridDim.x + b));
     }
 }
 
-template <typename R, int TPS, int MODE, int BLOCK, bool TRACKG, int CP, int NDIR, bool EST>
-__global__ void __launch_bounds__(BLOCK) k_or_half_sweep(LinkField<R> f, Geom g, int parity, Rule<R> rule,
-                                                         GField gacc, double* est)
+template <typename R, int TPS, int MODE, int BLOCK, bool TRACKG, int CP, int NDIR, bool EST, typename F>
+__global__ void __launch_bounds__(BLOCK) k_or_half_sweep(F f, Geom g, int parity, Rule<R> rule, GField gacc,
+                                                         double* est)
 {
-    half_sweep_body<R, TPS, MODE, BLOCK, TRACKG, CP, NDIR, EST>(f, g, parity, rule, gacc, est);
+    half_sweep_body<R, TPS, MODE, BLOCK, TRACKG, CP, NDIR, EST, F>(f, g, parity, rule, gacc, est);
 }
 
 // The same kernel held to at least 2 waves per SIMD (at most 256 registers per
 // lane): the register-limit axis of run-time tuning, for the one-lane float64
 // shape.
-template <typename R, int TPS, int MODE, int BLOCK, bool TRACKG, int CP, int NDIR, bool EST>
+template <typename R, int TPS, int MODE, int BLOCK, bool TRACKG, int CP, int NDIR, bool EST, typename F>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
-k_or_half_sweep_w2(LinkField<R> f, Geom g, int parity, Rule<R> rule, GField gacc, double* est)
+k_or_half_sweep_w2(F f, Geom g, int parity, Rule<R> rule, GField gacc, double* est)
 {
-    half_sweep_body<R, TPS, MODE, BLOCK, TRACKG, CP, NDIR, EST>(f, g, parity, rule, gacc, est);
+    half_sweep_body<R, TPS, MODE, BLOCK, TRACKG, CP, NDIR, EST, F>(f, g, parity, rule, gacc, est);
 }
 
 // Blocks of one half-sweep launch in configuration c (the estimate buffer
@@ -69,28 +70,28 @@ inline uint32_t sweep_grid(const Geom& g, const SweepConfig& c)
     return (uint32_t)(((uint64_t)g.vh * (uint64_t)c.tps + (uint64_t)c.block - 1) / (uint64_t)c.block);
 }
 
-template <int NDIR, bool EST, typename R, int TPS, int MODE, bool TRACKG>
-hipError_t launch_tps(const LinkField<R>& f, const Geom& g, int parity, const Rule<R>& rule, const SweepConfig& c,
+template <int NDIR, bool EST, typename R, int TPS, int MODE, bool TRACKG, typename F>
+hipError_t launch_tps(const F& f, const Geom& g, int parity, const Rule<R>& rule, const SweepConfig& c,
                       const GField& gacc, hipStream_t st, double* est)
 {
     const int block = c.block;
     const uint32_t grid = sweep_grid(g, c);
     if (grid == 0) return hipSuccess;
     // minw = 2 selects the register-capped kernel for the one-lane float64 shape
-    // (other shapes already run 2 or more waves per SIMD)
-    constexpr bool kCap = sizeof(R) == 8 && TPS == 1;
+    // of the 12-real layout (other shapes already run 2 or more waves per SIMD)
+    constexpr bool kCap = sizeof(R) == 8 && TPS == 1 && std::is_same<F, LinkField<R>>::value;
     const bool cap = kCap && c.minw == 2;
 #define GF_LAUNCH(B, CPV)                                                                                         \
     do {                                                                                                          \
         if constexpr (kCap) {                                                                                     \
             if (cap) {                                                                                            \
-                hipLaunchKernelGGL((k_or_half_sweep_w2<R, TPS, MODE, B, TRACKG, CPV, NDIR, EST>), dim3(grid),     \
+                hipLaunchKernelGGL((k_or_half_sweep_w2<R, TPS, MODE, B, TRACKG, CPV, NDIR, EST, F>), dim3(grid),  \
                                    dim3(B), 0, st, f, g, parity, rule, gacc, est);                                \
                 break;                                                                                            \
             }                                                                                                     \
         }                                                                                                         \
-        hipLaunchKernelGGL((k_or_half_sweep<R, TPS, MODE, B, TRACKG, CPV, NDIR, EST>), dim3(grid), dim3(B), 0, st, \
-                           f, g, parity, rule, gacc, est);                                                        \
+        hipLaunchKernelGGL((k_or_half_sweep<R, TPS, MODE, B, TRACKG, CPV, NDIR, EST, F>), dim3(grid), dim3(B), 0,  \
+                           st, f, g, parity, rule, gacc, est);                                                    \
     } while (0)
 #define GF_LAUNCH_SMALL_BLOCKS(CPV)                  \
     switch (block) {                                 \
@@ -129,8 +130,8 @@ hipError_t launch_tps(const LinkField<R>& f, const Geom& g, int parity, const Ru
     return hipGetLastError();
 }
 
-template <int NDIR, bool EST, typename R, int MODE, bool TRACKG>
-hipError_t launch_mode(const LinkField<R>& f, const Geom& g, int parity, const Rule<R>& rule, const SweepConfig& c,
+template <int NDIR, bool EST, typename R, int MODE, bool TRACKG, typename F>
+hipError_t launch_mode(const F& f, const Geom& g, int parity, const Rule<R>& rule, const SweepConfig& c,
                        const GField& gacc, hipStream_t st, double* est)
 {
     switch (c.tps) {
@@ -180,6 +181,27 @@ hipError_t hb_half_sweep(const LinkField<float>& f, const Geom& g, int parity, f
     const Rule<float> rule{1.0f, T, (uint32_t)seed, (uint32_t)(seed >> 32), sweep};
     if (gacc.base) return launch_mode<NDIR, false, float, HEATBATH, true>(f, g, parity, rule, cfg, gacc, st, nullptr);
     return launch_mode<NDIR, false, float, HEATBATH, false>(f, g, parity, rule, cfg, gacc, st, nullptr);
+}
+
+// Float64 links stored in 8 reals (Link8Field): the same kernel, decoding on
+// load and encoding on store.
+template <int NDIR, bool EST>
+hipError_t or_half_sweep(const Link8Field& f, const Geom& g, int parity, double omega, int mode,
+                         const SweepConfig& cfg, hipStream_t st, double* est)
+{
+    const GField none{nullptr, 0};
+    const Rule<double> rule{omega, 1.0, 0u, 0u, 0u};
+    return mode == OR_EXACT ? launch_mode<NDIR, EST, double, 0, false>(f, g, parity, rule, cfg, none, st, est)
+                            : launch_mode<NDIR, EST, double, 1, false>(f, g, parity, rule, cfg, none, st, est);
+}
+
+template <int NDIR>
+hipError_t hb_half_sweep(const Link8Field& f, const Geom& g, int parity, double T, uint64_t seed, uint32_t sweep,
+                         const SweepConfig& cfg, hipStream_t st)
+{
+    const GField none{nullptr, 0};
+    const Rule<double> rule{1.0, T, (uint32_t)seed, (uint32_t)(seed >> 32), sweep};
+    return launch_mode<NDIR, false, double, HEATBATH, false>(f, g, parity, rule, cfg, none, st, nullptr);
 }
 
 }  // namespace sweep_impl

@@ -31,13 +31,14 @@ std::string device_arch()
 // A GF_MIXED lattice's float32 sweeps also update g(x) (another 96 B per site
 // update and more registers), so they are a kernel of their own: "fp32g".  The
 // Coulomb kernels (K over three directions) are keyed apart with a "-coulomb"
-// suffix.
+// suffix, SU(2) lattices with "-su2" and 8-real links with "-min8".
 std::string cache_key(gf_lattice L, gf_prec kernel)
 {
     char buf[128];
     const char* k = kernel == GF_FP64 ? "fp64" : (L->gacc.base ? "fp32g" : "fp32");
-    snprintf(buf, sizeof buf, "%s %d %d %d %d %s%s%s", device_arch().c_str(), L->dims[0], L->dims[1], L->dims[2],
-             L->dims[3], k, L->gauge == GAUGE_COULOMB ? "-coulomb" : "", L->group == 2 ? "-su2" : "");
+    snprintf(buf, sizeof buf, "%s %d %d %d %d %s%s%s%s", device_arch().c_str(), L->dims[0], L->dims[1], L->dims[2],
+             L->dims[3], k, L->gauge == GAUGE_COULOMB ? "-coulomb" : "", L->group == 2 ? "-su2" : "",
+             L->min8 ? "-min8" : "");
     return buf;
 }
 
@@ -87,7 +88,8 @@ gf_status tune(gf_lattice L, gf_prec kernel, bool heat_bath, int32_t n_sweeps, c
     }
 
     const bool su2 = L->group == 2;
-    const size_t chunks = (size_t)2 * 4 * L->geom.ld * (kernel == GF_FP32 ? (su2 ? 1 : 3) : (su2 ? 2 : 6));
+    const size_t chunks =
+        (size_t)2 * 4 * L->geom.ld * (kernel == GF_FP32 ? (su2 ? 1 : 3) : (su2 ? 2 : (L->min8 ? kMin8Chunks : 6)));
     const size_t bytes = chunks * 16;
     void* scratch = nullptr;
     void* gscratch = nullptr;
@@ -111,10 +113,11 @@ gf_status tune(gf_lattice L, gf_prec kernel, bool heat_bath, int32_t n_sweeps, c
     const LinkField<double> f64{(double2*)scratch, L->geom.ld};
     const Su2Field<float> q32{(float4*)scratch, L->geom.ld};
     const Su2Field<double> q64{(double2*)scratch, L->geom.ld};
+    const Link8Field f8{(double2*)scratch, L->geom.ld};
     uint32_t hb_sweep = 0;
     // the register cap changes only the one-lane float64 kernel (every other
     // shape already runs 2 or more waves per SIMD)
-    const bool cap_axis = !su2 && kernel == GF_FP64;
+    const bool cap_axis = !su2 && !L->min8 && kernel == GF_FP64;
     for (int minw : {0, 2})
     for (int nt : {0, 1, 2})
     for (int tps : {1, 2, 4, 8}) {
@@ -133,6 +136,10 @@ gf_status tune(gf_lattice L, gf_prec kernel, bool heat_bath, int32_t n_sweeps, c
                         r = launch_su2_or(q32, L->geom, p, 1.7f, GF_OR_EXACT, c, L->stream, L->gauge, nullptr);
                     else if (su2)
                         r = launch_su2_or(q64, L->geom, p, 1.7, GF_OR_EXACT, c, L->stream, L->gauge, nullptr);
+                    else if (L->min8 && heat_bath)
+                        r = launch_hb_half_sweep(f8, L->geom, p, 1.0, 1u, hb_sweep, c, L->stream, L->gauge);
+                    else if (L->min8)
+                        r = launch_or_half_sweep(f8, L->geom, p, 1.7, GF_OR_EXACT, c, L->stream, L->gauge);
                     else if (heat_bath && kernel == GF_FP32)
                         r = launch_hb_half_sweep(f32, L->geom, p, 1.0f, 1u, hb_sweep, c, track ? g_s : g_none,
                                                  L->stream, L->gauge);

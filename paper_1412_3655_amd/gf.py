@@ -117,6 +117,8 @@ _SIGNATURES = {
     "gf_destroy_lattice": [_vp],
     "gf_create_lattice_su2": [ctypes.POINTER(_i32), ctypes.c_int, _vp, ctypes.POINTER(_vp)],
     "gf_lattice_group": [_vp, ctypes.POINTER(_i32)],
+    "gf_create_lattice_min8": [ctypes.POINTER(_i32), _vp, ctypes.POINTER(_vp)],
+    "gf_lattice_storage": [_vp, ctypes.POINTER(_i32)],
     "gf_lattice_info": [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
     "gf_set_sweep_config": [_vp, ctypes.c_int, _i32, _i32, _i32, _i32],
     "gf_set_anneal_config": [_vp, ctypes.c_int, _i32, _i32, _i32, _i32],
@@ -260,16 +262,29 @@ def gf_last_error() -> str:
 _LATTICE_STREAM = {}
 
 
-def gf_create_lattice(dims, prec: int = GF_FP64, stream=None, group: int = 3) -> ctypes.c_void_p:
-    """group 3: SU(3) (gf_create_lattice); group 2: SU(2) (gf_create_lattice_su2)."""
+def gf_create_lattice(dims, prec: int = GF_FP64, stream=None, group: int = 3, storage: int = 12) -> ctypes.c_void_p:
+    """group 3: SU(3) (gf_create_lattice); group 2: SU(2) (gf_create_lattice_su2).
+    storage 8: SU(3) float64 links in 8 reals (gf_create_lattice_min8; prec must be GF_FP64)."""
     d = (_i32 * 4)(*[int(x) for x in dims])
     out = _vp()
     h = _stream_handle(stream)
     if group not in (2, 3):
         raise ValueError("group must be 2 (SU(2)) or 3 (SU(3))")
-    _call("gf_create_lattice_su2" if group == 2 else "gf_create_lattice", d, int(prec), h, ctypes.byref(out))
+    if storage not in (8, 12) or (storage == 8 and (group != 3 or prec != GF_FP64)):
+        raise ValueError("storage 8 is for SU(3) float64 lattices; otherwise 12")
+    if storage == 8:
+        _call("gf_create_lattice_min8", d, h, ctypes.byref(out))
+    else:
+        _call("gf_create_lattice_su2" if group == 2 else "gf_create_lattice", d, int(prec), h, ctypes.byref(out))
     _LATTICE_STREAM[out.value] = h
     return out
+
+
+def gf_lattice_storage(lat) -> int:
+    """Reals stored per link: 12, 8 (gf_create_lattice_min8) or 4 (SU(2))."""
+    n = _i32()
+    _call("gf_lattice_storage", lat, ctypes.byref(n))
+    return n.value
 
 
 def gf_lattice_group(lat) -> int:
@@ -509,11 +524,12 @@ def gf_plaquette(lat) -> float:
 class Lattice:
     """Owning wrapper: ``with Lattice(dims, GF_FP64) as lat: ...``."""
 
-    def __init__(self, dims, prec: int = GF_FP64, stream=None, gauge: int = GF_LANDAU, group: int = 3):
+    def __init__(self, dims, prec: int = GF_FP64, stream=None, gauge: int = GF_LANDAU, group: int = 3,
+                 storage: int = 12):
         self.dims = tuple(int(d) for d in dims)
         self.prec = prec
         self.group = group
-        self.handle = gf_create_lattice(self.dims, prec, stream, group)
+        self.handle = gf_create_lattice(self.dims, prec, stream, group, storage)
         if gauge != GF_LANDAU:
             gf_set_gauge(self.handle, gauge)
 
