@@ -54,19 +54,76 @@ __device__ __forceinline__ double with_low_bit(double v, uint32_t bit)
     return __hiloint2double(__double2hiint(v), (int)(((uint32_t)__double2loint(v) & ~1u) | bit));
 }
 
+// The codec's square roots and quotients take operands in fixed ranges (every
+// square root of a value in [1/3, 1], every divisor of magnitude <= 2 or a
+// finite 1 + t^2), so they skip the general routines' range scaling and
+// special-value handling: a hardware reciprocal or reciprocal square root
+// seed refined by Newton's (reciprocal) and Goldschmidt's (square root)
+// iterations, two steps each (a seed good to 2^-14 ends within 1-2 units in
+// the last place), then one residual correction.
+
+// 1/d for 1 <= |d| < 2^1000
+__device__ __forceinline__ double recip(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    double e = fmad(-d, r, 1.0);
+    r = fmad(r, e, r);
+    e = fmad(-d, r, 1.0);
+    return fmad(r, e, r);
+}
+
+// n / d for |n| <= 2 and 0 < |d| <= 2 (d = +-0 or subnormal gives an infinite
+// or NaN quotient, which the caller clamps)
+__device__ __forceinline__ double quotient(double n, double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    double e = fmad(-d, r, 1.0);
+    r = fmad(r, e, r);
+    e = fmad(-d, r, 1.0);
+    r = fmad(r, e, r);
+    const double q = n * r;
+    return fmad(r, fmad(-d, q, n), q);
+}
+
+// sqrt(x) and 1/sqrt(x) for 1/4 <= x <= 2
+__device__ __forceinline__ void sqrt_rsqrt(double x, double& sq, double& rs)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    double r = fmad(-g, h, 0.5);
+    g = fmad(g, r, g);
+    h = fmad(h, r, h);
+    r = fmad(-g, h, 0.5);
+    g = fmad(g, r, g);
+    h = fmad(h, r, h);
+    g = fmad(fmad(-g, g, x), h, g);
+    double i = 2.0 * h;
+    i = fmad(i, fmad(-g, i, 1.0), i);
+    sq = g;
+    rs = i;
+}
+
+__device__ __forceinline__ double sqrt_of(double x)
+{
+    double sq, rs;
+    sqrt_rsqrt(x, sq, rs);
+    return sq;
+}
+
 // (cos, sin) of the phase whose half-angle tangent is t
 __device__ __forceinline__ void phase_of_tan_half(double t, double& c, double& s)
 {
-    const double d = 1.0 / fmad(t, t, 1.0);
+    const double d = recip(fmad(t, t, 1.0));
     c = fmad(-t, t, 1.0) * d;
     s = (2.0 * t) * d;
 }
 
-// half-angle tangent of the phase of z = re + i im (|z| > 0)
-__device__ __forceinline__ double tan_half_of(double re, double im)
+// half-angle tangent of the phase of z = re + i im, |z|^2 = a2 >= 1/3
+__device__ __forceinline__ double tan_half_of(double re, double im, double a2)
 {
-    const double a = sqrt(fmad(re, re, im * im));
-    double t = re >= 0.0 ? im / (a + re) : (a - re) / im;
+    const double a = sqrt_of(a2);
+    const bool right = re >= 0.0;
+    double t = quotient(right ? im : a - re, right ? a + re : im);
     if (!(fabs(t) <= 1e150)) t = copysign(1e150, im);
     return t;
 }
@@ -95,13 +152,13 @@ __device__ __forceinline__ void decode_min8(const double2 (&p)[kMin8Chunks], M3<
     const bool q = low_bit(sr) != 0u;
     const double ai2 = fmad(air, air, aii * aii);
     const double aj2 = fmad(ajr, ajr, aji * aji);
-    const double rho = sqrt(fmax(0.0, (1.0 - ai2) - aj2));
+    const double rho = sqrt_of(fmax(1.0 / 3.0, (1.0 - ai2) - aj2));
     double c, s;
     phase_of_tan_half(t0, c, s);
     const double akr = rho * c, aki = rho * s;
-    const double n = sqrt(1.0 - aj2);
-    const double in = 1.0 / n;
-    const double bm = sqrt(fmax(0.0, 1.0 - fmad(sr, sr, si * si)));
+    double n, in;
+    sqrt_rsqrt(1.0 - aj2, n, in);
+    const double bm = sqrt_of(fmax(0.5, 1.0 - fmad(sr, sr, si * si)));
     phase_of_tan_half(t1, c, s);
     const double br = bm * c, bi = bm * s;
     const double alr = q ? sr : br, ali = q ? si : bi;
@@ -140,7 +197,9 @@ __device__ __forceinline__ void encode_min8(const M3<double>& u, double2 (&p)[kM
     const double m1 = fmad(u.re[0][1], u.re[0][1], u.im[0][1] * u.im[0][1]);
     const double m2 = fmad(u.re[0][2], u.re[0][2], u.im[0][2] * u.im[0][2]);
     uint32_t k = m1 > m0 ? 1u : 0u;
-    if (m2 > fmax(m0, m1)) k = 2u;
+    const double mk = fmax(m0, m1);
+    if (m2 > mk) k = 2u;
+    const double ak2 = fmax(mk, m2);
     const double akr = frame_pick(k, 0, u.re[0][0], u.re[0][1], u.re[0][2]);
     const double aki = frame_pick(k, 0, u.im[0][0], u.im[0][1], u.im[0][2]);
     const double air = frame_pick(k, 1, u.re[0][0], u.re[0][1], u.re[0][2]);
@@ -154,8 +213,8 @@ __device__ __forceinline__ void encode_min8(const M3<double>& u, double2 (&p)[kM
     const double r1jr = frame_pick(k, 2, u.re[1][0], u.re[1][1], u.re[1][2]);
     const double r1ji = frame_pick(k, 2, u.im[1][0], u.im[1][1], u.im[1][2]);
     const double aj2 = fmad(ajr, ajr, aji * aji);
-    const double n = sqrt(1.0 - aj2);
-    const double in = 1.0 / n;
+    double n, in;
+    sqrt_rsqrt(1.0 - aj2, n, in);
     // alpha = <e1, r1> = (-ai r1_k + ak r1_i) / n
     double alr = fmad(-air, r1kr, aii * r1ki);
     double ali = fmad(-air, r1ki, -aii * r1kr);
@@ -163,22 +222,16 @@ __device__ __forceinline__ void encode_min8(const M3<double>& u, double2 (&p)[kM
     ali = fmad(akr, r1ii, fmad(aki, r1ir, ali));
     alr *= in;
     ali *= in;
-    // beta = <e2, r1> = -(conj(ak) aj r1_k + conj(ai) aj r1_i) / n + n r1_j
-    const double xr = fmad(akr, ajr, aki * aji), xi = fmad(akr, aji, -aki * ajr);  // conj(ak) aj
-    const double yr = fmad(air, ajr, aii * aji), yi = fmad(air, aji, -aii * ajr);  // conj(ai) aj
-    double ber = fmad(xr, r1kr, -xi * r1ki);
-    double bei = fmad(xr, r1ki, xi * r1kr);
-    ber = fmad(yr, r1ir, fmad(-yi, r1ii, ber));
-    bei = fmad(yr, r1ii, fmad(yi, r1ir, bei));
-    ber = fmad(n, r1jr, -ber * in);
-    bei = fmad(n, r1ji, -bei * in);
-    const bool q = fmad(ber, ber, bei * bei) > fmad(alr, alr, ali * ali);
+    // beta: e1 has no j component and e2_j = n, so r1_j = beta n
+    const double ber = r1jr * in, bei = r1ji * in;
+    const double al2 = fmad(alr, alr, ali * ali), be2 = fmad(ber, ber, bei * bei);
+    const bool q = be2 > al2;
     const double smr = q ? alr : ber, smi = q ? ali : bei;
     const double bgr = q ? ber : alr, bgi = q ? bei : ali;
     p[0] = make_double2(with_low_bit(air, k & 1u), with_low_bit(aii, k >> 1));
     p[1] = make_double2(ajr, aji);
-    p[2] = make_double2(tan_half_of(akr, aki), with_low_bit(smr, q ? 1u : 0u));
-    p[3] = make_double2(smi, tan_half_of(bgr, bgi));
+    p[2] = make_double2(tan_half_of(akr, aki, ak2), with_low_bit(smr, q ? 1u : 0u));
+    p[3] = make_double2(smi, tan_half_of(bgr, bgi, fmax(0.5, fmax(al2, be2))));
 }
 
 template <bool NT = false>
