@@ -62,30 +62,38 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "or_sweep_f64_32x4_traffic.md")
 TRAFFIC_FILE_48 = os.path.join(ROOT, "profiles", "or_sweep_f64_48x96_traffic.md")
 FULL_DIMS = (48, 48, 48, 96)
 SWEEP_SOURCES = ["gf_sweep.hip", "gf_sweep_impl.h", "gf_site.h", "gf_device.h"]
+# the 8-real sweep also compiles its codec and launcher
+MIN8_SOURCES = SWEEP_SOURCES + ["gf_min8.h", "gf_sweep_min8.hip"]
+TRAFFIC_FILE_48_MIN8 = os.path.join(ROOT, "profiles", "or_sweep_f64min8_48x96_traffic.md")
+TRAFFIC_FILE_32_MIN8 = os.path.join(ROOT, "profiles", "or_sweep_f64min8_32x4_traffic.md")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def sweep_source_hash() -> str:
+def sweep_source_hash(sources=SWEEP_SOURCES) -> str:
     h = hashlib.sha256()
-    for name in SWEEP_SOURCES:
+    for name in sources:
         with open(os.path.join(ROOT, "paper_1412_3655_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def committed_traffic(path=TRAFFIC_FILE):
-    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
-    or None when it is missing or the sweep kernel changed since."""
+def committed_traffic(path, sources, config):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary, or None when it
+    is missing, the sweep kernel changed since, or it was taken in another launch configuration
+    (tps, block, cache policy) than `config`."""
     try:
         text = open(path).read()
-    except OSError:
+    except (OSError, TypeError):
         return None
     src = re.search(r"kernel_source_sha256:\s*([0-9a-f]+)", text)
     val = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not src or not val or src.group(1) != sweep_source_hash():
+    cfg = re.search(r"kernel_config:\s*(\d+) (\d+) (\d+)", text)
+    if not src or not val or not cfg or src.group(1) != sweep_source_hash(sources):
+        return None
+    if tuple(int(x) for x in cfg.groups()) != tuple(config):
         return None
     return float(val.group(1))
 
@@ -329,8 +337,13 @@ def sweep_leg(gf, torch, stream, u, dims, args, steps, storage, input_name, traf
     name = "x".join(map(str, dims))
     with gf.Lattice(dims, gf.GF_FP64, stream=stream, storage=storage) as lat:
         lat.set_links(u)
-        (tps, block, nt, minw), table = lat.autotune(gf.GF_FP64, n_sweeps=3)
-        log(f"{name} fp64/{storage} autotune: tps={tps} block={block} cache policy={nt} min waves={minw}")
+        if args.no_tune:
+            (tps, block, nt, minw), table = ((args.tps, args.block, args.nt, args.minw) if storage == 12 else
+                                             (args.tps8, args.block8, args.nt8, 0)), []
+            lat.set_sweep_config(tps, block, nt, min_waves=minw)
+        else:
+            (tps, block, nt, minw), table = lat.autotune(gf.GF_FP64, n_sweeps=3)
+        log(f"{name} fp64/{storage}: tps={tps} block={block} cache policy={nt} min waves={minw}")
         with torch.cuda.stream(stream):
             lat.sweep(args.warmup, args.omega, args.mode)
             total, wall, per_launch = time_run(lat, torch, stream, steps, args.omega, args.mode, args.chunk)
@@ -357,7 +370,8 @@ def sweep_leg(gf, torch, stream, u, dims, args, steps, storage, input_name, traf
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": committed_traffic(traffic_file) if traffic_file else None,
+            "traffic": committed_traffic(traffic_file, SWEEP_SOURCES if storage == 12 else MIN8_SOURCES,
+                                         (tps, block, nt)),
             "kernel": "k_or_half_sweep<double, TPS=%d, exact, BLOCK=%d, cache policy %d%s%s>" % (
                 tps, block, nt, ", 2 waves/SIMD" if minw == 2 else "", ", 8-real links" if storage == 8 else ""),
             "algorithmic_bytes_per_launch": launch_bytes,
@@ -373,10 +387,12 @@ def min8_legs(gf, torch, stream, links, dims, full, args):
     site update instead of 1536 B), on the bandwidth lattice and on 48^3 x 96."""
     out = {"bytes_per_site_update": BYTES_PER_SITE["f64_min8"]}
     out["bandwidth_lattice"] = sweep_leg(gf, torch, stream, links, dims, args, args.steps, 8,
-                                         f"eps={args.eps}, seed {args.seed}")
+                                         f"eps={args.eps}, seed {args.seed}",
+                                         TRAFFIC_FILE_48_MIN8 if tuple(dims) == FULL_DIMS else
+                                         TRAFFIC_FILE_32_MIN8 if tuple(dims) == (32, 32, 32, 32) else None)
     if full is not None:
         out["fullsize_48x96"] = sweep_leg(gf, torch, stream, full, FULL_DIMS, args, args.full_steps, 8,
-                                          "eps=1.0, seed 0")
+                                          "eps=1.0, seed 0", TRAFFIC_FILE_48_MIN8)
     return out
 
 
@@ -521,6 +537,9 @@ def main(argv=None):
                     help="cache policy: 0 plain, 1 non-temporal loads and stores, 2 non-temporal stores")
     ap.add_argument("--minw", type=int, default=0,
                     help="register limit of the float64 sweep: 0 compiler's allocation, 2 at least 2 waves per SIMD")
+    ap.add_argument("--tps8", type=int, default=2, help="with --no-tune: lanes per site of the 8-real sweeps")
+    ap.add_argument("--block8", type=int, default=128, help="with --no-tune: block of the 8-real sweeps")
+    ap.add_argument("--nt8", type=int, default=1, help="with --no-tune: cache policy of the 8-real sweeps")
     ap.add_argument("--nt32", type=int, default=0)
     ap.add_argument("--tps32", type=int, default=4)
     ap.add_argument("--block32", type=int, default=256)
@@ -564,7 +583,8 @@ def main(argv=None):
                     help="second run to theta < 1e-12 on a smoother input of the same lattice (0: skip)")
     ap.add_argument("--theta-switch", type=float, default=-1.0,
                     help="float32 -> float64 switch of the mixed runs; < 0: chosen by gf_tune_switch")
-    ap.add_argument("--no-tune", action="store_true", help="use --tps/--block instead of the autotuner")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="use --tps/--block/--nt (12-real) and --tps8/--block8/--nt8 (8-real) instead of the autotuner")
     ap.add_argument("--gen-threads", type=int, default=8, help="host threads generating the inputs up front")
     args = ap.parse_args(argv)
 
@@ -659,7 +679,9 @@ def main(argv=None):
     rate = V * args.steps / r64["total"]
     launch_bytes = (V // 2) * BYTES_PER_SITE["f64"]
     achieved = launch_bytes / r64["per_launch"] / 1e9
-    traffic = committed_traffic()
+    traffic = committed_traffic(TRAFFIC_FILE if tuple(dims) == (32, 32, 32, 32) else
+                                TRAFFIC_FILE_48 if tuple(dims) == FULL_DIMS else None, SWEEP_SOURCES,
+                                (args.tps, args.block, args.nt))
     line = {
         "metric": METRIC,
         "value": rate,

@@ -192,15 +192,17 @@ typedef struct {
     int32_t block;
     int32_t nontemporal;
     int32_t min_waves;   /* register limit: 0 = compiler's allocation, 2 = at least 2 waves per SIMD */
-    double us_per_sweep; /* mean time of one sweep (both colours), microseconds */
+    double us_per_sweep; /* time of one sweep (both colours), microseconds: the faster of two rounds' means */
 } gf_tune_entry;
 
 /* Autotuner (the paper tunes threads per site, launch bounds and texture
  * loads at run time, Sec. 4 and 5): time every valid sweep configuration
  * (lanes per site, block size, cache policy, and for float64 the register
  * limit) of precision `kernel`
- * (GF_FP64 or GF_FP32) on a scratch copy of the lattice's links (one warm-up
- * sweep, then n_sweeps timed sweeps each), write up to cap entries to table
+ * (GF_FP64 or GF_FP32) on a scratch copy of the lattice's links (two rounds
+ * over all configurations, each with one warm-up sweep and then n_sweeps timed
+ * sweeps per configuration; a configuration keeps its faster round), write up
+ * to cap entries to table
  * (may be NULL), and make the fastest the lattice's configuration.  When
  * cache_path is not NULL, a result stored there for the same device
  * architecture, extents and kernel (float64; float32; float32 with the g(x)
