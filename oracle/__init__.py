@@ -120,8 +120,6 @@ def _declare(L):
     L.oracle_measure.argtypes = [_dp, _ip, _dp, _dp]
     L.oracle_plaquette.argtypes = [_dp, _ip]
     L.oracle_plaquette.restype = ctypes.c_double
-    L.oracle_fp32_floor.argtypes = [_dp, _ip]
-    L.oracle_fp32_floor.restype = ctypes.c_double
     L.oracle_unitarity.argtypes = [_dp, ctypes.c_int64, _dp, _dp]
     L.oracle_reunitarize.argtypes = [_dp, ctypes.c_int64]
     L.oracle_gauge_transform.argtypes = [_dp, _ip, _dp]
@@ -289,13 +287,6 @@ def plaquette(u, dims) -> float:
     u = _links(u)
     d = _dims(dims, u)
     return float(lib().oracle_plaquette(_p(u), _p(d, _ip)))
-
-
-def fp32_floor(u, dims) -> float:
-    """(1/(3V)) sum_x tr[E E^dag], E = Delta(x) of the float32 two-row store (K in float32) - Delta(x)."""
-    u = _links(u)
-    d = _dims(dims, u)
-    return float(lib().oracle_fp32_floor(_p(u), _p(d, _ip)))
 
 
 def unitarity(u):

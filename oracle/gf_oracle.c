@@ -54,10 +54,6 @@
  *   oracle_min8_* .......... the minimal 8-parameter SU(3) representation
  *                            that Sec. 4.1 names (the paper gives no
  *                            formulae; see the definition at the functions).
- *   oracle_fp32_floor ...... the float32 rounding floor of theta: Delta(x)
- *                            of the float32 two-row store (Sec. 3.1) with K
- *                            summed in float32, against Delta(x) in float64;
- *                            the mixed-precision switch point is set from it.
  *
  * Readings taken where the paper is silent (each also listed in the design
  * notes of the repository):
@@ -433,100 +429,6 @@ void oracle_measure(const double* U, const int32_t* dims, double* theta, double*
     free(fr);
     *theta = st / (3.0 * (double)g.V);
     *F = sf / (12.0 * (double)g.V);
-}
-
-/* ------------------------------------------------------------------ */
-/* float32 rounding floor of the gauge condition                       */
-/* ------------------------------------------------------------------ */
-
-/* The link as a float32 two-row store holds it: rows 0 and 1 rounded to
- * float32, row 2 = conj(row 0 x row 1) formed in float32 arithmetic. */
-static void link_as_f32(const cx* u, float re[9], float im[9])
-{
-    for (int k = 0; k < 6; ++k) {
-        re[k] = (float)creal(u[k]);
-        im[k] = (float)cimag(u[k]);
-    }
-    for (int j = 0; j < 3; ++j) {
-        const int a = (j + 1) % 3, b = (j + 2) % 3;
-        const float pr = re[a] * re[3 + b] - im[a] * im[3 + b];
-        const float pi = re[a] * im[3 + b] + im[a] * re[3 + b];
-        const float qr = re[b] * re[3 + a] - im[b] * im[3 + a];
-        const float qi = re[b] * im[3 + a] + im[b] * re[3 + a];
-        re[6 + j] = pr - qr;
-        im[6 + j] = -(pi - qi);
-    }
-}
-
-/* Delta = [(K - K^dag) / (2i)]_traceless from K given as real/imaginary parts
- * (float32 arithmetic for the float32 K). */
-static void delta_f32(const float kr[9], const float ki[9], float dr[9], float di[9])
-{
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-            /* (K_ij - conj(K_ji)) / (2i) */
-            const float nr = kr[3 * i + j] - kr[3 * j + i];
-            const float ni = ki[3 * i + j] + ki[3 * j + i];
-            dr[3 * i + j] = 0.5f * ni;
-            di[3 * i + j] = -0.5f * nr;
-        }
-    const float t = (dr[0] + dr[4] + dr[8]) / 3.0f;
-    dr[0] -= t;
-    dr[4] -= t;
-    dr[8] -= t;
-}
-
-/* Per site: tr[E E^dag], E = Delta(x) from the float32 two-row store of the
- * links with K summed in float32 (mu = 0..3, forward link then backward
- * link) minus Delta(x) in float64. */
-static double fp32_floor_site(const double* U, const geom* g, long s)
-{
-    float kr[9] = {0}, ki[9] = {0};
-    for (int mu = 0; mu < 4; ++mu) {
-        float re[9], im[9];
-        link_as_f32(clink_at(U, s, mu), re, im);
-        for (int k = 0; k < 9; ++k) {
-            kr[k] += re[k];
-            ki[k] += im[k];
-        }
-        link_as_f32(clink_at(U, hop(g, s, mu, -1), mu), re, im);
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) {
-                kr[3 * i + j] += re[3 * j + i];
-                ki[3 * i + j] += -im[3 * j + i];
-            }
-    }
-    float dr[9], di[9];
-    delta_f32(kr, ki, dr, di);
-    cx K[9], D[9];
-    local_K(U, g, s, 4, K);
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) D[3 * i + j] = (K[3 * i + j] - conj(K[3 * j + i])) / (2.0 * I);
-    const cx t = (D[0] + D[4] + D[8]) / 3.0;
-    D[0] -= t;
-    D[4] -= t;
-    D[8] -= t;
-    double acc = 0.0;
-    for (int k = 0; k < 9; ++k) {
-        const double er = (double)dr[k] - creal(D[k]), ei = (double)di[k] - cimag(D[k]);
-        acc += er * er + ei * ei;
-    }
-    return acc;
-}
-
-/* (1/(N_c V)) sum_x tr[E E^dag]: the mean-square float32 rounding error of
- * the local gauge condition, the level below which float32 sweeps cannot
- * resolve the gauge condition of this configuration. */
-double oracle_fp32_floor(const double* U, const int32_t* dims)
-{
-    geom g = mkgeom(dims);
-    double* e = (double*)malloc(sizeof(double) * (size_t)g.V);
-#pragma omp parallel for schedule(static) if (g.V >= OMP_MIN_SITES)
-    for (long s = 0; s < g.V; ++s) e[s] = fp32_floor_site(U, &g, s);
-    double acc = 0.0;
-    for (long s = 0; s < g.V; ++s) acc += e[s];
-    free(e);
-    return acc / (3.0 * (double)g.V);
 }
 
 /* P = (1/(18 V)) sum_x sum_{mu<nu} Re tr[U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag] */

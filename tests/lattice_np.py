@@ -76,3 +76,34 @@ def random_su2(rng, n):
 def quaternion_coeffs(k):
     """Coefficients of the real-orthogonal projection of 2x2 k on QBASIS."""
     return np.array([np.real(np.trace(dag(e) @ k)) / 2.0 for e in QBASIS])
+
+
+def float_exact_links(dims, seed):
+    """Links whose entries are 0, +-1 or +-i (real signed cyclic permutations with det 1, and
+    diag(i, -i, 1), diag(-i, i, 1)): float32 stores them exactly, every float32 product and sum
+    formed from them is exact, and the imaginary diagonal of K sums to zero at every site."""
+    rng = np.random.default_rng(seed)
+    V = gi.volume(dims)
+    P = np.array([[0, 1, 0], [0, 0, 1], [1, 0, 0]], dtype=np.complex128)
+    mats = []
+    for k in range(3):
+        Pk = np.linalg.matrix_power(P, k)
+        for signs in ((1, 1, 1), (1, -1, -1), (-1, 1, -1), (-1, -1, 1)):
+            mats.append(np.diag(signs).astype(np.complex128) @ Pk)
+    mats.append(np.diag([1j, -1j, 1]))
+    mats.append(np.diag([-1j, 1j, 1]))
+    mats = np.array(mats)
+    for m in mats:
+        assert abs(np.linalg.det(m) - 1) < 1e-15
+    pick = rng.integers(0, len(mats), size=(V, 4))
+    return gi.to_canonical(mats[pick])
+
+
+def storage_floor(u, dims):
+    """theta-floor from storage alone: rows 0, 1 rounded to float32, everything else exact."""
+    c = gi.complex_view(u).copy()
+    c[:, :, :2, :] = c[:, :, :2, :].astype(np.complex64).astype(np.complex128)
+    c[:, :, 2, :] = np.conj(np.cross(c[:, :, 0, :], c[:, :, 1, :]))
+    r = gi.to_canonical(c)
+    E = delta_from_K(r, dims) - delta_from_K(u, dims)
+    return float(np.sum(np.abs(E) ** 2) / (3 * u.shape[0]))

@@ -570,57 +570,6 @@ def test_generator_group_membership_and_haar_moments():
     assert np.abs(np.linalg.det(h) - 1).max() < 1e-14
 
 
-def _float_exact_links(dims, seed):
-    """Links whose entries are 0, +-1 or +-i (real signed cyclic permutations with det 1, and
-    diag(i, -i, 1), diag(-i, i, 1)): float32 stores them exactly, every float32 product and sum
-    formed from them is exact, and the imaginary diagonal of K sums to zero at every site."""
-    rng = np.random.default_rng(seed)
-    V = gi.volume(dims)
-    P = np.array([[0, 1, 0], [0, 0, 1], [1, 0, 0]], dtype=np.complex128)
-    mats = []
-    for k in range(3):
-        Pk = np.linalg.matrix_power(P, k)
-        for signs in ((1, 1, 1), (1, -1, -1), (-1, 1, -1), (-1, -1, 1)):
-            mats.append(np.diag(signs).astype(np.complex128) @ Pk)
-    mats.append(np.diag([1j, -1j, 1]))
-    mats.append(np.diag([-1j, 1j, 1]))
-    mats = np.array(mats)
-    for m in mats:
-        assert abs(np.linalg.det(m) - 1) < 1e-15
-    pick = rng.integers(0, len(mats), size=(V, 4))
-    return gi.to_canonical(mats[pick])
-
-
-def _storage_floor(u, dims):
-    """theta-floor from storage alone: rows 0, 1 rounded to float32, everything else exact."""
-    c = gi.complex_view(u).copy()
-    c[:, :, :2, :] = c[:, :, :2, :].astype(np.complex64).astype(np.complex128)
-    c[:, :, 2, :] = np.conj(np.cross(c[:, :, 0, :], c[:, :, 1, :]))
-    r = gi.to_canonical(c)
-    E = ln.delta_from_K(r, dims) - ln.delta_from_K(u, dims)
-    return float(np.sum(np.abs(E) ** 2) / (3 * u.shape[0]))
-
-
-def test_fp32_floor_pins():
-    """The float32 rounding floor of theta: exactly 0 where float32 is exact; on generic links it
-    is a few float32 units squared (u = 2^-24) and exceeds the storage-only floor by the float32
-    arithmetic (row-2 rebuild, K sums), but not by orders of magnitude."""
-    dims = (4, 4, 4, 4)
-    ex = _float_exact_links(dims, 3)
-    assert oracle.fp32_floor(ex, dims) == 0.0
-    u2 = 2.0 ** -48
-    for eps in (0.2, 0.6, 1.0):
-        u = gi.gen_links(dims, eps, 5)
-        f = oracle.fp32_floor(u, dims)
-        s = _storage_floor(u, dims)
-        assert 1.0 * u2 < f < 30.0 * u2, (eps, f / u2)
-        assert 2.0 < f / s < 20.0, (eps, f / s)
-        # a statistical property of rounding, not of the gauge: a Haar gauge rotation keeps it
-        h = gi.haar_su3(np.random.default_rng(9), gi.volume(dims))
-        fr = oracle.fp32_floor(oracle.gauge_transform(u.copy(), dims, gi.to_canonical(h)), dims)
-        assert abs(fr / f - 1.0) < 0.2, (eps, fr / f)
-
-
 def test_unitarity_measure_closed_forms():
     """(max ||U^dag U - 1||_F, max |det U - 1|) on matrices with known answers: diag(1+d, 1, 1)
     gives (2d + d^2, d); a unitary phase matrix gives (0, 0) to rounding; s*W with W in SU(3)
