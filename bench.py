@@ -393,6 +393,16 @@ def min8_legs(gf, torch, stream, links, dims, full, args):
     if full is not None:
         out["fullsize_48x96"] = sweep_leg(gf, torch, stream, full, FULL_DIMS, args, args.full_steps, 8,
                                           "eps=1.0, seed 0", TRAFFIC_FILE_48_MIN8)
+    # the storage as a tuning axis: both storages timed on each lattice, the faster kept
+    for name, u, d in (("bandwidth_lattice", links, dims), ("fullsize_48x96", full, FULL_DIMS)):
+        if u is None:
+            continue
+        with gf.Lattice(d, gf.GF_FP64, stream=stream) as lat:
+            lat.set_links(u)
+            reals, us12, us8 = lat.autotune_storage(3)
+        log(f"{'x'.join(map(str, d))} storage autotune: {reals} reals (12: {us12:.1f} us, 8: {us8:.1f} us per sweep)")
+        out.setdefault("storage_autotune", {})[name] = {"chosen_reals_per_link": reals,
+                                                        "us_per_sweep_12": us12, "us_per_sweep_8": us8}
     return out
 
 

@@ -154,6 +154,29 @@ gf_status gf_create_lattice_min8(const int32_t dims[4], void* hip_stream, gf_lat
  * 4 (SU(2) quaternion). */
 gf_status gf_lattice_storage(gf_lattice lat, int32_t* reals_per_link);
 
+/* Switch an SU(3) GF_FP64 lattice between 12-real and 8-real storage of its
+ * float64 links (reals_per_link 12 or 8; GF_E_ARG otherwise; GF_E_STATE for
+ * other lattices).  The links are converted on the device: 12 -> 8 projects
+ * rows 0, 1 of each link onto SU(3) as gf_set_links on an 8-real lattice
+ * does (a change at rounding level for SU(3) links), 8 -> 12 stores the
+ * decoded rows exactly.  The old field is freed after the new one is written
+ * (both are held meanwhile); captured sweep graphs are dropped and the
+ * register limit of the float64 configurations reset to 0.  Syncs. */
+gf_status gf_set_storage(gf_lattice lat, int32_t reals_per_link);
+
+/* Storage as an autotuning axis (Sec. 4.1 and 5: the parameterisation and
+ * the kernel configuration are both run-time choices in the paper's
+ * design): tune the float64 overrelaxation sweep of an SU(3) GF_FP64
+ * lattice (as gf_autotune with kernel GF_FP64 and no cache) in its current
+ * storage, then on a scratch copy of its links converted to the other
+ * storage, and switch the lattice to the faster storage with its fastest
+ * configuration (gf_set_storage's conversion).  *reals_per_link (may be
+ * NULL) receives the storage chosen, *us_12 and *us_8 (may be NULL) the best
+ * time per sweep of each, in microseconds.  GF_E_STATE for other lattices.
+ * Syncs. */
+gf_status gf_autotune_storage(gf_lattice lat, int32_t n_sweeps, int32_t* reals_per_link, double* us_12,
+                              double* us_8);
+
 /* Free every device buffer of the lattice (waits for its stream).  NULL is accepted. */
 gf_status gf_destroy_lattice(gf_lattice lat);
 

@@ -422,6 +422,40 @@ gf_status download_canonical(gf_lattice L, double* dev_canon)
     return GF_OK;
 }
 
+// Convert the float64 field of an SU(3) GF_FP64 lattice to the other storage
+// (min8 = true: 8 reals per link).  Allocates the new field, converts the
+// links if there are any, frees the old field.  Syncs.
+gf_status do_set_storage(gf_lattice L, bool min8)
+{
+    if (L->group != 3 || L->prec != GF_FP64)
+        return fail(GF_E_STATE, "the storage of links can change on SU(3) GF_FP64 lattices only");
+    if (L->min8 == min8) return GF_OK;
+    const LatticeSizes from = lattice_sizes(L->geom, L->prec, L->group, L->min8);
+    const LatticeSizes to = lattice_sizes(L->geom, L->prec, L->group, min8);
+    double2* f = nullptr;
+    GF_HIP(hipMalloc((void**)&f, to.f64));
+    hipError_t e = hipSuccess;
+    if (L->has_links) {
+        if (min8)
+            e = gf::launch_convert(field64(L), Link8Field{f, L->geom.ld}, L->geom, L->stream);
+        else
+            e = gf::launch_convert(field8(L), LinkField<double>{f, L->geom.ld}, L->geom, L->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(f);
+        return fail(GF_E_HIP, "storage conversion: %s", hipGetErrorString(e));
+    }
+    (void)hipFree(L->f64);
+    L->f64 = f;
+    L->min8 = min8;
+    L->bytes += (int64_t)to.f64 - (int64_t)from.f64;
+    clear_graphs(L);  // captured launches hold the old field's address
+    L->cfg64.minw = 0;
+    L->cfg_hb64.minw = 0;
+    return GF_OK;
+}
+
 void release(gf_lattice L)
 {
     clear_graphs(L);
@@ -551,6 +585,14 @@ gf_status gf_lattice_storage(gf_lattice L, int32_t* reals_per_link)
     if (!L || !reals_per_link) return fail(GF_E_ARG, "null argument");
     *reals_per_link = L->group == 2 ? 4 : (L->min8 ? 8 : 12);
     return GF_OK;
+}
+
+gf_status gf_set_storage(gf_lattice L, int32_t reals_per_link)
+{
+    if (!L) return fail(GF_E_ARG, "null lattice");
+    if (reals_per_link != 8 && reals_per_link != 12)
+        return fail(GF_E_ARG, "reals per link must be 8 or 12 (got %d)", reals_per_link);
+    return do_set_storage(L, reals_per_link == 8);
 }
 
 gf_status gf_lattice_group(gf_lattice L, int32_t* nc)

@@ -104,6 +104,7 @@ gf_status do_fp32_floor(gf_lattice L, double* floor);
 gf_status resolve_switch(gf_lattice L, double theta_target, double theta_switch, double* out);
 gf_status upload_canonical(gf_lattice L, const double* dev_canon);
 gf_status download_canonical(gf_lattice L, double* dev_canon);
+gf_status do_set_storage(gf_lattice L, bool min8);
 void release(gf_lattice L);
 
 // Float32 phase of GF_MIXED: it is left once theta < theta_switch, or once

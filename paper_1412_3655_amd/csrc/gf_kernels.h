@@ -129,6 +129,11 @@ hipError_t launch_plaquette(const Link8Field& f, const Geom& g, double* partial,
 hipError_t launch_pack(const double* canon, const Link8Field& f, const Geom& g, hipStream_t st);
 hipError_t launch_unpack(const Link8Field& f, const Geom& g, double* canon, hipStream_t st);
 
+// Every link of a float64 field converted to the other storage (12 -> 8 reals
+// projects rows 0, 1 onto SU(3) like a store; 8 -> 12 writes the decoded rows).
+hipError_t launch_convert(const LinkField<double>& from, const Link8Field& to, const Geom& g, hipStream_t st);
+hipError_t launch_convert(const Link8Field& from, const LinkField<double>& to, const Geom& g, hipStream_t st);
+
 // Canonical float64 [site][mu][3][3][2] (device) <-> device layout.
 hipError_t launch_pack(const double* canon, const LinkField<double>& f, const Geom& g, hipStream_t st);
 hipError_t launch_pack(const double* canon, const LinkField<float>& f, const Geom& g, hipStream_t st);

@@ -326,6 +326,19 @@ __global__ void __launch_bounds__(RBLOCK) k_unpack(Field f, Geom g, double* cano
         }
 }
 
+// Every link of one field written into another of the other storage (12-real
+// rows 0, 1 with row 2 rebuilt <-> 8-real codec).
+template <typename From, typename To>
+__global__ void __launch_bounds__(RBLOCK) k_convert(From from, To to, uint32_t vh)
+{
+    const uint32_t h = blockIdx.x * RBLOCK + threadIdx.x;
+    if (h >= vh) return;
+    const int parity = blockIdx.y >> 2, mu = blockIdx.y & 3;
+    M3<double> u;
+    load_full_f64(from, parity, mu, h, u);
+    store_link(to, parity, mu, h, u);
+}
+
 uint32_t site_blocks(const Geom& g)
 {
     return (g.vh + RBLOCK - 1) / RBLOCK;
@@ -512,6 +525,19 @@ hipError_t launch_pack(const double* c, const Link8Field& f, const Geom& g, hipS
 hipError_t launch_unpack(const Link8Field& f, const Geom& g, double* c, hipStream_t st)
 {
     return unpack_impl(f, g, c, st);
+}
+
+hipError_t launch_convert(const LinkField<double>& from, const Link8Field& to, const Geom& g, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_convert<LinkField<double>, Link8Field>), dim3(site_blocks(g), 8), dim3(RBLOCK), 0, st, from,
+                       to, g.vh);
+    return hipGetLastError();
+}
+hipError_t launch_convert(const Link8Field& from, const LinkField<double>& to, const Geom& g, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_convert<Link8Field, LinkField<double>>), dim3(site_blocks(g), 8), dim3(RBLOCK), 0, st, from,
+                       to, g.vh);
+    return hipGetLastError();
 }
 
 }  // namespace gf

@@ -36,13 +36,13 @@ std::string device_arch()
 // update and more registers), so they are a kernel of their own: "fp32g".  The
 // Coulomb kernels (K over three directions) are keyed apart with a "-coulomb"
 // suffix, SU(2) lattices with "-su2" and 8-real links with "-min8".
-std::string cache_key(gf_lattice L, gf_prec kernel)
+std::string cache_key(gf_lattice L, gf_prec kernel, bool min8)
 {
     char buf[128];
     const char* k = kernel == GF_FP64 ? "fp64" : (L->gacc.base ? "fp32g" : "fp32");
     snprintf(buf, sizeof buf, "%s %d %d %d %d %s%s%s%s", device_arch().c_str(), L->dims[0], L->dims[1], L->dims[2],
              L->dims[3], k, L->gauge == GAUGE_COULOMB ? "-coulomb" : "", L->group == 2 ? "-su2" : "",
-             L->min8 ? "-min8" : "");
+             min8 ? "-min8" : "");
     return buf;
 }
 
@@ -72,8 +72,12 @@ bool cache_lookup(const char* path, const std::string& key, SweepConfig* out)
 // false) or of the heat-bath sweep (true, at T = 1) of precision `kernel` on a
 // scratch copy of the links, apply the fastest to the lattice and append it to
 // the cache; shared by gf_autotune and gf_autotune_anneal.
+// other_storage (SU(3) GF_FP64 lattices): time the sweep of the lattice's
+// links converted to the other float64 storage (12 <-> 8 reals) on the
+// scratch copy, and leave the lattice's configuration alone (the caller
+// decides whether to switch).
 gf_status tune(gf_lattice L, gf_prec kernel, bool heat_bath, int32_t n_sweeps, const char* cache_path,
-               gf_tune_entry* table, int32_t cap, int32_t* n_out, gf_tune_entry* chosen)
+               gf_tune_entry* table, int32_t cap, int32_t* n_out, gf_tune_entry* chosen, bool other_storage = false)
 {
     GF_TRY(check_ready(L));
     if (kernel != GF_FP64 && kernel != GF_FP32) return fail(GF_E_ARG, "kernel precision must be GF_FP64 or GF_FP32");
@@ -81,9 +85,14 @@ gf_status tune(gf_lattice L, gf_prec kernel, bool heat_bath, int32_t n_sweeps, c
         return fail(GF_E_ARG, "the lattice has no links of that precision");
     if (n_sweeps < 1 || cap < 0 || (cap > 0 && !table)) return fail(GF_E_ARG, "bad arguments");
     if (n_out) *n_out = 0;
-    SweepConfig& target = heat_bath ? (kernel == GF_FP32 ? L->cfg_hb32 : L->cfg_hb64)
-                                    : (kernel == GF_FP32 ? L->cfg32 : L->cfg64);
-    const std::string key = cache_key(L, kernel) + (heat_bath ? "-hb" : "");
+    if (other_storage && (L->group != 3 || L->prec != GF_FP64 || kernel != GF_FP64))
+        return fail(GF_E_STATE, "the storage of links can change on SU(3) GF_FP64 lattices only");
+    const bool m8 = L->min8 != other_storage;  // storage of the links timed
+    SweepConfig scratch_target{};
+    SweepConfig& target = other_storage ? scratch_target
+                                        : heat_bath ? (kernel == GF_FP32 ? L->cfg_hb32 : L->cfg_hb64)
+                                                    : (kernel == GF_FP32 ? L->cfg32 : L->cfg64);
+    const std::string key = cache_key(L, kernel, m8) + (heat_bath ? "-hb" : "");
     SweepConfig best{};
     if (cache_path && cache_lookup(cache_path, key, &best)) {
         target = best;
@@ -93,7 +102,7 @@ gf_status tune(gf_lattice L, gf_prec kernel, bool heat_bath, int32_t n_sweeps, c
 
     const bool su2 = L->group == 2;
     const size_t chunks =
-        (size_t)2 * 4 * L->geom.ld * (kernel == GF_FP32 ? (su2 ? 1 : 3) : (su2 ? 2 : (L->min8 ? kMin8Chunks : 6)));
+        (size_t)2 * 4 * L->geom.ld * (kernel == GF_FP32 ? (su2 ? 1 : 3) : (su2 ? 2 : (m8 ? kMin8Chunks : 6)));
     const size_t bytes = chunks * 16;
     void* scratch = nullptr;
     void* gscratch = nullptr;
@@ -107,7 +116,11 @@ gf_status tune(gf_lattice L, gf_prec kernel, bool heat_bath, int32_t n_sweeps, c
     if (e == hipSuccess && track) e = hipMalloc(&gscratch, gbytes);
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    if (e == hipSuccess)
+    if (e == hipSuccess && other_storage && m8)
+        e = launch_convert(field64(L), Link8Field{(double2*)scratch, L->geom.ld}, L->geom, L->stream);
+    else if (e == hipSuccess && other_storage)
+        e = launch_convert(field8(L), LinkField<double>{(double2*)scratch, L->geom.ld}, L->geom, L->stream);
+    else if (e == hipSuccess)
         e = hipMemcpyAsync(scratch, kernel == GF_FP32 ? (void*)L->f32 : (void*)L->f64, bytes, hipMemcpyDeviceToDevice,
                            L->stream);
     if (e == hipSuccess && track) e = hipMemcpyAsync(gscratch, L->gacc.base, gbytes, hipMemcpyDeviceToDevice, L->stream);
@@ -121,7 +134,7 @@ gf_status tune(gf_lattice L, gf_prec kernel, bool heat_bath, int32_t n_sweeps, c
     uint32_t hb_sweep = 0;
     // the register cap changes only the one-lane float64 kernel (every other
     // shape already runs 2 or more waves per SIMD)
-    const bool cap_axis = !su2 && !L->min8 && kernel == GF_FP64;
+    const bool cap_axis = !su2 && !m8 && kernel == GF_FP64;
     std::vector<SweepConfig> configs;
     for (int minw : {0, 2})
         for (int nt : {0, 1, 2})
@@ -149,9 +162,9 @@ gf_status tune(gf_lattice L, gf_prec kernel, bool heat_bath, int32_t n_sweeps, c
                         r = launch_su2_or(q32, L->geom, p, 1.7f, GF_OR_EXACT, c, L->stream, L->gauge, nullptr);
                     else if (su2)
                         r = launch_su2_or(q64, L->geom, p, 1.7, GF_OR_EXACT, c, L->stream, L->gauge, nullptr);
-                    else if (L->min8 && heat_bath)
+                    else if (m8 && heat_bath)
                         r = launch_hb_half_sweep(f8, L->geom, p, 1.0, 1u, hb_sweep, c, L->stream, L->gauge);
-                    else if (L->min8)
+                    else if (m8)
                         r = launch_or_half_sweep(f8, L->geom, p, 1.7, GF_OR_EXACT, c, L->stream, L->gauge);
                     else if (heat_bath && kernel == GF_FP32)
                         r = launch_hb_half_sweep(f32, L->geom, p, 1.0f, 1u, hb_sweep, c, track ? g_s : g_none,
@@ -216,6 +229,27 @@ extern "C" gf_status gf_autotune(gf_lattice L, gf_prec kernel, int32_t n_sweeps,
 {
     TraceRange range("gf_autotune");
     return tune(L, kernel, false, n_sweeps, cache_path, table, cap, n_out, chosen);
+}
+
+extern "C" gf_status gf_autotune_storage(gf_lattice L, int32_t n_sweeps, int32_t* reals_per_link, double* us_12,
+                                         double* us_8)
+{
+    TraceRange range("gf_autotune_storage");
+    GF_TRY(check_ready(L));
+    if (L->group != 3 || L->prec != GF_FP64)
+        return fail(GF_E_STATE, "the storage of links can change on SU(3) GF_FP64 lattices only");
+    gf_tune_entry cur{}, oth{};
+    GF_TRY(tune(L, GF_FP64, false, n_sweeps, nullptr, nullptr, 0, nullptr, &cur, false));
+    GF_TRY(tune(L, GF_FP64, false, n_sweeps, nullptr, nullptr, 0, nullptr, &oth, true));
+    const double t_cur = cur.us_per_sweep, t_oth = oth.us_per_sweep;
+    if (us_12) *us_12 = L->min8 ? t_oth : t_cur;
+    if (us_8) *us_8 = L->min8 ? t_cur : t_oth;
+    if (t_oth < t_cur) {
+        GF_TRY(do_set_storage(L, !L->min8));
+        L->cfg64 = SweepConfig{oth.tps, oth.block, oth.nontemporal, oth.min_waves};
+    }
+    if (reals_per_link) *reals_per_link = L->min8 ? 8 : 12;
+    return GF_OK;
 }
 
 extern "C" gf_status gf_autotune_anneal(gf_lattice L, gf_prec kernel, int32_t n_sweeps, const char* cache_path,

@@ -119,6 +119,9 @@ _SIGNATURES = {
     "gf_lattice_group": [_vp, ctypes.POINTER(_i32)],
     "gf_create_lattice_min8": [ctypes.POINTER(_i32), _vp, ctypes.POINTER(_vp)],
     "gf_lattice_storage": [_vp, ctypes.POINTER(_i32)],
+    "gf_set_storage": [_vp, _i32],
+    "gf_autotune_storage": [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_double),
+                            ctypes.POINTER(ctypes.c_double)],
     "gf_lattice_info": [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
     "gf_set_sweep_config": [_vp, ctypes.c_int, _i32, _i32, _i32, _i32],
     "gf_set_anneal_config": [_vp, ctypes.c_int, _i32, _i32, _i32, _i32],
@@ -285,6 +288,19 @@ def gf_lattice_storage(lat) -> int:
     n = _i32()
     _call("gf_lattice_storage", lat, ctypes.byref(n))
     return n.value
+
+
+def gf_set_storage(lat, reals_per_link: int) -> None:
+    _call("gf_set_storage", lat, int(reals_per_link))
+
+
+def gf_autotune_storage(lat, n_sweeps: int = 3):
+    """(reals per link chosen, us per sweep with 12 reals, with 8 reals)."""
+    n = _i32()
+    a = ctypes.c_double()
+    b = ctypes.c_double()
+    _call("gf_autotune_storage", lat, int(n_sweeps), ctypes.byref(n), ctypes.byref(a), ctypes.byref(b))
+    return n.value, a.value, b.value
 
 
 def gf_lattice_group(lat) -> int:
@@ -536,6 +552,18 @@ class Lattice:
     @property
     def volume(self) -> int:
         return gf_lattice_info(self.handle)[0]
+
+    @property
+    def storage(self) -> int:
+        """Reals stored per link (12, 8 or 4); assign 8 or 12 to convert a float64 SU(3) lattice."""
+        return gf_lattice_storage(self.handle)
+
+    @storage.setter
+    def storage(self, reals_per_link: int):
+        gf_set_storage(self.handle, reals_per_link)
+
+    def autotune_storage(self, n_sweeps: int = 3):
+        return gf_autotune_storage(self.handle, n_sweeps)
 
     def close(self):
         if self.handle is not None and self.handle.value:

@@ -8,7 +8,8 @@ the stored links are SU(3) to rounding, so the sweep must match the oracle's pla
 from the links the representation holds (oracle.min8_store of the input), to the tolerances of
 the 12-real float64 path: 1e-12 after one sweep, 1e-10 after 100, theta relative 1e-12, F 1e-14.
 The decode/encode pair itself: set_links then get_links reproduces the oracle's stored links to
-4e-15.  Launch shapes give bitwise equal links.
+4e-15.  Launch shapes give bitwise equal links.  The storage of a float64 lattice can also be
+switched at run time (gf_set_storage) and chosen by timing (gf_autotune_storage).
 """
 
 import sys
@@ -293,3 +294,73 @@ def test_full_size_32x4_one_sweep():
         say(f"  max|diff| after 1 sweep: {d:.3e}")
         assert d <= 1e-12
         assert abs(th1 - th1_o) <= 1e-10 * th1_o and abs(F1 - F1_o) <= 1e-13
+
+
+def test_set_storage_converts_both_ways():
+    """12 -> 8 reals holds the oracle's stored links (4e-15), 8 -> 12 keeps them bitwise; sweeps
+    after each conversion match the oracle from those links; graphs captured before a conversion
+    are not replayed on the freed field."""
+    import torch
+
+    dims = RAGGED
+    u = gi.gen_links(dims, 0.7, 78)
+    stream = torch.cuda.Stream()
+    with gf.Lattice(dims, gf.GF_FP64, stream=stream) as lat:
+        lat.set_links(u)
+        lat.sweep(2, 1.7)  # captures a graph over the 12-real field
+        before = lat.get_links()
+        b12 = gf.gf_lattice_info(lat.handle)[1]
+        lat.storage = 8
+        assert lat.storage == 8 and gf.gf_lattice_info(lat.handle)[1] < b12
+        got8 = lat.get_links()
+        assert float(np.abs(got8 - stored(before)).max()) <= 4e-15
+        ref = got8.copy()
+        oracle.sweep(ref, dims, 2, 1.7, 0)
+        lat.sweep(2, 1.7)  # a new graph over the 8-real field
+        after8 = lat.get_links()
+        assert float(np.abs(after8 - ref).max()) <= 1e-12
+        lat.storage = 12
+        assert lat.storage == 12 and gf.gf_lattice_info(lat.handle)[1] == b12
+        assert np.array_equal(lat.get_links(), after8)
+        ref = after8.copy()
+        oracle.sweep(ref, dims, 2, 1.7, 0)
+        lat.sweep(2, 1.7)
+        assert float(np.abs(lat.get_links() - ref).max()) <= 1e-12
+        with pytest.raises(gf.GFError) as e:
+            lat.storage = 9
+        assert e.value.status == gf.GF_E_ARG
+    for prec, group in ((gf.GF_MIXED, 3), (gf.GF_FP32, 3), (gf.GF_FP64, 2)):
+        with gf.Lattice(dims, prec, group=group) as lat:
+            with pytest.raises(gf.GFError) as e:
+                lat.storage = 8
+            assert e.value.status == gf.GF_E_STATE
+
+
+@pytest.mark.parametrize("start", [12, 8])
+def test_autotune_storage(start):
+    """The tuner times both storages and keeps the faster, with its configuration; the links are
+    those of the chosen storage (unchanged when the storage stays, the stored projection when it
+    switches to 8 reals)."""
+    dims = (16, 16, 16, 16)
+    u = gi.gen_links(dims, 0.8, 79)
+    with gf.Lattice(dims, gf.GF_FP64, storage=start) as lat:
+        lat.set_links(u)
+        before = lat.get_links()
+        reals, us12, us8 = lat.autotune_storage(2)
+        say(f"storage autotune from {start}: chose {reals}; 12 reals {us12:.1f} us, 8 reals {us8:.1f} us")
+        assert reals in (8, 12) and lat.storage == reals and us12 > 0 and us8 > 0
+        assert reals == (8 if us8 < us12 else 12)
+        got = lat.get_links()
+        if reals == start:
+            assert np.array_equal(got, before)
+        else:
+            assert float(np.abs(got - stored(before)).max()) <= 4e-15
+        ref = got.copy()
+        oracle.sweep(ref, dims, 1, 1.7, 0)
+        lat.sweep(1, 1.7)
+        assert float(np.abs(lat.get_links() - ref).max()) <= 1e-12
+    with gf.Lattice(dims, gf.GF_MIXED) as lat:
+        lat.set_links(u)
+        with pytest.raises(gf.GFError) as e:
+            lat.autotune_storage(2)
+        assert e.value.status == gf.GF_E_STATE
