@@ -299,11 +299,12 @@ def serving_leg(gf, inputs, stream, args):
            "distinct_inputs": len(seeds), "last_arrival_s": jobs[-1].arrival, "pool_tps32": t32, "pool_tps64": t64,
            "hbm_budget_bytes": budget,
            "largest_job_bytes": max(gf.gf_pool_job_bytes(j.dims, gf.GF_MIXED) for j in jobs)}
-    st = serving.run_pool(jobs, links_of, gf.GF_MIXED, 10, 256, budget, fix, True, t32, t64)
+    jlog = log if args.serve_verbose else None
+    st = serving.run_pool(jobs, links_of, gf.GF_MIXED, 10, 256, budget, fix, True, t32, t64, log=jlog)
     out["pool_mixed"] = st.summary()
     log(f"serving pool: {st.converged}/{len(jobs)} converged, {st.seconds:.1f} s, max queue {st.max_queue}, "
         f"peak {st.peak_bytes / 1e9:.2f} GB")
-    st = serving.run_fifo(jobs, links_of, gf.GF_FP64, fix, True, args.tps, args.block, args.nt)
+    st = serving.run_fifo(jobs, links_of, gf.GF_FP64, fix, True, args.tps, args.block, args.nt, log=jlog)
     out["fifo_fp64"] = st.summary()
     log(f"serving fifo: {st.converged}/{len(jobs)} converged, {st.seconds:.1f} s")
     a, b = out["pool_mixed"]["converged_lattices_per_s"], out["fifo_fp64"]["converged_lattices_per_s"]
@@ -311,10 +312,10 @@ def serving_leg(gf, inputs, stream, args):
     if args.serve_closed:
         # the same jobs all queued at t = 0: peak throughput, latency counted from t = 0
         closed = {}
-        st = serving.run_pool(jobs, links_of, gf.GF_MIXED, 10, 256, budget, fix, False, t32, t64)
+        st = serving.run_pool(jobs, links_of, gf.GF_MIXED, 10, 256, budget, fix, False, t32, t64, log=jlog)
         closed["pool_mixed"] = st.summary()
         log(f"serving closed loop pool: {st.converged}/{len(jobs)} converged, {st.seconds:.1f} s")
-        st = serving.run_fifo(jobs, links_of, gf.GF_FP64, fix, False, args.tps, args.block, args.nt)
+        st = serving.run_fifo(jobs, links_of, gf.GF_FP64, fix, False, args.tps, args.block, args.nt, log=jlog)
         closed["fifo_fp64"] = st.summary()
         log(f"serving closed loop fifo: {st.converged}/{len(jobs)} converged, {st.seconds:.1f} s")
         a, b = closed["pool_mixed"]["converged_lattices_per_s"], closed["fifo_fp64"]["converged_lattices_per_s"]
@@ -536,6 +537,8 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="further timed regions of --steps sweeps after the headline one (median and spread)")
     ap.add_argument("--dims", type=str, default="32,32,32,32")
     ap.add_argument("--eps", type=float, default=0.8)
     ap.add_argument("--seed", type=int, default=0)
@@ -570,6 +573,7 @@ def main(argv=None):
     ap.add_argument("--serve", action="store_true", help="(the serving leg runs by default; kept for scripts)")
     ap.add_argument("--no-serve", action="store_true", help="skip the Poisson-arrival serving workload")
     ap.add_argument("--serve-jobs", type=int, default=100)
+    ap.add_argument("--serve-verbose", action="store_true", help="log every finished serving job")
     ap.add_argument("--serve-closed", action="store_true",
                     help="also run the serving jobs closed loop (all queued at t = 0: peak lattices/s)")
     ap.add_argument("--serve-budget-gb", type=float, default=4.0,
@@ -657,6 +661,9 @@ def main(argv=None):
             lat.sweep(args.warmup, args.omega, args.mode)
             lat.sweep(args.chunk, args.omega, args.mode)  # captures the chunk's graph
             total, wall, per_launch = time_run(lat, torch, stream, args.steps, args.omega, args.mode, args.chunk)
+            # further timed regions of the same length, reported beside the headline region
+            repeats = [time_run(lat, torch, stream, args.steps, args.omega, args.mode, args.chunk)
+                       for _ in range(args.repeats)]
             lat.sweep(args.chunk, args.omega, 1 - args.mode)
             total_other, _, _ = time_run(lat, torch, stream, args.steps, args.omega, 1 - args.mode, args.chunk)
         th, F = lat.measure()
@@ -664,7 +671,7 @@ def main(argv=None):
         log(f"fp64: {args.steps} sweeps in {total * 1e3:.2f} ms (mean half-sweep {per_launch * 1e6:.1f} us); "
             f"theta {th:.3e} F {F:.6f} dP {abs(P1 - P0):.1e}")
         result["f64"] = dict(total=total, wall=wall, per_launch=per_launch, theta=th, F=F, dplaq=abs(P1 - P0),
-                             total_other=total_other)
+                             total_other=total_other, repeats=repeats)
 
     if not args.no_fp32:
         with gf.Lattice(dims, gf.GF_FP32, stream=stream) as lat:
@@ -750,6 +757,16 @@ def main(argv=None):
         },
         "input_generation_s": t_gen,
     }
+    if r64["repeats"]:
+        reps = sorted(V * args.steps / t for (t, _, _) in r64["repeats"])
+        line["repeats"] = {
+            "count": len(reps),
+            "value_median": reps[len(reps) // 2],
+            "value_min": reps[0],
+            "value_max": reps[-1],
+            "mean_launch_us": [round(p * 1e6, 2) for (_, _, p) in r64["repeats"]],
+            "note": "further timed regions of --steps sweeps each, after the headline region",
+        }
     if "f32" in result:
         r32 = result["f32"]
         rate32 = V * args.steps / r32["total"]
@@ -783,6 +800,12 @@ def main(argv=None):
         fix8 = fix_8x4_leg(gf, torch, inputs.get((8, 8, 8, 8), 0.6, 0), args)
         line["fix_8x4"] = {k: {kk: vv for kk, vv in v.items() if kk != "links"} for k, v in fix8.items()}
     line["device_copy_GBps"] = copy_bandwidth(gf)
+    copy_best = max(line["device_copy_GBps"].values())
+    line["roofline"]["frac_of_copy"] = line["roofline"]["achieved"] / copy_best
+    for leg in (line.get("fullsize_48x96_f64"), *(line.get("f64_min8", {}).get(k) for k in
+                                                  ("bandwidth_lattice", "fullsize_48x96"))):
+        if leg:
+            leg["roofline"]["frac_of_copy"] = leg["roofline"]["achieved"] / copy_best
     if not args.no_batched:
         line["batched_64"] = batched_leg(gf, inputs, stream, args)
     if not args.no_serve:
