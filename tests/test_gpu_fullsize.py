@@ -101,6 +101,9 @@ def test_48x96_mixed_pipeline_invariants(big_links):
         f"theta {th_g:.3e} F {F_g:.9f} converged {r.converged}; |dP| {abs(P - P0):.2e}")
     assert abs(P - P0) < 1e-12
     assert F_g >= F_a - 1e-6
+    # this eps = 1.0 input is one of the rough ones that do not reach 1e-13 within the cap (the
+    # design notes' input section); the iteration must still have reduced theta by 3 decades
+    assert th_g < 1e-3 * th_a
     du, dd = oracle.unitarity(links)
     assert du < 1e-12 and dd < 1e-12
     th_o, F_o = oracle.measure(links, BIG)
