@@ -253,21 +253,25 @@ def batched_leg(gf, inputs, stream, args):
            "jobs": 64, "sites": sum(serving.volume(j.dims) for j in jobs), "max_sweeps": args.job_max_sweeps,
            "pool_tps32": t32, "pool_tps64": t64}
     tune = not args.no_pool_autotune
+    ov = not args.no_overlap
     out["pool_autotune"] = tune
+    out["pool_overlap"] = ov
     legs = [("pool_mixed", lambda: serving.run_pool(jobs, lambda j: links[j.job_id], gf.GF_MIXED, 10, 64, None,
-                                                    fix, False, t32, t64, autotune=tune))]
+                                                    fix, False, t32, t64, autotune=tune, overlap=ov))]
     if args.batched_fp64_pool:
         legs.append(("pool_fp64", lambda: serving.run_pool(jobs, lambda j: links[j.job_id], gf.GF_FP64, 10, 64,
-                                                           None, fix, False, t32, t64, autotune=tune)))
-    legs.append(("fifo_fp64", lambda: serving.run_fifo(jobs, lambda j: links[j.job_id], gf.GF_FP64, fix, False,
-                                                       args.tps, args.block, args.nt)))
+                                                           None, fix, False, t32, t64, autotune=tune, overlap=ov)))
+    if not args.no_fifo:
+        legs.append(("fifo_fp64", lambda: serving.run_fifo(jobs, lambda j: links[j.job_id], gf.GF_FP64, fix, False,
+                                                           args.tps, args.block, args.nt)))
     for name, fn in legs:
         st = fn()
         out[name] = st.summary()
         log(f"batched {name}: {st.converged}/64 converged in {st.seconds:.2f} s")
-    out["speedup_converged_per_s_pool_mixed_vs_fifo_fp64"] = (
-        (out["pool_mixed"]["converged_lattices_per_s"] or 0) / out["fifo_fp64"]["converged_lattices_per_s"]
-        if out["fifo_fp64"]["converged_lattices_per_s"] else None)
+    if "fifo_fp64" in out:
+        out["speedup_converged_per_s_pool_mixed_vs_fifo_fp64"] = (
+            (out["pool_mixed"]["converged_lattices_per_s"] or 0) / out["fifo_fp64"]["converged_lattices_per_s"]
+            if out["fifo_fp64"]["converged_lattices_per_s"] else None)
     return out
 
 
@@ -298,12 +302,16 @@ def serving_leg(gf, inputs, stream, args):
            "jobs": len(jobs), "rate_per_s": 20.0, "max_sweeps": args.job_max_sweeps,
            "distinct_inputs": len(seeds), "last_arrival_s": jobs[-1].arrival, "pool_tps32": t32, "pool_tps64": t64,
            "hbm_budget_bytes": budget,
-           "largest_job_bytes": max(gf.gf_pool_job_bytes(j.dims, gf.GF_MIXED) for j in jobs)}
+           "largest_job_bytes": max(gf.gf_pool_job_bytes(j.dims, gf.GF_MIXED) for j in jobs),
+           "pool_overlap": not args.no_overlap}
+    ov = not args.no_overlap
     jlog = log if args.serve_verbose else None
-    st = serving.run_pool(jobs, links_of, gf.GF_MIXED, 10, 256, budget, fix, True, t32, t64, log=jlog)
+    st = serving.run_pool(jobs, links_of, gf.GF_MIXED, 10, 256, budget, fix, True, t32, t64, log=jlog, overlap=ov)
     out["pool_mixed"] = st.summary()
     log(f"serving pool: {st.converged}/{len(jobs)} converged, {st.seconds:.1f} s, max queue {st.max_queue}, "
         f"peak {st.peak_bytes / 1e9:.2f} GB")
+    if args.no_fifo:
+        return out
     st = serving.run_fifo(jobs, links_of, gf.GF_FP64, fix, True, args.tps, args.block, args.nt, log=jlog)
     out["fifo_fp64"] = st.summary()
     log(f"serving fifo: {st.converged}/{len(jobs)} converged, {st.seconds:.1f} s")
@@ -312,7 +320,8 @@ def serving_leg(gf, inputs, stream, args):
     if args.serve_closed:
         # the same jobs all queued at t = 0: peak throughput, latency counted from t = 0
         closed = {}
-        st = serving.run_pool(jobs, links_of, gf.GF_MIXED, 10, 256, budget, fix, False, t32, t64, log=jlog)
+        st = serving.run_pool(jobs, links_of, gf.GF_MIXED, 10, 256, budget, fix, False, t32, t64, log=jlog,
+                              overlap=ov)
         closed["pool_mixed"] = st.summary()
         log(f"serving closed loop pool: {st.converged}/{len(jobs)} converged, {st.seconds:.1f} s")
         st = serving.run_fifo(jobs, links_of, gf.GF_FP64, fix, False, args.tps, args.block, args.nt, log=jlog)
@@ -578,6 +587,11 @@ def main(argv=None):
                     help="also run the serving jobs closed loop (all queued at t = 0: peak lattices/s)")
     ap.add_argument("--serve-budget-gb", type=float, default=4.0,
                     help="HBM budget of the serving pool in GB (0: 80 %% of free device memory)")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="batched and serving pools: step, retire and admit one after another instead of "
+                         "retiring and admitting while the next step runs")
+    ap.add_argument("--no-fifo", action="store_true",
+                    help="batched and serving legs: skip the float64 one-lattice-at-a-time comparison")
     ap.add_argument("--pool-tps32", type=int, default=2,
                     help="lanes per site of the pool's float32 sweeps (2: fastest over the batched set on MI355X)")
     ap.add_argument("--no-pool-autotune", action="store_true",

@@ -431,12 +431,18 @@ gf_status gf_plaquette(gf_lattice lat, double* P);
 /* measurement launches cover the jobs due for them; the launches of a step  */
 /* are captured once in a hipGraph per work structure and replayed with each */
 /* sweep node's grid set to the step's tile count.                            */
+/*                                                                            */
+/* A step can be left in flight (gf_pool_step_async) while the host admits,   */
+/* polls, fetches and releases jobs: these touch only jobs the step does not  */
+/* use, and move links on a transfer stream of the pool's own, so the host's  */
+/* work overlaps the GPU's.  Results are the same either way.                 */
 /* ------------------------------------------------------------------------ */
 
 typedef struct gf_pool_* gf_pool; /* opaque, library-owned */
 
 typedef struct {
-    size_t hbm_budget;   /* bytes of device memory the pool may hold for job lattices */
+    size_t hbm_budget;   /* bytes of device memory the pool may hold for job lattices (its tables and
+                            the 33.6 MB staging buffer of admissions and fetches come on top) */
     int32_t max_slots;   /* maximum number of resident jobs, 1..4096 */
     int32_t prec;        /* gf_prec of every job: GF_MIXED or GF_FP64 */
     int32_t check_every; /* sweeps per pool step = every job's measurement cadence, >= 1 */
@@ -455,15 +461,16 @@ typedef struct {
     gf_fix_result result;
     int32_t status; /* GF_OK, or the error that ended the job (e.g. GF_E_NUMERIC); other jobs are unaffected */
     double t_admit; /* seconds on the library's steady clock */
-    double t_done;  /* end of the pool step in which the job finished */
+    double t_done;  /* when the pool step in which the job finished was completed */
 } gf_pool_done;
 
-/* Create a pool.  hip_stream: a non-default hipStream_t for all pool work,
- * or NULL to let the pool create its own (default priority).  Allocates only
- * bookkeeping; job lattices are allocated on admission. */
+/* Create a pool.  hip_stream: a non-default hipStream_t for the pool's steps,
+ * or NULL to let the pool create its own (default priority); admissions and
+ * fetches use a second stream the pool creates.  Allocates bookkeeping and a
+ * 33.6 MB staging buffer; job lattices are allocated on admission. */
 gf_status gf_pool_create(const gf_pool_config* cfg, void* hip_stream, gf_pool* out);
 
-/* Wait for the pool's stream and free everything, including unreleased jobs.  NULL is accepted. */
+/* Wait for the pool's streams and free everything, including unreleased jobs.  NULL is accepted. */
 gf_status gf_pool_destroy(gf_pool pool);
 
 /* Device bytes one job of extents dims needs in a pool of precision prec. */
@@ -473,26 +480,45 @@ gf_status gf_pool_job_bytes(const int32_t dims[4], int32_t prec, int64_t* bytes)
  * resident lattice, then (if anneal_sweeps > 0) run anneal_sweeps heat-bath
  * sweeps from T_start to T_end with Philox key `seed` (as gf_anneal) before the
  * fix-until iteration with params (as gf_fix_until; params->mode must equal the
- * pool's mode).  GF_E_FULL (nothing changed) when no slot is free or the
- * budget would be exceeded; GF_E_ARG for a duplicate job_id or bad
- * arguments.  Syncs (the first measurement of a job without annealing). */
+ * pool's mode).  The links move in chunks through the staging buffer on the
+ * transfer stream, beside a step in flight, which the job joins at the next
+ * step.  Returns once host_links has been read and, for a job without
+ * annealing, its first measurement taken (a non-finite one admits the job,
+ * which finishes at once with GF_E_NUMERIC).  GF_E_FULL (nothing changed) when
+ * no slot is free or the budget would be exceeded (lattices released during a
+ * step in flight count until it is completed); GF_E_ARG for a duplicate job_id
+ * or bad arguments.  Syncs the transfer stream. */
 gf_status gf_pool_admit(gf_pool pool, uint64_t job_id, const int32_t dims[4], const double* host_links,
                         const gf_fix_params* params, int32_t anneal_sweeps, double T_start, double T_end,
                         uint64_t seed);
 
-/* One pool step (see above).  Syncs. */
+/* One pool step (see above): completes a step in flight, then runs the next.  Syncs. */
 gf_status gf_pool_step(gf_pool pool);
+
+/* Complete the step in flight (if any: wait for it, free lattices released
+ * meanwhile, finish or advance its jobs, so that gf_pool_poll reports those
+ * that finished), then plan and launch the next step and return without
+ * waiting for it.  Launches nothing when no job is active. */
+gf_status gf_pool_step_async(gf_pool pool);
+
+/* Complete the step in flight, if any (as gf_pool_step_async does first).  Syncs. */
+gf_status gf_pool_sync(gf_pool pool);
 
 /* Move up to cap jobs that finished since the last poll into out[]; *n = count. */
 gf_status gf_pool_poll(gf_pool pool, gf_pool_done* out, int32_t cap, int32_t* n);
 
-/* Download a finished job's links (host canonical array) and free its lattice.  Syncs. */
+/* Download a finished job's links (host canonical array) through the staging
+ * buffer on the transfer stream, beside a step in flight, and free its
+ * lattice (as gf_pool_release).  Syncs the transfer stream. */
 gf_status gf_pool_fetch_links(gf_pool pool, uint64_t job_id, double* host);
 
-/* Free a finished job's lattice without downloading it. */
+/* Free a finished job's lattice without downloading it; while a step is in
+ * flight the lattice is freed, and its bytes returned to the budget, when
+ * that step is completed (freeing device memory synchronises the device). */
 gf_status gf_pool_release(gf_pool pool, uint64_t job_id);
 
-/* Cancel a resident job that has not finished: it takes no further part in
+/* Cancel a resident job that has not finished (a step in flight is completed
+ * first, so the job may finish in it instead): it takes no further part in
  * pool steps and is reported by the next gf_pool_poll with status
  * GF_E_CANCELLED and its last measured theta and F (converged = 0); its links
  * stay resident until gf_pool_release / gf_pool_fetch_links.  Other jobs are
@@ -501,7 +527,8 @@ gf_status gf_pool_release(gf_pool pool, uint64_t job_id);
 gf_status gf_pool_cancel(gf_pool pool, uint64_t job_id);
 
 /* Autotuner of the pool's batched overrelaxation sweep (threads per site and
- * block size, Sec. 4 and 5 of the paper tune these at run time): copies the
+ * block size, Sec. 4 and 5 of the paper tune these at run time; a step in
+ * flight is completed first): copies the
  * `kernel` links (GF_FP32: the float32 links and g(x) of a GF_MIXED pool;
  * GF_FP64: the float64 links) of the resident jobs, in slot order and up to
  * scratch_bytes of copies, times one warm-up and n_sweeps sweeps (both
@@ -517,7 +544,9 @@ gf_status gf_pool_autotune(gf_pool pool, int32_t kernel, int32_t n_sweeps, size_
 /* The pool's current sweep shape (any pointer may be NULL). */
 gf_status gf_pool_get_shape(gf_pool pool, int32_t* tps32, int32_t* block32, int32_t* tps64, int32_t* block64);
 
-/* Resident jobs still iterating, finished jobs not yet released, and device bytes held. */
+/* Resident jobs still iterating, finished jobs not yet released, and device
+ * bytes held for job lattices (including those released during a step in
+ * flight and not yet freed). */
 gf_status gf_pool_stats(gf_pool pool, int32_t* active, int32_t* finished, int64_t* bytes_in_use);
 
 /* Bandwidth probe: a plain float4 copy of `bytes` (>= 4096, multiple of 16)

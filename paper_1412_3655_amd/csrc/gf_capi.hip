@@ -258,56 +258,73 @@ gf_status do_promote(gf_lattice L)
 // Coulomb gauge: theta_C(t), F_C(t) of every timeslice into L->hslices;
 // *theta = the largest theta_C(t) (the condition holds once it holds in every
 // timeslice), *F = the mean of F_C(t), added in timeslice order.
-gf_status do_measure_slices(gf_lattice L, double* theta, double* F)
+// The measurement's kernels and the copy of its result to pinned host memory,
+// enqueued on `st` (the lattice's stream, or another one that no work on the
+// lattice runs on meanwhile); measure_read takes the result after `st` has
+// been synchronised.
+gf_status measure_enqueue(gf_lattice L, hipStream_t st)
 {
-    if (L->group == 2 && is_fp32(L))
-        GF_HIP(gf::launch_su2_measure(su2_32(L), L->geom, gf::GAUGE_COULOMB, L->partial, L->dslices, L->stream));
-    else if (L->group == 2)
-        GF_HIP(gf::launch_su2_measure(su2_64(L), L->geom, gf::GAUGE_COULOMB, L->partial, L->dslices, L->stream));
-    else if (L->min8)
-        GF_HIP(gf::launch_measure_slices(field8(L), L->geom, L->partial, L->dslices, L->stream));
-    else if (is_fp32(L))
-        GF_HIP(gf::launch_measure_slices(field32(L), L->geom, L->partial, L->dslices, L->stream));
-    else
-        GF_HIP(gf::launch_measure_slices(field64(L), L->geom, L->partial, L->dslices, L->stream));
-    const int nt = L->dims[3];
-    GF_HIP(hipMemcpyAsync(L->hslices, L->dslices, 2 * (size_t)nt * sizeof(double), hipMemcpyDeviceToHost, L->stream));
-    GF_HIP(hipStreamSynchronize(L->stream));
-    double th = 0.0, f = 0.0;
-    bool finite = true;
-    for (int t = 0; t < nt; ++t) {
-        const double a = L->hslices[2 * t], b = L->hslices[2 * t + 1];
-        finite = finite && std::isfinite(a) && std::isfinite(b);
-        if (a > th) th = a;
-        f += b;
+    if (L->gauge == gf::GAUGE_COULOMB) {
+        if (L->group == 2 && is_fp32(L))
+            GF_HIP(gf::launch_su2_measure(su2_32(L), L->geom, gf::GAUGE_COULOMB, L->partial, L->dslices, st));
+        else if (L->group == 2)
+            GF_HIP(gf::launch_su2_measure(su2_64(L), L->geom, gf::GAUGE_COULOMB, L->partial, L->dslices, st));
+        else if (L->min8)
+            GF_HIP(gf::launch_measure_slices(field8(L), L->geom, L->partial, L->dslices, st));
+        else if (is_fp32(L))
+            GF_HIP(gf::launch_measure_slices(field32(L), L->geom, L->partial, L->dslices, st));
+        else
+            GF_HIP(gf::launch_measure_slices(field64(L), L->geom, L->partial, L->dslices, st));
+        GF_HIP(hipMemcpyAsync(L->hslices, L->dslices, 2 * (size_t)L->dims[3] * sizeof(double), hipMemcpyDeviceToHost,
+                              st));
+        return GF_OK;
     }
-    *theta = th;
-    *F = f / (double)nt;
-    if (!finite) return fail(GF_E_NUMERIC, "a timeslice's theta_C or F_C is not finite");
+    if (L->group == 2 && is_fp32(L))
+        GF_HIP(gf::launch_su2_measure(su2_32(L), L->geom, gf::GAUGE_LANDAU, L->partial, L->dres, st));
+    else if (L->group == 2)
+        GF_HIP(gf::launch_su2_measure(su2_64(L), L->geom, gf::GAUGE_LANDAU, L->partial, L->dres, st));
+    else if (L->min8)
+        GF_HIP(gf::launch_measure(field8(L), L->geom, L->partial, L->dres, st));
+    else if (is_fp32(L))
+        GF_HIP(gf::launch_measure(field32(L), L->geom, L->partial, L->dres, st));
+    else
+        GF_HIP(gf::launch_measure(field64(L), L->geom, L->partial, L->dres, st));
+    GF_HIP(hipMemcpyAsync(L->hres, L->dres, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    return GF_OK;
+}
+
+// Coulomb gauge: theta is the largest timeslice's theta_C, F the mean of the
+// timeslices' F_C.
+gf_status measure_read(gf_lattice L, double* theta, double* F)
+{
+    if (L->gauge == gf::GAUGE_COULOMB) {
+        const int nt = L->dims[3];
+        double th = 0.0, f = 0.0;
+        bool finite = true;
+        for (int t = 0; t < nt; ++t) {
+            const double a = L->hslices[2 * t], b = L->hslices[2 * t + 1];
+            finite = finite && std::isfinite(a) && std::isfinite(b);
+            if (a > th) th = a;
+            f += b;
+        }
+        *theta = th;
+        *F = f / (double)nt;
+        if (!finite) return fail(GF_E_NUMERIC, "a timeslice's theta_C or F_C is not finite");
+        return GF_OK;
+    }
+    *theta = L->hres[0];
+    *F = L->hres[1];
+    if (!std::isfinite(*theta) || !std::isfinite(*F))
+        return fail(GF_E_NUMERIC, "theta = %g, F = %g is not finite", *theta, *F);
     return GF_OK;
 }
 
 gf_status do_measure(gf_lattice L, double* theta, double* F)
 {
     ++L->n_measures;
-    if (L->gauge == gf::GAUGE_COULOMB) return do_measure_slices(L, theta, F);
-    if (L->group == 2 && is_fp32(L))
-        GF_HIP(gf::launch_su2_measure(su2_32(L), L->geom, gf::GAUGE_LANDAU, L->partial, L->dres, L->stream));
-    else if (L->group == 2)
-        GF_HIP(gf::launch_su2_measure(su2_64(L), L->geom, gf::GAUGE_LANDAU, L->partial, L->dres, L->stream));
-    else if (L->min8)
-        GF_HIP(gf::launch_measure(field8(L), L->geom, L->partial, L->dres, L->stream));
-    else if (is_fp32(L))
-        GF_HIP(gf::launch_measure(field32(L), L->geom, L->partial, L->dres, L->stream));
-    else
-        GF_HIP(gf::launch_measure(field64(L), L->geom, L->partial, L->dres, L->stream));
-    GF_HIP(hipMemcpyAsync(L->hres, L->dres, 2 * sizeof(double), hipMemcpyDeviceToHost, L->stream));
+    GF_TRY(measure_enqueue(L, L->stream));
     GF_HIP(hipStreamSynchronize(L->stream));
-    *theta = L->hres[0];
-    *F = L->hres[1];
-    if (!std::isfinite(*theta) || !std::isfinite(*F))
-        return fail(GF_E_NUMERIC, "theta = %g, F = %g is not finite", *theta, *F);
-    return GF_OK;
+    return measure_read(L, theta, F);
 }
 
 // One sweep whose half-sweeps also sum tr[Delta Delta^dag] of every site's K
@@ -807,7 +824,9 @@ gf_status gf_measure_timeslices(gf_lattice L, double* theta_t, double* F_t)
     if (!theta_t || !F_t) return fail(GF_E_ARG, "null argument");
     if (L->gauge != gf::GAUGE_COULOMB) return fail(GF_E_STATE, "per-timeslice values need a Coulomb-gauge lattice");
     double th = 0.0, f = 0.0;
-    GF_TRY(do_measure_slices(L, &th, &f));
+    GF_TRY(measure_enqueue(L, L->stream));
+    GF_HIP(hipStreamSynchronize(L->stream));
+    GF_TRY(measure_read(L, &th, &f));
     for (int t = 0; t < L->dims[3]; ++t) {
         theta_t[t] = L->hslices[2 * t];
         F_t[t] = L->hslices[2 * t + 1];

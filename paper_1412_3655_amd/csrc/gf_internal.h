@@ -99,6 +99,8 @@ gf_status do_sweeps(gf_lattice L, int32_t n, double omega, int mode);
 gf_status do_reunitarize(gf_lattice L);
 gf_status do_promote(gf_lattice L);
 gf_status do_measure(gf_lattice L, double* theta, double* F);
+gf_status measure_enqueue(gf_lattice L, hipStream_t st);
+gf_status measure_read(gf_lattice L, double* theta, double* F);
 gf_status do_est_sweep(gf_lattice L, double omega, int mode, double* theta_est);
 gf_status do_fp32_floor(gf_lattice L, double* floor);
 gf_status resolve_switch(gf_lattice L, double theta_target, double theta_switch, double* out);

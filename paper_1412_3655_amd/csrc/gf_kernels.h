@@ -139,6 +139,17 @@ hipError_t launch_pack(const double* canon, const LinkField<double>& f, const Ge
 hipError_t launch_pack(const double* canon, const LinkField<float>& f, const Geom& g, hipStream_t st);
 hipError_t launch_unpack(const LinkField<double>& f, const Geom& g, double* canon, hipStream_t st);
 hipError_t launch_unpack(const LinkField<float>& f, const Geom& g, double* canon, hipStream_t st);
+// The same for the canonical links first .. first+n-1 (4 per site, lexicographic
+// site order), held at canon[0 .. 18 n): a lattice moves through a staging
+// buffer smaller than itself.  The range must lie inside the lattice.
+hipError_t launch_pack_range(const double* canon, const LinkField<double>& f, const Geom& g, uint64_t first,
+                             uint64_t n, hipStream_t st);
+hipError_t launch_pack_range(const double* canon, const LinkField<float>& f, const Geom& g, uint64_t first,
+                             uint64_t n, hipStream_t st);
+hipError_t launch_unpack_range(const LinkField<double>& f, const Geom& g, double* canon, uint64_t first, uint64_t n,
+                               hipStream_t st);
+hipError_t launch_unpack_range(const LinkField<float>& f, const Geom& g, double* canon, uint64_t first, uint64_t n,
+                               hipStream_t st);
 
 // Mixed precision: g(x) <- 1; Gram-Schmidt of g; and the float64 rebuild
 // U_mu(x) <- g(x) U0_mu(x) g(x+mu^)^dag in place over the float64 field that

@@ -279,19 +279,20 @@ __device__ __forceinline__ void lex_to_half(const Geom& g, uint32_t s, int* pari
 }
 
 // R: the field's real type; Field: 12-real LinkField<R> or 8-real Link8Field
-// (rows 0 and 1 of the canonical link are encoded).
+// (rows 0 and 1 of the canonical link are encoded).  Links first .. first+n-1
+// (canonical order, 4 per site), read from canon[0 .. 18 n).
 template <typename R, typename Field>
-__global__ void __launch_bounds__(RBLOCK) k_pack(const double* canon, Field f, Geom g)
+__global__ void __launch_bounds__(RBLOCK) k_pack(const double* canon, Field f, Geom g, uint64_t first, uint64_t n)
 {
-    const uint64_t gid = (uint64_t)blockIdx.x * RBLOCK + threadIdx.x;
-    const uint64_t nlinks = (uint64_t)g.vh * 8;
-    if (gid >= nlinks) return;
+    const uint64_t i = (uint64_t)blockIdx.x * RBLOCK + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t gid = first + i;
     const uint32_t s = (uint32_t)(gid >> 2);
     const int mu = (int)(gid & 3);
     int parity;
     uint32_t h;
     lex_to_half(g, s, &parity, &h);
-    const double* src = canon + gid * 18;
+    const double* src = canon + i * 18;
     M3<R> u;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -303,12 +304,13 @@ __global__ void __launch_bounds__(RBLOCK) k_pack(const double* canon, Field f, G
     store_link(f, parity, mu, h, u);
 }
 
+// Links first .. first+n-1 written to canon[0 .. 18 n).
 template <typename Field>
-__global__ void __launch_bounds__(RBLOCK) k_unpack(Field f, Geom g, double* canon)
+__global__ void __launch_bounds__(RBLOCK) k_unpack(Field f, Geom g, double* canon, uint64_t first, uint64_t n)
 {
-    const uint64_t gid = (uint64_t)blockIdx.x * RBLOCK + threadIdx.x;
-    const uint64_t nlinks = (uint64_t)g.vh * 8;
-    if (gid >= nlinks) return;
+    const uint64_t i = (uint64_t)blockIdx.x * RBLOCK + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t gid = first + i;
     const uint32_t s = (uint32_t)(gid >> 2);
     const int mu = (int)(gid & 3);
     int parity;
@@ -316,7 +318,7 @@ __global__ void __launch_bounds__(RBLOCK) k_unpack(Field f, Geom g, double* cano
     lex_to_half(g, s, &parity, &h);
     M3<double> u;
     load_full_f64(f, parity, mu, h, u);
-    double* dst = canon + gid * 18;
+    double* dst = canon + i * 18;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -389,21 +391,30 @@ hipError_t reunit_impl(const LinkField<R>& f, const Geom& g, hipStream_t st)
     return hipGetLastError();
 }
 
+// n = 0 stands for every link of the lattice; a range must lie inside it.
 template <typename R, typename Field>
-hipError_t pack_impl(const double* canon, const Field& f, const Geom& g, hipStream_t st)
+hipError_t pack_impl(const double* canon, const Field& f, const Geom& g, hipStream_t st, uint64_t first = 0,
+                     uint64_t n = 0)
 {
-    const uint64_t n = (uint64_t)g.vh * 8;
+    const uint64_t nlinks = (uint64_t)g.vh * 8;
+    if (n == 0 && first == 0) n = nlinks;
+    if (first > nlinks || n > nlinks - first) return hipErrorInvalidValue;
+    if (n == 0) return hipSuccess;
     hipLaunchKernelGGL((k_pack<R, Field>), dim3((uint32_t)((n + RBLOCK - 1) / RBLOCK)), dim3(RBLOCK), 0, st, canon, f,
-                       g);
+                       g, first, n);
     return hipGetLastError();
 }
 
 template <typename Field>
-hipError_t unpack_impl(const Field& f, const Geom& g, double* canon, hipStream_t st)
+hipError_t unpack_impl(const Field& f, const Geom& g, double* canon, hipStream_t st, uint64_t first = 0,
+                       uint64_t n = 0)
 {
-    const uint64_t n = (uint64_t)g.vh * 8;
+    const uint64_t nlinks = (uint64_t)g.vh * 8;
+    if (n == 0 && first == 0) n = nlinks;
+    if (first > nlinks || n > nlinks - first) return hipErrorInvalidValue;
+    if (n == 0) return hipSuccess;
     hipLaunchKernelGGL((k_unpack<Field>), dim3((uint32_t)((n + RBLOCK - 1) / RBLOCK)), dim3(RBLOCK), 0, st, f, g,
-                       canon);
+                       canon, first, n);
     return hipGetLastError();
 }
 
@@ -504,6 +515,26 @@ hipError_t launch_unpack(const LinkField<double>& f, const Geom& g, double* c, h
 hipError_t launch_unpack(const LinkField<float>& f, const Geom& g, double* c, hipStream_t st)
 {
     return unpack_impl(f, g, c, st);
+}
+hipError_t launch_pack_range(const double* c, const LinkField<double>& f, const Geom& g, uint64_t first, uint64_t n,
+                             hipStream_t st)
+{
+    return n ? pack_impl<double>(c, f, g, st, first, n) : hipSuccess;
+}
+hipError_t launch_pack_range(const double* c, const LinkField<float>& f, const Geom& g, uint64_t first, uint64_t n,
+                             hipStream_t st)
+{
+    return n ? pack_impl<float>(c, f, g, st, first, n) : hipSuccess;
+}
+hipError_t launch_unpack_range(const LinkField<double>& f, const Geom& g, double* c, uint64_t first, uint64_t n,
+                               hipStream_t st)
+{
+    return n ? unpack_impl(f, g, c, st, first, n) : hipSuccess;
+}
+hipError_t launch_unpack_range(const LinkField<float>& f, const Geom& g, double* c, uint64_t first, uint64_t n,
+                               hipStream_t st)
+{
+    return n ? unpack_impl(f, g, c, st, first, n) : hipSuccess;
 }
 
 hipError_t launch_measure(const Link8Field& f, const Geom& g, double* p, double* o, hipStream_t st)

@@ -20,6 +20,14 @@
 // coefficients of the exact power in registers, which pushes the float64
 // sweep over the register file into accumulation-register spills.
 //
+// A step may be left running while the host admits, polls, fetches and
+// releases jobs (gf_pool_step_async): those touch only lattices that the step
+// in flight does not use, on a second stream, so the host's work (copying a
+// job's links from pageable memory through a fixed staging buffer, packing
+// them, its first measurement) overlaps the GPU's.  Lattices released while a
+// step runs are freed when it has been completed (freeing synchronises the
+// device).
+//
 // The per-site bodies are the same functions the single-lattice kernels use
 // (gf_site.h) and the block decomposition of the measurement is the same, so
 // every job's links, theta and F are bitwise those of the same job run alone
@@ -45,6 +53,9 @@ constexpr int kHeatBathBlock = 128;  // threads per block of the heat-bath sweep
 // with g: 2 lanes, float64: 1 lane, 3 % ahead of 2; 128 threads for both);
 // gf_pool_autotune picks them for the resident mix.
 constexpr int kDefaultTps32 = 2, kDefaultTps64 = 1, kDefaultBlock = 128;
+// Staging buffer through which admissions and fetches move a job's canonical
+// links (18 doubles per link) in chunks; a multiple of one site's 4 links.
+constexpr size_t kStageLinks = (size_t)4 * 58254;  // 33.6 MB
 
 struct SlotDev {
     LinkField<double> f64;
@@ -344,6 +355,11 @@ struct gf_pool_ {
     std::vector<uint32_t> seg_tiles;     // tiles per (k, kind) list of the step being launched
     std::vector<size_t> launch_log;      // (k, kind) segment of every launch while capturing
     int grid_other = 0;                  // persistent grid of the reunitarisation / measurement kernels
+    // transfers of admitted / fetched jobs, beside a step in flight
+    hipStream_t xfer = nullptr;
+    double* stage = nullptr;  // kStageLinks canonical links
+    bool in_flight = false;   // a launched step has not been completed
+    std::vector<std::pair<gf_lattice, int64_t>> deferred;  // released while a step ran: freed at its completion
 };
 
 namespace {
@@ -658,189 +674,78 @@ void enter_fix(gf_pool P, Job& j)
     if (st != GF_OK) finish(P, j, st);
 }
 
+// A finished job's lattice is not used by a step in flight, but freeing device
+// memory synchronises the device: while a step runs, the lattice waits (its
+// bytes still counted) until the step is completed.
 void release_job(gf_pool P, Job& j)
 {
-    if (j.lat) {
+    if (j.lat && P->in_flight) {
+        P->deferred.emplace_back(j.lat, j.bytes);
+    } else if (j.lat) {
         (void)gf_destroy_lattice(j.lat);
         P->bytes_in_use -= j.bytes;
     }
     j = Job();
 }
 
-}  // namespace
-
-extern "C" {
-
-double gf_clock(void)
+void free_deferred(gf_pool P)
 {
-    return now_s();
+    for (auto& d : P->deferred) {
+        (void)gf_destroy_lattice(d.first);
+        P->bytes_in_use -= d.second;
+    }
+    P->deferred.clear();
 }
 
-gf_status gf_pool_job_bytes(const int32_t dims[4], int32_t prec, int64_t* bytes)
+// A job's canonical links in from host memory, chunk by chunk through the
+// staging buffer, on the transfer stream; returns once the host buffer has been
+// read and the lattice is packed.
+gf_status upload_job(gf_pool P, gf_lattice L, const double* host)
 {
-    if (!dims || !bytes) return fail(GF_E_ARG, "null argument");
-    for (int m = 0; m < 4; ++m)
-        if (dims[m] < 2 || dims[m] % 2) return fail(GF_E_ARG, "extents must be even and >= 2");
-    if (prec != GF_FP64 && prec != GF_MIXED && prec != GF_FP32) return fail(GF_E_ARG, "bad precision");
-    int64_t V = 1;
-    GF_TRY(check_dims(dims, &V));
-    *bytes = lattice_bytes(dims, prec);
-    if (*bytes < 0) return fail(GF_E_ARG, "internal: index division check failed");
+    const uint64_t nlinks = (uint64_t)L->volume * 4;
+    hipError_t e = hipSuccess;
+    for (uint64_t first = 0; first < nlinks && e == hipSuccess; first += kStageLinks) {
+        const uint64_t n = std::min<uint64_t>(kStageLinks, nlinks - first);
+        e = hipMemcpyAsync(P->stage, host + first * 18, n * 18 * sizeof(double), hipMemcpyHostToDevice, P->xfer);
+        if (e == hipSuccess && L->f32) e = gf::launch_pack_range(P->stage, field32(L), L->geom, first, n, P->xfer);
+        if (e == hipSuccess && L->f64) e = gf::launch_pack_range(P->stage, field64(L), L->geom, first, n, P->xfer);
+    }
+    if (e == hipSuccess && L->gacc.base) e = gf::launch_g_identity(L->gacc, L->geom, P->xfer);
+    const hipError_t es = hipStreamSynchronize(P->xfer);  // also after a failed enqueue: nothing stays queued
+    if (e == hipSuccess) e = es;
+    if (e != hipSuccess) return fail(GF_E_HIP, "admission upload: %s", hipGetErrorString(e));
+    L->phase = 0;
+    L->has_links = true;
+    L->anneal_sweeps = 0;
     return GF_OK;
 }
 
-gf_status gf_pool_create(const gf_pool_config* cfg, void* hip_stream, gf_pool* out)
+// A finished job's links out to host memory the same way (the field its
+// result is in: float64 once promoted).
+gf_status download_job(gf_pool P, gf_lattice L, double* host)
 {
-    if (!cfg || !out) return fail(GF_E_ARG, "null argument");
-    *out = nullptr;
-    if (cfg->max_slots < 1 || cfg->max_slots > 4096) return fail(GF_E_ARG, "max_slots must be 1..4096");
-    if (cfg->prec != GF_MIXED && cfg->prec != GF_FP64) return fail(GF_E_ARG, "pool precision must be GF_MIXED or GF_FP64");
-    if (cfg->check_every < 1 || cfg->check_every > 1000) return fail(GF_E_ARG, "check_every must be 1..1000");
-    if (cfg->mode != GF_OR_EXACT && cfg->mode != GF_OR_BINOMIAL1) return fail(GF_E_ARG, "unknown mode");
-    gf_pool_config c = *cfg;
-    if (c.tps32 == 0) c.tps32 = kDefaultTps32;
-    if (c.tps64 == 0) c.tps64 = kDefaultTps64;
-    if (c.block32 == 0) c.block32 = kDefaultBlock;
-    if (c.block64 == 0) c.block64 = kDefaultBlock;
-    GF_TRY(check_pool_shape(c.tps32, c.block32));
-    GF_TRY(check_pool_shape(c.tps64, c.block64));
-
-    gf_pool_* P = new (std::nothrow) gf_pool_();
-    if (!P) return fail(GF_E_NOMEM, "host allocation failed");
-    P->cfg = c;
-    P->chunk = c.check_every;
-    if (hip_stream) {
-        P->stream = (hipStream_t)hip_stream;
-    } else {
-        hipError_t e = hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking);
-        if (e != hipSuccess) {
-            delete P;
-            return fail(GF_E_HIP, "hipStreamCreate: %s", hipGetErrorString(e));
-        }
-        P->own_stream = true;
-    }
-    P->jobs.resize(c.max_slots);
-    P->slot_host.resize(c.max_slots);
-    P->list_stride = (size_t)c.max_slots + 1;
-    const size_t nseg = (size_t)P->chunk * NKIND;
-    hipError_t e = hipMalloc((void**)&P->slots_dev, sizeof(SlotDev) * c.max_slots);
-    if (e == hipSuccess) e = hipMalloc((void**)&P->lists_dev, sizeof(Entry) * nseg * P->list_stride);
-    if (e == hipSuccess) e = hipMalloc((void**)&P->counts_dev, sizeof(uint32_t) * nseg);
-    if (e == hipSuccess) e = hipMalloc((void**)&P->results_dev, sizeof(double) * 2 * c.max_slots);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&P->slots_pin, sizeof(SlotDev) * c.max_slots, hipHostMallocDefault);
-    if (e == hipSuccess)
-        e = hipHostMalloc((void**)&P->lists_pin, sizeof(Entry) * nseg * P->list_stride, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&P->counts_pin, sizeof(uint32_t) * nseg, hipHostMallocDefault);
-    if (e == hipSuccess)
-        e = hipHostMalloc((void**)&P->results_pin, sizeof(double) * 2 * c.max_slots, hipHostMallocDefault);
-    int dev = 0, ncu = 0;
-    if (e == hipSuccess) e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess) {
-        gf_pool_destroy(P);
-        return fail(GF_E_HIP, "pool allocation failed: %s", hipGetErrorString(e));
-    }
-    // persistent grid of the reunitarisation / measurement kernels: a few resident blocks per compute unit
-    P->grid_other = 4 * ncu;
-    P->seg_tiles.assign(nseg, 0);
-    std::memset(P->slots_pin, 0, sizeof(SlotDev) * c.max_slots);
-    *out = P;
-    return GF_OK;
-}
-
-gf_status gf_pool_destroy(gf_pool P)
-{
-    if (!P) return GF_OK;
-    if (P->stream) (void)hipStreamSynchronize(P->stream);
-    for (auto& j : P->jobs) release_job(P, j);
-    for (auto& kv : P->graphs) destroy_step_graph(kv.second);
-    if (P->slots_dev) (void)hipFree(P->slots_dev);
-    if (P->lists_dev) (void)hipFree(P->lists_dev);
-    if (P->counts_dev) (void)hipFree(P->counts_dev);
-    if (P->results_dev) (void)hipFree(P->results_dev);
-    if (P->slots_pin) (void)hipHostFree(P->slots_pin);
-    if (P->lists_pin) (void)hipHostFree(P->lists_pin);
-    if (P->counts_pin) (void)hipHostFree(P->counts_pin);
-    if (P->results_pin) (void)hipHostFree(P->results_pin);
-    if (P->own_stream && P->stream) (void)hipStreamDestroy(P->stream);
-    delete P;
-    return GF_OK;
-}
-
-gf_status gf_pool_admit(gf_pool P, uint64_t job_id, const int32_t dims[4], const double* host_links,
-                        const gf_fix_params* params, int32_t anneal_sweeps, double T_start, double T_end,
-                        uint64_t seed)
-{
-    GF_TRY(pool_check(P));
-    if (!dims || !host_links || !params) return fail(GF_E_ARG, "null argument");
-    GF_TRY(check_omega(params->omega, params->mode));
-    if (params->mode != P->cfg.mode) return fail(GF_E_ARG, "job mode %d differs from the pool's %d", params->mode,
-                                                 P->cfg.mode);
-    if (params->check_every != P->cfg.check_every)
-        return fail(GF_E_ARG, "job check_every %d differs from the pool's %d", params->check_every, P->cfg.check_every);
-    if (params->max_sweeps < 0 || params->reunit_every < 0 || !(params->theta_target >= 0.0) ||
-        std::isnan(params->theta_switch))
-        return fail(GF_E_ARG, "bad fix parameters");
-    if (anneal_sweeps < 0) return fail(GF_E_ARG, "anneal_sweeps < 0");
-    if (anneal_sweeps > 0 && (!(T_end > 0.0) || !(T_start >= T_end) || !std::isfinite(T_start)))
-        return fail(GF_E_ARG, "need T_start >= T_end > 0");
-    for (auto& j : P->jobs)
-        if (j.lat && j.id == job_id) return fail(GF_E_ARG, "job id %llu is already in the pool", (unsigned long long)job_id);
-    int64_t bytes = 0;
-    GF_TRY(gf_pool_job_bytes(dims, P->cfg.prec, &bytes));
-    int slot = -1;
-    for (int s = 0; s < (int)P->jobs.size(); ++s)
-        if (!P->jobs[s].lat) {
-            slot = s;
-            break;
-        }
-    if (slot < 0) return fail(GF_E_FULL, "all %d slots are taken", P->cfg.max_slots);
-    if ((size_t)(P->bytes_in_use + bytes) > P->cfg.hbm_budget)
-        return fail(GF_E_FULL, "job needs %lld bytes, %lld of %zu in use", (long long)bytes,
-                    (long long)P->bytes_in_use, P->cfg.hbm_budget);
-
-    gf_lattice L = nullptr;
-    GF_TRY(gf_create_lattice(dims, (gf_prec)P->cfg.prec, P->stream, &L));
-    // the job's own lattice object takes the pool's shape (its solo kernels
-    // are not used for sweeps while it is in the pool)
-    L->cfg32 = SweepConfig{P->cfg.tps32, P->cfg.block32};
-    L->cfg64 = SweepConfig{P->cfg.tps64, P->cfg.block64};
-    gf_status st = gf_set_links(L, host_links);
-    if (st != GF_OK) {
-        gf_destroy_lattice(L);
-        return st;
-    }
-    Job& j = P->jobs[slot];
-    j = Job();
-    j.id = job_id;
-    j.lat = L;
-    j.slot = slot;
-    j.p = *params;
-    j.anneal_total = anneal_sweeps;
-    j.T0 = T_start;
-    j.T1 = T_end;
-    j.seed = seed;
-    j.t_admit = now_s();
-    j.bytes = L->bytes;
-    P->bytes_in_use += j.bytes;
-    if (anneal_sweeps > 0) {
-        j.state = J_ANNEAL;
-    } else {
-        j.state = J_FIX;
-        st = do_measure(L, &j.theta, &j.F);
-        if (st != GF_OK)
-            finish(P, j, st);
+    const uint64_t nlinks = (uint64_t)L->volume * 4;
+    hipError_t e = hipSuccess;
+    for (uint64_t first = 0; first < nlinks && e == hipSuccess; first += kStageLinks) {
+        const uint64_t n = std::min<uint64_t>(kStageLinks, nlinks - first);
+        if (is_fp32(L))
+            e = gf::launch_unpack_range(field32(L), L->geom, P->stage, first, n, P->xfer);
         else
-            enter_fix(P, j);
+            e = gf::launch_unpack_range(field64(L), L->geom, P->stage, first, n, P->xfer);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(host + first * 18, P->stage, n * 18 * sizeof(double), hipMemcpyDeviceToHost, P->xfer);
     }
-    fill_slot(P, slot);
+    const hipError_t es = hipStreamSynchronize(P->xfer);
+    if (e == hipSuccess) e = es;
+    if (e != hipSuccess) return fail(GF_E_HIP, "fetch: %s", hipGetErrorString(e));
     return GF_OK;
 }
 
-gf_status gf_pool_step(gf_pool P)
+// Loop heads of the jobs in the fix phase, then the plan of the next step:
+// work lists, slot table, the graph launch and the copy of the results, all
+// enqueued; the step is in flight until complete_step.
+gf_status launch_step(gf_pool P)
 {
-    TraceRange range("gf_pool_step");
-    GF_TRY(pool_check(P));
     const int C = P->chunk;
     // loop heads (finish / promote) of jobs in the fix phase
     for (auto& j : P->jobs)
@@ -911,9 +816,18 @@ gf_status gf_pool_step(gf_pool P)
     GF_TRY(run_graph(P, sig));
     GF_HIP(hipMemcpyAsync(P->results_pin, P->results_dev, sizeof(double) * 2 * P->jobs.size(), hipMemcpyDeviceToHost,
                           P->stream));
-    GF_HIP(hipStreamSynchronize(P->stream));
+    P->in_flight = true;
+    return GF_OK;
+}
 
-    // apply the step's outcome
+// Wait for the step in flight (if any), free what was released meanwhile, and
+// apply the step's outcome to its jobs.
+gf_status complete_step(gf_pool P)
+{
+    if (!P->in_flight) return GF_OK;
+    P->in_flight = false;
+    GF_HIP(hipStreamSynchronize(P->stream));
+    free_deferred(P);
     for (auto& j : P->jobs) {
         if (!j.lat || j.state == J_DONE || j.plan_n == 0) continue;
         gf_lattice L = j.lat;
@@ -945,6 +859,222 @@ gf_status gf_pool_step(gf_pool P)
     return GF_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+double gf_clock(void)
+{
+    return now_s();
+}
+
+gf_status gf_pool_job_bytes(const int32_t dims[4], int32_t prec, int64_t* bytes)
+{
+    if (!dims || !bytes) return fail(GF_E_ARG, "null argument");
+    for (int m = 0; m < 4; ++m)
+        if (dims[m] < 2 || dims[m] % 2) return fail(GF_E_ARG, "extents must be even and >= 2");
+    if (prec != GF_FP64 && prec != GF_MIXED && prec != GF_FP32) return fail(GF_E_ARG, "bad precision");
+    int64_t V = 1;
+    GF_TRY(check_dims(dims, &V));
+    *bytes = lattice_bytes(dims, prec);
+    if (*bytes < 0) return fail(GF_E_ARG, "internal: index division check failed");
+    return GF_OK;
+}
+
+gf_status gf_pool_create(const gf_pool_config* cfg, void* hip_stream, gf_pool* out)
+{
+    if (!cfg || !out) return fail(GF_E_ARG, "null argument");
+    *out = nullptr;
+    if (cfg->max_slots < 1 || cfg->max_slots > 4096) return fail(GF_E_ARG, "max_slots must be 1..4096");
+    if (cfg->prec != GF_MIXED && cfg->prec != GF_FP64) return fail(GF_E_ARG, "pool precision must be GF_MIXED or GF_FP64");
+    if (cfg->check_every < 1 || cfg->check_every > 1000) return fail(GF_E_ARG, "check_every must be 1..1000");
+    if (cfg->mode != GF_OR_EXACT && cfg->mode != GF_OR_BINOMIAL1) return fail(GF_E_ARG, "unknown mode");
+    gf_pool_config c = *cfg;
+    if (c.tps32 == 0) c.tps32 = kDefaultTps32;
+    if (c.tps64 == 0) c.tps64 = kDefaultTps64;
+    if (c.block32 == 0) c.block32 = kDefaultBlock;
+    if (c.block64 == 0) c.block64 = kDefaultBlock;
+    GF_TRY(check_pool_shape(c.tps32, c.block32));
+    GF_TRY(check_pool_shape(c.tps64, c.block64));
+
+    gf_pool_* P = new (std::nothrow) gf_pool_();
+    if (!P) return fail(GF_E_NOMEM, "host allocation failed");
+    P->cfg = c;
+    P->chunk = c.check_every;
+    if (hip_stream) {
+        P->stream = (hipStream_t)hip_stream;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete P;
+            return fail(GF_E_HIP, "hipStreamCreate: %s", hipGetErrorString(e));
+        }
+        P->own_stream = true;
+    }
+    P->jobs.resize(c.max_slots);
+    P->slot_host.resize(c.max_slots);
+    P->list_stride = (size_t)c.max_slots + 1;
+    const size_t nseg = (size_t)P->chunk * NKIND;
+    hipError_t e = hipMalloc((void**)&P->slots_dev, sizeof(SlotDev) * c.max_slots);
+    if (e == hipSuccess) e = hipMalloc((void**)&P->lists_dev, sizeof(Entry) * nseg * P->list_stride);
+    if (e == hipSuccess) e = hipMalloc((void**)&P->counts_dev, sizeof(uint32_t) * nseg);
+    if (e == hipSuccess) e = hipMalloc((void**)&P->results_dev, sizeof(double) * 2 * c.max_slots);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&P->slots_pin, sizeof(SlotDev) * c.max_slots, hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void**)&P->lists_pin, sizeof(Entry) * nseg * P->list_stride, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&P->counts_pin, sizeof(uint32_t) * nseg, hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void**)&P->results_pin, sizeof(double) * 2 * c.max_slots, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void**)&P->stage, kStageLinks * 18 * sizeof(double));
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->xfer, hipStreamNonBlocking);
+    int dev = 0, ncu = 0;
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) {
+        gf_pool_destroy(P);
+        return fail(GF_E_HIP, "pool allocation failed: %s", hipGetErrorString(e));
+    }
+    // persistent grid of the reunitarisation / measurement kernels: a few resident blocks per compute unit
+    P->grid_other = 4 * ncu;
+    P->seg_tiles.assign(nseg, 0);
+    std::memset(P->slots_pin, 0, sizeof(SlotDev) * c.max_slots);
+    *out = P;
+    return GF_OK;
+}
+
+gf_status gf_pool_destroy(gf_pool P)
+{
+    if (!P) return GF_OK;
+    if (P->stream) (void)hipStreamSynchronize(P->stream);
+    if (P->xfer) (void)hipStreamSynchronize(P->xfer);
+    P->in_flight = false;
+    free_deferred(P);
+    for (auto& j : P->jobs) release_job(P, j);
+    for (auto& kv : P->graphs) destroy_step_graph(kv.second);
+    if (P->slots_dev) (void)hipFree(P->slots_dev);
+    if (P->lists_dev) (void)hipFree(P->lists_dev);
+    if (P->counts_dev) (void)hipFree(P->counts_dev);
+    if (P->results_dev) (void)hipFree(P->results_dev);
+    if (P->slots_pin) (void)hipHostFree(P->slots_pin);
+    if (P->lists_pin) (void)hipHostFree(P->lists_pin);
+    if (P->counts_pin) (void)hipHostFree(P->counts_pin);
+    if (P->results_pin) (void)hipHostFree(P->results_pin);
+    if (P->stage) (void)hipFree(P->stage);
+    if (P->xfer) (void)hipStreamDestroy(P->xfer);
+    if (P->own_stream && P->stream) (void)hipStreamDestroy(P->stream);
+    delete P;
+    return GF_OK;
+}
+
+gf_status gf_pool_admit(gf_pool P, uint64_t job_id, const int32_t dims[4], const double* host_links,
+                        const gf_fix_params* params, int32_t anneal_sweeps, double T_start, double T_end,
+                        uint64_t seed)
+{
+    GF_TRY(pool_check(P));
+    if (!dims || !host_links || !params) return fail(GF_E_ARG, "null argument");
+    GF_TRY(check_omega(params->omega, params->mode));
+    if (params->mode != P->cfg.mode) return fail(GF_E_ARG, "job mode %d differs from the pool's %d", params->mode,
+                                                 P->cfg.mode);
+    if (params->check_every != P->cfg.check_every)
+        return fail(GF_E_ARG, "job check_every %d differs from the pool's %d", params->check_every, P->cfg.check_every);
+    if (params->max_sweeps < 0 || params->reunit_every < 0 || !(params->theta_target >= 0.0) ||
+        std::isnan(params->theta_switch))
+        return fail(GF_E_ARG, "bad fix parameters");
+    if (anneal_sweeps < 0) return fail(GF_E_ARG, "anneal_sweeps < 0");
+    if (anneal_sweeps > 0 && (!(T_end > 0.0) || !(T_start >= T_end) || !std::isfinite(T_start)))
+        return fail(GF_E_ARG, "need T_start >= T_end > 0");
+    for (auto& j : P->jobs)
+        if (j.lat && j.id == job_id) return fail(GF_E_ARG, "job id %llu is already in the pool", (unsigned long long)job_id);
+    int64_t bytes = 0;
+    GF_TRY(gf_pool_job_bytes(dims, P->cfg.prec, &bytes));
+    int slot = -1;
+    for (int s = 0; s < (int)P->jobs.size(); ++s)
+        if (!P->jobs[s].lat) {
+            slot = s;
+            break;
+        }
+    if (slot < 0) return fail(GF_E_FULL, "all %d slots are taken", P->cfg.max_slots);
+    if ((size_t)(P->bytes_in_use + bytes) > P->cfg.hbm_budget)
+        return fail(GF_E_FULL, "job needs %lld bytes, %lld of %zu in use", (long long)bytes,
+                    (long long)P->bytes_in_use, P->cfg.hbm_budget);
+
+    gf_lattice L = nullptr;
+    GF_TRY(gf_create_lattice(dims, (gf_prec)P->cfg.prec, P->stream, &L));
+    // the job's own lattice object takes the pool's shape (its solo kernels
+    // are not used for sweeps while it is in the pool)
+    L->cfg32 = SweepConfig{P->cfg.tps32, P->cfg.block32};
+    L->cfg64 = SweepConfig{P->cfg.tps64, P->cfg.block64};
+    gf_status st = upload_job(P, L, host_links);
+    double theta = 0.0, F = 0.0;
+    if (st == GF_OK && anneal_sweeps == 0) {
+        // the first measurement of gf_fix_until, beside a step in flight
+        ++L->n_measures;
+        st = measure_enqueue(L, P->xfer);
+        const hipError_t e = hipStreamSynchronize(P->xfer);
+        if (st == GF_OK && e != hipSuccess) st = fail(GF_E_HIP, "admission measurement: %s", hipGetErrorString(e));
+        if (st == GF_OK) {
+            st = measure_read(L, &theta, &F);
+            if (st == GF_E_NUMERIC) st = GF_OK;  // admitted: the job finishes with GF_E_NUMERIC below
+        }
+    }
+    if (st != GF_OK) {
+        if (P->in_flight)
+            P->deferred.emplace_back(L, 0);
+        else
+            gf_destroy_lattice(L);
+        return st;
+    }
+    Job& j = P->jobs[slot];
+    j = Job();
+    j.id = job_id;
+    j.lat = L;
+    j.slot = slot;
+    j.p = *params;
+    j.anneal_total = anneal_sweeps;
+    j.T0 = T_start;
+    j.T1 = T_end;
+    j.seed = seed;
+    j.t_admit = now_s();
+    j.bytes = L->bytes;
+    P->bytes_in_use += j.bytes;
+    if (anneal_sweeps > 0) {
+        j.state = J_ANNEAL;
+    } else {
+        j.state = J_FIX;
+        j.theta = theta;
+        j.F = F;
+        if (!std::isfinite(theta) || !std::isfinite(F))
+            finish(P, j, GF_E_NUMERIC);
+        else
+            enter_fix(P, j);
+    }
+    fill_slot(P, slot);
+    return GF_OK;
+}
+
+gf_status gf_pool_step(gf_pool P)
+{
+    TraceRange range("gf_pool_step");
+    GF_TRY(pool_check(P));
+    GF_TRY(complete_step(P));
+    GF_TRY(launch_step(P));
+    return complete_step(P);
+}
+
+gf_status gf_pool_step_async(gf_pool P)
+{
+    TraceRange range("gf_pool_step_async");
+    GF_TRY(pool_check(P));
+    GF_TRY(complete_step(P));
+    return launch_step(P);
+}
+
+gf_status gf_pool_sync(gf_pool P)
+{
+    GF_TRY(pool_check(P));
+    return complete_step(P);
+}
+
 gf_status gf_pool_poll(gf_pool P, gf_pool_done* out, int32_t cap, int32_t* n)
 {
     GF_TRY(pool_check(P));
@@ -963,8 +1093,8 @@ gf_status gf_pool_fetch_links(gf_pool P, uint64_t job_id, double* host)
     for (auto& j : P->jobs)
         if (j.lat && j.id == job_id) {
             if (j.state != J_DONE) return fail(GF_E_STATE, "job %llu has not finished", (unsigned long long)job_id);
-            gf_status st = gf_get_links(j.lat, host);
-            if (st != GF_OK) return st;
+            GF_TRY(check_ready(j.lat));
+            GF_TRY(download_job(P, j.lat, host));
             release_job(P, j);
             return GF_OK;
         }
@@ -986,6 +1116,7 @@ gf_status gf_pool_release(gf_pool P, uint64_t job_id)
 gf_status gf_pool_cancel(gf_pool P, uint64_t job_id)
 {
     GF_TRY(pool_check(P));
+    GF_TRY(complete_step(P));  // the job may be in the step in flight
     for (auto& j : P->jobs)
         if (j.lat && j.id == job_id) {
             if (j.state == J_DONE) return fail(GF_E_STATE, "job %llu has already finished", (unsigned long long)job_id);
@@ -1000,6 +1131,7 @@ gf_status gf_pool_autotune(gf_pool P, int32_t kernel, int32_t n_sweeps, size_t s
 {
     TraceRange range("gf_pool_autotune");
     GF_TRY(pool_check(P));
+    GF_TRY(complete_step(P));  // it times launches of the resident jobs' fields
     if (kernel != GF_FP32 && kernel != GF_FP64) return fail(GF_E_ARG, "kernel must be GF_FP32 or GF_FP64");
     if (kernel == GF_FP32 && P->cfg.prec != GF_MIXED)
         return fail(GF_E_ARG, "a GF_FP64 pool has no float32 sweeps to tune");

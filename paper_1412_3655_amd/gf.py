@@ -157,6 +157,8 @@ _SIGNATURES = {
     "gf_pool_admit": [_vp, ctypes.c_uint64, ctypes.POINTER(_i32), _dp, ctypes.POINTER(gf_fix_params), _i32,
                       ctypes.c_double, ctypes.c_double, ctypes.c_uint64],
     "gf_pool_step": [_vp],
+    "gf_pool_step_async": [_vp],
+    "gf_pool_sync": [_vp],
     "gf_pool_poll": [_vp, ctypes.POINTER(gf_pool_done), _i32, ctypes.POINTER(_i32)],
     "gf_pool_fetch_links": [_vp, ctypes.c_uint64, _dp],
     "gf_pool_release": [_vp, ctypes.c_uint64],
@@ -727,6 +729,14 @@ def gf_pool_step(pool) -> None:
     _call("gf_pool_step", pool)
 
 
+def gf_pool_step_async(pool) -> None:
+    _call("gf_pool_step_async", pool)
+
+
+def gf_pool_sync(pool) -> None:
+    _call("gf_pool_sync", pool)
+
+
 def gf_pool_poll(pool, cap: int = 256):
     """Finished jobs since the last poll: list of dicts."""
     buf = (gf_pool_done * cap)()
@@ -814,6 +824,13 @@ class Pool:
 
     def step(self):
         gf_pool_step(self.handle)
+
+    def step_async(self):
+        """Complete the step in flight, launch the next and return without waiting for it."""
+        gf_pool_step_async(self.handle)
+
+    def sync(self):
+        gf_pool_sync(self.handle)
 
     def poll(self, cap: int = 256):
         return gf_pool_poll(self.handle, cap)

@@ -6,9 +6,10 @@ footprint, resident lattices, batched sweeps (one launch per kernel kind over
 every lattice) captured in hipGraphs, retirement.  This module is the arrival-side driver: it releases jobs into a
 FIFO queue at their arrival times, admits from the head of the queue whenever
 the pool has room (slots and bytes), steps the pool, and retires finished
-jobs (freeing their lattices, which lets queued jobs in).  Latency of a job =
-end of the pool step in which it finished - its arrival, on the library's
-steady clock.
+jobs (freeing their lattices, which lets queued jobs in); by default the host
+work of a pass (retiring, downloading, admitting) runs while the next step is
+on the GPU.  Latency of a job = completion of the pool step in which it
+finished - its arrival, on the library's steady clock.
 
 `run_fifo` is the comparison path: one lattice at a time, in arrival order,
 with gf_anneal + gf_fix_until on a lone lattice of the given precision.
@@ -130,12 +131,19 @@ def serving_trace(n=1000, rate=20.0, master_seed=5, anneal_fraction=0.3, anneal_
 
 
 def run_pool(jobs, links_of, prec=gf.GF_MIXED, check_every=10, max_slots=256, hbm_budget=None,
-             fix=None, open_loop=True, tps32=0, tps64=0, log=None, collect=False, autotune=False):
+             fix=None, open_loop=True, tps32=0, tps64=0, log=None, collect=False, autotune=False,
+             overlap=True):
     """Run `jobs` through a pool; links_of(job) -> canonical host links.  collect=True
     downloads every finished job's links into stats.results[job_id] = (result, links)
     (the download is inside the timed run).  autotune=True runs gf_pool_autotune on the jobs
     resident before the first step (inside the timed run), for the float32 sweeps of a
-    mixed pool and the float64 sweeps."""
+    mixed pool and the float64 sweeps.
+
+    overlap=True: each pass completes the step in flight, frees the lattices of the jobs
+    that finished in it, launches the next step and, while it runs, downloads finished
+    jobs (collect=True) and admits queued ones, which join the step after it.
+    overlap=False: step, retire and admit one after another with the GPU idle between
+    steps.  Every job's result is the same either way."""
     fix = dict(fix or {})
     import torch
 
@@ -150,7 +158,8 @@ def run_pool(jobs, links_of, prec=gf.GF_MIXED, check_every=10, max_slots=256, hb
                  tps32=tps32, tps64=tps64) as pool:
         t0 = gf.gf_clock()
         done = 0
-        while done < len(jobs):
+
+        def admit_queued():
             now = gf.gf_clock() - t0
             while arrivals and (not open_loop or arrivals[0].arrival <= now):
                 queue.append(arrivals.popleft())
@@ -166,44 +175,81 @@ def run_pool(jobs, links_of, prec=gf.GF_MIXED, check_every=10, max_slots=256, hb
             stats.max_queue = max(stats.max_queue, len(queue))
             stats.max_resident = max(stats.max_resident, active + finished)
             stats.peak_bytes = max(stats.peak_bytes, held)
+            return active
+
+        def record(d, links=None):
+            nonlocal done
+            j = by_id.pop(d["job_id"])
+            if collect:
+                stats.results[d["job_id"]] = (d, links)
+            lat = d["t_done"] - t0 - j.arrival if open_loop else d["t_done"] - t0
+            r = d["result"]
+            stats.latencies.append(lat)
+            stats.sweeps += r.sweeps + j.anneal
+            stats.sweeps_fp32 += r.sweeps_fp32
+            stats.sweeps_fp64 += r.sweeps_fp64
+            stats.site_updates += (r.sweeps + j.anneal) * volume(j.dims)
+            stats.site_updates_fp32 += r.sweeps_fp32 * volume(j.dims)
+            stats.site_updates_fp64 += r.sweeps_fp64 * volume(j.dims)
+            stats.site_updates_anneal += j.anneal * volume(j.dims)
+            if d["status"] != gf.GF_OK:
+                stats.failed += 1
+            elif r.converged:
+                stats.converged += 1
+                stats.conv_latencies.append(lat)
+            done += 1
+            if log:
+                log(f"  job {j.job_id} {j.dims} eps={j.eps:.2f} anneal={j.anneal}: sweeps {r.sweeps} "
+                    f"({r.sweeps_fp32}/{r.sweeps_fp64}) theta {r.theta:.2e} latency {lat:.2f} s")
+
+        def tune_once(active):
             if active and autotune and not stats.tuning:
+                held = pool.stats()[2]
                 kinds = [gf.GF_FP32, gf.GF_FP64] if prec == gf.GF_MIXED else [gf.GF_FP64]
                 for k in kinds:
                     _, rows = pool.autotune(k, 3, scratch_bytes=min(held, 16 << 30))
                     stats.tuning["fp32" if k == gf.GF_FP32 else "fp64"] = [
                         [t, b, round(us, 1)] for (t, b, _, us) in rows]
                 stats.shape = pool.shape
-            if active:
-                pool.step()
-            elif finished == 0 and arrivals and not queue:
+
+        def idle(active, finished):
+            if active or finished:
+                return
+            if arrivals and not queue:
                 time.sleep(max(0.0, min(0.05, arrivals[0].arrival - (gf.gf_clock() - t0))))
-            elif queue and active == 0 and finished == 0:
+            elif queue:
                 raise RuntimeError(f"job {queue[0].job_id} {queue[0].dims} does not fit the pool budget")
-            for d in pool.poll():
-                j = by_id.pop(d["job_id"])
-                if collect:
-                    stats.results[d["job_id"]] = (d, pool.fetch_links(d["job_id"]))
+
+        while done < len(jobs):
+            if overlap:
+                pool.sync()
+                ended = pool.poll()
+                if not collect:
+                    for d in ended:
+                        pool.release(d["job_id"])  # nothing in flight: freed now, room for admissions
+                active, finished, _ = pool.stats()
+                tune_once(active)
+                if active:
+                    pool.step_async()
+                for d in ended:
+                    record(d, pool.fetch_links(d["job_id"]) if collect else None)
+                active = admit_queued()
+                idle(active, pool.stats()[1])
+            else:
+                active = admit_queued()
+                tune_once(active)
+                finished = pool.stats()[1]
+                if active:
+                    pool.step()
                 else:
-                    pool.release(d["job_id"])
-                lat = d["t_done"] - t0 - j.arrival if open_loop else d["t_done"] - t0
-                r = d["result"]
-                stats.latencies.append(lat)
-                stats.sweeps += r.sweeps + j.anneal
-                stats.sweeps_fp32 += r.sweeps_fp32
-                stats.sweeps_fp64 += r.sweeps_fp64
-                stats.site_updates += (r.sweeps + j.anneal) * volume(j.dims)
-                stats.site_updates_fp32 += r.sweeps_fp32 * volume(j.dims)
-                stats.site_updates_fp64 += r.sweeps_fp64 * volume(j.dims)
-                stats.site_updates_anneal += j.anneal * volume(j.dims)
-                if d["status"] != gf.GF_OK:
-                    stats.failed += 1
-                elif r.converged:
-                    stats.converged += 1
-                    stats.conv_latencies.append(lat)
-                done += 1
-                if log:
-                    log(f"  job {j.job_id} {j.dims} eps={j.eps:.2f} anneal={j.anneal}: sweeps {r.sweeps} "
-                        f"({r.sweeps_fp32}/{r.sweeps_fp64}) theta {r.theta:.2e} latency {lat:.2f} s")
+                    idle(active, finished)
+                for d in pool.poll():
+                    if collect:
+                        record(d, pool.fetch_links(d["job_id"]))
+                    else:
+                        pool.release(d["job_id"])
+                        record(d)
+        pool.sync()
         stats.seconds = gf.gf_clock() - t0
         stats.shape = pool.shape
     return stats

@@ -201,6 +201,57 @@ def test_pool_cancel_mid_run():
         assert pool.stats() == (0, 0, 0)
 
 
+def test_pool_step_in_flight_release_cancel_and_budget():
+    """With a step in flight (gf_pool_step_async): a finished job's lattice released meanwhile
+    still counts against the budget until the step is completed (gf_pool_sync), an admission
+    that needs its bytes is refused until then, cancelling a job completes the step first, and
+    every job that ran to the end equals its solo run bitwise."""
+    say("pool step in flight: release, budget, cancel")
+    ce = 5
+    small, big = (4, 4, 4, 4), (8, 8, 8, 8)
+    u_small = gi.gen_links(small, 0.3, 41)
+    u_big = gi.gen_links(big, 0.8, 42)
+    need_s = gf.gf_pool_job_bytes(small, gf.GF_MIXED)
+    need_b = gf.gf_pool_job_bytes(big, gf.GF_MIXED)
+    ref_small = solo(small, u_small, gf.GF_MIXED, 0, 0, ce)
+    ref_big = solo(big, u_big, gf.GF_MIXED, 0, 0, ce)
+    kw = {k: v for k, v in fix_kw(ce).items() if k not in ("check_every", "mode")}
+    with gf.Pool(2 * need_b, 8, prec=gf.GF_MIXED, check_every=ce) as pool:
+        assert pool.admit(1, small, u_small, **kw)
+        assert pool.admit(2, big, u_big, **kw)
+        done = {}
+        for _ in range(2000):
+            pool.step_async()
+            for d in pool.poll():
+                done[d["job_id"]] = d
+            if 1 in done:
+                break
+        assert 1 in done and 2 not in done, "the small job finishes first"
+        assert done[1]["result"] == ref_small[0]
+        # job 2 is in the step in flight: job 1's lattice comes out beside it
+        assert np.array_equal(pool.fetch_links(1), ref_small[1])
+        assert pool.stats() == (1, 0, need_s + need_b)  # released, not yet freed
+        assert not pool.admit(3, big, u_big, **kw)  # needs job 1's bytes
+        pool.sync()
+        assert pool.stats()[2] == need_b
+        assert pool.admit(3, big, u_big, **kw)  # joins job 2 mid-run
+        for _ in range(3):
+            pool.step_async()
+        pool.cancel(3)  # completes the step in flight first
+        for _ in range(4000):
+            for d in pool.poll():
+                done[d["job_id"]] = d
+            if len(done) == 3:
+                break
+            pool.step_async()
+        pool.sync()
+        assert done[3]["status"] == gf.GF_E_CANCELLED and done[3]["result"].sweeps == 3 * ce
+        assert done[2]["status"] == gf.GF_OK and done[2]["result"] == ref_big[0]
+        assert np.array_equal(pool.fetch_links(2), ref_big[1])
+        pool.release(3)
+        assert pool.stats() == (0, 0, 0)
+
+
 BATCH_SHAPES = [(12, 12, 12, 12), (16, 16, 16, 16), (16, 16, 16, 32), (24, 24, 24, 48)]
 
 

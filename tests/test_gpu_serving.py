@@ -61,9 +61,12 @@ WAVES = [
 ]
 
 
-@pytest.mark.parametrize("prec", [gf.GF_MIXED, gf.GF_FP64])
-def test_admission_while_others_run_equals_solo(prec):
-    say(f"mid-run admission vs solo, prec={prec}")
+@pytest.mark.parametrize("prec,overlap", [(gf.GF_MIXED, False), (gf.GF_FP64, False), (gf.GF_MIXED, True),
+                                          (gf.GF_FP64, True)])
+def test_admission_while_others_run_equals_solo(prec, overlap):
+    """overlap=True: every admission, fetch and release happens while a step is in flight
+    (gf_pool_step_async), on the pool's transfer stream."""
+    say(f"mid-run admission vs solo, prec={prec} overlap={overlap}")
     inputs = [gi.gen_links(d, e, s) for (d, e, s, _, _) in WAVES]
     ref = [solo(d, u, prec, a, 500 + i) for i, ((d, e, s, a, _), u) in enumerate(zip(WAVES, inputs))]
     done = {}
@@ -79,12 +82,15 @@ def test_admission_while_others_run_equals_solo(prec):
                 assert pool.admit(700 + i, d, inputs[i], anneal_sweeps=a, T_start=1.25, T_end=0.01,
                                   seed=500 + i, **{k: v for k, v in FIX.items() if k != "check_every"})
             active, _, _ = pool.stats()
-            if active:
+            if active and overlap:
+                pool.step_async()  # completes the previous step, launches this one
+            elif active:
                 pool.step()
             step += 1
             for r in pool.poll():
                 done[r["job_id"]] = (r, pool.fetch_links(r["job_id"]))
             assert step < 5000
+        pool.sync()
         assert admitted_mid_run >= 4
         for i, ((dims, e, s, a, at), (r_solo, l_solo)) in enumerate(zip(WAVES, ref)):
             d, links = done[700 + i]
@@ -97,12 +103,13 @@ def test_admission_while_others_run_equals_solo(prec):
         assert pool.stats() == (0, 0, 0)
 
 
-def test_run_pool_queues_backfills_and_equals_solo():
+@pytest.mark.parametrize("overlap", [True, False])
+def test_run_pool_queues_backfills_and_equals_solo(overlap):
     """The request loop under a budget of two of the largest jobs: a burst of 8 arrivals at
     t = 0, then staggered ones, queue (max queue depth > 0), are backfilled as jobs retire,
     every job finishes with its solo result, latencies are non-negative and the pool never
-    holds more than the budget."""
-    say("serving.run_pool under a tight budget")
+    holds more than the budget; with the host's work overlapping the steps and without."""
+    say(f"serving.run_pool under a tight budget, overlap={overlap}")
     shapes = [(4, 4, 4, 4), (6, 4, 4, 4), (4, 6, 4, 6), (6, 6, 6, 6)]
     rng = np.random.default_rng(11)
     jobs = []
@@ -116,7 +123,7 @@ def test_run_pool_queues_backfills_and_equals_solo():
     inputs = {j.job_id: gi.gen_links(j.dims, j.eps, 40 + j.job_id) for j in jobs}
     budget = 2 * gf.gf_pool_job_bytes((6, 6, 6, 6), gf.GF_MIXED)
     st = serving.run_pool(jobs, lambda j: inputs[j.job_id], prec=gf.GF_MIXED, check_every=CE, max_slots=8,
-                          hbm_budget=budget, fix=FIX, collect=True)
+                          hbm_budget=budget, fix=FIX, collect=True, overlap=overlap)
     s = st.summary()
     say(f"  {s['converged']}/{s['jobs']} converged, max queue {s['max_queue_depth']}, "
         f"max resident {s['max_resident_jobs']}, peak bytes {s['peak_hbm_bytes']} of {budget}")
