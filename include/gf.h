@@ -150,29 +150,41 @@ gf_status gf_lattice_group(gf_lattice lat, int32_t* nc);
  * Otherwise as gf_create_lattice(dims, GF_FP64, ...). */
 gf_status gf_create_lattice_min8(const int32_t dims[4], void* hip_stream, gf_lattice* out);
 
-/* Reals stored per link: 12 (SU(3), two rows), 8 (gf_create_lattice_min8) or
- * 4 (SU(2) quaternion). */
+/* Reals stored per link of the lattice's sweeping precision (the float64
+ * links of GF_FP64, the float32 links of GF_FP32 and GF_MIXED): 12 (SU(3),
+ * two rows), 8 (gf_create_lattice_min8, gf_set_storage) or 4 (SU(2)
+ * quaternion). */
 gf_status gf_lattice_storage(gf_lattice lat, int32_t* reals_per_link);
 
-/* Switch an SU(3) GF_FP64 lattice between 12-real and 8-real storage of its
- * float64 links (reals_per_link 12 or 8; GF_E_ARG otherwise; GF_E_STATE for
- * other lattices).  The links are converted on the device: 12 -> 8 projects
- * rows 0, 1 of each link onto SU(3) as gf_set_links on an 8-real lattice
- * does (a change at rounding level for SU(3) links), 8 -> 12 stores the
- * decoded rows exactly.  The old field is freed after the new one is written
- * (both are held meanwhile); captured sweep graphs are dropped and the
- * register limit of the float64 configurations reset to 0.  Syncs. */
+/* Switch an SU(3) lattice between 12-real and 8-real storage of the links
+ * of its sweeping precision (reals_per_link 12 or 8; GF_E_ARG otherwise;
+ * GF_E_STATE for SU(2) lattices): the float64 links of a GF_FP64 lattice,
+ * the float32 links of a GF_FP32 or GF_MIXED one (a GF_MIXED lattice keeps
+ * its float64 links, the original links and then the polish sweeps', in 12
+ * reals).  The links are converted on the device: 12 -> 8 projects rows 0, 1
+ * of each link onto SU(3) as gf_set_links on an 8-real lattice does (a
+ * change at rounding level for SU(3) links), 8 -> 12 stores the decoded rows
+ * (exactly for float64; float32 values are decoded in float64 and the rows
+ * rounded).  Float32 links in 8 reals: 32 B per link, a float32 site update
+ * moves 512 B instead of 768 B; the sweeps decode and encode in float32,
+ * measurement decodes the stored values in float64, gf_set_links encodes in
+ * float64 and rounds the 8 values to float32, and the float32 floor of
+ * gf_tune_switch is that of links rounded through this storage.  The old
+ * field is freed after the new one is written (both are held meanwhile);
+ * captured sweep graphs are dropped and the register limit of the
+ * configurations of the converted links reset to 0.  Syncs. */
 gf_status gf_set_storage(gf_lattice lat, int32_t reals_per_link);
 
 /* Storage as an autotuning axis (Sec. 4.1 and 5: the parameterisation and
  * the kernel configuration are both run-time choices in the paper's
- * design): tune the float64 overrelaxation sweep of an SU(3) GF_FP64
- * lattice (as gf_autotune with kernel GF_FP64 and no cache) in its current
+ * design): tune the overrelaxation sweep of the sweeping precision of an
+ * SU(3) lattice (as gf_autotune with kernel GF_FP64 for GF_FP64 lattices,
+ * GF_FP32 for GF_FP32 and GF_MIXED ones, and no cache) in its current
  * storage, then on a scratch copy of its links converted to the other
  * storage, and switch the lattice to the faster storage with its fastest
  * configuration (gf_set_storage's conversion).  *reals_per_link (may be
  * NULL) receives the storage chosen, *us_12 and *us_8 (may be NULL) the best
- * time per sweep of each, in microseconds.  GF_E_STATE for other lattices.
+ * time per sweep of each, in microseconds.  GF_E_STATE for SU(2) lattices.
  * Syncs. */
 gf_status gf_autotune_storage(gf_lattice lat, int32_t n_sweeps, int32_t* reals_per_link, double* us_12,
                               double* us_8);

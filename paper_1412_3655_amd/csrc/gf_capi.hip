@@ -93,9 +93,12 @@ LatticeSizes lattice_sizes(const Geom& g, gf_prec prec, int group, bool min8)
     LatticeSizes z;
     const size_t nchunks = (size_t)2 * 4 * g.ld;  // per chunk slot
     const bool su2 = group == 2;
-    const size_t c64 = su2 ? 2 : (min8 ? (size_t)gf::kMin8Chunks : 6);
+    // min8: the links of the lattice's sweeping precision in 8 reals (the
+    // float64 field of GF_FP64, the float32 field of GF_FP32 and GF_MIXED)
+    const size_t c64 = su2 ? 2 : (min8 && prec == GF_FP64 ? (size_t)gf::kMin8Chunks : 6);
+    const size_t c32 = su2 ? 1 : (min8 ? (size_t)gf::kMin8Chunks32 : 3);
     if (prec == GF_FP64 || prec == GF_MIXED) z.f64 = nchunks * c64 * sizeof(double2);
-    if (prec == GF_FP32 || prec == GF_MIXED) z.f32 = nchunks * (su2 ? 1 : 3) * sizeof(float4);
+    if (prec == GF_FP32 || prec == GF_MIXED) z.f32 = nchunks * c32 * sizeof(float4);
     if (prec == GF_MIXED) z.gacc = (size_t)2 * 3 * g.ld * sizeof(float4);
     // partial sums of the whole-lattice reductions, or of the per-timeslice
     // Coulomb ones, whichever needs more
@@ -119,6 +122,11 @@ Link8Field field8(const gf_lattice_* L)
 LinkField<float> field32(const gf_lattice_* L)
 {
     return LinkField<float>{L->f32, L->geom.ld};
+}
+
+Link8Field32 field8f(const gf_lattice_* L)
+{
+    return Link8Field32{L->f32, L->geom.ld};
 }
 
 Su2Field<double> su2_64(const gf_lattice_* L)
@@ -166,8 +174,11 @@ gf_status do_half_sweep(gf_lattice L, int parity, double omega, int mode)
             GF_HIP(gf::launch_su2_or(su2_64(L), L->geom, parity, omega, mode, L->cfg64, L->stream, L->gauge, nullptr));
         return GF_OK;
     }
-    if (L->min8)
+    if (min8_64(L))
         GF_HIP(gf::launch_or_half_sweep(field8(L), L->geom, parity, omega, mode, L->cfg64, L->stream, L->gauge));
+    else if (is_fp32(L) && L->min8)
+        GF_HIP(gf::launch_or_half_sweep(field8f(L), L->geom, parity, (float)omega, mode, L->cfg32, g_tracking(L),
+                                        L->stream, L->gauge));
     else if (is_fp32(L))
         GF_HIP(gf::launch_or_half_sweep(field32(L), L->geom, parity, (float)omega, mode, L->cfg32, g_tracking(L),
                                         L->stream, L->gauge));
@@ -227,8 +238,8 @@ gf_status do_sweeps(gf_lattice L, int32_t n, double omega, int mode)
 gf_status do_reunitarize(gf_lattice L)
 {
     // 8-real links decode to SU(3) to rounding and are re-encoded from rows 0
-    // and 1 at every store: they are reunitarised at every sweep already
-    if (L->min8) return GF_OK;
+    // and 1 at every store: they are reunitarised at every sweep already (g(x)
+    // of a GF_MIXED lattice is not)
     if (L->group == 2) {
         if (is_fp32(L))
             GF_HIP(gf::launch_su2_reunitarize(su2_32(L), L->geom, L->stream));
@@ -236,9 +247,9 @@ gf_status do_reunitarize(gf_lattice L)
             GF_HIP(gf::launch_su2_reunitarize(su2_64(L), L->geom, L->stream));
         return GF_OK;
     }
-    if (is_fp32(L))
+    if (is_fp32(L) && !L->min8)
         GF_HIP(gf::launch_reunitarize(field32(L), L->geom, L->stream));
-    else
+    else if (!is_fp32(L) && !min8_64(L))
         GF_HIP(gf::launch_reunitarize(field64(L), L->geom, L->stream));
     if (g_tracking(L).base) GF_HIP(gf::launch_g_reunitarize(L->gacc, L->geom, L->stream));
     return GF_OK;
@@ -255,9 +266,6 @@ gf_status do_promote(gf_lattice L)
     return GF_OK;
 }
 
-// Coulomb gauge: theta_C(t), F_C(t) of every timeslice into L->hslices;
-// *theta = the largest theta_C(t) (the condition holds once it holds in every
-// timeslice), *F = the mean of F_C(t), added in timeslice order.
 // The measurement's kernels and the copy of its result to pinned host memory,
 // enqueued on `st` (the lattice's stream, or another one that no work on the
 // lattice runs on meanwhile); measure_read takes the result after `st` has
@@ -269,8 +277,10 @@ gf_status measure_enqueue(gf_lattice L, hipStream_t st)
             GF_HIP(gf::launch_su2_measure(su2_32(L), L->geom, gf::GAUGE_COULOMB, L->partial, L->dslices, st));
         else if (L->group == 2)
             GF_HIP(gf::launch_su2_measure(su2_64(L), L->geom, gf::GAUGE_COULOMB, L->partial, L->dslices, st));
-        else if (L->min8)
+        else if (min8_64(L))
             GF_HIP(gf::launch_measure_slices(field8(L), L->geom, L->partial, L->dslices, st));
+        else if (is_fp32(L) && L->min8)
+            GF_HIP(gf::launch_measure_slices(field8f(L), L->geom, L->partial, L->dslices, st));
         else if (is_fp32(L))
             GF_HIP(gf::launch_measure_slices(field32(L), L->geom, L->partial, L->dslices, st));
         else
@@ -283,8 +293,10 @@ gf_status measure_enqueue(gf_lattice L, hipStream_t st)
         GF_HIP(gf::launch_su2_measure(su2_32(L), L->geom, gf::GAUGE_LANDAU, L->partial, L->dres, st));
     else if (L->group == 2)
         GF_HIP(gf::launch_su2_measure(su2_64(L), L->geom, gf::GAUGE_LANDAU, L->partial, L->dres, st));
-    else if (L->min8)
+    else if (min8_64(L))
         GF_HIP(gf::launch_measure(field8(L), L->geom, L->partial, L->dres, st));
+    else if (is_fp32(L) && L->min8)
+        GF_HIP(gf::launch_measure(field8f(L), L->geom, L->partial, L->dres, st));
     else if (is_fp32(L))
         GF_HIP(gf::launch_measure(field32(L), L->geom, L->partial, L->dres, st));
     else
@@ -293,8 +305,9 @@ gf_status measure_enqueue(gf_lattice L, hipStream_t st)
     return GF_OK;
 }
 
-// Coulomb gauge: theta is the largest timeslice's theta_C, F the mean of the
-// timeslices' F_C.
+// Coulomb gauge: theta_C(t), F_C(t) of every timeslice are in L->hslices;
+// *theta = the largest theta_C(t) (the condition holds once it holds in every
+// timeslice), *F = the mean of F_C(t), added in timeslice order.
 gf_status measure_read(gf_lattice L, double* theta, double* F)
 {
     if (L->gauge == gf::GAUGE_COULOMB) {
@@ -354,9 +367,12 @@ gf_status do_est_sweep(gf_lattice L, double omega, int mode, double* theta_est)
                                      L->est));
         else if (su2)
             GF_HIP(gf::launch_su2_or(su2_64(L), L->geom, parity, omega, mode, L->cfg64, L->stream, L->gauge, L->est));
-        else if (L->min8)
+        else if (min8_64(L))
             GF_HIP(gf::launch_or_half_sweep(field8(L), L->geom, parity, omega, mode, L->cfg64, L->stream, L->gauge,
                                             L->est));
+        else if (is_fp32(L) && L->min8)
+            GF_HIP(gf::launch_or_half_sweep(field8f(L), L->geom, parity, (float)omega, mode, L->cfg32, g_tracking(L),
+                                            L->stream, L->gauge, L->est));
         else if (is_fp32(L))
             GF_HIP(gf::launch_or_half_sweep(field32(L), L->geom, parity, (float)omega, mode, L->cfg32, g_tracking(L),
                                             L->stream, L->gauge, L->est));
@@ -377,9 +393,10 @@ gf_status do_est_sweep(gf_lattice L, double omega, int mode, double* theta_est)
 gf_status do_fp32_floor(gf_lattice L, double* floor)
 {
     if (L->group == 2) return fail(GF_E_STATE, "the float32 floor is defined for SU(3) lattices");
-    if (L->min8) return fail(GF_E_STATE, "the float32 floor is defined for 12-real (two-row) links");
+    if (min8_64(L)) return fail(GF_E_STATE, "the float32 floor needs float64 links in 12 reals");
     if (!L->f64) return fail(GF_E_STATE, "the float32 floor needs float64 links (GF_FP64 or GF_MIXED lattice)");
-    GF_HIP(gf::launch_fp32_floor(field64(L), L->geom, L->partial, L->dres, L->stream));
+    // a GF_MIXED lattice in 8 reals: the floor of its 8-real float32 links
+    GF_HIP(gf::launch_fp32_floor(field64(L), L->geom, L->partial, L->dres, L->stream, L->min8));
     GF_HIP(hipMemcpyAsync(L->hres, L->dres, sizeof(double), hipMemcpyDeviceToHost, L->stream));
     GF_HIP(hipStreamSynchronize(L->stream));
     *floor = L->hres[0];
@@ -409,8 +426,11 @@ gf_status upload_canonical(gf_lattice L, const double* dev_canon)
         L->anneal_sweeps = 0;
         return GF_OK;
     }
-    if (L->f32) GF_HIP(gf::launch_pack(dev_canon, field32(L), L->geom, L->stream));
-    if (L->f64 && L->min8)
+    if (L->f32 && L->min8)
+        GF_HIP(gf::launch_pack(dev_canon, field8f(L), L->geom, L->stream));
+    else if (L->f32)
+        GF_HIP(gf::launch_pack(dev_canon, field32(L), L->geom, L->stream));
+    if (L->f64 && min8_64(L))
         GF_HIP(gf::launch_pack(dev_canon, field8(L), L->geom, L->stream));
     else if (L->f64)
         GF_HIP(gf::launch_pack(dev_canon, field64(L), L->geom, L->stream));
@@ -430,8 +450,10 @@ gf_status download_canonical(gf_lattice L, double* dev_canon)
             GF_HIP(gf::launch_su2_unpack(su2_64(L), L->geom, dev_canon, L->stream));
         return GF_OK;
     }
-    if (L->min8)
+    if (min8_64(L))
         GF_HIP(gf::launch_unpack(field8(L), L->geom, dev_canon, L->stream));
+    else if (is_fp32(L) && L->min8)
+        GF_HIP(gf::launch_unpack(field8f(L), L->geom, dev_canon, L->stream));
     else if (is_fp32(L))
         GF_HIP(gf::launch_unpack(field32(L), L->geom, dev_canon, L->stream));
     else
@@ -439,37 +461,49 @@ gf_status download_canonical(gf_lattice L, double* dev_canon)
     return GF_OK;
 }
 
-// Convert the float64 field of an SU(3) GF_FP64 lattice to the other storage
-// (min8 = true: 8 reals per link).  Allocates the new field, converts the
-// links if there are any, frees the old field.  Syncs.
+// Convert the links of an SU(3) lattice's sweeping precision (the float64
+// field of GF_FP64, the float32 field of GF_FP32 and GF_MIXED) to the other
+// storage (min8 = true: 8 reals per link).  Allocates the new field, converts
+// the links if there are any, frees the old field.  Syncs.
 gf_status do_set_storage(gf_lattice L, bool min8)
 {
-    if (L->group != 3 || L->prec != GF_FP64)
-        return fail(GF_E_STATE, "the storage of links can change on SU(3) GF_FP64 lattices only");
+    if (L->group != 3) return fail(GF_E_STATE, "the storage of links can change on SU(3) lattices only");
     if (L->min8 == min8) return GF_OK;
     const LatticeSizes from = lattice_sizes(L->geom, L->prec, L->group, L->min8);
     const LatticeSizes to = lattice_sizes(L->geom, L->prec, L->group, min8);
-    double2* f = nullptr;
-    GF_HIP(hipMalloc((void**)&f, to.f64));
+    const bool f64 = L->prec == GF_FP64;
+    void* f = nullptr;
+    GF_HIP(hipMalloc(&f, f64 ? to.f64 : to.f32));
     hipError_t e = hipSuccess;
-    if (L->has_links) {
+    if (L->has_links && f64) {
         if (min8)
-            e = gf::launch_convert(field64(L), Link8Field{f, L->geom.ld}, L->geom, L->stream);
+            e = gf::launch_convert(field64(L), Link8Field{(double2*)f, L->geom.ld}, L->geom, L->stream);
         else
-            e = gf::launch_convert(field8(L), LinkField<double>{f, L->geom.ld}, L->geom, L->stream);
+            e = gf::launch_convert(field8(L), LinkField<double>{(double2*)f, L->geom.ld}, L->geom, L->stream);
+    } else if (L->has_links) {
+        if (min8)
+            e = gf::launch_convert(field32(L), Link8Field32{(float4*)f, L->geom.ld}, L->geom, L->stream);
+        else
+            e = gf::launch_convert(field8f(L), LinkField<float>{(float4*)f, L->geom.ld}, L->geom, L->stream);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
     if (e != hipSuccess) {
         (void)hipFree(f);
         return fail(GF_E_HIP, "storage conversion: %s", hipGetErrorString(e));
     }
-    (void)hipFree(L->f64);
-    L->f64 = f;
+    if (f64) {
+        (void)hipFree(L->f64);
+        L->f64 = (double2*)f;
+        L->bytes += (int64_t)to.f64 - (int64_t)from.f64;
+        L->cfg64.minw = 0;
+        L->cfg_hb64.minw = 0;
+    } else {
+        (void)hipFree(L->f32);
+        L->f32 = (float4*)f;
+        L->bytes += (int64_t)to.f32 - (int64_t)from.f32;
+    }
     L->min8 = min8;
-    L->bytes += (int64_t)to.f64 - (int64_t)from.f64;
     clear_graphs(L);  // captured launches hold the old field's address
-    L->cfg64.minw = 0;
-    L->cfg_hb64.minw = 0;
     return GF_OK;
 }
 
@@ -657,7 +691,7 @@ gf_status set_config(gf_lattice L, gf_prec kernel, int32_t tps, int32_t block, i
                     "256 or 512 (not 512 with tps 1), cache policy 0, 1 or 2 (1 and 2 only with tps <= 4 and block "
                     "<= 256), min_waves 0 or 2 (2 only with tps 1)",
                     tps, block, nontemporal, min_waves);
-    if (L->min8 && min_waves != 0)
+    if ((kernel == GF_FP64 ? min8_64(L) : L->min8) && min_waves != 0)
         return fail(GF_E_ARG, "8-real links: min_waves must be 0 (the register cap is an axis of the 12-real kernel)");
     if (heat_bath)
         (kernel == GF_FP32 ? L->cfg_hb32 : L->cfg_hb64) = c;
@@ -779,9 +813,12 @@ gf_status gf_anneal(gf_lattice L, int32_t n_sweeps, double T_start, double T_end
             else if (L->group == 2)
                 GF_HIP(gf::launch_su2_hb(su2_64(L), L->geom, parity, T, seed, sweep, L->cfg_hb64, L->stream,
                                          L->gauge));
-            else if (L->min8)
+            else if (min8_64(L))
                 GF_HIP(gf::launch_hb_half_sweep(field8(L), L->geom, parity, T, seed, sweep, L->cfg_hb64, L->stream,
                                                 L->gauge));
+            else if (is_fp32(L) && L->min8)
+                GF_HIP(gf::launch_hb_half_sweep(field8f(L), L->geom, parity, (float)T, seed, sweep, L->cfg_hb32,
+                                                g_tracking(L), L->stream, L->gauge));
             else if (is_fp32(L))
                 GF_HIP(gf::launch_hb_half_sweep(field32(L), L->geom, parity, (float)T, seed, sweep, L->cfg_hb32,
                                                 g_tracking(L), L->stream, L->gauge));
@@ -876,8 +913,10 @@ gf_status gf_plaquette(gf_lattice L, double* P)
         GF_HIP(gf::launch_su2_plaquette(su2_32(L), L->geom, L->partial, L->dres, L->stream));
     else if (L->group == 2)
         GF_HIP(gf::launch_su2_plaquette(su2_64(L), L->geom, L->partial, L->dres, L->stream));
-    else if (L->min8)
+    else if (min8_64(L))
         GF_HIP(gf::launch_plaquette(field8(L), L->geom, L->partial, L->dres, L->stream));
+    else if (is_fp32(L) && L->min8)
+        GF_HIP(gf::launch_plaquette(field8f(L), L->geom, L->partial, L->dres, L->stream));
     else if (is_fp32(L))
         GF_HIP(gf::launch_plaquette(field32(L), L->geom, L->partial, L->dres, L->stream));
     else

@@ -31,7 +31,8 @@ struct gf_lattice_ {
     double* hslices = nullptr;              // pinned host copy of dslices
     int gauge = gf::GAUGE_LANDAU;           // functional: GAUGE_LANDAU or GAUGE_COULOMB
     int group = 3;                          // gauge group SU(3) or SU(2); f64 / f32 hold quaternions for SU(2)
-    bool min8 = false;                      // SU(3) float64 links stored in 8 reals (f64 holds a Link8Field)
+    bool min8 = false;                      // SU(3) links of the sweeping precision in 8 reals: f64 holds a
+                                            // Link8Field (GF_FP64), f32 a Link8Field32 (GF_FP32, GF_MIXED)
     double* est = nullptr;                  // per-block sums of a sweep's theta estimate (allocated on use)
     size_t est_cap = 0;                     // doubles held by est
     bool adaptive = false;                  // gf_fix_until: exact measurement only near a decision
@@ -89,8 +90,15 @@ bool make_geom(const int32_t dims[4], Geom* out);
 gf_status check_dims(const int32_t dims[4], int64_t* V);
 LinkField<double> field64(const gf_lattice_* L);
 Link8Field field8(const gf_lattice_* L);
+Link8Field32 field8f(const gf_lattice_* L);
 LinkField<float> field32(const gf_lattice_* L);
 bool is_fp32(const gf_lattice_* L);
+// The float64 field is in 8 reals (GF_FP64 lattices only; a GF_MIXED lattice
+// keeps its float64 links in 12).
+inline bool min8_64(const gf_lattice_* L)
+{
+    return L->min8 && L->prec == GF_FP64;
+}
 GField g_tracking(const gf_lattice_* L);
 gf_status check_ready(gf_lattice L);
 gf_status check_omega(double omega, int mode);

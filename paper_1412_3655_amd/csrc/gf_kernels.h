@@ -85,6 +85,21 @@ hipError_t launch_or_half_sweep_min8_coulomb(const Link8Field& f, const Geom& g,
 hipError_t launch_or_half_sweep_min8_est(const Link8Field& f, const Geom& g, int parity, double omega, int mode,
                                          const SweepConfig& cfg, hipStream_t st, double* est, int gauge);
 
+// Float32 links stored in 8 reals (gf_min8.h): the float32 sweeps (g tracked
+// when gacc.base is set), decoding and encoding in float32; est as above.
+hipError_t launch_or_half_sweep(const Link8Field32& f, const Geom& g, int parity, float omega, int mode,
+                                const SweepConfig& cfg, const GField& gacc, hipStream_t st, int gauge = GAUGE_LANDAU,
+                                double* est = nullptr);
+hipError_t launch_hb_half_sweep(const Link8Field32& f, const Geom& g, int parity, float T, uint64_t seed,
+                                uint32_t sweep, const SweepConfig& cfg, const GField& gacc, hipStream_t st,
+                                int gauge = GAUGE_LANDAU);
+hipError_t launch_or_half_sweep_min8f_coulomb(const Link8Field32& f, const Geom& g, int parity, float omega,
+                                              int mode, const SweepConfig& cfg, const GField& gacc, hipStream_t st,
+                                              double* est);
+hipError_t launch_or_half_sweep_min8f_est(const Link8Field32& f, const Geom& g, int parity, float omega, int mode,
+                                          const SweepConfig& cfg, const GField& gacc, hipStream_t st, double* est,
+                                          int gauge);
+
 // theta / F: per-block partial sums (2 doubles per block) then one finalize
 // block; out[0] = theta, out[1] = F.  partial must hold measure_partials(g).
 uint32_t measure_blocks(const Geom& g);
@@ -110,8 +125,10 @@ hipError_t launch_measure_slices(const LinkField<float>& f, const Geom& g, doubl
 
 // out[0] = (1/(3V)) sum_x tr[E E^dag], E = Delta computed in float32 from the
 // float32-rounded links minus Delta in float64: the float32 rounding floor of
-// theta for this configuration.  partial as for launch_measure.
-hipError_t launch_fp32_floor(const LinkField<double>& f, const Geom& g, double* partial, double* out, hipStream_t st);
+// theta for this configuration.  min8: the links rounded through the 8-real
+// float32 storage instead of rows 0, 1 rounded.  partial as for launch_measure.
+hipError_t launch_fp32_floor(const LinkField<double>& f, const Geom& g, double* partial, double* out, hipStream_t st,
+                             bool min8 = false);
 
 // Average plaquette into out[0]; partial as for launch_measure.
 hipError_t launch_plaquette(const LinkField<double>& f, const Geom& g, double* partial, double* out, hipStream_t st);
@@ -121,18 +138,30 @@ hipError_t launch_plaquette(const LinkField<float>& f, const Geom& g, double* pa
 hipError_t launch_reunitarize(const LinkField<double>& f, const Geom& g, hipStream_t st);
 hipError_t launch_reunitarize(const LinkField<float>& f, const Geom& g, hipStream_t st);
 
-// The reductions and layout conversion of float64 links stored in 8 reals
-// (pack encodes, unpack decodes).
+// The reductions and layout conversion of links stored in 8 reals (pack
+// encodes, unpack decodes; float32 values are decoded and encoded in float64,
+// the encoded values rounded to float32).
 hipError_t launch_measure(const Link8Field& f, const Geom& g, double* partial, double* out, hipStream_t st);
 hipError_t launch_measure_slices(const Link8Field& f, const Geom& g, double* partial, double* out, hipStream_t st);
 hipError_t launch_plaquette(const Link8Field& f, const Geom& g, double* partial, double* out, hipStream_t st);
 hipError_t launch_pack(const double* canon, const Link8Field& f, const Geom& g, hipStream_t st);
 hipError_t launch_unpack(const Link8Field& f, const Geom& g, double* canon, hipStream_t st);
+hipError_t launch_measure(const Link8Field32& f, const Geom& g, double* partial, double* out, hipStream_t st);
+hipError_t launch_measure_slices(const Link8Field32& f, const Geom& g, double* partial, double* out, hipStream_t st);
+hipError_t launch_plaquette(const Link8Field32& f, const Geom& g, double* partial, double* out, hipStream_t st);
+hipError_t launch_pack(const double* canon, const Link8Field32& f, const Geom& g, hipStream_t st);
+hipError_t launch_unpack(const Link8Field32& f, const Geom& g, double* canon, hipStream_t st);
+hipError_t launch_pack_range(const double* canon, const Link8Field32& f, const Geom& g, uint64_t first, uint64_t n,
+                             hipStream_t st);
+hipError_t launch_unpack_range(const Link8Field32& f, const Geom& g, double* canon, uint64_t first, uint64_t n,
+                               hipStream_t st);
 
 // Every link of a float64 field converted to the other storage (12 -> 8 reals
 // projects rows 0, 1 onto SU(3) like a store; 8 -> 12 writes the decoded rows).
 hipError_t launch_convert(const LinkField<double>& from, const Link8Field& to, const Geom& g, hipStream_t st);
 hipError_t launch_convert(const Link8Field& from, const LinkField<double>& to, const Geom& g, hipStream_t st);
+hipError_t launch_convert(const LinkField<float>& from, const Link8Field32& to, const Geom& g, hipStream_t st);
+hipError_t launch_convert(const Link8Field32& from, const LinkField<float>& to, const Geom& g, hipStream_t st);
 
 // Canonical float64 [site][mu][3][3][2] (device) <-> device layout.
 hipError_t launch_pack(const double* canon, const LinkField<double>& f, const Geom& g, hipStream_t st);

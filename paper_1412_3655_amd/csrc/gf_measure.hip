@@ -124,6 +124,10 @@ __device__ __forceinline__ void delta_components(const M3<T>& K, T d[9])
 // K(x) of the site from the float64 links, in float64 (K64) and, with every
 // stored real rounded to float32 and row 2 rebuilt in float32, in float32
 // (K32): what a float32 sweep sees of the same configuration.
+// M8: the float32 links are the 8-real float32 storage of the float64 ones
+// (encoded in float64, the values rounded, decoded in float32), as the 8-real
+// float32 sweep sees them; otherwise rows 0, 1 rounded to float32.
+template <bool M8>
 __device__ __forceinline__ void site_K_both(const LinkField<double>& f, const Geom& g, int parity, uint32_t h,
                                             M3<double>& K64, M3<float>& K32)
 {
@@ -145,15 +149,21 @@ __device__ __forceinline__ void site_K_both(const LinkField<double>& f, const Ge
             M3<float> v;
             const int p = b ? 1 - parity : parity;
             load_rows01(f, p, mu, b ? back_h(g, h, s, mu) : h, u);
+            if constexpr (M8) {
+                float4 q[kMin8Chunks32];
+                encode_min8(u, q);
+                decode_min8(q, v);
+            } else {
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+                for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    v.re[i][j] = (float)u.re[i][j];
-                    v.im[i][j] = (float)u.im[i][j];
-                }
+                    for (int j = 0; j < 3; ++j) {
+                        v.re[i][j] = (float)u.re[i][j];
+                        v.im[i][j] = (float)u.im[i][j];
+                    }
+                rebuild_row2(v);
+            }
             rebuild_row2(u);
-            rebuild_row2(v);
 #pragma unroll
             for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -168,6 +178,7 @@ __device__ __forceinline__ void site_K_both(const LinkField<double>& f, const Ge
 
 // Per site: tr[E E^dag] with E = Delta(K32) - Delta(K64), the float32 rounding
 // error of the local gauge condition.
+template <bool M8>
 __global__ void __launch_bounds__(RBLOCK) k_fp32_floor(LinkField<double> f, Geom g, double* partial)
 {
     const int parity = blockIdx.y;
@@ -176,7 +187,7 @@ __global__ void __launch_bounds__(RBLOCK) k_fp32_floor(LinkField<double> f, Geom
     if (h < g.vh) {
         M3<double> K64;
         M3<float> K32;
-        site_K_both(f, g, parity, h, K64, K32);
+        site_K_both<M8>(f, g, parity, h, K64, K32);
         double d64[9];
         float d32[9];
         delta_components(K64, d64);
@@ -463,10 +474,14 @@ hipError_t launch_measure_slices(const LinkField<float>& f, const Geom& g, doubl
     return measure_slices_impl(f, g, p, o, st);
 }
 
-hipError_t launch_fp32_floor(const LinkField<double>& f, const Geom& g, double* partial, double* out, hipStream_t st)
+hipError_t launch_fp32_floor(const LinkField<double>& f, const Geom& g, double* partial, double* out, hipStream_t st,
+                             bool min8)
 {
     const uint32_t nb = site_blocks(g);
-    hipLaunchKernelGGL(k_fp32_floor, dim3(nb, 2), dim3(RBLOCK), 0, st, f, g, partial);
+    if (min8)
+        hipLaunchKernelGGL(k_fp32_floor<true>, dim3(nb, 2), dim3(RBLOCK), 0, st, f, g, partial);
+    else
+        hipLaunchKernelGGL(k_fp32_floor<false>, dim3(nb, 2), dim3(RBLOCK), 0, st, f, g, partial);
     const double V = 2.0 * (double)g.vh;
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RBLOCK), 0, st, partial, 2 * nb, 1.0 / (3.0 * V), 0.0, out);
     return hipGetLastError();
@@ -567,6 +582,49 @@ hipError_t launch_convert(const LinkField<double>& from, const Link8Field& to, c
 hipError_t launch_convert(const Link8Field& from, const LinkField<double>& to, const Geom& g, hipStream_t st)
 {
     hipLaunchKernelGGL((k_convert<Link8Field, LinkField<double>>), dim3(site_blocks(g), 8), dim3(RBLOCK), 0, st, from,
+                       to, g.vh);
+    return hipGetLastError();
+}
+
+hipError_t launch_measure(const Link8Field32& f, const Geom& g, double* p, double* o, hipStream_t st)
+{
+    return measure_impl(f, g, p, o, st);
+}
+hipError_t launch_measure_slices(const Link8Field32& f, const Geom& g, double* p, double* o, hipStream_t st)
+{
+    return measure_slices_impl(f, g, p, o, st);
+}
+hipError_t launch_plaquette(const Link8Field32& f, const Geom& g, double* p, double* o, hipStream_t st)
+{
+    return plaquette_impl(f, g, p, o, st);
+}
+hipError_t launch_pack(const double* c, const Link8Field32& f, const Geom& g, hipStream_t st)
+{
+    return pack_impl<double>(c, f, g, st);
+}
+hipError_t launch_unpack(const Link8Field32& f, const Geom& g, double* c, hipStream_t st)
+{
+    return unpack_impl(f, g, c, st);
+}
+hipError_t launch_pack_range(const double* c, const Link8Field32& f, const Geom& g, uint64_t first, uint64_t n,
+                             hipStream_t st)
+{
+    return n ? pack_impl<double>(c, f, g, st, first, n) : hipSuccess;
+}
+hipError_t launch_unpack_range(const Link8Field32& f, const Geom& g, double* c, uint64_t first, uint64_t n,
+                               hipStream_t st)
+{
+    return n ? unpack_impl(f, g, c, st, first, n) : hipSuccess;
+}
+hipError_t launch_convert(const LinkField<float>& from, const Link8Field32& to, const Geom& g, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_convert<LinkField<float>, Link8Field32>), dim3(site_blocks(g), 8), dim3(RBLOCK), 0, st, from,
+                       to, g.vh);
+    return hipGetLastError();
+}
+hipError_t launch_convert(const Link8Field32& from, const LinkField<float>& to, const Geom& g, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_convert<Link8Field32, LinkField<float>>), dim3(site_blocks(g), 8), dim3(RBLOCK), 0, st, from,
                        to, g.vh);
     return hipGetLastError();
 }

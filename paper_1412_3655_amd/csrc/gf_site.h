@@ -298,14 +298,13 @@ __device__ __forceinline__ double delta_norm2(const M3<T>& K)
 // the group returns tr[Delta Delta^dag] of the site's K before the update (the
 // gauge-condition term of the configuration the site sees), every other lane
 // and every call without est 0.  F: the link field, 12 reals per link
-// (LinkField<R>) or float64 in 8 reals (Link8Field, decoded on load and
-// encoded on store).
+// (LinkField<R>) or 8 reals (Link8Field for float64, Link8Field32 for
+// float32; decoded on load and encoded on store, in R).
 template <typename R, int TPS, int MODE, bool TRACKG, int CP = 0, int NDIR = NDIR_LANDAU, typename F = LinkField<R>>
 __device__ __forceinline__ double site_update(const F& f, const Geom& g, int parity, uint32_t h, int r,
                                               const Rule<R>& rule, const GField& gacc, bool est = false)
 {
-    constexpr bool kMin8 = std::is_same<F, Link8Field>::value;
-    static_assert(!kMin8 || (std::is_same<R, double>::value && !TRACKG), "8-real links are float64");
+    constexpr bool kMin8 = Min8Of<F>::value;
     constexpr int NL = 8 / TPS;
     const Site s = decode_site(g, parity, h);
     const uint32_t lex = 2 * h + (uint32_t)(s.x & 1);
@@ -322,8 +321,9 @@ __device__ __forceinline__ double site_update(const F& f, const Geom& g, int par
         at[k] = bwd[k] ? back_h(g, h, s, mu_of[k]) : h;
     }
     if constexpr (kMin8) {
+        static_assert(std::is_same<R, typename Min8Of<F>::R>::value, "decoded in the field's precision");
         // every load first, then the decodes (each yields SU(3) to rounding)
-        double2 raw[NL][kMin8Chunks];
+        typename Min8Of<F>::C raw[NL][Min8Of<F>::N];
 #pragma unroll
         for (int k = 0; k < NL; ++k)
             load_min8_raw<nt_loads(CP)>(f, bwd[k] ? 1 - parity : parity, mu_of[k], at[k], raw[k]);

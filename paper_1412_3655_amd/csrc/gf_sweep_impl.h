@@ -8,7 +8,8 @@
 // sites is over the half index of one colour: every link is read once and
 // written once per half-sweep (per site update in FP64 with 12-real links:
 // 768 B read and 768 B written; with 8-real links 512 B and 512 B), whatever
-// the gauge.  The 8-real instantiations are compiled in gf_sweep_min8*.hip.
+// the gauge.  The 8-real instantiations are compiled in gf_sweep_min8*.hip
+// (float64) and gf_sweep_min8f*.hip (float32: 256 B read and 256 B written).
 #pragma once
 
 #include "gf_kernels.h"
@@ -202,6 +203,29 @@ hipError_t hb_half_sweep(const Link8Field& f, const Geom& g, int parity, double 
     const GField none{nullptr, 0};
     const Rule<double> rule{1.0, T, (uint32_t)seed, (uint32_t)(seed >> 32), sweep};
     return launch_mode<NDIR, false, double, HEATBATH, false>(f, g, parity, rule, cfg, none, st, nullptr);
+}
+
+// Float32 links stored in 8 reals (Link8Field32): the float32 sweeps, g(x)
+// tracked when gacc.base is set.
+template <int NDIR, bool EST>
+hipError_t or_half_sweep(const Link8Field32& f, const Geom& g, int parity, float omega, int mode,
+                         const SweepConfig& cfg, const GField& gacc, hipStream_t st, double* est)
+{
+    const Rule<float> rule{omega, 1.0f, 0u, 0u, 0u};
+    if (gacc.base)
+        return mode == OR_EXACT ? launch_mode<NDIR, EST, float, 0, true>(f, g, parity, rule, cfg, gacc, st, est)
+                                : launch_mode<NDIR, EST, float, 1, true>(f, g, parity, rule, cfg, gacc, st, est);
+    return mode == OR_EXACT ? launch_mode<NDIR, EST, float, 0, false>(f, g, parity, rule, cfg, gacc, st, est)
+                            : launch_mode<NDIR, EST, float, 1, false>(f, g, parity, rule, cfg, gacc, st, est);
+}
+
+template <int NDIR>
+hipError_t hb_half_sweep(const Link8Field32& f, const Geom& g, int parity, float T, uint64_t seed, uint32_t sweep,
+                         const SweepConfig& cfg, const GField& gacc, hipStream_t st)
+{
+    const Rule<float> rule{1.0f, T, (uint32_t)seed, (uint32_t)(seed >> 32), sweep};
+    if (gacc.base) return launch_mode<NDIR, false, float, HEATBATH, true>(f, g, parity, rule, cfg, gacc, st, nullptr);
+    return launch_mode<NDIR, false, float, HEATBATH, false>(f, g, parity, rule, cfg, gacc, st, nullptr);
 }
 
 }  // namespace sweep_impl

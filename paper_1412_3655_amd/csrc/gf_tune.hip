@@ -72,10 +72,11 @@ bool cache_lookup(const char* path, const std::string& key, SweepConfig* out)
 // false) or of the heat-bath sweep (true, at T = 1) of precision `kernel` on a
 // scratch copy of the links, apply the fastest to the lattice and append it to
 // the cache; shared by gf_autotune and gf_autotune_anneal.
-// other_storage (SU(3) GF_FP64 lattices): time the sweep of the lattice's
-// links converted to the other float64 storage (12 <-> 8 reals) on the
-// scratch copy, and leave the lattice's configuration alone (the caller
-// decides whether to switch).
+// other_storage (SU(3) lattices, kernel = the lattice's sweeping precision:
+// GF_FP64 for GF_FP64 lattices, GF_FP32 for GF_FP32 and GF_MIXED): time the
+// sweep of the lattice's links converted to the other storage (12 <-> 8
+// reals) on the scratch copy, and leave the lattice's configuration alone (the
+// caller decides whether to switch).
 gf_status tune(gf_lattice L, gf_prec kernel, bool heat_bath, int32_t n_sweeps, const char* cache_path,
                gf_tune_entry* table, int32_t cap, int32_t* n_out, gf_tune_entry* chosen, bool other_storage = false)
 {
@@ -85,9 +86,10 @@ gf_status tune(gf_lattice L, gf_prec kernel, bool heat_bath, int32_t n_sweeps, c
         return fail(GF_E_ARG, "the lattice has no links of that precision");
     if (n_sweeps < 1 || cap < 0 || (cap > 0 && !table)) return fail(GF_E_ARG, "bad arguments");
     if (n_out) *n_out = 0;
-    if (other_storage && (L->group != 3 || L->prec != GF_FP64 || kernel != GF_FP64))
-        return fail(GF_E_STATE, "the storage of links can change on SU(3) GF_FP64 lattices only");
-    const bool m8 = L->min8 != other_storage;  // storage of the links timed
+    if (other_storage && (L->group != 3 || (kernel == GF_FP64) != (L->prec == GF_FP64)))
+        return fail(GF_E_STATE, "the storage of links can change for SU(3) links of the sweeping precision only");
+    const bool cur8 = kernel == GF_FP64 ? min8_64(L) : L->min8;  // storage of the kernel's links
+    const bool m8 = cur8 != other_storage;                       // storage of the links timed
     SweepConfig scratch_target{};
     SweepConfig& target = other_storage ? scratch_target
                                         : heat_bath ? (kernel == GF_FP32 ? L->cfg_hb32 : L->cfg_hb64)
@@ -101,8 +103,8 @@ gf_status tune(gf_lattice L, gf_prec kernel, bool heat_bath, int32_t n_sweeps, c
     }
 
     const bool su2 = L->group == 2;
-    const size_t chunks =
-        (size_t)2 * 4 * L->geom.ld * (kernel == GF_FP32 ? (su2 ? 1 : 3) : (su2 ? 2 : (m8 ? kMin8Chunks : 6)));
+    const size_t chunks = (size_t)2 * 4 * L->geom.ld *
+                          (kernel == GF_FP32 ? (su2 ? 1 : (m8 ? kMin8Chunks32 : 3)) : (su2 ? 2 : (m8 ? kMin8Chunks : 6)));
     const size_t bytes = chunks * 16;
     void* scratch = nullptr;
     void* gscratch = nullptr;
@@ -116,7 +118,11 @@ gf_status tune(gf_lattice L, gf_prec kernel, bool heat_bath, int32_t n_sweeps, c
     if (e == hipSuccess && track) e = hipMalloc(&gscratch, gbytes);
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    if (e == hipSuccess && other_storage && m8)
+    if (e == hipSuccess && other_storage && kernel == GF_FP32 && m8)
+        e = launch_convert(field32(L), Link8Field32{(float4*)scratch, L->geom.ld}, L->geom, L->stream);
+    else if (e == hipSuccess && other_storage && kernel == GF_FP32)
+        e = launch_convert(field8f(L), LinkField<float>{(float4*)scratch, L->geom.ld}, L->geom, L->stream);
+    else if (e == hipSuccess && other_storage && m8)
         e = launch_convert(field64(L), Link8Field{(double2*)scratch, L->geom.ld}, L->geom, L->stream);
     else if (e == hipSuccess && other_storage)
         e = launch_convert(field8(L), LinkField<double>{(double2*)scratch, L->geom.ld}, L->geom, L->stream);
@@ -131,6 +137,7 @@ gf_status tune(gf_lattice L, gf_prec kernel, bool heat_bath, int32_t n_sweeps, c
     const Su2Field<float> q32{(float4*)scratch, L->geom.ld};
     const Su2Field<double> q64{(double2*)scratch, L->geom.ld};
     const Link8Field f8{(double2*)scratch, L->geom.ld};
+    const Link8Field32 f8f{(float4*)scratch, L->geom.ld};
     uint32_t hb_sweep = 0;
     // the register cap changes only the one-lane float64 kernel (every other
     // shape already runs 2 or more waves per SIMD)
@@ -162,6 +169,12 @@ gf_status tune(gf_lattice L, gf_prec kernel, bool heat_bath, int32_t n_sweeps, c
                         r = launch_su2_or(q32, L->geom, p, 1.7f, GF_OR_EXACT, c, L->stream, L->gauge, nullptr);
                     else if (su2)
                         r = launch_su2_or(q64, L->geom, p, 1.7, GF_OR_EXACT, c, L->stream, L->gauge, nullptr);
+                    else if (m8 && heat_bath && kernel == GF_FP32)
+                        r = launch_hb_half_sweep(f8f, L->geom, p, 1.0f, 1u, hb_sweep, c, track ? g_s : g_none,
+                                                 L->stream, L->gauge);
+                    else if (m8 && kernel == GF_FP32)
+                        r = launch_or_half_sweep(f8f, L->geom, p, 1.7f, GF_OR_EXACT, c, track ? g_s : g_none,
+                                                 L->stream, L->gauge);
                     else if (m8 && heat_bath)
                         r = launch_hb_half_sweep(f8, L->geom, p, 1.0, 1u, hb_sweep, c, L->stream, L->gauge);
                     else if (m8)
@@ -236,17 +249,18 @@ extern "C" gf_status gf_autotune_storage(gf_lattice L, int32_t n_sweeps, int32_t
 {
     TraceRange range("gf_autotune_storage");
     GF_TRY(check_ready(L));
-    if (L->group != 3 || L->prec != GF_FP64)
-        return fail(GF_E_STATE, "the storage of links can change on SU(3) GF_FP64 lattices only");
+    if (L->group != 3) return fail(GF_E_STATE, "the storage of links can change on SU(3) lattices only");
+    // the links of the sweeping precision: float64 of GF_FP64, float32 of GF_FP32 and GF_MIXED
+    const gf_prec kernel = L->prec == GF_FP64 ? GF_FP64 : GF_FP32;
     gf_tune_entry cur{}, oth{};
-    GF_TRY(tune(L, GF_FP64, false, n_sweeps, nullptr, nullptr, 0, nullptr, &cur, false));
-    GF_TRY(tune(L, GF_FP64, false, n_sweeps, nullptr, nullptr, 0, nullptr, &oth, true));
+    GF_TRY(tune(L, kernel, false, n_sweeps, nullptr, nullptr, 0, nullptr, &cur, false));
+    GF_TRY(tune(L, kernel, false, n_sweeps, nullptr, nullptr, 0, nullptr, &oth, true));
     const double t_cur = cur.us_per_sweep, t_oth = oth.us_per_sweep;
     if (us_12) *us_12 = L->min8 ? t_oth : t_cur;
     if (us_8) *us_8 = L->min8 ? t_cur : t_oth;
     if (t_oth < t_cur) {
         GF_TRY(do_set_storage(L, !L->min8));
-        L->cfg64 = SweepConfig{oth.tps, oth.block, oth.nontemporal, oth.min_waves};
+        (kernel == GF_FP64 ? L->cfg64 : L->cfg32) = SweepConfig{oth.tps, oth.block, oth.nontemporal, oth.min_waves};
     }
     if (reals_per_link) *reals_per_link = L->min8 ? 8 : 12;
     return GF_OK;

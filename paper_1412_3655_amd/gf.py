@@ -269,24 +269,31 @@ _LATTICE_STREAM = {}
 
 def gf_create_lattice(dims, prec: int = GF_FP64, stream=None, group: int = 3, storage: int = 12) -> ctypes.c_void_p:
     """group 3: SU(3) (gf_create_lattice); group 2: SU(2) (gf_create_lattice_su2).
-    storage 8: SU(3) float64 links in 8 reals (gf_create_lattice_min8; prec must be GF_FP64)."""
+    storage 8: SU(3) links of the sweeping precision in 8 reals (GF_FP64: gf_create_lattice_min8;
+    GF_FP32 / GF_MIXED: gf_create_lattice, then gf_set_storage(8) before any links exist)."""
     d = (_i32 * 4)(*[int(x) for x in dims])
     out = _vp()
     h = _stream_handle(stream)
     if group not in (2, 3):
         raise ValueError("group must be 2 (SU(2)) or 3 (SU(3))")
-    if storage not in (8, 12) or (storage == 8 and (group != 3 or prec != GF_FP64)):
-        raise ValueError("storage 8 is for SU(3) float64 lattices; otherwise 12")
-    if storage == 8:
+    if storage not in (8, 12) or (storage == 8 and group != 3):
+        raise ValueError("storage 8 is for SU(3) lattices; otherwise 12")
+    if storage == 8 and prec == GF_FP64:
         _call("gf_create_lattice_min8", d, h, ctypes.byref(out))
     else:
         _call("gf_create_lattice_su2" if group == 2 else "gf_create_lattice", d, int(prec), h, ctypes.byref(out))
+        if storage == 8:
+            st = lib().gf_set_storage(out, 8)
+            if st != GF_OK:
+                err = GFError(st, lib().gf_last_error().decode(errors="replace"))
+                lib().gf_destroy_lattice(out)
+                raise err
     _LATTICE_STREAM[out.value] = h
     return out
 
 
 def gf_lattice_storage(lat) -> int:
-    """Reals stored per link: 12, 8 (gf_create_lattice_min8) or 4 (SU(2))."""
+    """Reals stored per link of the sweeping precision: 12, 8 or 4 (SU(2))."""
     n = _i32()
     _call("gf_lattice_storage", lat, ctypes.byref(n))
     return n.value

@@ -267,7 +267,7 @@ def test_autotune_graphs_and_errors(tmp_path):
         lat.sweep(2, 1.7)
         assert np.array_equal(lat.get_links(), tuned)
     with pytest.raises(ValueError):
-        gf.Lattice(RAGGED, gf.GF_MIXED, storage=8)
+        gf.Lattice(RAGGED, gf.GF_FP64, group=2, storage=8)
 
 
 def test_full_size_32x4_one_sweep():
@@ -329,8 +329,8 @@ def test_set_storage_converts_both_ways():
         with pytest.raises(gf.GFError) as e:
             lat.storage = 9
         assert e.value.status == gf.GF_E_ARG
-    for prec, group in ((gf.GF_MIXED, 3), (gf.GF_FP32, 3), (gf.GF_FP64, 2)):
-        with gf.Lattice(dims, prec, group=group) as lat:
+    for prec in (gf.GF_FP32, gf.GF_FP64):
+        with gf.Lattice(dims, prec, group=2) as lat:
             with pytest.raises(gf.GFError) as e:
                 lat.storage = 8
             assert e.value.status == gf.GF_E_STATE
@@ -359,8 +359,8 @@ def test_autotune_storage(start):
         oracle.sweep(ref, dims, 1, 1.7, 0)
         lat.sweep(1, 1.7)
         assert float(np.abs(lat.get_links() - ref).max()) <= 1e-12
-    with gf.Lattice(dims, gf.GF_MIXED) as lat:
-        lat.set_links(u)
+    with gf.Lattice(dims, gf.GF_FP64, group=2) as lat:
+        lat.set_links(gi.gen_links_su2(dims, 0.8, 79))
         with pytest.raises(gf.GFError) as e:
             lat.autotune_storage(2)
         assert e.value.status == gf.GF_E_STATE
