@@ -466,6 +466,8 @@ typedef struct {
                                                links; gf_pool_autotune picks the fastest for the
                                                resident jobs.  The heat-bath sweeps use one lane per
                                                site and 128-thread blocks. */
+    int32_t reals32;     /* storage of the float32 links of a GF_MIXED pool: 12 (or 0) two rows, 8 the
+                            8-real representation (gf_set_storage); 12 or 0 for a GF_FP64 pool */
 } gf_pool_config;
 
 typedef struct {
@@ -485,8 +487,9 @@ gf_status gf_pool_create(const gf_pool_config* cfg, void* hip_stream, gf_pool* o
 /* Wait for the pool's streams and free everything, including unreleased jobs.  NULL is accepted. */
 gf_status gf_pool_destroy(gf_pool pool);
 
-/* Device bytes one job of extents dims needs in a pool of precision prec. */
-gf_status gf_pool_job_bytes(const int32_t dims[4], int32_t prec, int64_t* bytes);
+/* Device bytes one job of extents dims needs in a pool of precision prec
+ * whose float32 links take reals32 reals (12 or 8; 0 = 12). */
+gf_status gf_pool_job_bytes(const int32_t dims[4], int32_t prec, int32_t reals32, int64_t* bytes);
 
 /* Admit a job: copy its host canonical links (4*V*18 doubles) into a new
  * resident lattice, then (if anneal_sweeps > 0) run anneal_sweeps heat-bath

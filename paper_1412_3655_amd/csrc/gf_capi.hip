@@ -548,7 +548,10 @@ const char* gf_version(void)
     return "libgf 0.1 (gfx950)";
 }
 
-namespace {
+}  // extern "C"
+
+namespace gf {
+namespace detail {
 
 gf_status create_lattice(const int32_t dims[4], gf_prec prec, int group, bool min8, void* hip_stream,
                          gf_lattice* out)
@@ -614,7 +617,10 @@ gf_status create_lattice(const int32_t dims[4], gf_prec prec, int group, bool mi
     return GF_OK;
 }
 
-}  // namespace
+}  // namespace detail
+}  // namespace gf
+
+extern "C" {
 
 gf_status gf_create_lattice(const int32_t dims[4], gf_prec prec, void* hip_stream, gf_lattice* out)
 {

@@ -115,6 +115,8 @@ gf_status resolve_switch(gf_lattice L, double theta_target, double theta_switch,
 gf_status upload_canonical(gf_lattice L, const double* dev_canon);
 gf_status download_canonical(gf_lattice L, double* dev_canon);
 gf_status do_set_storage(gf_lattice L, bool min8);
+gf_status create_lattice(const int32_t dims[4], gf_prec prec, int group, bool min8, void* hip_stream,
+                         gf_lattice* out);
 void release(gf_lattice L);
 
 // Float32 phase of GF_MIXED: it is left once theta < theta_switch, or once

@@ -151,6 +151,12 @@ __device__ __forceinline__ LinkField<float> field_of<float>(const SlotDev& sd)
     return sd.f32;
 }
 
+// The float32 links of a pool whose float32 links are stored in 8 reals.
+__device__ __forceinline__ Link8Field32 field8_of(const SlotDev& sd)
+{
+    return Link8Field32{sd.f32.base, sd.f32.ld};
+}
+
 // Linear schedule of gf_anneal: T_start at sweep 0, T_end at sweep n - 1,
 // both endpoints exact (float64).
 __device__ __forceinline__ double schedule_T(const SlotDev& sd, uint32_t s)
@@ -170,8 +176,9 @@ __device__ __forceinline__ double schedule_T(const SlotDev& sd, uint32_t s)
 // Cache); float64 sweeps load non-temporally and keep the forward order (on
 // MI355X the reverse order made them 1-2 % slower and the float32 ones 3 %
 // faster).  The order inside a colour does not change the result.  stride =
-// entries per list segment.  A tile is BLOCK / TPS sites.
-template <typename R, int TPS, int MODE, bool TRACKG, int BLOCK>
+// entries per list segment.  A tile is BLOCK / TPS sites.  M8: float32 links
+// stored in 8 reals.
+template <typename R, int TPS, int MODE, bool TRACKG, int BLOCK, bool M8>
 __global__ void __launch_bounds__(BLOCK) k_pool_sweep(const SlotDev* __restrict__ slots,
                                                       const Entry* __restrict__ list,
                                                       const uint32_t* __restrict__ count, uint32_t stride,
@@ -201,10 +208,15 @@ __global__ void __launch_bounds__(BLOCK) k_pool_sweep(const SlotDev* __restrict_
     } else {
         rule = Rule<R>{(R)sd.omega, R(1), 0u, 0u, 0u};
     }
-    site_update<R, TPS, MODE, TRACKG, CP>(field_of<R>(sd), sd.g, parity, h, r, rule, sd.gacc);
+    if constexpr (M8)
+        site_update<R, TPS, MODE, TRACKG, CP, NDIR_LANDAU, Link8Field32>(field8_of(sd), sd.g, parity, h, r, rule,
+                                                                         sd.gacc);
+    else
+        site_update<R, TPS, MODE, TRACKG, CP>(field_of<R>(sd), sd.g, parity, h, r, rule, sd.gacc);
 }
 
-template <typename R, bool WITH_G>
+// M8: 8-real links are SU(3) at every store; only g(x) is reunitarised.
+template <typename R, bool WITH_G, bool M8>
 __global__ void __launch_bounds__(PBLOCK) k_pool_reunit(const SlotDev* __restrict__ slots,
                                                         const Entry* __restrict__ list,
                                                         const uint32_t* __restrict__ count)
@@ -217,7 +229,7 @@ __global__ void __launch_bounds__(PBLOCK) k_pool_reunit(const SlotDev* __restric
         const uint32_t h = (t - list[i].first) * PBLOCK + threadIdx.x;
         if (h >= sd.g.vh) continue;
         const LinkField<R> f = field_of<R>(sd);
-        for (int pm = 0; pm < 8; ++pm) {
+        for (int pm = 0; pm < 8 && !M8; ++pm) {
             M3<R> u;
             load_rows01(f, pm >> 2, pm & 3, h, u);
             gram_schmidt_rows01(u);
@@ -237,7 +249,7 @@ __global__ void __launch_bounds__(PBLOCK) k_pool_reunit(const SlotDev* __restric
 
 // Tile b of a slot = measurement block (parity = b / nb, block = b % nb) of the
 // single-lattice measurement, writing the same partial.
-template <typename R>
+template <typename R, bool M8>
 __global__ void __launch_bounds__(PBLOCK) k_pool_measure(const SlotDev* __restrict__ slots,
                                                          const Entry* __restrict__ list,
                                                          const uint32_t* __restrict__ count)
@@ -252,7 +264,11 @@ __global__ void __launch_bounds__(PBLOCK) k_pool_measure(const SlotDev* __restri
         const int parity = (int)(b / nb);
         const uint32_t h = (b % nb) * PBLOCK + threadIdx.x;
         double th = 0.0, fr = 0.0;
-        if (h < sd.g.vh) measure_site(field_of<R>(sd), sd.g, parity, h, th, fr);
+        if constexpr (M8) {
+            if (h < sd.g.vh) measure_site(field8_of(sd), sd.g, parity, h, th, fr);
+        } else {
+            if (h < sd.g.vh) measure_site(field_of<R>(sd), sd.g, parity, h, th, fr);
+        }
         block_sum2<PBLOCK>(th, fr, sd.partial + 2 * (size_t)b);
         __syncthreads();
     }
@@ -379,11 +395,11 @@ gf_status check_pool_shape(int tps, int block)
 }
 
 // Device bytes of a job's lattice: what gf_create_lattice allocates for it.
-int64_t lattice_bytes(const int32_t dims[4], int32_t prec)
+int64_t lattice_bytes(const int32_t dims[4], int32_t prec, bool min8)
 {
     Geom g{};
     if (!make_geom(dims, &g)) return -1;
-    return lattice_sizes(g, (gf_prec)prec).total;
+    return lattice_sizes(g, (gf_prec)prec, 3, min8).total;
 }
 
 Entry* seg(gf_pool P, Entry* base, int k, int kind)
@@ -409,47 +425,56 @@ uint32_t tiles_of(const Geom& g, int kind, int tps, int block)
     }
 }
 
-template <typename R, int TPS, int MODE, bool TRACKG>
+template <typename R, int TPS, int MODE, bool TRACKG, bool M8>
 hipError_t launch_sweep_tps(hipStream_t st, const SlotDev* slots, int block, uint32_t tiles, const Entry* list,
                             const uint32_t* count, uint32_t stride, int parity, uint32_t k)
 {
     const dim3 grid(tiles);
     switch (block) {
         case 64:
-            hipLaunchKernelGGL((k_pool_sweep<R, TPS, MODE, TRACKG, 64>), grid, dim3(64), 0, st, slots, list, count,
+            hipLaunchKernelGGL((k_pool_sweep<R, TPS, MODE, TRACKG, 64, M8>), grid, dim3(64), 0, st, slots, list, count,
                                stride, parity, k);
             break;
         case 256:
-            hipLaunchKernelGGL((k_pool_sweep<R, TPS, MODE, TRACKG, 256>), grid, dim3(256), 0, st, slots, list, count,
-                               stride, parity, k);
+            hipLaunchKernelGGL((k_pool_sweep<R, TPS, MODE, TRACKG, 256, M8>), grid, dim3(256), 0, st, slots, list,
+                               count, stride, parity, k);
             break;
         default:
-            hipLaunchKernelGGL((k_pool_sweep<R, TPS, MODE, TRACKG, 128>), grid, dim3(128), 0, st, slots, list, count,
-                               stride, parity, k);
+            hipLaunchKernelGGL((k_pool_sweep<R, TPS, MODE, TRACKG, 128, M8>), grid, dim3(128), 0, st, slots, list,
+                               count, stride, parity, k);
             break;
     }
     return hipGetLastError();
 }
 
-// One sweep launch of kind (R, MODE, TRACKG) over `tiles` tiles of block / tps
-// sites (tps 1, 2 or 4; block 64, 128 or 256).
-template <typename R, int MODE, bool TRACKG>
+// One sweep launch of kind (R, MODE, TRACKG, M8) over `tiles` tiles of block /
+// tps sites (tps 1, 2 or 4; block 64, 128 or 256).
+template <typename R, int MODE, bool TRACKG, bool M8>
 hipError_t launch_sweep_shape(hipStream_t st, const SlotDev* slots, int tps, int block, uint32_t tiles,
                               const Entry* list, const uint32_t* count, uint32_t stride, int parity, uint32_t k)
 {
     switch (tps) {
-        case 1: return launch_sweep_tps<R, 1, MODE, TRACKG>(st, slots, block, tiles, list, count, stride, parity, k);
-        case 2: return launch_sweep_tps<R, 2, MODE, TRACKG>(st, slots, block, tiles, list, count, stride, parity, k);
-        default: return launch_sweep_tps<R, 4, MODE, TRACKG>(st, slots, block, tiles, list, count, stride, parity, k);
+        case 1:
+            return launch_sweep_tps<R, 1, MODE, TRACKG, M8>(st, slots, block, tiles, list, count, stride, parity, k);
+        case 2:
+            return launch_sweep_tps<R, 2, MODE, TRACKG, M8>(st, slots, block, tiles, list, count, stride, parity, k);
+        default:
+            return launch_sweep_tps<R, 4, MODE, TRACKG, M8>(st, slots, block, tiles, list, count, stride, parity, k);
     }
 }
 
+// The float32 kinds take the pool's float32 storage (M8: 8 reals per link).
 template <typename R, int MODE, bool TRACKG>
 hipError_t launch_sweep_kind(gf_pool P, int tps, int block, uint32_t tiles, const Entry* list, const uint32_t* count,
                              int parity, uint32_t k)
 {
-    return launch_sweep_shape<R, MODE, TRACKG>(P->stream, P->slots_dev, tps, block, tiles, list, count,
-                                               (uint32_t)P->list_stride, parity, k);
+    if constexpr (sizeof(R) == 4) {
+        if (P->cfg.reals32 == 8)
+            return launch_sweep_shape<R, MODE, TRACKG, true>(P->stream, P->slots_dev, tps, block, tiles, list, count,
+                                                             (uint32_t)P->list_stride, parity, k);
+    }
+    return launch_sweep_shape<R, MODE, TRACKG, false>(P->stream, P->slots_dev, tps, block, tiles, list, count,
+                                                      (uint32_t)P->list_stride, parity, k);
 }
 
 bool is_sweep_kind(int kind)
@@ -483,19 +508,27 @@ hipError_t launch_kind(gf_pool P, int k, int kind, int parity)
                        ? launch_sweep_kind<double, 0, false>(P, t64, b64, tiles, list, count, parity, kk)
                        : launch_sweep_kind<double, 1, false>(P, t64, b64, tiles, list, count, parity, kk);
         case K_R32:
-            hipLaunchKernelGGL((k_pool_reunit<float, true>), dim3(P->grid_other), dim3(PBLOCK), 0, P->stream,
-                               P->slots_dev, list, count);
+            if (P->cfg.reals32 == 8)
+                hipLaunchKernelGGL((k_pool_reunit<float, true, true>), dim3(P->grid_other), dim3(PBLOCK), 0, P->stream,
+                                   P->slots_dev, list, count);
+            else
+                hipLaunchKernelGGL((k_pool_reunit<float, true, false>), dim3(P->grid_other), dim3(PBLOCK), 0,
+                                   P->stream, P->slots_dev, list, count);
             break;
         case K_R64:
-            hipLaunchKernelGGL((k_pool_reunit<double, false>), dim3(P->grid_other), dim3(PBLOCK), 0, P->stream,
+            hipLaunchKernelGGL((k_pool_reunit<double, false, false>), dim3(P->grid_other), dim3(PBLOCK), 0, P->stream,
                                P->slots_dev, list, count);
             break;
         case K_M32:
-            hipLaunchKernelGGL((k_pool_measure<float>), dim3(P->grid_other), dim3(PBLOCK), 0, P->stream, P->slots_dev,
-                               list, count);
+            if (P->cfg.reals32 == 8)
+                hipLaunchKernelGGL((k_pool_measure<float, true>), dim3(P->grid_other), dim3(PBLOCK), 0, P->stream,
+                                   P->slots_dev, list, count);
+            else
+                hipLaunchKernelGGL((k_pool_measure<float, false>), dim3(P->grid_other), dim3(PBLOCK), 0, P->stream,
+                                   P->slots_dev, list, count);
             break;
         case K_M64:
-            hipLaunchKernelGGL((k_pool_measure<double>), dim3(P->grid_other), dim3(PBLOCK), 0, P->stream,
+            hipLaunchKernelGGL((k_pool_measure<double, false>), dim3(P->grid_other), dim3(PBLOCK), 0, P->stream,
                                P->slots_dev, list, count);
             break;
         default:
@@ -707,7 +740,10 @@ gf_status upload_job(gf_pool P, gf_lattice L, const double* host)
     for (uint64_t first = 0; first < nlinks && e == hipSuccess; first += kStageLinks) {
         const uint64_t n = std::min<uint64_t>(kStageLinks, nlinks - first);
         e = hipMemcpyAsync(P->stage, host + first * 18, n * 18 * sizeof(double), hipMemcpyHostToDevice, P->xfer);
-        if (e == hipSuccess && L->f32) e = gf::launch_pack_range(P->stage, field32(L), L->geom, first, n, P->xfer);
+        if (e == hipSuccess && L->f32 && L->min8)
+            e = gf::launch_pack_range(P->stage, field8f(L), L->geom, first, n, P->xfer);
+        else if (e == hipSuccess && L->f32)
+            e = gf::launch_pack_range(P->stage, field32(L), L->geom, first, n, P->xfer);
         if (e == hipSuccess && L->f64) e = gf::launch_pack_range(P->stage, field64(L), L->geom, first, n, P->xfer);
     }
     if (e == hipSuccess && L->gacc.base) e = gf::launch_g_identity(L->gacc, L->geom, P->xfer);
@@ -728,7 +764,9 @@ gf_status download_job(gf_pool P, gf_lattice L, double* host)
     hipError_t e = hipSuccess;
     for (uint64_t first = 0; first < nlinks && e == hipSuccess; first += kStageLinks) {
         const uint64_t n = std::min<uint64_t>(kStageLinks, nlinks - first);
-        if (is_fp32(L))
+        if (is_fp32(L) && L->min8)
+            e = gf::launch_unpack_range(field8f(L), L->geom, P->stage, first, n, P->xfer);
+        else if (is_fp32(L))
             e = gf::launch_unpack_range(field32(L), L->geom, P->stage, first, n, P->xfer);
         else
             e = gf::launch_unpack_range(field64(L), L->geom, P->stage, first, n, P->xfer);
@@ -868,15 +906,17 @@ double gf_clock(void)
     return now_s();
 }
 
-gf_status gf_pool_job_bytes(const int32_t dims[4], int32_t prec, int64_t* bytes)
+gf_status gf_pool_job_bytes(const int32_t dims[4], int32_t prec, int32_t reals32, int64_t* bytes)
 {
     if (!dims || !bytes) return fail(GF_E_ARG, "null argument");
     for (int m = 0; m < 4; ++m)
         if (dims[m] < 2 || dims[m] % 2) return fail(GF_E_ARG, "extents must be even and >= 2");
     if (prec != GF_FP64 && prec != GF_MIXED && prec != GF_FP32) return fail(GF_E_ARG, "bad precision");
+    if (reals32 != 0 && reals32 != 12 && reals32 != 8) return fail(GF_E_ARG, "reals32 must be 0, 12 or 8");
+    if (reals32 == 8 && prec == GF_FP64) return fail(GF_E_ARG, "a GF_FP64 job has no float32 links");
     int64_t V = 1;
     GF_TRY(check_dims(dims, &V));
-    *bytes = lattice_bytes(dims, prec);
+    *bytes = lattice_bytes(dims, prec, reals32 == 8);
     if (*bytes < 0) return fail(GF_E_ARG, "internal: index division check failed");
     return GF_OK;
 }
@@ -890,6 +930,9 @@ gf_status gf_pool_create(const gf_pool_config* cfg, void* hip_stream, gf_pool* o
     if (cfg->check_every < 1 || cfg->check_every > 1000) return fail(GF_E_ARG, "check_every must be 1..1000");
     if (cfg->mode != GF_OR_EXACT && cfg->mode != GF_OR_BINOMIAL1) return fail(GF_E_ARG, "unknown mode");
     gf_pool_config c = *cfg;
+    if (c.reals32 == 0) c.reals32 = 12;
+    if (c.reals32 != 12 && c.reals32 != 8) return fail(GF_E_ARG, "reals32 must be 0, 12 or 8");
+    if (c.reals32 == 8 && c.prec != GF_MIXED) return fail(GF_E_ARG, "8-real float32 links need a GF_MIXED pool");
     if (c.tps32 == 0) c.tps32 = kDefaultTps32;
     if (c.tps64 == 0) c.tps64 = kDefaultTps64;
     if (c.block32 == 0) c.block32 = kDefaultBlock;
@@ -986,7 +1029,7 @@ gf_status gf_pool_admit(gf_pool P, uint64_t job_id, const int32_t dims[4], const
     for (auto& j : P->jobs)
         if (j.lat && j.id == job_id) return fail(GF_E_ARG, "job id %llu is already in the pool", (unsigned long long)job_id);
     int64_t bytes = 0;
-    GF_TRY(gf_pool_job_bytes(dims, P->cfg.prec, &bytes));
+    GF_TRY(gf_pool_job_bytes(dims, P->cfg.prec, P->cfg.reals32, &bytes));
     int slot = -1;
     for (int s = 0; s < (int)P->jobs.size(); ++s)
         if (!P->jobs[s].lat) {
@@ -999,7 +1042,7 @@ gf_status gf_pool_admit(gf_pool P, uint64_t job_id, const int32_t dims[4], const
                     (long long)P->bytes_in_use, P->cfg.hbm_budget);
 
     gf_lattice L = nullptr;
-    GF_TRY(gf_create_lattice(dims, (gf_prec)P->cfg.prec, P->stream, &L));
+    GF_TRY(create_lattice(dims, (gf_prec)P->cfg.prec, 3, P->cfg.reals32 == 8, P->stream, &L));
     // the job's own lattice object takes the pool's shape (its solo kernels
     // are not used for sweeps while it is in the pool)
     L->cfg32 = SweepConfig{P->cfg.tps32, P->cfg.block32};
@@ -1152,7 +1195,7 @@ gf_status gf_pool_autotune(gf_pool P, int32_t kernel, int32_t n_sweeps, size_t s
     for (auto& j : P->jobs) {
         if (!j.lat) continue;
         gf_lattice L = j.lat;
-        const size_t fb = (size_t)2 * 4 * L->geom.ld * 16 * (f32 ? 3 : 6);
+        const size_t fb = (size_t)2 * 4 * L->geom.ld * 16 * (f32 ? (P->cfg.reals32 == 8 ? kMin8Chunks32 : 3) : 6);
         const size_t gb = f32 ? (size_t)2 * 3 * L->geom.ld * 16 : 0;
         if (used + fb + gb > scratch_bytes) break;
         Copy c{P->slot_host[j.slot], nullptr, nullptr};
@@ -1212,18 +1255,25 @@ gf_status gf_pool_autotune(gf_pool P, int32_t kernel, int32_t n_sweeps, size_t s
             auto sweep = [&]() -> hipError_t {
                 for (int parity = 0; parity < 2; ++parity) {
                     hipError_t r;
-                    if (f32)
+                    const uint32_t ns = (uint32_t)(n + 1);
+                    if (f32 && P->cfg.reals32 == 8)
                         r = mode == GF_OR_EXACT
-                                ? launch_sweep_shape<float, 0, true>(P->stream, slots_d, tps, block, tiles, list_d,
-                                                                     count_d, (uint32_t)(n + 1), parity, 0u)
-                                : launch_sweep_shape<float, 1, true>(P->stream, slots_d, tps, block, tiles, list_d,
-                                                                     count_d, (uint32_t)(n + 1), parity, 0u);
+                                ? launch_sweep_shape<float, 0, true, true>(P->stream, slots_d, tps, block, tiles,
+                                                                           list_d, count_d, ns, parity, 0u)
+                                : launch_sweep_shape<float, 1, true, true>(P->stream, slots_d, tps, block, tiles,
+                                                                           list_d, count_d, ns, parity, 0u);
+                    else if (f32)
+                        r = mode == GF_OR_EXACT
+                                ? launch_sweep_shape<float, 0, true, false>(P->stream, slots_d, tps, block, tiles,
+                                                                            list_d, count_d, ns, parity, 0u)
+                                : launch_sweep_shape<float, 1, true, false>(P->stream, slots_d, tps, block, tiles,
+                                                                            list_d, count_d, ns, parity, 0u);
                     else
                         r = mode == GF_OR_EXACT
-                                ? launch_sweep_shape<double, 0, false>(P->stream, slots_d, tps, block, tiles, list_d,
-                                                                       count_d, (uint32_t)(n + 1), parity, 0u)
-                                : launch_sweep_shape<double, 1, false>(P->stream, slots_d, tps, block, tiles, list_d,
-                                                                       count_d, (uint32_t)(n + 1), parity, 0u);
+                                ? launch_sweep_shape<double, 0, false, false>(P->stream, slots_d, tps, block, tiles,
+                                                                              list_d, count_d, ns, parity, 0u)
+                                : launch_sweep_shape<double, 1, false, false>(P->stream, slots_d, tps, block, tiles,
+                                                                              list_d, count_d, ns, parity, 0u);
                     if (r != hipSuccess) return r;
                 }
                 return hipSuccess;

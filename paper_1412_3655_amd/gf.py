@@ -83,6 +83,7 @@ class gf_pool_config(ctypes.Structure):
         ("block32", ctypes.c_int32),
         ("tps64", ctypes.c_int32),
         ("block64", ctypes.c_int32),
+        ("reals32", ctypes.c_int32),
     ]
 
 
@@ -153,7 +154,7 @@ _SIGNATURES = {
     "gf_plaquette": [_vp, _dp],
     "gf_pool_create": [ctypes.POINTER(gf_pool_config), _vp, ctypes.POINTER(_vp)],
     "gf_pool_destroy": [_vp],
-    "gf_pool_job_bytes": [ctypes.POINTER(_i32), _i32, ctypes.POINTER(ctypes.c_int64)],
+    "gf_pool_job_bytes": [ctypes.POINTER(_i32), _i32, _i32, ctypes.POINTER(ctypes.c_int64)],
     "gf_pool_admit": [_vp, ctypes.c_uint64, ctypes.POINTER(_i32), _dp, ctypes.POINTER(gf_fix_params), _i32,
                       ctypes.c_double, ctypes.c_double, ctypes.c_uint64],
     "gf_pool_step": [_vp],
@@ -690,18 +691,18 @@ def gf_clock() -> float:
     return float(lib().gf_clock())
 
 
-def gf_pool_job_bytes(dims, prec: int = GF_MIXED) -> int:
+def gf_pool_job_bytes(dims, prec: int = GF_MIXED, reals32: int = 12) -> int:
     d = (_i32 * 4)(*[int(x) for x in dims])
     b = ctypes.c_int64()
-    _call("gf_pool_job_bytes", d, int(prec), ctypes.byref(b))
+    _call("gf_pool_job_bytes", d, int(prec), int(reals32), ctypes.byref(b))
     return b.value
 
 
 def gf_pool_create(hbm_budget: int, max_slots: int, prec: int = GF_MIXED, check_every: int = 10,
                    mode: int = GF_OR_EXACT, tps32: int = 0, block32: int = 0, tps64: int = 0, block64: int = 0,
-                   stream=None):
+                   stream=None, reals32: int = 12):
     cfg = gf_pool_config(int(hbm_budget), int(max_slots), int(prec), int(check_every), int(mode), int(tps32),
-                         int(block32), int(tps64), int(block64))
+                         int(block32), int(tps64), int(block64), int(reals32))
     out = _vp()
     _call("gf_pool_create", ctypes.byref(cfg), _stream_handle(stream), ctypes.byref(out))
     return out
@@ -807,11 +808,12 @@ class Pool:
 
     def __init__(self, hbm_budget: int, max_slots: int, prec: int = GF_MIXED, check_every: int = 10,
                  mode: int = GF_OR_EXACT, tps32: int = 0, tps64: int = 0, stream=None, block32: int = 0,
-                 block64: int = 0):
+                 block64: int = 0, reals32: int = 12):
+        """reals32 = 8: the float32 links of a GF_MIXED pool in 8 reals (gf_set_storage)."""
         self.check_every = int(check_every)
         self.mode = int(mode)
         self.handle = gf_pool_create(hbm_budget, max_slots, prec, check_every, mode, tps32, block32, tps64, block64,
-                                     stream)
+                                     stream, reals32)
         self.dims = {}
 
     def autotune(self, kernel: int, n_sweeps: int = 3, scratch_bytes: int = 8 << 30):

@@ -132,7 +132,7 @@ def serving_trace(n=1000, rate=20.0, master_seed=5, anneal_fraction=0.3, anneal_
 
 def run_pool(jobs, links_of, prec=gf.GF_MIXED, check_every=10, max_slots=256, hbm_budget=None,
              fix=None, open_loop=True, tps32=0, tps64=0, log=None, collect=False, autotune=False,
-             overlap=True):
+             overlap=True, reals32=12):
     """Run `jobs` through a pool; links_of(job) -> canonical host links.  collect=True
     downloads every finished job's links into stats.results[job_id] = (result, links)
     (the download is inside the timed run).  autotune=True runs gf_pool_autotune on the jobs
@@ -143,7 +143,8 @@ def run_pool(jobs, links_of, prec=gf.GF_MIXED, check_every=10, max_slots=256, hb
     that finished in it, launches the next step and, while it runs, downloads finished
     jobs (collect=True) and admits queued ones, which join the step after it.
     overlap=False: step, retire and admit one after another with the GPU idle between
-    steps.  Every job's result is the same either way."""
+    steps.  Every job's result is the same either way.  reals32 = 8: the pool's float32 links
+    in 8 reals (a GF_MIXED pool)."""
     fix = dict(fix or {})
     import torch
 
@@ -155,7 +156,7 @@ def run_pool(jobs, links_of, prec=gf.GF_MIXED, check_every=10, max_slots=256, hb
     queue = collections.deque()
     by_id = {}
     with gf.Pool(hbm_budget, max_slots, prec=prec, check_every=check_every, mode=fix.get("mode", 0),
-                 tps32=tps32, tps64=tps64) as pool:
+                 tps32=tps32, tps64=tps64, reals32=reals32) as pool:
         t0 = gf.gf_clock()
         done = 0
 

@@ -102,3 +102,21 @@ def test_bench_cpu_baseline_fields():
     assert "4x4x4x4" in cb["sample"]
     # the timing copies the input: the caller's links are untouched
     assert np.array_equal(u, gi.gen_links(dims, 0.6, 3))
+
+
+def test_pool_job_bytes_by_storage():
+    """gf_pool_job_bytes is host arithmetic: a GF_MIXED job whose float32 links take 8 reals holds
+    one float4 chunk less per link than with 12 (2 colours x 4 directions x ld sites x 16 B, ld the
+    half volume padded to whole 64-site tiles); a GF_FP64 job has no float32 links to store in 8."""
+    for dims in [(4, 4, 4, 4), (6, 10, 6, 6), (16, 16, 16, 32)]:
+        V = 1
+        for d in dims:
+            V *= d
+        ld = -(-(V // 2) // 64) * 64
+        b12 = gf.gf_pool_job_bytes(dims, gf.GF_MIXED)
+        assert gf.gf_pool_job_bytes(dims, gf.GF_MIXED, 0) == b12
+        assert b12 - gf.gf_pool_job_bytes(dims, gf.GF_MIXED, 8) == 2 * 4 * ld * 16
+    for prec, reals in ((gf.GF_FP64, 8), (gf.GF_MIXED, 10)):
+        with pytest.raises(gf.GFError) as e:
+            gf.gf_pool_job_bytes((4, 4, 4, 4), prec, reals)
+        assert e.value.status == gf.GF_E_ARG

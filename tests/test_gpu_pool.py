@@ -48,8 +48,8 @@ def fix_kw(check_every):
                 reunit_every=2 * check_every, theta_switch=1e-8)
 
 
-def solo(dims, links, prec, anneal, seed, check_every):
-    with gf.Lattice(dims, prec) as lat:
+def solo(dims, links, prec, anneal, seed, check_every, storage=12):
+    with gf.Lattice(dims, prec, storage=storage) as lat:
         lat.set_links(links)
         if anneal:
             lat.anneal(anneal, 1.25, 0.05, seed)
@@ -57,13 +57,15 @@ def solo(dims, links, prec, anneal, seed, check_every):
         return r, lat.get_links()
 
 
-@pytest.mark.parametrize("prec", [gf.GF_MIXED, gf.GF_FP64])
-def test_pool_equals_solo(prec):
+@pytest.mark.parametrize("prec,reals32", [(gf.GF_MIXED, 12), (gf.GF_FP64, 12), (gf.GF_MIXED, 8)])
+def test_pool_equals_solo(prec, reals32):
+    """reals32 = 8: the pool's float32 links in 8 reals, against solo GF_MIXED lattices stored the
+    same way."""
     ce = 5
-    say(f"pool vs solo prec={prec}")
+    say(f"pool vs solo prec={prec} reals32={reals32}")
     inputs = [gi.gen_links(d, e, s) for (d, e, s, _) in JOBS]
-    ref = [solo(d, u, prec, a, 100 + i, ce) for i, ((d, e, s, a), u) in enumerate(zip(JOBS, inputs))]
-    with gf.Pool(1 << 34, 16, prec=prec, check_every=ce) as pool:
+    ref = [solo(d, u, prec, a, 100 + i, ce, reals32) for i, ((d, e, s, a), u) in enumerate(zip(JOBS, inputs))]
+    with gf.Pool(1 << 34, 16, prec=prec, check_every=ce, reals32=reals32) as pool:
         for i, ((d, e, s, a), u) in enumerate(zip(JOBS, inputs)):
             assert pool.admit(1000 + i, d, u, anneal_sweeps=a, T_start=1.25, T_end=0.05, seed=100 + i,
                               **{k: v for k, v in fix_kw(ce).items() if k not in ("check_every", "mode")})
@@ -85,6 +87,10 @@ def test_pool_equals_solo(prec):
             links = pool.fetch_links(1000 + i)
             assert np.array_equal(links, l_solo)
         assert pool.stats() == (0, 0, 0)
+    if reals32 == 8:
+        with pytest.raises(gf.GFError) as e:
+            gf.Pool(1 << 30, 4, prec=gf.GF_FP64, reals32=8)
+        assert e.value.status == gf.GF_E_ARG
 
 
 def test_pool_admission_backfill_and_failures():
@@ -331,7 +337,8 @@ def test_pool_large_slot_table_uses_the_search_fallback():
             assert np.array_equal(pool.fetch_links(i), ref[i][1])
 
 
-def test_pool_autotune_keeps_results():
+@pytest.mark.parametrize("reals32", [12, 8])
+def test_pool_autotune_keeps_results(reals32):
     """gf_pool_autotune times every (lanes, block) shape of the pool's sweeps on copies of the
     resident jobs, applies the fastest, and leaves the jobs' links alone: results still equal
     the solo runs bitwise.  A shape outside {1, 2, 4} x {64, 128, 256} is rejected."""
@@ -339,12 +346,12 @@ def test_pool_autotune_keeps_results():
     say("pool autotune keeps results")
     jobs = JOBS[:4]
     inputs = [gi.gen_links(d, e, s) for (d, e, s, _) in jobs]
-    ref = [solo(d, u, gf.GF_MIXED, a, 200 + i, ce) for i, ((d, e, s, a), u) in enumerate(zip(jobs, inputs))]
+    ref = [solo(d, u, gf.GF_MIXED, a, 200 + i, ce, reals32) for i, ((d, e, s, a), u) in enumerate(zip(jobs, inputs))]
     with pytest.raises(gf.GFError):
         gf.Pool(1 << 30, 4, prec=gf.GF_MIXED, tps32=8)
     with pytest.raises(gf.GFError):
         gf.Pool(1 << 30, 4, prec=gf.GF_MIXED, block64=512)
-    with gf.Pool(1 << 34, 8, prec=gf.GF_MIXED, check_every=ce, block32=64, block64=256) as pool:
+    with gf.Pool(1 << 34, 8, prec=gf.GF_MIXED, check_every=ce, block32=64, block64=256, reals32=reals32) as pool:
         assert pool.shape == (2, 64, 1, 256)
         with pytest.raises(gf.GFError) as e:
             pool.autotune(gf.GF_FP32)

@@ -40,8 +40,8 @@ FIX = dict(omega=1.7, mode=gf.GF_OR_EXACT, theta_target=1e-12, max_sweeps=3000, 
            reunit_every=4 * CE, theta_switch=-1.0)
 
 
-def solo(dims, links, prec, anneal, seed, T_end=0.01):
-    with gf.Lattice(dims, prec) as lat:
+def solo(dims, links, prec, anneal, seed, T_end=0.01, storage=12):
+    with gf.Lattice(dims, prec, storage=storage) as lat:
         lat.set_links(links)
         if anneal:
             lat.anneal(anneal, 1.25, T_end, seed)
@@ -103,13 +103,13 @@ def test_admission_while_others_run_equals_solo(prec, overlap):
         assert pool.stats() == (0, 0, 0)
 
 
-@pytest.mark.parametrize("overlap", [True, False])
-def test_run_pool_queues_backfills_and_equals_solo(overlap):
+@pytest.mark.parametrize("overlap,reals32", [(True, 12), (False, 12), (True, 8)])
+def test_run_pool_queues_backfills_and_equals_solo(overlap, reals32):
     """The request loop under a budget of two of the largest jobs: a burst of 8 arrivals at
     t = 0, then staggered ones, queue (max queue depth > 0), are backfilled as jobs retire,
     every job finishes with its solo result, latencies are non-negative and the pool never
     holds more than the budget; with the host's work overlapping the steps and without."""
-    say(f"serving.run_pool under a tight budget, overlap={overlap}")
+    say(f"serving.run_pool under a tight budget, overlap={overlap}, reals32={reals32}")
     shapes = [(4, 4, 4, 4), (6, 4, 4, 4), (4, 6, 4, 6), (6, 6, 6, 6)]
     rng = np.random.default_rng(11)
     jobs = []
@@ -121,9 +121,9 @@ def test_run_pool_queues_backfills_and_equals_solo(overlap):
         jobs.append(serving.Job(k, d, float(rng.uniform(0.4, 0.7)), 3000 + k, t,
                                 anneal=20 if k % 3 == 0 else 0))
     inputs = {j.job_id: gi.gen_links(j.dims, j.eps, 40 + j.job_id) for j in jobs}
-    budget = 2 * gf.gf_pool_job_bytes((6, 6, 6, 6), gf.GF_MIXED)
+    budget = 2 * gf.gf_pool_job_bytes((6, 6, 6, 6), gf.GF_MIXED, reals32)
     st = serving.run_pool(jobs, lambda j: inputs[j.job_id], prec=gf.GF_MIXED, check_every=CE, max_slots=8,
-                          hbm_budget=budget, fix=FIX, collect=True, overlap=overlap)
+                          hbm_budget=budget, fix=FIX, collect=True, overlap=overlap, reals32=reals32)
     s = st.summary()
     say(f"  {s['converged']}/{s['jobs']} converged, max queue {s['max_queue_depth']}, "
         f"max resident {s['max_resident_jobs']}, peak bytes {s['peak_hbm_bytes']} of {budget}")
@@ -133,6 +133,6 @@ def test_run_pool_queues_backfills_and_equals_solo(overlap):
     assert min(st.latencies) >= 0.0
     for j in jobs:
         d, links = st.results[j.job_id]
-        r_solo, l_solo = solo(j.dims, inputs[j.job_id], gf.GF_MIXED, j.anneal, j.seed)
+        r_solo, l_solo = solo(j.dims, inputs[j.job_id], gf.GF_MIXED, j.anneal, j.seed, storage=reals32)
         assert d["result"] == r_solo, (j, d["result"], r_solo)
         assert np.array_equal(links, l_solo)
