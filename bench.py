@@ -11,10 +11,14 @@ Extra legs (reported inside the same line; each has a --no-... switch): the
 float32 sweep rate; the float64 sweep on the 48^3 x 96 lattice (4.08 GB of
 links, far above the 256 MB Infinity Cache: the HBM-only bandwidth point);
 the float64 sweeps of both lattices with links stored in 8 reals (the minimal
-representation, 1024 B per site update); the 32^4 run to theta < 1e-12 in float64 and in mixed precision (capped; also
-on a smoother input of the same generator, eps = 0.6, which converges); the
+representation, 1024 B per site update); the float32 sweeps of the 48^3 x 96
+lattice with links in 12 and in 8 reals (768 / 512 B per site update); the
+32^4 run to theta < 1e-12 in float64 and in mixed precision with float32 links
+in 12 and in 8 reals (capped; also on a smoother input of the same generator,
+eps = 0.6, which converges); the
 8^4 convergence workload in float64 and mixed precision; the 64-lattice
-batched workload (mixed-precision pool vs float64 one lattice at a time); the
+batched workload (mixed-precision pool, float32 links in 8 reals by default,
+vs float64 one lattice at a time); the
 serving workload (Poisson arrivals of jobs of mixed volume, continuous-batching
 pool in mixed precision under an HBM budget vs float64 one lattice at a time:
 converged lattices/s and p50/p99 time to theta < 1e-12); the 48^3 x 96
@@ -46,7 +50,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, AMD published peak
 BYTES_PER_SITE = {"f64": 1536, "f32": 768,  # 8 links x 12 reals, read + write
-                  "f64_min8": 1024}  # 8 links x 8 reals (minimal representation), read + write
+                  "f64_min8": 1024, "f32_min8": 512}  # 8 links x 8 reals (minimal representation), read + write
 # Floating-point operations of one overrelaxation site update as the kernel computes it
 # (K tracked through the subgroups; exact power; add, sub, mul = 1, FMA = 2, sqrt, div,
 # atan2, sin, cos = 1 each): row 2 of 8 links 8 x 42 = 336, K from 8 leaves 7 x 18 = 126,
@@ -64,6 +68,9 @@ FULL_DIMS = (48, 48, 48, 96)
 SWEEP_SOURCES = ["gf_sweep.hip", "gf_sweep_impl.h", "gf_site.h", "gf_device.h"]
 # the 8-real sweep also compiles its codec and launcher
 MIN8_SOURCES = SWEEP_SOURCES + ["gf_min8.h", "gf_sweep_min8.hip"]
+MIN8F_SOURCES = SWEEP_SOURCES + ["gf_min8.h", "gf_sweep_min8f.hip"]
+TRAFFIC_FILE_48_F32 = os.path.join(ROOT, "profiles", "or_sweep_f32_48x96_traffic.md")
+TRAFFIC_FILE_48_F32_MIN8 = os.path.join(ROOT, "profiles", "or_sweep_f32min8_48x96_traffic.md")
 TRAFFIC_FILE_48_MIN8 = os.path.join(ROOT, "profiles", "or_sweep_f64min8_48x96_traffic.md")
 TRAFFIC_FILE_32_MIN8 = os.path.join(ROOT, "profiles", "or_sweep_f64min8_32x4_traffic.md")
 
@@ -192,28 +199,30 @@ def fix_until_leg(gf, torch, stream, links, dims, args, eps, adaptive_too=False)
     kw = dict(omega=args.omega, mode=args.mode, theta_target=1e-12, max_sweeps=args.fix_max_sweeps,
               check_every=10, reunit_every=100, theta_switch=args.theta_switch)
     P0 = None
-    runs = [("fp64", gf.GF_FP64, False), ("mixed", gf.GF_MIXED, False)]
+    runs = [("fp64", gf.GF_FP64, False, 12), ("mixed", gf.GF_MIXED, False, 12), ("mixed_min8", gf.GF_MIXED, False, 8)]
     if adaptive_too:
-        runs += [("fp64_adaptive", gf.GF_FP64, True), ("mixed_adaptive", gf.GF_MIXED, True)]
-    for name, prec, adaptive in runs:
-        with gf.Lattice(dims, prec, stream=stream) as lat:
+        runs += [("fp64_adaptive", gf.GF_FP64, True, 12), ("mixed_adaptive", gf.GF_MIXED, True, 12)]
+    for name, prec, adaptive, storage in runs:
+        with gf.Lattice(dims, prec, stream=stream, storage=storage) as lat:
             lat.set_check_policy(adaptive)
             lat.set_sweep_config(args.tps, args.block, args.nt, kernel=gf.GF_FP64, min_waves=args.minw)
             lat.set_links(links)
             if prec == gf.GF_MIXED:
                 # the float32 sweeps of a mixed lattice also update g(x): tuned as their own kernel
+                key = "mixed_fp32_config" if storage == 12 else "mixed_min8_fp32_config"
                 if args.no_tune:
                     lat.set_sweep_config(args.tps32, args.block32, args.nt32, kernel=gf.GF_FP32)
-                    out["mixed_fp32_config"] = [args.tps32, args.block32, args.nt32]
+                    out[key] = [args.tps32, args.block32, args.nt32]
                 else:
-                    out["mixed_fp32_config"] = list(lat.autotune(gf.GF_FP32, n_sweeps=5)[0])
-                log(f"fix_until eps={eps}: mixed float32 sweeps with g tracking at {out['mixed_fp32_config']}")
+                    out[key] = list(lat.autotune(gf.GF_FP32, n_sweeps=5)[0])
+                log(f"fix_until eps={eps}: {name} float32 sweeps with g tracking at {out[key]}")
             if P0 is None:
                 P0 = lat.plaquette()  # of the float64 input (a mixed lattice starts on float32 links)
             if prec == gf.GF_MIXED:
                 floor, sw = lat.tune_switch(1e-12)
-                out["fp32_theta_floor"] = floor
-                out["theta_switch"] = sw if args.theta_switch < 0 else args.theta_switch
+                pre = "" if storage == 12 else "min8_"
+                out[pre + "fp32_theta_floor"] = floor
+                out[pre + "theta_switch"] = sw if args.theta_switch < 0 else args.theta_switch
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             r = lat.fix_until(**kw)
@@ -226,9 +235,11 @@ def fix_until_leg(gf, torch, stream, links, dims, args, eps, adaptive_too=False)
         log(f"fix_until eps={eps} {name}: {dt:.2f} s, sweeps {r.sweeps} ({r.sweeps_fp32}/{r.sweeps_fp64}), "
             f"theta {r.theta:.3e}, F {r.F:.12f}")
     # the float64 GPU run is the reference here (it is parity-tested against the oracle)
-    out["mixed"]["dF_vs_fp64"] = out["mixed"]["F"] - out["fp64"]["F"]
-    out["mixed"]["dtheta_vs_fp64"] = out["mixed"]["theta"] - out["fp64"]["theta"]
+    for name in ("mixed", "mixed_min8"):
+        out[name]["dF_vs_fp64"] = out[name]["F"] - out["fp64"]["F"]
+        out[name]["dtheta_vs_fp64"] = out[name]["theta"] - out["fp64"]["theta"]
     out["speedup_mixed_vs_fp64"] = out["fp64"]["seconds"] / out["mixed"]["seconds"]
+    out["speedup_mixed_min8_vs_fp64"] = out["fp64"]["seconds"] / out["mixed_min8"]["seconds"]
     for name in ("fp64", "mixed"):
         a = out.get(name + "_adaptive")
         if a:
@@ -256,8 +267,10 @@ def batched_leg(gf, inputs, stream, args):
     ov = not args.no_overlap
     out["pool_autotune"] = tune
     out["pool_overlap"] = ov
+    r32 = args.pool_reals32
+    out["pool_float32_reals_per_link"] = r32
     legs = [("pool_mixed", lambda: serving.run_pool(jobs, lambda j: links[j.job_id], gf.GF_MIXED, 10, 64, None,
-                                                    fix, False, t32, t64, autotune=tune, overlap=ov))]
+                                                    fix, False, t32, t64, autotune=tune, overlap=ov, reals32=r32))]
     if args.batched_fp64_pool:
         legs.append(("pool_fp64", lambda: serving.run_pool(jobs, lambda j: links[j.job_id], gf.GF_FP64, 10, 64,
                                                            None, fix, False, t32, t64, autotune=tune, overlap=ov)))
@@ -302,11 +315,14 @@ def serving_leg(gf, inputs, stream, args):
            "jobs": len(jobs), "rate_per_s": 20.0, "max_sweeps": args.job_max_sweeps,
            "distinct_inputs": len(seeds), "last_arrival_s": jobs[-1].arrival, "pool_tps32": t32, "pool_tps64": t64,
            "hbm_budget_bytes": budget,
-           "largest_job_bytes": max(gf.gf_pool_job_bytes(j.dims, gf.GF_MIXED) for j in jobs),
+           "largest_job_bytes": max(gf.gf_pool_job_bytes(j.dims, gf.GF_MIXED, args.pool_reals32) for j in jobs),
            "pool_overlap": not args.no_overlap}
     ov = not args.no_overlap
     jlog = log if args.serve_verbose else None
-    st = serving.run_pool(jobs, links_of, gf.GF_MIXED, 10, 256, budget, fix, True, t32, t64, log=jlog, overlap=ov)
+    r32 = args.pool_reals32
+    out["pool_float32_reals_per_link"] = r32
+    st = serving.run_pool(jobs, links_of, gf.GF_MIXED, 10, 256, budget, fix, True, t32, t64, log=jlog, overlap=ov,
+                          reals32=r32)
     out["pool_mixed"] = st.summary()
     log(f"serving pool: {st.converged}/{len(jobs)} converged, {st.seconds:.1f} s, max queue {st.max_queue}, "
         f"peak {st.peak_bytes / 1e9:.2f} GB")
@@ -321,7 +337,7 @@ def serving_leg(gf, inputs, stream, args):
         # the same jobs all queued at t = 0: peak throughput, latency counted from t = 0
         closed = {}
         st = serving.run_pool(jobs, links_of, gf.GF_MIXED, 10, 256, budget, fix, False, t32, t64, log=jlog,
-                              overlap=ov)
+                              overlap=ov, reals32=r32)
         closed["pool_mixed"] = st.summary()
         log(f"serving closed loop pool: {st.converged}/{len(jobs)} converged, {st.seconds:.1f} s")
         st = serving.run_fifo(jobs, links_of, gf.GF_FP64, fix, False, args.tps, args.block, args.nt, log=jlog)
@@ -340,33 +356,38 @@ def fullsize_f64_leg(gf, torch, stream, u, args):
                      TRAFFIC_FILE_48)
 
 
-def sweep_leg(gf, torch, stream, u, dims, args, steps, storage, input_name, traffic_file=None):
-    """Tune, warm up and time `steps` float64 overrelaxation sweeps of one lattice whose links are
-    stored in `storage` reals (12: two rows; 8: the minimal representation)."""
+def sweep_leg(gf, torch, stream, u, dims, args, steps, storage, input_name, traffic_file=None, prec=None):
+    """Tune, warm up and time `steps` overrelaxation sweeps of one float64 (prec GF_FP64) or float32
+    (GF_FP32) lattice whose links are stored in `storage` reals (12: two rows; 8: the minimal
+    representation)."""
+    prec = gf.GF_FP64 if prec is None else prec
+    f32 = prec == gf.GF_FP32
+    tag = "fp32" if f32 else "fp64"
     V = u.shape[0]
     name = "x".join(map(str, dims))
-    with gf.Lattice(dims, gf.GF_FP64, stream=stream, storage=storage) as lat:
+    with gf.Lattice(dims, prec, stream=stream, storage=storage) as lat:
         lat.set_links(u)
         if args.no_tune:
-            (tps, block, nt, minw), table = ((args.tps, args.block, args.nt, args.minw) if storage == 12 else
+            (tps, block, nt, minw), table = ((args.tps32, args.block32, args.nt32, 0) if f32 else
+                                             (args.tps, args.block, args.nt, args.minw) if storage == 12 else
                                              (args.tps8, args.block8, args.nt8, 0)), []
             lat.set_sweep_config(tps, block, nt, min_waves=minw)
         else:
-            (tps, block, nt, minw), table = lat.autotune(gf.GF_FP64, n_sweeps=3)
-        log(f"{name} fp64/{storage}: tps={tps} block={block} cache policy={nt} min waves={minw}")
+            (tps, block, nt, minw), table = lat.autotune(prec, n_sweeps=3)
+        log(f"{name} {tag}/{storage}: tps={tps} block={block} cache policy={nt} min waves={minw}")
         with torch.cuda.stream(stream):
             lat.sweep(args.warmup, args.omega, args.mode)
             total, wall, per_launch = time_run(lat, torch, stream, steps, args.omega, args.mode, args.chunk)
         th, F = lat.measure()
     rate = V * steps / total
-    bps = BYTES_PER_SITE["f64"] if storage == 12 else BYTES_PER_SITE["f64_min8"]
+    bps = BYTES_PER_SITE[tag.replace("fp", "f") + ("" if storage == 12 else "_min8")]
     launch_bytes = (V // 2) * bps
     achieved = launch_bytes / per_launch / 1e9
-    log(f"{name} fp64/{storage}: {steps} sweeps in {total * 1e3:.1f} ms (mean half-sweep {per_launch * 1e6:.1f} us, "
+    log(f"{name} {tag}/{storage}: {steps} sweeps in {total * 1e3:.1f} ms (mean half-sweep {per_launch * 1e6:.1f} us, "
         f"{achieved:.0f} GB/s)")
     return {
-        "workload": "SU(3) Landau OR sweep, %s periodic, %s, omega=%g, %s power, FP64 %d-real links" % (
-            name, input_name, args.omega, "exact" if args.mode == 0 else "binomial", storage),
+        "workload": "SU(3) Landau OR sweep, %s periodic, %s, omega=%g, %s power, %s %d-real links" % (
+            name, input_name, args.omega, "exact" if args.mode == 0 else "binomial", tag.upper(), storage),
         "steps": steps,
         "value": rate,
         "unit": "site-updates/s",
@@ -380,10 +401,11 @@ def sweep_leg(gf, torch, stream, u, dims, args, steps, storage, input_name, traf
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": committed_traffic(traffic_file, SWEEP_SOURCES if storage == 12 else MIN8_SOURCES,
-                                         (tps, block, nt)),
-            "kernel": "k_or_half_sweep<double, TPS=%d, exact, BLOCK=%d, cache policy %d%s%s>" % (
-                tps, block, nt, ", 2 waves/SIMD" if minw == 2 else "", ", 8-real links" if storage == 8 else ""),
+            "traffic": committed_traffic(traffic_file, (MIN8F_SOURCES if f32 else MIN8_SOURCES) if storage == 8
+                                         else SWEEP_SOURCES, (tps, block, nt)),
+            "kernel": "k_or_half_sweep<%s, TPS=%d, exact, BLOCK=%d, cache policy %d%s%s>" % (
+                "float" if f32 else "double", tps, block, nt, ", 2 waves/SIMD" if minw == 2 else "",
+                ", 8-real links" if storage == 8 else ""),
             "algorithmic_bytes_per_launch": launch_bytes,
             "bytes_per_site_update": bps,
             "mean_launch_us": per_launch * 1e6,
@@ -416,13 +438,31 @@ def min8_legs(gf, torch, stream, links, dims, full, args):
     return out
 
 
+def fullsize_f32_legs(gf, torch, stream, full, args):
+    """Float32 overrelaxation sweeps on 48^3 x 96 (HBM-bound: 2.04 GB of 12-real float32 links)
+    with links in 12 reals (768 B per site update) and in 8 reals (512 B), and the storage tuner's
+    choice between them."""
+    out = {}
+    for storage, tf in ((12, TRAFFIC_FILE_48_F32), (8, TRAFFIC_FILE_48_F32_MIN8)):
+        out["reals_%d" % storage] = sweep_leg(gf, torch, stream, full, FULL_DIMS, args, args.full_steps, storage,
+                                              "eps=1.0, seed 0", tf, prec=gf.GF_FP32)
+    with gf.Lattice(FULL_DIMS, gf.GF_FP32, stream=stream) as lat:
+        lat.set_links(full)
+        reals, us12, us8 = lat.autotune_storage(3)
+    out["storage_autotune"] = {"chosen_reals_per_link": reals, "us_per_sweep_12": us12, "us_per_sweep_8": us8}
+    out["speedup_8_vs_12"] = out["reals_8"]["value"] / out["reals_12"]["value"]
+    log(f"48x96 fp32: 8 reals {out['speedup_8_vs_12']:.2f}x the 12-real sweep rate; tuner chose {reals}")
+    return out
+
+
 def fullsize_leg(gf, torch, stream, u, args):
     """The 48^3 x 96 workload (eps = 1.0, seed 0) in mixed precision: 2000 float32 heat-bath sweeps
     on g(x) with T falling linearly from 1.25 to 0.01 (Philox per site), then overrelaxation to
     theta < 1e-13 with float32 bulk, float64 polish and reunitarisation every 100 sweeps."""
     dims = FULL_DIMS
     V = u.shape[0]
-    out = {"workload": "48x48x48x96, eps=1.0, seed 0; anneal 2000 (T 1.25 -> 0.01), then OR to theta < 1e-13",
+    out = {"workload": "48x48x48x96, eps=1.0, seed 0; anneal 2000 (T 1.25 -> 0.01), then OR to theta < 1e-13; "
+                       "float32 links in the storage the tuner picks",
            "max_sweeps": args.full_max_sweeps}
     with gf.Lattice(dims, gf.GF_FP64, stream=stream) as lat:
         lat.set_links(u)
@@ -430,6 +470,10 @@ def fullsize_leg(gf, torch, stream, u, args):
     with gf.Lattice(dims, gf.GF_MIXED, stream=stream) as lat:
         lat.set_links(u)
         cfg = {}
+        # the float32 links' storage (12 or 8 reals) as a tuning axis, then every kernel's shape
+        reals, us12, us8 = lat.autotune_storage(3)
+        out["float32_storage"] = {"chosen_reals_per_link": reals, "us_per_sweep_12": us12, "us_per_sweep_8": us8}
+        log(f"fullsize mixed: float32 links in {reals} reals (12: {us12:.0f} us, 8: {us8:.0f} us per sweep)")
         for kernel, name in ((gf.GF_FP32, "f32"), (gf.GF_FP64, "f64")):
             chosen, _ = lat.autotune(kernel, n_sweeps=3)
             cfg[name] = list(chosen)
@@ -592,6 +636,8 @@ def main(argv=None):
                          "retiring and admitting while the next step runs")
     ap.add_argument("--no-fifo", action="store_true",
                     help="batched and serving legs: skip the float64 one-lattice-at-a-time comparison")
+    ap.add_argument("--pool-reals32", type=int, default=8, choices=(8, 12),
+                    help="batched and serving pools: reals per float32 link (8: the minimal representation)")
     ap.add_argument("--pool-tps32", type=int, default=2,
                     help="lanes per site of the pool's float32 sweeps (2: fastest over the batched set on MI355X)")
     ap.add_argument("--no-pool-autotune", action="store_true",
@@ -801,6 +847,8 @@ def main(argv=None):
         line["fullsize_48x96_f64"] = fullsize_f64_leg(gf, torch, stream, full, args)
     if not args.no_min8:
         line["f64_min8"] = min8_legs(gf, torch, stream, links, dims, full, args)
+    if not args.no_fullsize and not args.no_fp32:
+        line["fullsize_48x96_f32"] = fullsize_f32_legs(gf, torch, stream, full, args)
     del full
     fix8 = None
     if not args.no_fix:

@@ -94,9 +94,16 @@ __device__ __forceinline__ uint32_t low_bit(float v)
     return __float_as_uint(v) & 1u;
 }
 
+// Float32: a value whose lowest bit differs from the flag moves one unit in the
+// last place up or down in magnitude, chosen by its next bit, so that a flag
+// adds no bias.  (Clearing or setting the bit would shrink or grow the
+// flagged values by half a unit on average at every store, a drift that
+// sweeps compound: a float32 unit is 2^29 times a float64 one.)
 __device__ __forceinline__ float with_low_bit(float v, uint32_t bit)
 {
-    return __uint_as_float((__float_as_uint(v) & ~1u) | bit);
+    uint32_t u = __float_as_uint(v);
+    if ((u & 1u) != bit) u = (u & 2u) ? u - 1u : u + 1u;
+    return __uint_as_float(u);
 }
 
 // Largest stored half-angle tangent: t^2 + 1 stays finite in the type (the

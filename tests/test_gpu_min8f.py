@@ -66,7 +66,7 @@ def test_storage_roundtrip_and_footprint(prec):
     V = gi.volume(RAGGED)
     say(f"min8 float32 set/get vs float64 store: {d:.2e}; unitarity {du:.1e} {dd:.1e}; bytes {b8} vs {b12}")
     assert d <= 1e-6
-    assert du <= 2e-15 and dd <= 2e-15
+    assert du <= 4e-15 and dd <= 4e-15  # entries of the float64 decode within ~2 units each
     ld = -(-(V // 2) // 64) * 64  # sites per (colour, direction) plane, padded to whole 64-site tiles
     assert b12 - b8 == 2 * 4 * ld * 16  # one float4 chunk less per link
 
@@ -214,7 +214,7 @@ def test_anneal_keeps_the_orbit(prec):
             P64 = lat.plaquette()
     du, dd = oracle.unitarity(links.copy())
     say(f"min8 float32 anneal prec={prec}: F {F0:.6f} -> {F1:.6f}; plaquette drift {abs(P32 - P0):.2e}")
-    assert du <= 2e-15 and dd <= 2e-15
+    assert du <= 4e-15 and dd <= 4e-15  # entries of the float64 decode within ~2 units each
     assert abs(P32 - P0) < 1e-5
     assert F1 != F0
     if prec == gf.GF_MIXED:
@@ -297,3 +297,23 @@ def test_set_storage_converts_both_ways_and_autotune(tmp_path):
         reals, us12, us8 = lat.autotune_storage(2)
         say(f"float32 storage autotune: chose {reals}; 12 reals {us12:.1f} us, 8 reals {us8:.1f} us")
         assert lat.storage == reals == (8 if us8 < us12 else 12) and us12 > 0 and us8 > 0
+
+
+def test_flags_add_no_drift():
+    """The pivot and q flags ride in the lowest bits of three float32 values; setting them must not
+    bias those values (clearing or setting the bit shrinks or grows them by half a unit on average
+    at every store, which 1500 sweeps compound into a plaquette drift of the float32 links of
+    ~1e-5 on this input).  Unbiased flags leave the drift at the level of plain float32 rounding:
+    below 3e-6 here, where the 12-real float32 links drift 4.5e-7."""
+    dims = (16, 16, 16, 16)
+    u = gi.gen_links(dims, 0.8, 0)
+    P0 = oracle.plaquette(u, dims)
+    drift = {}
+    for storage in (12, 8):
+        with gf.Lattice(dims, gf.GF_MIXED, storage=storage) as lat:
+            lat.set_links(u)
+            lat.sweep(1500, 1.7)
+            lat.reunitarize()
+            drift[storage] = lat.plaquette() - P0
+    say(f"float32 plaquette drift after 1500 sweeps: 12 reals {drift[12]:+.2e}, 8 reals {drift[8]:+.2e}")
+    assert abs(drift[8]) < 3e-6
