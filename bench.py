@@ -89,20 +89,20 @@ def sweep_source_hash(sources=SWEEP_SOURCES) -> str:
 
 def committed_traffic(path, sources, config):
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary, or None when it
-    is missing, the sweep kernel changed since, or it was taken in another launch configuration
-    (tps, block, cache policy) than `config`."""
+    is missing, the sweep kernel changed since, or no counts were taken in the launch
+    configuration (tps, block, cache policy) `config`.  The summary holds one line
+    `traffic_per_launch: <tps> <block> <policy> <bytes>` per configuration counted."""
     try:
         text = open(path).read()
     except (OSError, TypeError):
         return None
     src = re.search(r"kernel_source_sha256:\s*([0-9a-f]+)", text)
-    val = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    cfg = re.search(r"kernel_config:\s*(\d+) (\d+) (\d+)", text)
-    if not src or not val or not cfg or src.group(1) != sweep_source_hash(sources):
+    if not src or src.group(1) != sweep_source_hash(sources):
         return None
-    if tuple(int(x) for x in cfg.groups()) != tuple(config):
-        return None
-    return float(val.group(1))
+    for m in re.finditer(r"traffic_per_launch:\s*(\d+) (\d+) (\d+) ([0-9.eE+]+)", text):
+        if tuple(int(x) for x in m.groups()[:3]) == tuple(config):
+            return float(m.group(4))
+    return None
 
 
 def host_cpu_model() -> str:
