@@ -197,6 +197,12 @@ __global__ void __launch_bounds__(BLOCK) k_pool_sweep(const SlotDev* __restrict_
         slot = list[i].slot;
         first = list[i].first;
     }
+    // The tile, hence its entry, is the block's: moving slot and first to scalar
+    // registers lets the slot descriptor load through the scalar cache and keeps
+    // the geometry's index arithmetic on the scalar unit, as in the
+    // single-lattice kernel, whose geometry is a kernel argument.
+    slot = __builtin_amdgcn_readfirstlane(slot);
+    first = __builtin_amdgcn_readfirstlane(first);
     const SlotDev sd = slots[slot];
     const uint32_t h = (t - first) * SPB + threadIdx.x / TPS;
     const int r = (int)(threadIdx.x % TPS);
