@@ -4,7 +4,8 @@ for float64; 2 lanes, 64-thread blocks for float32).
 
 48^3 x 96 (10,616,832 sites, eps = 1.0, seed 0): one float64 sweep and two
 heat-bath sweeps compared with the FP64 oracle link by link (1e-12), theta/F
-of the input, then the mixed-precision pipeline of that workload (2000 float32
+of the input, one float64 sweep with links in 12 and in 8 reals in the
+autotuner's launch configuration against the oracle, then the mixed-precision pipeline of that workload (2000 float32
 heat-bath sweeps T 1.25 -> 0.01 tracking g, overrelaxation with float32 bulk
 and float64 polish, reunitarisation every 100 sweeps) checked through what
 holds at any size: gauge invariance of the plaquette (1e-12 after the float64
@@ -78,6 +79,29 @@ def test_48x96_fp64_sweep_and_heat_bath_parity(big_links):
     say(f"  heat bath max|diff| {d:.2e}, oracle capped {capped}")
     assert capped == 0
     assert d <= 1e-12
+
+
+@pytest.mark.timeout(900)
+def test_48x96_autotuned_fp64_sweep_parity(big_links):
+    """One float64 sweep with links in 12 and in 8 reals, each in the launch configuration the
+    autotuner picks on this GPU (what the benchmark times), against the oracle link by link.  As
+    in the 8-real parity tests, the oracle sweeps the links the 8-real representation holds
+    (oracle.min8_store of the input): on this rough input some sites have nearly degenerate
+    subgroup blocks, where the sweep magnifies a rounding-level change of its input links."""
+    for storage in (12, 8):
+        u = big_links if storage == 12 else oracle.min8_store(big_links.copy())
+        say(f"48^3x96 autotuned, {storage} reals: oracle sweep")
+        ref = u.copy()
+        oracle.sweep(ref, BIG, 1, 1.7, oracle.OR_EXACT)
+        with gf.Lattice(BIG, storage=storage) as lat:
+            lat.set_links(u)
+            chosen, _ = lat.autotune(gf.GF_FP64, n_sweeps=3)
+            lat.sweep(1, 1.7, gf.GF_OR_EXACT)
+            got = lat.get_links()
+        d = float(np.abs(got - ref).max())
+        say(f"  {storage} reals, tuned {chosen}: max|diff| after 1 sweep {d:.2e}")
+        assert d <= 1e-12
+        del got, ref, u
 
 
 @pytest.mark.timeout(900)

@@ -296,6 +296,28 @@ def test_full_size_32x4_one_sweep():
         assert abs(F1 - F1_o) <= 1e-13
 
 
+def test_full_size_32x4_autotuned_one_sweep():
+    """32^4, eps = 0.8, seed 0, float64 links in 12 and in 8 reals, each in the launch configuration
+    the autotuner picks on this GPU (the configuration the benchmark times, whatever run-to-run
+    timing noise makes it): every link after one sweep against the oracle (for 8 reals, the
+    oracle's sweep of the links the representation holds, as in the 8-real parity tests)."""
+    dims = (32, 32, 32, 32)
+    say("full size 32^4 autotuned: generating")
+    u0 = gi.gen_links(dims, 0.8, 0)
+    for storage in (12, 8):
+        u = u0 if storage == 12 else oracle.min8_store(u0.copy())
+        ref = u.copy()
+        oracle.sweep(ref, dims, 1, 1.7, 0)
+        with gf.Lattice(dims, storage=storage) as lat:
+            lat.set_links(u)
+            chosen, _ = lat.autotune(gf.GF_FP64, n_sweeps=3)
+            lat.sweep(1, 1.7, 0)
+            got = lat.get_links()
+        d = maxdiff(got, ref)
+        say(f"  {storage} reals, tuned {chosen}: max|diff| after 1 sweep {d:.3e}")
+        assert d <= 1e-12
+
+
 def test_graph_replays_match_direct_launches():
     """On a non-default stream multi-sweep runs are replayed hipGraphs; every replay (with
     eager work and synchronisation between replays) must equal direct launches bitwise."""
