@@ -291,29 +291,36 @@ def batched_leg(gf, inputs, stream, args):
 def serving_jobs(args):
     from paper_1412_3655_amd import serving
 
-    jobs = serving.serving_trace(args.serve_jobs, 20.0, 5)
-    bank = {}
-    for j in jobs:
-        bank.setdefault((j.dims, j.eps), 3000 + len(bank))
-    return jobs, bank
+    buckets = (0.4, 0.7, 1.0) if args.serve_eps_buckets else None
+    jobs = serving.serving_trace(args.serve_jobs, 20.0, 5, eps_buckets=buckets)
+    if buckets:
+        # one input per (L, eps), shared by the jobs that draw it
+        bank = {}
+        for j in jobs:
+            bank.setdefault((j.dims, j.eps), 3000 + len(bank))
+        return jobs, {j.job_id: bank[(j.dims, j.eps)] for j in jobs}
+    return jobs, {j.job_id: j.seed for j in jobs}  # every job its own input, seed 2000 + k
 
 
 def serving_leg(gf, inputs, stream, args):
     """Poisson arrivals (20/s) of jobs of mixed volume: continuous batching vs FP64 FIFO."""
     from paper_1412_3655_amd import serving
 
-    jobs, seeds = serving_jobs(args)
-    links_of = lambda j: inputs.get(j.dims, j.eps, seeds[(j.dims, j.eps)])
+    jobs, seed_of = serving_jobs(args)
+    links_of = lambda j: inputs.get(j.dims, j.eps, seed_of[j.job_id])
+    if args.serve_eps_buckets:
+        eps_text = ("eps drawn uniform in [0.4, 1.0] and rounded to the nearest of {0.4, 0.7, 1.0}, and jobs with "
+                    "equal (L, eps) share one input")
+    else:
+        eps_text = "eps uniform in [0.4, 1.0], every job its own input (link seed 2000 + k)"
     fix = dict(omega=args.omega, mode=args.mode, theta_target=1e-12, max_sweeps=args.job_max_sweeps, check_every=10,
                reunit_every=100, theta_switch=args.theta_switch)
     t32, t64 = args.pool_tps32, args.pool_tps64
     budget = int(args.serve_budget_gb * 1e9) if args.serve_budget_gb > 0 else None
     out = {"workload": f"{len(jobs)} Poisson arrivals at 20/s (master seed 5), L^4 with V log-uniform in "
-                       "[8^4, 32^4], 30 % with a 500-sweep anneal (T 1.25 -> 0.01), to theta < 1e-12; eps drawn "
-                       "uniform in [0.4, 1.0] and rounded to the nearest of {0.4, 0.7, 1.0}, and jobs with equal "
-                       "(L, eps) share one input (each input takes seconds of CPU to generate)",
+                       "[8^4, 32^4], 30 % with a 500-sweep anneal (T 1.25 -> 0.01), to theta < 1e-12; " + eps_text,
            "jobs": len(jobs), "rate_per_s": 20.0, "max_sweeps": args.job_max_sweeps,
-           "distinct_inputs": len(seeds), "last_arrival_s": jobs[-1].arrival, "pool_tps32": t32, "pool_tps64": t64,
+           "distinct_inputs": len({(j.dims, j.eps, seed_of[j.job_id]) for j in jobs}), "last_arrival_s": jobs[-1].arrival, "pool_tps32": t32, "pool_tps64": t64,
            "hbm_budget_bytes": budget,
            "largest_job_bytes": max(gf.gf_pool_job_bytes(j.dims, gf.GF_MIXED, args.pool_reals32) for j in jobs),
            "pool_overlap": not args.no_overlap}
@@ -626,6 +633,9 @@ def main(argv=None):
     ap.add_argument("--serve", action="store_true", help="(the serving leg runs by default; kept for scripts)")
     ap.add_argument("--no-serve", action="store_true", help="skip the Poisson-arrival serving workload")
     ap.add_argument("--serve-jobs", type=int, default=100)
+    ap.add_argument("--serve-eps-buckets", action="store_true",
+                    help="serving leg: round eps to the nearest of {0.4, 0.7, 1.0} and share one input per (L, eps) "
+                         "(host memory and generation time of long traces)")
     ap.add_argument("--serve-verbose", action="store_true", help="log every finished serving job")
     ap.add_argument("--serve-closed", action="store_true",
                     help="also run the serving jobs closed loop (all queued at t = 0: peak lattices/s)")
@@ -659,7 +669,8 @@ def main(argv=None):
                     help="float32 -> float64 switch of the mixed runs; < 0: chosen by gf_tune_switch")
     ap.add_argument("--no-tune", action="store_true",
                     help="use --tps/--block/--nt (12-real) and --tps8/--block8/--nt8 (8-real) instead of the autotuner")
-    ap.add_argument("--gen-threads", type=int, default=8, help="host threads generating the inputs up front")
+    ap.add_argument("--gen-threads", type=int, default=min(16, os.cpu_count() or 1),
+                    help="host threads generating the inputs up front")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -696,8 +707,9 @@ def main(argv=None):
         for j in serving.batched_jobs(64, 4):
             inputs.want(j.dims, j.eps, j.seed)
     if not args.no_serve:
-        for (d, e), seed in serving_jobs(args)[1].items():
-            inputs.want(d, e, seed)
+        sjobs, seed_of = serving_jobs(args)
+        for j in sjobs:
+            inputs.want(j.dims, j.eps, seed_of[j.job_id])
     log(f"generating {len(inputs.fut)} inputs on {args.gen_threads} threads")
     links = inputs.get(dims, args.eps, args.seed)
     stream = torch.cuda.Stream()

@@ -110,11 +110,12 @@ def batched_jobs(n=64, master_seed=4):
 
 
 def serving_trace(n=1000, rate=20.0, master_seed=5, anneal_fraction=0.3, anneal_sweeps=500,
-                  eps_buckets=(0.4, 0.7, 1.0)):
+                  eps_buckets=None):
     """The serving workload: Poisson arrivals at `rate` per second; V log-uniform between 8^4 and
-    32^4 with L = even extent nearest V^(1/4); eps uniform in [0.4, 1.0], rounded to the nearest
-    of `eps_buckets` (so inputs can be generated once per (L, eps) and reused); a fraction of the
-    jobs with an annealing prelude; job seed 2000 + k."""
+    32^4 with L = even extent nearest V^(1/4); eps uniform in [0.4, 1.0] (rounded to the nearest
+    of `eps_buckets` when given, so that a long trace can generate one input per (L, eps) and
+    reuse it); a fraction of the jobs with an annealing prelude; job seed 2000 + k.  The random
+    draws do not depend on `eps_buckets`: arrivals, extents and preludes are the same either way."""
     rng = np.random.default_rng(master_seed)
     t = 0.0
     out = []
@@ -124,7 +125,8 @@ def serving_trace(n=1000, rate=20.0, master_seed=5, anneal_fraction=0.3, anneal_
         L = int(round(math.exp(logv / 4.0) / 2.0)) * 2
         L = min(32, max(8, L))
         eps = float(rng.uniform(0.4, 1.0))
-        eps = min(eps_buckets, key=lambda e: abs(e - eps))
+        if eps_buckets:
+            eps = min(eps_buckets, key=lambda e: abs(e - eps))
         anneal = anneal_sweeps if rng.random() < anneal_fraction else 0
         out.append(Job(k, (L, L, L, L), eps, 2000 + k, t, anneal))
     return out
