@@ -648,12 +648,14 @@ def main(argv=None):
                     help="batched and serving legs: skip the float64 one-lattice-at-a-time comparison")
     ap.add_argument("--pool-reals32", type=int, default=8, choices=(8, 12),
                     help="batched and serving pools: reals per float32 link (8: the minimal representation)")
-    ap.add_argument("--pool-tps32", type=int, default=2,
-                    help="lanes per site of the pool's float32 sweeps (2: fastest over the batched set on MI355X)")
+    ap.add_argument("--pool-tps32", type=int, default=0,
+                    help="lanes per site of the pool's float32 sweeps (0: the library's default, 1 with 8-real "
+                         "links and 2 with 12-real links, the fastest over the batched set on MI355X)")
     ap.add_argument("--no-pool-autotune", action="store_true",
                     help="batched leg: keep the pool's default sweep shape instead of gf_pool_autotune")
-    ap.add_argument("--pool-tps64", type=int, default=1,
-                    help="lanes per site of the pool's float64 sweeps (1: fastest over the batched set on MI355X)")
+    ap.add_argument("--pool-tps64", type=int, default=0,
+                    help="lanes per site of the pool's float64 sweeps (0: the library's default, 1, the fastest "
+                         "over the batched set on MI355X)")
     ap.add_argument("--fullsize", action="store_true", help="(the 48^3x96 legs run by default; kept for scripts)")
     ap.add_argument("--no-fullsize", action="store_true",
                     help="skip the 48^3x96 float64 sweep and the 48^3x96 anneal + mixed-precision workload")

@@ -461,7 +461,8 @@ typedef struct {
     int32_t mode;        /* gf_or_mode of every job */
     int32_t tps32, block32, tps64, block64; /* shape of the pool's float32 / float64 overrelaxation
                                                sweeps: lanes per site (1, 2 or 4; 0 = default: 2 for
-                                               float32, 1 for float64) and threads per block (64, 128
+                                               float32 in 12 reals, 1 for float32 in 8 reals, 1 for
+                                               float64) and threads per block (64, 128
                                                or 256; 0 = 128).  Every shape gives bitwise the same
                                                links; gf_pool_autotune picks the fastest for the
                                                resident jobs.  The heat-bath sweeps use one lane per
@@ -548,7 +549,8 @@ gf_status gf_pool_cancel(gf_pool pool, uint64_t job_id);
  * GF_FP64: the float64 links) of the resident jobs, in slot order and up to
  * scratch_bytes of copies, times one warm-up and n_sweeps sweeps (both
  * colours) of that set for every shape (lanes per site 1, 2, 4; threads per
- * block 64, 128, 256) with HIP events, writes up to cap entries to table (may
+ * block 64, 128, 256) with HIP events, in two rounds over all shapes of which
+ * each shape keeps its faster time, writes up to cap entries to table (may
  * be NULL; nontemporal = the pool's cache policy, 0 float32, 1 float64), and
  * makes the fastest the pool's shape for that kernel (*chosen, may be NULL).
  * The jobs' links are not changed.  GF_E_STATE if no resident job fits in

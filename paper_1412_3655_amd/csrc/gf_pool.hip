@@ -50,9 +50,10 @@ constexpr int kHeatBathTps = 1;  // lanes per site of the heat-bath sweeps (its 
 constexpr int kHeatBathBlock = 128;  // threads per block of the heat-bath sweeps
 // Default shape of the overrelaxation sweeps (lanes per site, threads per
 // block): the fastest over 64 lattices of 12^4 to 24^3x48 on MI355X (float32
-// with g: 2 lanes, float64: 1 lane, 3 % ahead of 2; 128 threads for both);
-// gf_pool_autotune picks them for the resident mix.
-constexpr int kDefaultTps32 = 2, kDefaultTps64 = 1, kDefaultBlock = 128;
+// with g: 2 lanes with 12-real links, 1 lane with 8-real links, 5 % ahead of
+// 2; float64: 1 lane, 3 % ahead of 2; 128 threads for all); gf_pool_autotune
+// picks them for the resident mix.
+constexpr int kDefaultTps32 = 2, kDefaultTps32Min8 = 1, kDefaultTps64 = 1, kDefaultBlock = 128;
 // Staging buffer through which admissions and fetches move a job's canonical
 // links (18 doubles per link) in chunks; a multiple of one site's 4 links.
 constexpr size_t kStageLinks = (size_t)4 * 58254;  // 33.6 MB
@@ -939,7 +940,7 @@ gf_status gf_pool_create(const gf_pool_config* cfg, void* hip_stream, gf_pool* o
     if (c.reals32 == 0) c.reals32 = 12;
     if (c.reals32 != 12 && c.reals32 != 8) return fail(GF_E_ARG, "reals32 must be 0, 12 or 8");
     if (c.reals32 == 8 && c.prec != GF_MIXED) return fail(GF_E_ARG, "8-real float32 links need a GF_MIXED pool");
-    if (c.tps32 == 0) c.tps32 = kDefaultTps32;
+    if (c.tps32 == 0) c.tps32 = c.reals32 == 8 ? kDefaultTps32Min8 : kDefaultTps32;
     if (c.tps64 == 0) c.tps64 = kDefaultTps64;
     if (c.block32 == 0) c.block32 = kDefaultBlock;
     if (c.block64 == 0) c.block64 = kDefaultBlock;
@@ -1244,11 +1245,16 @@ gf_status gf_pool_autotune(gf_pool P, int32_t kernel, int32_t n_sweeps, size_t s
     if (st == GF_OK && e == hipSuccess) e = hipStreamSynchronize(P->stream);
 
     const int mode = P->cfg.mode;
-    int best_tps = 0, best_block = 0, m = 0;
-    double best_us = 1e300;
-    for (int tps : {1, 2, 4}) {
-        for (int block : {64, 128, 256}) {
+    // Two rounds over every shape, each shape keeping its faster time: a single
+    // round favours the shapes timed after the clocks have settled.
+    static const int kShapes[9][2] = {{1, 64}, {1, 128}, {1, 256}, {2, 64}, {2, 128},
+                                      {2, 256}, {4, 64}, {4, 128}, {4, 256}};
+    double shape_us[9];
+    for (double& x : shape_us) x = 1e300;
+    for (int round = 0; round < 2; ++round) {
+        for (int si = 0; si < 9; ++si) {
             if (st != GF_OK || e != hipSuccess) break;
+            const int tps = kShapes[si][0], block = kShapes[si][1];
             uint32_t tiles = 0;
             for (size_t i = 0; i < n; ++i) {
                 list[i] = Entry{(uint32_t)i, tiles};
@@ -1292,14 +1298,19 @@ gf_status gf_pool_autotune(gf_pool P, int32_t kernel, int32_t n_sweeps, size_t s
             float ms = 0.f;
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
             if (e != hipSuccess) break;
-            const double us = 1e3 * (double)ms / n_sweeps;
-            if (m < cap) table[m] = gf_tune_entry{tps, block, f32 ? 0 : 1, 0, us};
-            ++m;
-            if (us < best_us) {
-                best_us = us;
-                best_tps = tps;
-                best_block = block;
-            }
+            shape_us[si] = std::min(shape_us[si], 1e3 * (double)ms / n_sweeps);
+        }
+    }
+    int best_tps = 0, best_block = 0, m = 0;
+    double best_us = 1e300;
+    for (int si = 0; si < 9 && st == GF_OK && e == hipSuccess; ++si) {
+        const int tps = kShapes[si][0], block = kShapes[si][1];
+        if (m < cap) table[m] = gf_tune_entry{tps, block, f32 ? 0 : 1, 0, shape_us[si]};
+        ++m;
+        if (shape_us[si] < best_us) {
+            best_us = shape_us[si];
+            best_tps = tps;
+            best_block = block;
         }
     }
     if (st == GF_OK && e != hipSuccess) st = fail(GF_E_HIP, "pool autotune: %s", hipGetErrorString(e));
