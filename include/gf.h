@@ -469,6 +469,11 @@ typedef struct {
                                                site and 128-thread blocks. */
     int32_t reals32;     /* storage of the float32 links of a GF_MIXED pool: 12 (or 0) two rows, 8 the
                             8-real representation (gf_set_storage); 12 or 0 for a GF_FP64 pool */
+    int32_t cache32, cache64; /* cache policy of the link loads and stores of the float32 / float64
+                                 overrelaxation sweeps: 1 plain, 2 non-temporal, 0 = default (float32:
+                                 non-temporal in 8 reals, plain in 12 reals; float64: non-temporal); the
+                                 same links either way, and an axis of gf_pool_autotune.  The heat-bath
+                                 sweeps keep plain accesses for float32, non-temporal for float64. */
 } gf_pool_config;
 
 typedef struct {
@@ -549,10 +554,11 @@ gf_status gf_pool_cancel(gf_pool pool, uint64_t job_id);
  * GF_FP64: the float64 links) of the resident jobs, in slot order and up to
  * scratch_bytes of copies, times one warm-up and n_sweeps sweeps (both
  * colours) of that set for every shape (lanes per site 1, 2, 4; threads per
- * block 64, 128, 256) with HIP events, in two rounds over all shapes of which
- * each shape keeps its faster time, writes up to cap entries to table (may
- * be NULL; nontemporal = the pool's cache policy, 0 float32, 1 float64), and
- * makes the fastest the pool's shape for that kernel (*chosen, may be NULL).
+ * block 64, 128, 256; cache policy plain or non-temporal: 18 shapes) with HIP
+ * events, in two rounds over all shapes of which each shape keeps its faster
+ * time, writes up to cap entries to table (may be NULL; nontemporal = 0 plain,
+ * 1 non-temporal), and makes the fastest the pool's shape and cache policy for
+ * that kernel (*chosen, may be NULL).
  * The jobs' links are not changed.  GF_E_STATE if no resident job fits in
  * scratch_bytes.  Allocates and frees the copies.  Syncs. */
 gf_status gf_pool_autotune(gf_pool pool, int32_t kernel, int32_t n_sweeps, size_t scratch_bytes,
@@ -560,6 +566,10 @@ gf_status gf_pool_autotune(gf_pool pool, int32_t kernel, int32_t n_sweeps, size_
 
 /* The pool's current sweep shape (any pointer may be NULL). */
 gf_status gf_pool_get_shape(gf_pool pool, int32_t* tps32, int32_t* block32, int32_t* tps64, int32_t* block64);
+
+/* The pool's current cache policy of the float32 / float64 overrelaxation
+ * sweeps as in gf_pool_config (1 plain, 2 non-temporal; any pointer may be NULL). */
+gf_status gf_pool_get_cache(gf_pool pool, int32_t* cache32, int32_t* cache64);
 
 /* Resident jobs still iterating, finished jobs not yet released, and device
  * bytes held for job lattices (including those released during a step in

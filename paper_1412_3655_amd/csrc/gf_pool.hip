@@ -51,7 +51,9 @@ constexpr int kHeatBathBlock = 128;  // threads per block of the heat-bath sweep
 // Default shape of the overrelaxation sweeps (lanes per site, threads per
 // block): the fastest over 64 lattices of 12^4 to 24^3x48 on MI355X (float32
 // with g: 2 lanes with 12-real links, 1 lane with 8-real links, 5 % ahead of
-// 2; float64: 1 lane, 3 % ahead of 2; 128 threads for all); gf_pool_autotune
+// 2; float64: 1 lane, 3 % ahead of 2; 128 threads for all) and cache policy
+// (non-temporal for float32 in 8 reals, 1-4 % ahead of plain at one lane;
+// plain for float32 in 12 reals; non-temporal for float64); gf_pool_autotune
 // picks them for the resident mix.
 constexpr int kDefaultTps32 = 2, kDefaultTps32Min8 = 1, kDefaultTps64 = 1, kDefaultBlock = 128;
 // Staging buffer through which admissions and fetches move a job's canonical
@@ -167,26 +169,25 @@ __device__ __forceinline__ double schedule_T(const SlotDev& sd, uint32_t s)
     return sd.T0 + (sd.T1 - sd.T0) * (double)s / (double)(sd.n_anneal - 1);
 }
 
-// float64 links use non-temporal accesses, float32 ones plain accesses (the
-// autotuner's choice for either on MI355X: a float32 lattice can stay in the
-// Infinity Cache, a float64 one streams).
+// CP: cache policy of the link accesses (gf_device.h: 0 plain, 1 non-temporal),
+// a pool setting per precision (defaults above) and an axis of
+// gf_pool_autotune.
 // Block t sweeps tile t of the list (the host launches one block per tile of
 // the list; a block past the tile total lands past the last lattice's sites
-// and leaves).  White float32 sweeps take the tiles in reverse order, so they
-// start on the links the black sweep touched last (still in the Infinity
-// Cache); float64 sweeps load non-temporally and keep the forward order (on
-// MI355X the reverse order made them 1-2 % slower and the float32 ones 3 %
-// faster).  The order inside a colour does not change the result.  stride =
-// entries per list segment.  A tile is BLOCK / TPS sites.  M8: float32 links
-// stored in 8 reals.
-template <typename R, int TPS, int MODE, bool TRACKG, int BLOCK, bool M8>
+// and leaves).  With plain loads the white half-sweep takes the tiles in
+// reverse order, so it starts on the links the black sweep touched last
+// (still in the Infinity Cache); with non-temporal loads it keeps the forward
+// order (on MI355X the reverse order made non-temporal float64 sweeps 1-2 %
+// slower and plain float32 ones 3 % faster).  The order inside a colour does
+// not change the result.  stride = entries per list segment.  A tile is
+// BLOCK / TPS sites.  M8: float32 links stored in 8 reals.
+template <typename R, int TPS, int MODE, bool TRACKG, int BLOCK, bool M8, int CP>
 __global__ void __launch_bounds__(BLOCK) k_pool_sweep(const SlotDev* __restrict__ slots,
                                                       const Entry* __restrict__ list,
                                                       const uint32_t* __restrict__ count, uint32_t stride,
                                                       int parity, uint32_t k)
 {
     constexpr uint32_t SPB = BLOCK / TPS;
-    constexpr int CP = sizeof(R) == 8 ? 1 : 0;  // cache policy (gf_device.h)
     const uint32_t t = (parity && !nt_loads(CP)) ? gridDim.x - 1u - blockIdx.x : blockIdx.x;
     uint32_t slot, first;
     if (stride <= 64u * kWaveEntries) {
@@ -432,55 +433,76 @@ uint32_t tiles_of(const Geom& g, int kind, int tps, int block)
     }
 }
 
-template <typename R, int TPS, int MODE, bool TRACKG, bool M8>
+template <typename R, int TPS, int MODE, bool TRACKG, bool M8, int CP>
 hipError_t launch_sweep_tps(hipStream_t st, const SlotDev* slots, int block, uint32_t tiles, const Entry* list,
                             const uint32_t* count, uint32_t stride, int parity, uint32_t k)
 {
     const dim3 grid(tiles);
     switch (block) {
         case 64:
-            hipLaunchKernelGGL((k_pool_sweep<R, TPS, MODE, TRACKG, 64, M8>), grid, dim3(64), 0, st, slots, list, count,
-                               stride, parity, k);
+            hipLaunchKernelGGL((k_pool_sweep<R, TPS, MODE, TRACKG, 64, M8, CP>), grid, dim3(64), 0, st, slots, list,
+                               count, stride, parity, k);
             break;
         case 256:
-            hipLaunchKernelGGL((k_pool_sweep<R, TPS, MODE, TRACKG, 256, M8>), grid, dim3(256), 0, st, slots, list,
+            hipLaunchKernelGGL((k_pool_sweep<R, TPS, MODE, TRACKG, 256, M8, CP>), grid, dim3(256), 0, st, slots, list,
                                count, stride, parity, k);
             break;
         default:
-            hipLaunchKernelGGL((k_pool_sweep<R, TPS, MODE, TRACKG, 128, M8>), grid, dim3(128), 0, st, slots, list,
+            hipLaunchKernelGGL((k_pool_sweep<R, TPS, MODE, TRACKG, 128, M8, CP>), grid, dim3(128), 0, st, slots, list,
                                count, stride, parity, k);
             break;
     }
     return hipGetLastError();
 }
 
-// One sweep launch of kind (R, MODE, TRACKG, M8) over `tiles` tiles of block /
-// tps sites (tps 1, 2 or 4; block 64, 128 or 256).
-template <typename R, int MODE, bool TRACKG, bool M8>
-hipError_t launch_sweep_shape(hipStream_t st, const SlotDev* slots, int tps, int block, uint32_t tiles,
-                              const Entry* list, const uint32_t* count, uint32_t stride, int parity, uint32_t k)
+template <typename R, int MODE, bool TRACKG, bool M8, int CP>
+hipError_t launch_sweep_shape_cp(hipStream_t st, const SlotDev* slots, int tps, int block, uint32_t tiles,
+                                 const Entry* list, const uint32_t* count, uint32_t stride, int parity, uint32_t k)
 {
     switch (tps) {
         case 1:
-            return launch_sweep_tps<R, 1, MODE, TRACKG, M8>(st, slots, block, tiles, list, count, stride, parity, k);
+            return launch_sweep_tps<R, 1, MODE, TRACKG, M8, CP>(st, slots, block, tiles, list, count, stride, parity,
+                                                                k);
         case 2:
-            return launch_sweep_tps<R, 2, MODE, TRACKG, M8>(st, slots, block, tiles, list, count, stride, parity, k);
+            return launch_sweep_tps<R, 2, MODE, TRACKG, M8, CP>(st, slots, block, tiles, list, count, stride, parity,
+                                                                k);
         default:
-            return launch_sweep_tps<R, 4, MODE, TRACKG, M8>(st, slots, block, tiles, list, count, stride, parity, k);
+            return launch_sweep_tps<R, 4, MODE, TRACKG, M8, CP>(st, slots, block, tiles, list, count, stride, parity,
+                                                                k);
+    }
+}
+
+// One sweep launch of kind (R, MODE, TRACKG, M8) over `tiles` tiles of block /
+// tps sites (tps 1, 2 or 4; block 64, 128 or 256) with cache policy cp (0
+// plain loads and stores, 1 non-temporal; gf_device.h).  The heat-bath kinds
+// keep the fixed policy: plain for float32, non-temporal for float64.
+template <typename R, int MODE, bool TRACKG, bool M8>
+hipError_t launch_sweep_shape(hipStream_t st, const SlotDev* slots, int tps, int block, int cp, uint32_t tiles,
+                              const Entry* list, const uint32_t* count, uint32_t stride, int parity, uint32_t k)
+{
+    if constexpr (MODE == HEATBATH) {
+        constexpr int CPH = sizeof(R) == 8 ? 1 : 0;
+        return launch_sweep_shape_cp<R, MODE, TRACKG, M8, CPH>(st, slots, tps, block, tiles, list, count, stride,
+                                                               parity, k);
+    } else {
+        return cp == 1 ? launch_sweep_shape_cp<R, MODE, TRACKG, M8, 1>(st, slots, tps, block, tiles, list, count,
+                                                                       stride, parity, k)
+                       : launch_sweep_shape_cp<R, MODE, TRACKG, M8, 0>(st, slots, tps, block, tiles, list, count,
+                                                                       stride, parity, k);
     }
 }
 
 // The float32 kinds take the pool's float32 storage (M8: 8 reals per link).
 template <typename R, int MODE, bool TRACKG>
-hipError_t launch_sweep_kind(gf_pool P, int tps, int block, uint32_t tiles, const Entry* list, const uint32_t* count,
-                             int parity, uint32_t k)
+hipError_t launch_sweep_kind(gf_pool P, int tps, int block, int cp, uint32_t tiles, const Entry* list,
+                             const uint32_t* count, int parity, uint32_t k)
 {
     if constexpr (sizeof(R) == 4) {
         if (P->cfg.reals32 == 8)
-            return launch_sweep_shape<R, MODE, TRACKG, true>(P->stream, P->slots_dev, tps, block, tiles, list, count,
-                                                             (uint32_t)P->list_stride, parity, k);
+            return launch_sweep_shape<R, MODE, TRACKG, true>(P->stream, P->slots_dev, tps, block, cp, tiles, list,
+                                                             count, (uint32_t)P->list_stride, parity, k);
     }
-    return launch_sweep_shape<R, MODE, TRACKG, false>(P->stream, P->slots_dev, tps, block, tiles, list, count,
+    return launch_sweep_shape<R, MODE, TRACKG, false>(P->stream, P->slots_dev, tps, block, cp, tiles, list, count,
                                                       (uint32_t)P->list_stride, parity, k);
 }
 
@@ -498,22 +520,23 @@ hipError_t launch_kind(gf_pool P, int k, int kind, int parity)
     const uint32_t kk = (uint32_t)k;
     const int mode = P->cfg.mode;
     const int t32 = P->cfg.tps32, t64 = P->cfg.tps64, b32 = P->cfg.block32, b64 = P->cfg.block64;
+    const int c32 = P->cfg.cache32 - 1, c64 = P->cfg.cache64 - 1;  // kernel cache policy codes
     P->launch_log.push_back(sgi);
     switch (kind) {
         case K_HB32:
-            return launch_sweep_kind<float, HEATBATH, true>(P, kHeatBathTps, kHeatBathBlock, tiles, list, count, parity,
-                                                            kk);
+            return launch_sweep_kind<float, HEATBATH, true>(P, kHeatBathTps, kHeatBathBlock, 0, tiles, list, count,
+                                                            parity, kk);
         case K_HB64:
-            return launch_sweep_kind<double, HEATBATH, false>(P, kHeatBathTps, kHeatBathBlock, tiles, list, count,
+            return launch_sweep_kind<double, HEATBATH, false>(P, kHeatBathTps, kHeatBathBlock, 1, tiles, list, count,
                                                               parity, kk);
         case K_OR32:
             return mode == GF_OR_EXACT
-                       ? launch_sweep_kind<float, 0, true>(P, t32, b32, tiles, list, count, parity, kk)
-                       : launch_sweep_kind<float, 1, true>(P, t32, b32, tiles, list, count, parity, kk);
+                       ? launch_sweep_kind<float, 0, true>(P, t32, b32, c32, tiles, list, count, parity, kk)
+                       : launch_sweep_kind<float, 1, true>(P, t32, b32, c32, tiles, list, count, parity, kk);
         case K_OR64:
             return mode == GF_OR_EXACT
-                       ? launch_sweep_kind<double, 0, false>(P, t64, b64, tiles, list, count, parity, kk)
-                       : launch_sweep_kind<double, 1, false>(P, t64, b64, tiles, list, count, parity, kk);
+                       ? launch_sweep_kind<double, 0, false>(P, t64, b64, c64, tiles, list, count, parity, kk)
+                       : launch_sweep_kind<double, 1, false>(P, t64, b64, c64, tiles, list, count, parity, kk);
         case K_R32:
             if (P->cfg.reals32 == 8)
                 hipLaunchKernelGGL((k_pool_reunit<float, true, true>), dim3(P->grid_other), dim3(PBLOCK), 0, P->stream,
@@ -944,8 +967,12 @@ gf_status gf_pool_create(const gf_pool_config* cfg, void* hip_stream, gf_pool* o
     if (c.tps64 == 0) c.tps64 = kDefaultTps64;
     if (c.block32 == 0) c.block32 = kDefaultBlock;
     if (c.block64 == 0) c.block64 = kDefaultBlock;
+    if (c.cache32 == 0) c.cache32 = c.reals32 == 8 ? 2 : 1;  // 8 reals: non-temporal; 12: plain
+    if (c.cache64 == 0) c.cache64 = 2;  // non-temporal
     GF_TRY(check_pool_shape(c.tps32, c.block32));
     GF_TRY(check_pool_shape(c.tps64, c.block64));
+    if (c.cache32 < 1 || c.cache32 > 2 || c.cache64 < 1 || c.cache64 > 2)
+        return fail(GF_E_ARG, "cache32 / cache64 must be 0 (default), 1 (plain) or 2 (non-temporal)");
 
     gf_pool_* P = new (std::nothrow) gf_pool_();
     if (!P) return fail(GF_E_NOMEM, "host allocation failed");
@@ -1052,8 +1079,8 @@ gf_status gf_pool_admit(gf_pool P, uint64_t job_id, const int32_t dims[4], const
     GF_TRY(create_lattice(dims, (gf_prec)P->cfg.prec, 3, P->cfg.reals32 == 8, P->stream, &L));
     // the job's own lattice object takes the pool's shape (its solo kernels
     // are not used for sweeps while it is in the pool)
-    L->cfg32 = SweepConfig{P->cfg.tps32, P->cfg.block32};
-    L->cfg64 = SweepConfig{P->cfg.tps64, P->cfg.block64};
+    L->cfg32 = SweepConfig{P->cfg.tps32, P->cfg.block32, P->cfg.cache32 - 1};
+    L->cfg64 = SweepConfig{P->cfg.tps64, P->cfg.block64, P->cfg.cache64 - 1};
     gf_status st = upload_job(P, L, host_links);
     double theta = 0.0, F = 0.0;
     if (st == GF_OK && anneal_sweeps == 0) {
@@ -1245,16 +1272,28 @@ gf_status gf_pool_autotune(gf_pool P, int32_t kernel, int32_t n_sweeps, size_t s
     if (st == GF_OK && e == hipSuccess) e = hipStreamSynchronize(P->stream);
 
     const int mode = P->cfg.mode;
-    // Two rounds over every shape, each shape keeping its faster time: a single
-    // round favours the shapes timed after the clocks have settled.
-    static const int kShapes[9][2] = {{1, 64}, {1, 128}, {1, 256}, {2, 64}, {2, 128},
-                                      {2, 256}, {4, 64}, {4, 128}, {4, 256}};
-    double shape_us[9];
+    // Two rounds over every shape (lanes per site, block, cache policy), each
+    // shape keeping its faster time: a single round favours the shapes timed
+    // after the clocks have settled.
+    constexpr int kNShapes = 18;
+    int shapes[kNShapes][3];
+    {
+        int q = 0;
+        for (int tps : {1, 2, 4})
+            for (int block : {64, 128, 256})
+                for (int cp : {0, 1}) {
+                    shapes[q][0] = tps;
+                    shapes[q][1] = block;
+                    shapes[q][2] = cp;
+                    ++q;
+                }
+    }
+    double shape_us[kNShapes];
     for (double& x : shape_us) x = 1e300;
     for (int round = 0; round < 2; ++round) {
-        for (int si = 0; si < 9; ++si) {
+        for (int si = 0; si < kNShapes; ++si) {
             if (st != GF_OK || e != hipSuccess) break;
-            const int tps = kShapes[si][0], block = kShapes[si][1];
+            const int tps = shapes[si][0], block = shapes[si][1], cp = shapes[si][2];
             uint32_t tiles = 0;
             for (size_t i = 0; i < n; ++i) {
                 list[i] = Entry{(uint32_t)i, tiles};
@@ -1270,21 +1309,21 @@ gf_status gf_pool_autotune(gf_pool P, int32_t kernel, int32_t n_sweeps, size_t s
                     const uint32_t ns = (uint32_t)(n + 1);
                     if (f32 && P->cfg.reals32 == 8)
                         r = mode == GF_OR_EXACT
-                                ? launch_sweep_shape<float, 0, true, true>(P->stream, slots_d, tps, block, tiles,
+                                ? launch_sweep_shape<float, 0, true, true>(P->stream, slots_d, tps, block, cp, tiles,
                                                                            list_d, count_d, ns, parity, 0u)
-                                : launch_sweep_shape<float, 1, true, true>(P->stream, slots_d, tps, block, tiles,
+                                : launch_sweep_shape<float, 1, true, true>(P->stream, slots_d, tps, block, cp, tiles,
                                                                            list_d, count_d, ns, parity, 0u);
                     else if (f32)
                         r = mode == GF_OR_EXACT
-                                ? launch_sweep_shape<float, 0, true, false>(P->stream, slots_d, tps, block, tiles,
+                                ? launch_sweep_shape<float, 0, true, false>(P->stream, slots_d, tps, block, cp, tiles,
                                                                             list_d, count_d, ns, parity, 0u)
-                                : launch_sweep_shape<float, 1, true, false>(P->stream, slots_d, tps, block, tiles,
+                                : launch_sweep_shape<float, 1, true, false>(P->stream, slots_d, tps, block, cp, tiles,
                                                                             list_d, count_d, ns, parity, 0u);
                     else
                         r = mode == GF_OR_EXACT
-                                ? launch_sweep_shape<double, 0, false, false>(P->stream, slots_d, tps, block, tiles,
+                                ? launch_sweep_shape<double, 0, false, false>(P->stream, slots_d, tps, block, cp, tiles,
                                                                               list_d, count_d, ns, parity, 0u)
-                                : launch_sweep_shape<double, 1, false, false>(P->stream, slots_d, tps, block, tiles,
+                                : launch_sweep_shape<double, 1, false, false>(P->stream, slots_d, tps, block, cp, tiles,
                                                                               list_d, count_d, ns, parity, 0u);
                     if (r != hipSuccess) return r;
                 }
@@ -1301,16 +1340,17 @@ gf_status gf_pool_autotune(gf_pool P, int32_t kernel, int32_t n_sweeps, size_t s
             shape_us[si] = std::min(shape_us[si], 1e3 * (double)ms / n_sweeps);
         }
     }
-    int best_tps = 0, best_block = 0, m = 0;
+    int best_tps = 0, best_block = 0, best_cp = 0, m = 0;
     double best_us = 1e300;
-    for (int si = 0; si < 9 && st == GF_OK && e == hipSuccess; ++si) {
-        const int tps = kShapes[si][0], block = kShapes[si][1];
-        if (m < cap) table[m] = gf_tune_entry{tps, block, f32 ? 0 : 1, 0, shape_us[si]};
+    for (int si = 0; si < kNShapes && st == GF_OK && e == hipSuccess; ++si) {
+        const int tps = shapes[si][0], block = shapes[si][1], cp = shapes[si][2];
+        if (m < cap) table[m] = gf_tune_entry{tps, block, cp, 0, shape_us[si]};
         ++m;
         if (shape_us[si] < best_us) {
             best_us = shape_us[si];
             best_tps = tps;
             best_block = block;
+            best_cp = cp;
         }
     }
     if (st == GF_OK && e != hipSuccess) st = fail(GF_E_HIP, "pool autotune: %s", hipGetErrorString(e));
@@ -1328,15 +1368,17 @@ gf_status gf_pool_autotune(gf_pool P, int32_t kernel, int32_t n_sweeps, size_t s
     if (f32) {
         P->cfg.tps32 = best_tps;
         P->cfg.block32 = best_block;
+        P->cfg.cache32 = best_cp + 1;
     } else {
         P->cfg.tps64 = best_tps;
         P->cfg.block64 = best_block;
+        P->cfg.cache64 = best_cp + 1;
     }
     // captured steps hold the previous shape's kernels
     for (auto& kv : P->graphs) destroy_step_graph(kv.second);
     P->graphs.clear();
     if (n_out) *n_out = std::min(m, cap);
-    if (chosen) *chosen = gf_tune_entry{best_tps, best_block, f32 ? 0 : 1, 0, best_us};
+    if (chosen) *chosen = gf_tune_entry{best_tps, best_block, best_cp, 0, best_us};
     return GF_OK;
 }
 
@@ -1347,6 +1389,14 @@ gf_status gf_pool_get_shape(gf_pool P, int32_t* tps32, int32_t* block32, int32_t
     if (block32) *block32 = P->cfg.block32;
     if (tps64) *tps64 = P->cfg.tps64;
     if (block64) *block64 = P->cfg.block64;
+    return GF_OK;
+}
+
+gf_status gf_pool_get_cache(gf_pool P, int32_t* cache32, int32_t* cache64)
+{
+    GF_TRY(pool_check(P));
+    if (cache32) *cache32 = P->cfg.cache32;
+    if (cache64) *cache64 = P->cfg.cache64;
     return GF_OK;
 }
 

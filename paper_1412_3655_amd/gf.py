@@ -84,6 +84,8 @@ class gf_pool_config(ctypes.Structure):
         ("tps64", ctypes.c_int32),
         ("block64", ctypes.c_int32),
         ("reals32", ctypes.c_int32),
+        ("cache32", ctypes.c_int32),
+        ("cache64", ctypes.c_int32),
     ]
 
 
@@ -167,6 +169,7 @@ _SIGNATURES = {
     "gf_pool_stats": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_int64)],
     "gf_pool_autotune": [_vp, _i32, _i32, ctypes.c_size_t, ctypes.POINTER(gf_tune_entry), _i32,
                          ctypes.POINTER(_i32), ctypes.POINTER(gf_tune_entry)],
+    "gf_pool_get_cache": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
     "gf_pool_get_shape": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                           ctypes.POINTER(_i32)],
     "gf_clock": [],
@@ -700,9 +703,9 @@ def gf_pool_job_bytes(dims, prec: int = GF_MIXED, reals32: int = 12) -> int:
 
 def gf_pool_create(hbm_budget: int, max_slots: int, prec: int = GF_MIXED, check_every: int = 10,
                    mode: int = GF_OR_EXACT, tps32: int = 0, block32: int = 0, tps64: int = 0, block64: int = 0,
-                   stream=None, reals32: int = 12):
+                   stream=None, reals32: int = 12, cache32: int = 0, cache64: int = 0):
     cfg = gf_pool_config(int(hbm_budget), int(max_slots), int(prec), int(check_every), int(mode), int(tps32),
-                         int(block32), int(tps64), int(block64), int(reals32))
+                         int(block32), int(tps64), int(block64), int(reals32), int(cache32), int(cache64))
     out = _vp()
     _call("gf_pool_create", ctypes.byref(cfg), _stream_handle(stream), ctypes.byref(out))
     return out
@@ -786,14 +789,22 @@ def gf_pool_stats(pool):
 
 def gf_pool_autotune(pool, kernel: int, n_sweeps: int = 3, scratch_bytes: int = 8 << 30):
     """((tps, block, nontemporal), table of (tps, block, nontemporal, us_per_sweep)) of the pool's
-    sweep of `kernel` (GF_FP32 / GF_FP64), timed on copies of the resident jobs."""
-    table = (gf_tune_entry * 16)()
+    sweep of `kernel` (GF_FP32 / GF_FP64), timed on copies of the resident jobs (nontemporal: 0
+    plain, 1 non-temporal link accesses)."""
+    table = (gf_tune_entry * 32)()
     n = _i32()
     best = gf_tune_entry()
-    _call("gf_pool_autotune", pool, int(kernel), int(n_sweeps), int(scratch_bytes), table, 16, ctypes.byref(n),
+    _call("gf_pool_autotune", pool, int(kernel), int(n_sweeps), int(scratch_bytes), table, 32, ctypes.byref(n),
           ctypes.byref(best))
     rows = [(table[i].tps, table[i].block, table[i].nontemporal, table[i].us_per_sweep) for i in range(n.value)]
     return (best.tps, best.block, best.nontemporal), rows
+
+
+def gf_pool_get_cache(pool):
+    """(cache32, cache64) of the pool's overrelaxation sweeps: 1 plain, 2 non-temporal."""
+    v = [_i32() for _ in range(2)]
+    _call("gf_pool_get_cache", pool, *[ctypes.byref(x) for x in v])
+    return tuple(x.value for x in v)
 
 
 def gf_pool_get_shape(pool):
@@ -808,12 +819,13 @@ class Pool:
 
     def __init__(self, hbm_budget: int, max_slots: int, prec: int = GF_MIXED, check_every: int = 10,
                  mode: int = GF_OR_EXACT, tps32: int = 0, tps64: int = 0, stream=None, block32: int = 0,
-                 block64: int = 0, reals32: int = 12):
-        """reals32 = 8: the float32 links of a GF_MIXED pool in 8 reals (gf_set_storage)."""
+                 block64: int = 0, reals32: int = 12, cache32: int = 0, cache64: int = 0):
+        """reals32 = 8: the float32 links of a GF_MIXED pool in 8 reals (gf_set_storage).
+        cache32 / cache64: cache policy of the overrelaxation sweeps (1 plain, 2 non-temporal, 0 default)."""
         self.check_every = int(check_every)
         self.mode = int(mode)
         self.handle = gf_pool_create(hbm_budget, max_slots, prec, check_every, mode, tps32, block32, tps64, block64,
-                                     stream, reals32)
+                                     stream, reals32, cache32, cache64)
         self.dims = {}
 
     def autotune(self, kernel: int, n_sweeps: int = 3, scratch_bytes: int = 8 << 30):
@@ -822,6 +834,10 @@ class Pool:
     @property
     def shape(self):
         return gf_pool_get_shape(self.handle)
+
+    @property
+    def cache(self):
+        return gf_pool_get_cache(self.handle)
 
     def admit(self, job_id, dims, links, **kw) -> bool:
         kw.setdefault("check_every", self.check_every)

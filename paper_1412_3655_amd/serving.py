@@ -57,6 +57,7 @@ class RunStats:
     max_resident: int = 0    # most jobs resident in the pool at once
     peak_bytes: int = 0      # most device bytes the pool held for job lattices
     shape: tuple = ()        # (tps32, block32, tps64, block64) of the pool's sweeps
+    cache: tuple = ()        # (cache32, cache64): 1 plain, 2 non-temporal link accesses
     tuning: dict = field(default_factory=dict)  # autotuner tables (kernel -> rows), when tuned
 
     def summary(self) -> dict:
@@ -89,6 +90,7 @@ class RunStats:
             "max_resident_jobs": self.max_resident,
             "peak_hbm_bytes": self.peak_bytes,
             "pool_shape_tps32_block32_tps64_block64": list(self.shape) or None,
+            "pool_cache32_cache64": list(self.cache) or None,
             "pool_autotune_us_per_sweep": self.tuning or None,
         }
 
@@ -212,8 +214,9 @@ def run_pool(jobs, links_of, prec=gf.GF_MIXED, check_every=10, max_slots=256, hb
                 for k in kinds:
                     _, rows = pool.autotune(k, 3, scratch_bytes=min(held, 16 << 30))
                     stats.tuning["fp32" if k == gf.GF_FP32 else "fp64"] = [
-                        [t, b, round(us, 1)] for (t, b, _, us) in rows]
+                        [t, b, nt, round(us, 1)] for (t, b, nt, us) in rows]
                 stats.shape = pool.shape
+                stats.cache = pool.cache
 
         def idle(active, finished):
             if active or finished:
@@ -255,6 +258,7 @@ def run_pool(jobs, links_of, prec=gf.GF_MIXED, check_every=10, max_slots=256, hb
         pool.sync()
         stats.seconds = gf.gf_clock() - t0
         stats.shape = pool.shape
+        stats.cache = pool.cache
     return stats
 
 

@@ -57,15 +57,21 @@ def solo(dims, links, prec, anneal, seed, check_every, storage=12):
         return r, lat.get_links()
 
 
-@pytest.mark.parametrize("prec,reals32", [(gf.GF_MIXED, 12), (gf.GF_FP64, 12), (gf.GF_MIXED, 8)])
-def test_pool_equals_solo(prec, reals32):
+@pytest.mark.parametrize("prec,reals32,cache32,cache64", [(gf.GF_MIXED, 12, 0, 0), (gf.GF_FP64, 12, 0, 0),
+                                                         (gf.GF_MIXED, 8, 0, 0), (gf.GF_MIXED, 8, 2, 1),
+                                                         (gf.GF_MIXED, 12, 2, 1), (gf.GF_FP64, 12, 0, 1)])
+def test_pool_equals_solo(prec, reals32, cache32, cache64):
     """reals32 = 8: the pool's float32 links in 8 reals, against solo GF_MIXED lattices stored the
-    same way."""
+    same way.  cache32 / cache64: the cache policy of the pool's overrelaxation sweeps (default
+    plain for float32 and non-temporal for float64; 1 plain, 2 non-temporal), which changes
+    neither the order of updates within a colour's result nor the links."""
     ce = 5
-    say(f"pool vs solo prec={prec} reals32={reals32}")
+    say(f"pool vs solo prec={prec} reals32={reals32} cache {cache32}/{cache64}")
     inputs = [gi.gen_links(d, e, s) for (d, e, s, _) in JOBS]
     ref = [solo(d, u, prec, a, 100 + i, ce, reals32) for i, ((d, e, s, a), u) in enumerate(zip(JOBS, inputs))]
-    with gf.Pool(1 << 34, 16, prec=prec, check_every=ce, reals32=reals32) as pool:
+    with gf.Pool(1 << 34, 16, prec=prec, check_every=ce, reals32=reals32, cache32=cache32,
+                 cache64=cache64) as pool:
+        assert pool.cache == (cache32 or (2 if reals32 == 8 else 1), cache64 or 2)
         for i, ((d, e, s, a), u) in enumerate(zip(JOBS, inputs)):
             assert pool.admit(1000 + i, d, u, anneal_sweeps=a, T_start=1.25, T_end=0.05, seed=100 + i,
                               **{k: v for k, v in fix_kw(ce).items() if k not in ("check_every", "mode")})
@@ -351,6 +357,8 @@ def test_pool_autotune_keeps_results(reals32):
         gf.Pool(1 << 30, 4, prec=gf.GF_MIXED, tps32=8)
     with pytest.raises(gf.GFError):
         gf.Pool(1 << 30, 4, prec=gf.GF_MIXED, block64=512)
+    with pytest.raises(gf.GFError):
+        gf.Pool(1 << 30, 4, prec=gf.GF_MIXED, cache32=3)
     with gf.Pool(1 << 34, 8, prec=gf.GF_MIXED, check_every=ce, block32=64, block64=256, reals32=reals32) as pool:
         # default lanes per site of the float32 sweeps: 1 with 8-real links, 2 with 12-real links
         assert pool.shape == (1 if reals32 == 8 else 2, 64, 1, 256)
@@ -361,11 +369,12 @@ def test_pool_autotune_keeps_results(reals32):
             assert pool.admit(300 + i, d, u, anneal_sweeps=a, T_start=1.25, T_end=0.05, seed=200 + i,
                               **{k: v for k, v in fix_kw(ce).items() if k not in ("check_every", "mode")})
         pool.step()
-        (t32, b32, _), rows32 = pool.autotune(gf.GF_FP32, 2)
-        (t64, b64, _), rows64 = pool.autotune(gf.GF_FP64, 2)
+        (t32, b32, n32), rows32 = pool.autotune(gf.GF_FP32, 2)
+        (t64, b64, n64), rows64 = pool.autotune(gf.GF_FP64, 2)
         say(f"  float32 {t32}/{b32} of {len(rows32)} shapes, float64 {t64}/{b64} of {len(rows64)}")
-        assert len(rows32) == 9 and len(rows64) == 9
+        assert len(rows32) == 18 and len(rows64) == 18  # 3 lanes x 3 blocks x 2 cache policies
         assert pool.shape == (t32, b32, t64, b64)
+        assert pool.cache == (n32 + 1, n64 + 1)  # the chosen policy: 0 plain, 1 non-temporal
         assert min(r[3] for r in rows32) == [r[3] for r in rows32 if (r[0], r[1]) == (t32, b32)][0]
         done = {}
         for _ in range(2000):
