@@ -15,7 +15,8 @@ representation, 1024 B per site update); the float32 sweeps of the 48^3 x 96
 lattice with links in 12 and in 8 reals (768 / 512 B per site update); the
 32^4 run to theta < 1e-12 in float64 and in mixed precision with float32 links
 in 12 and in 8 reals (capped; also on a smoother input of the same generator,
-eps = 0.6, which converges); the
+eps = 0.6, which converges, and on the same input after a 2000-sweep
+simulated-annealing prelude, which also converges); the
 8^4 convergence workload in float64 and mixed precision; the 64-lattice
 batched workload (mixed-precision pool, float32 links in 8 reals by default,
 vs float64 one lattice at a time); the
@@ -191,15 +192,22 @@ def copy_bandwidth(gf, nbytes=1 << 30, reps=10):
     return best
 
 
-def fix_until_leg(gf, torch, stream, links, dims, args, eps, adaptive_too=False):
+def fix_until_leg(gf, torch, stream, links, dims, args, eps, adaptive_too=False, anneal=0, max_sweeps=None):
     """The run of one input to theta < 1e-12: plain FP64 and FP32-bulk / FP64-polish (GF_MIXED),
     with exact checks every 10 sweeps, and (adaptive_too) again with adaptive checks (the
-    fused estimate decides where the exact measurement runs; same result bitwise)."""
+    fused estimate decides where the exact measurement runs; same result bitwise).  anneal > 0:
+    a simulated-annealing prelude of that many heat-bath sweeps (T 1.25 -> 0.01, Philox key 0)
+    first, timed apart, and only the float64 and the 8-real mixed runs."""
     out = {"eps": eps}
-    kw = dict(omega=args.omega, mode=args.mode, theta_target=1e-12, max_sweeps=args.fix_max_sweeps,
-              check_every=10, reunit_every=100, theta_switch=args.theta_switch)
+    kw = dict(omega=args.omega, mode=args.mode, theta_target=1e-12,
+              max_sweeps=max_sweeps or args.fix_max_sweeps, check_every=10, reunit_every=100,
+              theta_switch=args.theta_switch)
+    if anneal:
+        out["anneal_sweeps"] = anneal
     P0 = None
     runs = [("fp64", gf.GF_FP64, False, 12), ("mixed", gf.GF_MIXED, False, 12), ("mixed_min8", gf.GF_MIXED, False, 8)]
+    if anneal:
+        runs = [runs[0], runs[2]]
     if adaptive_too:
         runs += [("fp64_adaptive", gf.GF_FP64, True, 12), ("mixed_adaptive", gf.GF_MIXED, True, 12)]
     for name, prec, adaptive, storage in runs:
@@ -223,6 +231,15 @@ def fix_until_leg(gf, torch, stream, links, dims, args, eps, adaptive_too=False)
                 pre = "" if storage == 12 else "min8_"
                 out[pre + "fp32_theta_floor"] = floor
                 out[pre + "theta_switch"] = sw if args.theta_switch < 0 else args.theta_switch
+            ta = 0.0
+            if anneal:
+                if prec == gf.GF_MIXED and not args.no_tune:
+                    lat.autotune_anneal(gf.GF_FP32, n_sweeps=2)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                lat.anneal(anneal, 1.25, 0.01, 0)
+                torch.cuda.synchronize()
+                ta = time.perf_counter() - t0
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             r = lat.fix_until(**kw)
@@ -232,14 +249,22 @@ def fix_until_leg(gf, torch, stream, links, dims, args, eps, adaptive_too=False)
         out[name] = {"seconds": dt, "converged": r.converged, "sweeps": r.sweeps, "sweeps_fp32": r.sweeps_fp32,
                      "sweeps_fp64": r.sweeps_fp64, "theta": r.theta, "F": r.F, "plaquette_drift": abs(P1 - P0),
                      "exact_measurements": measures, "estimates": estimates}
+        if anneal:
+            out[name]["anneal_seconds"] = ta
+            out[name]["total_seconds"] = ta + dt
         log(f"fix_until eps={eps} {name}: {dt:.2f} s, sweeps {r.sweeps} ({r.sweeps_fp32}/{r.sweeps_fp64}), "
             f"theta {r.theta:.3e}, F {r.F:.12f}")
     # the float64 GPU run is the reference here (it is parity-tested against the oracle)
     for name in ("mixed", "mixed_min8"):
+        if name not in out:
+            continue
         out[name]["dF_vs_fp64"] = out[name]["F"] - out["fp64"]["F"]
         out[name]["dtheta_vs_fp64"] = out[name]["theta"] - out["fp64"]["theta"]
-    out["speedup_mixed_vs_fp64"] = out["fp64"]["seconds"] / out["mixed"]["seconds"]
-    out["speedup_mixed_min8_vs_fp64"] = out["fp64"]["seconds"] / out["mixed_min8"]["seconds"]
+        out["speedup_%s_vs_fp64" % name] = out["fp64"]["seconds"] / out[name]["seconds"]
+    if anneal:
+        out["note"] = ("the prelude's heat bath takes each input to a different basin than overrelaxation alone; "
+                       "on these rough inputs the sweep count to theta < 1e-12 then depends on the precision's "
+                       "trajectory, so the two runs' sweep counts differ")
     for name in ("fp64", "mixed"):
         a = out.get(name + "_adaptive")
         if a:
@@ -665,6 +690,10 @@ def main(argv=None):
     ap.add_argument("--full-max-sweeps", type=int, default=10000)
     ap.add_argument("--job-max-sweeps", type=int, default=10000)
     ap.add_argument("--fix-max-sweeps", type=int, default=20000)
+    ap.add_argument("--fix-anneal", type=int, default=2000,
+                    help="the 32^4 input again with a simulated-annealing prelude of this many heat-bath sweeps "
+                         "before the run to theta < 1e-12 (0: skip)")
+    ap.add_argument("--fix-anneal-max-sweeps", type=int, default=200000)
     ap.add_argument("--fix-eps-smooth", type=float, default=0.6,
                     help="second run to theta < 1e-12 on a smoother input of the same lattice (0: skip)")
     ap.add_argument("--theta-switch", type=float, default=-1.0,
@@ -867,6 +896,10 @@ def main(argv=None):
     fix8 = None
     if not args.no_fix:
         line["fix_until_theta_1e-12"] = fix_until_leg(gf, torch, stream, links, dims, args, args.eps)
+        if args.fix_anneal > 0:
+            line["fix_until_theta_1e-12_annealed"] = fix_until_leg(gf, torch, stream, links, dims, args, args.eps,
+                                                                   anneal=args.fix_anneal,
+                                                                   max_sweeps=args.fix_anneal_max_sweeps)
         if args.fix_eps_smooth > 0:
             smooth = inputs.get(dims, args.fix_eps_smooth, args.seed)
             line["fix_until_theta_1e-12_smooth"] = fix_until_leg(gf, torch, stream, smooth, dims, args,
