@@ -621,7 +621,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--repeats", type=int, default=5,
                     help="further timed regions of --steps sweeps after the headline one (median and spread)")
     ap.add_argument("--dims", type=str, default="32,32,32,32")
