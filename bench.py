@@ -302,10 +302,15 @@ def batched_leg(gf, inputs, stream, args):
     if not args.no_fifo:
         legs.append(("fifo_fp64", lambda: serving.run_fifo(jobs, lambda j: links[j.job_id], gf.GF_FP64, fix, False,
                                                            args.tps, args.block, args.nt)))
+    runs = {}
     for name, fn in legs:
         st = fn()
+        runs[name] = st
         out[name] = st.summary()
         log(f"batched {name}: {st.converged}/64 converged in {st.seconds:.2f} s")
+    if "fifo_fp64" in runs:
+        # final theta and F of every mixed-precision result against the float64 run of the same job
+        out["pool_mixed_vs_fifo_fp64_per_result"] = serving.compare_finals(runs["pool_mixed"], runs["fifo_fp64"])
     if "fifo_fp64" in out:
         out["speedup_converged_per_s_pool_mixed_vs_fifo_fp64"] = (
             (out["pool_mixed"]["converged_lattices_per_s"] or 0) / out["fifo_fp64"]["converged_lattices_per_s"]
@@ -360,8 +365,10 @@ def serving_leg(gf, inputs, stream, args):
         f"peak {st.peak_bytes / 1e9:.2f} GB")
     if args.no_fifo:
         return out
+    st_pool = st
     st = serving.run_fifo(jobs, links_of, gf.GF_FP64, fix, True, args.tps, args.block, args.nt, log=jlog)
     out["fifo_fp64"] = st.summary()
+    out["pool_mixed_vs_fifo_fp64_per_result"] = serving.compare_finals(st_pool, st)
     log(f"serving fifo: {st.converged}/{len(jobs)} converged, {st.seconds:.1f} s")
     a, b = out["pool_mixed"]["converged_lattices_per_s"], out["fifo_fp64"]["converged_lattices_per_s"]
     out["speedup_converged_per_s_pool_mixed_vs_fifo_fp64"] = a / b if a and b else None

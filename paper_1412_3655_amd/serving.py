@@ -45,6 +45,7 @@ class RunStats:
     latencies: list = field(default_factory=list)        # every finished job
     conv_latencies: list = field(default_factory=list)   # converged jobs only
     results: dict = field(default_factory=dict)          # job_id -> (result, links) when collected
+    finals: dict = field(default_factory=dict)           # job_id -> (converged, theta, F) of every finished job
     sweeps: int = 0
     sweeps_fp32: int = 0     # fix-phase sweeps in float32 (mixed precision)
     sweeps_fp64: int = 0     # fix-phase sweeps in float64
@@ -197,6 +198,8 @@ def run_pool(jobs, links_of, prec=gf.GF_MIXED, check_every=10, max_slots=256, hb
             stats.site_updates_fp32 += r.sweeps_fp32 * volume(j.dims)
             stats.site_updates_fp64 += r.sweeps_fp64 * volume(j.dims)
             stats.site_updates_anneal += j.anneal * volume(j.dims)
+            if d["status"] == gf.GF_OK:
+                stats.finals[j.job_id] = (bool(r.converged), r.theta, r.F)
             if d["status"] != gf.GF_OK:
                 stats.failed += 1
             elif r.converged:
@@ -290,6 +293,7 @@ def run_fifo(jobs, links_of, prec=gf.GF_FP64, fix=None, open_loop=True, tps=0, b
         if not ok:
             stats.failed += 1
             continue
+        stats.finals[j.job_id] = (bool(r.converged), r.theta, r.F)
         stats.sweeps += r.sweeps + j.anneal
         stats.sweeps_fp32 += r.sweeps_fp32
         stats.sweeps_fp64 += r.sweeps_fp64
@@ -305,3 +309,18 @@ def run_fifo(jobs, links_of, prec=gf.GF_FP64, fix=None, open_loop=True, tps=0, b
                 f"latency {lat_s:.2f} s")
     stats.seconds = gf.gf_clock() - t0
     return stats
+
+
+def compare_finals(mixed: RunStats, ref: RunStats) -> dict:
+    """Per-job final theta and F of a run (mixed precision) against a float64 reference run of the
+    same jobs: over the jobs that converged in both, the largest and the median |dF| and |dtheta|,
+    and how many landed on another maximum (|dF| > 1e-9: rough inputs whose trajectories part)."""
+    both = [k for k, v in mixed.finals.items() if v[0] and k in ref.finals and ref.finals[k][0]]
+    if not both:
+        return {"jobs_converged_in_both": 0}
+    dF = np.array([abs(mixed.finals[k][2] - ref.finals[k][2]) for k in both])
+    dth = np.array([abs(mixed.finals[k][1] - ref.finals[k][1]) for k in both])
+    same = dF <= 1e-9
+    return {"jobs_converged_in_both": len(both), "max_abs_dF": float(dF.max()), "median_abs_dF": float(np.median(dF)),
+            "max_abs_dtheta": float(dth.max()), "jobs_same_maximum_dF_le_1e-9": int(same.sum()),
+            "max_abs_dF_same_maximum": float(dF[same].max()) if same.any() else None}

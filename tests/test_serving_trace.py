@@ -40,3 +40,18 @@ def test_batched_jobs_draws():
     assert [j.seed for j in jobs] == [1000 + i for i in range(64)]
     assert all(0.4 <= j.eps <= 1.0 for j in jobs)
     assert sum(serving.volume(j.dims) for j in jobs) == 12719104
+
+
+def test_compare_finals():
+    """Per-result comparison of a mixed-precision run with a float64 run of the same jobs: only
+    jobs converged in both count; |dF| above 1e-9 marks another maximum."""
+    a = serving.RunStats(3, 0, 1.0)
+    b = serving.RunStats(3, 0, 1.0)
+    a.finals = {1: (True, 1e-13, 0.5), 2: (True, 2e-13, 0.6), 3: (False, 1e-7, 0.7), 4: (True, 1e-13, 0.1)}
+    b.finals = {1: (True, 3e-13, 0.5 + 1e-12), 2: (True, 2e-13, 0.6 + 1e-5), 3: (True, 1e-13, 0.7)}
+    c = serving.compare_finals(a, b)
+    assert c["jobs_converged_in_both"] == 2
+    assert c["jobs_same_maximum_dF_le_1e-9"] == 1
+    assert abs(c["max_abs_dF"] - 1e-5) < 1e-12 and abs(c["max_abs_dF_same_maximum"] - 1e-12) < 1e-15
+    assert abs(c["max_abs_dtheta"] - 2e-13) < 1e-20
+    assert serving.compare_finals(serving.RunStats(0, 0, 1.0), b) == {"jobs_converged_in_both": 0}
